@@ -1,0 +1,19 @@
+"""Dense brute force: every eigenpair of the assembled H by numpy.linalg.eigh
+(oracle; test infrastructure).  Feasible for n up to a few thousand (the
+16^3 workload assembles to a 4096 x 4096 matrix).
+
+Pin: plane-wave closed form of the discrete Laplacian spectrum at V = 0
+(tests/test_oracle_stencil.py).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .stencil import assemble_h
+
+
+def lowest(V, N, h, order, k, kpt=(0.0, 0.0, 0.0)):
+    """(lam[:k], X[:, :k], lam_all) of H, ascending."""
+    H = assemble_h(V, N, h, order, kpt)
+    lam, X = np.linalg.eigh(H)
+    return lam[:k], X[:, :k], lam

@@ -1,0 +1,132 @@
+"""Small dense steps of PPCG (oracle; test infrastructure).
+
+  sym            Hermitian part (M + M^H)/2 of a computed Gram
+  cholqr         Cholesky-QR: X^H X = R^H R, X <- X R^{-1} (section 4.5)
+  block_pencil   the 3q x 3q (2q x 2q without P) projected problem of the block
+                 update (eq. (4.1) with eq. (2.3)); C^H B C = I, the q lowest
+  rayleigh_ritz  the full Rayleigh-Ritz over [X, X_lock] (Algorithm 3, RR branch)
+
+Library primitives used as single steps: scipy.linalg.cholesky,
+scipy.linalg.solve_triangular, numpy.linalg.eigh.
+
+Readings where the paper is silent:
+  * Computed Grams are replaced by their Hermitian part.
+  * The block pencil is diagonally scaled (D = diag(B)^{-1/2}); W or P columns
+    whose squared norm is below (1e-14)^2 times the largest X-column squared
+    norm are dropped (zero search direction).  The scaled B is factored by a
+    Cholesky that accepts columns in the order X, W, P and drops a column
+    whose pivot falls below PIVOT_TOL (a direction that is numerically in the
+    span of the columns already accepted).
+  * Theorem 1 indicator in block form: if C_X of the kept eigenvectors is
+    numerically singular (Cholesky pivot of C_X^H C_X below PIVOT_TOL times
+    its largest diagonal entry) and P was used, the block is solved again
+    without P (the backtrack of Theorem 2).
+
+Pins: tests/test_oracle_dense.py (scipy.linalg.eigh(A, B) on random pencils,
+the closed-form 2 x 2 problem of eq. (3.5), C^H B C = I, CholQR invariants).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+
+DROP_TOL = 1e-14      # relative norm below which a W/P column counts as zero
+PIVOT_TOL = 1e-12     # Cholesky pivot (of a unit-diagonal matrix) floor
+
+
+class RankError(RuntimeError):
+    """Cholesky-QR or Rayleigh-Ritz met a numerically rank-deficient block."""
+
+
+def sym(M: np.ndarray) -> np.ndarray:
+    return 0.5 * (M + M.conj().T)
+
+
+def cholqr(X: np.ndarray):
+    """Return (X R^{-1}, R) with R upper triangular, R^H R = sym(X^H X)."""
+    G = sym(X.conj().T @ X)
+    try:
+        R = sla.cholesky(G, lower=False)
+    except np.linalg.LinAlgError as e:
+        raise RankError(f"Cholesky-QR breakdown: {e}") from None
+    # X R^{-1} = (R^{-T} X^T)^T, with R^T lower triangular (no conjugation)
+    Q = sla.solve_triangular(R.T, X.T, lower=True).T
+    return Q, R
+
+
+def _greedy_cholesky(B: np.ndarray, order: list, tol: float):
+    """Cholesky of B restricted to the columns accepted greedily in ``order``:
+    column c is accepted when its pivot B_cc - sum_p |L_cp|^2 over accepted p
+    is at least ``tol``.  Returns (accepted list, lower factor L)."""
+    acc = []
+    L = np.zeros((len(order), len(order)), dtype=B.dtype)
+    for c in order:
+        r = len(acc)
+        row = np.zeros(r, dtype=B.dtype)
+        for t, p in enumerate(acc):
+            row[t] = (B[c, p] - np.dot(row[:t], L[t, :t].conj())) / L[t, t]
+        piv = (B[c, c] - np.vdot(row, row)).real
+        if piv >= tol:
+            L[r, :r] = row
+            L[r, r] = np.sqrt(piv)
+            acc.append(c)
+    nacc = len(acc)
+    return acc, L[:nacc, :nacc]
+
+
+def block_pencil(A: np.ndarray, B: np.ndarray, nx: int, has_p: bool, _allow_backtrack=True):
+    """Lowest nx eigenpairs of the projected pencil (A, B) of one sub-block
+    S = [X_j, W_j, P_j] (columns 0..nx-1 are X_j, then nx W_j columns, then
+    nx P_j columns when has_p).  Returns (C, theta, used_p) where C has shape
+    (rows of A, nx), C^H B C = I on the kept rows and dropped rows are zero."""
+    nb = A.shape[0]
+    A = sym(A)
+    B = sym(B)
+    d = np.real(np.diag(B)).copy()
+    xmax = max(d[:nx].max(), np.finfo(float).tiny)
+    keep = []
+    for c in range(nb):
+        if c >= 2 * nx and not has_p:
+            continue
+        if c < nx or d[c] > (DROP_TOL ** 2) * xmax:
+            keep.append(c)
+    Dv = np.zeros(nb)
+    Dv[keep] = 1.0 / np.sqrt(d[keep])
+    Bs = Dv[:, None] * B * Dv[None, :]
+    As = Dv[:, None] * A * Dv[None, :]
+    acc, L = _greedy_cholesky(Bs, keep, PIVOT_TOL)
+    if len(acc) < nx:
+        raise RankError("block pencil has fewer independent columns than wanted pairs")
+    Asub = As[np.ix_(acc, acc)]
+    # M = L^{-1} A L^{-H}
+    T = sla.solve_triangular(L, Asub, lower=True)
+    M = sla.solve_triangular(L, T.conj().T, lower=True).conj().T
+    theta, Y = np.linalg.eigh(sym(M))
+    Cacc = sla.solve_triangular(L.conj().T, Y[:, :nx], lower=False)
+    C = np.zeros((nb, nx), dtype=np.result_type(A.dtype, B.dtype, np.float64))
+    C[acc, :] = Dv[acc, None] * Cacc
+    used_p = has_p and any(c >= 2 * nx for c in acc)
+    if used_p and _allow_backtrack:
+        Cx = C[:nx, :]
+        G = sym(Cx.conj().T @ Cx)
+        gmax = np.real(np.diag(G)).max()
+        _, Lx = _greedy_cholesky(G, list(range(nx)), PIVOT_TOL * gmax)
+        if Lx.shape[0] < nx:
+            return block_pencil(A, B, nx, False, _allow_backtrack=False)
+    return C, theta[:nx], used_p
+
+
+def rayleigh_ritz(S: np.ndarray, AS: np.ndarray):
+    """Ritz pairs of span(S): sym(S^H A S) C = sym(S^H S) C Omega, C^H S^H S C = I,
+    all columns, ascending.  Returns (S C, Omega, C)."""
+    SAS = sym(S.conj().T @ AS)
+    SS = sym(S.conj().T @ S)
+    try:
+        L = sla.cholesky(SS, lower=True)
+    except np.linalg.LinAlgError as e:
+        raise RankError(f"Rayleigh-Ritz Gram not positive definite: {e}") from None
+    T = sla.solve_triangular(L, SAS, lower=True)
+    M = sla.solve_triangular(L, T.conj().T, lower=True).conj().T
+    lam, Y = np.linalg.eigh(sym(M))
+    C = sla.solve_triangular(L.conj().T, Y, lower=False)
+    return S @ C, lam, C

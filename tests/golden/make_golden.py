@@ -1,0 +1,29 @@
+"""Writes the stored expected values under tests/golden/ from the oracle only.
+
+  wells16_k64_brute.txt : the 80 lowest eigenvalues of the 16^3 7-point
+                          workload (4 seeded wells, seed 101, h = 0.5) by
+                          dense numpy.linalg.eigh of the assembled matrix.
+
+Run: python tests/golden/make_golden.py
+"""
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle import brute  # noqa: E402
+from paper_1407_7506_amd import inputs as I  # noqa: E402
+
+
+def main():
+    p = I.wells16()
+    lam, _, _ = brute.lowest(p.V, p.grid.N, p.grid.h, p.grid.order, 80)
+    np.savetxt(os.path.join(HERE, "wells16_k64_brute.txt"), lam, fmt="%.17e",
+               header="16^3 7-point, 4 wells seed 101, h=0.5: lowest 80 eigenvalues (dense eigh)")
+
+
+if __name__ == "__main__":
+    main()

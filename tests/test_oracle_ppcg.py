@@ -1,0 +1,143 @@
+"""Pins of the oracle's PPCG iteration (not gpu): dense brute force, the
+closed-form spectrum at V = 0, the LOBPCG limit q = K (scipy's lobpcg),
+Cauchy interlacing and the subspace invariants, error paths."""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import brute, dense, ppcg_ref, stencil
+from paper_1407_7506_amd import inputs as I
+
+
+def run(p, **kw):
+    g = p.grid
+    A = lambda X: stencil.apply_h(X, p.V, g.N, g.h, g.order, g.kpt)
+    T = 1.0 / stencil.diag_h(p.V, g.h, g.order)
+    X0 = kw.pop("X0", p.start())
+    return ppcg_ref.ppcg(A, T, X0, p.k, p.q, kw.pop("tol", p.tol), kw.pop("rr_period", p.rr_period), **kw), A
+
+
+def subspace_dist(X, Y):
+    s = np.linalg.svd(X.conj().T @ Y, compute_uv=False)
+    return math.sqrt(max(0.0, 1.0 - s.min() ** 2))
+
+
+def check_solution(p, lam, X, info, A, tol):
+    lb, Xb, lall = brute.lowest(p.V, p.grid.N, p.grid.h, p.grid.order, p.k, p.grid.kpt)
+    scale = np.abs(lb).max()
+    assert np.all(np.diff(lam) >= -1e-14 * scale)
+    assert np.abs(lam - lb).max() / scale < 1e-10
+    # Cauchy interlacing: every Ritz value is above the exact one
+    assert np.all(lam >= lb - 1e-12 * scale)
+    np.testing.assert_allclose(X.conj().T @ X, np.eye(p.k), atol=1e-12)
+    R = A(X) - X * lam[None, :]
+    assert np.linalg.norm(R) / np.linalg.norm(lam) <= tol * 1.0000001
+    if lall[p.k] - lall[p.k - 1] > 1e-3:
+        assert subspace_dist(X, Xb) < 1e-6
+
+
+CASES = [
+    dict(N=8, k=12, q=4, order=2),
+    dict(N=8, k=12, q=4, order=4),
+    dict(N=6, k=10, q=2, order=4, kpt=(0.9, 0.0, 0.0)),
+    dict(N=8, k=10, q=4, order=2, nbuf=3),     # K = 13: uneven last block
+    dict(N=7, k=6, q=1, order=2),              # single-column blocks (Algorithm 2)
+    dict(N=8, k=16, q=8, order=2, rr_period=1),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "-".join(f"{k}{v}" for k, v in c.items()))
+def test_ppcg_matches_brute_force(case):
+    p = I.small_problem(tol=1e-9, **case)
+    (lam, X, info), A = run(p, record=True)
+    check_solution(p, lam, X, info, A, 1e-9)
+    assert info.fresh_resid <= 1e-9
+
+
+def laplacian_spectrum(N, h, order):
+    th = 2 * np.pi * np.arange(N) / N
+    if order == 2:
+        s = 2.0 * np.sin(th / 2) ** 2 / h ** 2
+    else:
+        s = 0.5 * (30 - 32 * np.cos(th) + 2 * np.cos(2 * th)) / (12 * h ** 2)
+    return np.sort((s[:, None, None] + s[None, :, None] + s[None, None, :]).ravel())
+
+
+@pytest.mark.parametrize("shift", [0.0, -1.7])
+def test_zero_potential_closed_form(shift):
+    # 8^3 7-point, h = 0.5: shells end at 1, 7, 19, 27 -> k = 19 is a shell boundary
+    N, k, q = 8, 19, 4
+    ex = laplacian_spectrum(N, 0.5, 2) + shift
+    assert ex[k] - ex[k - 1] > 1.0
+    p = I.small_problem(N=N, k=k, q=q, nwells=0, tol=1e-10)
+    p = I.Problem(p.name, p.grid, np.full(N ** 3, shift), k, q, p.nbuf, 5, 1e-10, 99)
+    (lam, X, info), A = run(p)
+    np.testing.assert_allclose(lam, ex[:k], atol=1e-11)
+
+
+def test_zero_potential_13pt_closed_form():
+    N, q = 8, 4
+    ex = laplacian_spectrum(N, 0.5, 4)
+    k = 7
+    assert ex[k] - ex[k - 1] > 0.5
+    p = I.small_problem(N=N, k=k, q=q, order=4, nwells=0, tol=1e-10)
+    (lam, X, info), A = run(p)
+    np.testing.assert_allclose(lam, ex[:k], atol=1e-11)
+
+
+def test_lobpcg_limit():
+    # q = K: one block holds every column; converged values agree with scipy's LOBPCG
+    p = I.small_problem(N=8, k=8, q=12, nbuf=4, tol=1e-9)
+    (lam, X, info), A = run(p)
+    g = p.grid
+    op = spla.LinearOperator((g.n, g.n), matvec=lambda x: A(np.ravel(x)), matmat=A, dtype=np.float64)
+    d = stencil.diag_h(p.V, g.h, g.order)
+    Tm = spla.LinearOperator((g.n, g.n), matvec=lambda x: np.ravel(x) / d,
+                             matmat=lambda Y: Y / d[:, None], dtype=np.float64)
+    ref, _ = spla.lobpcg(op, p.start(), M=Tm, largest=False, tol=1e-10, maxiter=500)
+    np.testing.assert_allclose(lam, np.sort(ref)[:p.k], rtol=1e-9, atol=1e-9)
+
+
+def test_theorem2_identity():
+    # x_j^* A w_j = r_j^* T r_j for X orthonormal, W = (I - X X^*) T R
+    p = I.small_problem(N=8, k=6, q=2)
+    g = p.grid
+    A = lambda X: stencil.apply_h(X, p.V, g.N, g.h, g.order)
+    t = 1.0 / stencil.diag_h(p.V, g.h, g.order)
+    X, _ = dense.cholqr(p.start())
+    AX = A(X)
+    R = AX - X @ (X.T @ AX)
+    W = t[:, None] * R
+    W -= X @ (X.T @ W)
+    lhs = np.sum(X * A(W), axis=0)
+    rhs = np.sum(R * (t[:, None] * R), axis=0)
+    np.testing.assert_allclose(lhs, rhs, rtol=1e-10)
+
+
+def test_error_paths():
+    p = I.small_problem(N=8, k=12, q=4)
+    with pytest.raises(ppcg_ref.NoConvergence) as e:
+        run(p, max_iter=3)
+    assert e.value.info.iters == 3 and e.value.lam.shape == (12,)
+    X0 = p.start()
+    X0[:, 4] = X0[:, 7]
+    with pytest.raises(dense.RankError):
+        run(p, X0=X0)
+    g = p.grid
+    with pytest.raises(ValueError):
+        ppcg_ref.ppcg(lambda X: X, -np.ones(g.n), p.start(), p.k, p.q, 1e-6, 5)
+
+
+def test_wells16_matches_golden_brute_force():
+    """The 16^3, k = 64 workload at tol 1e-6 against the stored brute-force
+    eigenvalues (tests/golden/wells16_k64_brute.txt, written by
+    tests/golden/make_golden.py from oracle.brute)."""
+    import os
+    p = I.wells16()
+    ref = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "wells16_k64_brute.txt"))
+    (lam, X, info), A = run(p)
+    assert np.abs(lam - ref[:p.k]).max() / np.abs(ref).max() < 1e-9
+    R = A(X) - X * lam[None, :]
+    assert np.linalg.norm(R) / np.linalg.norm(lam) <= p.tol
