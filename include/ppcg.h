@@ -1,0 +1,132 @@
+/*
+ * libppcg -- C ABI of the PPCG eigensolver hot path on MI355X (gfx950).
+ *
+ * Method: Vecharynski, Yang, Pask, "A Projected Preconditioned Conjugate
+ * Gradient Algorithm for Computing Many Extreme Eigenpairs of a Hermitian
+ * Matrix".  The problem statement (section 1; Algorithm 3 in the appendix):
+ * given a Hermitian A (only products A x are needed), a Hermitian positive
+ * definite preconditioner T, a start block X0 with k + nbuf columns, the
+ * Rayleigh-Ritz period rr_period and the sub-block width sbsize, return
+ * approximate eigenvectors X (n x k) and eigenvalues Lambda of the k
+ * algebraically smallest eigenvalues.
+ *
+ * Here A is the finite-difference Kohn-Sham operator
+ *     H = -1/2 Lap_h + diag(V)
+ * on a periodic N x N x N grid with spacing h (7-point or 13-point
+ * Laplacian), applied matrix-free, and T = diag(H)^{-1} (Jacobi).
+ *
+ * Conventions
+ *   - grid index of point (i, j, l) is i + N*(j + N*l) (x fastest); n = N^3.
+ *   - blocks are column-major n x ncols with leading dimension n, float64.
+ *   - every pointer marked "device" is a device pointer on the handle's
+ *     device; the caller owns it and keeps it alive until the call returns.
+ *     The library owns its workspace (allocated lazily per shape inside the
+ *     handle, released by ppcg_destroy).
+ *   - all work is ordered on the stream given to ppcg_create; calls return
+ *     after the stream work they enqueue has finished (synchronous).
+ *   - a handle is not thread-safe; use one handle per host thread.
+ *   - errors are return codes; ppcg_last_error() gives a message.
+ */
+#ifndef PPCG_H
+#define PPCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PPCG_OK = 0,
+  PPCG_EINVAL = 1,    /* bad argument: sizes, null pointers, NaN in V */
+  PPCG_ENOTHPD = 2,   /* Jacobi preconditioner not positive definite (diag(H) <= 0);
+                         Theorem 2 assumes an HPD T */
+  PPCG_ERANK = 3,     /* Cholesky breakdown of X^H X (Cholesky-QR) or of the
+                         Rayleigh-Ritz Gram, or a sub-block pencil of rank < sbsize */
+  PPCG_ENOCONV = 4,   /* max_iter reached; outputs hold the last Rayleigh-Ritz
+                         result, info->resid_final its residual */
+  PPCG_ENOSTATE = 5,  /* ppcg_grad called without a successful real solve */
+  PPCG_EHIP = 6,      /* HIP runtime failure */
+  PPCG_ENOMEM = 7     /* device allocation failed */
+} ppcg_status;
+
+typedef enum { PPCG_FP64 = 0, PPCG_MIXED = 1 } ppcg_precision;
+typedef enum { PPCG_PRECOND_NONE = 0, PPCG_PRECOND_JACOBI = 1 } ppcg_precond;
+
+typedef struct {
+  int32_t precision;  /* ppcg_precision.  PPCG_MIXED keeps W, P, HW, HP and the
+                         projections X^H W, X^H P in float32 (MFMA, float32
+                         accumulation); X, the Cholesky-QR, every Gram of the
+                         sub-block pencils, the pencils themselves, the
+                         Rayleigh-Ritz and the residual H X - X G stay float64 */
+  int32_t nbuf;       /* buffer vectors (section 4.3); -1 = sbsize*ceil((k +
+                         max(2, ceil(0.02 k)))/sbsize) - k, so k + nbuf is a
+                         multiple of sbsize */
+  int32_t max_iter;   /* iteration cap (default 20000 when <= 0) */
+  int32_t profile;    /* nonzero: time every kernel launch with HIP events on
+                         the handle's stream (see ppcg_kernel_times) */
+} ppcg_options;
+
+typedef struct {
+  int32_t nx;           /* grid points per dimension N (n = N^3) */
+  double h;             /* grid spacing */
+  int32_t order;        /* 2 = 7-point Laplacian, 4 = 13-point (fourth order) */
+  double kpt[3];        /* Bloch vector; must be 0 (complex operators are not
+                           in this build) */
+  const double* V;      /* device, n potential values */
+  int32_t precond;      /* ppcg_precond; only PPCG_PRECOND_JACOBI */
+} ppcg_operator;
+
+typedef struct {
+  int32_t iters;        /* PPCG iterations (loop bodies executed) */
+  int32_t n_rr;         /* Rayleigh-Ritz steps, the final one included */
+  int32_t n_locked;     /* columns locked when the solve ended */
+  int32_t n_backtrack;  /* sub-block solves redone without P (Theorem 2) */
+  double resid_final;   /* |H X - X Lambda|_F / |Lambda|_F of the returned pairs,
+                           from a fresh float64 H X */
+  double orth_err;      /* |X^H X - I|_F of the returned X */
+  double time_s;        /* wall time of the call */
+  double stage_ms[6];   /* GEMM, stencil (AX), RR, CholQR, small eig, other --
+                           filled when options.profile is set */
+} ppcg_info;
+
+typedef struct ppcg_handle ppcg_handle;
+
+/* Create a handle bound to the current HIP device and to `stream`
+ * (hipStream_t passed as void*; NULL = the default stream).  opt may be NULL
+ * (defaults: FP64, nbuf -1, max_iter 20000, no profiling). */
+ppcg_status ppcg_create(ppcg_handle** out, const ppcg_options* opt, void* stream);
+
+/* Solve for the k lowest eigenpairs (Algorithm 3).
+ *   k         wanted pairs, 0 < k; K = k + nbuf must satisfy K <= n/4
+ *   sbsize    sub-block width q of the block update (section 4.1), 1 <= q <= 16;
+ *             K must be a multiple of q
+ *   tol       relative subspace residual |HX - X(X^H H X)|_F / |X^H H X|_F
+ *             over the k wanted columns (eq. (4.2)); > 0
+ *   rr_period Rayleigh-Ritz every rr_period iterations (section 4.6); >= 1
+ *   X0        device, n x K start block (ld n), need not be orthonormal;
+ *             NULL is an error in this build
+ *   X_out     device, n x k (ld n): eigenvectors, orthonormal
+ *   lambda_out device, k: eigenvalues ascending
+ *   info      may be NULL
+ * On PPCG_ENOCONV the outputs hold the last Rayleigh-Ritz pairs. */
+ppcg_status ppcg_solve(ppcg_handle* h, const ppcg_operator* op, int32_t k, int32_t sbsize, double tol,
+                       int32_t rr_period, const double* X0, double* X_out, double* lambda_out, ppcg_info* info);
+
+/* Y = H X for ncols columns (device, ld n): the operator product alone. */
+ppcg_status ppcg_apply_h(ppcg_handle* h, const ppcg_operator* op, int32_t ncols, const double* X, double* Y);
+
+/* Per-kernel accumulated device time (ms) and launch counts since the last
+ * reset, for kernels launched while options.profile was set.  names,
+ * ms and counts are host arrays of capacity `cap`; returns the number of
+ * kernel kinds written. */
+int32_t ppcg_kernel_times(ppcg_handle* h, const char** names, double* ms, int64_t* counts, int32_t cap);
+void ppcg_reset_kernel_times(ppcg_handle* h);
+
+void ppcg_destroy(ppcg_handle* h);
+const char* ppcg_last_error(const ppcg_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PPCG_H */

@@ -1,0 +1,178 @@
+"""ctypes binding of libppcg (argument marshalling only).
+
+Every step of the solver runs in the HIP library; this module only converts
+torch tensors to device pointers, passes the current torch stream and turns
+status codes into exceptions.  It raises if libppcg.so is missing: there is
+no CPU fallback.
+
+Layout: a block is column-major n x ncols; in torch it is a (ncols, n)
+contiguous float64 CUDA tensor.  ``solve`` accepts the start block as an
+(n, K) tensor (any strides) and returns X as an (n, k) view of such a
+buffer.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_char_p, c_double, c_int32, c_int64, c_void_p
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libppcg.so")
+
+PPCG_FP64, PPCG_MIXED = 0, 1
+STATUS = {0: "PPCG_OK", 1: "PPCG_EINVAL", 2: "PPCG_ENOTHPD", 3: "PPCG_ERANK", 4: "PPCG_ENOCONV",
+          5: "PPCG_ENOSTATE", 6: "PPCG_EHIP", 7: "PPCG_ENOMEM"}
+
+
+class PPCGError(RuntimeError):
+    def __init__(self, code, msg, info=None):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+        self.info = info
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", c_int32), ("nbuf", c_int32), ("max_iter", c_int32), ("profile", c_int32)]
+
+
+class Operator(ctypes.Structure):
+    _fields_ = [("nx", c_int32), ("h", c_double), ("order", c_int32), ("kpt", c_double * 3),
+                ("V", c_void_p), ("precond", c_int32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iters", c_int32), ("n_rr", c_int32), ("n_locked", c_int32), ("n_backtrack", c_int32),
+                ("resid_final", c_double), ("orth_err", c_double), ("time_s", c_double),
+                ("stage_ms", c_double * 6)]
+
+    def as_dict(self):
+        return {f: (list(getattr(self, f)) if f == "stage_ms" else getattr(self, f)) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libppcg.so (raises when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1407_7506_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    L.ppcg_create.argtypes = [POINTER(c_void_p), POINTER(Options), c_void_p]
+    L.ppcg_create.restype = c_int32
+    L.ppcg_solve.argtypes = [c_void_p, POINTER(Operator), c_int32, c_int32, c_double, c_int32,
+                             c_void_p, c_void_p, c_void_p, POINTER(Info)]
+    L.ppcg_solve.restype = c_int32
+    L.ppcg_apply_h.argtypes = [c_void_p, POINTER(Operator), c_int32, c_void_p, c_void_p]
+    L.ppcg_apply_h.restype = c_int32
+    L.ppcg_kernel_times.argtypes = [c_void_p, POINTER(c_char_p), POINTER(c_double), POINTER(c_int64), c_int32]
+    L.ppcg_kernel_times.restype = c_int32
+    L.ppcg_reset_kernel_times.argtypes = [c_void_p]
+    L.ppcg_reset_kernel_times.restype = None
+    L.ppcg_destroy.argtypes = [c_void_p]
+    L.ppcg_destroy.restype = None
+    L.ppcg_last_error.argtypes = [c_void_p]
+    L.ppcg_last_error.restype = c_char_p
+    _lib = L
+    return L
+
+
+def _check_tensor(t, name, numel=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+        raise TypeError(f"{name} must be a CUDA float64 tensor")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+
+
+class Handle:
+    """One libppcg handle bound to the current device and torch stream."""
+
+    def __init__(self, precision: str = "fp64", nbuf: int = -1, max_iter: int = 0, profile: bool = False,
+                 stream=None):
+        import torch
+        self._L = lib()
+        opt = Options(PPCG_MIXED if precision == "mixed" else PPCG_FP64, nbuf, max_iter, 1 if profile else 0)
+        st = stream if stream is not None else torch.cuda.current_stream()
+        self.stream = st
+        h = c_void_p()
+        code = self._L.ppcg_create(byref(h), byref(opt), c_void_p(st.cuda_stream))
+        if code != 0:
+            raise PPCGError(code, "ppcg_create failed")
+        self._h = h
+        self.precision = precision
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.ppcg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def error(self) -> str:
+        return self._L.ppcg_last_error(self._h).decode()
+
+    @staticmethod
+    def operator(V, N, h=0.5, order=2, kpt=(0.0, 0.0, 0.0)):
+        _check_tensor(V, "V", N ** 3)
+        return Operator(int(N), float(h), int(order), (c_double * 3)(*kpt), c_void_p(V.data_ptr()), 1)
+
+    def apply_h(self, V, N, X, h=0.5, order=2):
+        """Y = H X for a (ncols, n) column-major block X."""
+        import torch
+        _check_tensor(X, "X")
+        X = X.contiguous()
+        ncols = X.numel() // (N ** 3)
+        Y = torch.empty_like(X)
+        op = self.operator(V, N, h, order)
+        code = self._L.ppcg_apply_h(self._h, byref(op), ncols, c_void_p(X.data_ptr()), c_void_p(Y.data_ptr()))
+        if code != 0:
+            raise PPCGError(code, self.error())
+        return Y
+
+    def solve(self, V, N, k, sbsize, tol, rr_period, X0, h=0.5, order=2, check=True):
+        """Lowest k eigenpairs.  X0: (n, K) start block (torch CUDA float64).
+        Returns (lam (k,), X (n, k), info dict)."""
+        import torch
+        n = N ** 3
+        _check_tensor(X0, "X0")
+        if X0.dim() != 2 or X0.shape[0] != n:
+            raise ValueError("X0 must have shape (n, K)")
+        X0cm = X0.t().contiguous()
+        Xout = torch.empty((k, n), dtype=torch.float64, device=X0.device)
+        lam = torch.empty(k, dtype=torch.float64, device=X0.device)
+        op = self.operator(V, N, h, order)
+        info = Info()
+        code = self._L.ppcg_solve(self._h, byref(op), int(k), int(sbsize), float(tol), int(rr_period),
+                                  c_void_p(X0cm.data_ptr()), c_void_p(Xout.data_ptr()), c_void_p(lam.data_ptr()),
+                                  byref(info))
+        if code != 0 and check:
+            raise PPCGError(code, self.error(), info.as_dict())
+        return lam, Xout.t(), info.as_dict()
+
+    def kernel_times(self):
+        cap = 64
+        names = (c_char_p * cap)()
+        ms = (c_double * cap)()
+        cnt = (c_int64 * cap)()
+        w = self._L.ppcg_kernel_times(self._h, names, ms, cnt, cap)
+        return {names[i].decode(): (ms[i], cnt[i]) for i in range(w)}
+
+    def reset_kernel_times(self):
+        self._L.ppcg_reset_kernel_times(self._h)
+
+
+def solve(V, N, k, sbsize, tol, rr_period, X0, precision="fp64", **kw):
+    """Convenience wrapper: one-shot handle on the current stream."""
+    h = Handle(precision=precision, nbuf=kw.pop("nbuf", -1), max_iter=kw.pop("max_iter", 0))
+    try:
+        return h.solve(V, N, k, sbsize, tol, rr_period, X0, **kw)
+    finally:
+        h.close()

@@ -1,0 +1,316 @@
+// Per-sub-block work of PPCG (Algorithm 3, steps 11-16; section 4.1):
+//   block_pencil  the 3q x 3q (2q x 2q while P is empty) projected problem
+//                 sym(S^H A S) c = theta sym(S^H S) c, S = [X_j W_j P_j],
+//                 keeping the q lowest pairs with C^H (S^H S) C = I
+//                 (eq. (2.3)); one workgroup per block, everything in LDS
+//   block_update  P_j <- W_j C_W + P_j C_P ;  X_j <- X_j C_X + P_j
+// Safeguards where the paper is silent: diagonal scaling of the pencil, zero
+// W/P columns dropped, a Cholesky of the scaled Gram that drops columns
+// whose pivot falls below pivot_tol (taken in the order X, W, P), and the
+// rank indicator of Theorem 1 (C_X singular) answered by re-solving the
+// block without P (Theorem 2).
+#include "common.hpp"
+#include "jacobi.hpp"
+#include "kernels.hpp"
+
+namespace ppcg {
+
+template <int NB>
+__global__ __launch_bounds__(256) void block_pencil_kernel(PencilArgs a) {
+  constexpr int LD = NB + 1;
+  constexpr int NT = 256;
+  __shared__ double b0[NB * LD], b1[NB * LD], b2[NB * LD], b3[NB * LD];
+  __shared__ double Dv[NB], cs[NB + 2];
+  __shared__ int keep[NB], acc[NB], pq[NB + 2], cnt, nacc, sing;
+  const int tid = threadIdx.x;
+  const int blk = blockIdx.x;
+  const int q = a.q, nS = a.nS;
+  const double* gram = a.gram + (long)blk * a.gstride;
+  const int ldgr = nS;
+  const int c0 = blk * q;
+  int flag = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    const bool allowP = (nS == 3 * q) && pass == 0;
+    // 1. load A (b0) and B (b1)
+    for (int e = tid; e < nS * nS; e += NT) {
+      int i = e % nS, j = e / nS;
+      b1[i + j * LD] = gram[i + j * ldgr];
+      if (j >= q) b0[i + j * LD] = gram[i + (nS + j - q) * ldgr];
+      else if (i < q) b0[i + j * LD] = a.G[(c0 + i) + (long)(c0 + j) * a.ldg];
+    }
+    __syncthreads();
+    for (int e = tid; e < nS * q; e += NT) {
+      int j = e % q, i = q + e / q;  // fill the X columns below the X block
+      if (i < nS) b0[i + j * LD] = b0[j + i * LD];
+    }
+    __syncthreads();
+    for (int e = tid; e < nS * nS; e += NT) {
+      int i = e % nS, j = e / nS;
+      if (i < j) {
+        double va = 0.5 * (b0[i + j * LD] + b0[j + i * LD]);
+        double vb = 0.5 * (b1[i + j * LD] + b1[j + i * LD]);
+        b0[i + j * LD] = va; b0[j + i * LD] = va;
+        b1[i + j * LD] = vb; b1[j + i * LD] = vb;
+      }
+    }
+    __syncthreads();
+    // 2. keep mask and scaling
+    if (tid == 0) {
+      double xmax = 0;
+      for (int i = 0; i < q; ++i) xmax = fmax(xmax, b1[i + i * LD]);
+      for (int i = 0; i < nS; ++i) {
+        double d = b1[i + i * LD];
+        int kp = (i < q) || (d > a.drop_tol * a.drop_tol * xmax);
+        if (i >= 2 * q && !allowP) kp = 0;
+        if (!(d > 0)) kp = 0;
+        keep[i] = kp;
+        Dv[i] = kp ? 1.0 / sqrt(d) : 0.0;
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < nS * nS; e += NT) {
+      int i = e % nS, j = e / nS;
+      double s = Dv[i] * Dv[j];
+      b0[i + j * LD] *= s;
+      b1[i + j * LD] *= s;
+    }
+    __syncthreads();
+    // 3. greedy right-looking Cholesky of the scaled Gram (b1, in place)
+    for (int c = 0; c < nS; ++c) {
+      if (!keep[c]) continue;  // uniform
+      double piv = b1[c + c * LD];
+      if (!(piv >= a.pivot_tol)) {
+        __syncthreads();
+        if (tid == 0) keep[c] = 0;
+        __syncthreads();
+        continue;
+      }
+      double lcc = sqrt(piv);
+      for (int i = c + 1 + tid; i < nS; i += NT)
+        if (keep[i]) b1[i + c * LD] /= lcc;
+      __syncthreads();
+      if (tid == 0) b1[c + c * LD] = lcc;
+      int nr = nS - c - 1;
+      for (int e = tid; e < nr * nr; e += NT) {
+        int i = c + 1 + e % nr, j = c + 1 + e / nr;
+        if (i >= j && keep[i] && keep[j]) b1[i + j * LD] -= b1[i + c * LD] * b1[j + c * LD];
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      int r = 0;
+      for (int i = 0; i < nS; ++i)
+        if (keep[i]) acc[r++] = i;
+      nacc = r;
+    }
+    __syncthreads();
+    const int r = nacc;
+    if (r < q) {
+      // rank failure: leave the block unchanged (C = [I; 0; 0]) and report
+      flag |= 4;
+      double* C = a.C + (long)blk * a.cstride;
+      for (int e = tid; e < 3 * q * q; e += NT) {
+        int i = e % (3 * q), t = e / (3 * q);
+        C[i + t * 3 * q] = (i == t) ? 1.0 : 0.0;
+      }
+      break;
+    }
+    // 4. compact: L (b2, lower r x r) and A (b3)
+    for (int e = tid; e < r * r; e += NT) {
+      int x = e % r, y = e / r;
+      b2[x + y * LD] = (x >= y) ? b1[acc[x] + acc[y] * LD] : 0.0;
+      b3[x + y * LD] = b0[acc[x] + acc[y] * LD];
+    }
+    __syncthreads();
+    // 5. Linv (b1) by forward substitution, one thread per column
+    for (int y = tid; y < r; y += NT) {
+      for (int x = 0; x < r; ++x) b1[x + y * LD] = 0.0;
+      for (int x = y; x < r; ++x) {
+        double s = (x == y) ? 1.0 : 0.0;
+        for (int t = y; t < x; ++t) s -= b2[x + t * LD] * b1[t + y * LD];
+        b1[x + y * LD] = s / b2[x + x * LD];
+      }
+    }
+    __syncthreads();
+    // 6. T = A Linv^T (b2), M = Linv T (b3)
+    for (int e = tid; e < r * r; e += NT) {
+      int x = e % r, y = e / r;
+      double s = 0;
+      for (int t = 0; t <= y; ++t) s += b3[x + t * LD] * b1[y + t * LD];
+      b2[x + y * LD] = s;
+    }
+    __syncthreads();
+    for (int e = tid; e < r * r; e += NT) {
+      int x = e % r, y = e / r;
+      double s = 0;
+      for (int t = 0; t <= x; ++t) s += b1[x + t * LD] * b2[t + y * LD];
+      b3[x + y * LD] = s;
+    }
+    __syncthreads();
+    for (int e = tid; e < r * r; e += NT) {
+      int x = e % r, y = e / r;
+      if (x < y) {
+        double v = 0.5 * (b3[x + y * LD] + b3[y + x * LD]);
+        b3[x + y * LD] = v;
+        b3[y + x * LD] = v;
+      }
+    }
+    __syncthreads();
+    // 7. eigen-decomposition M = Y diag Y^T (Y in b0)
+    double fro = 0;
+    if (tid == 0) {
+      for (int e = 0; e < r * r; ++e) fro += b3[(e % r) + (e / r) * LD] * b3[(e % r) + (e / r) * LD];
+      cs[0] = sqrt(fro);
+    }
+    __syncthreads();
+    double tiny = 2.2e-16 * cs[0];
+    __syncthreads();
+    lds_jacobi<NT>(b3, b0, r, LD, tiny, 40, cs, pq, &cnt);
+    // 8. ascending order (ties by index): rank -> keep[] reused as sel
+    for (int x = tid; x < r; x += NT) {
+      double lx = b3[x + x * LD];
+      int rk = 0;
+      for (int y = 0; y < r; ++y) {
+        double ly = b3[y + y * LD];
+        rk += (ly < lx) || (ly == lx && y < x);
+      }
+      pq[x] = rk;  // temporarily the rank of x
+    }
+    __syncthreads();
+    for (int x = tid; x < r; x += NT) keep[pq[x]] = x;
+    __syncthreads();
+    // 9. C_acc = Linv^T Y[:, sel[0..q)]  (b2, r x q)
+    for (int e = tid; e < r * q; e += NT) {
+      int x = e % r, t = e / r;
+      int col = keep[t];
+      double s = 0;
+      for (int y = x; y < r; ++y) s += b1[y + x * LD] * b0[y + col * LD];
+      b2[x + t * LD] = s;
+    }
+    __syncthreads();
+    // 10. Theorem 1 indicator when P columns took part
+    int usedP = 0;
+    for (int x = 0; x < r; ++x) usedP |= (acc[x] >= 2 * q);
+    if (usedP && pass == 0) {
+      // Gc = C_X^T C_X (b3, q x q); X columns are acc[0..q) when all kept
+      for (int e = tid; e < q * q; e += NT) {
+        int u = e % q, v = e / q;
+        double s = 0;
+        for (int x = 0; x < r; ++x) {
+          int i = acc[x];
+          if (i >= q) break;
+          s += (Dv[i] * b2[x + u * LD]) * (Dv[i] * b2[x + v * LD]);
+        }
+        b3[u + v * LD] = s;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        double gmax = 0;
+        for (int u = 0; u < q; ++u) gmax = fmax(gmax, b3[u + u * LD]);
+        int bad = 0;
+        // sequential Cholesky of the q x q Gram, relative pivot test
+        for (int c = 0; c < q && !bad; ++c) {
+          double piv = b3[c + c * LD];
+          if (!(piv >= a.pivot_tol * gmax)) { bad = 1; break; }
+          double l = sqrt(piv);
+          for (int i = c + 1; i < q; ++i) b3[i + c * LD] /= l;
+          for (int j = c + 1; j < q; ++j)
+            for (int i = j; i < q; ++i) b3[i + j * LD] -= b3[i + c * LD] * b3[j + c * LD];
+        }
+        sing = bad;
+      }
+      __syncthreads();
+      if (sing) {
+        flag |= 2;
+        continue;  // pass 1 without P
+      }
+    }
+    if (usedP) flag |= 1;
+    // 11. write C (nS x q, ld 3q): zero rows for dropped columns
+    double* C = a.C + (long)blk * a.cstride;
+    const int ldc = 3 * q;
+    for (int e = tid; e < ldc * q; e += NT) {
+      int i = e % ldc, t = e / ldc;
+      C[i + t * ldc] = 0.0;
+    }
+    __syncthreads();
+    for (int e = tid; e < r * q; e += NT) {
+      int x = e % r, t = e / r;
+      int i = acc[x];
+      C[i + t * ldc] = Dv[i] * b2[x + t * LD];
+    }
+    break;
+  }
+  if (tid == 0) a.flags[blk] = flag;
+}
+
+void launch_block_pencil(const PencilArgs& a, int nblocks, hipStream_t st) {
+  if (nblocks <= 0) return;
+  if (a.nS <= 24) hipLaunchKernelGGL(block_pencil_kernel<24>, dim3(nblocks), dim3(256), 0, st, a);
+  else hipLaunchKernelGGL(block_pencil_kernel<48>, dim3(nblocks), dim3(256), 0, st, a);
+}
+
+// ---------------------------------------------------------------------------
+template <class TW, int QM>
+__global__ __launch_bounds__(256) void block_update_kernel(BlockUpdArgs a) {
+  __shared__ double Cs[3 * QM * QM];
+  const int q = a.q;
+  const unsigned rtiles = (unsigned)(a.rows / 256);
+  unsigned L = xcd_remap(blockIdx.x, gridDim.x);
+  int blk = L / rtiles;
+  long r = (long)(L % rtiles) * 256 + threadIdx.x;
+  const double* C = a.C + (long)blk * a.cstride;
+  const int ldc = 3 * q;
+  for (int e = threadIdx.x; e < 3 * q * q; e += 256) {
+    int i = e % ldc, t = e / ldc;
+    Cs[i + t * 3 * QM] = C[i + t * ldc];
+  }
+  __syncthreads();
+  const long cb = (long)blk * q * a.ld;
+  double* X = a.X + cb;
+  TW* W = (TW*)a.W + cb;
+  TW* P = (TW*)a.P + cb;
+  double x[QM], w[QM], p[QM];
+#pragma unroll
+  for (int i = 0; i < QM; ++i) {
+    if (i < q) {
+      x[i] = X[r + i * a.ld];
+      w[i] = (double)W[r + i * a.ld];
+      p[i] = a.hasP ? (double)P[r + i * a.ld] : 0.0;
+    } else {
+      x[i] = w[i] = p[i] = 0.0;
+    }
+  }
+  for (int t = 0; t < q; ++t) {
+    const double* ct = Cs + t * 3 * QM;
+    double pn = 0, xn = 0;
+#pragma unroll
+    for (int i = 0; i < QM; ++i) {
+      if (i < q) {
+        pn += w[i] * ct[q + i];
+        if (a.hasP) pn += p[i] * ct[2 * q + i];
+        xn += x[i] * ct[i];
+      }
+    }
+    xn += pn;
+    P[r + t * a.ld] = (TW)pn;
+    X[r + t * a.ld] = xn;
+  }
+}
+
+void launch_block_update(const BlockUpdArgs& a, int nblocks, hipStream_t st) {
+  long blocks = (a.rows / 256) * nblocks;
+  if (blocks == 0) return;
+#define PPCG_BU(QM)                                                                                  \
+  do {                                                                                               \
+    if (a.f32) hipLaunchKernelGGL((block_update_kernel<float, QM>), dim3(blocks), dim3(256), 0, st, a); \
+    else hipLaunchKernelGGL((block_update_kernel<double, QM>), dim3(blocks), dim3(256), 0, st, a);      \
+  } while (0)
+  if (a.q <= 4) PPCG_BU(4);
+  else if (a.q <= 8) PPCG_BU(8);
+  else if (a.q <= 16) PPCG_BU(16);
+  else PPCG_BU(32);
+#undef PPCG_BU
+}
+
+}  // namespace ppcg

@@ -1,0 +1,52 @@
+// Shared device/host definitions for libppcg (gfx950 only).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define PPCG_DEV __device__ __forceinline__
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+namespace ppcg {
+
+// ---------------------------------------------------------------------------
+// Workgroup index remap so that consecutive logical indices run on one XCD.
+// The dispatcher places workgroup b on XCD (b mod 8); the logical index
+// returned here groups the workgroups of each XCD into one contiguous range,
+// so tiles that share operands (same row chunk / same row tile) share an L2.
+// ---------------------------------------------------------------------------
+PPCG_DEV unsigned xcd_remap(unsigned b, unsigned total) {
+  const unsigned nx = 8;
+  unsigned xcd = b % nx, idx = b / nx;
+  unsigned per = total / nx, rem = total % nx;
+  unsigned base = xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per;
+  return base + idx;
+}
+
+// MFMA wrappers: 16x16x4 tiles.  Lane l supplies a = A[l%16][l/16] and
+// b = B[l/16][l%16] (the reduction index is k = l/16).
+//   f64: accumulator value v of lane l is D[4v + l/16][l%16]
+//   f32: accumulator value v of lane l is D[4(l/16) + v][l%16]
+PPCG_DEV d4v mfma(double a, double b, d4v c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+PPCG_DEV f4v mfma(float a, float b, f4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+template <class T> struct AccT;
+template <> struct AccT<double> { typedef d4v type; };
+template <> struct AccT<float> { typedef f4v type; };
+
+// Row (within a 16x16 tile) of accumulator value v in lane l.
+template <class T> PPCG_DEV int acc_row(int l, int v);
+template <> PPCG_DEV int acc_row<double>(int l, int v) { return 4 * v + (l >> 4); }
+template <> PPCG_DEV int acc_row<float>(int l, int v) { return 4 * (l >> 4) + v; }
+
+// Wave-level sum (64 lanes), deterministic butterfly order.
+template <class T> PPCG_DEV T wave_sum(T v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+}  // namespace ppcg
