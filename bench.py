@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""Time to k eigenpairs at relative residual 1e-6 on one MI355X.
+
+Workload (one "step" = one complete solve, every hot-path stage included):
+  wells48_k512 -- 13-point periodic finite-difference Kohn-Sham Hamiltonian on
+  a 48^3 grid (n = 110592, h = 0.5) with 32 seeded Gaussian wells, k = 512
+  wanted pairs, sub-block width 16, 16 buffer vectors, Rayleigh-Ritz every 5
+  iterations, Jacobi preconditioner, random N(0,1) start block, tol 1e-6.
+Both precisions are timed: the mixed FP32-bulk path (the value reported) and
+the plain FP64 path (reported beside it).  Inputs are resident in HBM before
+the timed region starts.
+
+Prints ONE JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time to k eigenpairs @ resid 1e-6 (s), mixed/batched vs plain FP64; HBM GB/s"
+PEAK = {"hbm": 8000.0, "f64": 78.6, "f32": 157.3}   # GB/s, TFLOP/s (MI355X datasheet, dense)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for fn in sorted(os.listdir(os.path.join(ROOT, "paper_1407_7506_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_1407_7506_amd", "csrc", fn), "rb") as f:
+            h.update(fn.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def roofline(kt, precision):
+    """Dominant kernel (largest device time with an algorithmic model)."""
+    best = None
+    for name, (ms, cnt, fl, by) in kt.items():
+        if cnt == 0 or (fl <= 0 and by <= 0):
+            continue
+        if best is None or ms > best[1]:
+            best = (name, ms, cnt, fl, by)
+    if best is None:
+        return None
+    name, ms, cnt, fl, by = best
+    mfma = name.startswith("gram") or name.startswith("update")
+    if mfma:
+        f32 = precision == "mixed" and name in ("gram_proj", "update_proj")
+        achieved = fl / (ms * 1e-3) / 1e12
+        peak = PEAK["f32"] if f32 else PEAK["f64"]
+        out = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+               "frac": round(achieved / peak, 4), "kernel": name, "dtype": "f32" if f32 else "f64"}
+    else:
+        achieved = by / (ms * 1e-3) / 1e9
+        out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK["hbm"], "unit": "GB/s",
+               "frac": round(achieved / PEAK["hbm"], 4), "kernel": name}
+    out.update({"launches": cnt, "avg_launch_us": round(ms / cnt * 1e3, 2),
+                "algorithmic_flops_per_launch": fl / cnt, "algorithmic_bytes_per_launch": by / cnt,
+                "traffic": traffic_for(name)})
+    return out
+
+
+def traffic_for(name):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("source_sha") != kernel_source_sha():
+        return None
+    k = d.get("kernels", {}).get(name)
+    return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(p, gpu_iters, iters):
+    """The oracle as it stands, on the host cores, for `iters` iterations of the
+    same workload; extrapolated to the GPU's iteration count."""
+    import numpy as np
+    from oracle import ppcg_ref, stencil
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count()
+    g = p.grid
+    A = lambda X: stencil.apply_h(X, p.V, g.N, g.h, g.order)
+    T = 1.0 / stencil.diag_h(p.V, g.h, g.order)
+    X0 = p.start()
+    t0 = time.perf_counter()
+    try:
+        ppcg_ref.ppcg(A, T, X0, p.k, p.q, p.tol, p.rr_period, max_iter=iters)
+    except ppcg_ref.NoConvergence:
+        pass
+    dt = time.perf_counter() - t0
+    per_it = dt / iters
+    return {"value": round(per_it * gpu_iters, 2), "unit": "s", "cores": threads, "kind": "oracle",
+            "sample": f"{iters} oracle iterations of the same solve ({dt:.1f} s incl. set-up and "
+                      f"{iters // p.rr_period} Rayleigh-Ritz), scaled to the GPU's {gpu_iters} iterations",
+            "sample_s": round(dt, 2), "s_per_iter": round(per_it, 3)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cpu-iters", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["both", "fp64", "mixed"], default="both")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain device copy of 1 GiB (counter calibration under rocprofv3)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU; --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1407_7506_amd import binding as B
+    from paper_1407_7506_amd import inputs as I
+
+    p = I.wells48()
+    g = p.grid
+    V = torch.tensor(p.V, device="cuda")
+    X0 = torch.tensor(p.start(), device="cuda")
+    torch.cuda.synchronize()
+    if args.calib_copy:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    results = {}
+    precs = ["mixed", "fp64"] if args.only == "both" else [args.only]
+    for prec in precs:
+        h = B.Handle(prec, profile=True)
+        for _ in range(args.warmup):
+            h.solve(V, g.N, p.k, p.q, p.tol, p.rr_period, X0, h=g.h, order=g.order)
+        torch.cuda.synchronize()
+        h.reset_kernel_times()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = []
+        for _ in range(args.steps):
+            lam, X, info = h.solve(V, g.N, p.k, p.q, p.tol, p.rr_period, X0, h=g.h, order=g.order)
+            infos.append(info)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        kt = h.kernel_times()
+        results[prec] = {"s": dt / args.steps, "info": infos[-1], "lam": lam.cpu().numpy(), "kt": kt}
+        log(f"{prec}: {dt / args.steps:.3f} s/solve, iters {infos[-1]['iters']}, rr {infos[-1]['n_rr']}, "
+            f"resid {infos[-1]['resid_final']:.3e}")
+        top = sorted(kt.items(), key=lambda x: -x[1][0])[:8]
+        for name, (ms, cnt, fl, by) in top:
+            log(f"   {name:14s} {ms / args.steps:9.1f} ms/solve {cnt // args.steps:6d} launches "
+                f"{ms / max(cnt, 1) * 1e3:9.1f} us/launch")
+        h.close()
+
+    main_prec = "mixed" if "mixed" in results else "fp64"
+    r = results[main_prec]
+    kt = r["kt"]
+    tot_ms = sum(v[0] for v in kt.values())
+    out = {
+        "metric": METRIC,
+        "value": round(r["s"], 4),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["s"] * 1e3, 2),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64 (mixed)" if main_prec == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "wells48_k512: 13-point 48^3 periodic FD Hamiltonian, 32 seeded Gaussian wells, "
+                               "k=512, sbsize=16, nbuf=16, rr_period=5, tol=1e-6, Jacobi, N(0,1) start",
+                   "n": g.n, "k": p.k, "sbsize": p.q, "K": p.K, "rr_period": p.rr_period, "tol": p.tol,
+                   "precision": main_prec},
+        "iters": r["info"]["iters"],
+        "n_rr": r["info"]["n_rr"],
+        "resid_final": r["info"]["resid_final"],
+        "orth_err": r["info"]["orth_err"],
+        "roofline": roofline(kt, main_prec),
+        "kernel_share": {k: round(v[0] / tot_ms, 4) for k, v in sorted(kt.items(), key=lambda x: -x[1][0])[:8]},
+    }
+    if "fp64" in results and "mixed" in results:
+        lf, lm = results["fp64"]["lam"], results["mixed"]["lam"]
+        out["fp64_s"] = round(results["fp64"]["s"], 4)
+        out["fp64_iters"] = results["fp64"]["info"]["iters"]
+        out["speedup_mixed_vs_fp64"] = round(results["fp64"]["s"] / results["mixed"]["s"], 3)
+        out["mixed_vs_fp64_max_err"] = float(np.abs(lm - lf).max() / np.abs(lf).max())
+        out["roofline_fp64"] = roofline(results["fp64"]["kt"], "fp64")
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(p, r["info"]["iters"], args.cpu_iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

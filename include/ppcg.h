@@ -113,6 +113,10 @@ ppcg_status ppcg_create(ppcg_handle** out, const ppcg_options* opt, void* stream
 ppcg_status ppcg_solve(ppcg_handle* h, const ppcg_operator* op, int32_t k, int32_t sbsize, double tol,
                        int32_t rr_period, const double* X0, double* X_out, double* lambda_out, ppcg_info* info);
 
+/* Columns K = k + nbuf of the start block ppcg_solve expects for this handle's
+ * options (nbuf = -1 resolved by the default rule); -1 on bad arguments. */
+int32_t ppcg_columns(const ppcg_handle* h, int32_t k, int32_t sbsize);
+
 /* Y = H X for ncols columns (device, ld n): the operator product alone. */
 ppcg_status ppcg_apply_h(ppcg_handle* h, const ppcg_operator* op, int32_t ncols, const double* X, double* Y);
 
@@ -121,6 +125,12 @@ ppcg_status ppcg_apply_h(ppcg_handle* h, const ppcg_operator* op, int32_t ncols,
  * ms and counts are host arrays of capacity `cap`; returns the number of
  * kernel kinds written. */
 int32_t ppcg_kernel_times(ppcg_handle* h, const char** names, double* ms, int64_t* counts, int32_t cap);
+/* As ppcg_kernel_times, plus the algorithmic work of the same launches:
+ * flops (floating-point operations the method needs, not the padded work
+ * the kernels do) and bytes (compulsory HBM traffic: every input block read
+ * once, every output block written once).  Any array may be NULL. */
+int32_t ppcg_kernel_stats(ppcg_handle* h, const char** names, double* ms, int64_t* counts, double* flops,
+                          double* bytes, int32_t cap);
 void ppcg_reset_kernel_times(ppcg_handle* h);
 
 void ppcg_destroy(ppcg_handle* h);

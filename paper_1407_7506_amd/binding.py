@@ -66,10 +66,15 @@ def lib():
     L.ppcg_solve.argtypes = [c_void_p, POINTER(Operator), c_int32, c_int32, c_double, c_int32,
                              c_void_p, c_void_p, c_void_p, POINTER(Info)]
     L.ppcg_solve.restype = c_int32
+    L.ppcg_columns.argtypes = [c_void_p, c_int32, c_int32]
+    L.ppcg_columns.restype = c_int32
     L.ppcg_apply_h.argtypes = [c_void_p, POINTER(Operator), c_int32, c_void_p, c_void_p]
     L.ppcg_apply_h.restype = c_int32
     L.ppcg_kernel_times.argtypes = [c_void_p, POINTER(c_char_p), POINTER(c_double), POINTER(c_int64), c_int32]
     L.ppcg_kernel_times.restype = c_int32
+    L.ppcg_kernel_stats.argtypes = [c_void_p, POINTER(c_char_p), POINTER(c_double), POINTER(c_int64),
+                                    POINTER(c_double), POINTER(c_double), c_int32]
+    L.ppcg_kernel_stats.restype = c_int32
     L.ppcg_reset_kernel_times.argtypes = [c_void_p]
     L.ppcg_reset_kernel_times.restype = None
     L.ppcg_destroy.argtypes = [c_void_p]
@@ -124,6 +129,13 @@ class Handle:
         _check_tensor(V, "V", N ** 3)
         return Operator(int(N), float(h), int(order), (c_double * 3)(*kpt), c_void_p(V.data_ptr()), 1)
 
+    def columns(self, k, sbsize):
+        """K = k + nbuf columns the start block must have."""
+        K = self._L.ppcg_columns(self._h, int(k), int(sbsize))
+        if K < 0:
+            raise ValueError("bad k or sbsize")
+        return K
+
     def apply_h(self, V, N, X, h=0.5, order=2):
         """Y = H X for a (ncols, n) column-major block X."""
         import torch
@@ -143,8 +155,9 @@ class Handle:
         import torch
         n = N ** 3
         _check_tensor(X0, "X0")
-        if X0.dim() != 2 or X0.shape[0] != n:
-            raise ValueError("X0 must have shape (n, K)")
+        K = self.columns(k, sbsize)
+        if X0.dim() != 2 or X0.shape[0] != n or X0.shape[1] != K:
+            raise ValueError(f"X0 must have shape (n, K) = ({n}, {K})")
         X0cm = X0.t().contiguous()
         Xout = torch.empty((k, n), dtype=torch.float64, device=X0.device)
         lam = torch.empty(k, dtype=torch.float64, device=X0.device)
@@ -158,12 +171,15 @@ class Handle:
         return lam, Xout.t(), info.as_dict()
 
     def kernel_times(self):
+        """{kernel kind: (total ms, launches, algorithmic flops, compulsory bytes)}"""
         cap = 64
         names = (c_char_p * cap)()
         ms = (c_double * cap)()
         cnt = (c_int64 * cap)()
-        w = self._L.ppcg_kernel_times(self._h, names, ms, cnt, cap)
-        return {names[i].decode(): (ms[i], cnt[i]) for i in range(w)}
+        fl = (c_double * cap)()
+        by = (c_double * cap)()
+        w = self._L.ppcg_kernel_stats(self._h, names, ms, cnt, fl, by, cap)
+        return {names[i].decode(): (ms[i], cnt[i], fl[i], by[i]) for i in range(w)}
 
     def reset_kernel_times(self):
         self._L.ppcg_reset_kernel_times(self._h)

@@ -4,6 +4,10 @@
 //                 keeping the q lowest pairs with C^H (S^H S) C = I
 //                 (eq. (2.3)); one workgroup per block, everything in LDS
 //   block_update  P_j <- W_j C_W + P_j C_P ;  X_j <- X_j C_X + P_j
+// In the mixed-precision path H W and H P are float32 products, whose
+// rounding error (~1e-7 |H| |w|) would swamp the X-W coupling x^H H w =
+// r^H T r (Theorem 2), which is second order in the residual; those entries
+// are therefore taken from the float64 H X as (H X_j)^H W_j.
 // Safeguards where the paper is silent: diagonal scaling of the pencil, zero
 // W/P columns dropped, a Cholesky of the scaled Gram that drops columns
 // whose pivot falls below pivot_tol (taken in the order X, W, P), and the
@@ -26,7 +30,7 @@ __global__ __launch_bounds__(256) void block_pencil_kernel(PencilArgs a) {
   const int blk = blockIdx.x;
   const int q = a.q, nS = a.nS;
   const double* gram = a.gram + (long)blk * a.gstride;
-  const int ldgr = nS;
+  const int ldgr = nS + (a.ax_rows ? q : 0);
   const int c0 = blk * q;
   int flag = 0;
   for (int pass = 0; pass < 2; ++pass) {
@@ -35,8 +39,12 @@ __global__ __launch_bounds__(256) void block_pencil_kernel(PencilArgs a) {
     for (int e = tid; e < nS * nS; e += NT) {
       int i = e % nS, j = e / nS;
       b1[i + j * LD] = gram[i + j * ldgr];
-      if (j >= q) b0[i + j * LD] = gram[i + (nS + j - q) * ldgr];
-      else if (i < q) b0[i + j * LD] = a.G[(c0 + i) + (long)(c0 + j) * a.ldg];
+      if (j >= q) {
+        // X rows of the W / P columns: (H X_j)^H W_j and (H X_j)^H P_j when available
+        b0[i + j * LD] = (a.ax_rows && i < q) ? gram[(nS + i) + j * ldgr] : gram[i + (nS + j - q) * ldgr];
+      } else if (i < q) {
+        b0[i + j * LD] = a.G[(c0 + i) + (long)(c0 + j) * a.ldg];
+      }
     }
     __syncthreads();
     for (int e = tid; e < nS * q; e += NT) {

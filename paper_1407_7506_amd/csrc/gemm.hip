@@ -55,7 +55,9 @@ template <> struct VecLoad<float, 4> {
 // reduction index k = g maps to physical row r0 + g*Q + e in step e: every
 // lane issues one contiguous vector load per column and step.
 // ---------------------------------------------------------------------------
-template <class T, int TM, int TN>
+// SITE only distinguishes call sites in profiles (projection Grams = 1,
+// per-block Grams = 2, others = 0); the code is identical.
+template <class T, int TM, int TN, int SITE>
 __global__ __launch_bounds__(64) void gram_kernel(GramArgs a) {
   constexpr int Q = 4;
   typedef typename AccT<T>::type acc_t;
@@ -181,7 +183,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs r) {
 // 16 consecutive rows of a column per lane group.  Lane group g reads
 // Q consecutive k of the small matrix B in one vector load.
 // ---------------------------------------------------------------------------
-template <class T, int TJ, int TR>
+template <class T, int TJ, int TR, int SITE>
 __global__ __launch_bounds__(64) void update_kernel(UpdateArgs a) {
   constexpr int Q = 4;
   typedef typename AccT<T>::type acc_t;
@@ -260,7 +262,7 @@ __global__ __launch_bounds__(64) void update_kernel(UpdateArgs a) {
           if (scaled) c *= (T)a.dsc[r];
           val += beta * c;
         }
-        cp[r] = val;
+        if (!a.c0_keep) cp[r] = val;
         if (c32) c32[r] = (float)val;
       }
     }
@@ -276,7 +278,9 @@ void launch_gram_t(const GramArgs& a0, int njobs, hipStream_t st) {
   a.tiles_i = (a.M + 16 * TM - 1) / (16 * TM);
   a.tiles_j = (a.N + 16 * TN - 1) / (16 * TN);
   long blocks = (long)a.tiles_i * a.tiles_j * a.splits * njobs;
-  hipLaunchKernelGGL((gram_kernel<T, TM, TN>), dim3(blocks), dim3(64), 0, st, a);
+  if (a.site == 1) hipLaunchKernelGGL((gram_kernel<T, TM, TN, 1>), dim3(blocks), dim3(64), 0, st, a);
+  else if (a.site == 2) hipLaunchKernelGGL((gram_kernel<T, TM, TN, 2>), dim3(blocks), dim3(64), 0, st, a);
+  else hipLaunchKernelGGL((gram_kernel<T, TM, TN, 0>), dim3(blocks), dim3(64), 0, st, a);
 }
 
 void launch_gram(const GramArgs& a, int njobs, bool f32acc, hipStream_t st) {
@@ -299,8 +303,13 @@ void launch_update(const UpdateArgs& a0, int njobs, bool f32, hipStream_t st) {
   a.tiles_r = (int)(a.rows / (16 * TR));
   long blocks = (long)a.tiles_j * a.tiles_r * njobs;
   if (blocks == 0) return;
-  if (f32) hipLaunchKernelGGL((update_kernel<float, TJ, TR>), dim3(blocks), dim3(64), 0, st, a);
-  else hipLaunchKernelGGL((update_kernel<double, TJ, TR>), dim3(blocks), dim3(64), 0, st, a);
+  if (f32) {
+    if (a.site == 1) hipLaunchKernelGGL((update_kernel<float, TJ, TR, 1>), dim3(blocks), dim3(64), 0, st, a);
+    else hipLaunchKernelGGL((update_kernel<float, TJ, TR, 0>), dim3(blocks), dim3(64), 0, st, a);
+  } else {
+    if (a.site == 1) hipLaunchKernelGGL((update_kernel<double, TJ, TR, 1>), dim3(blocks), dim3(64), 0, st, a);
+    else hipLaunchKernelGGL((update_kernel<double, TJ, TR, 0>), dim3(blocks), dim3(64), 0, st, a);
+  }
 }
 
 }  // namespace ppcg

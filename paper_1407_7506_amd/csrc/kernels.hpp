@@ -30,6 +30,7 @@ struct GramArgs {
   int tiles_i, tiles_j;
   int upper_only;
   long job_col_off;   // per-job element offset added to all column pointers
+  int site;           // call site (selects a distinct kernel symbol for profiling)
 };
 
 struct ReduceArgs {
@@ -59,7 +60,9 @@ struct UpdateArgs {
   long rows;       // multiple of 64
   double alpha, beta;
   int b_upper;     // B upper triangular: k range limited per column tile
+  int c0_keep;     // 1: do not overwrite C0 (only the float copy C32 is written)
   int tiles_j, tiles_r;
+  int site;        // call site (selects a distinct kernel symbol for profiling)
 };
 
 void launch_gram(const GramArgs& a, int njobs, bool f32acc, hipStream_t st);
@@ -100,6 +103,8 @@ struct PencilArgs {
   const double* G;      // X^H A X of the active columns (m x m, ldg); the X block is G[jq.., jq..]
   int ldg;
   int q, nS;            // nS = 2q (no P) or 3q
+  int ax_rows;          // 1: the Gram has q extra rows (H X_j)^H [...] after the nS rows of S, and the
+                        //    X-W / X-P blocks of the projected A are taken from them
   double* C;            // out: per block nS x q (ld 3q), stride cstride
   long cstride;
   int* flags;           // out: per block bit0 = P used, bit1 = backtracked, bit2 = rank failure

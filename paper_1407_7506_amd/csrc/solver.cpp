@@ -76,8 +76,9 @@ struct Prof {
   std::map<std::string, int> ids;
   std::vector<double> ms;
   std::vector<long> counts;
-  int cur = -1;
-  hipEvent_t cur_ev = nullptr;
+  std::vector<double> flops, bytes;
+  struct Open { int kind; hipEvent_t ev; double fl, by; };
+  std::vector<Open> open;
   hipEvent_t get() {
     if (!pool.empty()) {
       hipEvent_t e = pool.back();
@@ -96,19 +97,26 @@ struct Prof {
     ids[n] = k;
     ms.push_back(0);
     counts.push_back(0);
+    flops.push_back(0);
+    bytes.push_back(0);
     return k;
   }
-  void begin(const char* n) {
+  // fl / by: algorithmic flops and compulsory HBM bytes of the launch
+  void begin(const char* n, double fl = 0, double by = 0) {
     if (!on) return;
-    cur = id(n);
-    cur_ev = get();
-    HIPCHECK(hipEventRecord(cur_ev, st));
+    hipEvent_t e = get();
+    HIPCHECK(hipEventRecord(e, st));
+    open.push_back({id(n), e, fl, by});
   }
   void end() {
-    if (!on) return;
+    if (!on || open.empty()) return;
+    Open o = open.back();
+    open.pop_back();
     hipEvent_t b = get();
     HIPCHECK(hipEventRecord(b, st));
-    pending.push_back({cur, cur_ev, b});
+    pending.push_back({o.kind, o.ev, b});
+    flops[o.kind] += o.fl;
+    bytes[o.kind] += o.by;
     if (pending.size() > 4096) collect();
   }
   void collect() {
@@ -128,6 +136,8 @@ struct Prof {
     collect();
     std::fill(ms.begin(), ms.end(), 0.0);
     std::fill(counts.begin(), counts.end(), 0L);
+    std::fill(flops.begin(), flops.end(), 0.0);
+    std::fill(bytes.begin(), bytes.end(), 0.0);
   }
   ~Prof() {
     for (auto e : pool) hipEventDestroy(e);
@@ -136,7 +146,7 @@ struct Prof {
 
 struct Scope {
   Prof& p;
-  Scope(Prof& p_, const char* n) : p(p_) { p.begin(n); }
+  Scope(Prof& p_, const char* n, double fl = 0, double by = 0) : p(p_) { p.begin(n, fl, by); }
   ~Scope() { p.end(); }
 };
 
@@ -151,6 +161,7 @@ struct ppcg_handle {
   // workspace
   DBuf X, Xt, W, P, AW, AP;           // float64 blocks (W..AP only in FP64 mode)
   DBuf X32, W32, P32, AW32, AP32;     // float32 blocks (mixed mode)
+  DBuf AXm;                           // float64 H X kept in mixed mode
   DBuf Vd, V32, td;
   DBuf G, GWP, L, Li, Rinv, SAS, SS, V1, Mr, Yv, Cc, lam;
   DBuf part, bgram, bC, bflags, cn, scal, iflag, eigw, dminp;
@@ -158,7 +169,7 @@ struct ppcg_handle {
   double* hpind = nullptr;
   size_t hpin_bytes = 0;
   ~ppcg_handle() {
-    for (DBuf* b : {&X, &Xt, &W, &P, &AW, &AP, &X32, &W32, &P32, &AW32, &AP32, &Vd, &V32, &td, &G, &GWP, &L, &Li,
+    for (DBuf* b : {&X, &Xt, &W, &P, &AW, &AP, &X32, &W32, &P32, &AW32, &AP32, &AXm, &Vd, &V32, &td, &G, &GWP, &L, &Li,
                     &Rinv, &SAS, &SS, &V1, &Mr, &Yv, &Cc, &lam, &part, &bgram, &bC, &bflags, &cn, &scal, &iflag,
                     &eigw, &dminp})
       b->release();
@@ -214,7 +225,9 @@ struct Solve {
   // ---- kernels --------------------------------------------------------------
   void stencil(const void* Xs, void* Ys, int ncols, bool f32) {
     if (ncols <= 0) return;
-    Scope s(prof, f32 ? "stencil_f32" : "stencil_f64");
+    double es = f32 ? 4 : 8;
+    Scope s(prof, f32 ? "stencil_f32" : "stencil_f64", (order == 4 ? 16.0 : 10.0) * n * ncols,
+            2.0 * es * n * ncols + es * n);
     StencilArgs a{};
     a.X = Xs;
     a.Y = Ys;
@@ -239,6 +252,12 @@ struct Solve {
     return c;
   }
 
+  static int site_of(const char* name) {
+    if (!strcmp(name, "gram_proj") || !strcmp(name, "update_proj")) return 1;
+    if (!strcmp(name, "gram_block")) return 2;
+    return 0;
+  }
+
   int pick_splits(long tiles, long njobs, long rws) {
     long target = 2048;
     long s = (target + tiles * njobs - 1) / (tiles * njobs);
@@ -253,11 +272,12 @@ struct Solve {
     if (M <= 0 || Nn <= 0) return;
     long tiles = (long)((M + 63) / 64) * ((Nn + 63) / 64);
     int splits = pick_splits(tiles, njobs, rws);
+    size_t es = f32acc ? 4 : 8;
+    size_t one = (size_t)njobs * M * Nn * es;
+    if (one > H->part.bytes) throw PpcgError{PPCG_EINVAL, "internal: partial buffer too small"};
+    splits = (int)std::min<size_t>((size_t)splits, H->part.bytes / one);
     long chunk = round_up((rws + splits - 1) / splits, 16);
     splits = (int)((rws + chunk - 1) / chunk);
-    size_t es = f32acc ? 4 : 8;
-    size_t need = (size_t)njobs * splits * M * Nn * es;
-    if (need > H->part.bytes) throw PpcgError{PPCG_EINVAL, "internal: partial buffer too small"};
     GramArgs g{};
     g.A = A;
     g.B = B;
@@ -275,7 +295,11 @@ struct Solve {
     g.upper_only = upper;
     g.job_col_off = job_col_off;
     {
-      Scope s(prof, name);
+      double nn = (double)std::min(rws, n), es_in = f32acc ? 4.0 : 8.0;
+      double fl = upper ? (double)M * (M + 1) * nn : 2.0 * M * Nn * nn;
+      double by = (double)njobs * (upper ? M : (M + Nn)) * nn * es_in;
+      Scope s(prof, name, fl * njobs, by);
+      g.site = site_of(name);
       launch_gram(g, njobs, f32acc, st);
     }
     ReduceArgs r{};
@@ -299,7 +323,7 @@ struct Solve {
   // C = beta (D C) + alpha A B
   void update(const void* A, long lda, int Kk, const void* B, long ldb, int Nn, void* C0, void* C1, int N0, long ldc,
               float* C32, const double* dsc, long rws, double alpha, double beta, bool b_upper, bool f32,
-              const char* name = "update") {
+              const char* name = "update", bool c0_keep = false) {
     if (Nn <= 0 || rws <= 0) return;
     UpdateArgs u{};
     u.A = A;
@@ -318,7 +342,12 @@ struct Solve {
     u.alpha = alpha;
     u.beta = beta;
     u.b_upper = b_upper;
-    Scope s(prof, name);
+    u.c0_keep = c0_keep;
+    double nn = (double)std::min(rws, n), es = f32 ? 4.0 : 8.0;
+    double fl = b_upper ? (double)Nn * (Nn + 1) * nn : 2.0 * Kk * Nn * nn;
+    double by = ((double)Kk + Nn * (beta != 0 ? 2.0 : 1.0)) * nn * es + (C32 ? 4.0 * Nn * nn : 0.0);
+    Scope s(prof, name, fl, by);
+    u.site = site_of(name);
     launch_update(u, 1, f32, st);
   }
 
@@ -328,6 +357,7 @@ struct Solve {
     H->X.ensure(nk8);
     H->Xt.ensure(nk8);
     if (mixed) {
+      H->AXm.ensure(nk8);
       H->X32.ensure(nk4);
       H->W32.ensure(nk4);
       H->P32.ensure(nk4);
@@ -353,7 +383,7 @@ struct Solve {
     H->dminp.ensure(1024 * 8);
     int s = K / q;
     int nS = 3 * q;
-    H->bgram.ensure((size_t)s * nS * (2 * nS - q) * 8);
+    H->bgram.ensure((size_t)s * (nS + q) * (2 * nS - q) * 8);
     H->bC.ensure((size_t)s * 3 * q * q * 8);
     H->bflags.ensure((size_t)s * 4 + 256);
     H->eigw.ensure(eig_workspace_bytes(K));
@@ -368,14 +398,14 @@ struct Solve {
     };
     acc(K, 2 * K, 1, rows, mixed ? 4 : 8);
     acc(K, K, 1, rows, 8);
-    acc(nS, 2 * nS - q, s, rows, 8);
+    acc(nS + q, 2 * nS - q, s, rows, 8);
     acc(K, K, 1, Kp, 8);
     H->part.ensure(need);
     H->pinned((size_t)(4 * Kp + 64) * 8);
     // zero everything that carries padding rows
     std::vector<DBuf*> blocks = {&H->X, &H->Xt};
     if (mixed) {
-      for (DBuf* b : {&H->X32, &H->W32, &H->P32, &H->AW32, &H->AP32}) blocks.push_back(b);
+      for (DBuf* b : {&H->X32, &H->W32, &H->P32, &H->AW32, &H->AP32, &H->AXm}) blocks.push_back(b);
     } else {
       for (DBuf* b : {&H->W, &H->P, &H->AW, &H->AP}) blocks.push_back(b);
     }
@@ -426,16 +456,20 @@ struct Solve {
   // Column norms of the wanted active columns go to cn.
   void residual(int m) {
     double* Xa = X() + (long)nl * ld;
-    double* R = mixed ? Xt() + (long)nl * ld : H->W.d() + (long)nl * ld;
+    // plain: H X and then W overwrite the W block; mixed: H X stays in AXm (float64)
+    // and only the float copy W32 of the residual is written
+    double* R = mixed ? H->AXm.d() + (long)nl * ld : H->W.d() + (long)nl * ld;
     stencil(Xa, R, m, false);
     ColSet A = cols1(Xa, m, false), B = cols1(R, m, false);
     gram(A, B, m, m, rows, ld, nullptr, 0, H->G.p, Kp, true, false, 1, 0, 0, "gram_xax");
-    update(Xa, ld, m, H->G.p, Kp, m, R, nullptr, m, ld, mixed ? H->W32.f() + (long)nl * ld : nullptr, nullptr, rows,
-           -1.0, 1.0, false, false, "update_resid");
+    float* W32a = mixed ? H->W32.f() + (long)nl * ld : nullptr;
+    update(Xa, ld, m, H->G.p, Kp, m, R, nullptr, m, ld, W32a, nullptr, rows, -1.0, 1.0, false, false, "update_resid",
+           mixed);
     int nwa = std::max(0, k - nl);
     {
       Scope s(prof, "colnorm");
-      launch_colnorm2(R, 0, ld, rows, nwa, H->cn.d(), st);
+      if (mixed) launch_colnorm2(W32a, 1, ld, rows, nwa, H->cn.d(), st);
+      else launch_colnorm2(R, 0, ld, rows, nwa, H->cn.d(), st);
       launch_frob2_sub(H->G.d(), Kp, nwa, H->scal.d(), st);
     }
   }
@@ -461,9 +495,8 @@ struct Solve {
   // for all columns, the locking decision and the new active split.  Returns the
   // fresh residual of the k lowest pairs.
   double rayleigh_ritz() {
-    Scope rs(prof, "rr_total");
     double* S = X();
-    double* AS = mixed ? Xt() : H->AW.d();
+    double* AS = mixed ? H->AXm.d() : H->AW.d();
     stencil(S, AS, K, false);
     ColSet A = cols1(S, K, false);
     gram(A, cols1(AS, K, false), K, K, rows, ld, nullptr, 0, H->SAS.p, Kp, true, false, 1, 0, 0, "gram_rr");
@@ -494,12 +527,17 @@ struct Solve {
            false, false, "update_rot");
     swapX();
     // fresh residual W = H X - X Lambda (all K columns)
-    double* R = mixed ? Xt() : H->W.d();
+    double* R = mixed ? H->AXm.d() : H->W.d();
     stencil(X(), R, K, false);
     {
       Scope s(prof, "ritz_resid");
-      launch_ritz_resid(R, X(), H->lam.d(), R, mixed ? H->W32.f() : nullptr, ld, rows, K, st);
-      launch_colnorm2(R, 0, ld, rows, K, H->cn.d(), st);
+      if (mixed) {
+        launch_ritz_resid(R, X(), H->lam.d(), nullptr, H->W32.f(), ld, rows, K, st);
+        launch_colnorm2(H->W32.p, 1, ld, rows, K, H->cn.d(), st);
+      } else {
+        launch_ritz_resid(R, X(), H->lam.d(), R, nullptr, ld, rows, K, st);
+        launch_colnorm2(R, 0, ld, rows, K, H->cn.d(), st);
+      }
     }
     HIPCHECK(hipMemcpyAsync(H->hpind, H->cn.p, (size_t)K * 8, hipMemcpyDeviceToHost, st));
     HIPCHECK(hipMemcpyAsync(H->hpind + Kp, H->lam.p, (size_t)K * 8, hipMemcpyDeviceToHost, st));
@@ -581,7 +619,14 @@ struct Solve {
         A.end[t] = (t + 1) * q;
         A.f32[t] = f[t];
       }
+      if (mixed) {  // rows (H X_j)^H [...] from the float64 H X
+        A.p[na] = H->AXm.d() + off;
+        A.end[na] = (na + 1) * q;
+        A.f32[na] = false;
+        ++na;
+      }
       A.nseg = na;
+      const int Ma = na * q;
       int bi = 0;
       for (int t = 0; t < 5; ++t) {
         if (!hasP && (t == 2 || t == 4)) continue;
@@ -592,11 +637,12 @@ struct Solve {
       }
       B.nseg = bi;
       int Nb = 2 * nS - q;
-      gram(A, B, nS, Nb, rows, ld, nullptr, 0, H->bgram.p, nS, false, false, s, (long)q * ld, (long)nS * Nb,
+      gram(A, B, Ma, Nb, rows, ld, nullptr, 0, H->bgram.p, Ma, false, false, s, (long)q * ld, (long)Ma * Nb,
            "gram_block");
       PencilArgs pa{};
       pa.gram = H->bgram.d();
-      pa.gstride = (long)nS * Nb;
+      pa.gstride = (long)Ma * Nb;
+      pa.ax_rows = mixed;
       pa.G = H->G.d();
       pa.ldg = Kp;
       pa.q = q;
@@ -606,7 +652,7 @@ struct Solve {
       pa.flags = H->bflags.i();
       pa.drop_tol = 1e-14;
       pa.pivot_tol = 1e-12;
-      Scope sc(prof, "block_pencil");
+      Scope sc(prof, "block_pencil", 0, 0);
       launch_block_pencil(pa, s, st);
     }
     // steps 14-15
@@ -622,7 +668,8 @@ struct Solve {
       bu.q = q;
       bu.C = H->bC.d();
       bu.cstride = 3L * q * q;
-      Scope sc(prof, "block_update");
+      Scope sc(prof, "block_update", 6.0 * (double)n * q * q * s * (hasP ? 1.0 : 2.0 / 3.0),
+               (double)n * q * s * (hasP ? 5.0 : 4.0) * (double)esz());
       launch_block_update(bu, s, st);
     }
     hasP = true;
@@ -634,7 +681,6 @@ struct Solve {
       if (H->hpin[j] & 2) info.n_backtrack++;
     }
     if (it % rr_period != 0) {
-      Scope sc(prof, "cholqr_total");
       cholqr(m);
       residual(m);
     } else {
@@ -796,6 +842,16 @@ ppcg_status ppcg_solve(ppcg_handle* h, const ppcg_operator* op, int32_t k, int32
   });
 }
 
+int32_t ppcg_columns(const ppcg_handle* h, int32_t k, int32_t sbsize) {
+  if (!h || k <= 0 || sbsize < 1) return -1;
+  int nbuf = h->opt.nbuf;
+  if (nbuf < 0) {
+    int extra = std::max(2, (int)std::ceil(0.02 * k));
+    nbuf = sbsize * ((k + extra + sbsize - 1) / sbsize) - k;
+  }
+  return k + nbuf;
+}
+
 ppcg_status ppcg_apply_h(ppcg_handle* h, const ppcg_operator* op, int32_t ncols, const double* X, double* Y) {
   if (!h || !op || !op->V || !X || !Y || ncols < 0) return PPCG_EINVAL;
   return guard(h, [&]() {
@@ -831,6 +887,17 @@ ppcg_status ppcg_apply_h(ppcg_handle* h, const ppcg_operator* op, int32_t ncols,
     HIPCHECK(hipStreamSynchronize(h->st));
     return PPCG_OK;
   });
+}
+
+int32_t ppcg_kernel_stats(ppcg_handle* h, const char** names, double* ms, int64_t* counts, double* flops,
+                          double* bytes, int32_t cap) {
+  if (!h) return 0;
+  int32_t w = ppcg_kernel_times(h, names, ms, counts, cap);
+  for (int32_t i = 0; i < w; ++i) {
+    if (flops) flops[i] = h->prof.flops[i];
+    if (bytes) bytes[i] = h->prof.bytes[i];
+  }
+  return w;
 }
 
 int32_t ppcg_kernel_times(ppcg_handle* h, const char** names, double* ms, int64_t* counts, int32_t cap) {
