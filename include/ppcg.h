@@ -59,7 +59,7 @@ typedef struct {
                          accumulation); X, the Cholesky-QR, every Gram of the
                          sub-block pencils, the pencils themselves, the
                          Rayleigh-Ritz and the residual H X - X G stay float64 */
-  int32_t nbuf;       /* buffer vectors (section 4.3); -1 = sbsize*ceil((k +
+  int32_t nbuf;       /* buffer vectors (section 5.3); -1 = sbsize*ceil((k +
                          max(2, ceil(0.02 k)))/sbsize) - k, so k + nbuf is a
                          multiple of sbsize */
   int32_t max_iter;   /* iteration cap (default 20000 when <= 0) */
@@ -99,11 +99,11 @@ ppcg_status ppcg_create(ppcg_handle** out, const ppcg_options* opt, void* stream
 
 /* Solve for the k lowest eigenpairs (Algorithm 3).
  *   k         wanted pairs, 0 < k; K = k + nbuf must satisfy K <= n/4
- *   sbsize    sub-block width q of the block update (section 4.1), 1 <= q <= 16;
+ *   sbsize    sub-block width q of the block update (section 5.1), 1 <= q <= 16;
  *             K must be a multiple of q
  *   tol       relative subspace residual |HX - X(X^H H X)|_F / |X^H H X|_F
- *             over the k wanted columns (eq. (4.2)); > 0
- *   rr_period Rayleigh-Ritz every rr_period iterations (section 4.6); >= 1
+ *             over the k wanted columns (section 5.2); > 0
+ *   rr_period Rayleigh-Ritz every rr_period iterations (section 5.6); >= 1
  *   X0        device, n x K start block (ld n), need not be orthonormal;
  *             NULL is an error in this build
  *   X_out     device, n x k (ld n): eigenvectors, orthonormal

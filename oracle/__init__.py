@@ -9,7 +9,7 @@ of the method's arithmetic.
 Modules
   stencil   matrix-free H = -1/2 Lap_h + diag(V) by np.roll, dense assembly
   dense     small dense steps: Cholesky-QR, block pencils, Rayleigh-Ritz
-  ppcg_ref  the PPCG iteration (paper, Algorithm 3 with sections 4.1-4.7)
+  ppcg_ref  the PPCG iteration (paper, Algorithm 3 with sections 5.1-5.7)
   brute     dense brute-force eigendecomposition for tiny grids
   grad      dL/dV by projected Sternheimer solves and by the dense formula
 

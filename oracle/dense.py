@@ -1,9 +1,10 @@
 """Small dense steps of PPCG (oracle; test infrastructure).
 
   sym            Hermitian part (M + M^H)/2 of a computed Gram
-  cholqr         Cholesky-QR: X^H X = R^H R, X <- X R^{-1} (section 4.5)
+  cholqr         Cholesky-QR: X^H X = R^H R, X <- X R^{-1} (section 5.5)
   block_pencil   the 3q x 3q (2q x 2q without P) projected problem of the block
-                 update (eq. (4.1) with eq. (2.3)); C^H B C = I, the q lowest
+                 update (section 5.1, with the projected problem of section 2);
+                 C^H B C = I, the q lowest
   rayleigh_ritz  the full Rayleigh-Ritz over [X, X_lock] (Algorithm 3, RR branch)
 
 Library primitives used as single steps: scipy.linalg.cholesky,
@@ -23,7 +24,7 @@ Readings where the paper is silent:
     without P (the backtrack of Theorem 2).
 
 Pins: tests/test_oracle_dense.py (scipy.linalg.eigh(A, B) on random pencils,
-the closed-form 2 x 2 problem of eq. (3.5), C^H B C = I, CholQR invariants).
+the closed-form 2 x 2 problem in the proof of Theorem 2, C^H B C = I, CholQR invariants).
 """
 from __future__ import annotations
 

@@ -1,9 +1,9 @@
 """The PPCG iteration, step by step (oracle; test infrastructure).
 
 Follows the paper's detailed algorithm (Algorithm 3, appendix) with the
-practical aspects of section 4: block updates (4.1), the relative subspace
-residual (4.2), buffer vectors (4.3), projections of W and P (4.4),
-Cholesky-QR (4.5), periodic Rayleigh-Ritz (4.6) and soft locking (4.7).
+practical aspects of section 5: block updates (5.1), the relative subspace
+residual (5.2), buffer vectors (5.3), projections of W and P (5.4),
+Cholesky-QR (5.5), periodic Rayleigh-Ritz (5.6) and soft locking (5.7).
 
 Readings of places where the paper is silent or ambiguous (each is listed in
 the design doc as well):

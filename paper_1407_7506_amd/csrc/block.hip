@@ -1,8 +1,8 @@
-// Per-sub-block work of PPCG (Algorithm 3, steps 11-16; section 4.1):
+// Per-sub-block work of PPCG (Algorithm 3, steps 11-16; section 5.1):
 //   block_pencil  the 3q x 3q (2q x 2q while P is empty) projected problem
 //                 sym(S^H A S) c = theta sym(S^H S) c, S = [X_j W_j P_j],
 //                 keeping the q lowest pairs with C^H (S^H S) C = I
-//                 (eq. (2.3)); one workgroup per block, everything in LDS
+//                 (projected problem of section 2); one workgroup per block, everything in LDS
 //   block_update  P_j <- W_j C_W + P_j C_P ;  X_j <- X_j C_X + P_j
 // In the mixed-precision path H W and H P are float32 products, whose
 // rounding error (~1e-7 |H| |w|) would swamp the X-W coupling x^H H w =

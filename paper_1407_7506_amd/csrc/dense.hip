@@ -1,7 +1,7 @@
 // Dense m x m kernels (column-major, ld >= m):
 //   chol_inverse      G = L L^H and L^{-1}, blocked (32 x 32 tiles), for
-//                     Cholesky-QR (section 4.5) and the Rayleigh-Ritz
-//                     reduction to a standard problem (section 4.6)
+//                     Cholesky-QR (section 5.5) and the Rayleigh-Ritz
+//                     reduction to a standard problem (section 5.6)
 //   block_jacobi_eig  Hermitian eigen-decomposition of the reduced
 //                     Rayleigh-Ritz matrix by block Jacobi: pairs of 16-wide
 //                     diagonal blocks are diagonalised in LDS and their

@@ -3,9 +3,9 @@
 //   reduce  deterministic fixed-order sum of the split partials
 //   update  C <- beta * (D C) + alpha * A B with A tall, B small
 // Used for the projections of W and P (Algorithm 3, steps 9-10), the
-// Cholesky-QR Gram and X R^{-1} (section 4.5), the residual
-// W = AX - X (X^H A X) (eq. (2.2)) and the Rayleigh-Ritz Grams and rotation
-// (section 4.6).
+// Cholesky-QR Gram and X R^{-1} (section 5.5), the residual
+// W = AX - X (X^H A X) (section 2) and the Rayleigh-Ritz Grams and rotation
+// (section 5.6).
 #include "common.hpp"
 #include "kernels.hpp"
 

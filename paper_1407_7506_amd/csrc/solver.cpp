@@ -1,5 +1,5 @@
 // Host driver of libppcg: iteration control of the PPCG method (Algorithm 3
-// of the paper, with the practical aspects of section 4), workspace, locking
+// of the paper, with the practical aspects of section 5), workspace, locking
 // and the C ABI.  Every arithmetic step runs in the HIP kernels of this
 // library; the host only decides control flow from a few scalars copied
 // back per iteration.

@@ -31,7 +31,7 @@ def test_block_pencil_matches_scipy(nb, cplx):
 
 
 def test_two_by_two_closed_form():
-    # eq. (3.5): pencil [[a, b], [b, c]] vs diag(1, d) -- lowest root of
+    # 2 x 2 pencil in the proof of Theorem 2: [[a, b], [b, c]] vs diag(1, d) -- lowest root of
     # det(A - theta B) = 0:  d theta^2 - (a d + c) theta + (a c - b^2) = 0
     a, b, c, d = 0.7, 0.3, 2.5, 0.04
     A = np.array([[a, b], [b, c]])
