@@ -164,16 +164,21 @@ __global__ __launch_bounds__(256) void block_pencil_kernel(PencilArgs a) {
       }
     }
     __syncthreads();
-    // 7. eigen-decomposition M = Y diag Y^T (Y in b0)
-    double fro = 0;
-    if (tid == 0) {
-      for (int e = 0; e < r * r; ++e) fro += b3[(e % r) + (e / r) * LD] * b3[(e % r) + (e / r) * LD];
-      cs[0] = sqrt(fro);
+    // 7. eigen-decomposition M = Y diag Y^T (Y in b0).  Rotations below
+    //    1e-12 |M|_F are skipped: the pencil only has to give a good step.
+    {
+      double fro = 0;
+      for (int e = tid; e < r * r; e += NT) {
+        double v = b3[(e % r) + (e / r) * LD];
+        fro += v * v;
+      }
+      fro = wave_sum(fro);
+      if ((tid & 63) == 0) cs[tid >> 6] = fro;
+      __syncthreads();
+      fro = (cs[0] + cs[1]) + (cs[2] + cs[3]);
+      __syncthreads();
+      lds_jacobi<NT>(b3, b0, r, LD, 1e-12 * sqrt(fro), 40, cs, pq, &cnt);
     }
-    __syncthreads();
-    double tiny = 2.2e-16 * cs[0];
-    __syncthreads();
-    lds_jacobi<NT>(b3, b0, r, LD, tiny, 40, cs, pq, &cnt);
     // 8. ascending order (ties by index): rank -> keep[] reused as sel
     for (int x = tid; x < r; x += NT) {
       double lx = b3[x + x * LD];

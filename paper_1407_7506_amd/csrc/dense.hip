@@ -234,20 +234,19 @@ void launch_symmetrize(double* G, int ld, int m, hipStream_t st) {
   hipLaunchKernelGGL(symmetrize_kernel, dim3((t + 255) / 256), dim3(256), 0, st, G, ld, m);
 }
 
+// out[j] = sum_{i < nw} G[i, j]^2 for j < nw (one workgroup per column)
 __global__ __launch_bounds__(256) void frob2_sub_kernel(const double* G, int ld, int nw, double* out) {
+  const double* g = G + (long)blockIdx.x * ld;
   double s = 0;
-  for (long e = threadIdx.x; e < (long)nw * nw; e += 256) {
-    double v = G[(e % nw) + (e / nw) * ld];
-    s += v * v;
-  }
+  for (int i = threadIdx.x; i < nw; i += 256) s += g[i] * g[i];
   __shared__ double red[4];
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) *out = (red[0] + red[1]) + (red[2] + red[3]);
+  if (threadIdx.x == 0) out[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 void launch_frob2_sub(const double* G, int ld, int nw, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(frob2_sub_kernel, dim3(1), dim3(256), 0, st, G, ld, nw, out);
+  if (nw > 0) hipLaunchKernelGGL(frob2_sub_kernel, dim3(nw), dim3(256), 0, st, G, ld, nw, out);
 }
 
 __global__ __launch_bounds__(256) void orth_err2_kernel(const double* G, int ld, int k, double* out) {
@@ -271,6 +270,11 @@ void launch_orth_err2(const double* G, int ld, int k, double* out, hipStream_t s
 // block Jacobi
 // ---------------------------------------------------------------------------
 constexpr int JB = 16;           // block width
+// Rotations are skipped once |M_pq| <= kJacobiRelTol |M|_F.  Off-diagonal
+// entries of that size change the Ritz residual of a column by at most
+// ~1e-13 |M|_F sqrt(K), far below any locking threshold, and the eigenvalues
+// (Rayleigh quotients of the rotated columns) by O(off^2 / gap).
+constexpr double kJacobiRelTol = 1e-13;
 constexpr int J2 = 2 * JB;       // pair size
 constexpr int JLD = J2 + 1;
 
@@ -316,7 +320,7 @@ __global__ __launch_bounds__(256) void bj_norm_kernel(const double* M, int ld, i
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) {
-    *tiny = 2.2e-16 * sqrt((red[0] + red[1]) + (red[2] + red[3]));
+    *tiny = kJacobiRelTol * sqrt((red[0] + red[1]) + (red[2] + red[3]));
     *counter = 0;
   }
 }
@@ -325,7 +329,7 @@ __global__ void bj_zero_kernel(int* counter) { *counter = 0; }
 
 __global__ __launch_bounds__(256) void bj_pair_kernel(double* M, int ld, int m, int nbe, int round, double* Qbuf,
                                                       int* flags, int* counter, const double* tinyp) {
-  __shared__ double S[J2 * JLD], Q[J2 * JLD], R[J2 * 65];
+  __shared__ double S[J2 * JLD], Q[J2 * JLD];
   __shared__ double cs[J2 + 2];
   __shared__ int pq[J2 + 2], cnt, any;
   const int tid = threadIdx.x, t = blockIdx.x;
@@ -358,21 +362,37 @@ __global__ __launch_bounds__(256) void bj_pair_kernel(double* M, int ld, int m, 
     flags[t] = 1;
     atomicAdd(counter, 1);
   }
-  // rows of the pair: M[rows, :] <- Q^T M[rows, :], 64 columns at a time
-  for (int c0 = 0; c0 < m; c0 += 64) {
-    const int nc = min(64, m - c0);
-    __syncthreads();
-    for (int e = tid; e < n2 * nc; e += 256) {
-      int x = e % n2, c = e / n2;
-      R[x + c * J2] = M[gidx(x) + (long)(c0 + c) * ld];
-    }
-    __syncthreads();
-    for (int e = tid; e < n2 * nc; e += 256) {
-      int x = e % n2, c = e / n2;
-      double s = 0;
-      for (int u = 0; u < n2; ++u) s += Q[u + x * JLD] * R[u + c * J2];
-      M[gidx(x) + (long)(c0 + c) * ld] = s;
-    }
+}
+
+// rows of each rotated pair: M[rows, chunk] <- Q^T M[rows, chunk], 64 columns per workgroup
+__global__ __launch_bounds__(256) void bj_row_kernel(double* M, int ld, int m, int nbe, int round, const double* Qbuf,
+                                                     const int* flags) {
+  __shared__ double Q[J2 * JLD], R[J2 * 65];
+  const int t = blockIdx.x;
+  if (!flags[t]) return;
+  const int tid = threadIdx.x;
+  const int nblk = (m + JB - 1) / JB;
+  int I = pair_block(t, round, nbe), J = pair_block(nbe - 1 - t, round, nbe);
+  if (I > J) { int x = I; I = J; J = x; }
+  const int i0 = I * JB, j0 = J * JB;
+  const int nI = I < nblk ? min(JB, m - i0) : 0;
+  const int nJ = J < nblk ? min(JB, m - j0) : 0;
+  const int n2 = nI + nJ;
+  auto gidx = [&](int a) { return a < nI ? i0 + a : j0 + (a - nI); };
+  const double* Qg = Qbuf + (long)t * J2 * J2;
+  for (int e = tid; e < n2 * n2; e += 256) Q[(e % n2) + (e / n2) * JLD] = Qg[(e % n2) + (e / n2) * J2];
+  const int c0 = blockIdx.y * 64;
+  const int nc = min(64, m - c0);
+  for (int e = tid; e < n2 * nc; e += 256) {
+    int x = e % n2, c = e / n2;
+    R[x + c * J2] = M[gidx(x) + (long)(c0 + c) * ld];
+  }
+  __syncthreads();
+  for (int e = tid; e < n2 * nc; e += 256) {
+    int x = e % n2, c = e / n2;
+    double s = 0;
+    for (int u = 0; u < n2; ++u) s += Q[u + x * JLD] * R[u + c * J2];
+    M[gidx(x) + (long)(c0 + c) * ld] = s;
   }
 }
 
@@ -455,6 +475,8 @@ int block_jacobi_eig(double* M, int ld, int m, double* V, int ldv, double* lam, 
     for (int round = 0; round < rounds; ++round) {
       hipLaunchKernelGGL(bj_pair_kernel, dim3(np), dim3(256), 0, st, M, ld, m, nbe, round, w.Q, w.flags, w.counter,
                          w.tiny);
+      hipLaunchKernelGGL(bj_row_kernel, dim3(np, (m + 63) / 64), dim3(256), 0, st, M, ld, m, nbe, round, w.Q,
+                         w.flags);
       hipLaunchKernelGGL(bj_col_kernel, dim3(np, (m + 63) / 64), dim3(256), 0, st, M, ld, w.Vt, m, m, nbe, round,
                          w.Q, w.flags);
     }

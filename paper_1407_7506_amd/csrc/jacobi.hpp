@@ -1,8 +1,10 @@
 // Cyclic two-sided Jacobi for a small real symmetric matrix held in LDS,
 // executed by one workgroup of NT threads.  Pairs follow the round-robin
-// (circle) ordering so the rotations of one round are disjoint; a rotation
-// is applied only when |M_pq| > tiny, and the sweep loop stops after a
-// sweep with no rotation.  On exit diag(M) holds the eigenvalues and V the
+// (circle) ordering, so the rotations of one round are disjoint and the
+// two-sided update J^T M J splits into independent 2x2 blocks
+// (rows of pair a, columns of pair b): one pass per round.  A rotation is
+// applied only when |M_pq| > tiny; the sweep loop stops after a sweep with
+// no rotation.  On exit diag(M) holds the eigenvalues and V the
 // eigenvectors (M_out = V^T M_in V).
 #pragma once
 #include "common.hpp"
@@ -13,9 +15,10 @@ PPCG_DEV int rr_player(int pos, int round, int rr) {
   return pos == 0 ? 0 : ((pos - 1 + round) % (rr - 1)) + 1;
 }
 
+// cs: 2*(r+1)/2 doubles, pq: 2*(r+1)/2 ints (LDS)
 template <int NT>
-PPCG_DEV void lds_jacobi(double* M, double* V, int r, int LD, double tiny, int maxsweeps, double* cs, int* pq,
-                         int* cnt) {
+PPCG_DEV int lds_jacobi(double* M, double* V, int r, int LD, double tiny, int maxsweeps, double* cs, int* pq,
+                        int* cnt) {
   const int tid = threadIdx.x;
   const int rr = r + (r & 1);
   const int np = rr / 2;
@@ -23,9 +26,10 @@ PPCG_DEV void lds_jacobi(double* M, double* V, int r, int LD, double tiny, int m
     int i = e % r, j = e / r;
     V[i + j * LD] = (i == j) ? 1.0 : 0.0;
   }
+  int sweeps = 0;
   if (r <= 1) {
     __syncthreads();
-    return;
+    return 0;
   }
   for (int sweep = 0; sweep < maxsweeps; ++sweep) {
     if (tid == 0) *cnt = 0;
@@ -35,7 +39,6 @@ PPCG_DEV void lds_jacobi(double* M, double* V, int r, int LD, double tiny, int m
         int a = rr_player(tid, round, rr), b = rr_player(rr - 1 - tid, round, rr);
         int p = a < b ? a : b, q = a < b ? b : a;
         double c = 1.0, s = 0.0;
-        int act = 0;
         if (q < r) {
           double apq = M[p + q * LD];
           if (fabs(apq) > tiny) {
@@ -43,48 +46,52 @@ PPCG_DEV void lds_jacobi(double* M, double* V, int r, int LD, double tiny, int m
             double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
             c = 1.0 / sqrt(1.0 + t * t);
             s = t * c;
-            act = 1;
+            atomicAdd(cnt, 1);
           }
         }
-        pq[2 * tid] = act ? p : -1;
+        pq[2 * tid] = p;
         pq[2 * tid + 1] = q;
         cs[2 * tid] = c;
         cs[2 * tid + 1] = s;
-        if (act) atomicAdd(cnt, 1);
       }
       __syncthreads();
-      // rows p, q  <-  J^T M
-      for (int w = tid; w < np * r; w += NT) {
-        int t = w / r, j = w % r;
-        int p = pq[2 * t];
-        if (p < 0) continue;
-        int q = pq[2 * t + 1];
-        double c = cs[2 * t], s = cs[2 * t + 1];
-        double mp = M[p + j * LD], mq = M[q + j * LD];
-        M[p + j * LD] = c * mp - s * mq;
-        M[q + j * LD] = s * mp + c * mq;
+      // 2x2 blocks: rows {p_a, q_a} x columns {p_b, q_b}
+      for (int w = tid; w < np * np; w += NT) {
+        int ta = w % np, tb = w / np;
+        double ca = cs[2 * ta], sa = cs[2 * ta + 1], cb = cs[2 * tb], sb = cs[2 * tb + 1];
+        if (sa == 0.0 && sb == 0.0) continue;
+        int p = pq[2 * ta], q = pq[2 * ta + 1], p2 = pq[2 * tb], q2 = pq[2 * tb + 1];
+        bool vq = q < r, vq2 = q2 < r;
+        double b00 = M[p + p2 * LD];
+        double b01 = vq2 ? M[p + q2 * LD] : 0.0;
+        double b10 = vq ? M[q + p2 * LD] : 0.0;
+        double b11 = (vq && vq2) ? M[q + q2 * LD] : 0.0;
+        double r00 = ca * b00 - sa * b10, r10 = sa * b00 + ca * b10;
+        double r01 = ca * b01 - sa * b11, r11 = sa * b01 + ca * b11;
+        M[p + p2 * LD] = cb * r00 - sb * r01;
+        if (vq2) M[p + q2 * LD] = sb * r00 + cb * r01;
+        if (vq) M[q + p2 * LD] = cb * r10 - sb * r11;
+        if (vq && vq2) M[q + q2 * LD] = sb * r10 + cb * r11;
       }
-      __syncthreads();
-      // columns p, q  <-  M J ;  V <- V J
-      for (int w = tid; w < np * r; w += NT) {
-        int t = w / r, i = w % r;
-        int p = pq[2 * t];
-        if (p < 0) continue;
-        int q = pq[2 * t + 1];
-        double c = cs[2 * t], s = cs[2 * t + 1];
-        double mp = M[i + p * LD], mq = M[i + q * LD];
-        M[i + p * LD] = c * mp - s * mq;
-        M[i + q * LD] = s * mp + c * mq;
-        double vp = V[i + p * LD], vq = V[i + q * LD];
-        V[i + p * LD] = c * vp - s * vq;
-        V[i + q * LD] = s * vp + c * vq;
+      // V <- V J (columns of each rotated pair)
+      for (int w = tid; w < r * np; w += NT) {
+        int i = w % r, tb = w / r;
+        double sb = cs[2 * tb + 1];
+        if (sb == 0.0) continue;
+        double cb = cs[2 * tb];
+        int p2 = pq[2 * tb], q2 = pq[2 * tb + 1];
+        double vp = V[i + p2 * LD], vq = V[i + q2 * LD];
+        V[i + p2 * LD] = cb * vp - sb * vq;
+        V[i + q2 * LD] = sb * vp + cb * vq;
       }
       __syncthreads();
     }
+    ++sweeps;
     if (*cnt == 0) break;
     __syncthreads();
   }
   __syncthreads();
+  return sweeps;
 }
 
 }  // namespace ppcg

@@ -144,7 +144,7 @@ size_t eig_workspace_bytes(int m);
 int block_jacobi_eig(double* M, int ld, int m, double* V, int ldv, double* lam, void* work, int* hostbuf,
                      hipStream_t st);
 
-// rho and helpers: den = |G[:nw, :nw]|_F^2
+// rho and helpers: out[j] = sum_{i<nw} G[i, j]^2, j < nw
 void launch_frob2_sub(const double* G, int ld, int nw, double* out, hipStream_t st);
 // out = |G[:k, :k] - I|_F^2
 void launch_orth_err2(const double* G, int ld, int k, double* out, hipStream_t st);

@@ -378,7 +378,7 @@ struct Solve {
     H->GWP.ensure((size_t)Kp * 2 * K * 8);
     H->lam.ensure((size_t)Kp * 8);
     H->cn.ensure((size_t)Kp * 8);
-    H->scal.ensure(256);
+    H->scal.ensure((size_t)Kp * 8 + 256);
     H->iflag.ensure(256);
     H->dminp.ensure(1024 * 8);
     int s = K / q;
@@ -401,7 +401,7 @@ struct Solve {
     acc(nS + q, 2 * nS - q, s, rows, 8);
     acc(K, K, 1, Kp, 8);
     H->part.ensure(need);
-    H->pinned((size_t)(4 * Kp + 64) * 8);
+    H->pinned((size_t)(4 * Kp + 64) * 8);  // doubles [0, 2Kp), ints from 4Kp + 8
     // zero everything that carries padding rows
     std::vector<DBuf*> blocks = {&H->X, &H->Xt};
     if (mixed) {
@@ -478,12 +478,15 @@ struct Solve {
   double rho() {
     int nwa = std::max(0, k - nl);
     HIPCHECK(hipMemcpyAsync(H->hpind, H->cn.p, (size_t)std::max(nwa, 1) * 8, hipMemcpyDeviceToHost, st));
-    HIPCHECK(hipMemcpyAsync(H->hpind + Kp, H->scal.p, 8, hipMemcpyDeviceToHost, st));
-    HIPCHECK(hipMemcpyAsync(H->hpin + 2 * (Kp + 1), H->iflag.p, 4, hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipMemcpyAsync(H->hpind + Kp, H->scal.p, (size_t)std::max(nwa, 1) * 8, hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipMemcpyAsync(H->hpin + 4 * Kp + 8, H->iflag.p, 4, hipMemcpyDeviceToHost, st));
     HIPCHECK(hipStreamSynchronize(st));
-    if (H->hpin[2 * (Kp + 1)]) throw PpcgError{PPCG_ERANK, "Cholesky-QR breakdown (X^H X not positive definite)"};
-    double num = 0, den = H->hpind[Kp];
-    for (int i = 0; i < nwa; ++i) num += H->hpind[i];
+    if (H->hpin[4 * Kp + 8]) throw PpcgError{PPCG_ERANK, "Cholesky-QR breakdown (X^H X not positive definite)"};
+    double num = 0, den = 0;
+    for (int i = 0; i < nwa; ++i) {
+      num += H->hpind[i];
+      den += H->hpind[Kp + i];
+    }
     for (size_t i = 0; i < lock_wn.size(); ++i) {
       num += lock_wn[i] * lock_wn[i];
       den += lock_lam[i] * lock_lam[i];
