@@ -66,6 +66,10 @@ def lib():
     L.ppcg_solve.argtypes = [c_void_p, POINTER(Operator), c_int32, c_int32, c_double, c_int32,
                              c_void_p, c_void_p, c_void_p, POINTER(Info)]
     L.ppcg_solve.restype = c_int32
+    L.ppcg_grad.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int32, POINTER(c_int32)]
+    L.ppcg_grad.restype = c_int32
+    L.ppcg_density.argtypes = [c_void_p, c_void_p]
+    L.ppcg_density.restype = c_int32
     L.ppcg_columns.argtypes = [c_void_p, c_int32, c_int32]
     L.ppcg_columns.restype = c_int32
     L.ppcg_apply_h.argtypes = [c_void_p, POINTER(Operator), c_int32, c_void_p, c_void_p]
@@ -109,6 +113,7 @@ class Handle:
             raise PPCGError(code, "ppcg_create failed")
         self._h = h
         self.precision = precision
+        self._last_n = None
 
     def close(self):
         if getattr(self, "_h", None):
@@ -166,9 +171,40 @@ class Handle:
         code = self._L.ppcg_solve(self._h, byref(op), int(k), int(sbsize), float(tol), int(rr_period),
                                   c_void_p(X0cm.data_ptr()), c_void_p(Xout.data_ptr()), c_void_p(lam.data_ptr()),
                                   byref(info))
+        self._last_n = n if code == 0 else None
         if code != 0 and check:
             raise PPCGError(code, self.error(), info.as_dict())
         return lam, Xout.t(), info.as_dict()
+
+    def grad(self, g_lambda, w=None, tol=1e-10, max_iter=0):
+        """dL/dV for L = g_lambda . lambda + w . rho of the last solve (torch CUDA
+        float64 tensors); returns (dL/dV (n,), CG iterations)."""
+        import torch
+        _check_tensor(g_lambda, "g_lambda")
+        if w is not None:
+            _check_tensor(w, "w")
+        n = self._last_n
+        if n is None:
+            raise PPCGError(5, "no successful solve on this handle")
+        out = torch.empty(n, dtype=torch.float64, device=g_lambda.device)
+        it = c_int32(0)
+        code = self._L.ppcg_grad(self._h, c_void_p(g_lambda.contiguous().data_ptr()),
+                                 c_void_p(w.contiguous().data_ptr()) if w is not None else None,
+                                 c_void_p(out.data_ptr()), float(tol), int(max_iter), byref(it))
+        if code != 0:
+            raise PPCGError(code, self.error())
+        return out, it.value
+
+    def density(self):
+        """rho = sum_i x_i^2 of the last solve (torch CUDA float64, (n,))."""
+        import torch
+        if self._last_n is None:
+            raise PPCGError(5, "no successful solve on this handle")
+        rho = torch.empty(self._last_n, dtype=torch.float64, device="cuda")
+        code = self._L.ppcg_density(self._h, c_void_p(rho.data_ptr()))
+        if code != 0:
+            raise PPCGError(code, self.error())
+        return rho
 
     def kernel_times(self):
         """{kernel kind: (total ms, launches, algorithmic flops, compulsory bytes)}"""

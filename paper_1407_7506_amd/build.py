@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libppcg.so")
 OBJ = os.path.join(ROOT, "_build")
-SOURCES = ["gemm.hip", "stencil.hip", "block.hip", "dense.hip", "prep.hip", "solver.cpp"]
+SOURCES = ["gemm.hip", "stencil.hip", "block.hip", "dense.hip", "prep.hip", "grad.hip", "solver.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wno-unused-result",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -165,7 +165,9 @@ __global__ __launch_bounds__(256) void block_pencil_kernel(PencilArgs a) {
     }
     __syncthreads();
     // 7. eigen-decomposition M = Y diag Y^T (Y in b0).  Rotations below
-    //    1e-12 |M|_F are skipped: the pencil only has to give a good step.
+    //    jacobi_rel |M|_F are skipped: the pencil only has to give a good
+    //    step, and the caller sizes jacobi_rel well below the X-W coupling
+    //    (of the order of the residual) that the step has to resolve.
     {
       double fro = 0;
       for (int e = tid; e < r * r; e += NT) {
@@ -177,7 +179,7 @@ __global__ __launch_bounds__(256) void block_pencil_kernel(PencilArgs a) {
       __syncthreads();
       fro = (cs[0] + cs[1]) + (cs[2] + cs[3]);
       __syncthreads();
-      lds_jacobi<NT>(b3, b0, r, LD, 1e-12 * sqrt(fro), 40, cs, pq, &cnt);
+      lds_jacobi<NT>(b3, b0, r, LD, a.jacobi_rel * sqrt(fro), 40, cs, pq, &cnt);
     }
     // 8. ascending order (ties by index): rank -> keep[] reused as sel
     for (int x = tid; x < r; x += NT) {

@@ -270,11 +270,11 @@ void launch_orth_err2(const double* G, int ld, int k, double* out, hipStream_t s
 // block Jacobi
 // ---------------------------------------------------------------------------
 constexpr int JB = 16;           // block width
-// Rotations are skipped once |M_pq| <= kJacobiRelTol |M|_F.  Off-diagonal
-// entries of that size change the Ritz residual of a column by at most
-// ~1e-13 |M|_F sqrt(K), far below any locking threshold, and the eigenvalues
-// (Rayleigh quotients of the rotated columns) by O(off^2 / gap).
-constexpr double kJacobiRelTol = 1e-13;
+// Rotations are skipped once |M_pq| <= rel_tol |M|_F.  Off-diagonal entries
+// of that size change the Ritz residual of a column by at most
+// rel_tol |M|_F sqrt(K) (the caller keeps this far below its locking
+// threshold) and the eigenvalues (Rayleigh quotients of the rotated
+// columns) by O(off^2 / gap).
 constexpr int J2 = 2 * JB;       // pair size
 constexpr int JLD = J2 + 1;
 
@@ -309,7 +309,8 @@ size_t eig_workspace_bytes(int m) {
 
 PPCG_DEV int pair_block(int t, int round, int nbe) { return rr_player(t, round, nbe); }
 
-__global__ __launch_bounds__(256) void bj_norm_kernel(const double* M, int ld, int m, double* tiny, int* counter) {
+__global__ __launch_bounds__(256) void bj_norm_kernel(const double* M, int ld, int m, double* tiny, int* counter,
+                                                      double rel_tol) {
   double s = 0;
   for (long e = threadIdx.x; e < (long)m * m; e += 256) {
     double v = M[(e % m) + (e / m) * ld];
@@ -320,7 +321,7 @@ __global__ __launch_bounds__(256) void bj_norm_kernel(const double* M, int ld, i
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) {
-    *tiny = kJacobiRelTol * sqrt((red[0] + red[1]) + (red[2] + red[3]));
+    *tiny = rel_tol * sqrt((red[0] + red[1]) + (red[2] + red[3]));
     *counter = 0;
   }
 }
@@ -460,14 +461,14 @@ __global__ void identity_kernel(double* V, int m) {
 }
 
 int block_jacobi_eig(double* M, int ld, int m, double* V, int ldv, double* lam, void* work, int* hostbuf,
-                     hipStream_t st) {
+                     double rel_tol, hipStream_t st) {
   JacobiWork w = carve(work, m);
   const int nblk = (m + JB - 1) / JB;
   const int nbe = nblk + (nblk & 1);
   const int np = nbe / 2;
   long mm = (long)m * m;
   hipLaunchKernelGGL(identity_kernel, dim3((mm + 255) / 256), dim3(256), 0, st, w.Vt, m);
-  hipLaunchKernelGGL(bj_norm_kernel, dim3(1), dim3(256), 0, st, M, ld, m, w.tiny, w.counter);
+  hipLaunchKernelGGL(bj_norm_kernel, dim3(1), dim3(256), 0, st, M, ld, m, w.tiny, w.counter, rel_tol);
   int sweeps = 0;
   const int rounds = nbe > 1 ? nbe - 1 : 1;
   for (int sweep = 0; sweep < 40; ++sweep) {

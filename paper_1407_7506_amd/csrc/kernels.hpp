@@ -82,6 +82,7 @@ struct StencilArgs {
   double w1, w2;      // off-diagonal weights / h^2
   const void* V;      // potential (same precision as X)
   int f32;
+  const double* shift;  // optional per-column shift: Y[:, j] -= shift[j] X[:, j] (float64 only)
 };
 void launch_stencil(const StencilArgs& a, hipStream_t st);
 
@@ -109,6 +110,7 @@ struct PencilArgs {
   long cstride;
   int* flags;           // out: per block bit0 = P used, bit1 = backtracked, bit2 = rank failure
   double drop_tol, pivot_tol;
+  double jacobi_rel;    // rotations below jacobi_rel |M|_F are skipped
 };
 void launch_block_pencil(const PencilArgs& a, int nblocks, hipStream_t st);
 
@@ -142,7 +144,20 @@ void launch_symmetrize(double* G, int ld, int m, hipStream_t st);
 // the caller (size from eig_workspace_bytes).  Returns sweeps used.
 size_t eig_workspace_bytes(int m);
 int block_jacobi_eig(double* M, int ld, int m, double* V, int ldv, double* lam, void* work, int* hostbuf,
-                     hipStream_t st);
+                     double rel_tol, hipStream_t st);
+
+// backward pass (grad.hip)
+void launch_coldot(const double* A, const double* B, long ld, long rows, int ncols, double* out, hipStream_t st);
+void launch_cg_precond(const double* R, double* Y, const double* V, double c0, const double* lam, long ld, long n,
+                       long rows, int ncols, int unprec, hipStream_t st);
+void launch_cg_alpha(const double* rz, const double* pAp, const int* done, double* alpha, int k, hipStream_t st);
+void launch_cg_beta(double* rz, const double* rznew, const int* done, double* beta, int k, hipStream_t st);
+void launch_cg_xr(double* Z, double* R, const double* P, const double* AP, const double* alpha, long ld, long rows,
+                  int k, hipStream_t st);
+void launch_cg_p(double* P, const double* Y, const double* beta, long ld, long rows, int k, hipStream_t st);
+void launch_cg_check(const double* rr, const double* bb, double tol, int* done, int* left, int k, hipStream_t st);
+void launch_grad_rows(const double* X, const double* Z, const double* g, long ld, long n, int k, double* out,
+                      hipStream_t st);
 
 // rho and helpers: out[j] = sum_{i<nw} G[i, j]^2, j < nw
 void launch_frob2_sub(const double* G, int ld, int nw, double* out, hipStream_t st);

@@ -165,13 +165,19 @@ struct ppcg_handle {
   DBuf Vd, V32, td;
   DBuf G, GWP, L, Li, Rinv, SAS, SS, V1, Mr, Yv, Cc, lam;
   DBuf part, bgram, bC, bflags, cn, scal, iflag, eigw, dminp;
+  DBuf gZ, gR, gP, gAP, gY, gw, gsc;  // backward-pass work
+  // state of the last successful solve (for ppcg_grad / ppcg_density)
+  bool has_state = false;
+  int s_N = 0, s_order = 0, s_k = 0;
+  long s_n = 0, s_rows = 0;
+  double s_c0 = 0, s_w1 = 0, s_w2 = 0, s_dmin = 0;
   int* hpin = nullptr;                // pinned host scratch
   double* hpind = nullptr;
   size_t hpin_bytes = 0;
   ~ppcg_handle() {
     for (DBuf* b : {&X, &Xt, &W, &P, &AW, &AP, &X32, &W32, &P32, &AW32, &AP32, &AXm, &Vd, &V32, &td, &G, &GWP, &L, &Li,
                     &Rinv, &SAS, &SS, &V1, &Mr, &Yv, &Cc, &lam, &part, &bgram, &bC, &bflags, &cn, &scal, &iflag,
-                    &eigw, &dminp})
+                    &eigw, &dminp, &gZ, &gR, &gP, &gAP, &gY, &gw, &gsc})
       b->release();
     if (hpin) hipHostFree(hpin);
   }
@@ -202,6 +208,7 @@ struct Solve {
   double tol;
   int rr_period, max_iter;
   bool mixed;
+  double dmin = 0;
   // state
   int nl = 0;        // locked columns (absolute prefix)
   bool hasP = false;
@@ -209,6 +216,12 @@ struct Solve {
   ppcg_info info{};
 
   Solve(ppcg_handle* h) : H(h), st(h->st), prof(h->prof) {}
+
+  // Jacobi skip thresholds relative to |M|_F, tied to the requested tolerance:
+  // the RR rotation error then stays ~1e-5 tol below the Ritz residuals that
+  // decide locking, and the pencils resolve X-W couplings down to ~1e-4 tol.
+  double rr_rel_tol() const { return std::max(2.2e-16, std::min(1e-11, 1e-5 * tol)); }
+  double pencil_rel_tol() const { return std::max(2.2e-16, std::min(1e-10, 1e-4 * tol)); }
 
   double* X() { return H->X.d(); }
   double* Xt() { return H->Xt.d(); }
@@ -429,6 +442,7 @@ struct Solve {
     for (int i = 0; i < nparts; ++i) mn = std::min(mn, H->hpind[i]);
     if (H->hpin[2 * nparts]) throw PpcgError{PPCG_EINVAL, "V contains NaN"};
     if (!(mn > 0)) throw PpcgError{PPCG_ENOTHPD, "diag(H) has a non-positive entry: Jacobi preconditioner not HPD"};
+    dmin = mn;
   }
 
   // X (active columns c0.., m of them) <- X R^{-1}; result lands in Xt then X/Xt swap
@@ -521,7 +535,7 @@ struct Solve {
     if (H->hpin[0]) throw PpcgError{PPCG_ERANK, "Rayleigh-Ritz Gram S^H S not positive definite"};
     {
       Scope s(prof, "eig");
-      block_jacobi_eig(H->Mr.d(), Kp, K, H->Yv.d(), Kp, H->lam.d(), H->eigw.p, H->hpin, st);
+      block_jacobi_eig(H->Mr.d(), Kp, K, H->Yv.d(), Kp, H->lam.d(), H->eigw.p, H->hpin, rr_rel_tol(), st);
     }
     // C = Linv^T Y, X <- S C
     update(H->Rinv.p, Kp, K, H->Yv.p, Kp, K, H->Cc.p, nullptr, K, Kp, nullptr, nullptr, Kp, 1.0, 0.0, false, false,
@@ -655,6 +669,7 @@ struct Solve {
       pa.flags = H->bflags.i();
       pa.drop_tol = 1e-14;
       pa.pivot_tol = 1e-12;
+      pa.jacobi_rel = pencil_rel_tol();
       Scope sc(prof, "block_pencil", 0, 0);
       launch_block_pencil(pa, s, st);
     }
@@ -748,6 +763,7 @@ struct Solve {
     if (K % q != 0) throw PpcgError{PPCG_EINVAL, "k + nbuf must be a multiple of sbsize"};
     if ((long)K * 4 > n) throw PpcgError{PPCG_EINVAL, "k + nbuf must not exceed n/4"};
     Kp = (int)round_up(K, 64);
+    H->has_state = false;
     allocate();
     prep(op->V);
     HIPCHECK(hipMemcpy2DAsync(X(), (size_t)ld * 8, X0, (size_t)n * 8, (size_t)n * 8, K, hipMemcpyDeviceToDevice, st));
@@ -780,9 +796,137 @@ struct Solve {
     }
     finish(Xout, lamout, fresh);
     prof.collect();
+    if (status == PPCG_OK) {
+      H->has_state = true;
+      H->s_N = N;
+      H->s_order = order;
+      H->s_k = k;
+      H->s_n = n;
+      H->s_rows = rows;
+      H->s_c0 = c0;
+      H->s_w1 = w1;
+      H->s_w2 = w2;
+      H->s_dmin = dmin;
+    }
     info.time_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (status == PPCG_ENOCONV) H->err = "max_iter reached";
     return status;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// backward pass: projected Sternheimer systems by block PCG
+// ---------------------------------------------------------------------------
+struct Grad {
+  ppcg_handle* H;
+  hipStream_t st;
+  Prof& prof;
+  int k;
+  long n, rows, ld;
+  Grad(ppcg_handle* h) : H(h), st(h->st), prof(h->prof) {}
+
+  // Y <- (I - X X^H) Y over the k saved eigenvectors
+  void project(double* Y) {
+    Solve s(H);
+    s.n = n;
+    s.rows = rows;
+    s.ld = ld;
+    ColSet A = Solve::cols1(H->X.p, k, false), B = Solve::cols1(Y, k, false);
+    s.gram(A, B, k, k, rows, ld, nullptr, 0, H->gsc.p, (int)round_up(k, 64), false, false, 1, 0, 0, "gram_grad");
+    s.update(H->X.p, ld, k, H->gsc.p, round_up(k, 64), k, Y, nullptr, k, ld, nullptr, nullptr, rows, -1.0, 1.0,
+             false, false, "update_grad");
+  }
+  void stencil_shift(const double* P, double* Y) {
+    StencilArgs a{};
+    a.X = P;
+    a.Y = Y;
+    a.ldx = a.ldy = ld;
+    a.ncols = k;
+    a.N = H->s_N;
+    a.order = H->s_order;
+    a.c0 = H->s_c0;
+    a.w1 = H->s_w1;
+    a.w2 = H->s_w2;
+    a.V = H->Vd.p;
+    a.f32 = 0;
+    a.shift = H->lam.d();
+    Scope sc(prof, "stencil_f64", (H->s_order == 4 ? 17.0 : 11.0) * n * k, 16.0 * n * k);
+    launch_stencil(a, st);
+  }
+
+  int run(const double* g, const double* w, double* out, double tol, int max_iter) {
+    if (!H->has_state) throw PpcgError{PPCG_ENOSTATE, "ppcg_grad needs a successful ppcg_solve on this handle"};
+    if (!g || !out || !(tol > 0)) throw PpcgError{PPCG_EINVAL, "null pointer or tol <= 0"};
+    k = H->s_k;
+    n = H->s_n;
+    rows = H->s_rows;
+    ld = rows;
+    if (!w) {
+      launch_grad_rows(H->X.d(), nullptr, g, ld, n, k, out, st);
+      HIPCHECK(hipStreamSynchronize(st));
+      return 0;
+    }
+    const size_t blk = (size_t)rows * k * 8;
+    for (DBuf* b : {&H->gZ, &H->gR, &H->gP, &H->gAP, &H->gY}) b->ensure(blk);
+    H->gw.ensure((size_t)rows * 8);
+    int kp = (int)round_up(k, 64);
+    H->gsc.ensure((size_t)kp * kp * 8 + (size_t)16 * kp * 8);
+    double* sc = H->gsc.d() + (size_t)kp * kp;  // per-column scalars
+    double *rz = sc, *rznew = sc + kp, *pAp = sc + 2 * kp, *alpha = sc + 3 * kp, *beta = sc + 4 * kp,
+           *bb = sc + 5 * kp, *rr = sc + 6 * kp;
+    int* done = (int*)(sc + 7 * kp);
+    int* left = (int*)(sc + 8 * kp);
+    // the partial buffer must hold a k x k Gram
+    H->part.ensure((size_t)k * k * 8 * 4);
+    HIPCHECK(hipMemsetAsync(H->gw.p, 0, H->gw.bytes, st));
+    HIPCHECK(hipMemcpyAsync(H->gw.p, w, n * 8, hipMemcpyDeviceToDevice, st));
+    double *Z = H->gZ.d(), *R = H->gR.d(), *P = H->gP.d(), *AP = H->gAP.d(), *Y = H->gY.d();
+    // b = Q (w x_i)
+    launch_scale_rows(H->gw.d(), H->X.p, R, ld, rows, k, 0, st);
+    project(R);
+    launch_coldot(R, R, ld, rows, k, bb, st);
+    launch_fill(Z, (long)rows * k, 0.0, st);
+    launch_zero_int(done, k, st);
+    // Jacobi preconditioner 1/(diag(H) - lambda_i) when it is positive definite
+    HIPCHECK(hipMemcpyAsync(H->hpind, H->lam.p, (size_t)k * 8, hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    double lmax = -1e308;
+    for (int j = 0; j < k; ++j) lmax = std::max(lmax, H->hpind[j]);
+    int unprec = !(H->s_dmin - lmax > 0);
+    auto precond = [&]() {
+      launch_cg_precond(R, Y, H->Vd.d(), H->s_c0, H->lam.d(), ld, n, rows, k, unprec, st);
+      project(Y);
+    };
+    precond();
+    HIPCHECK(hipMemcpyAsync(P, Y, blk, hipMemcpyDeviceToDevice, st));
+    launch_coldot(R, Y, ld, rows, k, rz, st);
+    int it = 0;
+    for (; it < max_iter; ++it) {
+      stencil_shift(P, AP);
+      project(AP);
+      launch_coldot(P, AP, ld, rows, k, pAp, st);
+      launch_cg_alpha(rz, pAp, done, alpha, k, st);
+      launch_cg_xr(Z, R, P, AP, alpha, ld, rows, k, st);
+      launch_coldot(R, R, ld, rows, k, rr, st);
+      launch_zero_int(left, 1, st);
+      launch_cg_check(rr, bb, tol, done, left, k, st);
+      if (it % 4 == 3 || it == max_iter - 1) {
+        HIPCHECK(hipMemcpyAsync(H->hpin, left, 4, hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipStreamSynchronize(st));
+        if (H->hpin[0] == 0) {
+          ++it;
+          break;
+        }
+      }
+      precond();
+      launch_coldot(R, Y, ld, rows, k, rznew, st);
+      launch_cg_beta(rz, rznew, done, beta, k, st);
+      launch_cg_p(P, Y, beta, ld, rows, k, st);
+    }
+    launch_grad_rows(H->X.d(), Z, g, ld, n, k, out, st);
+    HIPCHECK(hipStreamSynchronize(st));
+    prof.collect();
+    return it;
   }
 };
 
@@ -842,6 +986,28 @@ ppcg_status ppcg_solve(ppcg_handle* h, const ppcg_operator* op, int32_t k, int32
     }
     if (info) *info = s.info;
     return st;
+  });
+}
+
+ppcg_status ppcg_grad(ppcg_handle* h, const double* g_lambda, const double* w, double* dL_dV, double tol,
+                      int32_t max_iter, int32_t* iters) {
+  if (!h) return PPCG_EINVAL;
+  return guard(h, [&]() {
+    Grad g(h);
+    int it = g.run(g_lambda, w, dL_dV, tol, max_iter > 0 ? max_iter : 10000);
+    if (iters) *iters = it;
+    return PPCG_OK;
+  });
+}
+
+ppcg_status ppcg_density(ppcg_handle* h, double* rho) {
+  if (!h || !rho) return PPCG_EINVAL;
+  return guard(h, [&]() {
+    if (!h->has_state) throw PpcgError{PPCG_ENOSTATE, "ppcg_density needs a successful ppcg_solve on this handle"};
+    launch_grad_rows(h->X.d(), nullptr, nullptr, h->s_rows, h->s_n, h->s_k, rho, h->st);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(h->st));
+    return PPCG_OK;
   });
 }
 

@@ -40,6 +40,7 @@ __global__ __launch_bounds__(256) void stencil_kernel(StencilArgs a) {
            x[pz + (long)wr(k, 2) * NN] + x[pz + (long)wr(k, -2) * NN];
     out += (T)a.w2 * s2;
   }
+  if (a.shift) out -= (T)a.shift[col] * xc;
   y[p] = out;
 }
 

@@ -39,3 +39,8 @@ def test_binding_refuses_missing_library(monkeypatch):
     monkeypatch.setattr(binding, "_lib", None)
     with pytest.raises(RuntimeError):
         binding.lib()
+
+
+def test_autograd_module_imports_without_gpu():
+    from paper_1407_7506_amd import autograd
+    assert hasattr(autograd, "EigDensity") and hasattr(autograd, "EigConfig")

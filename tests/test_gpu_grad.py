@@ -1,0 +1,100 @@
+"""GPU backward pass (ppcg_grad / EigDensity) against the oracle: dense
+double-sum gradient on tiny grids, the oracle's Sternheimer solve on the same
+eigenvectors, invariants, and central finite differences on the 32^3 workload."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import grad as ograd  # noqa: E402
+from oracle import stencil  # noqa: E402
+from paper_1407_7506_amd import binding as B  # noqa: E402
+from paper_1407_7506_amd import inputs as I  # noqa: E402
+from paper_1407_7506_amd.autograd import EigConfig, EigDensity  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def dev(a):
+    return torch.tensor(np.ascontiguousarray(a), device="cuda")
+
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_grad_matches_dense_formula(order):
+    N, k, q = 8, 6, 2
+    V = I.gaussian_wells(N, 0.5, 2, 11)
+    H = stencil.assemble_h(V, N, 0.5, order)
+    lam_all, X_all = np.linalg.eigh(H)
+    assert lam_all[k] - lam_all[k - 1] > 1e-3
+    rng = np.random.default_rng(3)
+    g = rng.standard_normal(k)
+    w = rng.standard_normal(N ** 3)
+    h = B.Handle("fp64")
+    K = h.columns(k, q)
+    lam, X, info = h.solve(dev(V), N, k, q, 1e-12, 5, dev(I.start_block(N ** 3, K, 5)), order=order)
+    say("solve", info["iters"], "resid", info["resid_final"])
+    dV, its = h.grad(dev(g), dev(w), tol=1e-13)
+    ref = ograd.dense_grad(lam_all, X_all, k, g, w)
+    err = np.abs(dV.cpu().numpy() - ref).max() / np.abs(ref).max()
+    say("dense grad err", err, "cg iters", its)
+    assert err <= 1e-8
+    # Hellmann-Feynman and the shift invariance
+    hf, _ = h.grad(dev(g))
+    np.testing.assert_allclose(hf.cpu().numpy(), ograd.dense_grad(lam_all, X_all, k, g, None), atol=1e-12)
+    assert abs(dV.sum().item() - g.sum()) <= 1e-9 * max(1.0, abs(g.sum()))
+    rho = h.density().cpu().numpy()
+    np.testing.assert_allclose(rho, np.sum(X_all[:, :k] ** 2, axis=1), atol=1e-10)
+
+
+def test_grad_matches_oracle_sternheimer_wells32():
+    """Same eigenvectors on both sides: the GPU block PCG vs the oracle's CG."""
+    p = I.wells32()
+    g = p.grid
+    h = B.Handle("fp64")
+    lam, X, info = h.solve(dev(p.V), g.N, p.k, p.q, 1e-10, p.rr_period, dev(p.start()), order=g.order)
+    w = I.loss_weights(g.n, 305)
+    gl = np.ones(p.k)
+    dV, its = h.grad(dev(gl), dev(w), tol=1e-11)
+    Xn, ln = X.cpu().numpy(), lam.cpu().numpy()
+    A = lambda Y: stencil.apply_h(Y, p.V, g.N, g.h, g.order)
+    ref, oit, rel = ograd.sternheimer_grad(A, stencil.diag_h(p.V, g.h, g.order), Xn, ln, gl, w, tol=1e-11)
+    err = np.abs(dV.cpu().numpy() - ref).max() / np.abs(ref).max()
+    say("wells32 grad vs oracle", err, "cg iters gpu/oracle", its, oit)
+    assert err <= 1e-7
+    assert abs(dV.sum().item() - p.k) <= 1e-8 * p.k
+
+
+def test_fd_directions_wells32():
+    """Central finite differences (step 1e-5) of L = sum lambda + w . rho on
+    32 seeded unit directions, forward solves at tol 1e-12."""
+    p = I.wells32()
+    g = p.grid
+    w = dev(I.loss_weights(g.n, 305))
+    X0 = dev(p.start())
+    V = dev(p.V).requires_grad_(True)
+    cfg = EigConfig(N=g.N, k=p.k, sbsize=p.q, X0=X0, tol=1e-12, rr_period=p.rr_period, order=g.order,
+                    sternheimer_tol=1e-12)
+    lam, rho = EigDensity.apply(V, cfg)
+    L = lam.sum() + (w * rho).sum()
+    L.backward()
+    dV = V.grad.detach()
+    dirs = I.unit_directions(g.n, 32, 405)
+    h = B.Handle("fp64")
+    eps = 1e-5
+
+    def loss(Vv):
+        lm, Xm, _ = h.solve(Vv, g.N, p.k, p.q, 1e-12, p.rr_period, X0, order=g.order)
+        return lm.sum().item() + (w * h.density()).sum().item()
+
+    worst = 0.0
+    for i, d in enumerate(dirs):
+        dd = dev(d)
+        fd = (loss(V.detach() + eps * dd) - loss(V.detach() - eps * dd)) / (2 * eps)
+        an = torch.dot(dV, dd).item()
+        rel = abs(fd - an) / max(abs(fd), 1e-3)
+        worst = max(worst, rel)
+        say(f"dir {i}: fd {fd:.10f} analytic {an:.10f} rel {rel:.2e}")
+    assert worst <= 1e-4
