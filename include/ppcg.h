@@ -141,6 +141,26 @@ ppcg_status ppcg_density(ppcg_handle* h, double* rho);
  * options (nbuf = -1 resolved by the default rule); -1 on bad arguments. */
 int32_t ppcg_columns(const ppcg_handle* h, int32_t k, int32_t sbsize);
 
+/* Batched form: nprob independent problems of uneven sizes (own operator,
+ * k[b], start block X0[b] of n_b x K_b, outputs X_out[b] n_b x k[b] and
+ * lambda_out[b]), sharing sbsize, tol and rr_period.  All problems advance
+ * in lockstep: each stage of an iteration (projection Grams, stencils,
+ * per-block Grams, every 3q x 3q block pencil of every problem, block
+ * updates, Cholesky-QR, Rayleigh-Ritz) is one grouped launch over all
+ * unconverged problems, instead of one launch per problem.  Each problem
+ * follows exactly the arithmetic of ppcg_solve, so results equal those of
+ * nprob separate ppcg_solve calls.
+ *   ops, k, X0, X_out, lambda_out: host arrays of nprob entries (the
+ *                 pointers they hold are device pointers)
+ *   infos, statuses: host arrays of nprob entries, may be NULL
+ * Returns PPCG_OK when every problem converged, else the first failing
+ * problem's status (statuses[] holds each one).  The handle keeps one
+ * workspace per problem index. */
+ppcg_status ppcg_solve_batched(ppcg_handle* h, int32_t nprob, const ppcg_operator* ops, const int32_t* k,
+                               int32_t sbsize, double tol, int32_t rr_period, const double* const* X0,
+                               double* const* X_out, double* const* lambda_out, ppcg_info* infos,
+                               int32_t* statuses);
+
 /* Y = H X for ncols columns (device, ld n): the operator product alone. */
 ppcg_status ppcg_apply_h(ppcg_handle* h, const ppcg_operator* op, int32_t ncols, const double* X, double* Y);
 

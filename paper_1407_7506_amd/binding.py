@@ -66,6 +66,10 @@ def lib():
     L.ppcg_solve.argtypes = [c_void_p, POINTER(Operator), c_int32, c_int32, c_double, c_int32,
                              c_void_p, c_void_p, c_void_p, POINTER(Info)]
     L.ppcg_solve.restype = c_int32
+    L.ppcg_solve_batched.argtypes = [c_void_p, c_int32, POINTER(Operator), POINTER(c_int32), c_int32, c_double,
+                                     c_int32, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p),
+                                     POINTER(Info), POINTER(c_int32)]
+    L.ppcg_solve_batched.restype = c_int32
     L.ppcg_grad.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int32, POINTER(c_int32)]
     L.ppcg_grad.restype = c_int32
     L.ppcg_density.argtypes = [c_void_p, c_void_p]
@@ -175,6 +179,46 @@ class Handle:
         if code != 0 and check:
             raise PPCGError(code, self.error(), info.as_dict())
         return lam, Xout.t(), info.as_dict()
+
+    def solve_batched(self, problems, sbsize, tol, rr_period, check=True):
+        """Solve many independent problems in lockstep.  problems: list of
+        dicts with V (CUDA float64, N^3), N, k, X0 ((n, K) CUDA float64), and
+        optional h, order.  Returns a list of (lam, X (n, k), info, status)."""
+        import torch
+        nb = len(problems)
+        ops = (Operator * nb)()
+        ks = (c_int32 * nb)()
+        x0p = (c_void_p * nb)()
+        xop = (c_void_p * nb)()
+        lop = (c_void_p * nb)()
+        infos = (Info * nb)()
+        sts = (c_int32 * nb)()
+        keep = []
+        outs = []
+        for b, p in enumerate(problems):
+            N, k = int(p["N"]), int(p["k"])
+            n = N ** 3
+            K = self.columns(k, sbsize)
+            X0 = p["X0"]
+            _check_tensor(X0, "X0")
+            if X0.dim() != 2 or X0.shape[0] != n or X0.shape[1] != K:
+                raise ValueError(f"problem {b}: X0 must have shape ({n}, {K})")
+            X0cm = X0.t().contiguous()
+            Xo = torch.empty((k, n), dtype=torch.float64, device=X0.device)
+            lo = torch.empty(k, dtype=torch.float64, device=X0.device)
+            ops[b] = self.operator(p["V"], N, p.get("h", 0.5), p.get("order", 2))
+            ks[b] = k
+            x0p[b] = X0cm.data_ptr()
+            xop[b] = Xo.data_ptr()
+            lop[b] = lo.data_ptr()
+            keep += [X0cm, p["V"]]
+            outs.append((lo, Xo))
+        code = self._L.ppcg_solve_batched(self._h, nb, ops, ks, int(sbsize), float(tol), int(rr_period), x0p, xop,
+                                          lop, infos, sts)
+        self._last_n = None
+        if code != 0 and check:
+            raise PPCGError(code, self.error())
+        return [(outs[b][0], outs[b][1].t(), infos[b].as_dict(), STATUS.get(sts[b], sts[b])) for b in range(nb)]
 
     def grad(self, g_lambda, w=None, tol=1e-10, max_iter=0):
         """dL/dV for L = g_lambda . lambda + w . rho of the last solve (torch CUDA

@@ -20,14 +20,14 @@
 namespace ppcg {
 
 template <int NB>
-__global__ __launch_bounds__(256) void block_pencil_kernel(PencilArgs a) {
+PPCG_DEV void block_pencil_body(const PencilArgs& a, unsigned wg, unsigned) {
   constexpr int LD = NB + 1;
   constexpr int NT = 256;
   __shared__ double b0[NB * LD], b1[NB * LD], b2[NB * LD], b3[NB * LD];
   __shared__ double Dv[NB], cs[NB + 2];
   __shared__ int keep[NB], acc[NB], pq[NB + 2], cnt, nacc, sing;
   const int tid = threadIdx.x;
-  const int blk = blockIdx.x;
+  const int blk = (int)wg;
   const int q = a.q, nS = a.nS;
   const double* gram = a.gram + (long)blk * a.gstride;
   const int ldgr = nS + (a.ax_rows ? q : 0);
@@ -258,20 +258,35 @@ __global__ __launch_bounds__(256) void block_pencil_kernel(PencilArgs a) {
   }
   if (tid == 0) a.flags[blk] = flag;
 }
+template <int NB>
+__global__ __launch_bounds__(256) void block_pencil_kernel(PencilArgs a) {
+  block_pencil_body<NB>(a, blockIdx.x, gridDim.x);
+}
+template <int NB>
+__global__ __launch_bounds__(256) void block_pencil_grouped(const PencilArgs* jobs, const unsigned* start, int nj) {
+  int j = find_job(start, nj, blockIdx.x);
+  block_pencil_body<NB>(jobs[j], blockIdx.x - start[j], start[j + 1] - start[j]);
+}
 
-void launch_block_pencil(const PencilArgs& a, int nblocks, hipStream_t st) {
-  if (nblocks <= 0) return;
-  if (a.nS <= 24) hipLaunchKernelGGL(block_pencil_kernel<24>, dim3(nblocks), dim3(256), 0, st, a);
-  else hipLaunchKernelGGL(block_pencil_kernel<48>, dim3(nblocks), dim3(256), 0, st, a);
+void launch_block_pencil(const PencilArgs& a, hipStream_t st) {
+  unsigned blocks = a.nblocks > 0 ? (unsigned)a.nblocks : 0;
+  int kind = a.nS <= 24 ? OP_PENCIL24 : OP_PENCIL48;
+  if (g_rec) {
+    g_rec->add(kind, &a, sizeof(a), blocks);
+    return;
+  }
+  if (blocks == 0) return;
+  if (kind == OP_PENCIL24) hipLaunchKernelGGL(block_pencil_kernel<24>, dim3(blocks), dim3(256), 0, st, a);
+  else hipLaunchKernelGGL(block_pencil_kernel<48>, dim3(blocks), dim3(256), 0, st, a);
 }
 
 // ---------------------------------------------------------------------------
 template <class TW, int QM>
-__global__ __launch_bounds__(256) void block_update_kernel(BlockUpdArgs a) {
+PPCG_DEV void block_update_body(const BlockUpdArgs& a, unsigned wg, unsigned nwg) {
   __shared__ double Cs[3 * QM * QM];
   const int q = a.q;
   const unsigned rtiles = (unsigned)(a.rows / 256);
-  unsigned L = xcd_remap(blockIdx.x, gridDim.x);
+  unsigned L = xcd_remap(wg, nwg);
   int blk = L / rtiles;
   long r = (long)(L % rtiles) * 256 + threadIdx.x;
   const double* C = a.C + (long)blk * a.cstride;
@@ -313,19 +328,64 @@ __global__ __launch_bounds__(256) void block_update_kernel(BlockUpdArgs a) {
   }
 }
 
-void launch_block_update(const BlockUpdArgs& a, int nblocks, hipStream_t st) {
-  long blocks = (a.rows / 256) * nblocks;
+template <class TW, int QM>
+__global__ __launch_bounds__(256) void block_update_kernel(BlockUpdArgs a) {
+  block_update_body<TW, QM>(a, blockIdx.x, gridDim.x);
+}
+template <class TW, int QM>
+__global__ __launch_bounds__(256) void block_update_grouped(const BlockUpdArgs* jobs, const unsigned* start, int nj) {
+  int j = find_job(start, nj, blockIdx.x);
+  block_update_body<TW, QM>(jobs[j], blockIdx.x - start[j], start[j + 1] - start[j]);
+}
+
+static int bupd_kind(const BlockUpdArgs& a) {
+  int base = a.f32 ? OP_BUPD_F4 : OP_BUPD_D4;
+  return base + (a.q <= 4 ? 0 : a.q <= 8 ? 1 : a.q <= 16 ? 2 : 3);
+}
+
+void launch_block_update(const BlockUpdArgs& a, hipStream_t st) {
+  unsigned blocks = (unsigned)((a.rows / 256) * (a.nblocks > 0 ? a.nblocks : 0));
+  int kind = bupd_kind(a);
+  if (g_rec) {
+    g_rec->add(kind, &a, sizeof(a), blocks);
+    return;
+  }
   if (blocks == 0) return;
-#define PPCG_BU(QM)                                                                                  \
-  do {                                                                                               \
-    if (a.f32) hipLaunchKernelGGL((block_update_kernel<float, QM>), dim3(blocks), dim3(256), 0, st, a); \
-    else hipLaunchKernelGGL((block_update_kernel<double, QM>), dim3(blocks), dim3(256), 0, st, a);      \
-  } while (0)
-  if (a.q <= 4) PPCG_BU(4);
-  else if (a.q <= 8) PPCG_BU(8);
-  else if (a.q <= 16) PPCG_BU(16);
-  else PPCG_BU(32);
+#define PPCG_BU(T, QM) hipLaunchKernelGGL((block_update_kernel<T, QM>), dim3(blocks), dim3(256), 0, st, a)
+  switch (kind) {
+    case OP_BUPD_D4: PPCG_BU(double, 4); break;
+    case OP_BUPD_D8: PPCG_BU(double, 8); break;
+    case OP_BUPD_D16: PPCG_BU(double, 16); break;
+    case OP_BUPD_D32: PPCG_BU(double, 32); break;
+    case OP_BUPD_F4: PPCG_BU(float, 4); break;
+    case OP_BUPD_F8: PPCG_BU(float, 8); break;
+    case OP_BUPD_F16: PPCG_BU(float, 16); break;
+    case OP_BUPD_F32: PPCG_BU(float, 32); break;
+  }
 #undef PPCG_BU
+}
+
+bool launch_grouped_block(int kind, const void* jobs, const unsigned* start, int nj, unsigned total, hipStream_t st) {
+  const BlockUpdArgs* bj = (const BlockUpdArgs*)jobs;
+#define PPCG_GBU(T, QM) hipLaunchKernelGGL((block_update_grouped<T, QM>), dim3(total), dim3(256), 0, st, bj, start, nj)
+  switch (kind) {
+    case OP_PENCIL24:
+      hipLaunchKernelGGL(block_pencil_grouped<24>, dim3(total), dim3(256), 0, st, (const PencilArgs*)jobs, start, nj);
+      return true;
+    case OP_PENCIL48:
+      hipLaunchKernelGGL(block_pencil_grouped<48>, dim3(total), dim3(256), 0, st, (const PencilArgs*)jobs, start, nj);
+      return true;
+    case OP_BUPD_D4: PPCG_GBU(double, 4); return true;
+    case OP_BUPD_D8: PPCG_GBU(double, 8); return true;
+    case OP_BUPD_D16: PPCG_GBU(double, 16); return true;
+    case OP_BUPD_D32: PPCG_GBU(double, 32); return true;
+    case OP_BUPD_F4: PPCG_GBU(float, 4); return true;
+    case OP_BUPD_F8: PPCG_GBU(float, 8); return true;
+    case OP_BUPD_F16: PPCG_GBU(float, 16); return true;
+    case OP_BUPD_F32: PPCG_GBU(float, 32); return true;
+  }
+#undef PPCG_GBU
+  return false;
 }
 
 }  // namespace ppcg

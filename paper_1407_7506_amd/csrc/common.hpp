@@ -24,6 +24,19 @@ PPCG_DEV unsigned xcd_remap(unsigned b, unsigned total) {
   return base + idx;
 }
 
+// Grouped launches: one grid covers several jobs; job j owns workgroups
+// [start[j], start[j+1]).  Returns the job of workgroup b (binary search for
+// the last start <= b, so jobs with no workgroups are skipped).
+PPCG_DEV int find_job(const unsigned* start, int nj, unsigned b) {
+  int lo = 0, hi = nj - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 // MFMA wrappers: 16x16x4 tiles.  Lane l supplies a = A[l%16][l/16] and
 // b = B[l/16][l%16] (the reduction index is k = l/16).
 //   f64: accumulator value v of lane l is D[4v + l/16][l%16]

@@ -4,30 +4,82 @@
 //                     reduction to a standard problem (section 5.6)
 //   block_jacobi_eig  Hermitian eigen-decomposition of the reduced
 //                     Rayleigh-Ritz matrix by block Jacobi: pairs of 16-wide
-//                     diagonal blocks are diagonalised in LDS and their
-//                     rotations applied to the block rows, then columns
-//   misc              fills, transposes, diagonal set, Frobenius norms
+//                     diagonal blocks are diagonalised in LDS, their
+//                     rotations applied to the block rows, then to the block
+//                     columns and the eigenvector accumulator
+//   misc              fills, transposes, diagonal set, Frobenius norms, copies
+// Both composite routines take a list of independent problems and advance
+// them in lockstep, one grouped launch per step.
+#include <algorithm>
+
 #include "common.hpp"
 #include "jacobi.hpp"
 #include "kernels.hpp"
 
 namespace ppcg {
 
+Recorder* g_rec = nullptr;
+
+// ---------------------------------------------------------------------------
+// staging of job arrays
+// ---------------------------------------------------------------------------
+Stage::~Stage() {
+  for (auto* v : {&chunks, &retired})
+    for (auto& c : *v) {
+      hipHostFree(c.h);
+      hipFree(c.d);
+    }
+}
+void* Stage::upload(const void* src, size_t bytes, hipStream_t st) {
+  size_t need = (bytes + 255) / 256 * 256;
+  if (chunks.empty() || chunks.back().used + need > chunks.back().cap) {
+    size_t cap = std::max<size_t>(need, 1 << 20);
+    Chunk c{nullptr, nullptr, cap, 0};
+    if (hipHostMalloc((void**)&c.h, cap, hipHostMallocDefault) != hipSuccess) throw std::bad_alloc();
+    if (hipMalloc((void**)&c.d, cap) != hipSuccess) {
+      hipHostFree(c.h);
+      throw std::bad_alloc();
+    }
+    if (!chunks.empty()) {  // keep the full chunk alive until reset
+      retired.push_back(chunks.back());
+      chunks.pop_back();
+    }
+    chunks.push_back(c);
+  }
+  Chunk& c = chunks.back();
+  std::memcpy(c.h + c.used, src, bytes);
+  void* d = c.d + c.used;
+  hipMemcpyAsync(d, c.h + c.used, bytes, hipMemcpyHostToDevice, st);
+  c.used += need;
+  return d;
+}
+void Stage::reset() {
+  for (auto& c : retired) {
+    hipHostFree(c.h);
+    hipFree(c.d);
+  }
+  retired.clear();
+  for (auto& c : chunks) c.used = 0;
+}
+
+// ---------------------------------------------------------------------------
+// blocked Cholesky and inverse
+// ---------------------------------------------------------------------------
 constexpr int CB = 32;       // Cholesky tile
 constexpr int CLD = CB + 1;
 
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void chol_diag_kernel(double* G, int ld, int m, int p, double* L, double* Li,
-                                                        int* flag) {
+struct DenseStep { double* G; double* L; double* Li; int ld, m; int* flag; };
+
+PPCG_DEV void chol_diag_body(const DenseStep& a, int p) {
   __shared__ double S[CB * CLD], I[CB * CLD];
   __shared__ int bad;
   const int tid = threadIdx.x;
   const int n0 = p * CB;
-  const int nb = min(CB, m - n0);
+  const int nb = min(CB, a.m - n0);
   for (int e = tid; e < CB * CB; e += 256) {
     int i = e % CB, j = e / CB;
     double v = 0.0;
-    if (i < nb && j < nb) v = (i >= j) ? G[(n0 + i) + (long)(n0 + j) * ld] : G[(n0 + j) + (long)(n0 + i) * ld];
+    if (i < nb && j < nb) v = (i >= j) ? a.G[(n0 + i) + (long)(n0 + j) * a.ld] : a.G[(n0 + j) + (long)(n0 + i) * a.ld];
     S[i + j * CLD] = v;
   }
   if (tid == 0) bad = 0;
@@ -60,33 +112,32 @@ __global__ __launch_bounds__(256) void chol_diag_kernel(double* G, int ld, int m
   __syncthreads();
   for (int e = tid; e < nb * nb; e += 256) {
     int i = e % nb, j = e / nb;
-    long o = (n0 + i) + (long)(n0 + j) * ld;
-    L[o] = (i >= j) ? S[i + j * CLD] : 0.0;
-    Li[o] = (i >= j) ? I[i + j * CLD] : 0.0;
+    long o = (n0 + i) + (long)(n0 + j) * a.ld;
+    a.L[o] = (i >= j) ? S[i + j * CLD] : 0.0;
+    a.Li[o] = (i >= j) ? I[i + j * CLD] : 0.0;
   }
-  if (tid == 0 && bad && *flag == 0) *flag = p + 1;
+  if (tid == 0 && bad && *a.flag == 0) *a.flag = p + 1;
 }
 
 // Tiles (i, j), p < j <= i: L_ip = G_ip Li_pp^T, G_ij -= L_ip L_jp^T.
 // The diagonal tile (i, i) stores L_ip and zeroes the upper tile (p, i).
-__global__ __launch_bounds__(256) void chol_trail_kernel(double* G, int ld, int m, int p, double* L,
-                                                         const double* Li) {
+PPCG_DEV void chol_trail_body(const DenseStep& a, int p, unsigned wg) {
   __shared__ double Lp[CB * CLD], Ai[CB * CLD], Aj[CB * CLD];
+  const int m = a.m, ld = a.ld;
   const int nbk = (m + CB - 1) / CB;
   const int span = nbk - p - 1;
-  const int i = p + 1 + blockIdx.x % span, j = p + 1 + blockIdx.x / span;
+  const int i = p + 1 + wg % span, j = p + 1 + wg / span;
   if (j > i) return;
   const int tid = threadIdx.x;
   const int n0 = p * CB, ni0 = i * CB, nj0 = j * CB;
   const int nbp = min(CB, m - n0), nbi = min(CB, m - ni0), nbj = min(CB, m - nj0);
   for (int e = tid; e < CB * CB; e += 256) {
     int x = e % CB, y = e / CB;
-    Lp[x + y * CLD] = (x < nbp && y < nbp) ? Li[(n0 + x) + (long)(n0 + y) * ld] : 0.0;
-    Ai[x + y * CLD] = (x < nbi && y < nbp) ? G[(ni0 + x) + (long)(n0 + y) * ld] : 0.0;
-    Aj[x + y * CLD] = (x < nbj && y < nbp) ? G[(nj0 + x) + (long)(n0 + y) * ld] : 0.0;
+    Lp[x + y * CLD] = (x < nbp && y < nbp) ? a.Li[(n0 + x) + (long)(n0 + y) * ld] : 0.0;
+    Ai[x + y * CLD] = (x < nbi && y < nbp) ? a.G[(ni0 + x) + (long)(n0 + y) * ld] : 0.0;
+    Aj[x + y * CLD] = (x < nbj && y < nbp) ? a.G[(nj0 + x) + (long)(n0 + y) * ld] : 0.0;
   }
   __syncthreads();
-  // L_ip[x][y] = sum_t A_ip[x][t] Li_pp[y][t]   (register results, 4 per thread)
   double li[4], lj[4];
   for (int s = 0; s < 4; ++s) {
     int e = tid + 256 * s, x = e % CB, y = e / CB;
@@ -111,20 +162,21 @@ __global__ __launch_bounds__(256) void chol_trail_kernel(double* G, int ld, int 
     if (x < nbi && y < nbj && (i != j || x >= y)) {
       double acc = 0;
       for (int t = 0; t < CB; ++t) acc += Ai[x + t * CLD] * Aj[y + t * CLD];
-      G[(ni0 + x) + (long)(nj0 + y) * ld] -= acc;
+      a.G[(ni0 + x) + (long)(nj0 + y) * ld] -= acc;
     }
     if (i == j && x < nbi && y < nbp) {
-      L[(ni0 + x) + (long)(n0 + y) * ld] = Ai[x + y * CLD];
-      L[(n0 + y) + (long)(ni0 + x) * ld] = 0.0;
+      a.L[(ni0 + x) + (long)(n0 + y) * ld] = Ai[x + y * CLD];
+      a.L[(n0 + y) + (long)(ni0 + x) * ld] = 0.0;
     }
   }
 }
 
 // Off-diagonal tiles of L^{-1} along block diagonal d:
 // Li_ij = -Li_ii sum_{t=j}^{i-1} L_it Li_tj, with i = j + d; zeroes tile (j, i).
-__global__ __launch_bounds__(256) void trinv_kernel(const double* L, double* Li, int ld, int m, int d) {
+PPCG_DEV void trinv_body(const DenseStep& a, int d, unsigned wg) {
   __shared__ double A[CB * CLD], B[CB * CLD], S[CB * CLD];
-  const int j = blockIdx.x, i = j + d;
+  const int m = a.m, ld = a.ld;
+  const int j = (int)wg, i = j + d;
   const int tid = threadIdx.x;
   const int ni0 = i * CB, nj0 = j * CB;
   const int nbi = min(CB, m - ni0), nbj = min(CB, m - nj0);
@@ -134,15 +186,15 @@ __global__ __launch_bounds__(256) void trinv_kernel(const double* L, double* Li,
     __syncthreads();
     for (int e = tid; e < CB * CB; e += 256) {
       int x = e % CB, y = e / CB;
-      A[x + y * CLD] = (x < nbi && y < nbt) ? L[(ni0 + x) + (long)(nt0 + y) * ld] : 0.0;
-      B[x + y * CLD] = (x < nbt && y < nbj) ? Li[(nt0 + x) + (long)(nj0 + y) * ld] : 0.0;
+      A[x + y * CLD] = (x < nbi && y < nbt) ? a.L[(ni0 + x) + (long)(nt0 + y) * ld] : 0.0;
+      B[x + y * CLD] = (x < nbt && y < nbj) ? a.Li[(nt0 + x) + (long)(nj0 + y) * ld] : 0.0;
     }
     __syncthreads();
     for (int s = 0; s < 4; ++s) {
       int e = tid + 256 * s, x = e % CB, y = e / CB;
-      double a = 0;
-      for (int u = 0; u < CB; ++u) a += A[x + u * CLD] * B[u + y * CLD];
-      acc[s] += a;
+      double v = 0;
+      for (int u = 0; u < CB; ++u) v += A[x + u * CLD] * B[u + y * CLD];
+      acc[s] += v;
     }
   }
   __syncthreads();
@@ -152,343 +204,511 @@ __global__ __launch_bounds__(256) void trinv_kernel(const double* L, double* Li,
   }
   for (int e = tid; e < CB * CB; e += 256) {
     int x = e % CB, y = e / CB;
-    A[x + y * CLD] = (x < nbi && y < nbi) ? Li[(ni0 + x) + (long)(ni0 + y) * ld] : 0.0;
+    A[x + y * CLD] = (x < nbi && y < nbi) ? a.Li[(ni0 + x) + (long)(ni0 + y) * ld] : 0.0;
   }
   __syncthreads();
   for (int s = 0; s < 4; ++s) {
     int e = tid + 256 * s, x = e % CB, y = e / CB;
     if (x < nbi && y < nbj) {
-      double a = 0;
-      for (int u = 0; u <= x; ++u) a += A[x + u * CLD] * S[u + y * CLD];
-      Li[(ni0 + x) + (long)(nj0 + y) * ld] = -a;
-      Li[(nj0 + y) + (long)(ni0 + x) * ld] = 0.0;
+      double v = 0;
+      for (int u = 0; u <= x; ++u) v += A[x + u * CLD] * S[u + y * CLD];
+      a.Li[(ni0 + x) + (long)(nj0 + y) * ld] = -v;
+      a.Li[(nj0 + y) + (long)(ni0 + x) * ld] = 0.0;
     }
   }
 }
 
-void chol_inverse(double* G, double* L, double* Linv, int m, int ld, int* flag, hipStream_t st) {
-  const int nbk = (m + CB - 1) / CB;
-  for (int p = 0; p < nbk; ++p) {
-    hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(256), 0, st, G, ld, m, p, L, Linv, flag);
-    int span = nbk - p - 1;
-    if (span > 0) hipLaunchKernelGGL(chol_trail_kernel, dim3(span * span), dim3(256), 0, st, G, ld, m, p, L, Linv);
+// step: 0 = diagonal tile p, 1 = trailing update after p, 2 = inverse diagonal p
+__global__ __launch_bounds__(256) void chol_step_grouped(const DenseStep* jobs, const unsigned* start, int nj,
+                                                         int step, int p) {
+  int j = find_job(start, nj, blockIdx.x);
+  unsigned wg = blockIdx.x - start[j];
+  if (step == 0) chol_diag_body(jobs[j], p);
+  else if (step == 1) chol_trail_body(jobs[j], p, wg);
+  else trinv_body(jobs[j], p, wg);
+}
+
+void chol_inverse_grouped(const std::vector<CholArgs>& jobs, Stage& stage, hipStream_t st) {
+  const int nj = (int)jobs.size();
+  if (nj == 0) return;
+  std::vector<DenseStep> ds(nj);
+  int P = 0;
+  for (int j = 0; j < nj; ++j) {
+    ds[j] = DenseStep{jobs[j].G, jobs[j].L, jobs[j].Li, jobs[j].ld, jobs[j].m, jobs[j].flag};
+    P = std::max(P, (jobs[j].m + CB - 1) / CB);
   }
-  for (int d = 1; d < nbk; ++d)
-    hipLaunchKernelGGL(trinv_kernel, dim3(nbk - d), dim3(256), 0, st, L, Linv, ld, m, d);
+  // every launch of the composite: (step, p) and its workgroup prefix sums,
+  // packed with the job array into one upload
+  struct L { int step, p; unsigned tot; size_t off; };
+  std::vector<L> ls;
+  std::vector<unsigned> starts;
+  auto plan = [&](int step, int p, auto wgs_of) {
+    L l{step, p, 0, starts.size()};
+    for (int j = 0; j < nj; ++j) {
+      starts.push_back(l.tot);
+      l.tot += wgs_of((jobs[j].m + CB - 1) / CB);
+    }
+    starts.push_back(l.tot);
+    if (l.tot) ls.push_back(l);
+  };
+  for (int p = 0; p < P; ++p) {
+    plan(0, p, [&](int nbk) { return (unsigned)(p < nbk ? 1 : 0); });
+    plan(1, p, [&](int nbk) {
+      int span = nbk - p - 1;
+      return (unsigned)(span > 0 ? span * span : 0);
+    });
+  }
+  for (int d = 1; d < P; ++d) plan(2, d, [&](int nbk) { return (unsigned)(d < nbk ? nbk - d : 0); });
+  size_t jb = sizeof(DenseStep) * nj;
+  std::vector<uint8_t> buf(jb + sizeof(unsigned) * starts.size());
+  std::memcpy(buf.data(), ds.data(), jb);
+  std::memcpy(buf.data() + jb, starts.data(), sizeof(unsigned) * starts.size());
+  uint8_t* dev = (uint8_t*)stage.upload(buf.data(), buf.size(), st);
+  const DenseStep* dj = (const DenseStep*)dev;
+  const unsigned* sd = (const unsigned*)(dev + jb);
+  for (const L& l : ls)
+    hipLaunchKernelGGL(chol_step_grouped, dim3(l.tot), dim3(256), 0, st, dj, sd + l.off, nj, l.step, l.p);
 }
 
 // ---------------------------------------------------------------------------
-__global__ void transpose_kernel(const double* src, int lds, double* dst, int ldd, int m, int n) {
+// small element-wise kernels (direct and grouped)
+// ---------------------------------------------------------------------------
+PPCG_DEV void transpose_body(const TransposeArgs& a, unsigned wg, unsigned) {
   __shared__ double t[32][33];
-  int bx = blockIdx.x * 32, by = blockIdx.y * 32;
-  int tx = threadIdx.x, ty = threadIdx.y;
+  const unsigned gx = (a.m + 31) / 32;
+  int bx = (wg % gx) * 32, by = (wg / gx) * 32;
+  int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
   for (int k = ty; k < 32; k += 8) {
     int r = bx + tx, c = by + k;
-    if (r < m && c < n) t[k][tx] = src[r + (long)c * lds];
+    if (r < a.m && c < a.n) t[k][tx] = a.src[r + (long)c * a.lds];
   }
   __syncthreads();
   for (int k = ty; k < 32; k += 8) {
     int r = by + tx, c = bx + k;  // dst is n x m
-    if (r < n && c < m) dst[r + (long)c * ldd] = t[tx][k];
+    if (r < a.n && c < a.m) a.dst[r + (long)c * a.ldd] = t[tx][k];
   }
 }
-void launch_transpose(const double* src, int lds, double* dst, int ldd, int m, int n, hipStream_t st) {
-  dim3 g((m + 31) / 32, (n + 31) / 32);
-  hipLaunchKernelGGL(transpose_kernel, g, dim3(32, 8), 0, st, src, lds, dst, ldd, m, n);
+PPCG_DEV void fill_body(const FillArgs& a, unsigned wg, unsigned) {
+  long e = wg * 256L + threadIdx.x;
+  if (e < a.count) a.p[e] = a.v;
 }
-
-__global__ void fill_kernel(double* p, long count, double v) {
-  long e = blockIdx.x * 256L + threadIdx.x;
-  if (e < count) p[e] = v;
+PPCG_DEV void set_diag_body(const SetDiagArgs& a, unsigned wg, unsigned) {
+  long e = wg * 256L + threadIdx.x;
+  if (e >= (long)a.m * a.m) return;
+  int i = e % a.m, j = e / a.m;
+  a.G[i + (long)j * a.ld] = (i == j) ? a.lam[i] : 0.0;
 }
-void launch_fill(double* p, long count, double v, hipStream_t st) {
-  if (count <= 0) return;
-  hipLaunchKernelGGL(fill_kernel, dim3((count + 255) / 256), dim3(256), 0, st, p, count, v);
-}
-
-__global__ void set_diag_kernel(double* G, int ld, int m, const double* lam) {
-  long e = blockIdx.x * 256L + threadIdx.x;
-  if (e >= (long)m * m) return;
-  int i = e % m, j = e / m;
-  G[i + (long)j * ld] = (i == j) ? lam[i] : 0.0;
-}
-void launch_set_diag(double* G, int ld, int m, const double* lam, hipStream_t st) {
-  long t = (long)m * m;
-  if (t == 0) return;
-  hipLaunchKernelGGL(set_diag_kernel, dim3((t + 255) / 256), dim3(256), 0, st, G, ld, m, lam);
-}
-
-__global__ void symmetrize_kernel(double* G, int ld, int m) {
-  long e = blockIdx.x * 256L + threadIdx.x;
-  if (e >= (long)m * m) return;
-  int i = e % m, j = e / m;
+PPCG_DEV void symm_body(const SymmArgs& a, unsigned wg, unsigned) {
+  long e = wg * 256L + threadIdx.x;
+  if (e >= (long)a.m * a.m) return;
+  int i = e % a.m, j = e / a.m;
   if (i < j) {
-    double v = 0.5 * (G[i + (long)j * ld] + G[j + (long)i * ld]);
-    G[i + (long)j * ld] = v;
-    G[j + (long)i * ld] = v;
+    double v = 0.5 * (a.G[i + (long)j * a.ld] + a.G[j + (long)i * a.ld]);
+    a.G[i + (long)j * a.ld] = v;
+    a.G[j + (long)i * a.ld] = v;
   }
 }
-void launch_symmetrize(double* G, int ld, int m, hipStream_t st) {
-  long t = (long)m * m;
-  if (t == 0) return;
-  hipLaunchKernelGGL(symmetrize_kernel, dim3((t + 255) / 256), dim3(256), 0, st, G, ld, m);
-}
-
 // out[j] = sum_{i < nw} G[i, j]^2 for j < nw (one workgroup per column)
-__global__ __launch_bounds__(256) void frob2_sub_kernel(const double* G, int ld, int nw, double* out) {
-  const double* g = G + (long)blockIdx.x * ld;
+PPCG_DEV void frob2_body(const Frob2Args& a, unsigned wg, unsigned) {
+  const double* g = a.G + (long)wg * a.ld;
   double s = 0;
-  for (int i = threadIdx.x; i < nw; i += 256) s += g[i] * g[i];
+  for (int i = threadIdx.x; i < a.nw; i += 256) s += g[i] * g[i];
   __shared__ double red[4];
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) out[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+  if (threadIdx.x == 0) a.out[wg] = (red[0] + red[1]) + (red[2] + red[3]);
 }
-void launch_frob2_sub(const double* G, int ld, int nw, double* out, hipStream_t st) {
-  if (nw > 0) hipLaunchKernelGGL(frob2_sub_kernel, dim3(nw), dim3(256), 0, st, G, ld, nw, out);
-}
-
-__global__ __launch_bounds__(256) void orth_err2_kernel(const double* G, int ld, int k, double* out) {
+PPCG_DEV void orth_body(const OrthArgs& a, unsigned, unsigned) {
   double s = 0;
-  for (long e = threadIdx.x; e < (long)k * k; e += 256) {
-    long i = e % k, j = e / k;
-    double v = G[i + j * ld] - (i == j ? 1.0 : 0.0);
+  for (long e = threadIdx.x; e < (long)a.k * a.k; e += 256) {
+    long i = e % a.k, j = e / a.k;
+    double v = a.G[i + j * a.ld] - (i == j ? 1.0 : 0.0);
     s += v * v;
   }
   __shared__ double red[4];
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) *out = (red[0] + red[1]) + (red[2] + red[3]);
+  if (threadIdx.x == 0) *a.out = (red[0] + red[1]) + (red[2] + red[3]);
+}
+PPCG_DEV void zero_int_body(const ZeroIntArgs& a, unsigned wg, unsigned) {
+  int e = wg * 256 + threadIdx.x;
+  if (e < a.n) a.p[e] = 0;
+}
+PPCG_DEV void copy_body(const CopyArgs& a, unsigned wg, unsigned) {
+  long e = wg * 256L + threadIdx.x;
+  if (e < a.count) a.dst[e] = a.src[e];
+}
+
+#define PPCG_SIMPLE(NAME, ARGS)                                                                          \
+  __global__ __launch_bounds__(256) void NAME##_kernel(ARGS a) { NAME##_body(a, blockIdx.x, gridDim.x); } \
+  __global__ __launch_bounds__(256) void NAME##_grouped(const ARGS* jobs, const unsigned* start, int nj) { \
+    int j = find_job(start, nj, blockIdx.x);                                                              \
+    NAME##_body(jobs[j], blockIdx.x - start[j], start[j + 1] - start[j]);                                 \
+  }
+PPCG_SIMPLE(transpose, TransposeArgs)
+PPCG_SIMPLE(fill, FillArgs)
+PPCG_SIMPLE(set_diag, SetDiagArgs)
+PPCG_SIMPLE(symm, SymmArgs)
+PPCG_SIMPLE(frob2, Frob2Args)
+PPCG_SIMPLE(orth, OrthArgs)
+PPCG_SIMPLE(zero_int, ZeroIntArgs)
+PPCG_SIMPLE(copy, CopyArgs)
+#undef PPCG_SIMPLE
+
+template <class A>
+static void simple_launch(int kind, void (*k)(A), const A& a, unsigned blocks, hipStream_t st) {
+  if (g_rec) {
+    g_rec->add(kind, &a, sizeof(a), blocks);
+    return;
+  }
+  if (blocks == 0) return;
+  hipLaunchKernelGGL(k, dim3(blocks), dim3(256), 0, st, a);
+}
+
+void launch_transpose(const double* src, int lds, double* dst, int ldd, int m, int n, hipStream_t st) {
+  TransposeArgs a{src, lds, dst, ldd, m, n};
+  simple_launch(OP_TRANSPOSE, transpose_kernel, a, (unsigned)(((m + 31) / 32) * ((n + 31) / 32)), st);
+}
+void launch_fill(double* p, long count, double v, hipStream_t st) {
+  FillArgs a{p, count, v};
+  simple_launch(OP_FILL, fill_kernel, a, (unsigned)(count > 0 ? (count + 255) / 256 : 0), st);
+}
+void launch_set_diag(double* G, int ld, int m, const double* lam, hipStream_t st) {
+  SetDiagArgs a{G, ld, m, lam};
+  long t = (long)m * m;
+  simple_launch(OP_SETDIAG, set_diag_kernel, a, (unsigned)((t + 255) / 256), st);
+}
+void launch_symmetrize(double* G, int ld, int m, hipStream_t st) {
+  SymmArgs a{G, ld, m};
+  long t = (long)m * m;
+  simple_launch(OP_SYMM, symm_kernel, a, (unsigned)((t + 255) / 256), st);
+}
+void launch_frob2_sub(const double* G, int ld, int nw, double* out, hipStream_t st) {
+  Frob2Args a{G, ld, nw, out};
+  simple_launch(OP_FROB2, frob2_kernel, a, (unsigned)(nw > 0 ? nw : 0), st);
 }
 void launch_orth_err2(const double* G, int ld, int k, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(orth_err2_kernel, dim3(1), dim3(256), 0, st, G, ld, k, out);
+  OrthArgs a{G, ld, k, out};
+  simple_launch(OP_ORTH, orth_kernel, a, 1u, st);
+}
+void launch_zero_int(int* p, int n, hipStream_t st) {
+  ZeroIntArgs a{p, n};
+  simple_launch(OP_ZEROINT, zero_int_kernel, a, (unsigned)(n > 0 ? (n + 255) / 256 : 0), st);
+}
+void launch_copy(const double* src, double* dst, long count, hipStream_t st) {
+  CopyArgs a{src, dst, count};
+  simple_launch(OP_COPY, copy_kernel, a, (unsigned)(count > 0 ? (count + 255) / 256 : 0), st);
+}
+void launch_d2h(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  if (g_rec) {
+    D2HArgs a{dst, src, bytes};
+    g_rec->add(OP_D2H, &a, sizeof(a), 0);
+    return;
+  }
+  if (bytes) hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st);
+}
+
+bool launch_grouped_dense(int kind, const void* jobs, const unsigned* start, int nj, unsigned total, hipStream_t st) {
+#define PPCG_G(NAME, ARGS) \
+  hipLaunchKernelGGL(NAME##_grouped, dim3(total), dim3(256), 0, st, (const ARGS*)jobs, start, nj)
+  switch (kind) {
+    case OP_TRANSPOSE: PPCG_G(transpose, TransposeArgs); return true;
+    case OP_FILL: PPCG_G(fill, FillArgs); return true;
+    case OP_SETDIAG: PPCG_G(set_diag, SetDiagArgs); return true;
+    case OP_SYMM: PPCG_G(symm, SymmArgs); return true;
+    case OP_FROB2: PPCG_G(frob2, Frob2Args); return true;
+    case OP_ORTH: PPCG_G(orth, OrthArgs); return true;
+    case OP_ZEROINT: PPCG_G(zero_int, ZeroIntArgs); return true;
+    case OP_COPY: PPCG_G(copy, CopyArgs); return true;
+  }
+#undef PPCG_G
+  return false;
 }
 
 // ---------------------------------------------------------------------------
 // block Jacobi
 // ---------------------------------------------------------------------------
 constexpr int JB = 16;           // block width
+constexpr int J2 = 2 * JB;       // pair size
+constexpr int JLD = J2 + 1;
 // Rotations are skipped once |M_pq| <= rel_tol |M|_F.  Off-diagonal entries
 // of that size change the Ritz residual of a column by at most
 // rel_tol |M|_F sqrt(K) (the caller keeps this far below its locking
 // threshold) and the eigenvalues (Rayleigh quotients of the rotated
 // columns) by O(off^2 / gap).
-constexpr int J2 = 2 * JB;       // pair size
-constexpr int JLD = J2 + 1;
 
-struct JacobiWork {
-  double* Q;       // npairs x J2 x J2
-  int* flags;      // npairs
-  int* counter;    // 1
-  double* tiny;    // 1
-  double* Vt;      // m x m (ld m) accumulated rotations
+struct EigDev {
+  double* M;
+  int ld, m;
+  double* V;
+  int ldv;
+  double* lam;
+  double* Q;       // np x J2 x J2
+  double* Vt;      // m x m accumulated rotations
+  double* tiny;
+  int* flags;      // np
   int* rank;       // m
+  int* counter;    // shared by all problems of a call
+  double rel_tol;
+  int nbe, np;
 };
 
-static JacobiWork carve(void* work, int m) {
-  int nblk = (m + JB - 1) / JB;
-  int np = (nblk + 1) / 2;
-  char* p = (char*)work;
-  JacobiWork w;
+static EigDev carve(const EigJob& j, int* counter) {
+  int nblk = (j.m + JB - 1) / JB;
+  int nbe = nblk + (nblk & 1);
+  int np = nbe / 2;
+  char* p = (char*)j.work;
+  EigDev w{};
+  w.M = j.M;
+  w.ld = j.ld;
+  w.m = j.m;
+  w.V = j.V;
+  w.ldv = j.ldv;
+  w.lam = j.lam;
   w.Q = (double*)p; p += sizeof(double) * np * J2 * J2;
-  w.Vt = (double*)p; p += sizeof(double) * (size_t)m * m;
+  w.Vt = (double*)p; p += sizeof(double) * (size_t)j.m * j.m;
   w.tiny = (double*)p; p += 256;
   w.flags = (int*)p; p += sizeof(int) * ((np + 63) / 64 * 64);
-  w.counter = (int*)p; p += 256;
   w.rank = (int*)p;
+  w.counter = counter;
+  w.rel_tol = j.rel_tol;
+  w.nbe = nbe;
+  w.np = np;
   return w;
 }
 size_t eig_workspace_bytes(int m) {
   int nblk = (m + JB - 1) / JB;
   int np = (nblk + 1) / 2;
   return sizeof(double) * (size_t)np * J2 * J2 + sizeof(double) * (size_t)m * m + 256 +
-         sizeof(int) * ((np + 63) / 64 * 64) + 256 + sizeof(int) * (size_t)m + 256;
+         sizeof(int) * ((np + 63) / 64 * 64) + sizeof(int) * (size_t)m + 256;
 }
 
-PPCG_DEV int pair_block(int t, int round, int nbe) { return rr_player(t, round, nbe); }
+PPCG_DEV void pair_of(const EigDev& a, int t, int round, int& nI, int& nJ, int& i0, int& j0) {
+  const int nblk = (a.m + JB - 1) / JB;
+  int I = rr_player(t, round, a.nbe), J = rr_player(a.nbe - 1 - t, round, a.nbe);
+  if (I > J) { int x = I; I = J; J = x; }
+  i0 = I * JB;
+  j0 = J * JB;
+  nI = I < nblk ? min(JB, a.m - i0) : 0;
+  nJ = J < nblk ? min(JB, a.m - j0) : 0;
+}
 
-__global__ __launch_bounds__(256) void bj_norm_kernel(const double* M, int ld, int m, double* tiny, int* counter,
-                                                      double rel_tol) {
-  double s = 0;
-  for (long e = threadIdx.x; e < (long)m * m; e += 256) {
-    double v = M[(e % m) + (e / m) * ld];
-    s += v * v;
-  }
-  __shared__ double red[4];
-  s = wave_sum(s);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    *tiny = rel_tol * sqrt((red[0] + red[1]) + (red[2] + red[3]));
-    *counter = 0;
+// step kernels; `round` is shared by all jobs of a launch
+PPCG_DEV void bj_init_body(const EigDev& a, unsigned wg) {  // Vt = I; tiny; (counter zeroed by host)
+  long mm = (long)a.m * a.m;
+  for (long e = wg * 256L + threadIdx.x; e < mm; e += 256L * 64) a.Vt[e] = ((e % a.m) == (e / a.m)) ? 1.0 : 0.0;
+  if (wg == 0) {
+    double s = 0;
+    for (long e = threadIdx.x; e < mm; e += 256) {
+      double v = a.M[(e % a.m) + (e / a.m) * a.ld];
+      s += v * v;
+    }
+    __shared__ double red[4];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) *a.tiny = a.rel_tol * sqrt((red[0] + red[1]) + (red[2] + red[3]));
   }
 }
 
-__global__ void bj_zero_kernel(int* counter) { *counter = 0; }
-
-__global__ __launch_bounds__(256) void bj_pair_kernel(double* M, int ld, int m, int nbe, int round, double* Qbuf,
-                                                      int* flags, int* counter, const double* tinyp) {
+PPCG_DEV void bj_pair_body(const EigDev& a, int round, unsigned t) {
   __shared__ double S[J2 * JLD], Q[J2 * JLD];
   __shared__ double cs[J2 + 2];
   __shared__ int pq[J2 + 2], cnt, any;
-  const int tid = threadIdx.x, t = blockIdx.x;
-  const int nblk = (m + JB - 1) / JB;
-  int I = pair_block(t, round, nbe), J = pair_block(nbe - 1 - t, round, nbe);
-  if (I > J) { int x = I; I = J; J = x; }
-  const int i0 = I * JB, j0 = J * JB;
-  const int nI = I < nblk ? min(JB, m - i0) : 0;
-  const int nJ = J < nblk ? min(JB, m - j0) : 0;
+  const int tid = threadIdx.x;
+  if (round >= a.nbe - 1 && !(a.nbe == 1 && round == 0)) return;
+  int nI, nJ, i0, j0;
+  pair_of(a, t, round, nI, nJ, i0, j0);
   const int n2 = nI + nJ;
-  auto gidx = [&](int a) { return a < nI ? i0 + a : j0 + (a - nI); };
-  const double tiny = *tinyp;
+  auto gidx = [&](int x) { return x < nI ? i0 + x : j0 + (x - nI); };
+  const double tiny = *a.tiny;
   if (tid == 0) any = 0;
   __syncthreads();
   for (int e = tid; e < n2 * n2; e += 256) {
     int x = e % n2, y = e / n2;
-    double v = M[gidx(x) + (long)gidx(y) * ld];
+    double v = a.M[gidx(x) + (long)gidx(y) * a.ld];
     S[x + y * JLD] = v;
     if (x != y && fabs(v) > tiny) any = 1;
   }
   __syncthreads();
   if (!any) {
-    if (tid == 0) flags[t] = 0;
+    if (tid == 0) a.flags[t] = 0;
     return;
   }
   lds_jacobi<256>(S, Q, n2, JLD, tiny, 40, cs, pq, &cnt);
-  double* Qg = Qbuf + (long)t * J2 * J2;
+  double* Qg = a.Q + (long)t * J2 * J2;
   for (int e = tid; e < n2 * n2; e += 256) Qg[(e % n2) + (e / n2) * J2] = Q[(e % n2) + (e / n2) * JLD];
   if (tid == 0) {
-    flags[t] = 1;
-    atomicAdd(counter, 1);
+    a.flags[t] = 1;
+    atomicAdd(a.counter, 1);
   }
 }
 
-// rows of each rotated pair: M[rows, chunk] <- Q^T M[rows, chunk], 64 columns per workgroup
-__global__ __launch_bounds__(256) void bj_row_kernel(double* M, int ld, int m, int nbe, int round, const double* Qbuf,
-                                                     const int* flags) {
-  __shared__ double Q[J2 * JLD], R[J2 * 65];
-  const int t = blockIdx.x;
-  if (!flags[t]) return;
-  const int tid = threadIdx.x;
-  const int nblk = (m + JB - 1) / JB;
-  int I = pair_block(t, round, nbe), J = pair_block(nbe - 1 - t, round, nbe);
-  if (I > J) { int x = I; I = J; J = x; }
-  const int i0 = I * JB, j0 = J * JB;
-  const int nI = I < nblk ? min(JB, m - i0) : 0;
-  const int nJ = J < nblk ? min(JB, m - j0) : 0;
-  const int n2 = nI + nJ;
-  auto gidx = [&](int a) { return a < nI ? i0 + a : j0 + (a - nI); };
-  const double* Qg = Qbuf + (long)t * J2 * J2;
-  for (int e = tid; e < n2 * n2; e += 256) Q[(e % n2) + (e / n2) * JLD] = Qg[(e % n2) + (e / n2) * J2];
-  const int c0 = blockIdx.y * 64;
-  const int nc = min(64, m - c0);
-  for (int e = tid; e < n2 * nc; e += 256) {
-    int x = e % n2, c = e / n2;
-    R[x + c * J2] = M[gidx(x) + (long)(c0 + c) * ld];
-  }
-  __syncthreads();
-  for (int e = tid; e < n2 * nc; e += 256) {
-    int x = e % n2, c = e / n2;
-    double s = 0;
-    for (int u = 0; u < n2; ++u) s += Q[u + x * JLD] * R[u + c * J2];
-    M[gidx(x) + (long)(c0 + c) * ld] = s;
-  }
-}
-
-__global__ __launch_bounds__(256) void bj_col_kernel(double* M, int ld, double* V, int ldv, int m, int nbe,
-                                                     int round, const double* Qbuf, const int* flags) {
+// which = 0: rows of the pair, M[rows, chunk] <- Q^T M[rows, chunk]
+// which = 1: columns of the pair for M and Vt, A[chunk, cols] <- A[chunk, cols] Q
+PPCG_DEV void bj_apply_body(const EigDev& a, int round, unsigned wg, int which) {
   __shared__ double Q[J2 * JLD], R[64 * (J2 + 1)];
-  const int t = blockIdx.x;
-  if (!flags[t]) return;
+  if (round >= a.nbe - 1 && !(a.nbe == 1 && round == 0)) return;
+  const int t = (int)(wg % a.np);
+  const int chunk = (int)(wg / a.np);
+  if (!a.flags[t]) return;
   const int tid = threadIdx.x;
-  const int nblk = (m + JB - 1) / JB;
-  int I = pair_block(t, round, nbe), J = pair_block(nbe - 1 - t, round, nbe);
-  if (I > J) { int x = I; I = J; J = x; }
-  const int i0 = I * JB, j0 = J * JB;
-  const int nI = I < nblk ? min(JB, m - i0) : 0;
-  const int nJ = J < nblk ? min(JB, m - j0) : 0;
+  int nI, nJ, i0, j0;
+  pair_of(a, t, round, nI, nJ, i0, j0);
   const int n2 = nI + nJ;
-  auto gidx = [&](int a) { return a < nI ? i0 + a : j0 + (a - nI); };
-  const double* Qg = Qbuf + (long)t * J2 * J2;
+  auto gidx = [&](int x) { return x < nI ? i0 + x : j0 + (x - nI); };
+  const double* Qg = a.Q + (long)t * J2 * J2;
   for (int e = tid; e < n2 * n2; e += 256) Q[(e % n2) + (e / n2) * JLD] = Qg[(e % n2) + (e / n2) * J2];
-  const int r0 = blockIdx.y * 64;
-  const int nr = min(64, m - r0);
+  const int c0 = chunk * 64;
+  const int nc = min(64, a.m - c0);
   constexpr int RLD = J2 + 1;
-  for (int which = 0; which < 2; ++which) {
-    double* A = which ? V : M;
-    const int lda = which ? ldv : ld;
+  if (which == 0) {
     __syncthreads();
-    for (int e = tid; e < nr * n2; e += 256) {
-      int r = e % nr, x = e / nr;
-      R[x + r * RLD] = A[(r0 + r) + (long)gidx(x) * lda];
+    for (int e = tid; e < n2 * nc; e += 256) {
+      int x = e % n2, c = e / n2;
+      R[x + c * RLD] = a.M[gidx(x) + (long)(c0 + c) * a.ld];
     }
     __syncthreads();
-    for (int e = tid; e < nr * n2; e += 256) {
-      int r = e % nr, x = e / nr;
+    for (int e = tid; e < n2 * nc; e += 256) {
+      int x = e % n2, c = e / n2;
+      double s = 0;
+      for (int u = 0; u < n2; ++u) s += Q[u + x * JLD] * R[u + c * RLD];
+      a.M[gidx(x) + (long)(c0 + c) * a.ld] = s;
+    }
+    return;
+  }
+  for (int w = 0; w < 2; ++w) {
+    double* A = w ? a.Vt : a.M;
+    const int lda = w ? a.m : a.ld;
+    __syncthreads();
+    for (int e = tid; e < nc * n2; e += 256) {
+      int r = e % nc, x = e / nc;
+      R[x + r * RLD] = A[(c0 + r) + (long)gidx(x) * lda];
+    }
+    __syncthreads();
+    for (int e = tid; e < nc * n2; e += 256) {
+      int r = e % nc, x = e / nc;
       double s = 0;
       for (int u = 0; u < n2; ++u) s += R[u + r * RLD] * Q[u + x * JLD];
-      A[(r0 + r) + (long)gidx(x) * lda] = s;
+      A[(c0 + r) + (long)gidx(x) * lda] = s;
     }
   }
 }
 
-__global__ __launch_bounds__(1024) void bj_rank_kernel(const double* M, int ld, int m, double* lam, int* rank) {
-  for (int x = threadIdx.x; x < m; x += 1024) {
-    double lx = M[x + (long)x * ld];
+// ranks of the diagonal (ascending, ties by index) -> lam; then Vt columns gathered into V
+PPCG_DEV void bj_rank_body(const EigDev& a) {
+  for (int x = threadIdx.x; x < a.m; x += 256) {
+    double lx = a.M[x + (long)x * a.ld];
     int rk = 0;
-    for (int y = 0; y < m; ++y) {
-      double ly = M[y + (long)y * ld];
+    for (int y = 0; y < a.m; ++y) {
+      double ly = a.M[y + (long)y * a.ld];
       rk += (ly < lx) || (ly == lx && y < x);
     }
-    rank[x] = rk;
-    lam[rk] = lx;
+    a.rank[x] = rk;
+    a.lam[rk] = lx;
+  }
+}
+PPCG_DEV void bj_gather_body(const EigDev& a, unsigned wg) {
+  long e = wg * 256L + threadIdx.x;
+  if (e >= (long)a.m * a.m) return;
+  int i = e % a.m, j = e / a.m;
+  a.V[i + (long)a.rank[j] * a.ldv] = a.Vt[i + (long)j * a.m];
+}
+
+// step: 0 init, 1 pair, 2 rows, 3 cols, 4 rank, 5 gather
+__global__ __launch_bounds__(256) void bj_grouped(const EigDev* jobs, const unsigned* start, int nj, int step,
+                                                  int round) {
+  int j = find_job(start, nj, blockIdx.x);
+  unsigned wg = blockIdx.x - start[j];
+  const EigDev& a = jobs[j];
+  switch (step) {
+    case 0: bj_init_body(a, wg); break;
+    case 1: bj_pair_body(a, round, wg); break;
+    case 2: bj_apply_body(a, round, wg, 0); break;
+    case 3: bj_apply_body(a, round, wg, 1); break;
+    case 4: bj_rank_body(a); break;
+    case 5: bj_gather_body(a, wg); break;
   }
 }
 
-__global__ void bj_gather_kernel(const double* Vt, int m, const int* rank, double* V, int ldv) {
-  long e = blockIdx.x * 256L + threadIdx.x;
-  if (e >= (long)m * m) return;
-  int i = e % m, j = e / m;
-  V[i + (long)rank[j] * ldv] = Vt[i + (long)j * m];
-}
+int block_jacobi_eig_grouped(const std::vector<EigJob>& jobs, Stage& stage, int* dev_counter, int* host_counter,
+                             hipStream_t st) {
+  const int nj = (int)jobs.size();
+  if (nj == 0) return 0;
+  std::vector<EigDev> ed(nj);
+  int maxr = 1;
+  for (int j = 0; j < nj; ++j) {
+    ed[j] = carve(jobs[j], dev_counter);
+    maxr = std::max(maxr, ed[j].nbe - 1);
+  }
 
-__global__ void identity_kernel(double* V, int m) {
-  long e = blockIdx.x * 256L + threadIdx.x;
-  if (e >= (long)m * m) return;
-  V[e] = ((e % m) == (e / m)) ? 1.0 : 0.0;
-}
-
-int block_jacobi_eig(double* M, int ld, int m, double* V, int ldv, double* lam, void* work, int* hostbuf,
-                     double rel_tol, hipStream_t st) {
-  JacobiWork w = carve(work, m);
-  const int nblk = (m + JB - 1) / JB;
-  const int nbe = nblk + (nblk & 1);
-  const int np = nbe / 2;
-  long mm = (long)m * m;
-  hipLaunchKernelGGL(identity_kernel, dim3((mm + 255) / 256), dim3(256), 0, st, w.Vt, m);
-  hipLaunchKernelGGL(bj_norm_kernel, dim3(1), dim3(256), 0, st, M, ld, m, w.tiny, w.counter, rel_tol);
+  // start arrays for the six step shapes
+  auto wgs = [&](int step, const EigDev& a) -> unsigned {
+    long mm = (long)a.m * a.m;
+    switch (step) {
+      case 0: return (unsigned)std::min<long>(64, std::max<long>(1, (mm + 255) / 256));
+      case 1: return (unsigned)a.np;
+      case 2:
+      case 3: return (unsigned)(a.np * ((a.m + 63) / 64));
+      case 4: return 1u;
+      default: return (unsigned)((mm + 255) / 256);
+    }
+  };
+  const unsigned* sd[6];
+  unsigned tot[6];
+  std::vector<unsigned> starts;
+  for (int step = 0; step < 6; ++step) {
+    unsigned t = 0;
+    for (int j = 0; j < nj; ++j) {
+      starts.push_back(t);
+      t += wgs(step, ed[j]);
+    }
+    starts.push_back(t);
+    tot[step] = t;
+  }
+  size_t jb = sizeof(EigDev) * nj;
+  std::vector<uint8_t> buf(jb + sizeof(unsigned) * starts.size());
+  std::memcpy(buf.data(), ed.data(), jb);
+  std::memcpy(buf.data() + jb, starts.data(), sizeof(unsigned) * starts.size());
+  uint8_t* dev = (uint8_t*)stage.upload(buf.data(), buf.size(), st);
+  const EigDev* dj = (const EigDev*)dev;
+  for (int step = 0; step < 6; ++step) sd[step] = (const unsigned*)(dev + jb) + step * (nj + 1);
+  auto run = [&](int step, int round) {
+    if (tot[step]) hipLaunchKernelGGL(bj_grouped, dim3(tot[step]), dim3(256), 0, st, dj, sd[step], nj, step, round);
+  };
+  run(0, 0);
   int sweeps = 0;
-  const int rounds = nbe > 1 ? nbe - 1 : 1;
   for (int sweep = 0; sweep < 40; ++sweep) {
-    hipLaunchKernelGGL(bj_zero_kernel, dim3(1), dim3(1), 0, st, w.counter);
-    for (int round = 0; round < rounds; ++round) {
-      hipLaunchKernelGGL(bj_pair_kernel, dim3(np), dim3(256), 0, st, M, ld, m, nbe, round, w.Q, w.flags, w.counter,
-                         w.tiny);
-      hipLaunchKernelGGL(bj_row_kernel, dim3(np, (m + 63) / 64), dim3(256), 0, st, M, ld, m, nbe, round, w.Q,
-                         w.flags);
-      hipLaunchKernelGGL(bj_col_kernel, dim3(np, (m + 63) / 64), dim3(256), 0, st, M, ld, w.Vt, m, m, nbe, round,
-                         w.Q, w.flags);
+    ZeroIntArgs z{dev_counter, 1};
+    hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(256), 0, st, z);
+    for (int round = 0; round < maxr; ++round) {
+      run(1, round);
+      run(2, round);
+      run(3, round);
     }
     ++sweeps;
-    hipMemcpyAsync(hostbuf, w.counter, sizeof(int), hipMemcpyDeviceToHost, st);
+    hipMemcpyAsync(host_counter, dev_counter, sizeof(int), hipMemcpyDeviceToHost, st);
     hipStreamSynchronize(st);
-    if (*hostbuf == 0) break;
+    if (*host_counter == 0) break;
   }
-  hipLaunchKernelGGL(bj_rank_kernel, dim3(1), dim3(1024), 0, st, M, ld, m, lam, w.rank);
-  hipLaunchKernelGGL(bj_gather_kernel, dim3((mm + 255) / 256), dim3(256), 0, st, w.Vt, m, w.rank, V, ldv);
+  run(4, 0);
+  run(5, 0);
   return sweeps;
+}
+
+bool launch_grouped_gemm(int, const void*, const unsigned*, int, unsigned, hipStream_t);
+bool launch_grouped_stencil(int, const void*, const unsigned*, int, unsigned, hipStream_t);
+bool launch_grouped_block(int, const void*, const unsigned*, int, unsigned, hipStream_t);
+bool launch_grouped_prep(int, const void*, const unsigned*, int, unsigned, hipStream_t);
+
+bool launch_grouped(int kind, const void* jobs, const unsigned* start, int nj, unsigned total, hipStream_t st) {
+  if (total == 0) return true;
+  return launch_grouped_gemm(kind, jobs, start, nj, total, st) ||
+         launch_grouped_stencil(kind, jobs, start, nj, total, st) ||
+         launch_grouped_block(kind, jobs, start, nj, total, st) ||
+         launch_grouped_dense(kind, jobs, start, nj, total, st) || launch_grouped_prep(kind, jobs, start, nj, total, st);
 }
 
 }  // namespace ppcg

@@ -55,15 +55,12 @@ template <> struct VecLoad<float, 4> {
 // reduction index k = g maps to physical row r0 + g*Q + e in step e: every
 // lane issues one contiguous vector load per column and step.
 // ---------------------------------------------------------------------------
-// SITE only distinguishes call sites in profiles (projection Grams = 1,
-// per-block Grams = 2, others = 0); the code is identical.
-template <class T, int TM, int TN, int SITE>
-__global__ __launch_bounds__(64) void gram_kernel(GramArgs a) {
+template <class T, int TM, int TN>
+PPCG_DEV void gram_body(const GramArgs& a, unsigned wg, unsigned nwg) {
   constexpr int Q = 4;
   typedef typename AccT<T>::type acc_t;
   const int l = threadIdx.x;
-  unsigned total = gridDim.x;
-  unsigned L = xcd_remap(blockIdx.x, total);
+  unsigned L = xcd_remap(wg, nwg);
   // logical index: tiles fastest, then split, then job
   const int ntile = a.tiles_i * a.tiles_j;
   int tile = L % ntile;
@@ -156,10 +153,22 @@ __global__ __launch_bounds__(64) void gram_kernel(GramArgs a) {
       }
 }
 
+// SITE only distinguishes call sites in profiles (projection Grams = 1,
+// per-block Grams = 2, others = 0); the code is identical.
+template <class T, int TM, int TN, int SITE>
+__global__ __launch_bounds__(64) void gram_kernel(GramArgs a) {
+  gram_body<T, TM, TN>(a, blockIdx.x, gridDim.x);
+}
+template <class T, int TM, int TN, int SITE>
+__global__ __launch_bounds__(64) void gram_grouped(const GramArgs* jobs, const unsigned* start, int nj) {
+  int j = find_job(start, nj, blockIdx.x);
+  gram_body<T, TM, TN>(jobs[j], blockIdx.x - start[j], start[j + 1] - start[j]);
+}
+
 // Sum of split partials in a fixed order.  dst[i + j*ldd] (+)= sum_s part[s].
 template <class T>
-__global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs r) {
-  long e = blockIdx.x * 256L + threadIdx.x;
+PPCG_DEV void reduce_body(const ReduceArgs& r, unsigned wg, unsigned) {
+  long e = wg * 256L + threadIdx.x;
   long per = (long)r.M * r.N;
   if (e >= per * r.njobs) return;
   int job = e / per;
@@ -176,6 +185,15 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs r) {
   // upper_only: the result is Hermitian by construction; mirror it
   if (r.upper_only && i < j) dbase[j + (long)i * r.ldd] = v;
 }
+template <class T>
+__global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs r) {
+  reduce_body<T>(r, blockIdx.x, gridDim.x);
+}
+template <class T>
+__global__ __launch_bounds__(256) void reduce_grouped(const ReduceArgs* jobs, const unsigned* start, int nj) {
+  int j = find_job(start, nj, blockIdx.x);
+  reduce_body<T>(jobs[j], blockIdx.x - start[j], start[j + 1] - start[j]);
+}
 
 // ---------------------------------------------------------------------------
 // update: C[r, j] = beta * (D C)[r, j] + alpha * sum_k A[r, k] B[k, j]
@@ -183,12 +201,12 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs r) {
 // 16 consecutive rows of a column per lane group.  Lane group g reads
 // Q consecutive k of the small matrix B in one vector load.
 // ---------------------------------------------------------------------------
-template <class T, int TJ, int TR, int SITE>
-__global__ __launch_bounds__(64) void update_kernel(UpdateArgs a) {
+template <class T, int TJ, int TR>
+PPCG_DEV void update_body(const UpdateArgs& a, unsigned wg, unsigned nwg) {
   constexpr int Q = 4;
   typedef typename AccT<T>::type acc_t;
   const int l = threadIdx.x, lc = l & 15, g = l >> 4;
-  unsigned L = xcd_remap(blockIdx.x, gridDim.x);
+  unsigned L = xcd_remap(wg, nwg);
   // column tiles fastest so the row tile of A is shared inside one XCD
   int tj = L % a.tiles_j;
   int rest = L / a.tiles_j;
@@ -268,48 +286,111 @@ __global__ __launch_bounds__(64) void update_kernel(UpdateArgs a) {
     }
 }
 
+template <class T, int TJ, int TR, int SITE>
+__global__ __launch_bounds__(64) void update_kernel(UpdateArgs a) {
+  update_body<T, TJ, TR>(a, blockIdx.x, gridDim.x);
+}
+template <class T, int TJ, int TR, int SITE>
+__global__ __launch_bounds__(64) void update_grouped(const UpdateArgs* jobs, const unsigned* start, int nj) {
+  int j = find_job(start, nj, blockIdx.x);
+  update_body<T, TJ, TR>(jobs[j], blockIdx.x - start[j], start[j + 1] - start[j]);
+}
+
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
-template <class T>
-void launch_gram_t(const GramArgs& a0, int njobs, hipStream_t st) {
-  GramArgs a = a0;
-  constexpr int TM = 4, TN = 4;
-  a.tiles_i = (a.M + 16 * TM - 1) / (16 * TM);
-  a.tiles_j = (a.N + 16 * TN - 1) / (16 * TN);
-  long blocks = (long)a.tiles_i * a.tiles_j * a.splits * njobs;
-  if (a.site == 1) hipLaunchKernelGGL((gram_kernel<T, TM, TN, 1>), dim3(blocks), dim3(64), 0, st, a);
-  else if (a.site == 2) hipLaunchKernelGGL((gram_kernel<T, TM, TN, 2>), dim3(blocks), dim3(64), 0, st, a);
-  else hipLaunchKernelGGL((gram_kernel<T, TM, TN, 0>), dim3(blocks), dim3(64), 0, st, a);
+constexpr int GTM = 4, GTN = 4, UTJ = 4, UTR = 4;
+
+void gram_tiles(GramArgs& a) {
+  a.tiles_i = (a.M + 16 * GTM - 1) / (16 * GTM);
+  a.tiles_j = (a.N + 16 * GTN - 1) / (16 * GTN);
+}
+void update_tiles(UpdateArgs& a) {
+  a.tiles_j = (a.N + 16 * UTJ - 1) / (16 * UTJ);
+  a.tiles_r = (int)(a.rows / (16 * UTR));
 }
 
-void launch_gram(const GramArgs& a, int njobs, bool f32acc, hipStream_t st) {
-  if (f32acc) launch_gram_t<float>(a, njobs, st);
-  else launch_gram_t<double>(a, njobs, st);
+void launch_gram(const GramArgs& a0, bool f32acc, hipStream_t st) {
+  GramArgs a = a0;
+  gram_tiles(a);
+  unsigned blocks = (unsigned)((long)a.tiles_i * a.tiles_j * a.splits * a.njobs);
+  if (blocks == 0) return;
+  int kind = (f32acc ? OP_GRAM_F0 : OP_GRAM_D0) + (a.site == 1 ? 1 : a.site == 2 ? 2 : 0);
+  if (g_rec) {
+    g_rec->add(kind, &a, sizeof(a), blocks);
+    return;
+  }
+#define PPCG_GRAM(T, S) hipLaunchKernelGGL((gram_kernel<T, GTM, GTN, S>), dim3(blocks), dim3(64), 0, st, a)
+  switch (kind) {
+    case OP_GRAM_D0: PPCG_GRAM(double, 0); break;
+    case OP_GRAM_D1: PPCG_GRAM(double, 1); break;
+    case OP_GRAM_D2: PPCG_GRAM(double, 2); break;
+    case OP_GRAM_F0: PPCG_GRAM(float, 0); break;
+    case OP_GRAM_F1: PPCG_GRAM(float, 1); break;
+    case OP_GRAM_F2: PPCG_GRAM(float, 2); break;
+  }
+#undef PPCG_GRAM
 }
 
 void launch_reduce(const ReduceArgs& r, bool f32, hipStream_t st) {
   long tot = (long)r.M * r.N * r.njobs;
-  long blocks = (tot + 255) / 256;
+  unsigned blocks = (unsigned)((tot + 255) / 256);
   if (blocks == 0) return;
+  if (g_rec) {
+    g_rec->add(f32 ? OP_REDUCE_F : OP_REDUCE_D, &r, sizeof(r), blocks);
+    return;
+  }
   if (f32) hipLaunchKernelGGL(reduce_kernel<float>, dim3(blocks), dim3(256), 0, st, r);
   else hipLaunchKernelGGL(reduce_kernel<double>, dim3(blocks), dim3(256), 0, st, r);
 }
 
-void launch_update(const UpdateArgs& a0, int njobs, bool f32, hipStream_t st) {
+void launch_update(const UpdateArgs& a0, bool f32, hipStream_t st) {
   UpdateArgs a = a0;
-  constexpr int TJ = 4, TR = 4;
-  a.tiles_j = (a.N + 16 * TJ - 1) / (16 * TJ);
-  a.tiles_r = (int)(a.rows / (16 * TR));
-  long blocks = (long)a.tiles_j * a.tiles_r * njobs;
+  update_tiles(a);
+  unsigned blocks = (unsigned)((long)a.tiles_j * a.tiles_r);
   if (blocks == 0) return;
-  if (f32) {
-    if (a.site == 1) hipLaunchKernelGGL((update_kernel<float, TJ, TR, 1>), dim3(blocks), dim3(64), 0, st, a);
-    else hipLaunchKernelGGL((update_kernel<float, TJ, TR, 0>), dim3(blocks), dim3(64), 0, st, a);
-  } else {
-    if (a.site == 1) hipLaunchKernelGGL((update_kernel<double, TJ, TR, 1>), dim3(blocks), dim3(64), 0, st, a);
-    else hipLaunchKernelGGL((update_kernel<double, TJ, TR, 0>), dim3(blocks), dim3(64), 0, st, a);
+  int kind = (f32 ? OP_UPDATE_F0 : OP_UPDATE_D0) + (a.site == 1 ? 1 : 0);
+  if (g_rec) {
+    g_rec->add(kind, &a, sizeof(a), blocks);
+    return;
   }
+#define PPCG_UPD(T, S) hipLaunchKernelGGL((update_kernel<T, UTJ, UTR, S>), dim3(blocks), dim3(64), 0, st, a)
+  switch (kind) {
+    case OP_UPDATE_D0: PPCG_UPD(double, 0); break;
+    case OP_UPDATE_D1: PPCG_UPD(double, 1); break;
+    case OP_UPDATE_F0: PPCG_UPD(float, 0); break;
+    case OP_UPDATE_F1: PPCG_UPD(float, 1); break;
+  }
+#undef PPCG_UPD
+}
+
+bool launch_grouped_gemm(int kind, const void* jobs, const unsigned* start, int nj, unsigned total, hipStream_t st) {
+#define PPCG_GG(T, S) \
+  hipLaunchKernelGGL((gram_grouped<T, GTM, GTN, S>), dim3(total), dim3(64), 0, st, (const GramArgs*)jobs, start, nj)
+#define PPCG_GU(T, S)                                                                                   \
+  hipLaunchKernelGGL((update_grouped<T, UTJ, UTR, S>), dim3(total), dim3(64), 0, st, (const UpdateArgs*)jobs, \
+                     start, nj)
+  switch (kind) {
+    case OP_GRAM_D0: PPCG_GG(double, 0); return true;
+    case OP_GRAM_D1: PPCG_GG(double, 1); return true;
+    case OP_GRAM_D2: PPCG_GG(double, 2); return true;
+    case OP_GRAM_F0: PPCG_GG(float, 0); return true;
+    case OP_GRAM_F1: PPCG_GG(float, 1); return true;
+    case OP_GRAM_F2: PPCG_GG(float, 2); return true;
+    case OP_UPDATE_D0: PPCG_GU(double, 0); return true;
+    case OP_UPDATE_D1: PPCG_GU(double, 1); return true;
+    case OP_UPDATE_F0: PPCG_GU(float, 0); return true;
+    case OP_UPDATE_F1: PPCG_GU(float, 1); return true;
+    case OP_REDUCE_D:
+      hipLaunchKernelGGL(reduce_grouped<double>, dim3(total), dim3(256), 0, st, (const ReduceArgs*)jobs, start, nj);
+      return true;
+    case OP_REDUCE_F:
+      hipLaunchKernelGGL(reduce_grouped<float>, dim3(total), dim3(256), 0, st, (const ReduceArgs*)jobs, start, nj);
+      return true;
+  }
+#undef PPCG_GG
+#undef PPCG_GU
+  return false;
 }
 
 }  // namespace ppcg

@@ -1,6 +1,18 @@
-// Kernel argument structs and host-side launchers (internal to libppcg).
+// Kernel argument structs, host-side launchers and the launch recorder
+// (internal to libppcg).
+//
+// Every launcher either launches its kernel directly (one job, arguments by
+// value) or, while a Recorder is active, appends (op kind, arguments,
+// workgroup count) to the recorder.  The batched driver records the same
+// stage for many problems and then issues one grouped launch per
+// (position, op kind): the grouped kernel finds its job from a device job
+// array by workgroup prefix sums.
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <vector>
 
 namespace ppcg {
 
@@ -30,6 +42,7 @@ struct GramArgs {
   int tiles_i, tiles_j;
   int upper_only;
   long job_col_off;   // per-job element offset added to all column pointers
+  int njobs;          // strided jobs (blocks) inside this gram
   int site;           // call site (selects a distinct kernel symbol for profiling)
 };
 
@@ -65,11 +78,6 @@ struct UpdateArgs {
   int site;        // call site (selects a distinct kernel symbol for profiling)
 };
 
-void launch_gram(const GramArgs& a, int njobs, bool f32acc, hipStream_t st);
-void launch_reduce(const ReduceArgs& r, bool f32, hipStream_t st);
-void launch_update(const UpdateArgs& a, int njobs, bool f32, hipStream_t st);
-
-// -------------------------------------------------------------------------
 // stencil: Y = H X on an N^3 periodic grid (7- or 13-point), columns [0, ncols)
 struct StencilArgs {
   const void* X;
@@ -84,22 +92,10 @@ struct StencilArgs {
   int f32;
   const double* shift;  // optional per-column shift: Y[:, j] -= shift[j] X[:, j] (float64 only)
 };
-void launch_stencil(const StencilArgs& a, hipStream_t st);
 
-// Y[r, j] = X[r, j] * d[r]  (d may be null: copy), optional float copy
-void launch_scale_rows(const double* d, const void* X, void* Y, long ld, long rows, int ncols, int f32, hipStream_t st);
-// Y32 = (float) X64, ncols columns
-void launch_to_f32(const double* X, float* Y, long ld, long rows, int ncols, hipStream_t st);
-// out[c] = sum_r |X[r, c]|^2 (X f64 or f32), deterministic
-void launch_colnorm2(const void* X, int f32, long ld, long rows, int ncols, double* out, hipStream_t st);
-// W[r, j] = AX[r, j] - X[r, j] * lam[j]; also out[j] = |W[:, j]|^2
-void launch_ritz_resid(const double* AX, const double* X, const double* lam, double* W, float* W32, long ld,
-                       long rows, int ncols, hipStream_t st);
-
-// -------------------------------------------------------------------------
 // block pencils (steps 12-13): one workgroup per sub-block
 struct PencilArgs {
-  const double* gram;   // per block: S^H [S | AW | AP], nS x (2 nS - q), ld = nS, stride gstride
+  const double* gram;   // per block: Gram rows x (2 nS - q), ld = rows, stride gstride
   long gstride;
   const double* G;      // X^H A X of the active columns (m x m, ldg); the X block is G[jq.., jq..]
   int ldg;
@@ -111,8 +107,8 @@ struct PencilArgs {
   int* flags;           // out: per block bit0 = P used, bit1 = backtracked, bit2 = rank failure
   double drop_tol, pivot_tol;
   double jacobi_rel;    // rotations below jacobi_rel |M|_F are skipped
+  int nblocks;
 };
-void launch_block_pencil(const PencilArgs& a, int nblocks, hipStream_t st);
 
 // block update (steps 14-15): P_j <- W_j C_W + P_j C_P ; X_j <- X_j C_X + P_j
 struct BlockUpdArgs {
@@ -125,26 +121,129 @@ struct BlockUpdArgs {
   int q;
   const double* C;  // per block (3q x q, ld 3q), stride cstride
   long cstride;
+  int nblocks;
 };
-void launch_block_update(const BlockUpdArgs& a, int nblocks, hipStream_t st);
 
-// -------------------------------------------------------------------------
+// small per-problem kernels
+struct ColnormArgs { const void* X; int f32; long ld, rows; int ncols; double* out; };
+struct RitzArgs { const double* AX; const double* X; const double* lam; double* W; float* W32; long ld, rows; int ncols; };
+struct TransposeArgs { const double* src; int lds; double* dst; int ldd; int m, n; };
+struct FillArgs { double* p; long count; double v; };
+struct SetDiagArgs { double* G; int ld, m; const double* lam; };
+struct SymmArgs { double* G; int ld, m; };
+struct Frob2Args { const double* G; int ld, nw; double* out; };
+struct OrthArgs { const double* G; int ld, k; double* out; };
+struct ZeroIntArgs { int* p; int n; };
+struct CopyArgs { const double* src; double* dst; long count; };
+struct PrepArgs { const double* V; long n; double c0; double* td; float* V32; double* dmin_part; int nparts; int* nan_flag; };
+// Cholesky G = L L^H (lower) of an m x m block with L, L^{-1}; composite op
+struct CholArgs { double* G; double* L; double* Li; int m, ld; int* flag; };
+// device-to-host copy (executed in order at its position, not grouped)
+struct D2HArgs { void* dst; const void* src; size_t bytes; };
+
+enum OpKind : int {
+  OP_GRAM_D0, OP_GRAM_D1, OP_GRAM_D2, OP_GRAM_F0, OP_GRAM_F1, OP_GRAM_F2,
+  OP_REDUCE_D, OP_REDUCE_F,
+  OP_UPDATE_D0, OP_UPDATE_D1, OP_UPDATE_F0, OP_UPDATE_F1,
+  OP_STENCIL_D2, OP_STENCIL_D4, OP_STENCIL_F2, OP_STENCIL_F4,
+  OP_COLNORM_D, OP_COLNORM_F, OP_RITZ,
+  OP_PENCIL24, OP_PENCIL48,
+  OP_BUPD_D4, OP_BUPD_D8, OP_BUPD_D16, OP_BUPD_D32, OP_BUPD_F4, OP_BUPD_F8, OP_BUPD_F16, OP_BUPD_F32,
+  OP_TRANSPOSE, OP_FILL, OP_SETDIAG, OP_SYMM, OP_FROB2, OP_ORTH, OP_ZEROINT, OP_COPY, OP_PREP,
+  OP_CHOL,   // composite: expanded by the grouped executor
+  OP_D2H,    // host copy
+  OP_COUNT
+};
+
+struct RecOp {
+  int kind;
+  unsigned nwg;
+  std::vector<uint8_t> args;
+};
+
+struct Recorder {
+  std::vector<std::vector<RecOp>> lists;  // one op list per problem
+  int cur = -1;
+  void begin(int nprob) {
+    lists.assign(nprob, {});
+    cur = -1;
+  }
+  void add(int kind, const void* a, size_t sz, unsigned nwg) {
+    RecOp op;
+    op.kind = kind;
+    op.nwg = nwg;
+    op.args.resize(sz);
+    std::memcpy(op.args.data(), a, sz);
+    lists[cur].push_back(std::move(op));
+  }
+};
+extern Recorder* g_rec;  // non-null while the batched driver records
+
+// Pinned host staging + device mirror for job arrays.  Bump allocation; the
+// owner calls reset() only after synchronising the stream, so a region is
+// never rewritten while its host-to-device copy may be pending.  Chunks that
+// overflow are kept until reset.
+struct Stage {
+  struct Chunk { uint8_t* h; uint8_t* d; size_t cap, used; };
+  std::vector<Chunk> chunks;
+  std::vector<Chunk> retired;
+  ~Stage();
+  // copies `bytes` from src into the staging area and enqueues the upload;
+  // returns the device address
+  void* upload(const void* src, size_t bytes, hipStream_t st);
+  void reset();
+};
+
+// Grouped launch of `nj` jobs of op `kind` (device job array, device start
+// array of nj+1 prefix sums, `total` workgroups).  Returns false for kinds
+// that cannot be grouped.
+bool launch_grouped(int kind, const void* jobs, const unsigned* start, int nj, unsigned total, hipStream_t st);
+size_t op_args_size(int kind);
+
+void launch_gram(const GramArgs& a, bool f32acc, hipStream_t st);
+void launch_reduce(const ReduceArgs& r, bool f32, hipStream_t st);
+void launch_update(const UpdateArgs& a, bool f32, hipStream_t st);
+void gram_tiles(GramArgs& a);
+void update_tiles(UpdateArgs& a);
+void launch_stencil(const StencilArgs& a, hipStream_t st);
+
+// Y[r, j] = X[r, j] * d[r]  (d may be null: copy)
+void launch_scale_rows(const double* d, const void* X, void* Y, long ld, long rows, int ncols, int f32, hipStream_t st);
+// out[c] = sum_r |X[r, c]|^2 (X f64 or f32), deterministic
+void launch_colnorm2(const void* X, int f32, long ld, long rows, int ncols, double* out, hipStream_t st);
+// W[r, j] = AX[r, j] - X[r, j] * lam[j] (W and/or its float copy W32)
+void launch_ritz_resid(const double* AX, const double* X, const double* lam, double* W, float* W32, long ld,
+                       long rows, int ncols, hipStream_t st);
+
+void launch_block_pencil(const PencilArgs& a, hipStream_t st);
+void launch_block_update(const BlockUpdArgs& a, hipStream_t st);
+
 // dense m x m (column-major, ld) kernels
 // Cholesky G = L L^H (lower), L and Linv written to separate buffers; flag
 // set to 1 + (first failing diagonal block) on a non-positive pivot.
-void chol_inverse(double* G, double* L, double* Linv, int m, int ld, int* flag, hipStream_t st);
-// Upper triangle of dst = src^H (used to form R^{-1} = Linv^H)
+void chol_inverse_grouped(const std::vector<CholArgs>& jobs, Stage& stage, hipStream_t st);
 void launch_transpose(const double* src, int lds, double* dst, int ldd, int m, int n, hipStream_t st);
 void launch_fill(double* p, long count, double v, hipStream_t st);
 void launch_set_diag(double* G, int ld, int m, const double* lam, hipStream_t st);
 void launch_symmetrize(double* G, int ld, int m, hipStream_t st);
+// out[j] = sum_{i<nw} G[i, j]^2, j < nw
+void launch_frob2_sub(const double* G, int ld, int nw, double* out, hipStream_t st);
+// out = |G[:k, :k] - I|_F^2
+void launch_orth_err2(const double* G, int ld, int k, double* out, hipStream_t st);
+void launch_copy(const double* src, double* dst, long count, hipStream_t st);
+void launch_d2h(void* dst, const void* src, size_t bytes, hipStream_t st);
 
 // Hermitian eigensolver for m x m (ld) by block Jacobi; eigenvalues
 // ascending in lam, eigenvectors in V (m x m, ldv).  Work buffers owned by
 // the caller (size from eig_workspace_bytes).  Returns sweeps used.
 size_t eig_workspace_bytes(int m);
-int block_jacobi_eig(double* M, int ld, int m, double* V, int ldv, double* lam, void* work, int* hostbuf,
-                     double rel_tol, hipStream_t st);
+struct EigJob { double* M; int ld, m; double* V; int ldv; double* lam; void* work; double rel_tol; };
+// All problems in lockstep (one workgroup set per problem and launch);
+// dev_counter / host_counter: one int of device / pinned host memory for the
+// rotation count of a sweep.  Synchronises the stream once per sweep.
+// Returns the sweeps used.
+int block_jacobi_eig_grouped(const std::vector<EigJob>& jobs, Stage& stage, int* dev_counter, int* host_counter,
+                             hipStream_t st);
 
 // backward pass (grad.hip)
 void launch_coldot(const double* A, const double* B, long ld, long rows, int ncols, double* out, hipStream_t st);
@@ -159,9 +258,8 @@ void launch_cg_check(const double* rr, const double* bb, double tol, int* done, 
 void launch_grad_rows(const double* X, const double* Z, const double* g, long ld, long n, int k, double* out,
                       hipStream_t st);
 
-// rho and helpers: out[j] = sum_{i<nw} G[i, j]^2, j < nw
-void launch_frob2_sub(const double* G, int ld, int nw, double* out, hipStream_t st);
-// out = |G[:k, :k] - I|_F^2
-void launch_orth_err2(const double* G, int ld, int k, double* out, hipStream_t st);
+void launch_prep_diag(const double* V, long n, double c0, double* td, float* V32, double* dmin_part, int nparts,
+                      int* nan_flag, hipStream_t st);
+void launch_zero_int(int* p, int n, hipStream_t st);
 
 }  // namespace ppcg

@@ -1,43 +1,76 @@
-// Set-up kernels: Jacobi preconditioner T = diag(H)^{-1} (the paper only
+// Set-up kernel: Jacobi preconditioner T = diag(H)^{-1} (the paper only
 // requires T Hermitian positive definite, Theorem 2), float copy of V, and
 // the scan for NaN / non-positive diagonal.
 #include "common.hpp"
 #include "kernels.hpp"
-#include "prep.hpp"
 
 namespace ppcg {
 
-__global__ __launch_bounds__(256) void prep_diag_kernel(const double* V, long n, double c0, double* td, float* V32,
-                                                        double* dmin_part, int* nan_flag) {
+PPCG_DEV void prep_body(const PrepArgs& a, unsigned wg, unsigned nwg) {
   double mn = 1e308;
   int bad = 0;
-  for (long r = blockIdx.x * 256L + threadIdx.x; r < n; r += (long)gridDim.x * 256) {
-    double v = V[r];
-    double d = c0 + v;
+  for (long r = wg * 256L + threadIdx.x; r < a.n; r += (long)nwg * 256) {
+    double v = a.V[r];
+    double d = a.c0 + v;
     if (v != v) bad = 1;
     mn = fmin(mn, d);
-    td[r] = 1.0 / d;
-    if (V32) V32[r] = (float)v;
+    a.td[r] = 1.0 / d;
+    if (a.V32) a.V32[r] = (float)v;
   }
   for (int o = 32; o > 0; o >>= 1) mn = fmin(mn, __shfl_xor(mn, o, 64));
   __shared__ double red[4];
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mn;
-  if (bad) atomicOr(nan_flag, 1);
+  if (bad) atomicOr(a.nan_flag, 1);
   __syncthreads();
-  if (threadIdx.x == 0) dmin_part[blockIdx.x] = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
+  if (threadIdx.x == 0) a.dmin_part[wg] = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
+}
+__global__ __launch_bounds__(256) void prep_kernel(PrepArgs a) { prep_body(a, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(256) void prep_grouped(const PrepArgs* jobs, const unsigned* start, int nj) {
+  int j = find_job(start, nj, blockIdx.x);
+  prep_body(jobs[j], blockIdx.x - start[j], start[j + 1] - start[j]);
 }
 
 void launch_prep_diag(const double* V, long n, double c0, double* td, float* V32, double* dmin_part, int nparts,
                       int* nan_flag, hipStream_t st) {
-  hipLaunchKernelGGL(prep_diag_kernel, dim3(nparts), dim3(256), 0, st, V, n, c0, td, V32, dmin_part, nan_flag);
+  PrepArgs a{V, n, c0, td, V32, dmin_part, nparts, nan_flag};
+  if (g_rec) {
+    g_rec->add(OP_PREP, &a, sizeof(a), (unsigned)nparts);
+    return;
+  }
+  hipLaunchKernelGGL(prep_kernel, dim3(nparts), dim3(256), 0, st, a);
 }
 
-__global__ void zero_int_kernel(int* p, int n) {
-  int e = blockIdx.x * 256 + threadIdx.x;
-  if (e < n) p[e] = 0;
+bool launch_grouped_prep(int kind, const void* jobs, const unsigned* start, int nj, unsigned total, hipStream_t st) {
+  if (kind != OP_PREP) return false;
+  hipLaunchKernelGGL(prep_grouped, dim3(total), dim3(256), 0, st, (const PrepArgs*)jobs, start, nj);
+  return true;
 }
-void launch_zero_int(int* p, int n, hipStream_t st) {
-  if (n > 0) hipLaunchKernelGGL(zero_int_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, n);
+
+size_t op_args_size(int kind) {
+  switch (kind) {
+    case OP_GRAM_D0: case OP_GRAM_D1: case OP_GRAM_D2: case OP_GRAM_F0: case OP_GRAM_F1: case OP_GRAM_F2:
+      return sizeof(GramArgs);
+    case OP_REDUCE_D: case OP_REDUCE_F: return sizeof(ReduceArgs);
+    case OP_UPDATE_D0: case OP_UPDATE_D1: case OP_UPDATE_F0: case OP_UPDATE_F1: return sizeof(UpdateArgs);
+    case OP_STENCIL_D2: case OP_STENCIL_D4: case OP_STENCIL_F2: case OP_STENCIL_F4: return sizeof(StencilArgs);
+    case OP_COLNORM_D: case OP_COLNORM_F: return sizeof(ColnormArgs);
+    case OP_RITZ: return sizeof(RitzArgs);
+    case OP_PENCIL24: case OP_PENCIL48: return sizeof(PencilArgs);
+    case OP_BUPD_D4: case OP_BUPD_D8: case OP_BUPD_D16: case OP_BUPD_D32:
+    case OP_BUPD_F4: case OP_BUPD_F8: case OP_BUPD_F16: case OP_BUPD_F32: return sizeof(BlockUpdArgs);
+    case OP_TRANSPOSE: return sizeof(TransposeArgs);
+    case OP_FILL: return sizeof(FillArgs);
+    case OP_SETDIAG: return sizeof(SetDiagArgs);
+    case OP_SYMM: return sizeof(SymmArgs);
+    case OP_FROB2: return sizeof(Frob2Args);
+    case OP_ORTH: return sizeof(OrthArgs);
+    case OP_ZEROINT: return sizeof(ZeroIntArgs);
+    case OP_COPY: return sizeof(CopyArgs);
+    case OP_PREP: return sizeof(PrepArgs);
+    case OP_CHOL: return sizeof(CholArgs);
+    case OP_D2H: return sizeof(D2HArgs);
+  }
+  return 0;
 }
 
 }  // namespace ppcg

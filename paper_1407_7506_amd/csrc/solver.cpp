@@ -3,6 +3,12 @@
 // and the C ABI.  Every arithmetic step runs in the HIP kernels of this
 // library; the host only decides control flow from a few scalars copied
 // back per iteration.
+//
+// One problem (`Prob`) is a sequence of enqueue phases (no synchronisation
+// inside) and post-phase host logic.  The `Driver` advances a set of
+// problems in lockstep: a single solve launches every kernel directly; a
+// batched solve records each phase for all problems and replays it as one
+// grouped launch per kernel and position (see kernels.hpp).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -12,12 +18,12 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
 #include "kernels.hpp"
 #include "ppcg.h"
-#include "prep.hpp"
 
 using namespace ppcg;
 
@@ -28,9 +34,9 @@ struct PpcgError {
   std::string msg;
 };
 
-#define HIPCHECK(x)                                                                   \
-  do {                                                                                \
-    hipError_t e_ = (x);                                                              \
+#define HIPCHECK(x)                                                                                      \
+  do {                                                                                                   \
+    hipError_t e_ = (x);                                                                                 \
     if (e_ != hipSuccess) throw PpcgError{PPCG_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)}; \
   } while (0)
 
@@ -59,6 +65,7 @@ struct DBuf {
     p = nullptr;
     bytes = 0;
   }
+  ~DBuf() { release(); }
   double* d() const { return (double*)p; }
   float* f() const { return (float*)p; }
   int* i() const { return (int*)p; }
@@ -101,15 +108,17 @@ struct Prof {
     bytes.push_back(0);
     return k;
   }
+  // events are only recorded around real launches (not while recording a batch)
+  bool active() const { return on && g_rec == nullptr; }
   // fl / by: algorithmic flops and compulsory HBM bytes of the launch
   void begin(const char* n, double fl = 0, double by = 0) {
-    if (!on) return;
+    if (!active()) return;
     hipEvent_t e = get();
     HIPCHECK(hipEventRecord(e, st));
     open.push_back({id(n), e, fl, by});
   }
   void end() {
-    if (!on || open.empty()) return;
+    if (!active() || open.empty()) return;
     Open o = open.back();
     open.pop_back();
     hipEvent_t b = get();
@@ -146,39 +155,27 @@ struct Prof {
 
 struct Scope {
   Prof& p;
-  Scope(Prof& p_, const char* n, double fl = 0, double by = 0) : p(p_) { p.begin(n, fl, by); }
-  ~Scope() { p.end(); }
+  bool live;
+  Scope(Prof& p_, const char* n, double fl = 0, double by = 0) : p(p_), live(p_.active()) {
+    if (live) p.begin(n, fl, by);
+  }
+  ~Scope() {
+    if (live) p.end();
+  }
 };
 
-}  // namespace
-
-struct ppcg_handle {
-  hipStream_t st = nullptr;
-  int device = 0;
-  ppcg_options opt{};
-  std::string err;
-  Prof prof;
-  // workspace
+// per-problem workspace
+struct Work {
   DBuf X, Xt, W, P, AW, AP;           // float64 blocks (W..AP only in FP64 mode)
   DBuf X32, W32, P32, AW32, AP32;     // float32 blocks (mixed mode)
   DBuf AXm;                           // float64 H X kept in mixed mode
   DBuf Vd, V32, td;
   DBuf G, GWP, L, Li, Rinv, SAS, SS, V1, Mr, Yv, Cc, lam;
   DBuf part, bgram, bC, bflags, cn, scal, iflag, eigw, dminp;
-  DBuf gZ, gR, gP, gAP, gY, gw, gsc;  // backward-pass work
-  // state of the last successful solve (for ppcg_grad / ppcg_density)
-  bool has_state = false;
-  int s_N = 0, s_order = 0, s_k = 0;
-  long s_n = 0, s_rows = 0;
-  double s_c0 = 0, s_w1 = 0, s_w2 = 0, s_dmin = 0;
-  int* hpin = nullptr;                // pinned host scratch
+  int* hpin = nullptr;                // pinned host scratch: doubles [0, 2Kp), ints from 4Kp + 8
   double* hpind = nullptr;
   size_t hpin_bytes = 0;
-  ~ppcg_handle() {
-    for (DBuf* b : {&X, &Xt, &W, &P, &AW, &AP, &X32, &W32, &P32, &AW32, &AP32, &AXm, &Vd, &V32, &td, &G, &GWP, &L, &Li,
-                    &Rinv, &SAS, &SS, &V1, &Mr, &Yv, &Cc, &lam, &part, &bgram, &bC, &bflags, &cn, &scal, &iflag,
-                    &eigw, &dminp, &gZ, &gR, &gP, &gAP, &gY, &gw, &gsc})
-      b->release();
+  ~Work() {
     if (hpin) hipHostFree(hpin);
   }
   void pinned(size_t b) {
@@ -191,31 +188,74 @@ struct ppcg_handle {
   }
 };
 
+}  // namespace
+
+struct ppcg_handle {
+  hipStream_t st = nullptr;
+  int device = 0;
+  ppcg_options opt{};
+  std::string err;
+  Prof prof;
+  Stage stage;
+  std::vector<std::unique_ptr<Work>> works;
+  DBuf counter;                       // rotation counter of the grouped eigensolver
+  int* hcounter = nullptr;
+  DBuf gZ, gR, gP, gAP, gY, gw, gsc;  // backward-pass work
+  // state of the last successful single solve (for ppcg_grad / ppcg_density)
+  bool has_state = false;
+  int s_N = 0, s_order = 0, s_k = 0;
+  long s_n = 0, s_rows = 0;
+  double s_c0 = 0, s_w1 = 0, s_w2 = 0, s_dmin = 0;
+  ~ppcg_handle() {
+    if (hcounter) hipHostFree(hcounter);
+  }
+  Work& work(int i) {
+    while ((int)works.size() <= i) works.emplace_back(new Work());
+    return *works[i];
+  }
+};
+
 namespace {
 
+void sync(ppcg_handle* H) {
+  HIPCHECK(hipStreamSynchronize(H->st));
+  H->stage.reset();
+}
+
 // ---------------------------------------------------------------------------
-// one solve
+// one problem
 // ---------------------------------------------------------------------------
-struct Solve {
+struct Prob {
   ppcg_handle* H;
+  Work& Wk;
   hipStream_t st;
   Prof& prof;
   // problem
-  int N, order;
-  double hsp, c0, w1, w2;
-  long n, rows, ld;
-  int k, q, K, Kp;
-  double tol;
-  int rr_period, max_iter;
-  bool mixed;
-  double dmin = 0;
+  int N = 0, order = 2;
+  double hsp = 0, c0 = 0, w1 = 0, w2 = 0;
+  long n = 0, rows = 0, ld = 0;
+  int k = 0, q = 0, K = 0, Kp = 0;
+  double tol = 0;
+  int rr_period = 1, max_iter = 0;
+  bool mixed = false;
+  const double* V = nullptr;
+  const double* X0 = nullptr;
+  double* Xout = nullptr;
+  double* lamout = nullptr;
   // state
+  double dmin = 0;
   int nl = 0;        // locked columns (absolute prefix)
   bool hasP = false;
+  int it = 1;
+  bool noconv = false;
+  double fresh = INFINITY;
   std::vector<double> lock_wn, lock_lam;
   ppcg_info info{};
+  ppcg_status status = PPCG_OK;
+  std::string err;
+  std::chrono::steady_clock::time_point t0;
 
-  Solve(ppcg_handle* h) : H(h), st(h->st), prof(h->prof) {}
+  Prob(ppcg_handle* h, Work& w) : H(h), Wk(w), st(h->st), prof(h->prof) {}
 
   // Jacobi skip thresholds relative to |M|_F, tied to the requested tolerance:
   // the RR rotation error then stays ~1e-5 tol below the Ritz residuals that
@@ -223,21 +263,72 @@ struct Solve {
   double rr_rel_tol() const { return std::max(2.2e-16, std::min(1e-11, 1e-5 * tol)); }
   double pencil_rel_tol() const { return std::max(2.2e-16, std::min(1e-10, 1e-4 * tol)); }
 
-  double* X() { return H->X.d(); }
-  double* Xt() { return H->Xt.d(); }
-  void swapX() { std::swap(H->X, H->Xt); }
+  double* X() { return Wk.X.d(); }
+  double* Xt() { return Wk.Xt.d(); }
+  void swapX() {
+    std::swap(Wk.X.p, Wk.Xt.p);
+    std::swap(Wk.X.bytes, Wk.Xt.bytes);
+  }
 
   // W/P/AW/AP storage (f64 in plain mode, f32 in mixed mode)
-  void* Wb() { return mixed ? (void*)H->W32.p : H->W.p; }
-  void* Pb() { return mixed ? (void*)H->P32.p : H->P.p; }
-  void* AWb() { return mixed ? (void*)H->AW32.p : H->AW.p; }
-  void* APb() { return mixed ? (void*)H->AP32.p : H->AP.p; }
+  void* Wb() { return mixed ? (void*)Wk.W32.p : Wk.W.p; }
+  void* Pb() { return mixed ? (void*)Wk.P32.p : Wk.P.p; }
+  void* AWb() { return mixed ? (void*)Wk.AW32.p : Wk.AW.p; }
+  void* APb() { return mixed ? (void*)Wk.AP32.p : Wk.AP.p; }
   size_t esz() const { return mixed ? 4 : 8; }
   void* col(void* base, long c, size_t es) { return (char*)base + (size_t)c * ld * es; }
 
+  // ---- parameters -----------------------------------------------------------
+  void setup(const ppcg_operator* op, int k_, int q_, double tol_, int rrp, const double* X0_, double* Xout_,
+             double* lamout_) {
+    t0 = std::chrono::steady_clock::now();
+    if (!op || !op->V || !X0_ || !Xout_ || !lamout_) throw PpcgError{PPCG_EINVAL, "null pointer argument"};
+    if (op->kpt[0] != 0 || op->kpt[1] != 0 || op->kpt[2] != 0)
+      throw PpcgError{PPCG_EINVAL, "complex (Bloch) operators are not available in this build"};
+    if (op->order != 2 && op->order != 4) throw PpcgError{PPCG_EINVAL, "order must be 2 or 4"};
+    if (op->precond != PPCG_PRECOND_JACOBI) throw PpcgError{PPCG_EINVAL, "only the Jacobi preconditioner"};
+    if (op->nx < 4 || !(op->h > 0)) throw PpcgError{PPCG_EINVAL, "bad grid"};
+    N = op->nx;
+    order = op->order;
+    hsp = op->h;
+    double ih2 = 1.0 / (hsp * hsp);
+    if (order == 2) {
+      c0 = 3.0 * ih2;
+      w1 = -0.5 * ih2;
+      w2 = 0;
+    } else {
+      c0 = 3.0 * 1.25 * ih2;
+      w1 = -2.0 / 3.0 * ih2;
+      w2 = ih2 / 24.0;
+    }
+    n = (long)N * N * N;
+    rows = round_up(n, 256);
+    ld = rows;
+    k = k_;
+    q = q_;
+    tol = tol_;
+    rr_period = rrp;
+    mixed = H->opt.precision == PPCG_MIXED;
+    max_iter = H->opt.max_iter > 0 ? H->opt.max_iter : 20000;
+    if (k <= 0 || q < 1 || q > 16 || !(tol > 0) || rr_period < 1)
+      throw PpcgError{PPCG_EINVAL, "need k > 0, 1 <= sbsize <= 16, tol > 0, rr_period >= 1"};
+    int nbuf = H->opt.nbuf;
+    if (nbuf < 0) {
+      int extra = std::max(2, (int)std::ceil(0.02 * k));
+      nbuf = q * ((k + extra + q - 1) / q) - k;
+    }
+    K = k + nbuf;
+    if (K % q != 0) throw PpcgError{PPCG_EINVAL, "k + nbuf must be a multiple of sbsize"};
+    if ((long)K * 4 > n) throw PpcgError{PPCG_EINVAL, "k + nbuf must not exceed n/4"};
+    Kp = (int)round_up(K, 64);
+    V = op->V;
+    X0 = X0_;
+    Xout = Xout_;
+    lamout = lamout_;
+  }
+
   // ---- kernels --------------------------------------------------------------
   void stencil(const void* Xs, void* Ys, int ncols, bool f32) {
-    if (ncols <= 0) return;
     double es = f32 ? 4 : 8;
     Scope s(prof, f32 ? "stencil_f32" : "stencil_f64", (order == 4 ? 16.0 : 10.0) * n * ncols,
             2.0 * es * n * ncols + es * n);
@@ -251,7 +342,7 @@ struct Solve {
     a.c0 = c0;
     a.w1 = w1;
     a.w2 = w2;
-    a.V = f32 ? (const void*)H->V32.p : (const void*)H->Vd.p;
+    a.V = f32 ? (const void*)Wk.V32.p : (const void*)Wk.Vd.p;
     a.f32 = f32;
     launch_stencil(a, st);
   }
@@ -271,7 +362,7 @@ struct Solve {
     return 0;
   }
 
-  int pick_splits(long tiles, long njobs, long rws) {
+  static int pick_splits(long tiles, long njobs, long rws) {
     long target = 2048;
     long s = (target + tiles * njobs - 1) / (tiles * njobs);
     long maxs = std::max(1L, rws / 256);
@@ -287,8 +378,8 @@ struct Solve {
     int splits = pick_splits(tiles, njobs, rws);
     size_t es = f32acc ? 4 : 8;
     size_t one = (size_t)njobs * M * Nn * es;
-    if (one > H->part.bytes) throw PpcgError{PPCG_EINVAL, "internal: partial buffer too small"};
-    splits = (int)std::min<size_t>((size_t)splits, H->part.bytes / one);
+    if (one > Wk.part.bytes) throw PpcgError{PPCG_EINVAL, "internal: partial buffer too small"};
+    splits = (int)std::min<size_t>((size_t)splits, Wk.part.bytes / one);
     long chunk = round_up((rws + splits - 1) / splits, 16);
     splits = (int)((rws + chunk - 1) / chunk);
     GramArgs g{};
@@ -302,21 +393,22 @@ struct Solve {
     g.rows = rws;
     g.splits = splits;
     g.chunk = chunk;
-    g.out = H->part.p;
+    g.out = Wk.part.p;
     g.split_stride = (long)M * Nn;
     g.ldo = M;
     g.upper_only = upper;
     g.job_col_off = job_col_off;
+    g.njobs = njobs;
+    g.site = site_of(name);
     {
       double nn = (double)std::min(rws, n), es_in = f32acc ? 4.0 : 8.0;
       double fl = upper ? (double)M * (M + 1) * nn : 2.0 * M * Nn * nn;
       double by = (double)njobs * (upper ? M : (M + Nn)) * nn * es_in;
       Scope s(prof, name, fl * njobs, by);
-      g.site = site_of(name);
-      launch_gram(g, njobs, f32acc, st);
+      launch_gram(g, f32acc, st);
     }
     ReduceArgs r{};
-    r.part = H->part.p;
+    r.part = Wk.part.p;
     r.M = M;
     r.N = Nn;
     r.ldp = M;
@@ -356,50 +448,56 @@ struct Solve {
     u.beta = beta;
     u.b_upper = b_upper;
     u.c0_keep = c0_keep;
+    u.site = site_of(name);
     double nn = (double)std::min(rws, n), es = f32 ? 4.0 : 8.0;
     double fl = b_upper ? (double)Nn * (Nn + 1) * nn : 2.0 * Kk * Nn * nn;
     double by = ((double)Kk + Nn * (beta != 0 ? 2.0 : 1.0)) * nn * es + (C32 ? 4.0 * Nn * nn : 0.0);
     Scope s(prof, name, fl, by);
-    u.site = site_of(name);
-    launch_update(u, 1, f32, st);
+    launch_update(u, f32, st);
+  }
+
+  void chol(double* G, int m) {
+    CholArgs c{G, Wk.L.d(), Wk.Li.d(), m, Kp, Wk.iflag.i()};
+    Scope s(prof, "chol_inverse");
+    if (g_rec) g_rec->add(OP_CHOL, &c, sizeof(c), 0);
+    else chol_inverse_grouped({c}, H->stage, st);
   }
 
   // ---- set-up ---------------------------------------------------------------
   void allocate() {
     size_t nk8 = (size_t)rows * K * 8, nk4 = (size_t)rows * K * 4;
-    H->X.ensure(nk8);
-    H->Xt.ensure(nk8);
+    Wk.X.ensure(nk8);
+    Wk.Xt.ensure(nk8);
     if (mixed) {
-      H->AXm.ensure(nk8);
-      H->X32.ensure(nk4);
-      H->W32.ensure(nk4);
-      H->P32.ensure(nk4);
-      H->AW32.ensure(nk4);
-      H->AP32.ensure(nk4);
-      H->V32.ensure((size_t)rows * 4);
+      Wk.AXm.ensure(nk8);
+      Wk.X32.ensure(nk4);
+      Wk.W32.ensure(nk4);
+      Wk.P32.ensure(nk4);
+      Wk.AW32.ensure(nk4);
+      Wk.AP32.ensure(nk4);
+      Wk.V32.ensure((size_t)rows * 4);
     } else {
-      H->W.ensure(nk8);
-      H->P.ensure(nk8);
-      H->AW.ensure(nk8);
-      H->AP.ensure(nk8);
+      Wk.W.ensure(nk8);
+      Wk.P.ensure(nk8);
+      Wk.AW.ensure(nk8);
+      Wk.AP.ensure(nk8);
     }
-    H->Vd.ensure((size_t)rows * 8);
-    H->td.ensure((size_t)rows * 8);
+    Wk.Vd.ensure((size_t)rows * 8);
+    Wk.td.ensure((size_t)rows * 8);
     size_t kk = (size_t)Kp * Kp * 8;
-    for (DBuf* b : {&H->G, &H->L, &H->Li, &H->Rinv, &H->SAS, &H->SS, &H->V1, &H->Mr, &H->Yv, &H->Cc})
-      b->ensure(kk);
-    H->GWP.ensure((size_t)Kp * 2 * K * 8);
-    H->lam.ensure((size_t)Kp * 8);
-    H->cn.ensure((size_t)Kp * 8);
-    H->scal.ensure((size_t)Kp * 8 + 256);
-    H->iflag.ensure(256);
-    H->dminp.ensure(1024 * 8);
+    for (DBuf* b : {&Wk.G, &Wk.L, &Wk.Li, &Wk.Rinv, &Wk.SAS, &Wk.SS, &Wk.V1, &Wk.Mr, &Wk.Yv, &Wk.Cc}) b->ensure(kk);
+    Wk.GWP.ensure((size_t)Kp * 2 * K * 8);
+    Wk.lam.ensure((size_t)Kp * 8);
+    Wk.cn.ensure((size_t)Kp * 8);
+    Wk.scal.ensure((size_t)Kp * 8 + 256);
+    Wk.iflag.ensure(256);
+    Wk.dminp.ensure(1024 * 8);
     int s = K / q;
     int nS = 3 * q;
-    H->bgram.ensure((size_t)s * (nS + q) * (2 * nS - q) * 8);
-    H->bC.ensure((size_t)s * 3 * q * q * 8);
-    H->bflags.ensure((size_t)s * 4 + 256);
-    H->eigw.ensure(eig_workspace_bytes(K));
+    Wk.bgram.ensure((size_t)s * (nS + q) * (2 * nS - q) * 8);
+    Wk.bC.ensure((size_t)s * 3 * q * q * 8);
+    Wk.bflags.ensure((size_t)s * 4 + 256);
+    Wk.eigw.ensure(eig_workspace_bytes(K));
     // split partials: the largest Gram of the run
     size_t need = 0;
     auto acc = [&](long M, long Nn, long njobs, long rws, size_t es) {
@@ -413,93 +511,105 @@ struct Solve {
     acc(K, K, 1, rows, 8);
     acc(nS + q, 2 * nS - q, s, rows, 8);
     acc(K, K, 1, Kp, 8);
-    H->part.ensure(need);
-    H->pinned((size_t)(4 * Kp + 64) * 8);  // doubles [0, 2Kp), ints from 4Kp + 8
+    Wk.part.ensure(need);
+    Wk.pinned((size_t)(4 * Kp + 64) * 8);
     // zero everything that carries padding rows
-    std::vector<DBuf*> blocks = {&H->X, &H->Xt};
+    std::vector<DBuf*> blocks = {&Wk.X, &Wk.Xt};
     if (mixed) {
-      for (DBuf* b : {&H->X32, &H->W32, &H->P32, &H->AW32, &H->AP32, &H->AXm}) blocks.push_back(b);
+      for (DBuf* b : {&Wk.X32, &Wk.W32, &Wk.P32, &Wk.AW32, &Wk.AP32, &Wk.AXm}) blocks.push_back(b);
     } else {
-      for (DBuf* b : {&H->W, &H->P, &H->AW, &H->AP}) blocks.push_back(b);
+      for (DBuf* b : {&Wk.W, &Wk.P, &Wk.AW, &Wk.AP}) blocks.push_back(b);
     }
     for (DBuf* b : blocks) HIPCHECK(hipMemsetAsync(b->p, 0, b->bytes, st));
-    for (DBuf* b : {&H->Vd, &H->td, &H->G, &H->L, &H->Li, &H->Rinv, &H->SAS, &H->SS, &H->V1, &H->Mr, &H->Yv,
-                    &H->Cc, &H->GWP})
+    for (DBuf* b : {&Wk.Vd, &Wk.td, &Wk.G, &Wk.L, &Wk.Li, &Wk.Rinv, &Wk.SAS, &Wk.SS, &Wk.V1, &Wk.Mr, &Wk.Yv,
+                    &Wk.Cc, &Wk.GWP})
       HIPCHECK(hipMemsetAsync(b->p, 0, b->bytes, st));
-    if (mixed) HIPCHECK(hipMemsetAsync(H->V32.p, 0, H->V32.bytes, st));
+    if (mixed) HIPCHECK(hipMemsetAsync(Wk.V32.p, 0, Wk.V32.bytes, st));
+    HIPCHECK(hipMemcpyAsync(Wk.Vd.p, V, n * 8, hipMemcpyDeviceToDevice, st));
   }
 
-  void prep(const double* V) {
-    HIPCHECK(hipMemcpyAsync(H->Vd.p, V, n * 8, hipMemcpyDeviceToDevice, st));
-    int nparts = 256;
-    launch_zero_int(H->iflag.i(), 4, st);
-    launch_prep_diag(H->Vd.d(), n, c0, H->td.d(), mixed ? H->V32.f() : nullptr, H->dminp.d(), nparts, H->iflag.i(),
+  // phase: Jacobi preconditioner and checks of V
+  void enq_prep() {
+    const int nparts = 256;
+    launch_zero_int(Wk.iflag.i(), 4, st);
+    launch_prep_diag(Wk.Vd.d(), n, c0, Wk.td.d(), mixed ? Wk.V32.f() : nullptr, Wk.dminp.d(), nparts, Wk.iflag.i(),
                      st);
-    HIPCHECK(hipMemcpyAsync(H->hpind, H->dminp.p, nparts * 8, hipMemcpyDeviceToHost, st));
-    HIPCHECK(hipMemcpyAsync(H->hpin + 2 * nparts, H->iflag.p, 4, hipMemcpyDeviceToHost, st));
-    HIPCHECK(hipStreamSynchronize(st));
+    launch_d2h(Wk.hpind, Wk.dminp.p, nparts * 8, st);
+    launch_d2h(Wk.hpin + 2 * nparts, Wk.iflag.p, 4, st);
+  }
+  void post_prep() {
+    const int nparts = 256;
     double mn = 1e308;
-    for (int i = 0; i < nparts; ++i) mn = std::min(mn, H->hpind[i]);
-    if (H->hpin[2 * nparts]) throw PpcgError{PPCG_EINVAL, "V contains NaN"};
+    for (int i = 0; i < nparts; ++i) mn = std::min(mn, Wk.hpind[i]);
+    if (Wk.hpin[2 * nparts]) throw PpcgError{PPCG_EINVAL, "V contains NaN"};
     if (!(mn > 0)) throw PpcgError{PPCG_ENOTHPD, "diag(H) has a non-positive entry: Jacobi preconditioner not HPD"};
     dmin = mn;
   }
 
-  // X (active columns c0.., m of them) <- X R^{-1}; result lands in Xt then X/Xt swap
-  void cholqr(int m) {
+  // phase: orthonormal start block and first residual (steps 1-4)
+  void enq_init() {
+    HIPCHECK(hipMemcpy2DAsync(X(), (size_t)ld * 8, X0, (size_t)n * 8, (size_t)n * 8, K, hipMemcpyDeviceToDevice,
+                              st));
+    nl = 0;
+    hasP = false;
+    it = 1;
+    enq_cholqr(K);
+    enq_residual(K);
+    enq_rho_d2h();
+  }
+
+  // X (active columns) <- X R^{-1}; result lands in Xt then X/Xt swap
+  void enq_cholqr(int m) {
     double* Xa = X() + (long)nl * ld;
     {
       ColSet A = cols1(Xa, m, false);
-      gram(A, A, m, m, rows, ld, nullptr, 0, H->G.p, Kp, true, false, 1, 0, 0, "gram_xx");
+      gram(A, A, m, m, rows, ld, nullptr, 0, Wk.G.p, Kp, true, false, 1, 0, 0, "gram_xx");
     }
-    launch_zero_int(H->iflag.i(), 4, st);
-    {
-      Scope s(prof, "chol_inverse");
-      chol_inverse(H->G.d(), H->L.d(), H->Li.d(), m, Kp, H->iflag.i(), st);
-      launch_transpose(H->Li.d(), Kp, H->Rinv.d(), Kp, m, m, st);
-    }
+    launch_zero_int(Wk.iflag.i(), 4, st);
+    chol(Wk.G.d(), m);
+    launch_transpose(Wk.Li.d(), Kp, Wk.Rinv.d(), Kp, m, m, st);
     double* Xn = Xt() + (long)nl * ld;
-    update(Xa, ld, m, H->Rinv.p, Kp, m, Xn, nullptr, m, ld, mixed ? H->X32.f() + (long)nl * ld : nullptr, nullptr,
+    update(Xa, ld, m, Wk.Rinv.p, Kp, m, Xn, nullptr, m, ld, mixed ? Wk.X32.f() + (long)nl * ld : nullptr, nullptr,
            rows, 1.0, 0.0, true, false, "update_xr");
-    if (nl > 0) HIPCHECK(hipMemcpyAsync(Xt(), X(), (size_t)nl * ld * 8, hipMemcpyDeviceToDevice, st));
+    launch_copy(X(), Xt(), (long)nl * ld, st);  // locked prefix
     swapX();
   }
 
   // residual of the active columns: AX = H X, G = X^H AX, W = AX - X G.
-  // plain: AX and W live in W; mixed: in Xt (f64), then W32 = (float) W.
-  // Column norms of the wanted active columns go to cn.
-  void residual(int m) {
+  // plain: H X and then W overwrite the W block; mixed: H X stays in AXm
+  // (float64) and only the float copy W32 of the residual is written.
+  // Column norms of the wanted active columns go to cn, G's to scal.
+  void enq_residual(int m) {
     double* Xa = X() + (long)nl * ld;
-    // plain: H X and then W overwrite the W block; mixed: H X stays in AXm (float64)
-    // and only the float copy W32 of the residual is written
-    double* R = mixed ? H->AXm.d() + (long)nl * ld : H->W.d() + (long)nl * ld;
+    double* R = mixed ? Wk.AXm.d() + (long)nl * ld : Wk.W.d() + (long)nl * ld;
     stencil(Xa, R, m, false);
     ColSet A = cols1(Xa, m, false), B = cols1(R, m, false);
-    gram(A, B, m, m, rows, ld, nullptr, 0, H->G.p, Kp, true, false, 1, 0, 0, "gram_xax");
-    float* W32a = mixed ? H->W32.f() + (long)nl * ld : nullptr;
-    update(Xa, ld, m, H->G.p, Kp, m, R, nullptr, m, ld, W32a, nullptr, rows, -1.0, 1.0, false, false, "update_resid",
+    gram(A, B, m, m, rows, ld, nullptr, 0, Wk.G.p, Kp, true, false, 1, 0, 0, "gram_xax");
+    float* W32a = mixed ? Wk.W32.f() + (long)nl * ld : nullptr;
+    update(Xa, ld, m, Wk.G.p, Kp, m, R, nullptr, m, ld, W32a, nullptr, rows, -1.0, 1.0, false, false, "update_resid",
            mixed);
     int nwa = std::max(0, k - nl);
-    {
-      Scope s(prof, "colnorm");
-      if (mixed) launch_colnorm2(W32a, 1, ld, rows, nwa, H->cn.d(), st);
-      else launch_colnorm2(R, 0, ld, rows, nwa, H->cn.d(), st);
-      launch_frob2_sub(H->G.d(), Kp, nwa, H->scal.d(), st);
-    }
+    Scope s(prof, "colnorm");
+    if (mixed) launch_colnorm2(W32a, 1, ld, rows, nwa, Wk.cn.d(), st);
+    else launch_colnorm2(R, 0, ld, rows, nwa, Wk.cn.d(), st);
+    launch_frob2_sub(Wk.G.d(), Kp, nwa, Wk.scal.d(), st);
   }
 
-  // rho of the loop head from the last residual (cn, scal) and locked parts
-  double rho() {
+  void enq_rho_d2h() {
     int nwa = std::max(0, k - nl);
-    HIPCHECK(hipMemcpyAsync(H->hpind, H->cn.p, (size_t)std::max(nwa, 1) * 8, hipMemcpyDeviceToHost, st));
-    HIPCHECK(hipMemcpyAsync(H->hpind + Kp, H->scal.p, (size_t)std::max(nwa, 1) * 8, hipMemcpyDeviceToHost, st));
-    HIPCHECK(hipMemcpyAsync(H->hpin + 4 * Kp + 8, H->iflag.p, 4, hipMemcpyDeviceToHost, st));
-    HIPCHECK(hipStreamSynchronize(st));
-    if (H->hpin[4 * Kp + 8]) throw PpcgError{PPCG_ERANK, "Cholesky-QR breakdown (X^H X not positive definite)"};
+    launch_d2h(Wk.hpind, Wk.cn.p, (size_t)std::max(nwa, 1) * 8, st);
+    launch_d2h(Wk.hpind + Kp, Wk.scal.p, (size_t)std::max(nwa, 1) * 8, st);
+    launch_d2h(Wk.hpin + 4 * Kp + 8, Wk.iflag.p, 4, st);
+  }
+
+  // rho of the loop head from the last residual (cn, scal) and the locked parts
+  double post_rho() {
+    int nwa = std::max(0, k - nl);
+    if (Wk.hpin[4 * Kp + 8]) throw PpcgError{PPCG_ERANK, "Cholesky-QR breakdown (X^H X not positive definite)"};
     double num = 0, den = 0;
     for (int i = 0; i < nwa; ++i) {
-      num += H->hpind[i];
-      den += H->hpind[Kp + i];
+      num += Wk.hpind[i];
+      den += Wk.hpind[Kp + i];
     }
     for (size_t i = 0; i < lock_wn.size(); ++i) {
       num += lock_wn[i] * lock_wn[i];
@@ -508,66 +618,66 @@ struct Solve {
     return den > 0 ? std::sqrt(num / den) : INFINITY;
   }
 
-  // Rayleigh-Ritz over all K columns (S = [X_lock, X_act]), then W = H X - X Lambda
-  // for all columns, the locking decision and the new active split.  Returns the
-  // fresh residual of the k lowest pairs.
-  double rayleigh_ritz() {
+  // Rayleigh-Ritz over all K columns (S = [X_lock, X_act]), part 1: the
+  // reduced matrix Mr = L^{-1} S^H H S L^{-H} with S^H S = L L^H.
+  void enq_rr1() {
     double* S = X();
-    double* AS = mixed ? H->AXm.d() : H->AW.d();
+    double* AS = mixed ? Wk.AXm.d() : Wk.AW.d();
     stencil(S, AS, K, false);
     ColSet A = cols1(S, K, false);
-    gram(A, cols1(AS, K, false), K, K, rows, ld, nullptr, 0, H->SAS.p, Kp, true, false, 1, 0, 0, "gram_rr");
-    gram(A, A, K, K, rows, ld, nullptr, 0, H->SS.p, Kp, true, false, 1, 0, 0, "gram_rr");
-    launch_zero_int(H->iflag.i(), 4, st);
-    {
-      Scope s(prof, "chol_inverse");
-      chol_inverse(H->SS.d(), H->L.d(), H->Li.d(), K, Kp, H->iflag.i(), st);
-      launch_transpose(H->Li.d(), Kp, H->Rinv.d(), Kp, K, K, st);  // Rinv = Linv^T
-    }
-    // Mr = Linv SAS Linv^T
-    update(H->SAS.p, Kp, K, H->Rinv.p, Kp, K, H->V1.p, nullptr, K, Kp, nullptr, nullptr, Kp, 1.0, 0.0, true, false,
+    gram(A, cols1(AS, K, false), K, K, rows, ld, nullptr, 0, Wk.SAS.p, Kp, true, false, 1, 0, 0, "gram_rr");
+    gram(A, A, K, K, rows, ld, nullptr, 0, Wk.SS.p, Kp, true, false, 1, 0, 0, "gram_rr");
+    launch_zero_int(Wk.iflag.i(), 4, st);
+    chol(Wk.SS.d(), K);
+    launch_transpose(Wk.Li.d(), Kp, Wk.Rinv.d(), Kp, K, K, st);  // Rinv = Linv^T
+    update(Wk.SAS.p, Kp, K, Wk.Rinv.p, Kp, K, Wk.V1.p, nullptr, K, Kp, nullptr, nullptr, Kp, 1.0, 0.0, true, false,
            "update_small");
-    gram(cols1(H->Rinv.p, K, false), cols1(H->V1.p, K, false), K, K, Kp, Kp, nullptr, 0, H->Mr.p, Kp, false, false,
+    gram(cols1(Wk.Rinv.p, K, false), cols1(Wk.V1.p, K, false), K, K, Kp, Kp, nullptr, 0, Wk.Mr.p, Kp, false, false,
          1, 0, 0, "gram_small");
-    launch_symmetrize(H->Mr.d(), Kp, K, st);
-    HIPCHECK(hipMemcpyAsync(H->hpin, H->iflag.p, 4, hipMemcpyDeviceToHost, st));
-    HIPCHECK(hipStreamSynchronize(st));
-    if (H->hpin[0]) throw PpcgError{PPCG_ERANK, "Rayleigh-Ritz Gram S^H S not positive definite"};
-    {
-      Scope s(prof, "eig");
-      block_jacobi_eig(H->Mr.d(), Kp, K, H->Yv.d(), Kp, H->lam.d(), H->eigw.p, H->hpin, rr_rel_tol(), st);
-    }
-    // C = Linv^T Y, X <- S C
-    update(H->Rinv.p, Kp, K, H->Yv.p, Kp, K, H->Cc.p, nullptr, K, Kp, nullptr, nullptr, Kp, 1.0, 0.0, false, false,
+    launch_symmetrize(Wk.Mr.d(), Kp, K, st);
+    launch_d2h(Wk.hpin, Wk.iflag.p, 4, st);
+  }
+  void post_rr1() {
+    if (Wk.hpin[0]) throw PpcgError{PPCG_ERANK, "Rayleigh-Ritz Gram S^H S not positive definite"};
+  }
+  EigJob eig_job() { return EigJob{Wk.Mr.d(), Kp, K, Wk.Yv.d(), Kp, Wk.lam.d(), Wk.eigw.p, rr_rel_tol()}; }
+
+  // part 2: C = L^{-H} Y, X <- S C, fresh W = H X - X Lambda (all columns)
+  void enq_rr2() {
+    double* S = X();
+    update(Wk.Rinv.p, Kp, K, Wk.Yv.p, Kp, K, Wk.Cc.p, nullptr, K, Kp, nullptr, nullptr, Kp, 1.0, 0.0, false, false,
            "update_small");
-    update(S, ld, K, H->Cc.p, Kp, K, Xt(), nullptr, K, ld, mixed ? H->X32.f() : nullptr, nullptr, rows, 1.0, 0.0,
+    update(S, ld, K, Wk.Cc.p, Kp, K, Xt(), nullptr, K, ld, mixed ? Wk.X32.f() : nullptr, nullptr, rows, 1.0, 0.0,
            false, false, "update_rot");
     swapX();
-    // fresh residual W = H X - X Lambda (all K columns)
-    double* R = mixed ? H->AXm.d() : H->W.d();
+    double* R = mixed ? Wk.AXm.d() : Wk.W.d();
     stencil(X(), R, K, false);
     {
       Scope s(prof, "ritz_resid");
       if (mixed) {
-        launch_ritz_resid(R, X(), H->lam.d(), nullptr, H->W32.f(), ld, rows, K, st);
-        launch_colnorm2(H->W32.p, 1, ld, rows, K, H->cn.d(), st);
+        launch_ritz_resid(R, X(), Wk.lam.d(), nullptr, Wk.W32.f(), ld, rows, K, st);
+        launch_colnorm2(Wk.W32.p, 1, ld, rows, K, Wk.cn.d(), st);
       } else {
-        launch_ritz_resid(R, X(), H->lam.d(), R, nullptr, ld, rows, K, st);
-        launch_colnorm2(R, 0, ld, rows, K, H->cn.d(), st);
+        launch_ritz_resid(R, X(), Wk.lam.d(), R, nullptr, ld, rows, K, st);
+        launch_colnorm2(R, 0, ld, rows, K, Wk.cn.d(), st);
       }
     }
-    HIPCHECK(hipMemcpyAsync(H->hpind, H->cn.p, (size_t)K * 8, hipMemcpyDeviceToHost, st));
-    HIPCHECK(hipMemcpyAsync(H->hpind + Kp, H->lam.p, (size_t)K * 8, hipMemcpyDeviceToHost, st));
-    HIPCHECK(hipStreamSynchronize(st));
-    const double* wn2 = H->hpind;
-    const double* lam = H->hpind + Kp;
+    launch_d2h(Wk.hpind, Wk.cn.p, (size_t)K * 8, st);
+    launch_d2h(Wk.hpind + Kp, Wk.lam.p, (size_t)K * 8, st);
+  }
+
+  // locking decision from the fresh Ritz residuals; returns the fresh residual
+  // of the k lowest pairs
+  double post_rr() {
+    const double* wn2 = Wk.hpind;
+    const double* lam = Wk.hpind + Kp;
     double lk = 0, rk = 0;
     for (int i = 0; i < k; ++i) {
       lk += lam[i] * lam[i];
       rk += wn2[i];
     }
-    double fresh = lk > 0 ? std::sqrt(rk / lk) : INFINITY;
-    // locking: leading run of wanted Ritz vectors with |w_i| <= tol |Lambda_k|_F / (2 sqrt(k)),
+    fresh = lk > 0 ? std::sqrt(rk / lk) : INFINITY;
+    // leading run of wanted Ritz vectors with |w_i| <= tol |Lambda_k|_F / (2 sqrt(k)),
     // rounded down to a multiple of q
     double thr = 0.5 * tol * std::sqrt(lk) / std::sqrt((double)k);
     int nlnew = 0;
@@ -581,18 +691,23 @@ struct Solve {
       lock_wn[i] = std::sqrt(wn2[i]);
       lock_lam[i] = lam[i];
     }
-    int m = K - nl;
-    // active G = diag(Lambda_act); residual bookkeeping for rho
-    launch_set_diag(H->G.d(), Kp, m, H->lam.d() + nl, st);
-    int nwa = std::max(0, k - nl);
-    HIPCHECK(hipMemcpyAsync(H->cn.p, H->cn.d() + nl, (size_t)std::max(nwa, 1) * 8, hipMemcpyDeviceToDevice, st));
-    launch_frob2_sub(H->G.d(), Kp, nwa, H->scal.d(), st);
     info.n_rr++;
     return fresh;
   }
 
-  // one PPCG iteration body (steps 8-31)
-  void iteration(int it) {
+  // part 3: active G = diag(Lambda_act) and the residual bookkeeping for rho
+  void enq_rr3() {
+    int m = K - nl;
+    launch_set_diag(Wk.G.d(), Kp, m, Wk.lam.d() + nl, st);
+    int nwa = std::max(0, k - nl);
+    launch_copy(Wk.cn.d() + nl, Wk.scal.d(), std::max(nwa, 1), st);  // shift cn by nl through scal
+    launch_copy(Wk.scal.d(), Wk.cn.d(), std::max(nwa, 1), st);
+    launch_frob2_sub(Wk.G.d(), Kp, nwa, Wk.scal.d(), st);
+    enq_rho_d2h();
+  }
+
+  // phase: steps 8-15 of one iteration
+  void enq_body1() {
     const int m = K - nl;
     const int s = m / q;
     const long off = (long)nl * ld;
@@ -603,7 +718,7 @@ struct Solve {
     void* APa = col(APb(), nl, es);
     // steps 8-10: precondition and project W and P against all K columns of X
     {
-      ColSet A = cols1(mixed ? (const void*)H->X32.p : (const void*)X(), K, mixed);
+      ColSet A = cols1(mixed ? (const void*)Wk.X32.p : (const void*)X(), K, mixed);
       ColSet B{};
       B.p[0] = Wa;
       B.end[0] = m;
@@ -616,14 +731,14 @@ struct Solve {
         B.nseg = 2;
       }
       int ncol = hasP ? 2 * m : m;
-      gram(A, B, K, ncol, rows, ld, H->td.d(), m, H->GWP.p, Kp, false, mixed, 1, 0, 0, "gram_proj");
-      const void* Xs = mixed ? (const void*)H->X32.p : (const void*)X();
-      update(Xs, ld, K, H->GWP.p, Kp, ncol, Wa, Pa, m, ld, nullptr, H->td.d(), rows, -1.0, 1.0, false, mixed,
+      gram(A, B, K, ncol, rows, ld, Wk.td.d(), m, Wk.GWP.p, Kp, false, mixed, 1, 0, 0, "gram_proj");
+      const void* Xs = mixed ? (const void*)Wk.X32.p : (const void*)X();
+      update(Xs, ld, K, Wk.GWP.p, Kp, ncol, Wa, Pa, m, ld, nullptr, Wk.td.d(), rows, -1.0, 1.0, false, mixed,
              "update_proj");
     }
-    // AW = H W, AP = H P
+    // AW = H W, AP = H P (no columns while P is empty)
     stencil(Wa, AWa, m, mixed);
-    if (hasP) stencil(Pa, APa, m, mixed);
+    stencil(Pa, APa, hasP ? m : 0, mixed);
     // steps 11-13: per-block Grams and pencils
     const int nS = hasP ? 3 * q : 2 * q;
     {
@@ -637,7 +752,7 @@ struct Solve {
         A.f32[t] = f[t];
       }
       if (mixed) {  // rows (H X_j)^H [...] from the float64 H X
-        A.p[na] = H->AXm.d() + off;
+        A.p[na] = Wk.AXm.d() + off;
         A.end[na] = (na + 1) * q;
         A.f32[na] = false;
         ++na;
@@ -654,24 +769,25 @@ struct Solve {
       }
       B.nseg = bi;
       int Nb = 2 * nS - q;
-      gram(A, B, Ma, Nb, rows, ld, nullptr, 0, H->bgram.p, Ma, false, false, s, (long)q * ld, (long)Ma * Nb,
+      gram(A, B, Ma, Nb, rows, ld, nullptr, 0, Wk.bgram.p, Ma, false, false, s, (long)q * ld, (long)Ma * Nb,
            "gram_block");
       PencilArgs pa{};
-      pa.gram = H->bgram.d();
+      pa.gram = Wk.bgram.d();
       pa.gstride = (long)Ma * Nb;
       pa.ax_rows = mixed;
-      pa.G = H->G.d();
+      pa.G = Wk.G.d();
       pa.ldg = Kp;
       pa.q = q;
       pa.nS = nS;
-      pa.C = H->bC.d();
+      pa.C = Wk.bC.d();
       pa.cstride = 3L * q * q;
-      pa.flags = H->bflags.i();
+      pa.flags = Wk.bflags.i();
       pa.drop_tol = 1e-14;
       pa.pivot_tol = 1e-12;
       pa.jacobi_rel = pencil_rel_tol();
+      pa.nblocks = s;
       Scope sc(prof, "block_pencil", 0, 0);
-      launch_block_pencil(pa, s, st);
+      launch_block_pencil(pa, st);
     }
     // steps 14-15
     {
@@ -684,133 +800,260 @@ struct Solve {
       bu.ld = ld;
       bu.rows = rows;
       bu.q = q;
-      bu.C = H->bC.d();
+      bu.C = Wk.bC.d();
       bu.cstride = 3L * q * q;
+      bu.nblocks = s;
       Scope sc(prof, "block_update", 6.0 * (double)n * q * q * s * (hasP ? 1.0 : 2.0 / 3.0),
                (double)n * q * s * (hasP ? 5.0 : 4.0) * (double)esz());
-      launch_block_update(bu, s, st);
+      launch_block_update(bu, st);
+    }
+    launch_d2h(Wk.hpin, Wk.bflags.p, (size_t)s * 4, st);
+  }
+  void post_body1() {
+    const int s = (K - nl) / q;
+    for (int j = 0; j < s; ++j) {
+      if (Wk.hpin[j] & 4) throw PpcgError{PPCG_ERANK, "sub-block pencil has rank below sbsize"};
+      if (Wk.hpin[j] & 2) info.n_backtrack++;
     }
     hasP = true;
-    // pencil flags: rank failures / backtracks
-    HIPCHECK(hipMemcpyAsync(H->hpin, H->bflags.p, (size_t)s * 4, hipMemcpyDeviceToHost, st));
-    HIPCHECK(hipStreamSynchronize(st));
-    for (int j = 0; j < s; ++j) {
-      if (H->hpin[j] & 4) throw PpcgError{PPCG_ERANK, "sub-block pencil has rank below sbsize"};
-      if (H->hpin[j] & 2) info.n_backtrack++;
-    }
-    if (it % rr_period != 0) {
-      cholqr(m);
-      residual(m);
-    } else {
-      rayleigh_ritz();
-    }
   }
 
-  void finish(double* Xout, double* lamout, double fresh) {
+  // phase: steps 18-20
+  void enq_cq() {
+    int m = K - nl;
+    enq_cholqr(m);
+    enq_residual(m);
+    enq_rho_d2h();
+  }
+
+  // phase: outputs and the orthogonality check of the returned block
+  void enq_finish() {
     HIPCHECK(hipMemcpy2DAsync(Xout, (size_t)n * 8, X(), (size_t)ld * 8, (size_t)n * 8, k, hipMemcpyDeviceToDevice,
                               st));
-    HIPCHECK(hipMemcpyAsync(lamout, H->lam.p, (size_t)k * 8, hipMemcpyDeviceToDevice, st));
-    // orthogonality of the returned block
+    HIPCHECK(hipMemcpyAsync(lamout, Wk.lam.p, (size_t)k * 8, hipMemcpyDeviceToDevice, st));
     ColSet A = cols1(X(), k, false);
-    gram(A, A, k, k, rows, ld, nullptr, 0, H->G.p, Kp, false, false, 1, 0, 0, "gram_check");
-    launch_orth_err2(H->G.d(), Kp, k, H->scal.d(), st);
-    HIPCHECK(hipMemcpyAsync(H->hpind, H->scal.p, 8, hipMemcpyDeviceToHost, st));
-    HIPCHECK(hipStreamSynchronize(st));
-    info.orth_err = std::sqrt(H->hpind[0]);
+    gram(A, A, k, k, rows, ld, nullptr, 0, Wk.G.p, Kp, false, false, 1, 0, 0, "gram_check");
+    launch_orth_err2(Wk.G.d(), Kp, k, Wk.scal.d(), st);
+    launch_d2h(Wk.hpind, Wk.scal.p, 8, st);
+  }
+  void post_finish() {
+    info.orth_err = std::sqrt(Wk.hpind[0]);
     info.resid_final = fresh;
     info.n_locked = nl;
+    info.time_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+};
+
+// ---------------------------------------------------------------------------
+// lockstep driver
+// ---------------------------------------------------------------------------
+struct Driver {
+  ppcg_handle* H;
+  bool batched;
+  Recorder rec;
+
+  Driver(ppcg_handle* h, bool b) : H(h), batched(b) {}
+
+  static const char* op_name(int kind) {
+    switch (kind) {
+      case OP_GRAM_D0: case OP_GRAM_F0: return "gram";
+      case OP_GRAM_D1: case OP_GRAM_F1: return "gram_proj";
+      case OP_GRAM_D2: case OP_GRAM_F2: return "gram_block";
+      case OP_REDUCE_D: case OP_REDUCE_F: return "reduce";
+      case OP_UPDATE_D0: case OP_UPDATE_F0: return "update";
+      case OP_UPDATE_D1: case OP_UPDATE_F1: return "update_proj";
+      case OP_STENCIL_D2: case OP_STENCIL_D4: return "stencil_f64";
+      case OP_STENCIL_F2: case OP_STENCIL_F4: return "stencil_f32";
+      case OP_PENCIL24: case OP_PENCIL48: return "block_pencil";
+      case OP_CHOL: return "chol_inverse";
+      default: return (kind >= OP_BUPD_D4 && kind <= OP_BUPD_F32) ? "block_update" : "misc";
+    }
   }
 
-  ppcg_status run(const ppcg_operator* op, int k_, int q_, double tol_, int rrp, const double* X0, double* Xout,
-                  double* lamout) {
-    auto t0 = std::chrono::steady_clock::now();
-    if (!op || !op->V || !X0 || !Xout || !lamout) throw PpcgError{PPCG_EINVAL, "null pointer argument"};
-    if (op->kpt[0] != 0 || op->kpt[1] != 0 || op->kpt[2] != 0)
-      throw PpcgError{PPCG_EINVAL, "complex (Bloch) operators are not available in this build"};
-    if (op->order != 2 && op->order != 4) throw PpcgError{PPCG_EINVAL, "order must be 2 or 4"};
-    if (op->precond != PPCG_PRECOND_JACOBI) throw PpcgError{PPCG_EINVAL, "only the Jacobi preconditioner"};
-    if (op->nx < 4 || !(op->h > 0)) throw PpcgError{PPCG_EINVAL, "bad grid"};
-    N = op->nx;
-    order = op->order;
-    hsp = op->h;
-    double ih2 = 1.0 / (hsp * hsp);
-    if (order == 2) {
-      c0 = 3.0 * ih2;
-      w1 = -0.5 * ih2;
-      w2 = 0;
-    } else {
-      c0 = 3.0 * 1.25 * ih2;
-      w1 = -2.0 / 3.0 * ih2;
-      w2 = ih2 / 24.0;
+  // replay the recorded lists: one grouped launch per position and kind.
+  // Pass 1 packs every job array and prefix-sum array of the phase into one
+  // host buffer (one upload); pass 2 issues the launches in recorded order.
+  void flush() {
+    auto& L = rec.lists;
+    size_t len = L.empty() ? 0 : L[0].size();
+    for (auto& l : L)
+      if (l.size() != len) throw PpcgError{PPCG_EINVAL, "internal: batched phases diverged"};
+    hipStream_t st = H->st;
+    struct G { size_t pos; int kind; std::vector<int> idx; size_t jobs_off = 0, start_off = 0; unsigned tot = 0; };
+    std::vector<G> groups;
+    std::vector<uint8_t> buf;
+    auto align = [&]() { buf.resize((buf.size() + 15) / 16 * 16); };
+    for (size_t pos = 0; pos < len; ++pos) {
+      std::map<int, std::vector<int>> by_kind;
+      for (int i = 0; i < (int)L.size(); ++i) by_kind[L[i][pos].kind].push_back(i);
+      for (auto& kv : by_kind) {
+        G g;
+        g.pos = pos;
+        g.kind = kv.first;
+        g.idx = kv.second;
+        if (g.kind != OP_D2H && g.kind != OP_CHOL) {
+          size_t asz = op_args_size(g.kind);
+          align();
+          g.jobs_off = buf.size();
+          buf.resize(buf.size() + asz * g.idx.size());
+          for (size_t j = 0; j < g.idx.size(); ++j)
+            std::memcpy(buf.data() + g.jobs_off + j * asz, L[g.idx[j]][pos].args.data(), asz);
+          align();
+          g.start_off = buf.size();
+          buf.resize(buf.size() + sizeof(unsigned) * (g.idx.size() + 1));
+          unsigned* s = (unsigned*)(buf.data() + g.start_off);
+          for (size_t j = 0; j < g.idx.size(); ++j) {
+            s[j] = g.tot;
+            g.tot += L[g.idx[j]][pos].nwg;
+          }
+          s[g.idx.size()] = g.tot;
+        }
+        groups.push_back(std::move(g));
+      }
     }
-    n = (long)N * N * N;
-    rows = round_up(n, 256);
-    ld = rows;
-    k = k_;
-    q = q_;
-    tol = tol_;
-    rr_period = rrp;
-    mixed = H->opt.precision == PPCG_MIXED;
-    max_iter = H->opt.max_iter > 0 ? H->opt.max_iter : 20000;
-    if (k <= 0 || q < 1 || q > 16 || !(tol > 0) || rr_period < 1)
-      throw PpcgError{PPCG_EINVAL, "need k > 0, 1 <= sbsize <= 16, tol > 0, rr_period >= 1"};
-    int nbuf = H->opt.nbuf;
-    if (nbuf < 0) {
-      int extra = std::max(2, (int)std::ceil(0.02 * k));
-      nbuf = q * ((k + extra + q - 1) / q) - k;
-    }
-    K = k + nbuf;
-    if (K % q != 0) throw PpcgError{PPCG_EINVAL, "k + nbuf must be a multiple of sbsize"};
-    if ((long)K * 4 > n) throw PpcgError{PPCG_EINVAL, "k + nbuf must not exceed n/4"};
-    Kp = (int)round_up(K, 64);
-    H->has_state = false;
-    allocate();
-    prep(op->V);
-    HIPCHECK(hipMemcpy2DAsync(X(), (size_t)ld * 8, X0, (size_t)n * 8, (size_t)n * 8, K, hipMemcpyDeviceToDevice, st));
-    // steps 1-4: orthonormal start and first residual
-    nl = 0;
-    hasP = false;
-    cholqr(K);
-    if (mixed) {
-      // X32 for the projections (cholqr wrote the active part, i.e. all K)
-    }
-    residual(K);
-    int it = 1;
-    double fresh = INFINITY;
-    ppcg_status status = PPCG_OK;
-    while (true) {
-      double r = rho();
-      if (r <= tol) {
-        fresh = rayleigh_ritz();
-        if (fresh <= tol) break;
+    uint8_t* dev = buf.empty() ? nullptr : (uint8_t*)H->stage.upload(buf.data(), buf.size(), st);
+    for (G& g : groups) {
+      if (g.kind == OP_D2H) {
+        for (int i : g.idx) {
+          D2HArgs a;
+          std::memcpy(&a, L[i][g.pos].args.data(), sizeof(a));
+          if (a.bytes) HIPCHECK(hipMemcpyAsync(a.dst, a.src, a.bytes, hipMemcpyDeviceToHost, st));
+        }
         continue;
       }
-      if (it > max_iter) {
-        fresh = rayleigh_ritz();
-        status = PPCG_ENOCONV;
-        break;
+      Scope sc(H->prof, op_name(g.kind));
+      if (g.kind == OP_CHOL) {
+        std::vector<CholArgs> jobs;
+        for (int i : g.idx) {
+          CholArgs a;
+          std::memcpy(&a, L[i][g.pos].args.data(), sizeof(a));
+          jobs.push_back(a);
+        }
+        chol_inverse_grouped(jobs, H->stage, st);
+        continue;
       }
-      iteration(it);
-      info.iters = it;
-      ++it;
+      if (g.tot == 0) continue;
+      if (!launch_grouped(g.kind, dev + g.jobs_off, (const unsigned*)(dev + g.start_off), (int)g.idx.size(), g.tot,
+                          st))
+        throw PpcgError{PPCG_EINVAL, "internal: op cannot be grouped"};
     }
-    finish(Xout, lamout, fresh);
-    prof.collect();
-    if (status == PPCG_OK) {
-      H->has_state = true;
-      H->s_N = N;
-      H->s_order = order;
-      H->s_k = k;
-      H->s_n = n;
-      H->s_rows = rows;
-      H->s_c0 = c0;
-      H->s_w1 = w1;
-      H->s_w2 = w2;
-      H->s_dmin = dmin;
+  }
+
+  template <class F>
+  void phase(const std::vector<Prob*>& ps, F fn) {
+    if (ps.empty()) return;
+    if (!batched) {
+      for (Prob* p : ps) fn(*p);
+      return;
     }
-    info.time_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    if (status == PPCG_ENOCONV) H->err = "max_iter reached";
-    return status;
+    rec.begin((int)ps.size());
+    g_rec = &rec;
+    try {
+      for (int i = 0; i < (int)ps.size(); ++i) {
+        rec.cur = i;
+        fn(*ps[i]);
+      }
+    } catch (...) {
+      g_rec = nullptr;
+      throw;
+    }
+    g_rec = nullptr;
+    flush();
+  }
+
+  // run fn on each problem; a problem that throws leaves the set
+  template <class F>
+  void post(std::vector<Prob*>& ps, F fn) {
+    std::vector<Prob*> keep;
+    for (Prob* p : ps) {
+      try {
+        fn(*p);
+        keep.push_back(p);
+      } catch (const PpcgError& e) {
+        p->status = e.code;
+        p->err = e.msg;
+      }
+    }
+    ps.swap(keep);
+  }
+
+  void rayleigh_ritz(std::vector<Prob*>& ps) {
+    phase(ps, [](Prob& p) { p.enq_rr1(); });
+    sync(H);
+    post(ps, [](Prob& p) { p.post_rr1(); });
+    if (ps.empty()) return;
+    std::vector<EigJob> jobs;
+    for (Prob* p : ps) jobs.push_back(p->eig_job());
+    {
+      Scope s(H->prof, "eig");
+      if (!H->hcounter) HIPCHECK(hipHostMalloc((void**)&H->hcounter, 64, hipHostMallocDefault));
+      H->counter.ensure(256);
+      block_jacobi_eig_grouped(jobs, H->stage, H->counter.i(), H->hcounter, H->st);
+    }
+    phase(ps, [](Prob& p) { p.enq_rr2(); });
+    sync(H);
+    post(ps, [](Prob& p) { p.post_rr(); });
+  }
+
+  // Algorithm 3 over a set of problems in lockstep.  Each problem ends with
+  // status OK, ENOCONV or an error of its own.
+  void run(std::vector<Prob*> act) {
+    for (Prob* p : act) p->allocate();
+    phase(act, [](Prob& p) { p.enq_prep(); });
+    sync(H);
+    post(act, [](Prob& p) { p.post_prep(); });
+    phase(act, [](Prob& p) { p.enq_init(); });
+    sync(H);
+    while (!act.empty()) {
+      std::vector<Prob*> fin, body, done, again;
+      post(act, [&](Prob& p) {
+        double r = p.post_rho();
+        if (r <= p.tol) fin.push_back(&p);
+        else if (p.it > p.max_iter) {
+          p.noconv = true;
+          fin.push_back(&p);
+        } else body.push_back(&p);
+      });
+      // final Rayleigh-Ritz and the fresh residual check (loop head, rho <= tol)
+      if (!fin.empty()) {
+        rayleigh_ritz(fin);
+        for (Prob* p : fin) {
+          if (p->fresh <= p->tol) done.push_back(p);
+          else if (p->noconv) {
+            p->status = PPCG_ENOCONV;
+            p->err = "max_iter reached";
+            done.push_back(p);
+          } else again.push_back(p);
+        }
+        phase(again, [](Prob& p) { p.enq_rr3(); });
+      }
+      if (!body.empty()) {
+        phase(body, [](Prob& p) { p.enq_body1(); });
+        sync(H);
+        post(body, [](Prob& p) { p.post_body1(); });
+        std::vector<Prob*> cq, rr;
+        for (Prob* p : body) (p->it % p->rr_period != 0 ? cq : rr).push_back(p);
+        phase(cq, [](Prob& p) { p.enq_cq(); });
+        if (!rr.empty()) {
+          rayleigh_ritz(rr);
+          phase(rr, [](Prob& p) { p.enq_rr3(); });
+        }
+        for (Prob* p : body) {
+          p->info.iters = p->it;
+          p->it++;
+        }
+      }
+      phase(done, [](Prob& p) { p.enq_finish(); });
+      sync(H);
+      for (Prob* p : done) p->post_finish();
+      std::vector<Prob*> alive;
+      for (Prob* p : again)
+        if (p->status == PPCG_OK) alive.push_back(p);
+      for (Prob* p : body)
+        if (p->status == PPCG_OK) alive.push_back(p);
+      act.swap(alive);
+    }
+    H->prof.collect();
   }
 };
 
@@ -821,20 +1064,20 @@ struct Grad {
   ppcg_handle* H;
   hipStream_t st;
   Prof& prof;
-  int k;
-  long n, rows, ld;
+  int k = 0;
+  long n = 0, rows = 0, ld = 0;
   Grad(ppcg_handle* h) : H(h), st(h->st), prof(h->prof) {}
 
   // Y <- (I - X X^H) Y over the k saved eigenvectors
   void project(double* Y) {
-    Solve s(H);
+    Prob s(H, H->work(0));
     s.n = n;
     s.rows = rows;
     s.ld = ld;
-    ColSet A = Solve::cols1(H->X.p, k, false), B = Solve::cols1(Y, k, false);
+    ColSet A = Prob::cols1(H->work(0).X.p, k, false), B = Prob::cols1(Y, k, false);
     s.gram(A, B, k, k, rows, ld, nullptr, 0, H->gsc.p, (int)round_up(k, 64), false, false, 1, 0, 0, "gram_grad");
-    s.update(H->X.p, ld, k, H->gsc.p, round_up(k, 64), k, Y, nullptr, k, ld, nullptr, nullptr, rows, -1.0, 1.0,
-             false, false, "update_grad");
+    s.update(H->work(0).X.p, ld, k, H->gsc.p, round_up(k, 64), k, Y, nullptr, k, ld, nullptr, nullptr, rows, -1.0,
+             1.0, false, false, "update_grad");
   }
   void stencil_shift(const double* P, double* Y) {
     StencilArgs a{};
@@ -847,9 +1090,9 @@ struct Grad {
     a.c0 = H->s_c0;
     a.w1 = H->s_w1;
     a.w2 = H->s_w2;
-    a.V = H->Vd.p;
+    a.V = H->work(0).Vd.p;
     a.f32 = 0;
-    a.shift = H->lam.d();
+    a.shift = H->work(0).lam.d();
     Scope sc(prof, "stencil_f64", (H->s_order == 4 ? 17.0 : 11.0) * n * k, 16.0 * n * k);
     launch_stencil(a, st);
   }
@@ -857,13 +1100,14 @@ struct Grad {
   int run(const double* g, const double* w, double* out, double tol, int max_iter) {
     if (!H->has_state) throw PpcgError{PPCG_ENOSTATE, "ppcg_grad needs a successful ppcg_solve on this handle"};
     if (!g || !out || !(tol > 0)) throw PpcgError{PPCG_EINVAL, "null pointer or tol <= 0"};
+    Work& Wk = H->work(0);
     k = H->s_k;
     n = H->s_n;
     rows = H->s_rows;
     ld = rows;
     if (!w) {
-      launch_grad_rows(H->X.d(), nullptr, g, ld, n, k, out, st);
-      HIPCHECK(hipStreamSynchronize(st));
+      launch_grad_rows(Wk.X.d(), nullptr, g, ld, n, k, out, st);
+      sync(H);
       return 0;
     }
     const size_t blk = (size_t)rows * k * 8;
@@ -877,24 +1121,24 @@ struct Grad {
     int* done = (int*)(sc + 7 * kp);
     int* left = (int*)(sc + 8 * kp);
     // the partial buffer must hold a k x k Gram
-    H->part.ensure((size_t)k * k * 8 * 4);
+    Wk.part.ensure((size_t)k * k * 8 * 4);
     HIPCHECK(hipMemsetAsync(H->gw.p, 0, H->gw.bytes, st));
     HIPCHECK(hipMemcpyAsync(H->gw.p, w, n * 8, hipMemcpyDeviceToDevice, st));
     double *Z = H->gZ.d(), *R = H->gR.d(), *P = H->gP.d(), *AP = H->gAP.d(), *Y = H->gY.d();
     // b = Q (w x_i)
-    launch_scale_rows(H->gw.d(), H->X.p, R, ld, rows, k, 0, st);
+    launch_scale_rows(H->gw.d(), Wk.X.p, R, ld, rows, k, 0, st);
     project(R);
     launch_coldot(R, R, ld, rows, k, bb, st);
     launch_fill(Z, (long)rows * k, 0.0, st);
     launch_zero_int(done, k, st);
     // Jacobi preconditioner 1/(diag(H) - lambda_i) when it is positive definite
-    HIPCHECK(hipMemcpyAsync(H->hpind, H->lam.p, (size_t)k * 8, hipMemcpyDeviceToHost, st));
-    HIPCHECK(hipStreamSynchronize(st));
+    HIPCHECK(hipMemcpyAsync(Wk.hpind, Wk.lam.p, (size_t)k * 8, hipMemcpyDeviceToHost, st));
+    sync(H);
     double lmax = -1e308;
-    for (int j = 0; j < k; ++j) lmax = std::max(lmax, H->hpind[j]);
+    for (int j = 0; j < k; ++j) lmax = std::max(lmax, Wk.hpind[j]);
     int unprec = !(H->s_dmin - lmax > 0);
     auto precond = [&]() {
-      launch_cg_precond(R, Y, H->Vd.d(), H->s_c0, H->lam.d(), ld, n, rows, k, unprec, st);
+      launch_cg_precond(R, Y, Wk.Vd.d(), H->s_c0, Wk.lam.d(), ld, n, rows, k, unprec, st);
       project(Y);
     };
     precond();
@@ -911,9 +1155,9 @@ struct Grad {
       launch_zero_int(left, 1, st);
       launch_cg_check(rr, bb, tol, done, left, k, st);
       if (it % 4 == 3 || it == max_iter - 1) {
-        HIPCHECK(hipMemcpyAsync(H->hpin, left, 4, hipMemcpyDeviceToHost, st));
-        HIPCHECK(hipStreamSynchronize(st));
-        if (H->hpin[0] == 0) {
+        HIPCHECK(hipMemcpyAsync(Wk.hpin, left, 4, hipMemcpyDeviceToHost, st));
+        sync(H);
+        if (Wk.hpin[0] == 0) {
           ++it;
           break;
         }
@@ -923,8 +1167,8 @@ struct Grad {
       launch_cg_beta(rz, rznew, done, beta, k, st);
       launch_cg_p(P, Y, beta, ld, rows, k, st);
     }
-    launch_grad_rows(H->X.d(), Z, g, ld, n, k, out, st);
-    HIPCHECK(hipStreamSynchronize(st));
+    launch_grad_rows(Wk.X.d(), Z, g, ld, n, k, out, st);
+    sync(H);
     prof.collect();
     return it;
   }
@@ -935,9 +1179,11 @@ ppcg_status guard(ppcg_handle* h, const std::function<ppcg_status()>& f) {
     if (h) HIPCHECK(hipSetDevice(h->device));
     return f();
   } catch (const PpcgError& e) {
+    g_rec = nullptr;
     if (h) h->err = e.msg;
     return e.code;
   } catch (const std::exception& e) {
+    g_rec = nullptr;
     if (h) h->err = e.what();
     return PPCG_EHIP;
   }
@@ -976,16 +1222,66 @@ ppcg_status ppcg_solve(ppcg_handle* h, const ppcg_operator* op, int32_t k, int32
                        int32_t rr_period, const double* X0, double* X_out, double* lambda_out, ppcg_info* info) {
   if (!h) return PPCG_EINVAL;
   return guard(h, [&]() {
-    Solve s(h);
-    ppcg_status st = PPCG_OK;
+    h->has_state = false;
+    Prob p(h, h->work(0));
     try {
-      st = s.run(op, k, sbsize, tol, rr_period, X0, X_out, lambda_out);
+      p.setup(op, k, sbsize, tol, rr_period, X0, X_out, lambda_out);
+      Driver d(h, false);
+      d.run({&p});
     } catch (...) {
-      if (info) *info = s.info;
+      if (info) *info = p.info;
       throw;
     }
-    if (info) *info = s.info;
-    return st;
+    if (info) *info = p.info;
+    if (p.status != PPCG_OK) {
+      h->err = p.err;
+      return p.status;
+    }
+    h->has_state = true;
+    h->s_N = p.N;
+    h->s_order = p.order;
+    h->s_k = p.k;
+    h->s_n = p.n;
+    h->s_rows = p.rows;
+    h->s_c0 = p.c0;
+    h->s_w1 = p.w1;
+    h->s_w2 = p.w2;
+    h->s_dmin = p.dmin;
+    return PPCG_OK;
+  });
+}
+
+ppcg_status ppcg_solve_batched(ppcg_handle* h, int32_t nprob, const ppcg_operator* ops, const int32_t* k,
+                               int32_t sbsize, double tol, int32_t rr_period, const double* const* X0,
+                               double* const* X_out, double* const* lambda_out, ppcg_info* infos,
+                               int32_t* statuses) {
+  if (!h || nprob < 0 || (nprob > 0 && (!ops || !k || !X0 || !X_out || !lambda_out))) return PPCG_EINVAL;
+  return guard(h, [&]() {
+    h->has_state = false;
+    std::vector<std::unique_ptr<Prob>> ps;
+    std::vector<Prob*> run;
+    ppcg_status first = PPCG_OK;
+    for (int b = 0; b < nprob; ++b) {
+      ps.emplace_back(new Prob(h, h->work(b)));
+      try {
+        ps[b]->setup(&ops[b], k[b], sbsize, tol, rr_period, X0[b], X_out[b], lambda_out[b]);
+        run.push_back(ps[b].get());
+      } catch (const PpcgError& e) {
+        ps[b]->status = e.code;
+        ps[b]->err = e.msg;
+      }
+    }
+    Driver d(h, true);
+    d.run(run);
+    for (int b = 0; b < nprob; ++b) {
+      if (infos) infos[b] = ps[b]->info;
+      if (statuses) statuses[b] = ps[b]->status;
+      if (ps[b]->status != PPCG_OK && first == PPCG_OK) {
+        first = ps[b]->status;
+        h->err = "problem " + std::to_string(b) + ": " + ps[b]->err;
+      }
+    }
+    return first;
   });
 }
 
@@ -1004,9 +1300,9 @@ ppcg_status ppcg_density(ppcg_handle* h, double* rho) {
   if (!h || !rho) return PPCG_EINVAL;
   return guard(h, [&]() {
     if (!h->has_state) throw PpcgError{PPCG_ENOSTATE, "ppcg_density needs a successful ppcg_solve on this handle"};
-    launch_grad_rows(h->X.d(), nullptr, nullptr, h->s_rows, h->s_n, h->s_k, rho, h->st);
+    launch_grad_rows(h->work(0).X.d(), nullptr, nullptr, h->s_rows, h->s_n, h->s_k, rho, h->st);
     HIPCHECK(hipGetLastError());
-    HIPCHECK(hipStreamSynchronize(h->st));
+    sync(h);
     return PPCG_OK;
   });
 }
@@ -1027,25 +1323,18 @@ ppcg_status ppcg_apply_h(ppcg_handle* h, const ppcg_operator* op, int32_t ncols,
     if (op->order != 2 && op->order != 4) throw PpcgError{PPCG_EINVAL, "order must be 2 or 4"};
     if (op->kpt[0] != 0 || op->kpt[1] != 0 || op->kpt[2] != 0)
       throw PpcgError{PPCG_EINVAL, "complex (Bloch) operators are not available in this build"};
-    Solve s(h);
-    s.N = op->nx;
-    s.order = op->order;
     double ih2 = 1.0 / (op->h * op->h);
-    s.c0 = op->order == 2 ? 3.0 * ih2 : 3.75 * ih2;
-    s.w1 = op->order == 2 ? -0.5 * ih2 : -2.0 / 3.0 * ih2;
-    s.w2 = op->order == 2 ? 0.0 : ih2 / 24.0;
-    s.n = (long)s.N * s.N * s.N;
-    s.ld = s.n;
+    long n = (long)op->nx * op->nx * op->nx;
     StencilArgs a{};
     a.X = X;
     a.Y = Y;
-    a.ldx = a.ldy = s.n;
+    a.ldx = a.ldy = n;
     a.ncols = ncols;
-    a.N = s.N;
-    a.order = s.order;
-    a.c0 = s.c0;
-    a.w1 = s.w1;
-    a.w2 = s.w2;
+    a.N = op->nx;
+    a.order = op->order;
+    a.c0 = op->order == 2 ? 3.0 * ih2 : 3.75 * ih2;
+    a.w1 = op->order == 2 ? -0.5 * ih2 : -2.0 / 3.0 * ih2;
+    a.w2 = op->order == 2 ? 0.0 : ih2 / 24.0;
     a.V = op->V;
     a.f32 = 0;
     {
@@ -1053,20 +1342,9 @@ ppcg_status ppcg_apply_h(ppcg_handle* h, const ppcg_operator* op, int32_t ncols,
       launch_stencil(a, h->st);
     }
     HIPCHECK(hipGetLastError());
-    HIPCHECK(hipStreamSynchronize(h->st));
+    sync(h);
     return PPCG_OK;
   });
-}
-
-int32_t ppcg_kernel_stats(ppcg_handle* h, const char** names, double* ms, int64_t* counts, double* flops,
-                          double* bytes, int32_t cap) {
-  if (!h) return 0;
-  int32_t w = ppcg_kernel_times(h, names, ms, counts, cap);
-  for (int32_t i = 0; i < w; ++i) {
-    if (flops) flops[i] = h->prof.flops[i];
-    if (bytes) bytes[i] = h->prof.bytes[i];
-  }
-  return w;
 }
 
 int32_t ppcg_kernel_times(ppcg_handle* h, const char** names, double* ms, int64_t* counts, int32_t cap) {
@@ -1082,6 +1360,17 @@ int32_t ppcg_kernel_times(ppcg_handle* h, const char** names, double* ms, int64_
     if (names) names[i] = h->prof.names[i].c_str();
     if (ms) ms[i] = h->prof.ms[i];
     if (counts) counts[i] = h->prof.counts[i];
+  }
+  return w;
+}
+
+int32_t ppcg_kernel_stats(ppcg_handle* h, const char** names, double* ms, int64_t* counts, double* flops,
+                          double* bytes, int32_t cap) {
+  if (!h) return 0;
+  int32_t w = ppcg_kernel_times(h, names, ms, counts, cap);
+  for (int32_t i = 0; i < w; ++i) {
+    if (flops) flops[i] = h->prof.flops[i];
+    if (bytes) bytes[i] = h->prof.bytes[i];
   }
   return w;
 }

@@ -11,10 +11,10 @@
 namespace ppcg {
 
 template <class T, int ORDER>
-__global__ __launch_bounds__(256) void stencil_kernel(StencilArgs a) {
+PPCG_DEV void stencil_body(const StencilArgs& a, unsigned wg, unsigned nwg) {
   const long n = (long)a.N * a.N * a.N;
   const unsigned bpc = (unsigned)((n + 255) / 256);
-  unsigned L = xcd_remap(blockIdx.x, gridDim.x);
+  unsigned L = xcd_remap(wg, nwg);
   int col = L / bpc;
   long p = (long)(L % bpc) * 256 + threadIdx.x;
   if (col >= a.ncols || p >= n) return;
@@ -43,17 +43,30 @@ __global__ __launch_bounds__(256) void stencil_kernel(StencilArgs a) {
   if (a.shift) out -= (T)a.shift[col] * xc;
   y[p] = out;
 }
+template <class T, int ORDER>
+__global__ __launch_bounds__(256) void stencil_kernel(StencilArgs a) {
+  stencil_body<T, ORDER>(a, blockIdx.x, gridDim.x);
+}
+template <class T, int ORDER>
+__global__ __launch_bounds__(256) void stencil_grouped(const StencilArgs* jobs, const unsigned* start, int nj) {
+  int j = find_job(start, nj, blockIdx.x);
+  stencil_body<T, ORDER>(jobs[j], blockIdx.x - start[j], start[j + 1] - start[j]);
+}
 
 void launch_stencil(const StencilArgs& a, hipStream_t st) {
   long n = (long)a.N * a.N * a.N;
-  long blocks = ((n + 255) / 256) * a.ncols;
+  unsigned blocks = (unsigned)(((n + 255) / 256) * a.ncols);
+  int kind = a.f32 ? (a.order == 4 ? OP_STENCIL_F4 : OP_STENCIL_F2) : (a.order == 4 ? OP_STENCIL_D4 : OP_STENCIL_D2);
+  if (g_rec) {
+    g_rec->add(kind, &a, sizeof(a), blocks);
+    return;
+  }
   if (blocks == 0) return;
-  if (a.f32) {
-    if (a.order == 4) hipLaunchKernelGGL((stencil_kernel<float, 4>), dim3(blocks), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((stencil_kernel<float, 2>), dim3(blocks), dim3(256), 0, st, a);
-  } else {
-    if (a.order == 4) hipLaunchKernelGGL((stencil_kernel<double, 4>), dim3(blocks), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((stencil_kernel<double, 2>), dim3(blocks), dim3(256), 0, st, a);
+  switch (kind) {
+    case OP_STENCIL_F4: hipLaunchKernelGGL((stencil_kernel<float, 4>), dim3(blocks), dim3(256), 0, st, a); break;
+    case OP_STENCIL_F2: hipLaunchKernelGGL((stencil_kernel<float, 2>), dim3(blocks), dim3(256), 0, st, a); break;
+    case OP_STENCIL_D4: hipLaunchKernelGGL((stencil_kernel<double, 4>), dim3(blocks), dim3(256), 0, st, a); break;
+    case OP_STENCIL_D2: hipLaunchKernelGGL((stencil_kernel<double, 2>), dim3(blocks), dim3(256), 0, st, a); break;
   }
 }
 
@@ -80,24 +93,12 @@ void launch_scale_rows(const double* d, const void* X, void* Y, long ld, long ro
                           (double*)Y, ld, rows, ncols);
 }
 
-__global__ __launch_bounds__(256) void to_f32_kernel(const double* X, float* Y, long ld, long rows, int ncols) {
-  long e = blockIdx.x * 256L + threadIdx.x;
-  if (e >= rows * ncols) return;
-  long c = e / rows, r = e % rows;
-  Y[r + c * ld] = (float)X[r + c * ld];
-}
-void launch_to_f32(const double* X, float* Y, long ld, long rows, int ncols, hipStream_t st) {
-  long tot = rows * ncols;
-  if (tot == 0) return;
-  hipLaunchKernelGGL(to_f32_kernel, dim3((tot + 255) / 256), dim3(256), 0, st, X, Y, ld, rows, ncols);
-}
-
 // one workgroup per column, fixed-order tree reduction
 template <class T>
-__global__ __launch_bounds__(256) void colnorm2_kernel(const T* X, long ld, long rows, double* out) {
-  const T* x = X + (long)blockIdx.x * ld;
+PPCG_DEV void colnorm2_body(const ColnormArgs& a, unsigned wg, unsigned) {
+  const T* x = (const T*)a.X + (long)wg * a.ld;
   double s = 0;
-  for (long r = threadIdx.x; r < rows; r += 256) {
+  for (long r = threadIdx.x; r < a.rows; r += 256) {
     double v = (double)x[r];
     s += v * v;
   }
@@ -105,28 +106,74 @@ __global__ __launch_bounds__(256) void colnorm2_kernel(const T* X, long ld, long
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) out[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+  if (threadIdx.x == 0) a.out[wg] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+template <class T>
+__global__ __launch_bounds__(256) void colnorm2_kernel(ColnormArgs a) {
+  colnorm2_body<T>(a, blockIdx.x, gridDim.x);
+}
+template <class T>
+__global__ __launch_bounds__(256) void colnorm2_grouped(const ColnormArgs* jobs, const unsigned* start, int nj) {
+  int j = find_job(start, nj, blockIdx.x);
+  colnorm2_body<T>(jobs[j], blockIdx.x - start[j], start[j + 1] - start[j]);
 }
 void launch_colnorm2(const void* X, int f32, long ld, long rows, int ncols, double* out, hipStream_t st) {
-  if (ncols <= 0) return;
-  if (f32) hipLaunchKernelGGL(colnorm2_kernel<float>, dim3(ncols), dim3(256), 0, st, (const float*)X, ld, rows, out);
-  else hipLaunchKernelGGL(colnorm2_kernel<double>, dim3(ncols), dim3(256), 0, st, (const double*)X, ld, rows, out);
+  ColnormArgs a{X, f32, ld, rows, ncols, out};
+  unsigned blocks = ncols > 0 ? (unsigned)ncols : 0;
+  if (g_rec) {
+    g_rec->add(f32 ? OP_COLNORM_F : OP_COLNORM_D, &a, sizeof(a), blocks);
+    return;
+  }
+  if (blocks == 0) return;
+  if (f32) hipLaunchKernelGGL(colnorm2_kernel<float>, dim3(blocks), dim3(256), 0, st, a);
+  else hipLaunchKernelGGL(colnorm2_kernel<double>, dim3(blocks), dim3(256), 0, st, a);
 }
 
-__global__ __launch_bounds__(256) void ritz_resid_kernel(const double* AX, const double* X, const double* lam,
-                                                         double* W, float* W32, long ld, long rows) {
-  long c = blockIdx.y;
-  long r = blockIdx.x * 256L + threadIdx.x;
-  if (r >= rows) return;
-  double v = AX[r + c * ld] - X[r + c * ld] * lam[c];
-  if (W) W[r + c * ld] = v;
-  if (W32) W32[r + c * ld] = (float)v;
+PPCG_DEV void ritz_body(const RitzArgs& a, unsigned wg, unsigned) {
+  const unsigned bpc = (unsigned)((a.rows + 255) / 256);
+  long c = wg / bpc;
+  long r = (long)(wg % bpc) * 256 + threadIdx.x;
+  if (r >= a.rows) return;
+  double v = a.AX[r + c * a.ld] - a.X[r + c * a.ld] * a.lam[c];
+  if (a.W) a.W[r + c * a.ld] = v;
+  if (a.W32) a.W32[r + c * a.ld] = (float)v;
+}
+__global__ __launch_bounds__(256) void ritz_kernel(RitzArgs a) { ritz_body(a, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(256) void ritz_grouped(const RitzArgs* jobs, const unsigned* start, int nj) {
+  int j = find_job(start, nj, blockIdx.x);
+  ritz_body(jobs[j], blockIdx.x - start[j], start[j + 1] - start[j]);
 }
 void launch_ritz_resid(const double* AX, const double* X, const double* lam, double* W, float* W32, long ld,
                        long rows, int ncols, hipStream_t st) {
-  if (ncols <= 0) return;
-  hipLaunchKernelGGL(ritz_resid_kernel, dim3((rows + 255) / 256, ncols), dim3(256), 0, st, AX, X, lam, W, W32, ld,
-                     rows);
+  RitzArgs a{AX, X, lam, W, W32, ld, rows, ncols};
+  unsigned blocks = ncols > 0 ? (unsigned)(((rows + 255) / 256) * ncols) : 0;
+  if (g_rec) {
+    g_rec->add(OP_RITZ, &a, sizeof(a), blocks);
+    return;
+  }
+  if (blocks == 0) return;
+  hipLaunchKernelGGL(ritz_kernel, dim3(blocks), dim3(256), 0, st, a);
+}
+
+bool launch_grouped_stencil(int kind, const void* jobs, const unsigned* start, int nj, unsigned total,
+                            hipStream_t st) {
+  const StencilArgs* sj = (const StencilArgs*)jobs;
+  switch (kind) {
+    case OP_STENCIL_F4: hipLaunchKernelGGL((stencil_grouped<float, 4>), dim3(total), dim3(256), 0, st, sj, start, nj); return true;
+    case OP_STENCIL_F2: hipLaunchKernelGGL((stencil_grouped<float, 2>), dim3(total), dim3(256), 0, st, sj, start, nj); return true;
+    case OP_STENCIL_D4: hipLaunchKernelGGL((stencil_grouped<double, 4>), dim3(total), dim3(256), 0, st, sj, start, nj); return true;
+    case OP_STENCIL_D2: hipLaunchKernelGGL((stencil_grouped<double, 2>), dim3(total), dim3(256), 0, st, sj, start, nj); return true;
+    case OP_COLNORM_D:
+      hipLaunchKernelGGL(colnorm2_grouped<double>, dim3(total), dim3(256), 0, st, (const ColnormArgs*)jobs, start, nj);
+      return true;
+    case OP_COLNORM_F:
+      hipLaunchKernelGGL(colnorm2_grouped<float>, dim3(total), dim3(256), 0, st, (const ColnormArgs*)jobs, start, nj);
+      return true;
+    case OP_RITZ:
+      hipLaunchKernelGGL(ritz_grouped, dim3(total), dim3(256), 0, st, (const RitzArgs*)jobs, start, nj);
+      return true;
+  }
+  return false;
 }
 
 }  // namespace ppcg
