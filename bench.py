@@ -111,6 +111,57 @@ def cpu_baseline(p, gpu_iters, iters):
             "sample_s": round(dt, 2), "s_per_iter": round(per_it, 3)}
 
 
+def bench_batch(args):
+    """64 independent 7-point problems of uneven size (grids 24^3..40^3,
+    k 32..256, sbsize 8, tol 1e-6, FP64): one lockstep batched solve vs the
+    same problems solved one after another."""
+    import numpy as np
+    import torch
+    from paper_1407_7506_amd import binding as B
+    from paper_1407_7506_amd import inputs as I
+
+    ps = I.batch64()[:args.nprob]
+    probs = [dict(V=torch.tensor(p.V, device="cuda"), N=p.grid.N, k=p.k,
+                  X0=torch.tensor(p.start(), device="cuda"), order=2) for p in ps]
+    hb = B.Handle("fp64", profile=True)
+    hs = B.Handle("fp64")
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        hb.solve_batched(probs, 8, 1e-6, 5)
+        for p, pr in zip(ps, probs):
+            hs.solve(pr["V"], pr["N"], p.k, 8, 1e-6, 5, pr["X0"])
+    torch.cuda.synchronize()
+    hb.reset_kernel_times()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = hb.solve_batched(probs, 8, 1e-6, 5)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / args.steps
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        seq = [hs.solve(pr["V"], pr["N"], p.k, 8, 1e-6, 5, pr["X0"]) for p, pr in zip(ps, probs)]
+    torch.cuda.synchronize()
+    ts = (time.perf_counter() - t0) / args.steps
+    err = max(float(((r[0] - s_[0]).abs().max() / s_[0].abs().max()).item()) for r, s_ in zip(res, seq))
+    kt = hb.kernel_times()
+    log(f"batched {tb:.3f} s, sequential {ts:.3f} s, speedup {ts / tb:.2f}")
+    for name, (ms, cnt, fl, by) in sorted(kt.items(), key=lambda x: -x[1][0])[:10]:
+        log(f"   {name:14s} {ms / args.steps:9.1f} ms/solve {cnt // args.steps:6d} launches")
+    out = {
+        "metric": METRIC, "value": round(tb, 4), "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(tb * 1e3, 2), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"batch64: {len(ps)} 7-point problems, grids 24^3..40^3, k 32..256, sbsize 8, "
+                               "rr_period 5, tol 1e-6, FP64, one lockstep batched solve",
+                   "nprob": len(ps), "n_total": int(sum(p.grid.n for p in ps)), "k_total": int(sum(p.k for p in ps))},
+        "sequential_s": round(ts, 4), "speedup_batched_vs_sequential": round(ts / tb, 3),
+        "batched_vs_sequential_max_err": err,
+        "iters_max": max(r[2]["iters"] for r in res), "statuses_ok": all(r[3] == "PPCG_OK" for r in res),
+        "roofline": roofline(kt, "fp64"),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,10 +172,14 @@ def main():
     ap.add_argument("--only", choices=["both", "fp64", "mixed"], default="both")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain device copy of 1 GiB (counter calibration under rocprofv3)")
+    ap.add_argument("--workload", choices=["wells48", "batch64"], default="wells48")
+    ap.add_argument("--nprob", type=int, default=64, help="problems of the batch64 workload")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch64":
+        return bench_batch(args)
 
     import numpy as np
     import torch
