@@ -13,11 +13,18 @@
  * Here A is the finite-difference Kohn-Sham operator
  *     H = -1/2 Lap_h + diag(V)
  * on a periodic N x N x N grid with spacing h (7-point or 13-point
- * Laplacian), applied matrix-free, and T = diag(H)^{-1} (Jacobi).
+ * Laplacian), applied matrix-free, and T = diag(H)^{-1} (Jacobi).  With a
+ * nonzero Bloch vector kappa the operator is complex Hermitian: the coupling
+ * from grid point r to r + a h e_d carries the phase exp(i kappa_d a h) and
+ * the one from r to r - a h e_d its conjugate (a = 1, 2), which is the gauge
+ * form of -1/2 (grad + i kappa)^2 on a periodic cell; diag(H) is unchanged.
  *
  * Conventions
  *   - grid index of point (i, j, l) is i + N*(j + N*l) (x fastest); n = N^3.
- *   - blocks are column-major n x ncols with leading dimension n, float64.
+ *   - blocks are column-major n x ncols with leading dimension n, float64
+ *     for a real operator (kappa = 0) and interleaved complex float64
+ *     (re, im pairs, 16 bytes per element, numpy complex128) for a complex
+ *     one; V, eigenvalues and every other vector are real float64.
  *   - every pointer marked "device" is a device pointer on the handle's
  *     device; the caller owns it and keeps it alive until the call returns.
  *     The library owns its workspace (allocated lazily per shape inside the
@@ -71,8 +78,8 @@ typedef struct {
   int32_t nx;           /* grid points per dimension N (n = N^3) */
   double h;             /* grid spacing */
   int32_t order;        /* 2 = 7-point Laplacian, 4 = 13-point (fourth order) */
-  double kpt[3];        /* Bloch vector; must be 0 (complex operators are not
-                           in this build) */
+  double kpt[3];        /* Bloch vector kappa (1/length); all zero = real
+                           operator, otherwise complex Hermitian blocks */
   const double* V;      /* device, n potential values */
   int32_t precond;      /* ppcg_precond; only PPCG_PRECOND_JACOBI */
 } ppcg_operator;
@@ -99,14 +106,15 @@ ppcg_status ppcg_create(ppcg_handle** out, const ppcg_options* opt, void* stream
 
 /* Solve for the k lowest eigenpairs (Algorithm 3).
  *   k         wanted pairs, 0 < k; K = k + nbuf must satisfy K <= n/4
- *   sbsize    sub-block width q of the block update (section 5.1), 1 <= q <= 16;
+ *   sbsize    sub-block width q of the block update (section 5.1), 1 <= q <= 32;
  *             K must be a multiple of q
  *   tol       relative subspace residual |HX - X(X^H H X)|_F / |X^H H X|_F
  *             over the k wanted columns (section 5.2); > 0
  *   rr_period Rayleigh-Ritz every rr_period iterations (section 5.6); >= 1
  *   X0        device, n x K start block (ld n), need not be orthonormal;
- *             NULL is an error in this build
- *   X_out     device, n x k (ld n): eigenvectors, orthonormal
+ *             NULL is an error (complex when op->kpt != 0)
+ *   X_out     device, n x k (ld n): eigenvectors, orthonormal (complex when
+ *             op->kpt != 0)
  *   lambda_out device, k: eigenvalues ascending
  *   info      may be NULL
  * On PPCG_ENOCONV the outputs hold the last Rayleigh-Ritz pairs. */
@@ -128,13 +136,15 @@ ppcg_status ppcg_solve(ppcg_handle* h, const ppcg_operator* op, int32_t k, int32
  *   dL_dV     device, n (output)
  *   max_iter  CG iteration cap (<= 0: 10000); iters (may be NULL) receives
  *             the iterations used.
- * PPCG_ENOSTATE without a successful solve.  Requires a gap between
+ * PPCG_ENOSTATE without a successful solve; PPCG_EINVAL when that solve had a
+ * complex operator (real operators only).  Requires a gap between
  * lambda_k and lambda_{k+1} (the density is not differentiable otherwise). */
 ppcg_status ppcg_grad(ppcg_handle* h, const double* g_lambda, const double* w, double* dL_dV, double tol,
                       int32_t max_iter, int32_t* iters);
 
 /* rho[r] = sum_{i<k} x_i(r)^2 for the pairs of the last successful solve
- * (device, n).  PPCG_ENOSTATE without a successful solve. */
+ * (device, n).  PPCG_ENOSTATE without a successful solve, PPCG_EINVAL after a
+ * complex one. */
 ppcg_status ppcg_density(ppcg_handle* h, double* rho);
 
 /* Columns K = k + nbuf of the start block ppcg_solve expects for this handle's
@@ -153,6 +163,8 @@ int32_t ppcg_columns(const ppcg_handle* h, int32_t k, int32_t sbsize);
  *   ops, k, X0, X_out, lambda_out: host arrays of nprob entries (the
  *                 pointers they hold are device pointers)
  *   infos, statuses: host arrays of nprob entries, may be NULL
+ * A batch holds either only real or only complex operators; a problem whose
+ * kind differs from the first valid one gets PPCG_EINVAL.
  * Returns PPCG_OK when every problem converged, else the first failing
  * problem's status (statuses[] holds each one).  The handle keeps one
  * workspace per problem index. */
@@ -161,7 +173,8 @@ ppcg_status ppcg_solve_batched(ppcg_handle* h, int32_t nprob, const ppcg_operato
                                double* const* X_out, double* const* lambda_out, ppcg_info* infos,
                                int32_t* statuses);
 
-/* Y = H X for ncols columns (device, ld n): the operator product alone. */
+/* Y = H X for ncols columns (device, ld n): the operator product alone.
+ * X and Y are complex (interleaved) when op->kpt != 0. */
 ppcg_status ppcg_apply_h(ppcg_handle* h, const ppcg_operator* op, int32_t ncols, const double* X, double* Y);
 
 /* Per-kernel accumulated device time (ms) and launch counts since the last

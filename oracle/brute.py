@@ -17,3 +17,8 @@ def lowest(V, N, h, order, k, kpt=(0.0, 0.0, 0.0)):
     H = assemble_h(V, N, h, order, kpt)
     lam, X = np.linalg.eigh(H)
     return lam[:k], X[:, :k], lam
+
+
+def lowest_values(V, N, h, order, k, kpt=(0.0, 0.0, 0.0)):
+    """The k smallest eigenvalues of H (values only, numpy.linalg.eigvalsh)."""
+    return np.linalg.eigvalsh(assemble_h(V, N, h, order, kpt))[:k]

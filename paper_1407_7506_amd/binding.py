@@ -6,9 +6,10 @@ status codes into exceptions.  It raises if libppcg.so is missing: there is
 no CPU fallback.
 
 Layout: a block is column-major n x ncols; in torch it is a (ncols, n)
-contiguous float64 CUDA tensor.  ``solve`` accepts the start block as an
-(n, K) tensor (any strides) and returns X as an (n, k) view of such a
-buffer.
+contiguous CUDA tensor, float64 for a real operator and complex128 for a
+complex one (nonzero Bloch vector ``kpt``).  ``solve`` accepts the start
+block as an (n, K) tensor (any strides) and returns X as an (n, k) view of
+such a buffer.
 """
 from __future__ import annotations
 
@@ -93,10 +94,15 @@ def lib():
     return L
 
 
-def _check_tensor(t, name, numel=None):
+def _is_complex_kpt(kpt) -> bool:
+    return any(float(c) != 0.0 for c in kpt)
+
+
+def _check_tensor(t, name, numel=None, cplx=False):
     import torch
-    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
-        raise TypeError(f"{name} must be a CUDA float64 tensor")
+    want = torch.complex128 if cplx else torch.float64
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != want:
+        raise TypeError(f"{name} must be a CUDA {str(want).replace('torch.', '')} tensor")
     if numel is not None and t.numel() != numel:
         raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
 
@@ -145,32 +151,35 @@ class Handle:
             raise ValueError("bad k or sbsize")
         return K
 
-    def apply_h(self, V, N, X, h=0.5, order=2):
-        """Y = H X for a (ncols, n) column-major block X."""
+    def apply_h(self, V, N, X, h=0.5, order=2, kpt=(0.0, 0.0, 0.0)):
+        """Y = H X for a (ncols, n) column-major block X (complex128 when kpt != 0)."""
         import torch
-        _check_tensor(X, "X")
+        _check_tensor(X, "X", cplx=_is_complex_kpt(kpt))
         X = X.contiguous()
+        if X.numel() % (N ** 3):
+            raise ValueError("X must hold whole columns of length N^3")
         ncols = X.numel() // (N ** 3)
         Y = torch.empty_like(X)
-        op = self.operator(V, N, h, order)
+        op = self.operator(V, N, h, order, kpt)
         code = self._L.ppcg_apply_h(self._h, byref(op), ncols, c_void_p(X.data_ptr()), c_void_p(Y.data_ptr()))
         if code != 0:
             raise PPCGError(code, self.error())
         return Y
 
-    def solve(self, V, N, k, sbsize, tol, rr_period, X0, h=0.5, order=2, check=True):
-        """Lowest k eigenpairs.  X0: (n, K) start block (torch CUDA float64).
+    def solve(self, V, N, k, sbsize, tol, rr_period, X0, h=0.5, order=2, check=True, kpt=(0.0, 0.0, 0.0)):
+        """Lowest k eigenpairs.  X0: (n, K) start block (torch CUDA float64, or
+        complex128 for a nonzero Bloch vector kpt).
         Returns (lam (k,), X (n, k), info dict)."""
         import torch
         n = N ** 3
-        _check_tensor(X0, "X0")
+        _check_tensor(X0, "X0", cplx=_is_complex_kpt(kpt))
         K = self.columns(k, sbsize)
         if X0.dim() != 2 or X0.shape[0] != n or X0.shape[1] != K:
             raise ValueError(f"X0 must have shape (n, K) = ({n}, {K})")
         X0cm = X0.t().contiguous()
-        Xout = torch.empty((k, n), dtype=torch.float64, device=X0.device)
+        Xout = torch.empty((k, n), dtype=X0.dtype, device=X0.device)
         lam = torch.empty(k, dtype=torch.float64, device=X0.device)
-        op = self.operator(V, N, h, order)
+        op = self.operator(V, N, h, order, kpt)
         info = Info()
         code = self._L.ppcg_solve(self._h, byref(op), int(k), int(sbsize), float(tol), int(rr_period),
                                   c_void_p(X0cm.data_ptr()), c_void_p(Xout.data_ptr()), c_void_p(lam.data_ptr()),
@@ -182,8 +191,9 @@ class Handle:
 
     def solve_batched(self, problems, sbsize, tol, rr_period, check=True):
         """Solve many independent problems in lockstep.  problems: list of
-        dicts with V (CUDA float64, N^3), N, k, X0 ((n, K) CUDA float64), and
-        optional h, order.  Returns a list of (lam, X (n, k), info, status)."""
+        dicts with V (CUDA float64, N^3), N, k, X0 ((n, K) CUDA float64, or
+        complex128 with kpt), and optional h, order, kpt.  All problems are
+        real or all complex.  Returns a list of (lam, X (n, k), info, status)."""
         import torch
         nb = len(problems)
         ops = (Operator * nb)()
@@ -200,13 +210,14 @@ class Handle:
             n = N ** 3
             K = self.columns(k, sbsize)
             X0 = p["X0"]
-            _check_tensor(X0, "X0")
+            kpt = p.get("kpt", (0.0, 0.0, 0.0))
+            _check_tensor(X0, "X0", cplx=_is_complex_kpt(kpt))
             if X0.dim() != 2 or X0.shape[0] != n or X0.shape[1] != K:
                 raise ValueError(f"problem {b}: X0 must have shape ({n}, {K})")
             X0cm = X0.t().contiguous()
-            Xo = torch.empty((k, n), dtype=torch.float64, device=X0.device)
+            Xo = torch.empty((k, n), dtype=X0.dtype, device=X0.device)
             lo = torch.empty(k, dtype=torch.float64, device=X0.device)
-            ops[b] = self.operator(p["V"], N, p.get("h", 0.5), p.get("order", 2))
+            ops[b] = self.operator(p["V"], N, p.get("h", 0.5), p.get("order", 2), kpt)
             ks[b] = k
             x0p[b] = X0cm.data_ptr()
             xop[b] = Xo.data_ptr()

@@ -1,8 +1,12 @@
 // Per-sub-block work of PPCG (Algorithm 3, steps 11-16; section 5.1):
 //   block_pencil  the 3q x 3q (2q x 2q while P is empty) projected problem
-//                 sym(S^H A S) c = theta sym(S^H S) c, S = [X_j W_j P_j],
+//                 herm(S^H A S) c = theta herm(S^H S) c, S = [X_j W_j P_j],
 //                 keeping the q lowest pairs with C^H (S^H S) C = I
-//                 (projected problem of section 2); one workgroup per block, everything in LDS
+//                 (projected problem of section 2); one workgroup per
+//                 block, everything in LDS up to nS = 48; for nS up to 96
+//                 (sub-blocks of width up to 32) the four nS x nS work
+//                 matrices live in a per-block device scratch area (L2
+//                 resident) and only the vectors stay in LDS
 //   block_update  P_j <- W_j C_W + P_j C_P ;  X_j <- X_j C_X + P_j
 // In the mixed-precision path H W and H P are float32 products, whose
 // rounding error (~1e-7 |H| |w|) would swamp the X-W coupling x^H H w =
@@ -12,26 +16,37 @@
 // W/P columns dropped, a Cholesky of the scaled Gram that drops columns
 // whose pivot falls below pivot_tol (taken in the order X, W, P), and the
 // rank indicator of Theorem 1 (C_X singular) answered by re-solving the
-// block without P (Theorem 2).
+// block without P (Theorem 2).  S is double or zdouble (Hermitian).
+#include <stdexcept>
+
 #include "common.hpp"
 #include "jacobi.hpp"
 #include "kernels.hpp"
 
 namespace ppcg {
 
-template <int NB>
+template <int NB, class S>
 PPCG_DEV void block_pencil_body(const PencilArgs& a, unsigned wg, unsigned) {
   constexpr int LD = NB + 1;
   constexpr int NT = 256;
-  __shared__ double b0[NB * LD], b1[NB * LD], b2[NB * LD], b3[NB * LD];
+  constexpr bool IN_LDS = NB <= 48;
+  static_assert(IN_LDS || 4L * NB * LD <= pencil_work_elems(), "pencil scratch too small");
+  __shared__ S shm[IN_LDS ? 4 * NB * LD : 1];
   __shared__ double Dv[NB], cs[NB + 2];
+  __shared__ S uu[NB / 2 + 1];
   __shared__ int keep[NB], acc[NB], pq[NB + 2], cnt, nacc, sing;
   const int tid = threadIdx.x;
   const int blk = (int)wg;
+  S* b0 = IN_LDS ? shm : (S*)a.work + (long)blk * pencil_work_elems();
+  S* b1 = b0 + NB * LD;
+  S* b2 = b1 + NB * LD;
+  S* b3 = b2 + NB * LD;
   const int q = a.q, nS = a.nS;
-  const double* gram = a.gram + (long)blk * a.gstride;
+  const S* gram = (const S*)a.gram + (long)blk * a.gstride;
+  const S* Gm = (const S*)a.G;
   const int ldgr = nS + (a.ax_rows ? q : 0);
   const int c0 = blk * q;
+  const S zero = from_real<S>(0.0);
   int flag = 0;
   for (int pass = 0; pass < 2; ++pass) {
     const bool allowP = (nS == 3 * q) && pass == 0;
@@ -43,31 +58,35 @@ PPCG_DEV void block_pencil_body(const PencilArgs& a, unsigned wg, unsigned) {
         // X rows of the W / P columns: (H X_j)^H W_j and (H X_j)^H P_j when available
         b0[i + j * LD] = (a.ax_rows && i < q) ? gram[(nS + i) + j * ldgr] : gram[i + (nS + j - q) * ldgr];
       } else if (i < q) {
-        b0[i + j * LD] = a.G[(c0 + i) + (long)(c0 + j) * a.ldg];
+        b0[i + j * LD] = Gm[(c0 + i) + (long)(c0 + j) * a.ldg];
       }
     }
     __syncthreads();
     for (int e = tid; e < nS * q; e += NT) {
       int j = e % q, i = q + e / q;  // fill the X columns below the X block
-      if (i < nS) b0[i + j * LD] = b0[j + i * LD];
+      if (i < nS) b0[i + j * LD] = conj_(b0[j + i * LD]);
     }
     __syncthreads();
+    // Hermitian parts
     for (int e = tid; e < nS * nS; e += NT) {
       int i = e % nS, j = e / nS;
       if (i < j) {
-        double va = 0.5 * (b0[i + j * LD] + b0[j + i * LD]);
-        double vb = 0.5 * (b1[i + j * LD] + b1[j + i * LD]);
-        b0[i + j * LD] = va; b0[j + i * LD] = va;
-        b1[i + j * LD] = vb; b1[j + i * LD] = vb;
+        S va = 0.5 * (b0[i + j * LD] + conj_(b0[j + i * LD]));
+        S vb = 0.5 * (b1[i + j * LD] + conj_(b1[j + i * LD]));
+        b0[i + j * LD] = va; b0[j + i * LD] = conj_(va);
+        b1[i + j * LD] = vb; b1[j + i * LD] = conj_(vb);
+      } else if (i == j) {
+        b0[i + i * LD] = from_real<S>(real_(b0[i + i * LD]));
+        b1[i + i * LD] = from_real<S>(real_(b1[i + i * LD]));
       }
     }
     __syncthreads();
     // 2. keep mask and scaling
     if (tid == 0) {
       double xmax = 0;
-      for (int i = 0; i < q; ++i) xmax = fmax(xmax, b1[i + i * LD]);
+      for (int i = 0; i < q; ++i) xmax = fmax(xmax, real_(b1[i + i * LD]));
       for (int i = 0; i < nS; ++i) {
-        double d = b1[i + i * LD];
+        double d = real_(b1[i + i * LD]);
         int kp = (i < q) || (d > a.drop_tol * a.drop_tol * xmax);
         if (i >= 2 * q && !allowP) kp = 0;
         if (!(d > 0)) kp = 0;
@@ -78,15 +97,15 @@ PPCG_DEV void block_pencil_body(const PencilArgs& a, unsigned wg, unsigned) {
     __syncthreads();
     for (int e = tid; e < nS * nS; e += NT) {
       int i = e % nS, j = e / nS;
-      double s = Dv[i] * Dv[j];
-      b0[i + j * LD] *= s;
-      b1[i + j * LD] *= s;
+      double sc = Dv[i] * Dv[j];
+      b0[i + j * LD] = sc * b0[i + j * LD];
+      b1[i + j * LD] = sc * b1[i + j * LD];
     }
     __syncthreads();
     // 3. greedy right-looking Cholesky of the scaled Gram (b1, in place)
     for (int c = 0; c < nS; ++c) {
       if (!keep[c]) continue;  // uniform
-      double piv = b1[c + c * LD];
+      double piv = real_(b1[c + c * LD]);
       if (!(piv >= a.pivot_tol)) {
         __syncthreads();
         if (tid == 0) keep[c] = 0;
@@ -95,13 +114,13 @@ PPCG_DEV void block_pencil_body(const PencilArgs& a, unsigned wg, unsigned) {
       }
       double lcc = sqrt(piv);
       for (int i = c + 1 + tid; i < nS; i += NT)
-        if (keep[i]) b1[i + c * LD] /= lcc;
+        if (keep[i]) b1[i + c * LD] = (1.0 / lcc) * b1[i + c * LD];
       __syncthreads();
-      if (tid == 0) b1[c + c * LD] = lcc;
+      if (tid == 0) b1[c + c * LD] = from_real<S>(lcc);
       int nr = nS - c - 1;
       for (int e = tid; e < nr * nr; e += NT) {
         int i = c + 1 + e % nr, j = c + 1 + e / nr;
-        if (i >= j && keep[i] && keep[j]) b1[i + j * LD] -= b1[i + c * LD] * b1[j + c * LD];
+        if (i >= j && keep[i] && keep[j]) b1[i + j * LD] -= b1[i + c * LD] * conj_(b1[j + c * LD]);
       }
       __syncthreads();
     }
@@ -116,41 +135,41 @@ PPCG_DEV void block_pencil_body(const PencilArgs& a, unsigned wg, unsigned) {
     if (r < q) {
       // rank failure: leave the block unchanged (C = [I; 0; 0]) and report
       flag |= 4;
-      double* C = a.C + (long)blk * a.cstride;
+      S* C = (S*)a.C + (long)blk * a.cstride;
       for (int e = tid; e < 3 * q * q; e += NT) {
         int i = e % (3 * q), t = e / (3 * q);
-        C[i + t * 3 * q] = (i == t) ? 1.0 : 0.0;
+        C[i + t * 3 * q] = from_real<S>(i == t ? 1.0 : 0.0);
       }
       break;
     }
     // 4. compact: L (b2, lower r x r) and A (b3)
     for (int e = tid; e < r * r; e += NT) {
       int x = e % r, y = e / r;
-      b2[x + y * LD] = (x >= y) ? b1[acc[x] + acc[y] * LD] : 0.0;
+      b2[x + y * LD] = (x >= y) ? b1[acc[x] + acc[y] * LD] : zero;
       b3[x + y * LD] = b0[acc[x] + acc[y] * LD];
     }
     __syncthreads();
     // 5. Linv (b1) by forward substitution, one thread per column
     for (int y = tid; y < r; y += NT) {
-      for (int x = 0; x < r; ++x) b1[x + y * LD] = 0.0;
+      for (int x = 0; x < r; ++x) b1[x + y * LD] = zero;
       for (int x = y; x < r; ++x) {
-        double s = (x == y) ? 1.0 : 0.0;
+        S s = from_real<S>(x == y ? 1.0 : 0.0);
         for (int t = y; t < x; ++t) s -= b2[x + t * LD] * b1[t + y * LD];
-        b1[x + y * LD] = s / b2[x + x * LD];
+        b1[x + y * LD] = (1.0 / real_(b2[x + x * LD])) * s;
       }
     }
     __syncthreads();
-    // 6. T = A Linv^T (b2), M = Linv T (b3)
+    // 6. T = A Linv^H (b2), M = Linv T (b3)
     for (int e = tid; e < r * r; e += NT) {
       int x = e % r, y = e / r;
-      double s = 0;
-      for (int t = 0; t <= y; ++t) s += b3[x + t * LD] * b1[y + t * LD];
+      S s = zero;
+      for (int t = 0; t <= y; ++t) s += b3[x + t * LD] * conj_(b1[y + t * LD]);
       b2[x + y * LD] = s;
     }
     __syncthreads();
     for (int e = tid; e < r * r; e += NT) {
       int x = e % r, y = e / r;
-      double s = 0;
+      S s = zero;
       for (int t = 0; t <= x; ++t) s += b1[x + t * LD] * b2[t + y * LD];
       b3[x + y * LD] = s;
     }
@@ -158,35 +177,34 @@ PPCG_DEV void block_pencil_body(const PencilArgs& a, unsigned wg, unsigned) {
     for (int e = tid; e < r * r; e += NT) {
       int x = e % r, y = e / r;
       if (x < y) {
-        double v = 0.5 * (b3[x + y * LD] + b3[y + x * LD]);
+        S v = 0.5 * (b3[x + y * LD] + conj_(b3[y + x * LD]));
         b3[x + y * LD] = v;
-        b3[y + x * LD] = v;
+        b3[y + x * LD] = conj_(v);
+      } else if (x == y) {
+        b3[x + x * LD] = from_real<S>(real_(b3[x + x * LD]));
       }
     }
     __syncthreads();
-    // 7. eigen-decomposition M = Y diag Y^T (Y in b0).  Rotations below
+    // 7. eigen-decomposition M = Y diag Y^H (Y in b0).  Rotations below
     //    jacobi_rel |M|_F are skipped: the pencil only has to give a good
     //    step, and the caller sizes jacobi_rel well below the X-W coupling
     //    (of the order of the residual) that the step has to resolve.
     {
       double fro = 0;
-      for (int e = tid; e < r * r; e += NT) {
-        double v = b3[(e % r) + (e / r) * LD];
-        fro += v * v;
-      }
+      for (int e = tid; e < r * r; e += NT) fro += abs2_(b3[(e % r) + (e / r) * LD]);
       fro = wave_sum(fro);
       if ((tid & 63) == 0) cs[tid >> 6] = fro;
       __syncthreads();
       fro = (cs[0] + cs[1]) + (cs[2] + cs[3]);
       __syncthreads();
-      lds_jacobi<NT>(b3, b0, r, LD, a.jacobi_rel * sqrt(fro), 40, cs, pq, &cnt);
+      lds_jacobi<NT, S>(b3, b0, r, LD, a.jacobi_rel * sqrt(fro), 40, cs, uu, pq, &cnt);
     }
     // 8. ascending order (ties by index): rank -> keep[] reused as sel
     for (int x = tid; x < r; x += NT) {
-      double lx = b3[x + x * LD];
+      double lx = real_(b3[x + x * LD]);
       int rk = 0;
       for (int y = 0; y < r; ++y) {
-        double ly = b3[y + y * LD];
+        double ly = real_(b3[y + y * LD]);
         rk += (ly < lx) || (ly == lx && y < x);
       }
       pq[x] = rk;  // temporarily the rank of x
@@ -194,12 +212,12 @@ PPCG_DEV void block_pencil_body(const PencilArgs& a, unsigned wg, unsigned) {
     __syncthreads();
     for (int x = tid; x < r; x += NT) keep[pq[x]] = x;
     __syncthreads();
-    // 9. C_acc = Linv^T Y[:, sel[0..q)]  (b2, r x q)
+    // 9. C_acc = Linv^H Y[:, sel[0..q)]  (b2, r x q)
     for (int e = tid; e < r * q; e += NT) {
       int x = e % r, t = e / r;
       int col = keep[t];
-      double s = 0;
-      for (int y = x; y < r; ++y) s += b1[y + x * LD] * b0[y + col * LD];
+      S s = zero;
+      for (int y = x; y < r; ++y) s += conj_(b1[y + x * LD]) * b0[y + col * LD];
       b2[x + t * LD] = s;
     }
     __syncthreads();
@@ -207,30 +225,30 @@ PPCG_DEV void block_pencil_body(const PencilArgs& a, unsigned wg, unsigned) {
     int usedP = 0;
     for (int x = 0; x < r; ++x) usedP |= (acc[x] >= 2 * q);
     if (usedP && pass == 0) {
-      // Gc = C_X^T C_X (b3, q x q); X columns are acc[0..q) when all kept
+      // Gc = C_X^H C_X (b3, q x q) over the kept X rows
       for (int e = tid; e < q * q; e += NT) {
         int u = e % q, v = e / q;
-        double s = 0;
+        S s = zero;
         for (int x = 0; x < r; ++x) {
           int i = acc[x];
           if (i >= q) break;
-          s += (Dv[i] * b2[x + u * LD]) * (Dv[i] * b2[x + v * LD]);
+          s += (Dv[i] * Dv[i]) * (conj_(b2[x + u * LD]) * b2[x + v * LD]);
         }
         b3[u + v * LD] = s;
       }
       __syncthreads();
       if (tid == 0) {
         double gmax = 0;
-        for (int u = 0; u < q; ++u) gmax = fmax(gmax, b3[u + u * LD]);
+        for (int u = 0; u < q; ++u) gmax = fmax(gmax, real_(b3[u + u * LD]));
         int bad = 0;
         // sequential Cholesky of the q x q Gram, relative pivot test
         for (int c = 0; c < q && !bad; ++c) {
-          double piv = b3[c + c * LD];
+          double piv = real_(b3[c + c * LD]);
           if (!(piv >= a.pivot_tol * gmax)) { bad = 1; break; }
           double l = sqrt(piv);
-          for (int i = c + 1; i < q; ++i) b3[i + c * LD] /= l;
+          for (int i = c + 1; i < q; ++i) b3[i + c * LD] = (1.0 / l) * b3[i + c * LD];
           for (int j = c + 1; j < q; ++j)
-            for (int i = j; i < q; ++i) b3[i + j * LD] -= b3[i + c * LD] * b3[j + c * LD];
+            for (int i = j; i < q; ++i) b3[i + j * LD] -= b3[i + c * LD] * conj_(b3[j + c * LD]);
         }
         sing = bad;
       }
@@ -242,11 +260,11 @@ PPCG_DEV void block_pencil_body(const PencilArgs& a, unsigned wg, unsigned) {
     }
     if (usedP) flag |= 1;
     // 11. write C (nS x q, ld 3q): zero rows for dropped columns
-    double* C = a.C + (long)blk * a.cstride;
+    S* C = (S*)a.C + (long)blk * a.cstride;
     const int ldc = 3 * q;
     for (int e = tid; e < ldc * q; e += NT) {
       int i = e % ldc, t = e / ldc;
-      C[i + t * ldc] = 0.0;
+      C[i + t * ldc] = zero;
     }
     __syncthreads();
     for (int e = tid; e < r * q; e += NT) {
@@ -258,38 +276,57 @@ PPCG_DEV void block_pencil_body(const PencilArgs& a, unsigned wg, unsigned) {
   }
   if (tid == 0) a.flags[blk] = flag;
 }
-template <int NB>
+
+template <int NB, class S>
 __global__ __launch_bounds__(256) void block_pencil_kernel(PencilArgs a) {
-  block_pencil_body<NB>(a, blockIdx.x, gridDim.x);
+  block_pencil_body<NB, S>(a, blockIdx.x, gridDim.x);
 }
-template <int NB>
+template <int NB, class S>
 __global__ __launch_bounds__(256) void block_pencil_grouped(const PencilArgs* jobs, const unsigned* start, int nj) {
   int j = find_job(start, nj, blockIdx.x);
-  block_pencil_body<NB>(jobs[j], blockIdx.x - start[j], start[j + 1] - start[j]);
+  block_pencil_body<NB, S>(jobs[j], blockIdx.x - start[j], start[j + 1] - start[j]);
 }
+
+static int pencil_kind(const PencilArgs& a) {
+  if (a.cplx) return a.nS <= 24 ? OP_PENCILZ24 : (a.nS <= 48 ? OP_PENCILZ48 : OP_PENCILZ96);
+  return a.nS <= 24 ? OP_PENCIL24 : (a.nS <= 48 ? OP_PENCIL48 : OP_PENCIL96);
+}
+
+#define PPCG_PENCIL_SWITCH(KERNEL, GRID, ...)                                                                   \
+  switch (kind) {                                                                                              \
+    case OP_PENCIL24: hipLaunchKernelGGL((KERNEL<24, double>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;  \
+    case OP_PENCIL48: hipLaunchKernelGGL((KERNEL<48, double>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;  \
+    case OP_PENCILZ24: hipLaunchKernelGGL((KERNEL<24, zdouble>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break; \
+    case OP_PENCILZ48: hipLaunchKernelGGL((KERNEL<48, zdouble>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break; \
+    case OP_PENCIL96: hipLaunchKernelGGL((KERNEL<96, double>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;  \
+    case OP_PENCILZ96: hipLaunchKernelGGL((KERNEL<96, zdouble>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break; \
+    default: break;                                                                                            \
+  }
 
 void launch_block_pencil(const PencilArgs& a, hipStream_t st) {
   unsigned blocks = a.nblocks > 0 ? (unsigned)a.nblocks : 0;
-  int kind = a.nS <= 24 ? OP_PENCIL24 : OP_PENCIL48;
+  if (a.nS > 96 || (a.nS > 48 && !a.work))
+    throw std::invalid_argument("block pencil: nS > 96, or nS > 48 without device scratch");
+  int kind = pencil_kind(a);
   if (g_rec) {
     g_rec->add(kind, &a, sizeof(a), blocks);
     return;
   }
   if (blocks == 0) return;
-  if (kind == OP_PENCIL24) hipLaunchKernelGGL(block_pencil_kernel<24>, dim3(blocks), dim3(256), 0, st, a);
-  else hipLaunchKernelGGL(block_pencil_kernel<48>, dim3(blocks), dim3(256), 0, st, a);
+  PPCG_PENCIL_SWITCH(block_pencil_kernel, blocks, a)
 }
 
 // ---------------------------------------------------------------------------
-template <class TW, int QM>
+// TW: storage of W/P (double, float, zdouble, zfloat); SX: X and arithmetic
+template <class TW, class SX, int QM>
 PPCG_DEV void block_update_body(const BlockUpdArgs& a, unsigned wg, unsigned nwg) {
-  __shared__ double Cs[3 * QM * QM];
+  __shared__ SX Cs[3 * QM * QM];
   const int q = a.q;
   const unsigned rtiles = (unsigned)(a.rows / 256);
   unsigned L = xcd_remap(wg, nwg);
   int blk = L / rtiles;
   long r = (long)(L % rtiles) * 256 + threadIdx.x;
-  const double* C = a.C + (long)blk * a.cstride;
+  const SX* C = (const SX*)a.C + (long)blk * a.cstride;
   const int ldc = 3 * q;
   for (int e = threadIdx.x; e < 3 * q * q; e += 256) {
     int i = e % ldc, t = e / ldc;
@@ -297,23 +334,24 @@ PPCG_DEV void block_update_body(const BlockUpdArgs& a, unsigned wg, unsigned nwg
   }
   __syncthreads();
   const long cb = (long)blk * q * a.ld;
-  double* X = a.X + cb;
+  SX* X = (SX*)a.X + cb;
   TW* W = (TW*)a.W + cb;
   TW* P = (TW*)a.P + cb;
-  double x[QM], w[QM], p[QM];
+  const SX zero = from_real<SX>(0.0);
+  SX x[QM], w[QM], p[QM];
 #pragma unroll
   for (int i = 0; i < QM; ++i) {
     if (i < q) {
       x[i] = X[r + i * a.ld];
-      w[i] = (double)W[r + i * a.ld];
-      p[i] = a.hasP ? (double)P[r + i * a.ld] : 0.0;
+      w[i] = cvt<SX, TW>(W[r + i * a.ld]);
+      p[i] = a.hasP ? cvt<SX, TW>(P[r + i * a.ld]) : zero;
     } else {
-      x[i] = w[i] = p[i] = 0.0;
+      x[i] = w[i] = p[i] = zero;
     }
   }
   for (int t = 0; t < q; ++t) {
-    const double* ct = Cs + t * 3 * QM;
-    double pn = 0, xn = 0;
+    const SX* ct = Cs + t * 3 * QM;
+    SX pn = zero, xn = zero;
 #pragma unroll
     for (int i = 0; i < QM; ++i) {
       if (i < q) {
@@ -323,25 +361,46 @@ PPCG_DEV void block_update_body(const BlockUpdArgs& a, unsigned wg, unsigned nwg
       }
     }
     xn += pn;
-    P[r + t * a.ld] = (TW)pn;
+    P[r + t * a.ld] = cvt<TW, SX>(pn);
     X[r + t * a.ld] = xn;
   }
 }
 
-template <class TW, int QM>
+template <class TW, class SX, int QM>
 __global__ __launch_bounds__(256) void block_update_kernel(BlockUpdArgs a) {
-  block_update_body<TW, QM>(a, blockIdx.x, gridDim.x);
+  block_update_body<TW, SX, QM>(a, blockIdx.x, gridDim.x);
 }
-template <class TW, int QM>
+template <class TW, class SX, int QM>
 __global__ __launch_bounds__(256) void block_update_grouped(const BlockUpdArgs* jobs, const unsigned* start, int nj) {
   int j = find_job(start, nj, blockIdx.x);
-  block_update_body<TW, QM>(jobs[j], blockIdx.x - start[j], start[j + 1] - start[j]);
+  block_update_body<TW, SX, QM>(jobs[j], blockIdx.x - start[j], start[j + 1] - start[j]);
 }
 
 static int bupd_kind(const BlockUpdArgs& a) {
-  int base = a.f32 ? OP_BUPD_F4 : OP_BUPD_D4;
+  int base = a.cplx ? (a.f32 ? OP_BUPD_C4 : OP_BUPD_Z4) : (a.f32 ? OP_BUPD_F4 : OP_BUPD_D4);
   return base + (a.q <= 4 ? 0 : a.q <= 8 ? 1 : a.q <= 16 ? 2 : 3);
 }
+
+#define PPCG_BUPD_SWITCH(KERNEL, GRID, ...)                                                                      \
+  switch (kind) {                                                                                               \
+    case OP_BUPD_D4: hipLaunchKernelGGL((KERNEL<double, double, 4>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;    \
+    case OP_BUPD_D8: hipLaunchKernelGGL((KERNEL<double, double, 8>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;    \
+    case OP_BUPD_D16: hipLaunchKernelGGL((KERNEL<double, double, 16>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;  \
+    case OP_BUPD_D32: hipLaunchKernelGGL((KERNEL<double, double, 32>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;  \
+    case OP_BUPD_F4: hipLaunchKernelGGL((KERNEL<float, double, 4>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;     \
+    case OP_BUPD_F8: hipLaunchKernelGGL((KERNEL<float, double, 8>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;     \
+    case OP_BUPD_F16: hipLaunchKernelGGL((KERNEL<float, double, 16>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;   \
+    case OP_BUPD_F32: hipLaunchKernelGGL((KERNEL<float, double, 32>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;   \
+    case OP_BUPD_Z4: hipLaunchKernelGGL((KERNEL<zdouble, zdouble, 4>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;  \
+    case OP_BUPD_Z8: hipLaunchKernelGGL((KERNEL<zdouble, zdouble, 8>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;  \
+    case OP_BUPD_Z16: hipLaunchKernelGGL((KERNEL<zdouble, zdouble, 16>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break; \
+    case OP_BUPD_Z32: hipLaunchKernelGGL((KERNEL<zdouble, zdouble, 32>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break; \
+    case OP_BUPD_C4: hipLaunchKernelGGL((KERNEL<zfloat, zdouble, 4>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;   \
+    case OP_BUPD_C8: hipLaunchKernelGGL((KERNEL<zfloat, zdouble, 8>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;   \
+    case OP_BUPD_C16: hipLaunchKernelGGL((KERNEL<zfloat, zdouble, 16>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break; \
+    case OP_BUPD_C32: hipLaunchKernelGGL((KERNEL<zfloat, zdouble, 32>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break; \
+    default: break;                                                                                             \
+  }
 
 void launch_block_update(const BlockUpdArgs& a, hipStream_t st) {
   unsigned blocks = (unsigned)((a.rows / 256) * (a.nblocks > 0 ? a.nblocks : 0));
@@ -351,40 +410,20 @@ void launch_block_update(const BlockUpdArgs& a, hipStream_t st) {
     return;
   }
   if (blocks == 0) return;
-#define PPCG_BU(T, QM) hipLaunchKernelGGL((block_update_kernel<T, QM>), dim3(blocks), dim3(256), 0, st, a)
-  switch (kind) {
-    case OP_BUPD_D4: PPCG_BU(double, 4); break;
-    case OP_BUPD_D8: PPCG_BU(double, 8); break;
-    case OP_BUPD_D16: PPCG_BU(double, 16); break;
-    case OP_BUPD_D32: PPCG_BU(double, 32); break;
-    case OP_BUPD_F4: PPCG_BU(float, 4); break;
-    case OP_BUPD_F8: PPCG_BU(float, 8); break;
-    case OP_BUPD_F16: PPCG_BU(float, 16); break;
-    case OP_BUPD_F32: PPCG_BU(float, 32); break;
-  }
-#undef PPCG_BU
+  PPCG_BUPD_SWITCH(block_update_kernel, blocks, a)
 }
 
 bool launch_grouped_block(int kind, const void* jobs, const unsigned* start, int nj, unsigned total, hipStream_t st) {
-  const BlockUpdArgs* bj = (const BlockUpdArgs*)jobs;
-#define PPCG_GBU(T, QM) hipLaunchKernelGGL((block_update_grouped<T, QM>), dim3(total), dim3(256), 0, st, bj, start, nj)
-  switch (kind) {
-    case OP_PENCIL24:
-      hipLaunchKernelGGL(block_pencil_grouped<24>, dim3(total), dim3(256), 0, st, (const PencilArgs*)jobs, start, nj);
-      return true;
-    case OP_PENCIL48:
-      hipLaunchKernelGGL(block_pencil_grouped<48>, dim3(total), dim3(256), 0, st, (const PencilArgs*)jobs, start, nj);
-      return true;
-    case OP_BUPD_D4: PPCG_GBU(double, 4); return true;
-    case OP_BUPD_D8: PPCG_GBU(double, 8); return true;
-    case OP_BUPD_D16: PPCG_GBU(double, 16); return true;
-    case OP_BUPD_D32: PPCG_GBU(double, 32); return true;
-    case OP_BUPD_F4: PPCG_GBU(float, 4); return true;
-    case OP_BUPD_F8: PPCG_GBU(float, 8); return true;
-    case OP_BUPD_F16: PPCG_GBU(float, 16); return true;
-    case OP_BUPD_F32: PPCG_GBU(float, 32); return true;
+  if (kind >= OP_PENCIL24 && kind <= OP_PENCILZ96) {
+    const PencilArgs* pj = (const PencilArgs*)jobs;
+    PPCG_PENCIL_SWITCH(block_pencil_grouped, total, pj, start, nj)
+    return true;
   }
-#undef PPCG_GBU
+  if (kind >= OP_BUPD_D4 && kind <= OP_BUPD_C32) {
+    const BlockUpdArgs* bj = (const BlockUpdArgs*)jobs;
+    PPCG_BUPD_SWITCH(block_update_grouped, total, bj, start, nj)
+    return true;
+  }
   return false;
 }
 

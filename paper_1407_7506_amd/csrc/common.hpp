@@ -11,6 +11,58 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 namespace ppcg {
 
 // ---------------------------------------------------------------------------
+// Scalars: real (double, float) or complex (cpx<double>, cpx<float>, stored
+// interleaved re, im).  The same kernel templates serve both.
+// ---------------------------------------------------------------------------
+template <class R> struct cpx {
+  R x, y;
+};
+typedef cpx<double> zdouble;
+typedef cpx<float> zfloat;
+
+template <class S> struct sc_traits { typedef S real_t; static constexpr bool cplx = false; };
+template <class R> struct sc_traits<cpx<R>> { typedef R real_t; static constexpr bool cplx = true; };
+
+template <class R> PPCG_DEV cpx<R> operator+(cpx<R> a, cpx<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <class R> PPCG_DEV cpx<R> operator-(cpx<R> a, cpx<R> b) { return {a.x - b.x, a.y - b.y}; }
+template <class R> PPCG_DEV cpx<R> operator-(cpx<R> a) { return {-a.x, -a.y}; }
+template <class R> PPCG_DEV cpx<R> operator*(cpx<R> a, cpx<R> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <class R> PPCG_DEV cpx<R> operator*(R s, cpx<R> a) { return {s * a.x, s * a.y}; }
+template <class R> PPCG_DEV cpx<R> operator*(cpx<R> a, R s) { return {s * a.x, s * a.y}; }
+template <class R> PPCG_DEV cpx<R> operator/(cpx<R> a, R s) { return {a.x / s, a.y / s}; }
+template <class R> PPCG_DEV cpx<R>& operator+=(cpx<R>& a, cpx<R> b) { a.x += b.x; a.y += b.y; return a; }
+template <class R> PPCG_DEV cpx<R>& operator-=(cpx<R>& a, cpx<R> b) { a.x -= b.x; a.y -= b.y; return a; }
+template <class R> PPCG_DEV cpx<R>& operator*=(cpx<R>& a, R s) { a.x *= s; a.y *= s; return a; }
+template <class R> PPCG_DEV cpx<R>& operator/=(cpx<R>& a, R s) { a.x /= s; a.y /= s; return a; }
+
+PPCG_DEV double conj_(double a) { return a; }
+PPCG_DEV float conj_(float a) { return a; }
+template <class R> PPCG_DEV cpx<R> conj_(cpx<R> a) { return {a.x, -a.y}; }
+PPCG_DEV double real_(double a) { return a; }
+PPCG_DEV float real_(float a) { return a; }
+template <class R> PPCG_DEV R real_(cpx<R> a) { return a.x; }
+PPCG_DEV double abs2_(double a) { return a * a; }
+PPCG_DEV float abs2_(float a) { return a * a; }
+template <class R> PPCG_DEV R abs2_(cpx<R> a) { return a.x * a.x + a.y * a.y; }
+template <class S> PPCG_DEV S from_real(typename sc_traits<S>::real_t r);
+template <> PPCG_DEV double from_real<double>(double r) { return r; }
+template <> PPCG_DEV float from_real<float>(float r) { return r; }
+template <> PPCG_DEV zdouble from_real<zdouble>(double r) { return {r, 0.0}; }
+template <> PPCG_DEV zfloat from_real<zfloat>(float r) { return {r, 0.0f}; }
+// precision conversions (double <-> float, complex <-> complex)
+template <class D, class S> PPCG_DEV D cvt(S a);
+template <> PPCG_DEV double cvt<double, double>(double a) { return a; }
+template <> PPCG_DEV double cvt<double, float>(float a) { return a; }
+template <> PPCG_DEV float cvt<float, double>(double a) { return (float)a; }
+template <> PPCG_DEV float cvt<float, float>(float a) { return a; }
+template <> PPCG_DEV zdouble cvt<zdouble, zdouble>(zdouble a) { return a; }
+template <> PPCG_DEV zdouble cvt<zdouble, zfloat>(zfloat a) { return {a.x, a.y}; }
+template <> PPCG_DEV zfloat cvt<zfloat, zdouble>(zdouble a) { return {(float)a.x, (float)a.y}; }
+template <> PPCG_DEV zfloat cvt<zfloat, zfloat>(zfloat a) { return a; }
+
+// ---------------------------------------------------------------------------
 // Workgroup index remap so that consecutive logical indices run on one XCD.
 // The dispatcher places workgroup b on XCD (b mod 8); the logical index
 // returned here groups the workgroups of each XCD into one contiguous range,

@@ -70,59 +70,69 @@ constexpr int CLD = CB + 1;
 
 struct DenseStep { double* G; double* L; double* Li; int ld, m; int* flag; };
 
+template <class S>
 PPCG_DEV void chol_diag_body(const DenseStep& a, int p) {
-  __shared__ double S[CB * CLD], I[CB * CLD];
+  __shared__ S Sm[CB * CLD], I[CB * CLD];
   __shared__ int bad;
+  const S* G = (const S*)a.G;
+  S* Lo = (S*)a.L;
+  S* Li = (S*)a.Li;
+  const S zero = from_real<S>(0.0);
   const int tid = threadIdx.x;
   const int n0 = p * CB;
   const int nb = min(CB, a.m - n0);
   for (int e = tid; e < CB * CB; e += 256) {
     int i = e % CB, j = e / CB;
-    double v = 0.0;
-    if (i < nb && j < nb) v = (i >= j) ? a.G[(n0 + i) + (long)(n0 + j) * a.ld] : a.G[(n0 + j) + (long)(n0 + i) * a.ld];
-    S[i + j * CLD] = v;
+    S v = zero;
+    if (i < nb && j < nb) v = (i >= j) ? G[(n0 + i) + (long)(n0 + j) * a.ld] : conj_(G[(n0 + j) + (long)(n0 + i) * a.ld]);
+    Sm[i + j * CLD] = v;
   }
   if (tid == 0) bad = 0;
   __syncthreads();
   for (int c = 0; c < nb; ++c) {
-    double piv = S[c + c * CLD];
+    double piv = real_(Sm[c + c * CLD]);
     double lcc = (piv > 0) ? sqrt(piv) : 1.0;
     if (!(piv > 0) && tid == 0) bad = 1;
     __syncthreads();
-    for (int i = c + 1 + tid; i < nb; i += 256) S[i + c * CLD] /= lcc;
-    if (tid == 0) S[c + c * CLD] = lcc;
+    for (int i = c + 1 + tid; i < nb; i += 256) Sm[i + c * CLD] = (1.0 / lcc) * Sm[i + c * CLD];
+    if (tid == 0) Sm[c + c * CLD] = from_real<S>(lcc);
     __syncthreads();
     int nr = nb - c - 1;
     for (int e = tid; e < nr * nr; e += 256) {
       int i = c + 1 + e % nr, j = c + 1 + e / nr;
-      if (i >= j) S[i + j * CLD] -= S[i + c * CLD] * S[j + c * CLD];
+      if (i >= j) Sm[i + j * CLD] -= Sm[i + c * CLD] * conj_(Sm[j + c * CLD]);
     }
     __syncthreads();
   }
   // inverse of the lower-triangular tile, one thread per column
   if (tid < nb) {
     int y = tid;
-    for (int x = 0; x < nb; ++x) I[x + y * CLD] = 0.0;
+    for (int x = 0; x < nb; ++x) I[x + y * CLD] = zero;
     for (int x = y; x < nb; ++x) {
-      double s = (x == y) ? 1.0 : 0.0;
-      for (int t = y; t < x; ++t) s -= S[x + t * CLD] * I[t + y * CLD];
-      I[x + y * CLD] = s / S[x + x * CLD];
+      S sum = from_real<S>(x == y ? 1.0 : 0.0);
+      for (int t = y; t < x; ++t) sum -= Sm[x + t * CLD] * I[t + y * CLD];
+      I[x + y * CLD] = (1.0 / real_(Sm[x + x * CLD])) * sum;
     }
   }
   __syncthreads();
   for (int e = tid; e < nb * nb; e += 256) {
     int i = e % nb, j = e / nb;
     long o = (n0 + i) + (long)(n0 + j) * a.ld;
-    a.L[o] = (i >= j) ? S[i + j * CLD] : 0.0;
-    a.Li[o] = (i >= j) ? I[i + j * CLD] : 0.0;
+    Lo[o] = (i >= j) ? Sm[i + j * CLD] : zero;
+    Li[o] = (i >= j) ? I[i + j * CLD] : zero;
   }
   if (tid == 0 && bad && *a.flag == 0) *a.flag = p + 1;
 }
 
-// Tiles (i, j), p < j <= i: L_ip = G_ip Li_pp^T, G_ij -= L_ip L_jp^T.
+// Tiles (i, j), p < j <= i: L_ip = G_ip Li_pp^H, G_ij -= L_ip L_jp^H.
 // The diagonal tile (i, i) stores L_ip and zeroes the upper tile (p, i).
+template <class S>
 PPCG_DEV void chol_trail_body(const DenseStep& a, int p, unsigned wg) {
-  __shared__ double Lp[CB * CLD], Ai[CB * CLD], Aj[CB * CLD];
+  __shared__ S Lp[CB * CLD], Ai[CB * CLD], Aj[CB * CLD];
+  S* G = (S*)a.G;
+  S* Lo = (S*)a.L;
+  const S* Li = (const S*)a.Li;
+  const S zero = from_real<S>(0.0);
   const int m = a.m, ld = a.ld;
   const int nbk = (m + CB - 1) / CB;
   const int span = nbk - p - 1;
@@ -133,17 +143,17 @@ PPCG_DEV void chol_trail_body(const DenseStep& a, int p, unsigned wg) {
   const int nbp = min(CB, m - n0), nbi = min(CB, m - ni0), nbj = min(CB, m - nj0);
   for (int e = tid; e < CB * CB; e += 256) {
     int x = e % CB, y = e / CB;
-    Lp[x + y * CLD] = (x < nbp && y < nbp) ? a.Li[(n0 + x) + (long)(n0 + y) * ld] : 0.0;
-    Ai[x + y * CLD] = (x < nbi && y < nbp) ? a.G[(ni0 + x) + (long)(n0 + y) * ld] : 0.0;
-    Aj[x + y * CLD] = (x < nbj && y < nbp) ? a.G[(nj0 + x) + (long)(n0 + y) * ld] : 0.0;
+    Lp[x + y * CLD] = (x < nbp && y < nbp) ? Li[(n0 + x) + (long)(n0 + y) * ld] : zero;
+    Ai[x + y * CLD] = (x < nbi && y < nbp) ? G[(ni0 + x) + (long)(n0 + y) * ld] : zero;
+    Aj[x + y * CLD] = (x < nbj && y < nbp) ? G[(nj0 + x) + (long)(n0 + y) * ld] : zero;
   }
   __syncthreads();
-  double li[4], lj[4];
+  S li[4], lj[4];
   for (int s = 0; s < 4; ++s) {
     int e = tid + 256 * s, x = e % CB, y = e / CB;
-    double a1 = 0, a2 = 0;
+    S a1 = zero, a2 = zero;
     for (int t = 0; t <= y; ++t) {
-      double lv = Lp[y + t * CLD];
+      S lv = conj_(Lp[y + t * CLD]);
       a1 += Ai[x + t * CLD] * lv;
       a2 += Aj[x + t * CLD] * lv;
     }
@@ -160,39 +170,43 @@ PPCG_DEV void chol_trail_body(const DenseStep& a, int p, unsigned wg) {
   for (int s = 0; s < 4; ++s) {
     int e = tid + 256 * s, x = e % CB, y = e / CB;
     if (x < nbi && y < nbj && (i != j || x >= y)) {
-      double acc = 0;
-      for (int t = 0; t < CB; ++t) acc += Ai[x + t * CLD] * Aj[y + t * CLD];
-      a.G[(ni0 + x) + (long)(nj0 + y) * ld] -= acc;
+      S acc = zero;
+      for (int t = 0; t < CB; ++t) acc += Ai[x + t * CLD] * conj_(Aj[y + t * CLD]);
+      G[(ni0 + x) + (long)(nj0 + y) * ld] -= acc;
     }
     if (i == j && x < nbi && y < nbp) {
-      a.L[(ni0 + x) + (long)(n0 + y) * ld] = Ai[x + y * CLD];
-      a.L[(n0 + y) + (long)(ni0 + x) * ld] = 0.0;
+      Lo[(ni0 + x) + (long)(n0 + y) * ld] = Ai[x + y * CLD];
+      Lo[(n0 + y) + (long)(ni0 + x) * ld] = zero;
     }
   }
 }
 
 // Off-diagonal tiles of L^{-1} along block diagonal d:
 // Li_ij = -Li_ii sum_{t=j}^{i-1} L_it Li_tj, with i = j + d; zeroes tile (j, i).
+template <class S>
 PPCG_DEV void trinv_body(const DenseStep& a, int d, unsigned wg) {
-  __shared__ double A[CB * CLD], B[CB * CLD], S[CB * CLD];
+  __shared__ S A[CB * CLD], B[CB * CLD], Sm[CB * CLD];
+  const S* L = (const S*)a.L;
+  S* Li = (S*)a.Li;
+  const S zero = from_real<S>(0.0);
   const int m = a.m, ld = a.ld;
   const int j = (int)wg, i = j + d;
   const int tid = threadIdx.x;
   const int ni0 = i * CB, nj0 = j * CB;
   const int nbi = min(CB, m - ni0), nbj = min(CB, m - nj0);
-  double acc[4] = {0, 0, 0, 0};
+  S acc[4] = {zero, zero, zero, zero};
   for (int t = j; t < i; ++t) {
     const int nt0 = t * CB, nbt = min(CB, m - nt0);
     __syncthreads();
     for (int e = tid; e < CB * CB; e += 256) {
       int x = e % CB, y = e / CB;
-      A[x + y * CLD] = (x < nbi && y < nbt) ? a.L[(ni0 + x) + (long)(nt0 + y) * ld] : 0.0;
-      B[x + y * CLD] = (x < nbt && y < nbj) ? a.Li[(nt0 + x) + (long)(nj0 + y) * ld] : 0.0;
+      A[x + y * CLD] = (x < nbi && y < nbt) ? L[(ni0 + x) + (long)(nt0 + y) * ld] : zero;
+      B[x + y * CLD] = (x < nbt && y < nbj) ? Li[(nt0 + x) + (long)(nj0 + y) * ld] : zero;
     }
     __syncthreads();
     for (int s = 0; s < 4; ++s) {
       int e = tid + 256 * s, x = e % CB, y = e / CB;
-      double v = 0;
+      S v = zero;
       for (int u = 0; u < CB; ++u) v += A[x + u * CLD] * B[u + y * CLD];
       acc[s] += v;
     }
@@ -200,37 +214,39 @@ PPCG_DEV void trinv_body(const DenseStep& a, int d, unsigned wg) {
   __syncthreads();
   for (int s = 0; s < 4; ++s) {
     int e = tid + 256 * s, x = e % CB, y = e / CB;
-    S[x + y * CLD] = acc[s];
+    Sm[x + y * CLD] = acc[s];
   }
   for (int e = tid; e < CB * CB; e += 256) {
     int x = e % CB, y = e / CB;
-    A[x + y * CLD] = (x < nbi && y < nbi) ? a.Li[(ni0 + x) + (long)(ni0 + y) * ld] : 0.0;
+    A[x + y * CLD] = (x < nbi && y < nbi) ? Li[(ni0 + x) + (long)(ni0 + y) * ld] : zero;
   }
   __syncthreads();
   for (int s = 0; s < 4; ++s) {
     int e = tid + 256 * s, x = e % CB, y = e / CB;
     if (x < nbi && y < nbj) {
-      double v = 0;
-      for (int u = 0; u <= x; ++u) v += A[x + u * CLD] * S[u + y * CLD];
-      a.Li[(ni0 + x) + (long)(nj0 + y) * ld] = -v;
-      a.Li[(nj0 + y) + (long)(ni0 + x) * ld] = 0.0;
+      S v = zero;
+      for (int u = 0; u <= x; ++u) v += A[x + u * CLD] * Sm[u + y * CLD];
+      Li[(ni0 + x) + (long)(nj0 + y) * ld] = -v;
+      Li[(nj0 + y) + (long)(ni0 + x) * ld] = zero;
     }
   }
 }
 
 // step: 0 = diagonal tile p, 1 = trailing update after p, 2 = inverse diagonal p
+template <class S>
 __global__ __launch_bounds__(256) void chol_step_grouped(const DenseStep* jobs, const unsigned* start, int nj,
                                                          int step, int p) {
   int j = find_job(start, nj, blockIdx.x);
   unsigned wg = blockIdx.x - start[j];
-  if (step == 0) chol_diag_body(jobs[j], p);
-  else if (step == 1) chol_trail_body(jobs[j], p, wg);
-  else trinv_body(jobs[j], p, wg);
+  if (step == 0) chol_diag_body<S>(jobs[j], p);
+  else if (step == 1) chol_trail_body<S>(jobs[j], p, wg);
+  else trinv_body<S>(jobs[j], p, wg);
 }
 
 void chol_inverse_grouped(const std::vector<CholArgs>& jobs, Stage& stage, hipStream_t st) {
   const int nj = (int)jobs.size();
   if (nj == 0) return;
+  const bool cplx = jobs[0].cplx;
   std::vector<DenseStep> ds(nj);
   int P = 0;
   for (int j = 0; j < nj; ++j) {
@@ -266,26 +282,37 @@ void chol_inverse_grouped(const std::vector<CholArgs>& jobs, Stage& stage, hipSt
   uint8_t* dev = (uint8_t*)stage.upload(buf.data(), buf.size(), st);
   const DenseStep* dj = (const DenseStep*)dev;
   const unsigned* sd = (const unsigned*)(dev + jb);
-  for (const L& l : ls)
-    hipLaunchKernelGGL(chol_step_grouped, dim3(l.tot), dim3(256), 0, st, dj, sd + l.off, nj, l.step, l.p);
+  for (const L& l : ls) {
+    if (cplx) hipLaunchKernelGGL(chol_step_grouped<zdouble>, dim3(l.tot), dim3(256), 0, st, dj, sd + l.off, nj, l.step, l.p);
+    else hipLaunchKernelGGL(chol_step_grouped<double>, dim3(l.tot), dim3(256), 0, st, dj, sd + l.off, nj, l.step, l.p);
+  }
 }
 
 // ---------------------------------------------------------------------------
 // small element-wise kernels (direct and grouped)
 // ---------------------------------------------------------------------------
 PPCG_DEV void transpose_body(const TransposeArgs& a, unsigned wg, unsigned) {
-  __shared__ double t[32][33];
+  __shared__ double t[32][33], ti[32][33];
   const unsigned gx = (a.m + 31) / 32;
+  const int nc = a.cplx ? 2 : 1;
   int bx = (wg % gx) * 32, by = (wg / gx) * 32;
   int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
   for (int k = ty; k < 32; k += 8) {
     int r = bx + tx, c = by + k;
-    if (r < a.m && c < a.n) t[k][tx] = a.src[r + (long)c * a.lds];
+    if (r < a.m && c < a.n) {
+      long o = (r + (long)c * a.lds) * nc;
+      t[k][tx] = a.src[o];
+      if (a.cplx) ti[k][tx] = -a.src[o + 1];
+    }
   }
   __syncthreads();
   for (int k = ty; k < 32; k += 8) {
     int r = by + tx, c = bx + k;  // dst is n x m
-    if (r < a.n && c < a.m) a.dst[r + (long)c * a.ldd] = t[tx][k];
+    if (r < a.n && c < a.m) {
+      long o = (r + (long)c * a.ldd) * nc;
+      a.dst[o] = t[tx][k];
+      if (a.cplx) a.dst[o + 1] = ti[tx][k];
+    }
   }
 }
 PPCG_DEV void fill_body(const FillArgs& a, unsigned wg, unsigned) {
@@ -296,23 +323,36 @@ PPCG_DEV void set_diag_body(const SetDiagArgs& a, unsigned wg, unsigned) {
   long e = wg * 256L + threadIdx.x;
   if (e >= (long)a.m * a.m) return;
   int i = e % a.m, j = e / a.m;
-  a.G[i + (long)j * a.ld] = (i == j) ? a.lam[i] : 0.0;
+  const int nc = a.cplx ? 2 : 1;
+  long o = (i + (long)j * a.ld) * nc;
+  a.G[o] = (i == j) ? a.lam[i] : 0.0;
+  if (a.cplx) a.G[o + 1] = 0.0;
 }
 PPCG_DEV void symm_body(const SymmArgs& a, unsigned wg, unsigned) {
   long e = wg * 256L + threadIdx.x;
   if (e >= (long)a.m * a.m) return;
   int i = e % a.m, j = e / a.m;
+  const int nc = a.cplx ? 2 : 1;
+  long u = (i + (long)j * a.ld) * nc, l = (j + (long)i * a.ld) * nc;
   if (i < j) {
-    double v = 0.5 * (a.G[i + (long)j * a.ld] + a.G[j + (long)i * a.ld]);
-    a.G[i + (long)j * a.ld] = v;
-    a.G[j + (long)i * a.ld] = v;
+    double v = 0.5 * (a.G[u] + a.G[l]);
+    a.G[u] = v;
+    a.G[l] = v;
+    if (a.cplx) {
+      double w = 0.5 * (a.G[u + 1] - a.G[l + 1]);
+      a.G[u + 1] = w;
+      a.G[l + 1] = -w;
+    }
+  } else if (i == j && a.cplx) {
+    a.G[u + 1] = 0.0;
   }
 }
 // out[j] = sum_{i < nw} G[i, j]^2 for j < nw (one workgroup per column)
 PPCG_DEV void frob2_body(const Frob2Args& a, unsigned wg, unsigned) {
-  const double* g = a.G + (long)wg * a.ld;
+  const int nc = a.cplx ? 2 : 1;
+  const double* g = a.G + (long)wg * a.ld * nc;
   double s = 0;
-  for (int i = threadIdx.x; i < a.nw; i += 256) s += g[i] * g[i];
+  for (int i = threadIdx.x; i < a.nw * nc; i += 256) s += g[i] * g[i];
   __shared__ double red[4];
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
@@ -321,10 +361,13 @@ PPCG_DEV void frob2_body(const Frob2Args& a, unsigned wg, unsigned) {
 }
 PPCG_DEV void orth_body(const OrthArgs& a, unsigned, unsigned) {
   double s = 0;
+  const int nc = a.cplx ? 2 : 1;
   for (long e = threadIdx.x; e < (long)a.k * a.k; e += 256) {
     long i = e % a.k, j = e / a.k;
-    double v = a.G[i + j * a.ld] - (i == j ? 1.0 : 0.0);
+    long o = (i + j * a.ld) * nc;
+    double v = a.G[o] - (i == j ? 1.0 : 0.0);
     s += v * v;
+    if (a.cplx) s += a.G[o + 1] * a.G[o + 1];
   }
   __shared__ double red[4];
   s = wave_sum(s);
@@ -367,30 +410,30 @@ static void simple_launch(int kind, void (*k)(A), const A& a, unsigned blocks, h
   hipLaunchKernelGGL(k, dim3(blocks), dim3(256), 0, st, a);
 }
 
-void launch_transpose(const double* src, int lds, double* dst, int ldd, int m, int n, hipStream_t st) {
-  TransposeArgs a{src, lds, dst, ldd, m, n};
+void launch_transpose(const double* src, int lds, double* dst, int ldd, int m, int n, int cplx, hipStream_t st) {
+  TransposeArgs a{src, lds, dst, ldd, m, n, cplx};
   simple_launch(OP_TRANSPOSE, transpose_kernel, a, (unsigned)(((m + 31) / 32) * ((n + 31) / 32)), st);
 }
 void launch_fill(double* p, long count, double v, hipStream_t st) {
   FillArgs a{p, count, v};
   simple_launch(OP_FILL, fill_kernel, a, (unsigned)(count > 0 ? (count + 255) / 256 : 0), st);
 }
-void launch_set_diag(double* G, int ld, int m, const double* lam, hipStream_t st) {
-  SetDiagArgs a{G, ld, m, lam};
+void launch_set_diag(double* G, int ld, int m, const double* lam, int cplx, hipStream_t st) {
+  SetDiagArgs a{G, ld, m, lam, cplx};
   long t = (long)m * m;
   simple_launch(OP_SETDIAG, set_diag_kernel, a, (unsigned)((t + 255) / 256), st);
 }
-void launch_symmetrize(double* G, int ld, int m, hipStream_t st) {
-  SymmArgs a{G, ld, m};
+void launch_symmetrize(double* G, int ld, int m, int cplx, hipStream_t st) {
+  SymmArgs a{G, ld, m, cplx};
   long t = (long)m * m;
   simple_launch(OP_SYMM, symm_kernel, a, (unsigned)((t + 255) / 256), st);
 }
-void launch_frob2_sub(const double* G, int ld, int nw, double* out, hipStream_t st) {
-  Frob2Args a{G, ld, nw, out};
+void launch_frob2_sub(const double* G, int ld, int nw, double* out, int cplx, hipStream_t st) {
+  Frob2Args a{G, ld, nw, out, cplx};
   simple_launch(OP_FROB2, frob2_kernel, a, (unsigned)(nw > 0 ? nw : 0), st);
 }
-void launch_orth_err2(const double* G, int ld, int k, double* out, hipStream_t st) {
-  OrthArgs a{G, ld, k, out};
+void launch_orth_err2(const double* G, int ld, int k, double* out, int cplx, hipStream_t st) {
+  OrthArgs a{G, ld, k, out, cplx};
   simple_launch(OP_ORTH, orth_kernel, a, 1u, st);
 }
 void launch_zero_int(int* p, int n, hipStream_t st) {
@@ -445,7 +488,7 @@ struct EigDev {
   double* V;
   int ldv;
   double* lam;
-  double* Q;       // np x J2 x J2
+  double* Q;       // np x J2 x J2 scalars
   double* Vt;      // m x m accumulated rotations
   double* tiny;
   int* flags;      // np
@@ -459,6 +502,7 @@ static EigDev carve(const EigJob& j, int* counter) {
   int nblk = (j.m + JB - 1) / JB;
   int nbe = nblk + (nblk & 1);
   int np = nbe / 2;
+  const size_t es = j.cplx ? 16 : 8;
   char* p = (char*)j.work;
   EigDev w{};
   w.M = j.M;
@@ -467,8 +511,8 @@ static EigDev carve(const EigJob& j, int* counter) {
   w.V = j.V;
   w.ldv = j.ldv;
   w.lam = j.lam;
-  w.Q = (double*)p; p += sizeof(double) * np * J2 * J2;
-  w.Vt = (double*)p; p += sizeof(double) * (size_t)j.m * j.m;
+  w.Q = (double*)p; p += es * np * J2 * J2;
+  w.Vt = (double*)p; p += es * (size_t)j.m * j.m;
   w.tiny = (double*)p; p += 256;
   w.flags = (int*)p; p += sizeof(int) * ((np + 63) / 64 * 64);
   w.rank = (int*)p;
@@ -478,11 +522,12 @@ static EigDev carve(const EigJob& j, int* counter) {
   w.np = np;
   return w;
 }
-size_t eig_workspace_bytes(int m) {
+size_t eig_workspace_bytes(int m, int cplx) {
   int nblk = (m + JB - 1) / JB;
   int np = (nblk + 1) / 2;
-  return sizeof(double) * (size_t)np * J2 * J2 + sizeof(double) * (size_t)m * m + 256 +
-         sizeof(int) * ((np + 63) / 64 * 64) + sizeof(int) * (size_t)m + 256;
+  const size_t es = cplx ? 16 : 8;
+  return es * (size_t)np * J2 * J2 + es * (size_t)m * m + 256 + sizeof(int) * ((np + 63) / 64 * 64) +
+         sizeof(int) * (size_t)m + 256;
 }
 
 PPCG_DEV void pair_of(const EigDev& a, int t, int round, int& nI, int& nJ, int& i0, int& j0) {
@@ -496,15 +541,15 @@ PPCG_DEV void pair_of(const EigDev& a, int t, int round, int& nI, int& nJ, int& 
 }
 
 // step kernels; `round` is shared by all jobs of a launch
-PPCG_DEV void bj_init_body(const EigDev& a, unsigned wg) {  // Vt = I; tiny; (counter zeroed by host)
+template <class S>
+PPCG_DEV void bj_init_body(const EigDev& a, unsigned wg) {  // Vt = I; tiny (counter zeroed by the host)
   long mm = (long)a.m * a.m;
-  for (long e = wg * 256L + threadIdx.x; e < mm; e += 256L * 64) a.Vt[e] = ((e % a.m) == (e / a.m)) ? 1.0 : 0.0;
+  S* Vt = (S*)a.Vt;
+  const S* M = (const S*)a.M;
+  for (long e = wg * 256L + threadIdx.x; e < mm; e += 256L * 64) Vt[e] = from_real<S>(((e % a.m) == (e / a.m)) ? 1.0 : 0.0);
   if (wg == 0) {
     double s = 0;
-    for (long e = threadIdx.x; e < mm; e += 256) {
-      double v = a.M[(e % a.m) + (e / a.m) * a.ld];
-      s += v * v;
-    }
+    for (long e = threadIdx.x; e < mm; e += 256) s += abs2_(M[(e % a.m) + (e / a.m) * a.ld]);
     __shared__ double red[4];
     s = wave_sum(s);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
@@ -513,12 +558,15 @@ PPCG_DEV void bj_init_body(const EigDev& a, unsigned wg) {  // Vt = I; tiny; (co
   }
 }
 
+template <class S>
 PPCG_DEV void bj_pair_body(const EigDev& a, int round, unsigned t) {
-  __shared__ double S[J2 * JLD], Q[J2 * JLD];
+  __shared__ S Sm[J2 * JLD], Qs[J2 * JLD];
   __shared__ double cs[J2 + 2];
+  __shared__ S uu[J2 / 2 + 1];
   __shared__ int pq[J2 + 2], cnt, any;
+  const S* M = (const S*)a.M;
   const int tid = threadIdx.x;
-  if (round >= a.nbe - 1 && !(a.nbe == 1 && round == 0)) return;
+  if (round >= a.nbe - 1) return;
   int nI, nJ, i0, j0;
   pair_of(a, t, round, nI, nJ, i0, j0);
   const int n2 = nI + nJ;
@@ -528,29 +576,30 @@ PPCG_DEV void bj_pair_body(const EigDev& a, int round, unsigned t) {
   __syncthreads();
   for (int e = tid; e < n2 * n2; e += 256) {
     int x = e % n2, y = e / n2;
-    double v = a.M[gidx(x) + (long)gidx(y) * a.ld];
-    S[x + y * JLD] = v;
-    if (x != y && fabs(v) > tiny) any = 1;
+    S v = M[gidx(x) + (long)gidx(y) * a.ld];
+    Sm[x + y * JLD] = v;
+    if (x != y && sqrt(abs2_(v)) > tiny) any = 1;
   }
   __syncthreads();
   if (!any) {
     if (tid == 0) a.flags[t] = 0;
     return;
   }
-  lds_jacobi<256>(S, Q, n2, JLD, tiny, 40, cs, pq, &cnt);
-  double* Qg = a.Q + (long)t * J2 * J2;
-  for (int e = tid; e < n2 * n2; e += 256) Qg[(e % n2) + (e / n2) * J2] = Q[(e % n2) + (e / n2) * JLD];
+  lds_jacobi<256, S>(Sm, Qs, n2, JLD, tiny, 40, cs, uu, pq, &cnt);
+  S* Qg = (S*)a.Q + (long)t * J2 * J2;
+  for (int e = tid; e < n2 * n2; e += 256) Qg[(e % n2) + (e / n2) * J2] = Qs[(e % n2) + (e / n2) * JLD];
   if (tid == 0) {
     a.flags[t] = 1;
     atomicAdd(a.counter, 1);
   }
 }
 
-// which = 0: rows of the pair, M[rows, chunk] <- Q^T M[rows, chunk]
+// which = 0: rows of the pair, M[rows, chunk] <- Q^H M[rows, chunk]
 // which = 1: columns of the pair for M and Vt, A[chunk, cols] <- A[chunk, cols] Q
+template <class S>
 PPCG_DEV void bj_apply_body(const EigDev& a, int round, unsigned wg, int which) {
-  __shared__ double Q[J2 * JLD], R[64 * (J2 + 1)];
-  if (round >= a.nbe - 1 && !(a.nbe == 1 && round == 0)) return;
+  __shared__ S Qs[J2 * JLD], R[64 * (J2 + 1)];
+  if (round >= a.nbe - 1) return;
   const int t = (int)(wg % a.np);
   const int chunk = (int)(wg / a.np);
   if (!a.flags[t]) return;
@@ -559,28 +608,30 @@ PPCG_DEV void bj_apply_body(const EigDev& a, int round, unsigned wg, int which) 
   pair_of(a, t, round, nI, nJ, i0, j0);
   const int n2 = nI + nJ;
   auto gidx = [&](int x) { return x < nI ? i0 + x : j0 + (x - nI); };
-  const double* Qg = a.Q + (long)t * J2 * J2;
-  for (int e = tid; e < n2 * n2; e += 256) Q[(e % n2) + (e / n2) * JLD] = Qg[(e % n2) + (e / n2) * J2];
+  const S* Qg = (const S*)a.Q + (long)t * J2 * J2;
+  const S zero = from_real<S>(0.0);
+  for (int e = tid; e < n2 * n2; e += 256) Qs[(e % n2) + (e / n2) * JLD] = Qg[(e % n2) + (e / n2) * J2];
   const int c0 = chunk * 64;
   const int nc = min(64, a.m - c0);
   constexpr int RLD = J2 + 1;
   if (which == 0) {
+    S* M = (S*)a.M;
     __syncthreads();
     for (int e = tid; e < n2 * nc; e += 256) {
       int x = e % n2, c = e / n2;
-      R[x + c * RLD] = a.M[gidx(x) + (long)(c0 + c) * a.ld];
+      R[x + c * RLD] = M[gidx(x) + (long)(c0 + c) * a.ld];
     }
     __syncthreads();
     for (int e = tid; e < n2 * nc; e += 256) {
       int x = e % n2, c = e / n2;
-      double s = 0;
-      for (int u = 0; u < n2; ++u) s += Q[u + x * JLD] * R[u + c * RLD];
-      a.M[gidx(x) + (long)(c0 + c) * a.ld] = s;
+      S s = zero;
+      for (int u = 0; u < n2; ++u) s += conj_(Qs[u + x * JLD]) * R[u + c * RLD];
+      M[gidx(x) + (long)(c0 + c) * a.ld] = s;
     }
     return;
   }
   for (int w = 0; w < 2; ++w) {
-    double* A = w ? a.Vt : a.M;
+    S* A = w ? (S*)a.Vt : (S*)a.M;
     const int lda = w ? a.m : a.ld;
     __syncthreads();
     for (int e = tid; e < nc * n2; e += 256) {
@@ -590,46 +641,51 @@ PPCG_DEV void bj_apply_body(const EigDev& a, int round, unsigned wg, int which) 
     __syncthreads();
     for (int e = tid; e < nc * n2; e += 256) {
       int r = e % nc, x = e / nc;
-      double s = 0;
-      for (int u = 0; u < n2; ++u) s += R[u + r * RLD] * Q[u + x * JLD];
+      S s = zero;
+      for (int u = 0; u < n2; ++u) s += R[u + r * RLD] * Qs[u + x * JLD];
       A[(c0 + r) + (long)gidx(x) * lda] = s;
     }
   }
 }
 
-// ranks of the diagonal (ascending, ties by index) -> lam; then Vt columns gathered into V
+// ranks of the (real) diagonal (ascending, ties by index) -> lam; then Vt
+// columns gathered into V
+template <class S>
 PPCG_DEV void bj_rank_body(const EigDev& a) {
+  const S* M = (const S*)a.M;
   for (int x = threadIdx.x; x < a.m; x += 256) {
-    double lx = a.M[x + (long)x * a.ld];
+    double lx = real_(M[x + (long)x * a.ld]);
     int rk = 0;
     for (int y = 0; y < a.m; ++y) {
-      double ly = a.M[y + (long)y * a.ld];
+      double ly = real_(M[y + (long)y * a.ld]);
       rk += (ly < lx) || (ly == lx && y < x);
     }
     a.rank[x] = rk;
     a.lam[rk] = lx;
   }
 }
+template <class S>
 PPCG_DEV void bj_gather_body(const EigDev& a, unsigned wg) {
   long e = wg * 256L + threadIdx.x;
   if (e >= (long)a.m * a.m) return;
   int i = e % a.m, j = e / a.m;
-  a.V[i + (long)a.rank[j] * a.ldv] = a.Vt[i + (long)j * a.m];
+  ((S*)a.V)[i + (long)a.rank[j] * a.ldv] = ((const S*)a.Vt)[i + (long)j * a.m];
 }
 
 // step: 0 init, 1 pair, 2 rows, 3 cols, 4 rank, 5 gather
+template <class S>
 __global__ __launch_bounds__(256) void bj_grouped(const EigDev* jobs, const unsigned* start, int nj, int step,
                                                   int round) {
   int j = find_job(start, nj, blockIdx.x);
   unsigned wg = blockIdx.x - start[j];
   const EigDev& a = jobs[j];
   switch (step) {
-    case 0: bj_init_body(a, wg); break;
-    case 1: bj_pair_body(a, round, wg); break;
-    case 2: bj_apply_body(a, round, wg, 0); break;
-    case 3: bj_apply_body(a, round, wg, 1); break;
-    case 4: bj_rank_body(a); break;
-    case 5: bj_gather_body(a, wg); break;
+    case 0: bj_init_body<S>(a, wg); break;
+    case 1: bj_pair_body<S>(a, round, wg); break;
+    case 2: bj_apply_body<S>(a, round, wg, 0); break;
+    case 3: bj_apply_body<S>(a, round, wg, 1); break;
+    case 4: bj_rank_body<S>(a); break;
+    case 5: bj_gather_body<S>(a, wg); break;
   }
 }
 
@@ -637,13 +693,13 @@ int block_jacobi_eig_grouped(const std::vector<EigJob>& jobs, Stage& stage, int*
                              hipStream_t st) {
   const int nj = (int)jobs.size();
   if (nj == 0) return 0;
+  const bool cplx = jobs[0].cplx;
   std::vector<EigDev> ed(nj);
   int maxr = 1;
   for (int j = 0; j < nj; ++j) {
     ed[j] = carve(jobs[j], dev_counter);
     maxr = std::max(maxr, ed[j].nbe - 1);
   }
-
   // start arrays for the six step shapes
   auto wgs = [&](int step, const EigDev& a) -> unsigned {
     long mm = (long)a.m * a.m;
@@ -676,7 +732,9 @@ int block_jacobi_eig_grouped(const std::vector<EigJob>& jobs, Stage& stage, int*
   const EigDev* dj = (const EigDev*)dev;
   for (int step = 0; step < 6; ++step) sd[step] = (const unsigned*)(dev + jb) + step * (nj + 1);
   auto run = [&](int step, int round) {
-    if (tot[step]) hipLaunchKernelGGL(bj_grouped, dim3(tot[step]), dim3(256), 0, st, dj, sd[step], nj, step, round);
+    if (!tot[step]) return;
+    if (cplx) hipLaunchKernelGGL(bj_grouped<zdouble>, dim3(tot[step]), dim3(256), 0, st, dj, sd[step], nj, step, round);
+    else hipLaunchKernelGGL(bj_grouped<double>, dim3(tot[step]), dim3(256), 0, st, dj, sd[step], nj, step, round);
   };
   run(0, 0);
   int sweeps = 0;

@@ -44,6 +44,7 @@ struct GramArgs {
   long job_col_off;   // per-job element offset added to all column pointers
   int njobs;          // strided jobs (blocks) inside this gram
   int site;           // call site (selects a distinct kernel symbol for profiling)
+  int cplx;           // complex operands (f32 segments then mean complex float)
 };
 
 struct ReduceArgs {
@@ -56,6 +57,7 @@ struct ReduceArgs {
   long dst_job_stride;
   double alpha, beta;
   int upper_only;
+  int cplx;          // complex entries; the mirrored entry of upper_only is conjugated
 };
 
 struct UpdateArgs {
@@ -76,6 +78,7 @@ struct UpdateArgs {
   int c0_keep;     // 1: do not overwrite C0 (only the float copy C32 is written)
   int tiles_j, tiles_r;
   int site;        // call site (selects a distinct kernel symbol for profiling)
+  int cplx;        // complex A, B, C (C32 then complex float)
 };
 
 // stencil: Y = H X on an N^3 periodic grid (7- or 13-point), columns [0, ncols)
@@ -88,9 +91,11 @@ struct StencilArgs {
   int order;
   double c0;          // 3 w0 / h^2
   double w1, w2;      // off-diagonal weights / h^2
-  const void* V;      // potential (same precision as X)
+  const void* V;      // potential (real, same precision as X)
   int f32;
   const double* shift;  // optional per-column shift: Y[:, j] -= shift[j] X[:, j] (float64 only)
+  int cplx;           // complex X, Y (interleaved); Bloch phases below
+  double ph[3][2][2]; // ph[d][a-1] = exp(i kappa_d a h) as (re, im), a = 1, 2
 };
 
 // block pencils (steps 12-13): one workgroup per sub-block
@@ -108,7 +113,12 @@ struct PencilArgs {
   double drop_tol, pivot_tol;
   double jacobi_rel;    // rotations below jacobi_rel |M|_F are skipped
   int nblocks;
+  int cplx;             // complex Hermitian pencils (gram, G and C complex)
+  void* work;           // nS > 48 only: per block 4 * 96 * 97 scalars of device scratch for the
+                        // pencil matrices (too large for LDS), stride pencil_work_elems()
 };
+// scalars of device scratch one block pencil with nS > 48 uses
+constexpr long pencil_work_elems() { return 4L * 96 * 97; }
 
 // block update (steps 14-15): P_j <- W_j C_W + P_j C_P ; X_j <- X_j C_X + P_j
 struct BlockUpdArgs {
@@ -122,33 +132,38 @@ struct BlockUpdArgs {
   const double* C;  // per block (3q x q, ld 3q), stride cstride
   long cstride;
   int nblocks;
+  int cplx;         // complex X, W, P and C
 };
 
 // small per-problem kernels
 struct ColnormArgs { const void* X; int f32; long ld, rows; int ncols; double* out; };
 struct RitzArgs { const double* AX; const double* X; const double* lam; double* W; float* W32; long ld, rows; int ncols; };
-struct TransposeArgs { const double* src; int lds; double* dst; int ldd; int m, n; };
+struct TransposeArgs { const double* src; int lds; double* dst; int ldd; int m, n; int cplx; };  // cplx: conjugate
 struct FillArgs { double* p; long count; double v; };
-struct SetDiagArgs { double* G; int ld, m; const double* lam; };
-struct SymmArgs { double* G; int ld, m; };
-struct Frob2Args { const double* G; int ld, nw; double* out; };
-struct OrthArgs { const double* G; int ld, k; double* out; };
+struct SetDiagArgs { double* G; int ld, m; const double* lam; int cplx; };
+struct SymmArgs { double* G; int ld, m; int cplx; };
+struct Frob2Args { const double* G; int ld, nw; double* out; int cplx; };
+struct OrthArgs { const double* G; int ld, k; double* out; int cplx; };
 struct ZeroIntArgs { int* p; int n; };
 struct CopyArgs { const double* src; double* dst; long count; };
 struct PrepArgs { const double* V; long n; double c0; double* td; float* V32; double* dmin_part; int nparts; int* nan_flag; };
 // Cholesky G = L L^H (lower) of an m x m block with L, L^{-1}; composite op
-struct CholArgs { double* G; double* L; double* Li; int m, ld; int* flag; };
+struct CholArgs { double* G; double* L; double* Li; int m, ld; int* flag; int cplx; };
 // device-to-host copy (executed in order at its position, not grouped)
 struct D2HArgs { void* dst; const void* src; size_t bytes; };
 
 enum OpKind : int {
   OP_GRAM_D0, OP_GRAM_D1, OP_GRAM_D2, OP_GRAM_F0, OP_GRAM_F1, OP_GRAM_F2,
-  OP_REDUCE_D, OP_REDUCE_F,
+  OP_GRAM_Z0, OP_GRAM_Z1, OP_GRAM_Z2, OP_GRAM_C0, OP_GRAM_C1, OP_GRAM_C2,
+  OP_REDUCE_D, OP_REDUCE_F, OP_REDUCE_Z, OP_REDUCE_C,
   OP_UPDATE_D0, OP_UPDATE_D1, OP_UPDATE_F0, OP_UPDATE_F1,
+  OP_UPDATE_Z0, OP_UPDATE_Z1, OP_UPDATE_C0, OP_UPDATE_C1,
   OP_STENCIL_D2, OP_STENCIL_D4, OP_STENCIL_F2, OP_STENCIL_F4,
+  OP_STENCIL_Z2, OP_STENCIL_Z4, OP_STENCIL_C2, OP_STENCIL_C4,
   OP_COLNORM_D, OP_COLNORM_F, OP_RITZ,
-  OP_PENCIL24, OP_PENCIL48,
+  OP_PENCIL24, OP_PENCIL48, OP_PENCIL96, OP_PENCILZ24, OP_PENCILZ48, OP_PENCILZ96,
   OP_BUPD_D4, OP_BUPD_D8, OP_BUPD_D16, OP_BUPD_D32, OP_BUPD_F4, OP_BUPD_F8, OP_BUPD_F16, OP_BUPD_F32,
+  OP_BUPD_Z4, OP_BUPD_Z8, OP_BUPD_Z16, OP_BUPD_Z32, OP_BUPD_C4, OP_BUPD_C8, OP_BUPD_C16, OP_BUPD_C32,
   OP_TRANSPOSE, OP_FILL, OP_SETDIAG, OP_SYMM, OP_FROB2, OP_ORTH, OP_ZEROINT, OP_COPY, OP_PREP,
   OP_CHOL,   // composite: expanded by the grouped executor
   OP_D2H,    // host copy
@@ -222,22 +237,23 @@ void launch_block_update(const BlockUpdArgs& a, hipStream_t st);
 // Cholesky G = L L^H (lower), L and Linv written to separate buffers; flag
 // set to 1 + (first failing diagonal block) on a non-positive pivot.
 void chol_inverse_grouped(const std::vector<CholArgs>& jobs, Stage& stage, hipStream_t st);
-void launch_transpose(const double* src, int lds, double* dst, int ldd, int m, int n, hipStream_t st);
+// dst (n x m) = src^T (src^H when cplx)
+void launch_transpose(const double* src, int lds, double* dst, int ldd, int m, int n, int cplx, hipStream_t st);
 void launch_fill(double* p, long count, double v, hipStream_t st);
-void launch_set_diag(double* G, int ld, int m, const double* lam, hipStream_t st);
-void launch_symmetrize(double* G, int ld, int m, hipStream_t st);
+void launch_set_diag(double* G, int ld, int m, const double* lam, int cplx, hipStream_t st);
+void launch_symmetrize(double* G, int ld, int m, int cplx, hipStream_t st);
 // out[j] = sum_{i<nw} G[i, j]^2, j < nw
-void launch_frob2_sub(const double* G, int ld, int nw, double* out, hipStream_t st);
+void launch_frob2_sub(const double* G, int ld, int nw, double* out, int cplx, hipStream_t st);
 // out = |G[:k, :k] - I|_F^2
-void launch_orth_err2(const double* G, int ld, int k, double* out, hipStream_t st);
+void launch_orth_err2(const double* G, int ld, int k, double* out, int cplx, hipStream_t st);
 void launch_copy(const double* src, double* dst, long count, hipStream_t st);
 void launch_d2h(void* dst, const void* src, size_t bytes, hipStream_t st);
 
 // Hermitian eigensolver for m x m (ld) by block Jacobi; eigenvalues
 // ascending in lam, eigenvectors in V (m x m, ldv).  Work buffers owned by
 // the caller (size from eig_workspace_bytes).  Returns sweeps used.
-size_t eig_workspace_bytes(int m);
-struct EigJob { double* M; int ld, m; double* V; int ldv; double* lam; void* work; double rel_tol; };
+size_t eig_workspace_bytes(int m, int cplx);
+struct EigJob { double* M; int ld, m; double* V; int ldv; double* lam; void* work; double rel_tol; int cplx; };
 // All problems in lockstep (one workgroup set per problem and launch);
 // dev_counter / host_counter: one int of device / pinned host memory for the
 // rotation count of a sweep.  Synchronises the stream once per sweep.

@@ -47,17 +47,15 @@ bool launch_grouped_prep(int kind, const void* jobs, const unsigned* start, int 
 }
 
 size_t op_args_size(int kind) {
+  if (kind >= OP_GRAM_D0 && kind <= OP_GRAM_C2) return sizeof(GramArgs);
+  if (kind >= OP_REDUCE_D && kind <= OP_REDUCE_C) return sizeof(ReduceArgs);
+  if (kind >= OP_UPDATE_D0 && kind <= OP_UPDATE_C1) return sizeof(UpdateArgs);
+  if (kind >= OP_STENCIL_D2 && kind <= OP_STENCIL_C4) return sizeof(StencilArgs);
+  if (kind >= OP_PENCIL24 && kind <= OP_PENCILZ96) return sizeof(PencilArgs);
+  if (kind >= OP_BUPD_D4 && kind <= OP_BUPD_C32) return sizeof(BlockUpdArgs);
   switch (kind) {
-    case OP_GRAM_D0: case OP_GRAM_D1: case OP_GRAM_D2: case OP_GRAM_F0: case OP_GRAM_F1: case OP_GRAM_F2:
-      return sizeof(GramArgs);
-    case OP_REDUCE_D: case OP_REDUCE_F: return sizeof(ReduceArgs);
-    case OP_UPDATE_D0: case OP_UPDATE_D1: case OP_UPDATE_F0: case OP_UPDATE_F1: return sizeof(UpdateArgs);
-    case OP_STENCIL_D2: case OP_STENCIL_D4: case OP_STENCIL_F2: case OP_STENCIL_F4: return sizeof(StencilArgs);
     case OP_COLNORM_D: case OP_COLNORM_F: return sizeof(ColnormArgs);
     case OP_RITZ: return sizeof(RitzArgs);
-    case OP_PENCIL24: case OP_PENCIL48: return sizeof(PencilArgs);
-    case OP_BUPD_D4: case OP_BUPD_D8: case OP_BUPD_D16: case OP_BUPD_D32:
-    case OP_BUPD_F4: case OP_BUPD_F8: case OP_BUPD_F16: case OP_BUPD_F32: return sizeof(BlockUpdArgs);
     case OP_TRANSPOSE: return sizeof(TransposeArgs);
     case OP_FILL: return sizeof(FillArgs);
     case OP_SETDIAG: return sizeof(SetDiagArgs);

@@ -171,7 +171,7 @@ struct Work {
   DBuf AXm;                           // float64 H X kept in mixed mode
   DBuf Vd, V32, td;
   DBuf G, GWP, L, Li, Rinv, SAS, SS, V1, Mr, Yv, Cc, lam;
-  DBuf part, bgram, bC, bflags, cn, scal, iflag, eigw, dminp;
+  DBuf part, bgram, bC, bflags, cn, scal, iflag, eigw, dminp, pwork;
   int* hpin = nullptr;                // pinned host scratch: doubles [0, 2Kp), ints from 4Kp + 8
   double* hpind = nullptr;
   size_t hpin_bytes = 0;
@@ -203,6 +203,7 @@ struct ppcg_handle {
   DBuf gZ, gR, gP, gAP, gY, gw, gsc;  // backward-pass work
   // state of the last successful single solve (for ppcg_grad / ppcg_density)
   bool has_state = false;
+  bool s_cplx = false;
   int s_N = 0, s_order = 0, s_k = 0;
   long s_n = 0, s_rows = 0;
   double s_c0 = 0, s_w1 = 0, s_w2 = 0, s_dmin = 0;
@@ -225,6 +226,21 @@ void sync(ppcg_handle* H) {
 // ---------------------------------------------------------------------------
 // one problem
 // ---------------------------------------------------------------------------
+// Bloch phases exp(i kappa_d a h) of the couplings at distance a = 1, 2 along
+// direction d (the gauge form of the Bloch operator, section 1); true when the
+// operator is complex (some kappa_d != 0).
+static bool bloch_phases(const ppcg_operator* op, double ph[3][2][2]) {
+  bool c = false;
+  for (int d = 0; d < 3; ++d) {
+    c = c || op->kpt[d] != 0;
+    for (int a = 1; a <= 2; ++a) {
+      ph[d][a - 1][0] = std::cos(op->kpt[d] * a * op->h);
+      ph[d][a - 1][1] = std::sin(op->kpt[d] * a * op->h);
+    }
+  }
+  return c;
+}
+
 struct Prob {
   ppcg_handle* H;
   Work& Wk;
@@ -238,6 +254,8 @@ struct Prob {
   double tol = 0;
   int rr_period = 1, max_iter = 0;
   bool mixed = false;
+  bool cplx = false;          // complex Hermitian (Bloch phase) operator
+  double ph[3][2][2] = {};    // exp(i kappa_d a h), a = 1, 2
   const double* V = nullptr;
   const double* X0 = nullptr;
   double* Xout = nullptr;
@@ -275,17 +293,23 @@ struct Prob {
   void* Pb() { return mixed ? (void*)Wk.P32.p : Wk.P.p; }
   void* AWb() { return mixed ? (void*)Wk.AW32.p : Wk.AW.p; }
   void* APb() { return mixed ? (void*)Wk.AP32.p : Wk.AP.p; }
-  size_t esz() const { return mixed ? 4 : 8; }
+  size_t esz() const { return (mixed ? 4 : 8) * (cplx ? 2 : 1); }
   void* col(void* base, long c, size_t es) { return (char*)base + (size_t)c * ld * es; }
+  // element sizes: float64 blocks (X, H X) and the float shadow of X
+  size_t xs() const { return cplx ? 16 : 8; }
+  size_t x32s() const { return cplx ? 8 : 4; }
+  int nc() const { return cplx ? 2 : 1; }
+  // column c of a float64 / float block
+  double* xc(double* base, long c) { return (double*)col(base, c, xs()); }
+  float* fc(float* base, long c) { return (float*)col(base, c, x32s()); }
 
   // ---- parameters -----------------------------------------------------------
   void setup(const ppcg_operator* op, int k_, int q_, double tol_, int rrp, const double* X0_, double* Xout_,
              double* lamout_) {
     t0 = std::chrono::steady_clock::now();
     if (!op || !op->V || !X0_ || !Xout_ || !lamout_) throw PpcgError{PPCG_EINVAL, "null pointer argument"};
-    if (op->kpt[0] != 0 || op->kpt[1] != 0 || op->kpt[2] != 0)
-      throw PpcgError{PPCG_EINVAL, "complex (Bloch) operators are not available in this build"};
     if (op->order != 2 && op->order != 4) throw PpcgError{PPCG_EINVAL, "order must be 2 or 4"};
+    cplx = bloch_phases(op, ph);
     if (op->precond != PPCG_PRECOND_JACOBI) throw PpcgError{PPCG_EINVAL, "only the Jacobi preconditioner"};
     if (op->nx < 4 || !(op->h > 0)) throw PpcgError{PPCG_EINVAL, "bad grid"};
     N = op->nx;
@@ -310,8 +334,8 @@ struct Prob {
     rr_period = rrp;
     mixed = H->opt.precision == PPCG_MIXED;
     max_iter = H->opt.max_iter > 0 ? H->opt.max_iter : 20000;
-    if (k <= 0 || q < 1 || q > 16 || !(tol > 0) || rr_period < 1)
-      throw PpcgError{PPCG_EINVAL, "need k > 0, 1 <= sbsize <= 16, tol > 0, rr_period >= 1"};
+    if (k <= 0 || q < 1 || q > 32 || !(tol > 0) || rr_period < 1)
+      throw PpcgError{PPCG_EINVAL, "need k > 0, 1 <= sbsize <= 32, tol > 0, rr_period >= 1"};
     int nbuf = H->opt.nbuf;
     if (nbuf < 0) {
       int extra = std::max(2, (int)std::ceil(0.02 * k));
@@ -329,9 +353,9 @@ struct Prob {
 
   // ---- kernels --------------------------------------------------------------
   void stencil(const void* Xs, void* Ys, int ncols, bool f32) {
-    double es = f32 ? 4 : 8;
-    Scope s(prof, f32 ? "stencil_f32" : "stencil_f64", (order == 4 ? 16.0 : 10.0) * n * ncols,
-            2.0 * es * n * ncols + es * n);
+    double es = (f32 ? 4 : 8) * nc();
+    Scope s(prof, f32 ? "stencil_f32" : "stencil_f64", (order == 4 ? 16.0 : 10.0) * (cplx ? 3 : 1) * n * ncols,
+            2.0 * es * n * ncols + es / nc() * n);
     StencilArgs a{};
     a.X = Xs;
     a.Y = Ys;
@@ -344,6 +368,8 @@ struct Prob {
     a.w2 = w2;
     a.V = f32 ? (const void*)Wk.V32.p : (const void*)Wk.Vd.p;
     a.f32 = f32;
+    a.cplx = cplx;
+    std::memcpy(a.ph, ph, sizeof(ph));
     launch_stencil(a, st);
   }
 
@@ -376,7 +402,7 @@ struct Prob {
     if (M <= 0 || Nn <= 0) return;
     long tiles = (long)((M + 63) / 64) * ((Nn + 63) / 64);
     int splits = pick_splits(tiles, njobs, rws);
-    size_t es = f32acc ? 4 : 8;
+    size_t es = (f32acc ? 4 : 8) * nc();
     size_t one = (size_t)njobs * M * Nn * es;
     if (one > Wk.part.bytes) throw PpcgError{PPCG_EINVAL, "internal: partial buffer too small"};
     splits = (int)std::min<size_t>((size_t)splits, Wk.part.bytes / one);
@@ -400,9 +426,10 @@ struct Prob {
     g.job_col_off = job_col_off;
     g.njobs = njobs;
     g.site = site_of(name);
+    g.cplx = cplx;
     {
-      double nn = (double)std::min(rws, n), es_in = f32acc ? 4.0 : 8.0;
-      double fl = upper ? (double)M * (M + 1) * nn : 2.0 * M * Nn * nn;
+      double nn = (double)std::min(rws, n), es_in = (f32acc ? 4.0 : 8.0) * nc();
+      double fl = (upper ? (double)M * (M + 1) * nn : 2.0 * M * Nn * nn) * (cplx ? 4 : 1);
       double by = (double)njobs * (upper ? M : (M + Nn)) * nn * es_in;
       Scope s(prof, name, fl * njobs, by);
       launch_gram(g, f32acc, st);
@@ -421,6 +448,7 @@ struct Prob {
     r.alpha = 1.0;
     r.beta = 0.0;
     r.upper_only = upper;
+    r.cplx = cplx;
     Scope s(prof, "reduce");
     launch_reduce(r, f32acc, st);
   }
@@ -449,15 +477,16 @@ struct Prob {
     u.b_upper = b_upper;
     u.c0_keep = c0_keep;
     u.site = site_of(name);
-    double nn = (double)std::min(rws, n), es = f32 ? 4.0 : 8.0;
-    double fl = b_upper ? (double)Nn * (Nn + 1) * nn : 2.0 * Kk * Nn * nn;
-    double by = ((double)Kk + Nn * (beta != 0 ? 2.0 : 1.0)) * nn * es + (C32 ? 4.0 * Nn * nn : 0.0);
+    u.cplx = cplx;
+    double nn = (double)std::min(rws, n), es = (f32 ? 4.0 : 8.0) * nc();
+    double fl = (b_upper ? (double)Nn * (Nn + 1) * nn : 2.0 * Kk * Nn * nn) * (cplx ? 4 : 1);
+    double by = ((double)Kk + Nn * (beta != 0 ? 2.0 : 1.0)) * nn * es + (C32 ? 4.0 * nc() * Nn * nn : 0.0);
     Scope s(prof, name, fl, by);
     launch_update(u, f32, st);
   }
 
   void chol(double* G, int m) {
-    CholArgs c{G, Wk.L.d(), Wk.Li.d(), m, Kp, Wk.iflag.i()};
+    CholArgs c{G, Wk.L.d(), Wk.Li.d(), m, Kp, Wk.iflag.i(), cplx};
     Scope s(prof, "chol_inverse");
     if (g_rec) g_rec->add(OP_CHOL, &c, sizeof(c), 0);
     else chol_inverse_grouped({c}, H->stage, st);
@@ -465,7 +494,7 @@ struct Prob {
 
   // ---- set-up ---------------------------------------------------------------
   void allocate() {
-    size_t nk8 = (size_t)rows * K * 8, nk4 = (size_t)rows * K * 4;
+    size_t nk8 = (size_t)rows * K * xs(), nk4 = (size_t)rows * K * x32s();
     Wk.X.ensure(nk8);
     Wk.Xt.ensure(nk8);
     if (mixed) {
@@ -484,9 +513,9 @@ struct Prob {
     }
     Wk.Vd.ensure((size_t)rows * 8);
     Wk.td.ensure((size_t)rows * 8);
-    size_t kk = (size_t)Kp * Kp * 8;
+    size_t kk = (size_t)Kp * Kp * xs();
     for (DBuf* b : {&Wk.G, &Wk.L, &Wk.Li, &Wk.Rinv, &Wk.SAS, &Wk.SS, &Wk.V1, &Wk.Mr, &Wk.Yv, &Wk.Cc}) b->ensure(kk);
-    Wk.GWP.ensure((size_t)Kp * 2 * K * 8);
+    Wk.GWP.ensure((size_t)Kp * 2 * K * xs());
     Wk.lam.ensure((size_t)Kp * 8);
     Wk.cn.ensure((size_t)Kp * 8);
     Wk.scal.ensure((size_t)Kp * 8 + 256);
@@ -494,10 +523,11 @@ struct Prob {
     Wk.dminp.ensure(1024 * 8);
     int s = K / q;
     int nS = 3 * q;
-    Wk.bgram.ensure((size_t)s * (nS + q) * (2 * nS - q) * 8);
-    Wk.bC.ensure((size_t)s * 3 * q * q * 8);
+    Wk.bgram.ensure((size_t)s * (nS + q) * (2 * nS - q) * xs());
+    Wk.bC.ensure((size_t)s * 3 * q * q * xs());
     Wk.bflags.ensure((size_t)s * 4 + 256);
-    Wk.eigw.ensure(eig_workspace_bytes(K));
+    if (3 * q > 48) Wk.pwork.ensure((size_t)s * pencil_work_elems() * xs());
+    Wk.eigw.ensure(eig_workspace_bytes(K, cplx));
     // split partials: the largest Gram of the run
     size_t need = 0;
     auto acc = [&](long M, long Nn, long njobs, long rws, size_t es) {
@@ -507,10 +537,10 @@ struct Prob {
       sp = (int)((rws + chunk - 1) / chunk);
       need = std::max(need, (size_t)njobs * sp * M * Nn * es);
     };
-    acc(K, 2 * K, 1, rows, mixed ? 4 : 8);
-    acc(K, K, 1, rows, 8);
-    acc(nS + q, 2 * nS - q, s, rows, 8);
-    acc(K, K, 1, Kp, 8);
+    acc(K, 2 * K, 1, rows, esz());
+    acc(K, K, 1, rows, xs());
+    acc(nS + q, 2 * nS - q, s, rows, xs());
+    acc(K, K, 1, Kp, xs());
     Wk.part.ensure(need);
     Wk.pinned((size_t)(4 * Kp + 64) * 8);
     // zero everything that carries padding rows
@@ -548,8 +578,8 @@ struct Prob {
 
   // phase: orthonormal start block and first residual (steps 1-4)
   void enq_init() {
-    HIPCHECK(hipMemcpy2DAsync(X(), (size_t)ld * 8, X0, (size_t)n * 8, (size_t)n * 8, K, hipMemcpyDeviceToDevice,
-                              st));
+    HIPCHECK(hipMemcpy2DAsync(X(), (size_t)ld * xs(), X0, (size_t)n * xs(), (size_t)n * xs(), K,
+                              hipMemcpyDeviceToDevice, st));
     nl = 0;
     hasP = false;
     it = 1;
@@ -560,18 +590,18 @@ struct Prob {
 
   // X (active columns) <- X R^{-1}; result lands in Xt then X/Xt swap
   void enq_cholqr(int m) {
-    double* Xa = X() + (long)nl * ld;
+    double* Xa = xc(X(), nl);
     {
       ColSet A = cols1(Xa, m, false);
       gram(A, A, m, m, rows, ld, nullptr, 0, Wk.G.p, Kp, true, false, 1, 0, 0, "gram_xx");
     }
     launch_zero_int(Wk.iflag.i(), 4, st);
     chol(Wk.G.d(), m);
-    launch_transpose(Wk.Li.d(), Kp, Wk.Rinv.d(), Kp, m, m, st);
-    double* Xn = Xt() + (long)nl * ld;
-    update(Xa, ld, m, Wk.Rinv.p, Kp, m, Xn, nullptr, m, ld, mixed ? Wk.X32.f() + (long)nl * ld : nullptr, nullptr,
-           rows, 1.0, 0.0, true, false, "update_xr");
-    launch_copy(X(), Xt(), (long)nl * ld, st);  // locked prefix
+    launch_transpose(Wk.Li.d(), Kp, Wk.Rinv.d(), Kp, m, m, cplx, st);  // R^{-1} = L^{-H}
+    double* Xn = xc(Xt(), nl);
+    update(Xa, ld, m, Wk.Rinv.p, Kp, m, Xn, nullptr, m, ld, mixed ? fc(Wk.X32.f(), nl) : nullptr, nullptr, rows, 1.0,
+           0.0, true, false, "update_xr");
+    launch_copy(X(), Xt(), (long)nl * ld * nc(), st);  // locked prefix
     swapX();
   }
 
@@ -580,19 +610,20 @@ struct Prob {
   // (float64) and only the float copy W32 of the residual is written.
   // Column norms of the wanted active columns go to cn, G's to scal.
   void enq_residual(int m) {
-    double* Xa = X() + (long)nl * ld;
-    double* R = mixed ? Wk.AXm.d() + (long)nl * ld : Wk.W.d() + (long)nl * ld;
+    double* Xa = xc(X(), nl);
+    double* R = mixed ? xc(Wk.AXm.d(), nl) : xc(Wk.W.d(), nl);
     stencil(Xa, R, m, false);
     ColSet A = cols1(Xa, m, false), B = cols1(R, m, false);
     gram(A, B, m, m, rows, ld, nullptr, 0, Wk.G.p, Kp, true, false, 1, 0, 0, "gram_xax");
-    float* W32a = mixed ? Wk.W32.f() + (long)nl * ld : nullptr;
+    float* W32a = mixed ? fc(Wk.W32.f(), nl) : nullptr;
     update(Xa, ld, m, Wk.G.p, Kp, m, R, nullptr, m, ld, W32a, nullptr, rows, -1.0, 1.0, false, false, "update_resid",
            mixed);
     int nwa = std::max(0, k - nl);
     Scope s(prof, "colnorm");
-    if (mixed) launch_colnorm2(W32a, 1, ld, rows, nwa, Wk.cn.d(), st);
-    else launch_colnorm2(R, 0, ld, rows, nwa, Wk.cn.d(), st);
-    launch_frob2_sub(Wk.G.d(), Kp, nwa, Wk.scal.d(), st);
+    // a complex column is read as a real column of twice the length
+    if (mixed) launch_colnorm2(W32a, 1, ld * nc(), rows * nc(), nwa, Wk.cn.d(), st);
+    else launch_colnorm2(R, 0, ld * nc(), rows * nc(), nwa, Wk.cn.d(), st);
+    launch_frob2_sub(Wk.G.d(), Kp, nwa, Wk.scal.d(), cplx, st);
   }
 
   void enq_rho_d2h() {
@@ -629,18 +660,18 @@ struct Prob {
     gram(A, A, K, K, rows, ld, nullptr, 0, Wk.SS.p, Kp, true, false, 1, 0, 0, "gram_rr");
     launch_zero_int(Wk.iflag.i(), 4, st);
     chol(Wk.SS.d(), K);
-    launch_transpose(Wk.Li.d(), Kp, Wk.Rinv.d(), Kp, K, K, st);  // Rinv = Linv^T
+    launch_transpose(Wk.Li.d(), Kp, Wk.Rinv.d(), Kp, K, K, cplx, st);  // Rinv = Linv^H
     update(Wk.SAS.p, Kp, K, Wk.Rinv.p, Kp, K, Wk.V1.p, nullptr, K, Kp, nullptr, nullptr, Kp, 1.0, 0.0, true, false,
            "update_small");
     gram(cols1(Wk.Rinv.p, K, false), cols1(Wk.V1.p, K, false), K, K, Kp, Kp, nullptr, 0, Wk.Mr.p, Kp, false, false,
          1, 0, 0, "gram_small");
-    launch_symmetrize(Wk.Mr.d(), Kp, K, st);
+    launch_symmetrize(Wk.Mr.d(), Kp, K, cplx, st);
     launch_d2h(Wk.hpin, Wk.iflag.p, 4, st);
   }
   void post_rr1() {
     if (Wk.hpin[0]) throw PpcgError{PPCG_ERANK, "Rayleigh-Ritz Gram S^H S not positive definite"};
   }
-  EigJob eig_job() { return EigJob{Wk.Mr.d(), Kp, K, Wk.Yv.d(), Kp, Wk.lam.d(), Wk.eigw.p, rr_rel_tol()}; }
+  EigJob eig_job() { return EigJob{Wk.Mr.d(), Kp, K, Wk.Yv.d(), Kp, Wk.lam.d(), Wk.eigw.p, rr_rel_tol(), cplx}; }
 
   // part 2: C = L^{-H} Y, X <- S C, fresh W = H X - X Lambda (all columns)
   void enq_rr2() {
@@ -654,12 +685,14 @@ struct Prob {
     stencil(X(), R, K, false);
     {
       Scope s(prof, "ritz_resid");
+      // a complex column is read as a real column of twice the length (lambda is real)
+      const long ldr = ld * nc(), rowsr = rows * nc();
       if (mixed) {
-        launch_ritz_resid(R, X(), Wk.lam.d(), nullptr, Wk.W32.f(), ld, rows, K, st);
-        launch_colnorm2(Wk.W32.p, 1, ld, rows, K, Wk.cn.d(), st);
+        launch_ritz_resid(R, X(), Wk.lam.d(), nullptr, Wk.W32.f(), ldr, rowsr, K, st);
+        launch_colnorm2(Wk.W32.p, 1, ldr, rowsr, K, Wk.cn.d(), st);
       } else {
-        launch_ritz_resid(R, X(), Wk.lam.d(), R, nullptr, ld, rows, K, st);
-        launch_colnorm2(R, 0, ld, rows, K, Wk.cn.d(), st);
+        launch_ritz_resid(R, X(), Wk.lam.d(), R, nullptr, ldr, rowsr, K, st);
+        launch_colnorm2(R, 0, ldr, rowsr, K, Wk.cn.d(), st);
       }
     }
     launch_d2h(Wk.hpind, Wk.cn.p, (size_t)K * 8, st);
@@ -698,11 +731,11 @@ struct Prob {
   // part 3: active G = diag(Lambda_act) and the residual bookkeeping for rho
   void enq_rr3() {
     int m = K - nl;
-    launch_set_diag(Wk.G.d(), Kp, m, Wk.lam.d() + nl, st);
+    launch_set_diag(Wk.G.d(), Kp, m, Wk.lam.d() + nl, cplx, st);
     int nwa = std::max(0, k - nl);
     launch_copy(Wk.cn.d() + nl, Wk.scal.d(), std::max(nwa, 1), st);  // shift cn by nl through scal
     launch_copy(Wk.scal.d(), Wk.cn.d(), std::max(nwa, 1), st);
-    launch_frob2_sub(Wk.G.d(), Kp, nwa, Wk.scal.d(), st);
+    launch_frob2_sub(Wk.G.d(), Kp, nwa, Wk.scal.d(), cplx, st);
     enq_rho_d2h();
   }
 
@@ -710,7 +743,6 @@ struct Prob {
   void enq_body1() {
     const int m = K - nl;
     const int s = m / q;
-    const long off = (long)nl * ld;
     const size_t es = esz();
     void* Wa = col(Wb(), nl, es);
     void* Pa = col(Pb(), nl, es);
@@ -743,7 +775,7 @@ struct Prob {
     const int nS = hasP ? 3 * q : 2 * q;
     {
       ColSet A{}, B{};
-      const void* segs[5] = {X() + off, Wa, Pa, AWa, APa};
+      const void* segs[5] = {xc(X(), nl), Wa, Pa, AWa, APa};
       bool f[5] = {false, mixed, mixed, mixed, mixed};
       int na = hasP ? 3 : 2;
       for (int t = 0; t < na; ++t) {
@@ -752,7 +784,7 @@ struct Prob {
         A.f32[t] = f[t];
       }
       if (mixed) {  // rows (H X_j)^H [...] from the float64 H X
-        A.p[na] = Wk.AXm.d() + off;
+        A.p[na] = xc(Wk.AXm.d(), nl);
         A.end[na] = (na + 1) * q;
         A.f32[na] = false;
         ++na;
@@ -786,13 +818,15 @@ struct Prob {
       pa.pivot_tol = 1e-12;
       pa.jacobi_rel = pencil_rel_tol();
       pa.nblocks = s;
+      pa.cplx = cplx;
+      pa.work = Wk.pwork.p;
       Scope sc(prof, "block_pencil", 0, 0);
       launch_block_pencil(pa, st);
     }
     // steps 14-15
     {
       BlockUpdArgs bu{};
-      bu.X = X() + off;
+      bu.X = xc(X(), nl);
       bu.W = Wa;
       bu.P = Pa;
       bu.f32 = mixed;
@@ -803,7 +837,8 @@ struct Prob {
       bu.C = Wk.bC.d();
       bu.cstride = 3L * q * q;
       bu.nblocks = s;
-      Scope sc(prof, "block_update", 6.0 * (double)n * q * q * s * (hasP ? 1.0 : 2.0 / 3.0),
+      bu.cplx = cplx;
+      Scope sc(prof, "block_update", 6.0 * (cplx ? 4 : 1) * (double)n * q * q * s * (hasP ? 1.0 : 2.0 / 3.0),
                (double)n * q * s * (hasP ? 5.0 : 4.0) * (double)esz());
       launch_block_update(bu, st);
     }
@@ -828,12 +863,12 @@ struct Prob {
 
   // phase: outputs and the orthogonality check of the returned block
   void enq_finish() {
-    HIPCHECK(hipMemcpy2DAsync(Xout, (size_t)n * 8, X(), (size_t)ld * 8, (size_t)n * 8, k, hipMemcpyDeviceToDevice,
-                              st));
+    HIPCHECK(hipMemcpy2DAsync(Xout, (size_t)n * xs(), X(), (size_t)ld * xs(), (size_t)n * xs(), k,
+                              hipMemcpyDeviceToDevice, st));
     HIPCHECK(hipMemcpyAsync(lamout, Wk.lam.p, (size_t)k * 8, hipMemcpyDeviceToDevice, st));
     ColSet A = cols1(X(), k, false);
     gram(A, A, k, k, rows, ld, nullptr, 0, Wk.G.p, Kp, false, false, 1, 0, 0, "gram_check");
-    launch_orth_err2(Wk.G.d(), Kp, k, Wk.scal.d(), st);
+    launch_orth_err2(Wk.G.d(), Kp, k, Wk.scal.d(), cplx, st);
     launch_d2h(Wk.hpind, Wk.scal.p, 8, st);
   }
   void post_finish() {
@@ -856,17 +891,18 @@ struct Driver {
 
   static const char* op_name(int kind) {
     switch (kind) {
-      case OP_GRAM_D0: case OP_GRAM_F0: return "gram";
-      case OP_GRAM_D1: case OP_GRAM_F1: return "gram_proj";
-      case OP_GRAM_D2: case OP_GRAM_F2: return "gram_block";
-      case OP_REDUCE_D: case OP_REDUCE_F: return "reduce";
-      case OP_UPDATE_D0: case OP_UPDATE_F0: return "update";
-      case OP_UPDATE_D1: case OP_UPDATE_F1: return "update_proj";
-      case OP_STENCIL_D2: case OP_STENCIL_D4: return "stencil_f64";
-      case OP_STENCIL_F2: case OP_STENCIL_F4: return "stencil_f32";
-      case OP_PENCIL24: case OP_PENCIL48: return "block_pencil";
+      case OP_GRAM_D0: case OP_GRAM_F0: case OP_GRAM_Z0: case OP_GRAM_C0: return "gram";
+      case OP_GRAM_D1: case OP_GRAM_F1: case OP_GRAM_Z1: case OP_GRAM_C1: return "gram_proj";
+      case OP_GRAM_D2: case OP_GRAM_F2: case OP_GRAM_Z2: case OP_GRAM_C2: return "gram_block";
+      case OP_REDUCE_D: case OP_REDUCE_F: case OP_REDUCE_Z: case OP_REDUCE_C: return "reduce";
+      case OP_UPDATE_D0: case OP_UPDATE_F0: case OP_UPDATE_Z0: case OP_UPDATE_C0: return "update";
+      case OP_UPDATE_D1: case OP_UPDATE_F1: case OP_UPDATE_Z1: case OP_UPDATE_C1: return "update_proj";
+      case OP_STENCIL_D2: case OP_STENCIL_D4: case OP_STENCIL_Z2: case OP_STENCIL_Z4: return "stencil_f64";
+      case OP_STENCIL_F2: case OP_STENCIL_F4: case OP_STENCIL_C2: case OP_STENCIL_C4: return "stencil_f32";
+      case OP_PENCIL24: case OP_PENCIL48: case OP_PENCIL96:
+      case OP_PENCILZ24: case OP_PENCILZ48: case OP_PENCILZ96: return "block_pencil";
       case OP_CHOL: return "chol_inverse";
-      default: return (kind >= OP_BUPD_D4 && kind <= OP_BUPD_F32) ? "block_update" : "misc";
+      default: return (kind >= OP_BUPD_D4 && kind <= OP_BUPD_C32) ? "block_update" : "misc";
     }
   }
 
@@ -1099,6 +1135,7 @@ struct Grad {
 
   int run(const double* g, const double* w, double* out, double tol, int max_iter) {
     if (!H->has_state) throw PpcgError{PPCG_ENOSTATE, "ppcg_grad needs a successful ppcg_solve on this handle"};
+    if (H->s_cplx) throw PpcgError{PPCG_EINVAL, "ppcg_grad supports real (kappa = 0) operators only"};
     if (!g || !out || !(tol > 0)) throw PpcgError{PPCG_EINVAL, "null pointer or tol <= 0"};
     Work& Wk = H->work(0);
     k = H->s_k;
@@ -1238,6 +1275,7 @@ ppcg_status ppcg_solve(ppcg_handle* h, const ppcg_operator* op, int32_t k, int32
       return p.status;
     }
     h->has_state = true;
+    h->s_cplx = p.cplx;
     h->s_N = p.N;
     h->s_order = p.order;
     h->s_k = p.k;
@@ -1265,6 +1303,8 @@ ppcg_status ppcg_solve_batched(ppcg_handle* h, int32_t nprob, const ppcg_operato
       ps.emplace_back(new Prob(h, h->work(b)));
       try {
         ps[b]->setup(&ops[b], k[b], sbsize, tol, rr_period, X0[b], X_out[b], lambda_out[b]);
+        if (!run.empty() && ps[b]->cplx != run[0]->cplx)
+          throw PpcgError{PPCG_EINVAL, "a batch cannot mix real and complex (Bloch) operators"};
         run.push_back(ps[b].get());
       } catch (const PpcgError& e) {
         ps[b]->status = e.code;
@@ -1300,6 +1340,7 @@ ppcg_status ppcg_density(ppcg_handle* h, double* rho) {
   if (!h || !rho) return PPCG_EINVAL;
   return guard(h, [&]() {
     if (!h->has_state) throw PpcgError{PPCG_ENOSTATE, "ppcg_density needs a successful ppcg_solve on this handle"};
+    if (h->s_cplx) throw PpcgError{PPCG_EINVAL, "ppcg_density supports real (kappa = 0) operators only"};
     launch_grad_rows(h->work(0).X.d(), nullptr, nullptr, h->s_rows, h->s_n, h->s_k, rho, h->st);
     HIPCHECK(hipGetLastError());
     sync(h);
@@ -1321,8 +1362,6 @@ ppcg_status ppcg_apply_h(ppcg_handle* h, const ppcg_operator* op, int32_t ncols,
   if (!h || !op || !op->V || !X || !Y || ncols < 0) return PPCG_EINVAL;
   return guard(h, [&]() {
     if (op->order != 2 && op->order != 4) throw PpcgError{PPCG_EINVAL, "order must be 2 or 4"};
-    if (op->kpt[0] != 0 || op->kpt[1] != 0 || op->kpt[2] != 0)
-      throw PpcgError{PPCG_EINVAL, "complex (Bloch) operators are not available in this build"};
     double ih2 = 1.0 / (op->h * op->h);
     long n = (long)op->nx * op->nx * op->nx;
     StencilArgs a{};
@@ -1337,6 +1376,7 @@ ppcg_status ppcg_apply_h(ppcg_handle* h, const ppcg_operator* op, int32_t ncols,
     a.w2 = op->order == 2 ? 0.0 : ih2 / 24.0;
     a.V = op->V;
     a.f32 = 0;
+    a.cplx = bloch_phases(op, a.ph);
     {
       Scope sc(h->prof, "stencil_f64");
       launch_stencil(a, h->st);

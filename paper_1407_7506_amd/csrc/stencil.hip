@@ -10,17 +10,31 @@
 
 namespace ppcg {
 
-template <class T, int ORDER>
+template <class S>
+PPCG_DEV S phased(S xp, S xm, const double* ph) {
+  if constexpr (sc_traits<S>::cplx) {
+    typedef typename sc_traits<S>::real_t R;
+    cpx<R> f{(R)ph[0], (R)ph[1]};
+    return f * xp + conj_(f) * xm;
+  } else {
+    return xp + xm;
+  }
+}
+
+// S: double, float, zdouble, zfloat.  The coupling from point r to
+// r + a h e_d carries exp(i kappa_d a h) (gauge form of the Bloch phase).
+template <class S, int ORDER>
 PPCG_DEV void stencil_body(const StencilArgs& a, unsigned wg, unsigned nwg) {
+  typedef typename sc_traits<S>::real_t R;
   const long n = (long)a.N * a.N * a.N;
   const unsigned bpc = (unsigned)((n + 255) / 256);
   unsigned L = xcd_remap(wg, nwg);
   int col = L / bpc;
   long p = (long)(L % bpc) * 256 + threadIdx.x;
   if (col >= a.ncols || p >= n) return;
-  const T* x = (const T*)a.X + (long)col * a.ldx;
-  T* y = (T*)a.Y + (long)col * a.ldy;
-  const T* V = (const T*)a.V;
+  const S* x = (const S*)a.X + (long)col * a.ldx;
+  S* y = (S*)a.Y + (long)col * a.ldy;
+  const R* V = (const R*)a.V;
   const int N = a.N;
   const int NN = N * N;
   int i = (int)(p % N);
@@ -31,43 +45,61 @@ PPCG_DEV void stencil_body(const StencilArgs& a, unsigned wg, unsigned nwg) {
   const long pl = p - (long)j * N;      // (i, 0, k)
   const long pz = p - (long)k * NN;     // (i, j, 0)
   auto wr = [N](int c, int d) { int r = c + d; return r >= N ? r - N : (r < 0 ? r + N : r); };
-  T xc = x[p];
-  T s1 = x[b + wr(i, 1)] + x[b + wr(i, -1)] + x[pl + (long)wr(j, 1) * N] + x[pl + (long)wr(j, -1) * N] +
-         x[pz + (long)wr(k, 1) * NN] + x[pz + (long)wr(k, -1) * NN];
-  T out = ((T)a.c0 + V[p]) * xc + (T)a.w1 * s1;
+  S xc = x[p];
+  S s1 = phased<S>(x[b + wr(i, 1)], x[b + wr(i, -1)], a.ph[0][0]) +
+         phased<S>(x[pl + (long)wr(j, 1) * N], x[pl + (long)wr(j, -1) * N], a.ph[1][0]) +
+         phased<S>(x[pz + (long)wr(k, 1) * NN], x[pz + (long)wr(k, -1) * NN], a.ph[2][0]);
+  S out = ((R)a.c0 + V[p]) * xc + (R)a.w1 * s1;
   if (ORDER == 4) {
-    T s2 = x[b + wr(i, 2)] + x[b + wr(i, -2)] + x[pl + (long)wr(j, 2) * N] + x[pl + (long)wr(j, -2) * N] +
-           x[pz + (long)wr(k, 2) * NN] + x[pz + (long)wr(k, -2) * NN];
-    out += (T)a.w2 * s2;
+    S s2 = phased<S>(x[b + wr(i, 2)], x[b + wr(i, -2)], a.ph[0][1]) +
+           phased<S>(x[pl + (long)wr(j, 2) * N], x[pl + (long)wr(j, -2) * N], a.ph[1][1]) +
+           phased<S>(x[pz + (long)wr(k, 2) * NN], x[pz + (long)wr(k, -2) * NN], a.ph[2][1]);
+    out += (R)a.w2 * s2;
   }
-  if (a.shift) out -= (T)a.shift[col] * xc;
+  if (a.shift) out -= (R)a.shift[col] * xc;
   y[p] = out;
 }
-template <class T, int ORDER>
+template <class S, int ORDER>
 __global__ __launch_bounds__(256) void stencil_kernel(StencilArgs a) {
-  stencil_body<T, ORDER>(a, blockIdx.x, gridDim.x);
+  stencil_body<S, ORDER>(a, blockIdx.x, gridDim.x);
 }
-template <class T, int ORDER>
+template <class S, int ORDER>
 __global__ __launch_bounds__(256) void stencil_grouped(const StencilArgs* jobs, const unsigned* start, int nj) {
   int j = find_job(start, nj, blockIdx.x);
-  stencil_body<T, ORDER>(jobs[j], blockIdx.x - start[j], start[j + 1] - start[j]);
+  stencil_body<S, ORDER>(jobs[j], blockIdx.x - start[j], start[j + 1] - start[j]);
 }
+
+static int stencil_kind(const StencilArgs& a) {
+  int base = a.cplx ? (a.f32 ? OP_STENCIL_C2 : OP_STENCIL_Z2) : (a.f32 ? OP_STENCIL_F2 : OP_STENCIL_D2);
+  // D2, D4 / F2, F4 / Z2, Z4 / C2, C4 are adjacent except D and F
+  if (!a.cplx && a.f32) return a.order == 4 ? OP_STENCIL_F4 : OP_STENCIL_F2;
+  if (!a.cplx) return a.order == 4 ? OP_STENCIL_D4 : OP_STENCIL_D2;
+  return a.order == 4 ? base + 1 : base;
+}
+
+#define PPCG_STENCIL_SWITCH(KERNEL, GRID, ...)                                                                        \
+  switch (kind) {                                                                                                    \
+    case OP_STENCIL_D2: hipLaunchKernelGGL((KERNEL<double, 2>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;    \
+    case OP_STENCIL_D4: hipLaunchKernelGGL((KERNEL<double, 4>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;    \
+    case OP_STENCIL_F2: hipLaunchKernelGGL((KERNEL<float, 2>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;     \
+    case OP_STENCIL_F4: hipLaunchKernelGGL((KERNEL<float, 4>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;     \
+    case OP_STENCIL_Z2: hipLaunchKernelGGL((KERNEL<zdouble, 2>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;   \
+    case OP_STENCIL_Z4: hipLaunchKernelGGL((KERNEL<zdouble, 4>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;   \
+    case OP_STENCIL_C2: hipLaunchKernelGGL((KERNEL<zfloat, 2>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;    \
+    case OP_STENCIL_C4: hipLaunchKernelGGL((KERNEL<zfloat, 4>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;    \
+    default: break;                                                                                                  \
+  }
 
 void launch_stencil(const StencilArgs& a, hipStream_t st) {
   long n = (long)a.N * a.N * a.N;
   unsigned blocks = (unsigned)(((n + 255) / 256) * a.ncols);
-  int kind = a.f32 ? (a.order == 4 ? OP_STENCIL_F4 : OP_STENCIL_F2) : (a.order == 4 ? OP_STENCIL_D4 : OP_STENCIL_D2);
+  int kind = stencil_kind(a);
   if (g_rec) {
     g_rec->add(kind, &a, sizeof(a), blocks);
     return;
   }
   if (blocks == 0) return;
-  switch (kind) {
-    case OP_STENCIL_F4: hipLaunchKernelGGL((stencil_kernel<float, 4>), dim3(blocks), dim3(256), 0, st, a); break;
-    case OP_STENCIL_F2: hipLaunchKernelGGL((stencil_kernel<float, 2>), dim3(blocks), dim3(256), 0, st, a); break;
-    case OP_STENCIL_D4: hipLaunchKernelGGL((stencil_kernel<double, 4>), dim3(blocks), dim3(256), 0, st, a); break;
-    case OP_STENCIL_D2: hipLaunchKernelGGL((stencil_kernel<double, 2>), dim3(blocks), dim3(256), 0, st, a); break;
-  }
+  PPCG_STENCIL_SWITCH(stencil_kernel, blocks, a)
 }
 
 // ---------------------------------------------------------------------------
@@ -158,11 +190,11 @@ void launch_ritz_resid(const double* AX, const double* X, const double* lam, dou
 bool launch_grouped_stencil(int kind, const void* jobs, const unsigned* start, int nj, unsigned total,
                             hipStream_t st) {
   const StencilArgs* sj = (const StencilArgs*)jobs;
+  if (kind >= OP_STENCIL_D2 && kind <= OP_STENCIL_C4) {
+    PPCG_STENCIL_SWITCH(stencil_grouped, total, sj, start, nj)
+    return true;
+  }
   switch (kind) {
-    case OP_STENCIL_F4: hipLaunchKernelGGL((stencil_grouped<float, 4>), dim3(total), dim3(256), 0, st, sj, start, nj); return true;
-    case OP_STENCIL_F2: hipLaunchKernelGGL((stencil_grouped<float, 2>), dim3(total), dim3(256), 0, st, sj, start, nj); return true;
-    case OP_STENCIL_D4: hipLaunchKernelGGL((stencil_grouped<double, 4>), dim3(total), dim3(256), 0, st, sj, start, nj); return true;
-    case OP_STENCIL_D2: hipLaunchKernelGGL((stencil_grouped<double, 2>), dim3(total), dim3(256), 0, st, sj, start, nj); return true;
     case OP_COLNORM_D:
       hipLaunchKernelGGL(colnorm2_grouped<double>, dim3(total), dim3(256), 0, st, (const ColnormArgs*)jobs, start, nj);
       return true;

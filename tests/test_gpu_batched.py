@@ -13,6 +13,10 @@ from oracle import brute  # noqa: E402
 from paper_1407_7506_amd import binding as B  # noqa: E402
 from paper_1407_7506_amd import inputs as I  # noqa: E402
 
+# iteration cap of every handle here: a solve that stops converging ends
+# with PPCG_ENOCONV in seconds instead of running 20000 iterations
+MAX_IT = 4000
+
 
 def say(*a):
     print(*a, flush=True)
@@ -34,10 +38,10 @@ def small_batch():
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_batched_equals_single_solves(precision):
     ps = small_batch()
-    h = B.Handle(precision)
+    h = B.Handle(precision, max_iter=MAX_IT)
     probs = [dict(V=dev(p.V), N=p.grid.N, k=p.k, X0=dev(p.start()), order=p.grid.order) for p in ps]
     res = h.solve_batched(probs, 2, 1e-9, 5)
-    hs = B.Handle(precision)
+    hs = B.Handle(precision, max_iter=MAX_IT)
     for p, pr, (lam, X, info, status) in zip(ps, probs, res):
         assert status == "PPCG_OK"
         l1, X1, i1 = hs.solve(pr["V"], pr["N"], p.k, 2, 1e-9, 5, pr["X0"], order=pr["order"])
@@ -50,7 +54,7 @@ def test_batched_equals_single_solves(precision):
 
 def test_batched_reports_per_problem_errors():
     ps = small_batch()[:3]
-    h = B.Handle("fp64")
+    h = B.Handle("fp64", max_iter=MAX_IT)
     probs = [dict(V=dev(p.V), N=p.grid.N, k=p.k, X0=dev(p.start()), order=p.grid.order) for p in ps]
     probs[1]["V"] = dev(np.full(ps[1].grid.n, -50.0))       # diag(H) < 0: not HPD
     res = h.solve_batched(probs, 2, 1e-8, 5, check=False)
@@ -61,10 +65,10 @@ def test_batch64_workload_subset():
     """Eight problems of the 64-problem uneven workload (grids 24^3..40^3,
     k 32..256, sbsize 8) batched vs single solves."""
     ps = I.batch64()[:8]
-    h = B.Handle("fp64")
+    h = B.Handle("fp64", max_iter=MAX_IT)
     probs = [dict(V=dev(p.V), N=p.grid.N, k=p.k, X0=dev(p.start()), order=2) for p in ps]
     res = h.solve_batched(probs, 8, 1e-6, 5)
-    hs = B.Handle("fp64")
+    hs = B.Handle("fp64", max_iter=MAX_IT)
     for p, pr, (lam, X, info, status) in zip(ps, probs, res):
         l1, X1, i1 = hs.solve(pr["V"], pr["N"], p.k, 8, 1e-6, 5, pr["X0"])
         d = ((lam - l1).abs().max() / l1.abs().max()).item()

@@ -1,0 +1,211 @@
+"""GPU parity of the complex Hermitian (Bloch phase) path against the oracle,
+through the C ABI.
+
+The operator is the same finite-difference Hamiltonian with the coupling from
+r to r + a h e_d multiplied by exp(i kappa_d a h) (section 1 allows any
+Hermitian A; the Bloch workload uses kappa = (2 pi 0.25 / L, 0, 0)).  Blocks
+are complex128.  Eigenvalue errors are normalised by max |lambda| as in the
+real tests; eigenvectors are compared as subspaces (complex SVD of X^H Y)."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import brute, ppcg_ref, stencil  # noqa: E402
+from paper_1407_7506_amd import binding as B  # noqa: E402
+from paper_1407_7506_amd import inputs as I  # noqa: E402
+
+# iteration cap of every handle here: a solve that stops converging ends
+# with PPCG_ENOCONV in seconds instead of running 20000 iterations
+MAX_IT = 4000
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def h64():
+    h = B.Handle("fp64", max_iter=MAX_IT)
+    yield h
+    h.close()
+
+
+@pytest.fixture(scope="module")
+def hmix():
+    h = B.Handle("mixed", max_iter=MAX_IT)
+    yield h
+    h.close()
+
+
+def dev(a):
+    return torch.tensor(np.ascontiguousarray(a), device="cuda")
+
+
+def bloch_kpt(N, h=0.5, frac=0.25):
+    return (2.0 * math.pi * frac / (N * h), 0.0, 0.0)
+
+
+def gpu_solve(h, p, tol=None):
+    g = p.grid
+    lam, X, info = h.solve(dev(p.V), g.N, p.k, p.q, tol or p.tol, p.rr_period, dev(p.start()), h=g.h,
+                           order=g.order, kpt=g.kpt)
+    return lam.cpu().numpy(), X.cpu().numpy(), info
+
+
+def oracle_solve(p, tol):
+    g = p.grid
+    A = lambda X: stencil.apply_h(X, p.V, g.N, g.h, g.order, g.kpt)
+    T = 1.0 / stencil.diag_h(p.V, g.h, g.order)
+    return ppcg_ref.ppcg(A, T, p.start(), p.k, p.q, tol, p.rr_period)
+
+
+def subspace_dist(X, Y):
+    s = np.linalg.svd(X.conj().T @ Y, compute_uv=False)
+    return math.sqrt(max(0.0, 1.0 - s.min() ** 2))
+
+
+def fresh_resid(p, lam, X):
+    g = p.grid
+    R = stencil.apply_h(X, p.V, g.N, g.h, g.order, g.kpt) - X * lam[None, :]
+    return np.linalg.norm(R) / np.linalg.norm(lam)
+
+
+@pytest.mark.parametrize("N,order,kpt", [(10, 2, (0.9, 0.0, 0.0)), (9, 4, (0.3, -0.7, 1.1)),
+                                         (16, 4, (0.0, 0.0, 0.45)), (13, 2, (0.2, 0.5, -0.1))])
+def test_apply_h_complex_matches_oracle(h64, N, order, kpt):
+    say("apply_h complex", N, order, kpt)
+    V = I.gaussian_wells(N, 0.5, 3, N)
+    rng = np.random.default_rng(N + 1)
+    X = rng.standard_normal((N ** 3, 5)) + 1j * rng.standard_normal((N ** 3, 5))
+    Y = h64.apply_h(dev(V), N, dev(I.to_colmajor(X)), order=order, kpt=kpt)
+    ref = stencil.apply_h(X, V, N, 0.5, order, kpt)
+    got = I.from_colmajor(Y.cpu().numpy())
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_apply_h_rejects_real_block_for_bloch_operator(h64):
+    N = 8
+    V = dev(np.zeros(N ** 3))
+    with pytest.raises(TypeError):
+        h64.apply_h(V, N, dev(np.zeros((2, N ** 3))), kpt=(0.5, 0.0, 0.0))
+
+
+SMALL = [
+    dict(N=8, k=12, q=4, order=2, kpt=(0.9, 0.0, 0.0)),
+    dict(N=10, k=20, q=4, order=4, kpt=bloch_kpt(10)),
+    dict(N=11, k=30, q=2, order=4, kpt=(0.3, -0.7, 1.1)),      # odd grid: ragged row tail
+    dict(N=12, k=24, q=16, order=2, kpt=(0.0, 0.4, 0.0), nbuf=8),  # q = 16: complex 48 x 48 pencils
+    dict(N=8, k=6, q=1, order=2, kpt=(0.6, 0.0, 0.0)),
+    dict(N=10, k=15, q=5, order=2, kpt=(0.5, 0.5, 0.0), rr_period=1),
+    dict(N=12, k=60, q=32, order=4, kpt=bloch_kpt(12)),   # q = 32: complex 96 x 96 pencils in device scratch
+]
+
+
+def _ids(c):
+    return "-".join(f"{k}{v}" for k, v in c.items() if k != "kpt") + "-kpt" + "_".join(f"{x:.2f}" for x in c["kpt"])
+
+
+@pytest.mark.parametrize("case", SMALL, ids=_ids)
+def test_complex_fp64_matches_oracle_and_brute(h64, case):
+    p = I.small_problem(tol=1e-9, **case)
+    h = B.Handle("fp64", nbuf=p.nbuf, max_iter=MAX_IT) if p.nbuf != I.default_nbuf(p.k, p.q) else h64
+    say("complex fp64 vs oracle", p.name, p.grid.kpt, "K", p.K)
+    lam, X, info = gpu_solve(h, p)
+    assert X.dtype == np.complex128
+    lo, Xo, io = oracle_solve(p, 1e-9)
+    scale = np.abs(lo).max()
+    err = np.abs(lam - lo).max() / scale
+    say("  err", err, "iters gpu/oracle", info["iters"], io.iters)
+    assert err <= 1e-9
+    lb, Xb, lall = brute.lowest(p.V, p.grid.N, p.grid.h, p.grid.order, p.k, p.grid.kpt)
+    assert np.abs(lam - lb).max() / scale <= 1e-9
+    assert np.all(lam >= lb - 1e-12 * scale)          # Cauchy interlacing
+    assert np.all(np.diff(lam) >= -1e-14 * scale)
+    np.testing.assert_allclose(X.conj().T @ X, np.eye(p.k), atol=1e-12)
+    assert fresh_resid(p, lam, X) <= 1e-9 * 1.001
+    assert info["resid_final"] <= 1e-9
+    if lall[p.k] - lall[p.k - 1] > 1e-3:
+        assert subspace_dist(X, Xo) < 1e-6
+
+
+@pytest.mark.parametrize("case", SMALL[:4], ids=_ids)
+def test_complex_mixed_matches_oracle(hmix, case):
+    p = I.small_problem(tol=1e-8, **case)
+    if p.nbuf != I.default_nbuf(p.k, p.q):
+        hmix = B.Handle("mixed", nbuf=p.nbuf, max_iter=MAX_IT)
+    say("complex mixed vs oracle", p.name)
+    lam, X, info = gpu_solve(hmix, p)
+    lo, Xo, io = oracle_solve(p, 1e-8)
+    err = np.abs(lam - lo).max() / np.abs(lo).max()
+    say("  err", err, "iters", info["iters"], io.iters)
+    assert err <= 1e-8
+    np.testing.assert_allclose(X.conj().T @ X, np.eye(p.k), atol=1e-12)
+    assert fresh_resid(p, lam, X) <= 1e-8 * 1.001
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_reduced_bloch_grid_matches_brute_force(prec):
+    """The Bloch workload's operator family (13-point, smoothed field in
+    [-2, 0], kappa = (2 pi 0.25 / L, 0, 0)) on a reduced 24^3 grid, k = 64,
+    q = 8, solved to tol 1e-9 (FP64) / 1e-8 (mixed) and compared with the
+    stored dense eigenvalues of the assembled matrix."""
+    p = I.bloch96(N=24, k=64, q=8)
+    tol = 1e-9 if prec == "fp64" else 1e-8
+    h = B.Handle(prec, max_iter=MAX_IT)
+    say("reduced Bloch", prec, p.name, p.grid.kpt)
+    lam, X, info = gpu_solve(h, p, tol)
+    ref = np.loadtxt(os.path.join(HERE, "golden", "bloch24_k64_brute.txt"))[:p.k]
+    scale = np.abs(ref).max()
+    err = np.abs(lam - ref).max() / scale
+    say("  err", err, "iters", info["iters"], "resid", info["resid_final"])
+    assert err <= tol
+    assert np.all(lam >= ref - 1e-12 * scale)         # Cauchy interlacing
+    np.testing.assert_allclose(X.conj().T @ X, np.eye(p.k), atol=1e-12)
+    assert fresh_resid(p, lam, X) <= tol * 1.001
+    assert np.all(np.diff(lam) >= -1e-14 * scale)
+    h.close()
+
+
+def test_complex_deterministic(h64):
+    p = I.small_problem(N=10, k=20, q=4, order=4, kpt=bloch_kpt(10), tol=1e-9)
+    a = gpu_solve(h64, p)
+    b = gpu_solve(h64, p)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_grad_refuses_complex_state(h64):
+    p = I.small_problem(N=8, k=12, q=4, order=2, kpt=(0.9, 0.0, 0.0), tol=1e-8)
+    gpu_solve(h64, p)
+    with pytest.raises(B.PPCGError):
+        h64.grad(dev(np.ones(p.k)))
+    with pytest.raises(B.PPCGError):
+        h64.density()
+
+
+def test_batch_complex_matches_single(h64):
+    specs = [dict(N=8, k=12, q=4, order=2, kpt=(0.9, 0.0, 0.0), seed=3),
+             dict(N=10, k=8, q=4, order=4, kpt=bloch_kpt(10), seed=4),
+             dict(N=9, k=16, q=4, order=2, kpt=(0.1, 0.2, 0.3), seed=5)]
+    ps = [I.small_problem(tol=1e-9, **s) for s in specs]
+    hb = B.Handle("fp64", max_iter=MAX_IT)
+    probs = [dict(V=dev(p.V), N=p.grid.N, k=p.k, X0=dev(p.start()), h=p.grid.h, order=p.grid.order, kpt=p.grid.kpt)
+             for p in ps]
+    res = hb.solve_batched(probs, 4, 1e-9, 5)
+    for p, (lam, X, info, st) in zip(ps, res):
+        assert st == "PPCG_OK"
+        l1, X1, i1 = gpu_solve(h64, p, 1e-9)
+        scale = np.abs(l1).max()
+        assert np.abs(lam.cpu().numpy() - l1).max() <= 1e-12 * scale
+    # a batch that mixes real and complex operators is refused for the odd one
+    pr = I.small_problem(N=8, k=12, q=4, order=2, tol=1e-9)
+    mixed = probs[:1] + [dict(V=dev(pr.V), N=8, k=12, X0=dev(pr.start()), order=2)]
+    res = hb.solve_batched(mixed, 4, 1e-9, 5, check=False)
+    assert res[0][3] == "PPCG_OK" and res[1][3] == "PPCG_EINVAL"
+    hb.close()

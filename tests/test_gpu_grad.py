@@ -11,6 +11,10 @@ from oracle import grad as ograd  # noqa: E402
 from oracle import stencil  # noqa: E402
 from paper_1407_7506_amd import binding as B  # noqa: E402
 from paper_1407_7506_amd import inputs as I  # noqa: E402
+
+# iteration cap of every handle here: a solve that stops converging ends
+# with PPCG_ENOCONV in seconds instead of running 20000 iterations
+MAX_IT = 4000
 from paper_1407_7506_amd.autograd import EigConfig, EigDensity  # noqa: E402
 
 
@@ -32,7 +36,7 @@ def test_grad_matches_dense_formula(order):
     rng = np.random.default_rng(3)
     g = rng.standard_normal(k)
     w = rng.standard_normal(N ** 3)
-    h = B.Handle("fp64")
+    h = B.Handle("fp64", max_iter=MAX_IT)
     K = h.columns(k, q)
     lam, X, info = h.solve(dev(V), N, k, q, 1e-12, 5, dev(I.start_block(N ** 3, K, 5)), order=order)
     say("solve", info["iters"], "resid", info["resid_final"])
@@ -53,7 +57,7 @@ def test_grad_matches_oracle_sternheimer_wells32():
     """Same eigenvectors on both sides: the GPU block PCG vs the oracle's CG."""
     p = I.wells32()
     g = p.grid
-    h = B.Handle("fp64")
+    h = B.Handle("fp64", max_iter=MAX_IT)
     lam, X, info = h.solve(dev(p.V), g.N, p.k, p.q, 1e-10, p.rr_period, dev(p.start()), order=g.order)
     w = I.loss_weights(g.n, 305)
     gl = np.ones(p.k)
@@ -82,7 +86,7 @@ def test_fd_directions_wells32():
     L.backward()
     dV = V.grad.detach()
     dirs = I.unit_directions(g.n, 32, 405)
-    h = B.Handle("fp64")
+    h = B.Handle("fp64", max_iter=MAX_IT)
     eps = 1e-5
 
     def loss(Vv):

@@ -18,6 +18,10 @@ from oracle import brute, ppcg_ref, stencil  # noqa: E402
 from paper_1407_7506_amd import binding as B  # noqa: E402
 from paper_1407_7506_amd import inputs as I  # noqa: E402
 
+# iteration cap of every handle here: a solve that stops converging ends
+# with PPCG_ENOCONV in seconds instead of running 20000 iterations
+MAX_IT = 4000
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
@@ -27,14 +31,14 @@ def say(*a):
 
 @pytest.fixture(scope="module")
 def h64():
-    h = B.Handle("fp64")
+    h = B.Handle("fp64", max_iter=MAX_IT)
     yield h
     h.close()
 
 
 @pytest.fixture(scope="module")
 def hmix():
-    h = B.Handle("mixed")
+    h = B.Handle("mixed", max_iter=MAX_IT)
     yield h
     h.close()
 
@@ -87,6 +91,8 @@ SMALL = [
     dict(N=12, k=24, q=16, order=2, nbuf=8),   # q = 16, K = 32
     dict(N=8, k=6, q=1, order=2),              # single-column blocks (Algorithm 2)
     dict(N=10, k=15, q=5, order=2, rr_period=1),
+    dict(N=10, k=36, q=20, order=2),           # 2q = 40 and 3q = 60: LDS and device-scratch pencils
+    dict(N=12, k=60, q=32, order=4),           # q = 32: 96 x 96 pencils in device scratch
 ]
 
 
@@ -94,7 +100,7 @@ SMALL = [
 def test_fp64_matches_oracle(h64, case):
     p = I.small_problem(tol=1e-9, **case)
     if p.nbuf != I.default_nbuf(p.k, p.q):
-        h = B.Handle("fp64", nbuf=p.nbuf)
+        h = B.Handle("fp64", nbuf=p.nbuf, max_iter=MAX_IT)
     else:
         h = h64
     say("fp64 vs oracle", p.name, "K", p.K)
@@ -179,7 +185,7 @@ def test_error_paths(h64):
     with pytest.raises(B.PPCGError) as e:
         h64.solve(dev(p.V), g.N, p.k, p.q, 1e-6, 5, dev(X0))
     assert e.value.status == "PPCG_ERANK"
-    h2 = B.Handle("fp64", nbuf=2)                 # K = 14 is not a multiple of sbsize 4
+    h2 = B.Handle("fp64", nbuf=2, max_iter=MAX_IT)                 # K = 14 is not a multiple of sbsize 4
     with pytest.raises(B.PPCGError) as e:
         h2.solve(dev(p.V), g.N, p.k, 4, 1e-6, 5, dev(I.start_block(g.n, 14, 3)))
     assert e.value.status == "PPCG_EINVAL"
