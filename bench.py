@@ -40,8 +40,14 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
+F32_KERNELS = ("gram_proj", "update_proj", "stencil_f32")
+
+
 def roofline(kt, precision):
-    """Dominant kernel (largest device time with an algorithmic model)."""
+    """Dominant kernel (largest device time among kernels with an algorithmic
+    model), placed on the roofline by its own arithmetic intensity: MFMA-bound
+    when its flops at the dtype's dense peak take longer than its compulsory
+    bytes at the HBM peak, else HBM-bound."""
     best = None
     for name, (ms, cnt, fl, by) in kt.items():
         if cnt == 0 or (fl <= 0 and by <= 0):
@@ -51,18 +57,20 @@ def roofline(kt, precision):
     if best is None:
         return None
     name, ms, cnt, fl, by = best
-    mfma = name.startswith("gram") or name.startswith("update")
-    if mfma:
-        f32 = precision == "mixed" and name in ("gram_proj", "update_proj")
+    f32 = precision == "mixed" and name in F32_KERNELS
+    pflops = PEAK["f32"] if f32 else PEAK["f64"]
+    t_flop = fl / (pflops * 1e12)
+    t_byte = by / (PEAK["hbm"] * 1e9)
+    if t_flop >= t_byte:
         achieved = fl / (ms * 1e-3) / 1e12
-        peak = PEAK["f32"] if f32 else PEAK["f64"]
-        out = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-               "frac": round(achieved / peak, 4), "kernel": name, "dtype": "f32" if f32 else "f64"}
+        out = {"bound": "mfma", "achieved": round(achieved, 2), "peak": pflops, "unit": "TFLOP/s",
+               "frac": round(achieved / pflops, 4)}
     else:
         achieved = by / (ms * 1e-3) / 1e9
         out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK["hbm"], "unit": "GB/s",
-               "frac": round(achieved / PEAK["hbm"], 4), "kernel": name}
-    out.update({"launches": cnt, "avg_launch_us": round(ms / cnt * 1e3, 2),
+               "frac": round(achieved / PEAK["hbm"], 4)}
+    out.update({"kernel": name, "dtype": "f32" if f32 else "f64", "launches": cnt,
+                "avg_launch_us": round(ms / cnt * 1e3, 2),
                 "algorithmic_flops_per_launch": fl / cnt, "algorithmic_bytes_per_launch": by / cnt,
                 "traffic": traffic_for(name)})
     return out

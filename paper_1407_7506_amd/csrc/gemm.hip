@@ -7,6 +7,8 @@
 // W = AX - X (X^H A X) (section 2) and the Rayleigh-Ritz Grams and rotation
 // (section 5.6).  Real operands use one MFMA per 16x16x4 tile; complex
 // operands four (real and imaginary parts in separate accumulators).
+#include <type_traits>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -258,6 +260,57 @@ __global__ __launch_bounds__(256) void reduce_grouped(const ReduceArgs* jobs, co
 // 16 consecutive rows of a column per lane group.  Lane group g reads
 // Q consecutive k of the small matrix B in one vector load.
 // ---------------------------------------------------------------------------
+// epilogue of the update kernels: the wave's (16 TJ) x (16 TR) tile of the
+// transposed product, at output column j0 and row r0
+template <class T, int TJ, int TR, bool CPLX>
+PPCG_DEV void update_epilogue(const UpdateArgs& a, int job, int j0, long r0,
+                              const typename AccT<T>::type (&acc)[CPLX ? 2 : 1][TJ][TR]) {
+  constexpr int NC = CPLX ? 2 : 1;
+  const int l = threadIdx.x & 63, lc = l & 15;
+  const T alpha = (T)a.alpha, beta = (T)a.beta;
+#pragma unroll
+  for (int x = 0; x < TJ; ++x)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      int j = j0 + 16 * x + acc_row<T>(l, v);
+      if (j >= a.N) continue;
+      T* cp;
+      bool scaled;
+      if (j < a.N0) {
+        cp = (T*)a.C0 + ((long)job * a.job_c_off + (long)j * a.ldc) * NC;
+        scaled = a.dsc != nullptr;
+      } else {
+        cp = (T*)a.C1 + ((long)job * a.job_c_off + (long)(j - a.N0) * a.ldc) * NC;
+        scaled = false;
+      }
+      float* c32 = a.C32 ? (float*)a.C32 + ((long)job * a.job_c_off + (long)j * a.ldc) * NC : nullptr;
+#pragma unroll
+      for (int y = 0; y < TR; ++y) {
+        long r = (r0 + 16 * y + lc) * NC;
+        T v0 = alpha * acc[0][x][y][v];
+        T v1 = CPLX ? alpha * acc[NC - 1][x][y][v] : (T)0;
+        if (a.beta != 0) {
+          T c0 = cp[r], c1 = CPLX ? cp[r + 1] : (T)0;
+          if (scaled) {
+            T d = (T)a.dsc[r / NC];
+            c0 *= d;
+            c1 *= d;
+          }
+          v0 += beta * c0;
+          v1 += beta * c1;
+        }
+        if (!a.c0_keep) {
+          cp[r] = v0;
+          if (CPLX) cp[r + 1] = v1;
+        }
+        if (c32) {
+          c32[r] = (float)v0;
+          if (CPLX) c32[r + 1] = (float)v1;
+        }
+      }
+    }
+}
+
 template <class T, int TJ, int TR, bool CPLX>
 PPCG_DEV void update_body(const UpdateArgs& a, unsigned wg, unsigned nwg) {
   constexpr int Q = 4;
@@ -329,48 +382,7 @@ PPCG_DEV void update_body(const UpdateArgs& a, unsigned wg, unsigned nwg) {
           }
         }
   }
-  const T alpha = (T)a.alpha, beta = (T)a.beta;
-#pragma unroll
-  for (int x = 0; x < TJ; ++x)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      int j = j0 + 16 * x + acc_row<T>(l, v);
-      if (j >= a.N) continue;
-      T* cp;
-      bool scaled;
-      if (j < a.N0) {
-        cp = (T*)a.C0 + ((long)job * a.job_c_off + (long)j * a.ldc) * NC;
-        scaled = a.dsc != nullptr;
-      } else {
-        cp = (T*)a.C1 + ((long)job * a.job_c_off + (long)(j - a.N0) * a.ldc) * NC;
-        scaled = false;
-      }
-      float* c32 = a.C32 ? (float*)a.C32 + ((long)job * a.job_c_off + (long)j * a.ldc) * NC : nullptr;
-#pragma unroll
-      for (int y = 0; y < TR; ++y) {
-        long r = (r0 + 16 * y + lc) * NC;
-        T v0 = alpha * acc[0][x][y][v];
-        T v1 = CPLX ? alpha * acc[NC - 1][x][y][v] : (T)0;
-        if (a.beta != 0) {
-          T c0 = cp[r], c1 = CPLX ? cp[r + 1] : (T)0;
-          if (scaled) {
-            T d = (T)a.dsc[r / NC];
-            c0 *= d;
-            c1 *= d;
-          }
-          v0 += beta * c0;
-          v1 += beta * c1;
-        }
-        if (!a.c0_keep) {
-          cp[r] = v0;
-          if (CPLX) cp[r + 1] = v1;
-        }
-        if (c32) {
-          c32[r] = (float)v0;
-          if (CPLX) c32[r + 1] = (float)v1;
-        }
-      }
-    }
+  update_epilogue<T, TJ, TR, CPLX>(a, job, j0, r0, acc);
 }
 
 template <class T, int TJ, int TR, bool CPLX, int SITE>
@@ -384,27 +396,300 @@ __global__ __launch_bounds__(64) void update_grouped(const UpdateArgs* jobs, con
 }
 
 // ---------------------------------------------------------------------------
+// LDS-staged variants for large real shapes.  A workgroup of four waves
+// (2 x 2) owns a 128 x 128 output tile.  Each chunk of KC reduction indices
+// (rows of the tall operands for gram, columns of A for update) of both
+// operands is loaded once per workgroup into LDS (double buffered, one
+// barrier per chunk, the next chunk's global loads in flight during the
+// MFMAs of the current one) and every wave computes its 64 x 64 quadrant
+// from it: half the L2-to-CU traffic per flop of the one-wave kernels.
+// Panels whose reads are 4 consecutive reduction indices per lane use the
+// column stride KC + 2 (float64) or KC + 4 (float32) elements, so that the
+// 16-byte reads of 8 consecutive lanes fall into distinct bank groups.
+// ---------------------------------------------------------------------------
+constexpr int LB = 128;  // workgroup tile edge of the LDS-staged kernels
+template <class T, int KC> struct LdsPad { static constexpr int S = KC + (sizeof(T) == 8 ? 2 : 4); };
+
+PPCG_DEV void put4(double* d, const double* v) {
+  ((double2*)d)[0] = make_double2(v[0], v[1]);
+  ((double2*)d)[1] = make_double2(v[2], v[3]);
+}
+PPCG_DEV void put4(float* d, const float* v) { *(float4*)d = make_float4(v[0], v[1], v[2], v[3]); }
+PPCG_DEV void get4(const double* d, double* v) {
+  double2 x = ((const double2*)d)[0], y = ((const double2*)d)[1];
+  v[0] = x.x; v[1] = x.y; v[2] = y.x; v[3] = y.y;
+}
+PPCG_DEV void get4(const float* d, float* v) {
+  float4 x = *(const float4*)d;
+  v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+}
+
+// gram, C (M x N) partial over rows [rbeg, rend) of split s; real operands
+template <class T, int KC>
+PPCG_DEV void gram_lds_body(const GramArgs& a, unsigned wg, unsigned nwg) {
+  constexpr int S = LdsPad<T, KC>::S;
+  constexpr int PQ = KC / 4;             // quads (4 consecutive rows) per column and chunk
+  constexpr int NQ = LB * PQ / 256;      // quads per thread and panel
+  constexpr int CS = 256 / PQ;           // column step between a thread's quads
+  __shared__ __align__(16) T As[2][LB * S];
+  __shared__ __align__(16) T Bs[2][LB * S];
+  typedef typename AccT<T>::type acc_t;
+  const int tid = threadIdx.x, l = tid & 63, lc = l & 15, g = l >> 4;
+  const int wi = (tid >> 6) & 1, wj = tid >> 7;
+  unsigned L = xcd_remap(wg, nwg);
+  const int ntile = a.tiles_i * a.tiles_j;
+  const int tile = L % ntile;
+  const int rest = L / ntile;
+  const int split = rest % a.splits;
+  const int job = rest / a.splits;
+  const int ti = tile % a.tiles_i, tj = tile / a.tiles_i;
+  if (a.upper_only && ti > tj) return;  // tile wholly below the diagonal (uniform per workgroup)
+  const int i0 = ti * LB, j0 = tj * LB;
+  const long joff = (long)job * a.job_col_off;
+  const long rbeg = (long)split * a.chunk;
+  const long rend = rbeg + a.chunk < a.rows ? rbeg + a.chunk : a.rows;
+  const int nch = rend > rbeg ? (int)((rend - rbeg) / KC) : 0;
+
+  const int part = tid % PQ;
+  const char* pa[NQ];
+  const char* pb[NQ];
+  bool fa[NQ], fb[NQ], va[NQ], vb[NQ], sb[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int col = tid / PQ + q * CS;
+    const int ca = i0 + col, cb = j0 + col;
+    va[q] = ca < a.M;
+    vb[q] = cb < a.N;
+    pa[q] = (const char*)seg_col(a.A, va[q] ? ca : 0, a.ld, joff, fa[q], 8);
+    pb[q] = (const char*)seg_col(a.B, vb[q] ? cb : 0, a.ld, joff, fb[q], 8);
+    sb[q] = a.dsc != nullptr && cb < a.nsc;
+  }
+  T ra[NQ][4], rb[NQ][4];
+  auto gload = [&](long r) {
+    const long rr = r + 4 * part;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      if (va[q]) {
+        Load4<T, false>::go(pa[q] + rr * (fa[q] ? 4 : 8), fa[q], ra[q], nullptr);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) ra[q][e] = 0;
+      }
+      if (vb[q]) {
+        Load4<T, false>::go(pb[q] + rr * (fb[q] ? 4 : 8), fb[q], rb[q], nullptr);
+        if (sb[q]) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) rb[q][e] *= (T)a.dsc[rr + e];
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) rb[q][e] = 0;
+      }
+    }
+  };
+  auto sput = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int col = tid / PQ + q * CS;
+      put4(&As[buf][col * S + 4 * part], ra[q]);
+      put4(&Bs[buf][col * S + 4 * part], rb[q]);
+    }
+  };
+  acc_t acc[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[x][y] = acc_t{0, 0, 0, 0};
+  if (nch > 0) {
+    gload(rbeg);
+    sput(0);
+  }
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nch) gload(rbeg + (long)(c + 1) * KC);
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 16) {
+      T av[4][4], bv[4][4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        get4(&As[buf][(wi * 64 + 16 * t + lc) * S + kk + 4 * g], av[t]);
+        get4(&Bs[buf][(wj * 64 + 16 * t + lc) * S + kk + 4 * g], bv[t]);
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y) acc[x][y] = mfma(av[x][e], bv[y][e], acc[x][y]);
+    }
+    if (c + 1 < nch) sput(buf ^ 1);
+    __syncthreads();
+  }
+  T* out = (T*)a.out + ((long)job * a.splits + split) * a.split_stride;
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + wi * 64 + 16 * x + acc_row<T>(l, v);
+        const int j = j0 + wj * 64 + 16 * y + lc;
+        if (i < a.M && j < a.N) out[i + (long)j * a.ldo] = acc[x][y][v];
+      }
+}
+
+template <class T, int KC, int SITE>
+__global__ __launch_bounds__(256) void gram_lds_kernel(GramArgs a) {
+  gram_lds_body<T, KC>(a, blockIdx.x, gridDim.x);
+}
+template <class T, int KC, int SITE>
+__global__ __launch_bounds__(256) void gram_lds_grouped(const GramArgs* jobs, const unsigned* start, int nj) {
+  int j = find_job(start, nj, blockIdx.x);
+  gram_lds_body<T, KC>(jobs[j], blockIdx.x - start[j], start[j + 1] - start[j]);
+}
+
+// update, C (rows x N) = beta (D C) + alpha A B for one 128 x 128 tile; real
+template <class T, int KC>
+PPCG_DEV void update_lds_body(const UpdateArgs& a, unsigned wg, unsigned nwg) {
+  constexpr int SB = LdsPad<T, KC>::S;                 // B panel [col][k]
+  constexpr int SA = LB + (sizeof(T) == 8 ? 2 : 4);    // A panel [k][row]
+  constexpr int PE = 16 / (int)sizeof(T);              // rows per 16-byte piece of A
+  constexpr int PA = LB / PE;                          // pieces per column of the A panel
+  constexpr int NA = KC * PA / 256;                    // A pieces per thread
+  constexpr int PQ = KC / 4, NB = LB * PQ / 256;       // B quads per column / per thread
+  typedef typename AccT<T>::type acc_t;
+  typedef typename std::conditional<sizeof(T) == 8, double2, float4>::type v16;
+  __shared__ __align__(16) T As[2][KC * SA];
+  __shared__ __align__(16) T Bs[2][LB * SB];
+  const int tid = threadIdx.x, l = tid & 63, lc = l & 15, g = l >> 4;
+  const int wr = (tid >> 6) & 1, wj = tid >> 7;
+  unsigned L = xcd_remap(wg, nwg);
+  // column tiles fastest so the row panel of A is shared inside one XCD
+  const int tj = L % a.tiles_j;
+  const int rest = L / a.tiles_j;
+  const int tr = rest % a.tiles_r;
+  const int job = rest / a.tiles_r;
+  const int j0 = tj * LB;
+  const long r0 = (long)tr * LB;
+  const T* A = (const T*)a.A + (long)job * a.job_a_off;
+  const T* Bm = (const T*)a.B + (long)job * a.job_b_off;
+  int kend = a.K;
+  if (a.b_upper && j0 + LB < kend) kend = j0 + LB;
+  const int nch = (kend + KC - 1) / KC;
+  v16 ra[NA];
+  T rb[NB][4];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int pc = tid + 256 * q;
+      const int k = k0 + pc / PA, rp = pc % PA;
+      if (k < kend) ra[q] = *(const v16*)(A + r0 + rp * PE + (long)k * a.lda);
+      else ra[q] = v16{};
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int pc = tid + 256 * q;
+      const int j = j0 + pc / PQ, k = k0 + 4 * (pc % PQ);
+      const T* bp = Bm + (long)(j < a.N ? j : 0) * a.ldb;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) rb[q][e] = (j < a.N && k + e < kend) ? bp[k + e] : (T)0;
+    }
+  };
+  auto sput = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int pc = tid + 256 * q;
+      *(v16*)&As[buf][(pc / PA) * SA + (pc % PA) * PE] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int pc = tid + 256 * q;
+      put4(&Bs[buf][(pc / PQ) * SB + 4 * (pc % PQ)], rb[q]);
+    }
+  };
+  acc_t acc[1][4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[0][x][y] = acc_t{0, 0, 0, 0};
+  if (nch > 0) {
+    gload(0);
+    sput(0);
+  }
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nch) gload((c + 1) * KC);
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 16) {
+      T bv[4][4], av[4][4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) get4(&Bs[buf][(wj * 64 + 16 * x + lc) * SB + kk + 4 * g], bv[x]);
+#pragma unroll
+      for (int y = 0; y < 4; ++y)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) av[y][e] = As[buf][(kk + 4 * g + e) * SA + wr * 64 + 16 * y + lc];
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y) acc[0][x][y] = mfma(bv[x][e], av[y][e], acc[0][x][y]);
+    }
+    if (c + 1 < nch) sput(buf ^ 1);
+    __syncthreads();
+  }
+  update_epilogue<T, 4, 4, false>(a, job, j0 + wj * 64, r0 + wr * 64, acc);
+}
+
+template <class T, int KC, int SITE>
+__global__ __launch_bounds__(256) void update_lds_kernel(UpdateArgs a) {
+  update_lds_body<T, KC>(a, blockIdx.x, gridDim.x);
+}
+template <class T, int KC, int SITE>
+__global__ __launch_bounds__(256) void update_lds_grouped(const UpdateArgs* jobs, const unsigned* start, int nj) {
+  int j = find_job(start, nj, blockIdx.x);
+  update_lds_body<T, KC>(jobs[j], blockIdx.x - start[j], start[j + 1] - start[j]);
+}
+
+// ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
 constexpr int GTM = 4, GTN = 4, UTJ = 4, UTR = 4;   // real tiles
+constexpr int BTN = 5;  // real per-block Grams: 64 x 80 tiles, i.e. one tile per block for q <= 16
 constexpr int ZTM = 2, ZTN = 2, ZTJ = 2, ZTR = 2;   // complex tiles
 
+constexpr int GKC_D = 16, GKC_F = 32, UKC_D = 16, UKC_F = 32;  // LDS chunk depths
+
 void gram_tiles(GramArgs& a) {
-  int tm = a.cplx ? ZTM : GTM, tn = a.cplx ? ZTN : GTN;
+  if (a.lds) {
+    a.tiles_i = (a.M + LB - 1) / LB;
+    a.tiles_j = (a.N + LB - 1) / LB;
+    return;
+  }
+  int tm = a.cplx ? ZTM : GTM, tn = a.cplx ? ZTN : (a.site == 2 ? BTN : GTN);
   a.tiles_i = (a.M + 16 * tm - 1) / (16 * tm);
   a.tiles_j = (a.N + 16 * tn - 1) / (16 * tn);
 }
 void update_tiles(UpdateArgs& a) {
+  if (a.lds) {
+    a.tiles_j = (a.N + LB - 1) / LB;
+    a.tiles_r = (int)(a.rows / LB);
+    return;
+  }
   int tj = a.cplx ? ZTJ : UTJ, tr = a.cplx ? ZTR : UTR;
   a.tiles_j = (a.N + 16 * tj - 1) / (16 * tj);
   a.tiles_r = (int)(a.rows / (16 * tr));
 }
 
 static int gram_kind(const GramArgs& a, bool f32acc) {
+  if (a.lds) return (f32acc ? OP_GRAML_F0 : OP_GRAML_D0) + (a.site == 1 ? 1 : 0);
   int base = a.cplx ? (f32acc ? OP_GRAM_C0 : OP_GRAM_Z0) : (f32acc ? OP_GRAM_F0 : OP_GRAM_D0);
   return base + (a.site == 1 ? 1 : a.site == 2 ? 2 : 0);
 }
 static int update_kind(const UpdateArgs& a, bool f32) {
+  if (a.lds) return (f32 ? OP_UPDATEL_F0 : OP_UPDATEL_D0) + (a.site == 1 ? 1 : 0);
   int base = a.cplx ? (f32 ? OP_UPDATE_C0 : OP_UPDATE_Z0) : (f32 ? OP_UPDATE_F0 : OP_UPDATE_D0);
   return base + (a.site == 1 ? 1 : 0);
 }
@@ -412,16 +697,28 @@ static int update_kind(const UpdateArgs& a, bool f32) {
 #define PPCG_GRAM_CASES(KERNEL, GRID, ...)                                                                       \
   case OP_GRAM_D0: hipLaunchKernelGGL((KERNEL<double, GTM, GTN, false, 0>), dim3(GRID), dim3(64), 0, st, __VA_ARGS__); break; \
   case OP_GRAM_D1: hipLaunchKernelGGL((KERNEL<double, GTM, GTN, false, 1>), dim3(GRID), dim3(64), 0, st, __VA_ARGS__); break; \
-  case OP_GRAM_D2: hipLaunchKernelGGL((KERNEL<double, GTM, GTN, false, 2>), dim3(GRID), dim3(64), 0, st, __VA_ARGS__); break; \
+  case OP_GRAM_D2: hipLaunchKernelGGL((KERNEL<double, GTM, BTN, false, 2>), dim3(GRID), dim3(64), 0, st, __VA_ARGS__); break; \
   case OP_GRAM_F0: hipLaunchKernelGGL((KERNEL<float, GTM, GTN, false, 0>), dim3(GRID), dim3(64), 0, st, __VA_ARGS__); break;  \
   case OP_GRAM_F1: hipLaunchKernelGGL((KERNEL<float, GTM, GTN, false, 1>), dim3(GRID), dim3(64), 0, st, __VA_ARGS__); break;  \
-  case OP_GRAM_F2: hipLaunchKernelGGL((KERNEL<float, GTM, GTN, false, 2>), dim3(GRID), dim3(64), 0, st, __VA_ARGS__); break;  \
+  case OP_GRAM_F2: hipLaunchKernelGGL((KERNEL<float, GTM, BTN, false, 2>), dim3(GRID), dim3(64), 0, st, __VA_ARGS__); break;  \
   case OP_GRAM_Z0: hipLaunchKernelGGL((KERNEL<double, ZTM, ZTN, true, 0>), dim3(GRID), dim3(64), 0, st, __VA_ARGS__); break;  \
   case OP_GRAM_Z1: hipLaunchKernelGGL((KERNEL<double, ZTM, ZTN, true, 1>), dim3(GRID), dim3(64), 0, st, __VA_ARGS__); break;  \
   case OP_GRAM_Z2: hipLaunchKernelGGL((KERNEL<double, ZTM, ZTN, true, 2>), dim3(GRID), dim3(64), 0, st, __VA_ARGS__); break;  \
   case OP_GRAM_C0: hipLaunchKernelGGL((KERNEL<float, ZTM, ZTN, true, 0>), dim3(GRID), dim3(64), 0, st, __VA_ARGS__); break;   \
   case OP_GRAM_C1: hipLaunchKernelGGL((KERNEL<float, ZTM, ZTN, true, 1>), dim3(GRID), dim3(64), 0, st, __VA_ARGS__); break;   \
   case OP_GRAM_C2: hipLaunchKernelGGL((KERNEL<float, ZTM, ZTN, true, 2>), dim3(GRID), dim3(64), 0, st, __VA_ARGS__); break;
+
+#define PPCG_GRAML_CASES(KERNEL, GRID, ...)                                                                      \
+  case OP_GRAML_D0: hipLaunchKernelGGL((KERNEL<double, GKC_D, 0>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break; \
+  case OP_GRAML_D1: hipLaunchKernelGGL((KERNEL<double, GKC_D, 1>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break; \
+  case OP_GRAML_F0: hipLaunchKernelGGL((KERNEL<float, GKC_F, 0>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;  \
+  case OP_GRAML_F1: hipLaunchKernelGGL((KERNEL<float, GKC_F, 1>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;
+
+#define PPCG_UPDATEL_CASES(KERNEL, GRID, ...)                                                                    \
+  case OP_UPDATEL_D0: hipLaunchKernelGGL((KERNEL<double, UKC_D, 0>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break; \
+  case OP_UPDATEL_D1: hipLaunchKernelGGL((KERNEL<double, UKC_D, 1>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break; \
+  case OP_UPDATEL_F0: hipLaunchKernelGGL((KERNEL<float, UKC_F, 0>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;  \
+  case OP_UPDATEL_F1: hipLaunchKernelGGL((KERNEL<float, UKC_F, 1>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;
 
 #define PPCG_UPDATE_CASES(KERNEL, GRID, ...)                                                                     \
   case OP_UPDATE_D0: hipLaunchKernelGGL((KERNEL<double, UTJ, UTR, false, 0>), dim3(GRID), dim3(64), 0, st, __VA_ARGS__); break; \
@@ -433,8 +730,16 @@ static int update_kind(const UpdateArgs& a, bool f32) {
   case OP_UPDATE_C0: hipLaunchKernelGGL((KERNEL<float, ZTJ, ZTR, true, 0>), dim3(GRID), dim3(64), 0, st, __VA_ARGS__); break;   \
   case OP_UPDATE_C1: hipLaunchKernelGGL((KERNEL<float, ZTJ, ZTR, true, 1>), dim3(GRID), dim3(64), 0, st, __VA_ARGS__); break;
 
+static bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
 void launch_gram(const GramArgs& a0, bool f32acc, hipStream_t st) {
   GramArgs a = a0;
+  if (a.lds) {  // the LDS-staged kernel's preconditions; otherwise the one-wave kernel
+    bool ok = !a.cplx && a.njobs == 1 && a.chunk % 32 == 0 && a.ld % 4 == 0;
+    for (int s = 0; s < a.A.nseg; ++s) ok = ok && aligned16(a.A.p[s]);
+    for (int s = 0; s < a.B.nseg; ++s) ok = ok && aligned16(a.B.p[s]);
+    a.lds = ok;
+  }
   gram_tiles(a);
   unsigned blocks = (unsigned)((long)a.tiles_i * a.tiles_j * a.splits * a.njobs);
   if (blocks == 0) return;
@@ -443,7 +748,11 @@ void launch_gram(const GramArgs& a0, bool f32acc, hipStream_t st) {
     g_rec->add(kind, &a, sizeof(a), blocks);
     return;
   }
-  switch (kind) { PPCG_GRAM_CASES(gram_kernel, blocks, a) default: break; }
+  switch (kind) {
+    PPCG_GRAM_CASES(gram_kernel, blocks, a)
+    PPCG_GRAML_CASES(gram_lds_kernel, blocks, a)
+    default: break;
+  }
 }
 
 static int reduce_kind(const ReduceArgs& r, bool f32) {
@@ -469,6 +778,9 @@ void launch_reduce(const ReduceArgs& r, bool f32, hipStream_t st) {
 
 void launch_update(const UpdateArgs& a0, bool f32, hipStream_t st) {
   UpdateArgs a = a0;
+  if (a.lds)  // the LDS-staged kernel's preconditions; otherwise the one-wave kernel
+    a.lds = !a.cplx && a.rows % LB == 0 && a.lda % 4 == 0 && aligned16(a.A) && a.job_a_off == 0 &&
+            a.job_b_off == 0 && a.job_c_off == 0;
   update_tiles(a);
   unsigned blocks = (unsigned)((long)a.tiles_j * a.tiles_r);
   if (blocks == 0) return;
@@ -477,7 +789,11 @@ void launch_update(const UpdateArgs& a0, bool f32, hipStream_t st) {
     g_rec->add(kind, &a, sizeof(a), blocks);
     return;
   }
-  switch (kind) { PPCG_UPDATE_CASES(update_kernel, blocks, a) default: break; }
+  switch (kind) {
+    PPCG_UPDATE_CASES(update_kernel, blocks, a)
+    PPCG_UPDATEL_CASES(update_lds_kernel, blocks, a)
+    default: break;
+  }
 }
 
 bool launch_grouped_gemm(int kind, const void* jobs, const unsigned* start, int nj, unsigned total, hipStream_t st) {
@@ -487,6 +803,8 @@ bool launch_grouped_gemm(int kind, const void* jobs, const unsigned* start, int 
   switch (kind) {
     PPCG_GRAM_CASES(gram_grouped, total, gj, start, nj)
     PPCG_UPDATE_CASES(update_grouped, total, uj, start, nj)
+    PPCG_GRAML_CASES(gram_lds_grouped, total, gj, start, nj)
+    PPCG_UPDATEL_CASES(update_lds_grouped, total, uj, start, nj)
     case OP_REDUCE_D: hipLaunchKernelGGL((reduce_grouped<double, false>), dim3(total), dim3(256), 0, st, rj, start, nj); break;
     case OP_REDUCE_F: hipLaunchKernelGGL((reduce_grouped<float, false>), dim3(total), dim3(256), 0, st, rj, start, nj); break;
     case OP_REDUCE_Z: hipLaunchKernelGGL((reduce_grouped<double, true>), dim3(total), dim3(256), 0, st, rj, start, nj); break;

@@ -45,6 +45,7 @@ struct GramArgs {
   int njobs;          // strided jobs (blocks) inside this gram
   int site;           // call site (selects a distinct kernel symbol for profiling)
   int cplx;           // complex operands (f32 segments then mean complex float)
+  int lds;            // 1: LDS-staged 128 x 128 workgroup tiles (real, one job, chunk % 32 == 0)
 };
 
 struct ReduceArgs {
@@ -79,6 +80,7 @@ struct UpdateArgs {
   int tiles_j, tiles_r;
   int site;        // call site (selects a distinct kernel symbol for profiling)
   int cplx;        // complex A, B, C (C32 then complex float)
+  int lds;         // 1: LDS-staged 128 x 128 workgroup tiles (real, one job, rows % 128 == 0)
 };
 
 // stencil: Y = H X on an N^3 periodic grid (7- or 13-point), columns [0, ncols)
@@ -155,9 +157,11 @@ struct D2HArgs { void* dst; const void* src; size_t bytes; };
 enum OpKind : int {
   OP_GRAM_D0, OP_GRAM_D1, OP_GRAM_D2, OP_GRAM_F0, OP_GRAM_F1, OP_GRAM_F2,
   OP_GRAM_Z0, OP_GRAM_Z1, OP_GRAM_Z2, OP_GRAM_C0, OP_GRAM_C1, OP_GRAM_C2,
+  OP_GRAML_D0, OP_GRAML_D1, OP_GRAML_F0, OP_GRAML_F1,
   OP_REDUCE_D, OP_REDUCE_F, OP_REDUCE_Z, OP_REDUCE_C,
   OP_UPDATE_D0, OP_UPDATE_D1, OP_UPDATE_F0, OP_UPDATE_F1,
   OP_UPDATE_Z0, OP_UPDATE_Z1, OP_UPDATE_C0, OP_UPDATE_C1,
+  OP_UPDATEL_D0, OP_UPDATEL_D1, OP_UPDATEL_F0, OP_UPDATEL_F1,
   OP_STENCIL_D2, OP_STENCIL_D4, OP_STENCIL_F2, OP_STENCIL_F4,
   OP_STENCIL_Z2, OP_STENCIL_Z4, OP_STENCIL_C2, OP_STENCIL_C4,
   OP_COLNORM_D, OP_COLNORM_F, OP_RITZ,

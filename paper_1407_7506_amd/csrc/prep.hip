@@ -47,9 +47,9 @@ bool launch_grouped_prep(int kind, const void* jobs, const unsigned* start, int 
 }
 
 size_t op_args_size(int kind) {
-  if (kind >= OP_GRAM_D0 && kind <= OP_GRAM_C2) return sizeof(GramArgs);
+  if (kind >= OP_GRAM_D0 && kind <= OP_GRAML_F1) return sizeof(GramArgs);
   if (kind >= OP_REDUCE_D && kind <= OP_REDUCE_C) return sizeof(ReduceArgs);
-  if (kind >= OP_UPDATE_D0 && kind <= OP_UPDATE_C1) return sizeof(UpdateArgs);
+  if (kind >= OP_UPDATE_D0 && kind <= OP_UPDATEL_F1) return sizeof(UpdateArgs);
   if (kind >= OP_STENCIL_D2 && kind <= OP_STENCIL_C4) return sizeof(StencilArgs);
   if (kind >= OP_PENCIL24 && kind <= OP_PENCILZ96) return sizeof(PencilArgs);
   if (kind >= OP_BUPD_D4 && kind <= OP_BUPD_C32) return sizeof(BlockUpdArgs);

@@ -388,11 +388,33 @@ struct Prob {
     return 0;
   }
 
-  static int pick_splits(long tiles, long njobs, long rws) {
-    long target = 2048;
-    long s = (target + tiles * njobs - 1) / (tiles * njobs);
-    long maxs = std::max(1L, rws / 256);
-    return (int)std::max(1L, std::min(s, maxs));
+  // Gram kernel choice and row splitting.  Large real single-job Grams use
+  // the LDS-staged kernel (128 x 128 workgroup tiles, 4 waves): about 4096
+  // workgroups but no fewer than ~1000 rows per split.  The one-wave kernel
+  // (64 x 64 tiles) aims at 2048 workgroups.
+  struct GramPlan {
+    bool lds;
+    int splits;
+    long chunk;
+  };
+  GramPlan gram_plan(int M, int Nn, int njobs, long rws, int site = 0) const {
+    GramPlan g;
+    g.lds = !cplx && njobs == 1 && std::min(M, Nn) >= 96;
+    long tiles, s, maxs;
+    if (g.lds) {
+      tiles = (long)((M + 127) / 128) * ((Nn + 127) / 128);
+      s = (4096 + tiles - 1) / tiles;
+      maxs = std::max(1L, rws / 1024);
+    } else {
+      const int tn = (site == 2 && !cplx) ? 80 : 64;  // per-block Grams use 64 x 80 tiles
+      tiles = (long)((M + 63) / 64) * ((Nn + tn - 1) / tn) * njobs;
+      s = (2048 + tiles - 1) / tiles;
+      maxs = std::max(1L, rws / 256);
+    }
+    s = std::max(1L, std::min(s, maxs));
+    g.chunk = round_up((rws + s - 1) / s, 32);
+    g.splits = (int)((rws + g.chunk - 1) / g.chunk);
+    return g;
   }
 
   // dst (M x N, ldd) = A^H (D B) over `rws` rows; njobs strided jobs
@@ -400,14 +422,17 @@ struct Prob {
             void* dst, int ldd, bool upper, bool f32acc, int njobs = 1, long job_col_off = 0,
             long dst_job_stride = 0, const char* name = "gram") {
     if (M <= 0 || Nn <= 0) return;
-    long tiles = (long)((M + 63) / 64) * ((Nn + 63) / 64);
-    int splits = pick_splits(tiles, njobs, rws);
+    GramPlan plan = gram_plan(M, Nn, njobs, rws, site_of(name));
     size_t es = (f32acc ? 4 : 8) * nc();
     size_t one = (size_t)njobs * M * Nn * es;
     if (one > Wk.part.bytes) throw PpcgError{PPCG_EINVAL, "internal: partial buffer too small"};
-    splits = (int)std::min<size_t>((size_t)splits, Wk.part.bytes / one);
-    long chunk = round_up((rws + splits - 1) / splits, 16);
-    splits = (int)((rws + chunk - 1) / chunk);
+    if ((size_t)plan.splits * one > Wk.part.bytes) {  // fewer, longer splits
+      long sp = (long)(Wk.part.bytes / one);
+      plan.chunk = round_up((rws + sp - 1) / sp, 32);
+      plan.splits = (int)((rws + plan.chunk - 1) / plan.chunk);
+    }
+    const int splits = plan.splits;
+    const long chunk = plan.chunk;
     GramArgs g{};
     g.A = A;
     g.B = B;
@@ -427,6 +452,7 @@ struct Prob {
     g.njobs = njobs;
     g.site = site_of(name);
     g.cplx = cplx;
+    g.lds = plan.lds;
     {
       double nn = (double)std::min(rws, n), es_in = (f32acc ? 4.0 : 8.0) * nc();
       double fl = (upper ? (double)M * (M + 1) * nn : 2.0 * M * Nn * nn) * (cplx ? 4 : 1);
@@ -478,6 +504,7 @@ struct Prob {
     u.c0_keep = c0_keep;
     u.site = site_of(name);
     u.cplx = cplx;
+    u.lds = !cplx && rws % 128 == 0 && Nn >= 96;
     double nn = (double)std::min(rws, n), es = (f32 ? 4.0 : 8.0) * nc();
     double fl = (b_upper ? (double)Nn * (Nn + 1) * nn : 2.0 * Kk * Nn * nn) * (cplx ? 4 : 1);
     double by = ((double)Kk + Nn * (beta != 0 ? 2.0 : 1.0)) * nn * es + (C32 ? 4.0 * nc() * Nn * nn : 0.0);
@@ -530,16 +557,19 @@ struct Prob {
     Wk.eigw.ensure(eig_workspace_bytes(K, cplx));
     // split partials: the largest Gram of the run
     size_t need = 0;
-    auto acc = [&](long M, long Nn, long njobs, long rws, size_t es) {
-      long tiles = ((M + 63) / 64) * ((Nn + 63) / 64);
-      int sp = pick_splits(tiles, njobs, rws);
-      long chunk = round_up((rws + sp - 1) / sp, 16);
-      sp = (int)((rws + chunk - 1) / chunk);
-      need = std::max(need, (size_t)njobs * sp * M * Nn * es);
+    auto acc = [&](int M, int Nn, int njobs, long rws, size_t es, int site = 0) {
+      // the largest partial set over every shape up to M x Nn (active widths
+      // shrink with locking; every width is a multiple of q) and job count
+      for (int jb = 1; jb <= njobs; ++jb)
+        for (int mm = std::min(q, M); mm <= M; mm += q)
+          for (int nn = std::min(q, Nn); nn <= Nn; nn += q) {
+            GramPlan pl = gram_plan(mm, nn, jb, rws, site);
+            need = std::max(need, (size_t)jb * pl.splits * mm * nn * es);
+          }
     };
     acc(K, 2 * K, 1, rows, esz());
     acc(K, K, 1, rows, xs());
-    acc(nS + q, 2 * nS - q, s, rows, xs());
+    acc(nS + q, 2 * nS - q, s, rows, xs(), 2);
     acc(K, K, 1, Kp, xs());
     Wk.part.ensure(need);
     Wk.pinned((size_t)(4 * Kp + 64) * 8);
@@ -1157,8 +1187,11 @@ struct Grad {
            *bb = sc + 5 * kp, *rr = sc + 6 * kp;
     int* done = (int*)(sc + 7 * kp);
     int* left = (int*)(sc + 8 * kp);
-    // the partial buffer must hold a k x k Gram
-    Wk.part.ensure((size_t)k * k * 8 * 4);
+    // the partial buffer holds the split partials of the k x k projection Gram
+    {
+      Prob tmp(H, Wk);
+      Wk.part.ensure((size_t)tmp.gram_plan(k, k, 1, rows).splits * k * k * 8);
+    }
     HIPCHECK(hipMemsetAsync(H->gw.p, 0, H->gw.bytes, st));
     HIPCHECK(hipMemcpyAsync(H->gw.p, w, n * 8, hipMemcpyDeviceToDevice, st));
     double *Z = H->gZ.d(), *R = H->gR.d(), *P = H->gP.d(), *AP = H->gAP.d(), *Y = H->gY.d();
