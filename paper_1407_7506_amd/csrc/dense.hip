@@ -476,6 +476,13 @@ bool launch_grouped_dense(int kind, const void* jobs, const unsigned* start, int
 constexpr int JB = 16;           // block width
 constexpr int J2 = 2 * JB;       // pair size
 constexpr int JLD = J2 + 1;
+#ifndef PPCG_BJ_INNER
+#define PPCG_BJ_INNER 1
+#endif
+// Inner Jacobi sweeps per pair eigensolve.  The pair problem need not be
+// diagonalised exactly: the outer loop ends only after a sweep in which no
+// off-diagonal entry anywhere exceeds the threshold, whatever the inner count.
+constexpr int BJ_INNER = PPCG_BJ_INNER;
 // Rotations are skipped once |M_pq| <= rel_tol |M|_F.  Off-diagonal entries
 // of that size change the Ritz residual of a column by at most
 // rel_tol |M|_F sqrt(K) (the caller keeps this far below its locking
@@ -585,7 +592,7 @@ PPCG_DEV void bj_pair_body(const EigDev& a, int round, unsigned t) {
     if (tid == 0) a.flags[t] = 0;
     return;
   }
-  lds_jacobi<256, S>(Sm, Qs, n2, JLD, tiny, 40, cs, uu, pq, &cnt);
+  lds_jacobi<256, S>(Sm, Qs, n2, JLD, tiny, BJ_INNER, cs, uu, pq, &cnt);
   S* Qg = (S*)a.Q + (long)t * J2 * J2;
   for (int e = tid; e < n2 * n2; e += 256) Qg[(e % n2) + (e / n2) * J2] = Qs[(e % n2) + (e / n2) * JLD];
   if (tid == 0) {
@@ -594,57 +601,93 @@ PPCG_DEV void bj_pair_body(const EigDev& a, int round, unsigned t) {
   }
 }
 
-// which = 0: rows of the pair, M[rows, chunk] <- Q^H M[rows, chunk]
-// which = 1: columns of the pair for M and Vt, A[chunk, cols] <- A[chunk, cols] Q
+// One round's two-sided update in a single launch.  Items [0, np^2): the
+// tile (rows of pair a) x (columns of pair b) of M becomes Q_a^H M_ab Q_b
+// (Q = I for a pair that did not rotate); tiles are disjoint, so no item
+// depends on another.  Items [np^2, np^2 + np * ceil(m/64)): 64 rows of the
+// accumulated rotations, Vt[rows, cols of pair b] <- Vt[rows, cols] Q_b.
 template <class S>
-PPCG_DEV void bj_apply_body(const EigDev& a, int round, unsigned wg, int which) {
-  __shared__ S Qs[J2 * JLD], R[64 * (J2 + 1)];
+PPCG_DEV void bj_update_body(const EigDev& a, int round, unsigned wg) {
+  __shared__ S sh[4 * J2 * JLD];
   if (round >= a.nbe - 1) return;
-  const int t = (int)(wg % a.np);
-  const int chunk = (int)(wg / a.np);
-  if (!a.flags[t]) return;
   const int tid = threadIdx.x;
-  int nI, nJ, i0, j0;
-  pair_of(a, t, round, nI, nJ, i0, j0);
-  const int n2 = nI + nJ;
-  auto gidx = [&](int x) { return x < nI ? i0 + x : j0 + (x - nI); };
-  const S* Qg = (const S*)a.Q + (long)t * J2 * J2;
+  const int np = a.np;
+  const unsigned nmt = (unsigned)np * np;
   const S zero = from_real<S>(0.0);
-  for (int e = tid; e < n2 * n2; e += 256) Qs[(e % n2) + (e / n2) * JLD] = Qg[(e % n2) + (e / n2) * J2];
-  const int c0 = chunk * 64;
-  const int nc = min(64, a.m - c0);
-  constexpr int RLD = J2 + 1;
-  if (which == 0) {
+  if (wg < nmt) {
+    const int ta = (int)(wg % np), tb = (int)(wg / np);
+    const bool ra = a.flags[ta] != 0, rb = a.flags[tb] != 0;
+    if (!ra && !rb) return;
+    int nIa, nJa, i0a, j0a, nIb, nJb, i0b, j0b;
+    pair_of(a, ta, round, nIa, nJa, i0a, j0a);
+    pair_of(a, tb, round, nIb, nJb, i0b, j0b);
+    const int na = nIa + nJa, nb = nIb + nJb;
+    if (na == 0 || nb == 0) return;
+    auto ga = [&](int x) { return x < nIa ? i0a + x : j0a + (x - nIa); };
+    auto gb = [&](int y) { return y < nIb ? i0b + y : j0b + (y - nIb); };
+    S* Ms = sh;
+    S* Ts = sh + J2 * JLD;
+    S* QA = sh + 2 * J2 * JLD;
+    S* QB = sh + 3 * J2 * JLD;
     S* M = (S*)a.M;
+    const S* qa = (const S*)a.Q + (long)ta * J2 * J2;
+    const S* qb = (const S*)a.Q + (long)tb * J2 * J2;
+    for (int e = tid; e < na * nb; e += 256) {
+      int x = e % na, y = e / na;
+      Ms[x + y * JLD] = M[ga(x) + (long)gb(y) * a.ld];
+    }
+    if (ra)
+      for (int e = tid; e < na * na; e += 256) QA[(e % na) + (e / na) * JLD] = qa[(e % na) + (e / na) * J2];
+    if (rb)
+      for (int e = tid; e < nb * nb; e += 256) QB[(e % nb) + (e / nb) * JLD] = qb[(e % nb) + (e / nb) * J2];
     __syncthreads();
-    for (int e = tid; e < n2 * nc; e += 256) {
-      int x = e % n2, c = e / n2;
-      R[x + c * RLD] = M[gidx(x) + (long)(c0 + c) * a.ld];
+    for (int e = tid; e < na * nb; e += 256) {  // T = M_ab Q_b
+      int x = e % na, y = e / na;
+      S t = zero;
+      if (rb) {
+        for (int u = 0; u < nb; ++u) t += Ms[x + u * JLD] * QB[u + y * JLD];
+      } else {
+        t = Ms[x + y * JLD];
+      }
+      Ts[x + y * JLD] = t;
     }
     __syncthreads();
-    for (int e = tid; e < n2 * nc; e += 256) {
-      int x = e % n2, c = e / n2;
-      S s = zero;
-      for (int u = 0; u < n2; ++u) s += conj_(Qs[u + x * JLD]) * R[u + c * RLD];
-      M[gidx(x) + (long)(c0 + c) * a.ld] = s;
+    for (int e = tid; e < na * nb; e += 256) {  // Q_a^H T
+      int x = e % na, y = e / na;
+      S t = zero;
+      if (ra) {
+        for (int u = 0; u < na; ++u) t += conj_(QA[u + x * JLD]) * Ts[u + y * JLD];
+      } else {
+        t = Ts[x + y * JLD];
+      }
+      M[ga(x) + (long)gb(y) * a.ld] = t;
     }
     return;
   }
-  for (int w = 0; w < 2; ++w) {
-    S* A = w ? (S*)a.Vt : (S*)a.M;
-    const int lda = w ? a.m : a.ld;
-    __syncthreads();
-    for (int e = tid; e < nc * n2; e += 256) {
-      int r = e % nc, x = e / nc;
-      R[x + r * RLD] = A[(c0 + r) + (long)gidx(x) * lda];
-    }
-    __syncthreads();
-    for (int e = tid; e < nc * n2; e += 256) {
-      int r = e % nc, x = e / nc;
-      S s = zero;
-      for (int u = 0; u < n2; ++u) s += R[u + r * RLD] * Qs[u + x * JLD];
-      A[(c0 + r) + (long)gidx(x) * lda] = s;
-    }
+  const unsigned it = wg - nmt;
+  const int tb = (int)(it % np), chunk = (int)(it / np);
+  if (!a.flags[tb]) return;
+  int nI, nJ, i0, j0;
+  pair_of(a, tb, round, nI, nJ, i0, j0);
+  const int n2 = nI + nJ;
+  auto gidx = [&](int x) { return x < nI ? i0 + x : j0 + (x - nI); };
+  S* Qs = sh;
+  S* R = sh + J2 * JLD;  // 64 rows x n2, ld JLD
+  const S* Qg = (const S*)a.Q + (long)tb * J2 * J2;
+  for (int e = tid; e < n2 * n2; e += 256) Qs[(e % n2) + (e / n2) * JLD] = Qg[(e % n2) + (e / n2) * J2];
+  const int c0 = chunk * 64;
+  const int nc = min(64, a.m - c0);
+  S* Vt = (S*)a.Vt;
+  for (int e = tid; e < nc * n2; e += 256) {
+    int r = e % nc, x = e / nc;
+    R[x + r * JLD] = Vt[(c0 + r) + (long)gidx(x) * a.m];
+  }
+  __syncthreads();
+  for (int e = tid; e < nc * n2; e += 256) {
+    int r = e % nc, x = e / nc;
+    S t = zero;
+    for (int u = 0; u < n2; ++u) t += R[u + r * JLD] * Qs[u + x * JLD];
+    Vt[(c0 + r) + (long)gidx(x) * a.m] = t;
   }
 }
 
@@ -672,21 +715,17 @@ PPCG_DEV void bj_gather_body(const EigDev& a, unsigned wg) {
   ((S*)a.V)[i + (long)a.rank[j] * a.ldv] = ((const S*)a.Vt)[i + (long)j * a.m];
 }
 
-// step: 0 init, 1 pair, 2 rows, 3 cols, 4 rank, 5 gather
-template <class S>
-__global__ __launch_bounds__(256) void bj_grouped(const EigDev* jobs, const unsigned* start, int nj, int step,
-                                                  int round) {
+// STEP: 0 init, 1 pair eigensolves, 2 two-sided update of M and Vt, 3 rank, 4 gather
+template <class S, int STEP>
+__global__ __launch_bounds__(256) void bj_grouped(const EigDev* jobs, const unsigned* start, int nj, int round) {
   int j = find_job(start, nj, blockIdx.x);
   unsigned wg = blockIdx.x - start[j];
   const EigDev& a = jobs[j];
-  switch (step) {
-    case 0: bj_init_body<S>(a, wg); break;
-    case 1: bj_pair_body<S>(a, round, wg); break;
-    case 2: bj_apply_body<S>(a, round, wg, 0); break;
-    case 3: bj_apply_body<S>(a, round, wg, 1); break;
-    case 4: bj_rank_body<S>(a); break;
-    case 5: bj_gather_body<S>(a, wg); break;
-  }
+  if (STEP == 0) bj_init_body<S>(a, wg);
+  if (STEP == 1) bj_pair_body<S>(a, round, wg);
+  if (STEP == 2) bj_update_body<S>(a, round, wg);
+  if (STEP == 3) bj_rank_body<S>(a);
+  if (STEP == 4) bj_gather_body<S>(a, wg);
 }
 
 int block_jacobi_eig_grouped(const std::vector<EigJob>& jobs, Stage& stage, int* dev_counter, int* host_counter,
@@ -700,22 +739,22 @@ int block_jacobi_eig_grouped(const std::vector<EigJob>& jobs, Stage& stage, int*
     ed[j] = carve(jobs[j], dev_counter);
     maxr = std::max(maxr, ed[j].nbe - 1);
   }
-  // start arrays for the six step shapes
+  // start arrays for the five step shapes
   auto wgs = [&](int step, const EigDev& a) -> unsigned {
     long mm = (long)a.m * a.m;
     switch (step) {
       case 0: return (unsigned)std::min<long>(64, std::max<long>(1, (mm + 255) / 256));
       case 1: return (unsigned)a.np;
-      case 2:
-      case 3: return (unsigned)(a.np * ((a.m + 63) / 64));
-      case 4: return 1u;
+      case 2: return (unsigned)(a.np * a.np + a.np * ((a.m + 63) / 64));
+      case 3: return 1u;
       default: return (unsigned)((mm + 255) / 256);
     }
   };
-  const unsigned* sd[6];
-  unsigned tot[6];
+  constexpr int NSTEP = 5;
+  const unsigned* sd[NSTEP];
+  unsigned tot[NSTEP];
   std::vector<unsigned> starts;
-  for (int step = 0; step < 6; ++step) {
+  for (int step = 0; step < NSTEP; ++step) {
     unsigned t = 0;
     for (int j = 0; j < nj; ++j) {
       starts.push_back(t);
@@ -730,29 +769,46 @@ int block_jacobi_eig_grouped(const std::vector<EigJob>& jobs, Stage& stage, int*
   std::memcpy(buf.data() + jb, starts.data(), sizeof(unsigned) * starts.size());
   uint8_t* dev = (uint8_t*)stage.upload(buf.data(), buf.size(), st);
   const EigDev* dj = (const EigDev*)dev;
-  for (int step = 0; step < 6; ++step) sd[step] = (const unsigned*)(dev + jb) + step * (nj + 1);
+  for (int step = 0; step < NSTEP; ++step) sd[step] = (const unsigned*)(dev + jb) + step * (nj + 1);
+  auto launch = [&](auto kernel, int step, int round) {
+    hipLaunchKernelGGL(kernel, dim3(tot[step]), dim3(256), 0, st, dj, sd[step], nj, round);
+  };
   auto run = [&](int step, int round) {
     if (!tot[step]) return;
-    if (cplx) hipLaunchKernelGGL(bj_grouped<zdouble>, dim3(tot[step]), dim3(256), 0, st, dj, sd[step], nj, step, round);
-    else hipLaunchKernelGGL(bj_grouped<double>, dim3(tot[step]), dim3(256), 0, st, dj, sd[step], nj, step, round);
+    if (cplx) {
+      switch (step) {
+        case 0: launch(bj_grouped<zdouble, 0>, step, round); break;
+        case 1: launch(bj_grouped<zdouble, 1>, step, round); break;
+        case 2: launch(bj_grouped<zdouble, 2>, step, round); break;
+        case 3: launch(bj_grouped<zdouble, 3>, step, round); break;
+        default: launch(bj_grouped<zdouble, 4>, step, round); break;
+      }
+    } else {
+      switch (step) {
+        case 0: launch(bj_grouped<double, 0>, step, round); break;
+        case 1: launch(bj_grouped<double, 1>, step, round); break;
+        case 2: launch(bj_grouped<double, 2>, step, round); break;
+        case 3: launch(bj_grouped<double, 3>, step, round); break;
+        default: launch(bj_grouped<double, 4>, step, round); break;
+      }
+    }
   };
   run(0, 0);
   int sweeps = 0;
-  for (int sweep = 0; sweep < 40; ++sweep) {
+  for (int sweep = 0; sweep < 80; ++sweep) {
     ZeroIntArgs z{dev_counter, 1};
     hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(256), 0, st, z);
     for (int round = 0; round < maxr; ++round) {
       run(1, round);
       run(2, round);
-      run(3, round);
     }
     ++sweeps;
     hipMemcpyAsync(host_counter, dev_counter, sizeof(int), hipMemcpyDeviceToHost, st);
     hipStreamSynchronize(st);
     if (*host_counter == 0) break;
   }
+  run(3, 0);
   run(4, 0);
-  run(5, 0);
   return sweeps;
 }
 
