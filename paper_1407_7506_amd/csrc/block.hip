@@ -25,10 +25,17 @@
 
 namespace ppcg {
 
+#ifndef PPCG_PENCIL_NT
+#define PPCG_PENCIL_NT 1024
+#endif
+// threads of a pencil workgroup (the Jacobi rounds of the larger pencils
+// spread their 2x2 updates over more waves)
+template <int NB> constexpr int pencil_nt() { return NB <= 24 ? 256 : PPCG_PENCIL_NT; }
+
 template <int NB, class S>
 PPCG_DEV void block_pencil_body(const PencilArgs& a, unsigned wg, unsigned) {
   constexpr int LD = NB + 1;
-  constexpr int NT = 256;
+  constexpr int NT = pencil_nt<NB>();
   constexpr bool IN_LDS = NB <= 48;
   static_assert(IN_LDS || 4L * NB * LD <= pencil_work_elems(), "pencil scratch too small");
   __shared__ S shm[IN_LDS ? 4 * NB * LD : 1];
@@ -195,7 +202,9 @@ PPCG_DEV void block_pencil_body(const PencilArgs& a, unsigned wg, unsigned) {
       fro = wave_sum(fro);
       if ((tid & 63) == 0) cs[tid >> 6] = fro;
       __syncthreads();
-      fro = (cs[0] + cs[1]) + (cs[2] + cs[3]);
+      fro = 0;
+#pragma unroll
+      for (int w = 0; w < NT / 64; ++w) fro += cs[w];
       __syncthreads();
       lds_jacobi<NT, S>(b3, b0, r, LD, a.jacobi_rel * sqrt(fro), 40, cs, uu, pq, &cnt);
     }
@@ -278,11 +287,11 @@ PPCG_DEV void block_pencil_body(const PencilArgs& a, unsigned wg, unsigned) {
 }
 
 template <int NB, class S>
-__global__ __launch_bounds__(256) void block_pencil_kernel(PencilArgs a) {
+__global__ __launch_bounds__(pencil_nt<NB>()) void block_pencil_kernel(PencilArgs a) {
   block_pencil_body<NB, S>(a, blockIdx.x, gridDim.x);
 }
 template <int NB, class S>
-__global__ __launch_bounds__(256) void block_pencil_grouped(const PencilArgs* jobs, const unsigned* start, int nj) {
+__global__ __launch_bounds__(pencil_nt<NB>()) void block_pencil_grouped(const PencilArgs* jobs, const unsigned* start, int nj) {
   int j = find_job(start, nj, blockIdx.x);
   block_pencil_body<NB, S>(jobs[j], blockIdx.x - start[j], start[j + 1] - start[j]);
 }
@@ -294,12 +303,12 @@ static int pencil_kind(const PencilArgs& a) {
 
 #define PPCG_PENCIL_SWITCH(KERNEL, GRID, ...)                                                                   \
   switch (kind) {                                                                                              \
-    case OP_PENCIL24: hipLaunchKernelGGL((KERNEL<24, double>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;  \
-    case OP_PENCIL48: hipLaunchKernelGGL((KERNEL<48, double>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;  \
-    case OP_PENCILZ24: hipLaunchKernelGGL((KERNEL<24, zdouble>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break; \
-    case OP_PENCILZ48: hipLaunchKernelGGL((KERNEL<48, zdouble>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break; \
-    case OP_PENCIL96: hipLaunchKernelGGL((KERNEL<96, double>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;  \
-    case OP_PENCILZ96: hipLaunchKernelGGL((KERNEL<96, zdouble>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break; \
+    case OP_PENCIL24: hipLaunchKernelGGL((KERNEL<24, double>), dim3(GRID), dim3(pencil_nt<24>()), 0, st, __VA_ARGS__); break;  \
+    case OP_PENCIL48: hipLaunchKernelGGL((KERNEL<48, double>), dim3(GRID), dim3(pencil_nt<48>()), 0, st, __VA_ARGS__); break;  \
+    case OP_PENCILZ24: hipLaunchKernelGGL((KERNEL<24, zdouble>), dim3(GRID), dim3(pencil_nt<24>()), 0, st, __VA_ARGS__); break; \
+    case OP_PENCILZ48: hipLaunchKernelGGL((KERNEL<48, zdouble>), dim3(GRID), dim3(pencil_nt<48>()), 0, st, __VA_ARGS__); break; \
+    case OP_PENCIL96: hipLaunchKernelGGL((KERNEL<96, double>), dim3(GRID), dim3(pencil_nt<96>()), 0, st, __VA_ARGS__); break;  \
+    case OP_PENCILZ96: hipLaunchKernelGGL((KERNEL<96, zdouble>), dim3(GRID), dim3(pencil_nt<96>()), 0, st, __VA_ARGS__); break; \
     default: break;                                                                                            \
   }
 
