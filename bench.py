@@ -181,6 +181,8 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain device copy of 1 GiB (counter calibration under rocprofv3)")
     ap.add_argument("--workload", choices=["wells48", "batch64"], default="wells48")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="fixed kernel plans instead of the autotuner's (tuning happens in the warmup solve)")
     ap.add_argument("--nprob", type=int, default=64, help="problems of the batch64 workload")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -210,7 +212,7 @@ def main():
     results = {}
     precs = ["mixed", "fp64"] if args.only == "both" else [args.only]
     for prec in precs:
-        h = B.Handle(prec, profile=True)
+        h = B.Handle(prec, profile=True, autotune=not args.no_autotune)
         for _ in range(args.warmup):
             h.solve(V, g.N, p.k, p.q, p.tol, p.rr_period, X0, h=g.h, order=g.order)
         torch.cuda.synchronize()
@@ -224,7 +226,13 @@ def main():
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         kt = h.kernel_times()
-        results[prec] = {"s": dt / args.steps, "info": infos[-1], "lam": lam.cpu().numpy(), "kt": kt}
+        tune = h.tune_report()
+        if tune:
+            log(f"autotuner decisions ({prec}):")
+            for line in tune.splitlines():
+                log("   " + line)
+        results[prec] = {"s": dt / args.steps, "info": infos[-1], "lam": lam.cpu().numpy(), "kt": kt,
+                         "tune_classes": len(tune.splitlines())}
         log(f"{prec}: {dt / args.steps:.3f} s/solve, iters {infos[-1]['iters']}, rr {infos[-1]['n_rr']}, "
             f"resid {infos[-1]['resid_final']:.3e}")
         top = sorted(kt.items(), key=lambda x: -x[1][0])[:8]
@@ -260,6 +268,8 @@ def main():
         "orth_err": r["info"]["orth_err"],
         "roofline": roofline(kt, main_prec),
         "kernel_share": {k: round(v[0] / tot_ms, 4) for k, v in sorted(kt.items(), key=lambda x: -x[1][0])[:8]},
+        "autotune": {"enabled": not args.no_autotune, "shape_classes": r["tune_classes"],
+                     "note": "candidates timed during the warmup solve; timed solves use the chosen plans"},
     }
     if "fp64" in results and "mixed" in results:
         lf, lm = results["fp64"]["lam"], results["mixed"]["lam"]

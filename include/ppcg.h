@@ -72,7 +72,19 @@ typedef struct {
   int32_t max_iter;   /* iteration cap (default 20000 when <= 0) */
   int32_t profile;    /* nonzero: time every kernel launch with HIP events on
                          the handle's stream (see ppcg_kernel_times) */
+  int32_t flags;      /* bit set of ppcg_flags */
 } ppcg_options;
+
+typedef enum {
+  PPCG_NO_GRAPHS = 1, /* issue the block-Jacobi sweeps of the Rayleigh-Ritz
+                         eigensolve launch by launch instead of replaying the
+                         captured HIP graph of one sweep (same results) */
+  PPCG_AUTOTUNE = 2   /* time the candidate Gram / update kernels and row
+                         splits of each new shape class once on the handle and
+                         keep the fastest (see ppcg_tune_report); results stay
+                         within rounding of the untuned choice, and after the
+                         first solve of a shape class repeat exactly */
+} ppcg_flags;
 
 typedef struct {
   int32_t nx;           /* grid points per dimension N (n = N^3) */
@@ -189,6 +201,13 @@ int32_t ppcg_kernel_times(ppcg_handle* h, const char** names, double* ms, int64_
 int32_t ppcg_kernel_stats(ppcg_handle* h, const char** names, double* ms, int64_t* counts, double* flops,
                           double* bytes, int32_t cap);
 void ppcg_reset_kernel_times(ppcg_handle* h);
+
+/* The autotuner's decisions on this handle (PPCG_AUTOTUNE), one text line per
+ * shape class: the kernel variant, workgroup target and minimum rows per
+ * split chosen, its time and every candidate tried.  Writes at most cap - 1
+ * characters and a terminating 0 into buf (may be NULL); returns the full
+ * length, or -1 for a NULL handle. */
+int32_t ppcg_tune_report(const ppcg_handle* h, char* buf, int32_t cap);
 
 void ppcg_destroy(ppcg_handle* h);
 const char* ppcg_last_error(const ppcg_handle* h);

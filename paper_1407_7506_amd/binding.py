@@ -21,6 +21,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libppcg.so")
 
 PPCG_FP64, PPCG_MIXED = 0, 1
+PPCG_NO_GRAPHS, PPCG_AUTOTUNE = 1, 2
 STATUS = {0: "PPCG_OK", 1: "PPCG_EINVAL", 2: "PPCG_ENOTHPD", 3: "PPCG_ERANK", 4: "PPCG_ENOCONV",
           5: "PPCG_ENOSTATE", 6: "PPCG_EHIP", 7: "PPCG_ENOMEM"}
 
@@ -34,7 +35,8 @@ class PPCGError(RuntimeError):
 
 
 class Options(ctypes.Structure):
-    _fields_ = [("precision", c_int32), ("nbuf", c_int32), ("max_iter", c_int32), ("profile", c_int32)]
+    _fields_ = [("precision", c_int32), ("nbuf", c_int32), ("max_iter", c_int32), ("profile", c_int32),
+                ("flags", c_int32)]
 
 
 class Operator(ctypes.Structure):
@@ -88,6 +90,8 @@ def lib():
     L.ppcg_reset_kernel_times.restype = None
     L.ppcg_destroy.argtypes = [c_void_p]
     L.ppcg_destroy.restype = None
+    L.ppcg_tune_report.argtypes = [c_void_p, c_char_p, c_int32]
+    L.ppcg_tune_report.restype = c_int32
     L.ppcg_last_error.argtypes = [c_void_p]
     L.ppcg_last_error.restype = c_char_p
     _lib = L
@@ -111,10 +115,11 @@ class Handle:
     """One libppcg handle bound to the current device and torch stream."""
 
     def __init__(self, precision: str = "fp64", nbuf: int = -1, max_iter: int = 0, profile: bool = False,
-                 stream=None):
+                 stream=None, graphs: bool = True, autotune: bool = False):
         import torch
         self._L = lib()
-        opt = Options(PPCG_MIXED if precision == "mixed" else PPCG_FP64, nbuf, max_iter, 1 if profile else 0)
+        flags = (0 if graphs else PPCG_NO_GRAPHS) | (PPCG_AUTOTUNE if autotune else 0)
+        opt = Options(PPCG_MIXED if precision == "mixed" else PPCG_FP64, nbuf, max_iter, 1 if profile else 0, flags)
         st = stream if stream is not None else torch.cuda.current_stream()
         self.stream = st
         h = c_void_p()
@@ -187,7 +192,9 @@ class Handle:
         self._last_n = n if code == 0 else None
         if code != 0 and check:
             raise PPCGError(code, self.error(), info.as_dict())
-        return lam, Xout.t(), info.as_dict()
+        d = info.as_dict()
+        d["status"] = STATUS.get(code, code)
+        return lam, Xout.t(), d
 
     def solve_batched(self, problems, sbsize, tol, rr_period, check=True):
         """Solve many independent problems in lockstep.  problems: list of
@@ -260,6 +267,16 @@ class Handle:
         if code != 0:
             raise PPCGError(code, self.error())
         return rho
+
+    def tune_report(self) -> str:
+        """The autotuner's decisions (one line per shape class); empty without
+        autotune=True."""
+        n = self._L.ppcg_tune_report(self._h, None, 0)
+        if n <= 0:
+            return ""
+        buf = ctypes.create_string_buffer(n + 1)
+        self._L.ppcg_tune_report(self._h, buf, n + 1)
+        return buf.value.decode()
 
     def kernel_times(self):
         """{kernel kind: (total ms, launches, algorithmic flops, compulsory bytes)}"""

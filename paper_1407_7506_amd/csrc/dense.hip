@@ -12,6 +12,8 @@
 // them in lockstep, one grouped launch per step.
 #include <algorithm>
 
+#include <stdexcept>
+
 #include "common.hpp"
 #include "jacobi.hpp"
 #include "kernels.hpp"
@@ -728,11 +730,34 @@ __global__ __launch_bounds__(256) void bj_grouped(const EigDev* jobs, const unsi
   if (STEP == 4) bj_gather_body<S>(a, wg);
 }
 
-int block_jacobi_eig_grouped(const std::vector<EigJob>& jobs, Stage& stage, int* dev_counter, int* host_counter,
-                             hipStream_t st) {
+void EigGraphCache::clear() {
+  if (exec) hipGraphExecDestroy(exec);
+  if (graph) hipGraphDestroy(graph);
+  exec = nullptr;
+  graph = nullptr;
+  key.clear();
+}
+EigGraphCache::~EigGraphCache() {
+  clear();
+  if (dev) hipFree(dev);
+  if (stream) hipStreamDestroy(stream);
+}
+
+int block_jacobi_eig_grouped(const std::vector<EigJob>& jobs, Stage& stage, EigGraphCache* graphs, int* dev_counter,
+                             int* host_counter, hipStream_t st) {
   const int nj = (int)jobs.size();
   if (nj == 0) return 0;
   const bool cplx = jobs[0].cplx;
+  bool own_stream = false;
+  if (graphs) {
+    if (!graphs->stream && hipStreamCreateWithFlags(&graphs->stream, hipStreamNonBlocking) != hipSuccess) {
+      graphs->stream = nullptr;
+      graphs = nullptr;
+    } else {
+      st = graphs->stream;
+      own_stream = true;
+    }
+  }
   std::vector<EigDev> ed(nj);
   int maxr = 1;
   for (int j = 0; j < nj; ++j) {
@@ -767,7 +792,29 @@ int block_jacobi_eig_grouped(const std::vector<EigJob>& jobs, Stage& stage, int*
   std::vector<uint8_t> buf(jb + sizeof(unsigned) * starts.size());
   std::memcpy(buf.data(), ed.data(), jb);
   std::memcpy(buf.data() + jb, starts.data(), sizeof(unsigned) * starts.size());
-  uint8_t* dev = (uint8_t*)stage.upload(buf.data(), buf.size(), st);
+  // with a graph cache the array lives at the cache's fixed address (the
+  // captured sweep reads it there); else in the per-call staging area
+  bool reuse = false;
+  uint8_t* dev;
+  if (graphs) {
+    reuse = graphs->exec && graphs->key == buf;
+    if (!reuse) {
+      graphs->clear();
+      if (graphs->cap < buf.size()) {
+        if (graphs->dev) hipFree(graphs->dev);
+        graphs->dev = nullptr;
+        graphs->cap = 0;
+        if (hipMalloc(&graphs->dev, buf.size()) != hipSuccess) throw std::runtime_error("hipMalloc failed");
+        graphs->cap = buf.size();
+      }
+      if (hipMemcpyAsync(graphs->dev, buf.data(), buf.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        throw std::runtime_error("eigensolver job upload failed");
+    }
+    dev = (uint8_t*)graphs->dev;
+  } else {
+    dev = (uint8_t*)stage.upload(buf.data(), buf.size(), st);
+  }
   const EigDev* dj = (const EigDev*)dev;
   for (int step = 0; step < NSTEP; ++step) sd[step] = (const unsigned*)(dev + jb) + step * (nj + 1);
   auto launch = [&](auto kernel, int step, int round) {
@@ -793,22 +840,51 @@ int block_jacobi_eig_grouped(const std::vector<EigJob>& jobs, Stage& stage, int*
       }
     }
   };
-  run(0, 0);
-  int sweeps = 0;
-  for (int sweep = 0; sweep < 80; ++sweep) {
+  // one sweep: zero the rotation counter, every round's two launches, read the count back
+  auto sweep_ops = [&]() {
     ZeroIntArgs z{dev_counter, 1};
     hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(256), 0, st, z);
     for (int round = 0; round < maxr; ++round) {
       run(1, round);
       run(2, round);
     }
-    ++sweeps;
     hipMemcpyAsync(host_counter, dev_counter, sizeof(int), hipMemcpyDeviceToHost, st);
-    hipStreamSynchronize(st);
+  };
+  if (graphs && !reuse) {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+      sweep_ops();
+      ok = hipStreamEndCapture(st, &g) == hipSuccess && g != nullptr;
+    }
+    if (ok) ok = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) == hipSuccess;
+    if (ok) {
+      graphs->graph = g;
+      graphs->exec = ge;
+      graphs->key = buf;
+    } else {
+      if (g) hipGraphDestroy(g);
+      (void)hipGetLastError();
+      graphs->clear();
+      graphs = nullptr;  // this call runs without the graph
+    }
+  }
+  run(0, 0);
+  int sweeps = 0;
+  for (int sweep = 0; sweep < 80; ++sweep) {
+    if (graphs) {
+      if (hipGraphLaunch(graphs->exec, st) != hipSuccess) throw std::runtime_error("hipGraphLaunch failed");
+    } else {
+      sweep_ops();
+    }
+    ++sweeps;
+    if (hipStreamSynchronize(st) != hipSuccess) throw std::runtime_error("block Jacobi sweep failed");
     if (*host_counter == 0) break;
   }
   run(3, 0);
   run(4, 0);
+  if (own_stream && hipStreamSynchronize(st) != hipSuccess) throw std::runtime_error("block Jacobi failed");
   return sweeps;
 }
 

@@ -258,11 +258,29 @@ void launch_d2h(void* dst, const void* src, size_t bytes, hipStream_t st);
 // the caller (size from eig_workspace_bytes).  Returns sweeps used.
 size_t eig_workspace_bytes(int m, int cplx);
 struct EigJob { double* M; int ld, m; double* V; int ldv; double* lam; void* work; double rel_tol; int cplx; };
+// One sweep of the block Jacobi (every round's pair and update launches and the
+// read-back of its rotation count) captured as a HIP graph, kept for as long
+// as the job array (problem pointers and shapes) stays the same: successive
+// Rayleigh-Ritz steps of a solve replay it instead of re-issuing the launches.
+// With a cache the eigensolve runs on the cache's own stream; the caller's
+// stream must have no pending work that the eigensolve depends on (the solver
+// synchronizes it first), and the call returns with that stream drained.
+struct EigGraphCache {
+  std::vector<uint8_t> key;     // job array + workgroup prefix sums the graph was captured for
+  void* dev = nullptr;          // device copy of that array (fixed address, read by the graph)
+  size_t cap = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t stream = nullptr;  // the library's own stream (capture is not possible on the null stream)
+  void clear();
+  ~EigGraphCache();
+};
 // All problems in lockstep (one workgroup set per problem and launch);
 // dev_counter / host_counter: one int of device / pinned host memory for the
 // rotation count of a sweep.  Synchronises the stream once per sweep.
 // Returns the sweeps used.
-int block_jacobi_eig_grouped(const std::vector<EigJob>& jobs, Stage& stage, int* dev_counter, int* host_counter,
+int block_jacobi_eig_grouped(const std::vector<EigJob>& jobs, Stage& stage, EigGraphCache* graphs, int* dev_counter,
+                             int* host_counter,
                              hipStream_t st);
 
 // backward pass (grad.hip)

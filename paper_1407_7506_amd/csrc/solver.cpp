@@ -17,7 +17,9 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <cstdio>
 #include <map>
+#include <tuple>
 #include <memory>
 #include <string>
 #include <vector>
@@ -190,6 +192,27 @@ struct Work {
 
 }  // namespace
 
+// Autotuner table: the fastest kernel variant and row-split schedule found
+// for each shape class (powers-of-two buckets of the operand sizes).
+struct TuneKey {
+  int kind;     // 0 Gram, 1 update
+  int site;     // Gram call site (0 plain, 1 projection, 2 per-block); -1 for updates
+  int f32, cplx, multi, upper;
+  int mb, nb;   // buckets of M x N (Gram) or K x N (update)
+  long rb;      // bucket of the rows
+  bool operator<(const TuneKey& o) const {
+    return std::tie(kind, site, f32, cplx, multi, upper, mb, nb, rb) <
+           std::tie(o.kind, o.site, o.f32, o.cplx, o.multi, o.upper, o.mb, o.nb, o.rb);
+  }
+};
+struct TuneChoice {
+  int lds = 0;          // LDS-staged 128 x 128 kernel
+  int target = 2048;    // workgroups aimed at (Gram row splits)
+  int floor_rows = 256; // no fewer rows per split
+  double ms = 0;        // time of the chosen candidate
+  std::string tried;    // every candidate and its time
+};
+
 struct ppcg_handle {
   hipStream_t st = nullptr;
   int device = 0;
@@ -200,6 +223,10 @@ struct ppcg_handle {
   std::vector<std::unique_ptr<Work>> works;
   DBuf counter;                       // rotation counter of the grouped eigensolver
   int* hcounter = nullptr;
+  EigGraphCache eig_graph;            // captured block-Jacobi sweep
+  std::map<TuneKey, TuneChoice> tune; // autotuner decisions (PPCG_AUTOTUNE)
+  DBuf tune_scratch;                  // output copy for timing non-idempotent updates
+  hipEvent_t tev[2] = {nullptr, nullptr};
   DBuf gZ, gR, gP, gAP, gY, gw, gsc;  // backward-pass work
   // state of the last successful single solve (for ppcg_grad / ppcg_density)
   bool has_state = false;
@@ -209,6 +236,8 @@ struct ppcg_handle {
   double s_c0 = 0, s_w1 = 0, s_w2 = 0, s_dmin = 0;
   ~ppcg_handle() {
     if (hcounter) hipHostFree(hcounter);
+    for (hipEvent_t e : tev)
+      if (e) hipEventDestroy(e);
   }
   Work& work(int i) {
     while ((int)works.size() <= i) works.emplace_back(new Work());
@@ -351,6 +380,41 @@ struct Prob {
     lamout = lamout_;
   }
 
+  // ---- autotuner --------------------------------------------------------------
+  bool tuning() const { return (H->opt.flags & PPCG_AUTOTUNE) && !g_rec; }
+  static int bucket(long x) {
+    long b = 32;
+    while (b < x) b *= 2;
+    return (int)std::min<long>(b, 1L << 30);
+  }
+  // each candidate: one untimed run, then one timed with HIP events on the
+  // solver's stream; the fastest wins (ties: the earlier candidate)
+  template <class F>
+  TuneChoice time_candidates(std::vector<TuneChoice>& cands, F&& run) {
+    for (hipEvent_t& e : H->tev)
+      if (!e) HIPCHECK(hipEventCreate(&e));
+    int best = 0;
+    std::string tried;
+    for (size_t i = 0; i < cands.size(); ++i) {
+      run(cands[i]);
+      HIPCHECK(hipEventRecord(H->tev[0], st));
+      run(cands[i]);
+      HIPCHECK(hipEventRecord(H->tev[1], st));
+      HIPCHECK(hipEventSynchronize(H->tev[1]));
+      float ms = 0;
+      HIPCHECK(hipEventElapsedTime(&ms, H->tev[0], H->tev[1]));
+      cands[i].ms = ms;
+      char b[96];
+      snprintf(b, sizeof b, "%s%s/%d/%d:%.3f", i ? " " : "", cands[i].lds ? "lds" : "wave", cands[i].target,
+               cands[i].floor_rows, ms);
+      tried += b;
+      if (ms < cands[best].ms) best = (int)i;
+    }
+    TuneChoice c = cands[best];
+    c.tried = tried;
+    return c;
+  }
+
   // ---- kernels --------------------------------------------------------------
   void stencil(const void* Xs, void* Ys, int ncols, bool f32) {
     double es = (f32 ? 4 : 8) * nc();
@@ -397,20 +461,21 @@ struct Prob {
     int splits;
     long chunk;
   };
-  GramPlan gram_plan(int M, int Nn, int njobs, long rws, int site = 0) const {
+  bool gram_lds_ok(int M, int Nn, int njobs) const { return !cplx && njobs == 1 && std::min(M, Nn) >= 64; }
+  GramPlan gram_plan(int M, int Nn, int njobs, long rws, int site = 0, const TuneChoice* tc = nullptr) const {
     GramPlan g;
-    g.lds = !cplx && njobs == 1 && std::min(M, Nn) >= 96;
+    g.lds = tc ? (tc->lds && gram_lds_ok(M, Nn, njobs)) : (gram_lds_ok(M, Nn, njobs) && std::min(M, Nn) >= 96);
+    const long target = tc ? tc->target : (g.lds ? 4096 : 2048);
+    const long floor_rows = tc ? tc->floor_rows : (g.lds ? 1024 : 256);
     long tiles, s, maxs;
     if (g.lds) {
       tiles = (long)((M + 127) / 128) * ((Nn + 127) / 128);
-      s = (4096 + tiles - 1) / tiles;
-      maxs = std::max(1L, rws / 1024);
     } else {
       const int tn = (site == 2 && !cplx) ? 80 : 64;  // per-block Grams use 64 x 80 tiles
       tiles = (long)((M + 63) / 64) * ((Nn + tn - 1) / tn) * njobs;
-      s = (2048 + tiles - 1) / tiles;
-      maxs = std::max(1L, rws / 256);
     }
+    s = (target + tiles - 1) / tiles;
+    maxs = std::max(1L, rws / floor_rows);
     s = std::max(1L, std::min(s, maxs));
     g.chunk = round_up((rws + s - 1) / s, 32);
     g.splits = (int)((rws + g.chunk - 1) / g.chunk);
@@ -422,17 +487,18 @@ struct Prob {
             void* dst, int ldd, bool upper, bool f32acc, int njobs = 1, long job_col_off = 0,
             long dst_job_stride = 0, const char* name = "gram") {
     if (M <= 0 || Nn <= 0) return;
-    GramPlan plan = gram_plan(M, Nn, njobs, rws, site_of(name));
+    const int site = site_of(name);
     size_t es = (f32acc ? 4 : 8) * nc();
     size_t one = (size_t)njobs * M * Nn * es;
     if (one > Wk.part.bytes) throw PpcgError{PPCG_EINVAL, "internal: partial buffer too small"};
-    if ((size_t)plan.splits * one > Wk.part.bytes) {  // fewer, longer splits
-      long sp = (long)(Wk.part.bytes / one);
-      plan.chunk = round_up((rws + sp - 1) / sp, 32);
-      plan.splits = (int)((rws + plan.chunk - 1) / plan.chunk);
-    }
-    const int splits = plan.splits;
-    const long chunk = plan.chunk;
+    auto capped = [&](GramPlan pl) {
+      if ((size_t)pl.splits * one > Wk.part.bytes) {  // fewer, longer splits
+        long sp = (long)(Wk.part.bytes / one);
+        pl.chunk = round_up((rws + sp - 1) / sp, 32);
+        pl.splits = (int)((rws + pl.chunk - 1) / pl.chunk);
+      }
+      return pl;
+    };
     GramArgs g{};
     g.A = A;
     g.B = B;
@@ -442,30 +508,19 @@ struct Prob {
     g.N = Nn;
     g.ld = ldab;
     g.rows = rws;
-    g.splits = splits;
-    g.chunk = chunk;
     g.out = Wk.part.p;
     g.split_stride = (long)M * Nn;
     g.ldo = M;
     g.upper_only = upper;
     g.job_col_off = job_col_off;
     g.njobs = njobs;
-    g.site = site_of(name);
+    g.site = site;
     g.cplx = cplx;
-    g.lds = plan.lds;
-    {
-      double nn = (double)std::min(rws, n), es_in = (f32acc ? 4.0 : 8.0) * nc();
-      double fl = (upper ? (double)M * (M + 1) * nn : 2.0 * M * Nn * nn) * (cplx ? 4 : 1);
-      double by = (double)njobs * (upper ? M : (M + Nn)) * nn * es_in;
-      Scope s(prof, name, fl * njobs, by);
-      launch_gram(g, f32acc, st);
-    }
     ReduceArgs r{};
     r.part = Wk.part.p;
     r.M = M;
     r.N = Nn;
     r.ldp = M;
-    r.splits = splits;
     r.split_stride = (long)M * Nn;
     r.njobs = njobs;
     r.dst = dst;
@@ -475,6 +530,52 @@ struct Prob {
     r.beta = 0.0;
     r.upper_only = upper;
     r.cplx = cplx;
+    auto set_plan = [&](const GramPlan& pl) {
+      g.splits = pl.splits;
+      g.chunk = pl.chunk;
+      g.lds = pl.lds;
+      r.splits = pl.splits;
+    };
+    // the Gram and its reduction are idempotent (the reduction overwrites
+    // dst), so candidates run in place
+    const TuneChoice* tc = nullptr;
+    if (tuning()) {
+      TuneKey key{0, site, f32acc ? 1 : 0, cplx ? 1 : 0, njobs > 1 ? 1 : 0, upper ? 1 : 0, bucket(M), bucket(Nn),
+                  bucket(rws)};
+      auto it = H->tune.find(key);
+      if (it == H->tune.end()) {
+        std::vector<TuneChoice> cands;
+        for (int tgt : {1024, 2048, 4096}) {
+          TuneChoice c;
+          c.target = tgt;
+          cands.push_back(c);
+        }
+        if (gram_lds_ok(M, Nn, njobs))
+          for (int tgt : {2048, 4096, 8192})
+            for (int fl : {512, 1024}) {
+              TuneChoice c;
+              c.lds = 1;
+              c.target = tgt;
+              c.floor_rows = fl;
+              cands.push_back(c);
+            }
+        TuneChoice best = time_candidates(cands, [&](const TuneChoice& c) {
+          set_plan(capped(gram_plan(M, Nn, njobs, rws, site, &c)));
+          launch_gram(g, f32acc, st);
+          launch_reduce(r, f32acc, st);
+        });
+        it = H->tune.emplace(key, best).first;
+      }
+      tc = &it->second;
+    }
+    set_plan(capped(gram_plan(M, Nn, njobs, rws, site, tc)));
+    {
+      double nn = (double)std::min(rws, n), es_in = (f32acc ? 4.0 : 8.0) * nc();
+      double fl = (upper ? (double)M * (M + 1) * nn : 2.0 * M * Nn * nn) * (cplx ? 4 : 1);
+      double by = (double)njobs * (upper ? M : (M + Nn)) * nn * es_in;
+      Scope s(prof, name, fl * njobs, by);
+      launch_gram(g, f32acc, st);
+    }
     Scope s(prof, "reduce");
     launch_reduce(r, f32acc, st);
   }
@@ -504,7 +605,36 @@ struct Prob {
     u.c0_keep = c0_keep;
     u.site = site_of(name);
     u.cplx = cplx;
-    u.lds = !cplx && rws % 128 == 0 && Nn >= 96;
+    const bool lds_ok = !cplx && rws % 128 == 0 && Nn >= 64;
+    u.lds = lds_ok && Nn >= 96;
+    if (tuning() && lds_ok) {
+      TuneKey key{1, -1, f32 ? 1 : 0, 0, 0, b_upper ? 1 : 0, bucket(Kk), bucket(Nn), bucket(rws)};
+      auto it = H->tune.find(key);
+      if (it == H->tune.end()) {
+        // C = beta (D C) + alpha A B is idempotent only with beta = 0 or an
+        // unwritten C0; otherwise candidates write into a copy of C
+        UpdateArgs t = u;
+        const bool idem = beta == 0.0 || c0_keep;
+        if (!idem) {
+          const size_t esz = f32 ? 4 : 8;
+          const size_t c0b = (size_t)ldc * N0 * esz, c1b = C1 ? (size_t)ldc * (Nn - N0) * esz : 0;
+          H->tune_scratch.ensure(c0b + c1b);
+          HIPCHECK(hipMemcpyAsync(H->tune_scratch.p, C0, c0b, hipMemcpyDeviceToDevice, st));
+          if (C1) HIPCHECK(hipMemcpyAsync((char*)H->tune_scratch.p + c0b, C1, c1b, hipMemcpyDeviceToDevice, st));
+          t.C0 = H->tune_scratch.p;
+          t.C1 = C1 ? (char*)H->tune_scratch.p + c0b : nullptr;
+          t.C32 = nullptr;
+        }
+        std::vector<TuneChoice> cands(2);
+        cands[1].lds = 1;
+        TuneChoice best = time_candidates(cands, [&](const TuneChoice& c) {
+          t.lds = c.lds;
+          launch_update(t, f32, st);
+        });
+        it = H->tune.emplace(key, best).first;
+      }
+      u.lds = it->second.lds;
+    }
     double nn = (double)std::min(rws, n), es = (f32 ? 4.0 : 8.0) * nc();
     double fl = (b_upper ? (double)Nn * (Nn + 1) * nn : 2.0 * Kk * Nn * nn) * (cplx ? 4 : 1);
     double by = ((double)Kk + Nn * (beta != 0 ? 2.0 : 1.0)) * nn * es + (C32 ? 4.0 * nc() * Nn * nn : 0.0);
@@ -565,6 +695,18 @@ struct Prob {
           for (int nn = std::min(q, Nn); nn <= Nn; nn += q) {
             GramPlan pl = gram_plan(mm, nn, jb, rws, site);
             need = std::max(need, (size_t)jb * pl.splits * mm * nn * es);
+            if (H->opt.flags & PPCG_AUTOTUNE) {  // room for the finest candidate splits
+              TuneChoice c;
+              c.lds = 1;
+              c.target = 8192;
+              c.floor_rows = 512;
+              pl = gram_plan(mm, nn, jb, rws, site, &c);
+              need = std::max(need, (size_t)jb * pl.splits * mm * nn * es);
+              c.lds = 0;
+              c.target = 4096;
+              pl = gram_plan(mm, nn, jb, rws, site, &c);
+              need = std::max(need, (size_t)jb * pl.splits * mm * nn * es);
+            }
           }
     };
     acc(K, 2 * K, 1, rows, esz());
@@ -1054,7 +1196,8 @@ struct Driver {
       Scope s(H->prof, "eig");
       if (!H->hcounter) HIPCHECK(hipHostMalloc((void**)&H->hcounter, 64, hipHostMallocDefault));
       H->counter.ensure(256);
-      block_jacobi_eig_grouped(jobs, H->stage, H->counter.i(), H->hcounter, H->st);
+      EigGraphCache* gc = (H->opt.flags & PPCG_NO_GRAPHS) ? nullptr : &H->eig_graph;
+      block_jacobi_eig_grouped(jobs, H->stage, gc, H->counter.i(), H->hcounter, H->st);
     }
     phase(ps, [](Prob& p) { p.enq_rr2(); });
     sync(H);
@@ -1454,6 +1597,29 @@ void ppcg_reset_kernel_times(ppcg_handle* h) {
     h->prof.reset();
   } catch (...) {
   }
+}
+
+int32_t ppcg_tune_report(const ppcg_handle* h, char* buf, int32_t cap) {
+  if (!h) return -1;
+  std::string out;
+  for (const auto& kv : h->tune) {
+    const TuneKey& k = kv.first;
+    const TuneChoice& c = kv.second;
+    char line[256];
+    snprintf(line, sizeof line, "%s site=%d %s%s%s%s %s<=%d N<=%d rows<=%ld -> %s target=%d floor=%d %.3f ms [", 
+             k.kind ? "update" : "gram", k.site, k.f32 ? "f32" : "f64", k.cplx ? " complex" : "",
+             k.multi ? " batched-jobs" : "", k.upper ? " upper" : "", k.kind ? "K" : "M", k.mb, k.nb, k.rb,
+             c.lds ? "lds" : "wave", c.target, c.floor_rows, c.ms);
+    out += line;
+    out += c.tried;
+    out += "]\n";
+  }
+  if (buf && cap > 0) {
+    size_t w = std::min<size_t>(out.size(), (size_t)cap - 1);
+    std::memcpy(buf, out.data(), w);
+    buf[w] = 0;
+  }
+  return (int32_t)out.size();
 }
 
 void ppcg_destroy(ppcg_handle* h) { delete h; }

@@ -111,6 +111,20 @@ def start_block(n: int, K: int, seed: int, complex_: bool = False) -> np.ndarray
     return re + 1j * im
 
 
+def start_block_device(n: int, K: int, seed: int, complex_: bool, device="cuda"):
+    """Random start block generated on the device, as a (K, n) torch tensor
+    (column-major n x K): N(0,1) entries, or complex entries with independent
+    real and imaginary parts ~ N(0, 1/2), from torch's seeded generator of
+    that device.  Used for the 96^3 Bloch workload, whose 29.9 GB block would
+    take minutes through the numpy stream of start_block; the values differ
+    from start_block's, the distribution is the same."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    dt = torch.complex128 if complex_ else torch.float64
+    return torch.randn((K, n), generator=g, device=device, dtype=dt)
+
+
 def loss_weights(n: int, seed: int) -> np.ndarray:
     """Density weights w ~ N(0,1) of the loss sum_r w_r rho_r."""
     return np.random.default_rng(seed).standard_normal(n)

@@ -209,3 +209,41 @@ def test_batch_complex_matches_single(h64):
     res = hb.solve_batched(mixed, 4, 1e-9, 5, check=False)
     assert res[0][3] == "PPCG_OK" and res[1][3] == "PPCG_EINVAL"
     hb.close()
+
+
+def test_bloch96_full_size_properties():
+    """The 96^3 Bloch workload at full size (n = 884736, k = 2048, q = 32,
+    nbuf = 64, complex128 X, complex64 bulk), two PPCG iterations and the
+    final Rayleigh-Ritz (PPCG_ENOCONV by the iteration cap): properties that
+    hold at any iteration -- orthonormal X, ascending Ritz values above
+    min(V) (the kinetic part is positive semidefinite), and for sampled
+    columns the Rayleigh quotient x^H H x from the oracle's stencil equal to
+    the returned Ritz value."""
+    p = I.bloch96()
+    g = p.grid
+    say("bloch96 full size", g.n, p.k, p.q, p.K)
+    V = dev(p.V)
+    X0 = I.start_block_device(g.n, p.K, p.x0_seed, True, "cuda")   # (K, n) column-major
+    h = B.Handle("mixed", nbuf=p.nbuf, max_iter=2)
+    lam, X, info = h.solve(V, g.N, p.k, p.q, p.tol, p.rr_period, X0.t(), h=g.h, order=g.order, kpt=g.kpt,
+                           check=False)
+    del X0
+    say("  status", info["status"], "iters", info["iters"], "n_rr", info["n_rr"], "orth", info["orth_err"],
+        "time", info["time_s"])
+    assert info["status"] in ("PPCG_ENOCONV", "PPCG_OK")
+    assert info["iters"] == 2 and info["n_rr"] >= 1
+    assert info["orth_err"] <= 1e-10
+    lam = lam.cpu().numpy()
+    scale = np.abs(lam).max()
+    assert np.all(np.diff(lam) >= -1e-14 * scale)
+    assert lam[0] >= p.V.min() - 1e-12
+    for i in (0, 7, p.k // 2, p.k - 1):
+        x = X[:, i].cpu().numpy()
+        hx = stencil.apply_h(x, p.V, g.N, g.h, g.order, g.kpt)
+        nx2 = np.vdot(x, x).real
+        rq = np.vdot(x, hx).real / nx2
+        say("  col", i, "lambda", lam[i], "rq - lambda", rq - lam[i], "|x|^2 - 1", nx2 - 1,
+            "resid", np.linalg.norm(hx - lam[i] * x))
+        assert abs(nx2 - 1.0) <= 1e-10      # rounding of K = 2112-term rotations, as orth_err
+        assert abs(rq - lam[i]) <= 1e-10 * scale
+    h.close()

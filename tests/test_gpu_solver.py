@@ -224,3 +224,41 @@ def test_wells48_full_size_properties(h64, hmix):
     err = np.abs(out["mixed"] - out["fp64"]).max() / np.abs(out["fp64"]).max()
     say("  mixed vs fp64", err)
     assert err <= 1e-7
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_eig_graph_replay_matches_launches(prec):
+    """The Rayleigh-Ritz eigensolve replays a captured HIP graph of one block
+    Jacobi sweep (several replays per eigensolve, eager work of the solve in
+    between); the same solve issued launch by launch gives identical bits."""
+    p = I.small_problem(N=16, k=120, q=8, order=4, tol=1e-9)
+    hg = B.Handle(prec, max_iter=MAX_IT)
+    he = B.Handle(prec, max_iter=MAX_IT, graphs=False)
+    a = gpu_solve(hg, p)
+    b = gpu_solve(he, p)
+    c = gpu_solve(hg, p)   # second solve on the handle: the cached graph is reused
+    say("graph vs launches", prec, "iters", a[2]["iters"], b[2]["iters"], "n_rr", a[2]["n_rr"])
+    assert a[2]["n_rr"] >= 3
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1])
+    hg.close()
+    he.close()
+
+
+def test_autotune_repeats_exactly_and_agrees(h64):
+    """PPCG_AUTOTUNE: every new shape class times its candidate kernels and
+    row splits once and keeps the fastest.  Each solve's results come from the
+    chosen plans only, so solves on the tuned handle repeat bit for bit, and
+    they agree with the untuned plan to rounding."""
+    p = I.small_problem(N=16, k=120, q=8, order=4, tol=1e-9)
+    ht = B.Handle("fp64", max_iter=MAX_IT, autotune=True)
+    a = gpu_solve(ht, p)
+    b = gpu_solve(ht, p)
+    d = gpu_solve(h64, p)
+    rep = ht.tune_report()
+    say(rep)
+    assert "gram" in rep and "update" in rep
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    scale = np.abs(d[0]).max()
+    assert np.abs(a[0] - d[0]).max() <= 1e-12 * scale
+    ht.close()
