@@ -567,7 +567,8 @@ PPCG_DEV void bj_init_body(const EigDev& a, unsigned wg) {  // Vt = I; tiny (cou
   }
 }
 
-template <class S>
+// NT threads per pair problem (more waves hide the LDS latency of the rounds)
+template <class S, int NT>
 PPCG_DEV void bj_pair_body(const EigDev& a, int round, unsigned t) {
   __shared__ S Sm[J2 * JLD], Qs[J2 * JLD];
   __shared__ double cs[J2 + 2];
@@ -583,7 +584,7 @@ PPCG_DEV void bj_pair_body(const EigDev& a, int round, unsigned t) {
   const double tiny = *a.tiny;
   if (tid == 0) any = 0;
   __syncthreads();
-  for (int e = tid; e < n2 * n2; e += 256) {
+  for (int e = tid; e < n2 * n2; e += NT) {
     int x = e % n2, y = e / n2;
     S v = M[gidx(x) + (long)gidx(y) * a.ld];
     Sm[x + y * JLD] = v;
@@ -594,9 +595,9 @@ PPCG_DEV void bj_pair_body(const EigDev& a, int round, unsigned t) {
     if (tid == 0) a.flags[t] = 0;
     return;
   }
-  lds_jacobi<256, S>(Sm, Qs, n2, JLD, tiny, BJ_INNER, cs, uu, pq, &cnt);
+  lds_jacobi<NT, S>(Sm, Qs, n2, JLD, tiny, BJ_INNER, cs, uu, pq, &cnt);
   S* Qg = (S*)a.Q + (long)t * J2 * J2;
-  for (int e = tid; e < n2 * n2; e += 256) Qg[(e % n2) + (e / n2) * J2] = Qs[(e % n2) + (e / n2) * JLD];
+  for (int e = tid; e < n2 * n2; e += NT) Qg[(e % n2) + (e / n2) * J2] = Qs[(e % n2) + (e / n2) * JLD];
   if (tid == 0) {
     a.flags[t] = 1;
     atomicAdd(a.counter, 1);
@@ -718,13 +719,18 @@ PPCG_DEV void bj_gather_body(const EigDev& a, unsigned wg) {
 }
 
 // STEP: 0 init, 1 pair eigensolves, 2 two-sided update of M and Vt, 3 rank, 4 gather
+#ifndef PPCG_BJ_PAIR_NT
+#define PPCG_BJ_PAIR_NT 1024
+#endif
+constexpr int BJ_PAIR_NT = PPCG_BJ_PAIR_NT;
+template <int STEP> constexpr int bj_threads() { return STEP == 1 ? BJ_PAIR_NT : 256; }
 template <class S, int STEP>
-__global__ __launch_bounds__(256) void bj_grouped(const EigDev* jobs, const unsigned* start, int nj, int round) {
+__global__ __launch_bounds__(bj_threads<STEP>()) void bj_grouped(const EigDev* jobs, const unsigned* start, int nj, int round) {
   int j = find_job(start, nj, blockIdx.x);
   unsigned wg = blockIdx.x - start[j];
   const EigDev& a = jobs[j];
   if (STEP == 0) bj_init_body<S>(a, wg);
-  if (STEP == 1) bj_pair_body<S>(a, round, wg);
+  if (STEP == 1) bj_pair_body<S, BJ_PAIR_NT>(a, round, wg);
   if (STEP == 2) bj_update_body<S>(a, round, wg);
   if (STEP == 3) bj_rank_body<S>(a);
   if (STEP == 4) bj_gather_body<S>(a, wg);
@@ -818,7 +824,7 @@ int block_jacobi_eig_grouped(const std::vector<EigJob>& jobs, Stage& stage, EigG
   const EigDev* dj = (const EigDev*)dev;
   for (int step = 0; step < NSTEP; ++step) sd[step] = (const unsigned*)(dev + jb) + step * (nj + 1);
   auto launch = [&](auto kernel, int step, int round) {
-    hipLaunchKernelGGL(kernel, dim3(tot[step]), dim3(256), 0, st, dj, sd[step], nj, round);
+    hipLaunchKernelGGL(kernel, dim3(tot[step]), dim3(step == 1 ? BJ_PAIR_NT : 256), 0, st, dj, sd[step], nj, round);
   };
   auto run = [&](int step, int round) {
     if (!tot[step]) return;
