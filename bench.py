@@ -92,6 +92,67 @@ def traffic_for(name):
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
+# logical kernel name -> (symbol prefix, call-site template argument or None)
+TRAFFIC_KERNELS = {
+    "gram_proj": ("ppcg::gram", "1"), "update_proj": ("ppcg::update", "1"), "gram_block": ("ppcg::gram", "2"),
+    "stencil_f64": ("ppcg::stencil_kernel<double", None), "stencil_f32": ("ppcg::stencil_kernel<float", None),
+    "block_update": ("ppcg::block_update_kernel", None), "block_pencil": ("ppcg::block_pencil_kernel", None),
+}
+
+
+def _symbol_matches(sym, prefix, site):
+    if not sym.startswith(prefix):
+        return False
+    if site is None:
+        return True
+    return sym.rstrip().endswith(f", {site}>(ppcg::GramArgs)") or sym.rstrip().endswith(f", {site}>(ppcg::UpdateArgs)")
+
+
+def write_traffic(fetch_db, write_db, launches):
+    """profiles/traffic.json from two rocprofv3 --pmc databases (FETCH_SIZE,
+    WRITE_SIZE) of `bench.py --steps 1 --warmup 1 --only mixed --calib-copy`:
+    per logical kernel, the mean HBM bytes per dispatch over the last
+    `launches[name]` dispatches (the timed solve), each counter scaled by the
+    bytes it reports for the 1 GiB device copy of the calibration step."""
+    import sqlite3
+
+    def load(db, counter):
+        c = sqlite3.connect(db)
+        rows = c.execute("select dispatch_id, kernel_name, grid_size, value from counters_collection "
+                         "where counter_name = ? order by dispatch_id", (counter,)).fetchall()
+        return rows
+
+    out = {"source_sha": kernel_source_sha(), "kernels": {}, "calibration": {}}
+    per = {}
+    for db, counter in ((fetch_db, "FETCH_SIZE"), (write_db, "WRITE_SIZE")):
+        rows = load(db, counter)
+        # the calibration copy (1 GiB device-to-device, a runtime blit kernel):
+        # the copy dispatch with the largest count
+        cal = [r for r in rows if "copyBuffer" in r[1]]
+        if not cal:
+            raise SystemExit(f"{db}: no calibration copy dispatch found")
+        top = max(cal, key=lambda r: r[3])
+        measured = top[3] * 1024.0
+        factor = float(1 << 30) / measured
+        out["calibration"][counter] = {"kernel": top[1][:80], "KiB": top[3], "factor": factor}
+        for name, (prefix, site) in TRAFFIC_KERNELS.items():
+            ks = [r for r in rows if _symbol_matches(r[1], prefix, site)]
+            n = launches.get(name, 0)
+            if n <= 0 or len(ks) < n:
+                continue
+            ks = ks[-n:]
+            per.setdefault(name, {})[counter] = factor * 1024.0 * sum(r[3] for r in ks) / n
+    for name, d in per.items():
+        if "FETCH_SIZE" in d and "WRITE_SIZE" in d:
+            out["kernels"][name] = {"fetch_bytes_per_launch": d["FETCH_SIZE"], "write_bytes_per_launch": d["WRITE_SIZE"],
+                                    "hbm_bytes_per_launch": d["FETCH_SIZE"] + d["WRITE_SIZE"],
+                                    "launches": launches[name]}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    log(f"wrote {path}: {sorted(out['kernels'])}")
+
+
 def cpu_baseline(p, gpu_iters, iters):
     """The oracle as it stands, on the host cores, for `iters` iterations of the
     same workload; extrapolated to the GPU's iteration count."""
@@ -184,7 +245,14 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="fixed kernel plans instead of the autotuner's (tuning happens in the warmup solve)")
     ap.add_argument("--nprob", type=int, default=64, help="problems of the batch64 workload")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
+                    help="write profiles/traffic.json from two rocprofv3 --pmc databases and exit (no GPU use)")
+    ap.add_argument("--traffic-launches", default="",
+                    help="name=count,... launches per timed solve (from the bench run under the profiler)")
     args = ap.parse_args()
+    if args.traffic_from:
+        launches = {kv.split("=")[0]: int(kv.split("=")[1]) for kv in args.traffic_launches.split(",") if "=" in kv}
+        return write_traffic(args.traffic_from[0], args.traffic_from[1], launches)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
@@ -268,6 +336,7 @@ def main():
         "orth_err": r["info"]["orth_err"],
         "roofline": roofline(kt, main_prec),
         "kernel_share": {k: round(v[0] / tot_ms, 4) for k, v in sorted(kt.items(), key=lambda x: -x[1][0])[:8]},
+        "launches_per_solve": {k: v[1] // args.steps for k, v in kt.items() if k in TRAFFIC_KERNELS},
         "autotune": {"enabled": not args.no_autotune, "shape_classes": r["tune_classes"],
                      "note": "candidates timed during the warmup solve; timed solves use the chosen plans"},
     }

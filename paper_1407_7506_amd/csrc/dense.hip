@@ -66,18 +66,63 @@ void Stage::reset() {
 
 // ---------------------------------------------------------------------------
 // blocked Cholesky and inverse
+//
+// G = L L^H (lower, 32 x 32 tiles) and L^{-1}, in P + 1 launches for P tile
+// columns.  Launch 0 factors the first diagonal tile.  Launch p + 1 (p =
+// 0..P-1) runs, side by side:
+//   trailing tiles (i, j), p < j <= i:  G_ij -= L_ip L_jp^H with
+//       L_ip = G_ip Li_pp^H recomputed by the workgroup; the workgroup of
+//       tile (p+1, p+1) then factors it (the next diagonal step);
+//   inverse rows: with W_ic = delta_ic I - sum_{k<p} L_ik Li_kc (kept in the
+//       L buffer for i > c), block row p of the inverse is final,
+//       Li_pc = Li_pp W_pc (c < p), and every row below takes the step's
+//       term, W_ic -= L_ip (Li_pp W_pc) (c <= p; W_pp = I).
+// Block forward substitution of L Li = I in right-looking order: every
+// launch is one layer of independent 32 x 32 tile products, so the inverse
+// costs no launches of its own.
 // ---------------------------------------------------------------------------
 constexpr int CB = 32;       // Cholesky tile
 constexpr int CLD = CB + 1;
 
-struct DenseStep { double* G; double* L; double* Li; int ld, m; int* flag; };
+struct DenseStep { double* G; double* W; double* Li; int ld, m; int* flag; };
 
+// LDS tile <- 32 x 32 block of M at (r0, c0), zero outside nr x nc
+template <class S>
+PPCG_DEV void tile_get(S* T, const S* M, long ld, int r0, int c0, int nr, int nc) {
+  const S zero = from_real<S>(0.0);
+  for (int e = threadIdx.x; e < CB * CB; e += 256) {
+    int x = e % CB, y = e / CB;
+    T[x + y * CLD] = (x < nr && y < nc) ? M[(r0 + x) + (long)(c0 + y) * ld] : zero;
+  }
+}
+// C = A op(B) for the 4 entries of this thread (op = identity or ^H)
+template <class S, bool BH>
+PPCG_DEV void tile_mul4(S (&c)[4], const S* A, const S* B) {
+  const S zero = from_real<S>(0.0);
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    int e = threadIdx.x + 256 * s, x = e % CB, y = e / CB;
+    S v = zero;
+    for (int t = 0; t < CB; ++t) v += A[x + t * CLD] * (BH ? conj_(B[y + t * CLD]) : B[t + y * CLD]);
+    c[s] = v;
+  }
+}
+template <class S>
+PPCG_DEV void tile_put4(S* T, const S (&c)[4]) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    int e = threadIdx.x + 256 * s;
+    T[(e % CB) + (e / CB) * CLD] = c[s];
+  }
+}
+
+// factor the diagonal tile p of G (already updated by every earlier step):
+// Li_pp = L_pp^{-1}; a non-positive pivot sets *flag = p + 1
 template <class S>
 PPCG_DEV void chol_diag_body(const DenseStep& a, int p) {
   __shared__ S Sm[CB * CLD], I[CB * CLD];
   __shared__ int bad;
   const S* G = (const S*)a.G;
-  S* Lo = (S*)a.L;
   S* Li = (S*)a.Li;
   const S zero = from_real<S>(0.0);
   const int tid = threadIdx.x;
@@ -119,130 +164,102 @@ PPCG_DEV void chol_diag_body(const DenseStep& a, int p) {
   __syncthreads();
   for (int e = tid; e < nb * nb; e += 256) {
     int i = e % nb, j = e / nb;
-    long o = (n0 + i) + (long)(n0 + j) * a.ld;
-    Lo[o] = (i >= j) ? Sm[i + j * CLD] : zero;
-    Li[o] = (i >= j) ? I[i + j * CLD] : zero;
+    Li[(n0 + i) + (long)(n0 + j) * a.ld] = (i >= j) ? I[i + j * CLD] : zero;
   }
   if (tid == 0 && bad && *a.flag == 0) *a.flag = p + 1;
 }
 
-// Tiles (i, j), p < j <= i: L_ip = G_ip Li_pp^H, G_ij -= L_ip L_jp^H.
-// The diagonal tile (i, i) stores L_ip and zeroes the upper tile (p, i).
+// one workgroup item of launch p + 1 (see above)
 template <class S>
-PPCG_DEV void chol_trail_body(const DenseStep& a, int p, unsigned wg) {
-  __shared__ S Lp[CB * CLD], Ai[CB * CLD], Aj[CB * CLD];
+PPCG_DEV void chol_step_body(const DenseStep& a, int p, unsigned wg) {
+  __shared__ S T0[CB * CLD], T1[CB * CLD], T2[CB * CLD];
   S* G = (S*)a.G;
-  S* Lo = (S*)a.L;
-  const S* Li = (const S*)a.Li;
-  const S zero = from_real<S>(0.0);
+  S* W = (S*)a.W;
+  S* Li = (S*)a.Li;
   const int m = a.m, ld = a.ld;
   const int nbk = (m + CB - 1) / CB;
+  if (p >= nbk) return;
   const int span = nbk - p - 1;
-  const int i = p + 1 + wg % span, j = p + 1 + wg / span;
-  if (j > i) return;
-  const int tid = threadIdx.x;
-  const int n0 = p * CB, ni0 = i * CB, nj0 = j * CB;
-  const int nbp = min(CB, m - n0), nbi = min(CB, m - ni0), nbj = min(CB, m - nj0);
-  for (int e = tid; e < CB * CB; e += 256) {
-    int x = e % CB, y = e / CB;
-    Lp[x + y * CLD] = (x < nbp && y < nbp) ? Li[(n0 + x) + (long)(n0 + y) * ld] : zero;
-    Ai[x + y * CLD] = (x < nbi && y < nbp) ? G[(ni0 + x) + (long)(n0 + y) * ld] : zero;
-    Aj[x + y * CLD] = (x < nbj && y < nbp) ? G[(nj0 + x) + (long)(n0 + y) * ld] : zero;
-  }
-  __syncthreads();
-  S li[4], lj[4];
-  for (int s = 0; s < 4; ++s) {
-    int e = tid + 256 * s, x = e % CB, y = e / CB;
-    S a1 = zero, a2 = zero;
-    for (int t = 0; t <= y; ++t) {
-      S lv = conj_(Lp[y + t * CLD]);
-      a1 += Ai[x + t * CLD] * lv;
-      a2 += Aj[x + t * CLD] * lv;
-    }
-    li[s] = a1;
-    lj[s] = a2;
-  }
-  __syncthreads();
-  for (int s = 0; s < 4; ++s) {
-    int e = tid + 256 * s, x = e % CB, y = e / CB;
-    Ai[x + y * CLD] = li[s];
-    Aj[x + y * CLD] = lj[s];
-  }
-  __syncthreads();
-  for (int s = 0; s < 4; ++s) {
-    int e = tid + 256 * s, x = e % CB, y = e / CB;
-    if (x < nbi && y < nbj && (i != j || x >= y)) {
-      S acc = zero;
-      for (int t = 0; t < CB; ++t) acc += Ai[x + t * CLD] * conj_(Aj[y + t * CLD]);
-      G[(ni0 + x) + (long)(nj0 + y) * ld] -= acc;
-    }
-    if (i == j && x < nbi && y < nbp) {
-      Lo[(ni0 + x) + (long)(n0 + y) * ld] = Ai[x + y * CLD];
-      Lo[(n0 + y) + (long)(ni0 + x) * ld] = zero;
-    }
-  }
-}
-
-// Off-diagonal tiles of L^{-1} along block diagonal d:
-// Li_ij = -Li_ii sum_{t=j}^{i-1} L_it Li_tj, with i = j + d; zeroes tile (j, i).
-template <class S>
-PPCG_DEV void trinv_body(const DenseStep& a, int d, unsigned wg) {
-  __shared__ S A[CB * CLD], B[CB * CLD], Sm[CB * CLD];
-  const S* L = (const S*)a.L;
-  S* Li = (S*)a.Li;
-  const S zero = from_real<S>(0.0);
-  const int m = a.m, ld = a.ld;
-  const int j = (int)wg, i = j + d;
-  const int tid = threadIdx.x;
-  const int ni0 = i * CB, nj0 = j * CB;
-  const int nbi = min(CB, m - ni0), nbj = min(CB, m - nj0);
-  S acc[4] = {zero, zero, zero, zero};
-  for (int t = j; t < i; ++t) {
-    const int nt0 = t * CB, nbt = min(CB, m - nt0);
+  const int n0 = p * CB, nbp = min(CB, m - n0);
+  auto nb_of = [&](int t) { return min(CB, m - t * CB); };
+  S c[4];
+  unsigned it = wg;
+  if (it < (unsigned)(span * span)) {  // trailing tile (i, j)
+    const int i = p + 1 + (int)(it % span), j = p + 1 + (int)(it / span);
+    if (j > i) return;
+    const int nbi = nb_of(i), nbj = nb_of(j);
+    tile_get(T0, Li, ld, n0, n0, nbp, nbp);          // Li_pp
+    tile_get(T1, G, ld, i * CB, n0, nbi, nbp);       // G_ip
+    tile_get(T2, G, ld, j * CB, n0, nbj, nbp);       // G_jp
     __syncthreads();
-    for (int e = tid; e < CB * CB; e += 256) {
-      int x = e % CB, y = e / CB;
-      A[x + y * CLD] = (x < nbi && y < nbt) ? L[(ni0 + x) + (long)(nt0 + y) * ld] : zero;
-      B[x + y * CLD] = (x < nbt && y < nbj) ? Li[(nt0 + x) + (long)(nj0 + y) * ld] : zero;
-    }
+    S d[4];
+    tile_mul4<S, true>(c, T1, T0);                   // L_ip = G_ip Li_pp^H
+    tile_mul4<S, true>(d, T2, T0);                   // L_jp
     __syncthreads();
+    tile_put4(T1, c);
+    tile_put4(T2, d);
+    __syncthreads();
+    tile_mul4<S, true>(c, T1, T2);                   // L_ip L_jp^H
+#pragma unroll
     for (int s = 0; s < 4; ++s) {
-      int e = tid + 256 * s, x = e % CB, y = e / CB;
-      S v = zero;
-      for (int u = 0; u < CB; ++u) v += A[x + u * CLD] * B[u + y * CLD];
-      acc[s] += v;
+      int e = threadIdx.x + 256 * s, x = e % CB, y = e / CB;
+      if (x < nbi && y < nbj && (i != j || x >= y)) G[(i * CB + x) + (long)(j * CB + y) * ld] -= c[s];
     }
+    if (i == j && i == p + 1) {  // the next diagonal step, on the tile just updated
+      __syncthreads();
+      chol_diag_body<S>(a, p + 1);
+    }
+    return;
   }
-  __syncthreads();
-  for (int s = 0; s < 4; ++s) {
-    int e = tid + 256 * s, x = e % CB, y = e / CB;
-    Sm[x + y * CLD] = acc[s];
+  it -= span * span;
+  if (it < (unsigned)p) {  // row p of the inverse: Li_pc = Li_pp W_pc, c < p
+    const int cc = (int)it, nbc = nb_of(cc);
+    tile_get(T0, Li, ld, n0, n0, nbp, nbp);
+    tile_get(T1, W, ld, n0, cc * CB, nbp, nbc);
+    __syncthreads();
+    tile_mul4<S, false>(c, T0, T1);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      int e = threadIdx.x + 256 * s, x = e % CB, y = e / CB;
+      if (x < nbp && y < nbc) Li[(n0 + x) + (long)(cc * CB + y) * ld] = c[s];
+    }
+    return;
   }
-  for (int e = tid; e < CB * CB; e += 256) {
-    int x = e % CB, y = e / CB;
-    A[x + y * CLD] = (x < nbi && y < nbi) ? Li[(ni0 + x) + (long)(ni0 + y) * ld] : zero;
-  }
-  __syncthreads();
-  for (int s = 0; s < 4; ++s) {
-    int e = tid + 256 * s, x = e % CB, y = e / CB;
-    if (x < nbi && y < nbj) {
-      S v = zero;
-      for (int u = 0; u <= x; ++u) v += A[x + u * CLD] * Sm[u + y * CLD];
-      Li[(ni0 + x) + (long)(nj0 + y) * ld] = -v;
-      Li[(nj0 + y) + (long)(ni0 + x) * ld] = zero;
+  it -= p;
+  if (it < (unsigned)(span * (p + 1))) {  // W_ic -= L_ip (Li_pp W_pc), i > p, c <= p
+    const int i = p + 1 + (int)(it / (p + 1)), cc = (int)(it % (p + 1));
+    const int nbi = nb_of(i), nbc = nb_of(cc);
+    tile_get(T0, Li, ld, n0, n0, nbp, nbp);          // Li_pp
+    tile_get(T1, G, ld, i * CB, n0, nbi, nbp);       // G_ip
+    if (cc < p) tile_get(T2, W, ld, n0, cc * CB, nbp, nbc);
+    __syncthreads();
+    S d[4];
+    tile_mul4<S, true>(c, T1, T0);                   // L_ip
+    if (cc < p) tile_mul4<S, false>(d, T0, T2);      // Li_pp W_pc
+    __syncthreads();
+    tile_put4(T1, c);
+    if (cc < p) tile_put4(T2, d);
+    __syncthreads();
+    tile_mul4<S, false>(c, T1, cc < p ? T2 : T0);    // L_ip (Li_pp W_pc); W_pp = I
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      int e = threadIdx.x + 256 * s, x = e % CB, y = e / CB;
+      if (x < nbi && y < nbc) {
+        S* w = W + (i * CB + x) + (long)(cc * CB + y) * ld;
+        *w = (cc < p) ? *w - c[s] : -c[s];
+      }
     }
   }
 }
 
-// step: 0 = diagonal tile p, 1 = trailing update after p, 2 = inverse diagonal p
+// launch 0: the first diagonal tile; launch p + 1: chol_step_body(p)
 template <class S>
 __global__ __launch_bounds__(256) void chol_step_grouped(const DenseStep* jobs, const unsigned* start, int nj,
-                                                         int step, int p) {
+                                                         int launch) {
   int j = find_job(start, nj, blockIdx.x);
   unsigned wg = blockIdx.x - start[j];
-  if (step == 0) chol_diag_body<S>(jobs[j], p);
-  else if (step == 1) chol_trail_body<S>(jobs[j], p, wg);
-  else trinv_body<S>(jobs[j], p, wg);
+  if (launch == 0) chol_diag_body<S>(jobs[j], 0);
+  else chol_step_body<S>(jobs[j], launch - 1, wg);
 }
 
 void chol_inverse_grouped(const std::vector<CholArgs>& jobs, Stage& stage, hipStream_t st) {
@@ -255,28 +272,29 @@ void chol_inverse_grouped(const std::vector<CholArgs>& jobs, Stage& stage, hipSt
     ds[j] = DenseStep{jobs[j].G, jobs[j].L, jobs[j].Li, jobs[j].ld, jobs[j].m, jobs[j].flag};
     P = std::max(P, (jobs[j].m + CB - 1) / CB);
   }
-  // every launch of the composite: (step, p) and its workgroup prefix sums,
-  // packed with the job array into one upload
-  struct L { int step, p; unsigned tot; size_t off; };
-  std::vector<L> ls;
+  // workgroups of every launch and job, packed with the job array into one upload
+  std::vector<unsigned> tots;
+  std::vector<size_t> offs;
   std::vector<unsigned> starts;
-  auto plan = [&](int step, int p, auto wgs_of) {
-    L l{step, p, 0, starts.size()};
+  for (int l = 0; l <= P; ++l) {
+    offs.push_back(starts.size());
+    unsigned t = 0;
     for (int j = 0; j < nj; ++j) {
-      starts.push_back(l.tot);
-      l.tot += wgs_of((jobs[j].m + CB - 1) / CB);
+      starts.push_back(t);
+      const int nbk = (jobs[j].m + CB - 1) / CB;
+      if (l == 0) {
+        t += nbk > 0 ? 1 : 0;
+      } else {
+        const int p = l - 1;
+        if (p < nbk) {
+          const int span = nbk - p - 1;
+          t += (unsigned)(span * span + p + span * (p + 1));
+        }
+      }
     }
-    starts.push_back(l.tot);
-    if (l.tot) ls.push_back(l);
-  };
-  for (int p = 0; p < P; ++p) {
-    plan(0, p, [&](int nbk) { return (unsigned)(p < nbk ? 1 : 0); });
-    plan(1, p, [&](int nbk) {
-      int span = nbk - p - 1;
-      return (unsigned)(span > 0 ? span * span : 0);
-    });
+    starts.push_back(t);
+    tots.push_back(t);
   }
-  for (int d = 1; d < P; ++d) plan(2, d, [&](int nbk) { return (unsigned)(d < nbk ? nbk - d : 0); });
   size_t jb = sizeof(DenseStep) * nj;
   std::vector<uint8_t> buf(jb + sizeof(unsigned) * starts.size());
   std::memcpy(buf.data(), ds.data(), jb);
@@ -284,9 +302,10 @@ void chol_inverse_grouped(const std::vector<CholArgs>& jobs, Stage& stage, hipSt
   uint8_t* dev = (uint8_t*)stage.upload(buf.data(), buf.size(), st);
   const DenseStep* dj = (const DenseStep*)dev;
   const unsigned* sd = (const unsigned*)(dev + jb);
-  for (const L& l : ls) {
-    if (cplx) hipLaunchKernelGGL(chol_step_grouped<zdouble>, dim3(l.tot), dim3(256), 0, st, dj, sd + l.off, nj, l.step, l.p);
-    else hipLaunchKernelGGL(chol_step_grouped<double>, dim3(l.tot), dim3(256), 0, st, dj, sd + l.off, nj, l.step, l.p);
+  for (int l = 0; l <= P; ++l) {
+    if (!tots[l]) continue;
+    if (cplx) hipLaunchKernelGGL(chol_step_grouped<zdouble>, dim3(tots[l]), dim3(256), 0, st, dj, sd + offs[l], nj, l);
+    else hipLaunchKernelGGL(chol_step_grouped<double>, dim3(tots[l]), dim3(256), 0, st, dj, sd + offs[l], nj, l);
   }
 }
 
