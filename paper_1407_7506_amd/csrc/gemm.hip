@@ -425,14 +425,15 @@ PPCG_DEV void get4(const float* d, float* v) {
 }
 
 // gram, C (M x N) partial over rows [rbeg, rend) of split s; real operands
-template <class T, int KC>
+// (NBUF as for the update below)
+template <class T, int KC, int NBUF = 2>
 PPCG_DEV void gram_lds_body(const GramArgs& a, unsigned wg, unsigned nwg) {
   constexpr int S = LdsPad<T, KC>::S;
   constexpr int PQ = KC / 4;             // quads (4 consecutive rows) per column and chunk
   constexpr int NQ = LB * PQ / 256;      // quads per thread and panel
   constexpr int CS = 256 / PQ;           // column step between a thread's quads
-  __shared__ __align__(16) T As[2][LB * S];
-  __shared__ __align__(16) T Bs[2][LB * S];
+  __shared__ __align__(16) T As[NBUF][LB * S];
+  __shared__ __align__(16) T Bs[NBUF][LB * S];
   typedef typename AccT<T>::type acc_t;
   const int tid = threadIdx.x, l = tid & 63, lc = l & 15, g = l >> 4;
   const int wi = (tid >> 6) & 1, wj = tid >> 7;
@@ -506,7 +507,7 @@ PPCG_DEV void gram_lds_body(const GramArgs& a, unsigned wg, unsigned nwg) {
   }
   __syncthreads();
   for (int c = 0; c < nch; ++c) {
-    const int buf = c & 1;
+    const int buf = NBUF == 2 ? (c & 1) : 0;
     if (c + 1 < nch) gload(rbeg + (long)(c + 1) * KC);
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 16) {
@@ -523,7 +524,8 @@ PPCG_DEV void gram_lds_body(const GramArgs& a, unsigned wg, unsigned nwg) {
 #pragma unroll
           for (int y = 0; y < 4; ++y) acc[x][y] = mfma(av[x][e], bv[y][e], acc[x][y]);
     }
-    if (c + 1 < nch) sput(buf ^ 1);
+    if (NBUF == 1) __syncthreads();
+    if (c + 1 < nch) sput(NBUF == 2 ? buf ^ 1 : 0);
     __syncthreads();
   }
   T* out = (T*)a.out + ((long)job * a.splits + split) * a.split_stride;
@@ -549,8 +551,10 @@ __global__ __launch_bounds__(256) void gram_lds_grouped(const GramArgs* jobs, co
   gram_lds_body<T, KC>(jobs[j], blockIdx.x - start[j], start[j + 1] - start[j]);
 }
 
-// update, C (rows x N) = beta (D C) + alpha A B for one 128 x 128 tile; real
-template <class T, int KC>
+// update, C (rows x N) = beta (D C) + alpha A B for one 128 x 128 tile; real.
+// NBUF = 2: double-buffered LDS panels (one barrier per chunk); NBUF = 1: one
+// LDS buffer refilled between two barriers (half the LDS, deeper chunks).
+template <class T, int KC, int NBUF = 2>
 PPCG_DEV void update_lds_body(const UpdateArgs& a, unsigned wg, unsigned nwg) {
   constexpr int SB = LdsPad<T, KC>::S;                 // B panel [col][k]
   constexpr int SA = LB + (sizeof(T) == 8 ? 2 : 4);    // A panel [k][row]
@@ -560,8 +564,8 @@ PPCG_DEV void update_lds_body(const UpdateArgs& a, unsigned wg, unsigned nwg) {
   constexpr int PQ = KC / 4, NB = LB * PQ / 256;       // B quads per column / per thread
   typedef typename AccT<T>::type acc_t;
   typedef typename std::conditional<sizeof(T) == 8, double2, float4>::type v16;
-  __shared__ __align__(16) T As[2][KC * SA];
-  __shared__ __align__(16) T Bs[2][LB * SB];
+  __shared__ __align__(16) T As[NBUF][KC * SA];
+  __shared__ __align__(16) T Bs[NBUF][LB * SB];
   const int tid = threadIdx.x, l = tid & 63, lc = l & 15, g = l >> 4;
   const int wr = (tid >> 6) & 1, wj = tid >> 7;
   unsigned L = xcd_remap(wg, nwg);
@@ -619,7 +623,7 @@ PPCG_DEV void update_lds_body(const UpdateArgs& a, unsigned wg, unsigned nwg) {
   }
   __syncthreads();
   for (int c = 0; c < nch; ++c) {
-    const int buf = c & 1;
+    const int buf = NBUF == 2 ? (c & 1) : 0;
     if (c + 1 < nch) gload((c + 1) * KC);
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 16) {
@@ -637,7 +641,8 @@ PPCG_DEV void update_lds_body(const UpdateArgs& a, unsigned wg, unsigned nwg) {
 #pragma unroll
           for (int y = 0; y < 4; ++y) acc[0][x][y] = mfma(bv[x][e], av[y][e], acc[0][x][y]);
     }
-    if (c + 1 < nch) sput(buf ^ 1);
+    if (NBUF == 1) __syncthreads();
+    if (c + 1 < nch) sput(NBUF == 2 ? buf ^ 1 : 0);
     __syncthreads();
   }
   update_epilogue<T, 4, 4, false>(a, job, j0 + wj * 64, r0 + wr * 64, acc);
@@ -654,15 +659,162 @@ __global__ __launch_bounds__(256) void update_lds_grouped(const UpdateArgs* jobs
 }
 
 // ---------------------------------------------------------------------------
+// Per-block Grams in one pass over the block's columns (real, float64
+// accumulation).  The A and B column sets of a block share segments (X_j,
+// W_j, P_j appear in both); a workgroup of four waves owns one (block, row
+// split), stages each chunk of 16 rows of the union of the two sets once in
+// LDS (converted to float64, double buffered) and computes the whole
+// (M x N) partial Gram from it: each column is read from HBM once instead of
+// once per operand and output tile.  Wave w owns output tile rows w, w+4, ...
+// TR: output tile rows per wave, TC: output tile columns.
+// ---------------------------------------------------------------------------
+constexpr int BG_MAXU = 6 * 32;  // union columns: up to 6 segments of q <= 32
+template <int TR, int TC>
+PPCG_DEV void gram_block_body(const GramArgs& a, unsigned wg, unsigned nwg) {
+  constexpr int KC = 16, S = KC + 2;
+  typedef AccT<double>::type acc_t;
+  __shared__ __align__(16) double U[2][BG_MAXU * S];
+  __shared__ const char* uptr[BG_MAXU];
+  __shared__ unsigned char uf32[BG_MAXU];
+  __shared__ short amap[TR * 64];
+  __shared__ int nU;
+  const int tid = threadIdx.x, l = tid & 63, lc = l & 15, g = l >> 4, w = tid >> 6;
+  unsigned L = xcd_remap(wg, nwg);
+  const int split = (int)(L % a.splits), job = (int)(L / a.splits);
+  const long joff = (long)job * a.job_col_off;
+  const long rbeg = (long)split * a.chunk;
+  const long rend = rbeg + a.chunk < a.rows ? rbeg + a.chunk : a.rows;
+  const int nch = rend > rbeg ? (int)((rend - rbeg) / KC) : 0;
+  // union of the column sets: every B column, then the A segments found in no B segment
+  if (tid == 0) {
+    int n = 0;
+    for (int c = 0; c < a.N; ++c) {
+      bool f;
+      uptr[n] = (const char*)seg_col(a.B, c, a.ld, joff, f, 8);
+      uf32[n] = f;
+      ++n;
+    }
+    int a0 = 0;
+    for (int sA = 0; sA < a.A.nseg; ++sA) {
+      const int len = a.A.end[sA] - a0;
+      int map0 = -1, b0 = 0;
+      for (int sB = 0; sB < a.B.nseg; ++sB) {
+        const int blen = a.B.end[sB] - b0;
+        if (a.B.p[sB] == a.A.p[sA] && a.B.f32[sB] == a.A.f32[sA] && blen >= len) {
+          map0 = b0;
+          break;
+        }
+        b0 = a.B.end[sB];
+      }
+      for (int c = 0; c < len; ++c) {
+        if (map0 >= 0) {
+          amap[a0 + c] = (short)(map0 + c);
+        } else {
+          bool f;
+          uptr[n] = (const char*)seg_col(a.A, a0 + c, a.ld, joff, f, 8);
+          uf32[n] = f;
+          amap[a0 + c] = (short)n;
+          ++n;
+        }
+      }
+      a0 = a.A.end[sA];
+    }
+    nU = n;
+  }
+  __syncthreads();
+  const int nu = nU;
+  const int nq = nu * (KC / 4);   // 4-row quads per chunk, at most 3 per thread
+  double rq[3][4];
+  auto gload = [&](long r) {  // next chunk into registers
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      const int q = tid + 256 * t;
+      if (q < nq) {
+        const int col = q >> 2;
+        const bool f = uf32[col] != 0;
+        Load4<double, false>::go(uptr[col] + (r + 4 * (q & 3)) * (f ? 4 : 8), f, rq[t], nullptr);
+      }
+    }
+  };
+  auto sput = [&](int buf) {
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      const int q = tid + 256 * t;
+      if (q < nq) put4(&U[buf][(q >> 2) * S + 4 * (q & 3)], rq[t]);
+    }
+  };
+  acc_t acc[TR][TC];
+#pragma unroll
+  for (int x = 0; x < TR; ++x)
+#pragma unroll
+    for (int y = 0; y < TC; ++y) acc[x][y] = acc_t{0, 0, 0, 0};
+  if (nch > 0) {
+    gload(rbeg);
+    sput(0);
+  }
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nch) gload(rbeg + (long)(c + 1) * KC);
+    double av[TR][4], bv[TC][4];
+#pragma unroll
+    for (int x = 0; x < TR; ++x) {
+      const int i = (w + 4 * x) * 16 + lc;
+      if (i < a.M) get4(&U[buf][amap[i] * S + 4 * g], av[x]);
+      else av[x][0] = av[x][1] = av[x][2] = av[x][3] = 0.0;
+    }
+#pragma unroll
+    for (int y = 0; y < TC; ++y) {
+      const int j = 16 * y + lc;
+      if (j < a.N) get4(&U[buf][j * S + 4 * g], bv[y]);
+      else bv[y][0] = bv[y][1] = bv[y][2] = bv[y][3] = 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int x = 0; x < TR; ++x)
+#pragma unroll
+        for (int y = 0; y < TC; ++y) acc[x][y] = mfma(av[x][e], bv[y][e], acc[x][y]);
+    if (c + 1 < nch) sput(buf ^ 1);
+    __syncthreads();
+  }
+  double* out = (double*)a.out + ((long)job * a.splits + split) * a.split_stride;
+#pragma unroll
+  for (int x = 0; x < TR; ++x)
+#pragma unroll
+    for (int y = 0; y < TC; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = (w + 4 * x) * 16 + acc_row<double>(l, v);
+        const int j = 16 * y + lc;
+        if (i < a.M && j < a.N) out[i + (long)j * a.ldo] = acc[x][y][v];
+      }
+}
+
+template <int TR, int TC>
+__global__ __launch_bounds__(256) void gram_block_kernel(GramArgs a) {
+  gram_block_body<TR, TC>(a, blockIdx.x, gridDim.x);
+}
+template <int TR, int TC>
+__global__ __launch_bounds__(256) void gram_block_grouped(const GramArgs* jobs, const unsigned* start, int nj) {
+  int j = find_job(start, nj, blockIdx.x);
+  gram_block_body<TR, TC>(jobs[j], blockIdx.x - start[j], start[j + 1] - start[j]);
+}
+
+// ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
 constexpr int GTM = 4, GTN = 4, UTJ = 4, UTR = 4;   // real tiles
 constexpr int BTN = 5;  // real per-block Grams: 64 x 80 tiles, i.e. one tile per block for q <= 16
 constexpr int ZTM = 2, ZTN = 2, ZTJ = 2, ZTR = 2;   // complex tiles
 
-constexpr int GKC_D = 16, GKC_F = 32, UKC_D = 16, UKC_F = 32;  // LDS chunk depths
+constexpr int GKC_D = 16, GKC_F = 32, UKC_D = 32, UKC_F = 32;  // LDS chunk depths (measured best)
 
 void gram_tiles(GramArgs& a) {
+  if (a.lds == 2) {
+    a.tiles_i = a.tiles_j = 1;
+    return;
+  }
   if (a.lds) {
     a.tiles_i = (a.M + LB - 1) / LB;
     a.tiles_j = (a.N + LB - 1) / LB;
@@ -684,6 +836,7 @@ void update_tiles(UpdateArgs& a) {
 }
 
 static int gram_kind(const GramArgs& a, bool f32acc) {
+  if (a.lds == 2) return (a.M <= 64 && a.N <= 80) ? OP_GRAMB_1 : OP_GRAMB_2;
   if (a.lds) return (f32acc ? OP_GRAML_F0 : OP_GRAML_D0) + (a.site == 1 ? 1 : 0);
   int base = a.cplx ? (f32acc ? OP_GRAM_C0 : OP_GRAM_Z0) : (f32acc ? OP_GRAM_F0 : OP_GRAM_D0);
   return base + (a.site == 1 ? 1 : a.site == 2 ? 2 : 0);
@@ -714,6 +867,10 @@ static int update_kind(const UpdateArgs& a, bool f32) {
   case OP_GRAML_F0: hipLaunchKernelGGL((KERNEL<float, GKC_F, 0>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;  \
   case OP_GRAML_F1: hipLaunchKernelGGL((KERNEL<float, GKC_F, 1>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;
 
+#define PPCG_GRAMB_CASES(KERNEL, GRID, ...)                                                                      \
+  case OP_GRAMB_1: hipLaunchKernelGGL((KERNEL<1, 5>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;          \
+  case OP_GRAMB_2: hipLaunchKernelGGL((KERNEL<2, 10>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;
+
 #define PPCG_UPDATEL_CASES(KERNEL, GRID, ...)                                                                    \
   case OP_UPDATEL_D0: hipLaunchKernelGGL((KERNEL<double, UKC_D, 0>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break; \
   case OP_UPDATEL_D1: hipLaunchKernelGGL((KERNEL<double, UKC_D, 1>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break; \
@@ -734,7 +891,25 @@ static bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 void launch_gram(const GramArgs& a0, bool f32acc, hipStream_t st) {
   GramArgs a = a0;
-  if (a.lds) {  // the LDS-staged kernel's preconditions; otherwise the one-wave kernel
+  if (a.lds == 2) {  // the single-pass per-block kernel's preconditions
+    int extra = 0, a0 = 0;  // A segments that are not also B segments
+    for (int sA = 0; sA < a.A.nseg; ++sA) {
+      const int len = a.A.end[sA] - a0;
+      bool found = false;
+      int b0 = 0;
+      for (int sB = 0; sB < a.B.nseg && !found; ++sB) {
+        found = a.B.p[sB] == a.A.p[sA] && a.B.f32[sB] == a.A.f32[sA] && a.B.end[sB] - b0 >= len;
+        b0 = a.B.end[sB];
+      }
+      if (!found) extra += len;
+      a0 = a.A.end[sA];
+    }
+    bool ok = !a.cplx && !f32acc && a.M <= 128 && a.N <= 160 && a.N + extra <= BG_MAXU && a.chunk % 16 == 0 &&
+              a.ld % 4 == 0;
+    for (int s = 0; s < a.A.nseg; ++s) ok = ok && aligned16(a.A.p[s]);
+    for (int s = 0; s < a.B.nseg; ++s) ok = ok && aligned16(a.B.p[s]);
+    a.lds = ok ? 2 : 0;
+  } else if (a.lds) {  // the LDS-staged kernel's preconditions; otherwise the one-wave kernel
     bool ok = !a.cplx && a.njobs == 1 && a.chunk % 32 == 0 && a.ld % 4 == 0;
     for (int s = 0; s < a.A.nseg; ++s) ok = ok && aligned16(a.A.p[s]);
     for (int s = 0; s < a.B.nseg; ++s) ok = ok && aligned16(a.B.p[s]);
@@ -751,6 +926,7 @@ void launch_gram(const GramArgs& a0, bool f32acc, hipStream_t st) {
   switch (kind) {
     PPCG_GRAM_CASES(gram_kernel, blocks, a)
     PPCG_GRAML_CASES(gram_lds_kernel, blocks, a)
+    PPCG_GRAMB_CASES(gram_block_kernel, blocks, a)
     default: break;
   }
 }
@@ -804,6 +980,7 @@ bool launch_grouped_gemm(int kind, const void* jobs, const unsigned* start, int 
     PPCG_GRAM_CASES(gram_grouped, total, gj, start, nj)
     PPCG_UPDATE_CASES(update_grouped, total, uj, start, nj)
     PPCG_GRAML_CASES(gram_lds_grouped, total, gj, start, nj)
+    PPCG_GRAMB_CASES(gram_block_grouped, total, gj, start, nj)
     PPCG_UPDATEL_CASES(update_lds_grouped, total, uj, start, nj)
     case OP_REDUCE_D: hipLaunchKernelGGL((reduce_grouped<double, false>), dim3(total), dim3(256), 0, st, rj, start, nj); break;
     case OP_REDUCE_F: hipLaunchKernelGGL((reduce_grouped<float, false>), dim3(total), dim3(256), 0, st, rj, start, nj); break;

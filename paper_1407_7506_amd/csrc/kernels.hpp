@@ -45,7 +45,8 @@ struct GramArgs {
   int njobs;          // strided jobs (blocks) inside this gram
   int site;           // call site (selects a distinct kernel symbol for profiling)
   int cplx;           // complex operands (f32 segments then mean complex float)
-  int lds;            // 1: LDS-staged 128 x 128 workgroup tiles (real, one job, chunk % 32 == 0)
+  int lds;            // 1: LDS-staged 128 x 128 workgroup tiles (real, one job, chunk % 32 == 0);
+                      // 2: per-block single pass (real, float64 accumulation, M <= 128, N <= 160)
 };
 
 struct ReduceArgs {
@@ -157,7 +158,7 @@ struct D2HArgs { void* dst; const void* src; size_t bytes; };
 enum OpKind : int {
   OP_GRAM_D0, OP_GRAM_D1, OP_GRAM_D2, OP_GRAM_F0, OP_GRAM_F1, OP_GRAM_F2,
   OP_GRAM_Z0, OP_GRAM_Z1, OP_GRAM_Z2, OP_GRAM_C0, OP_GRAM_C1, OP_GRAM_C2,
-  OP_GRAML_D0, OP_GRAML_D1, OP_GRAML_F0, OP_GRAML_F1,
+  OP_GRAML_D0, OP_GRAML_D1, OP_GRAML_F0, OP_GRAML_F1, OP_GRAMB_1, OP_GRAMB_2,
   OP_REDUCE_D, OP_REDUCE_F, OP_REDUCE_Z, OP_REDUCE_C,
   OP_UPDATE_D0, OP_UPDATE_D1, OP_UPDATE_F0, OP_UPDATE_F1,
   OP_UPDATE_Z0, OP_UPDATE_Z1, OP_UPDATE_C0, OP_UPDATE_C1,

@@ -47,7 +47,7 @@ bool launch_grouped_prep(int kind, const void* jobs, const unsigned* start, int 
 }
 
 size_t op_args_size(int kind) {
-  if (kind >= OP_GRAM_D0 && kind <= OP_GRAML_F1) return sizeof(GramArgs);
+  if (kind >= OP_GRAM_D0 && kind <= OP_GRAMB_2) return sizeof(GramArgs);
   if (kind >= OP_REDUCE_D && kind <= OP_REDUCE_C) return sizeof(ReduceArgs);
   if (kind >= OP_UPDATE_D0 && kind <= OP_UPDATEL_F1) return sizeof(UpdateArgs);
   if (kind >= OP_STENCIL_D2 && kind <= OP_STENCIL_C4) return sizeof(StencilArgs);

@@ -405,7 +405,7 @@ struct Prob {
       HIPCHECK(hipEventElapsedTime(&ms, H->tev[0], H->tev[1]));
       cands[i].ms = ms;
       char b[96];
-      snprintf(b, sizeof b, "%s%s/%d/%d:%.3f", i ? " " : "", cands[i].lds ? "lds" : "wave", cands[i].target,
+      snprintf(b, sizeof b, "%s%s/%d/%d:%.3f", i ? " " : "", cands[i].lds == 2 ? "block" : (cands[i].lds ? "lds" : "wave"), cands[i].target,
                cands[i].floor_rows, ms);
       tried += b;
       if (ms < cands[best].ms) best = (int)i;
@@ -462,13 +462,21 @@ struct Prob {
     long chunk;
   };
   bool gram_lds_ok(int M, int Nn, int njobs) const { return !cplx && njobs == 1 && std::min(M, Nn) >= 64; }
+  // per-block Grams: the single-pass kernel (lds = 2) for real blocks
+  bool gram_block_ok(int M, int Nn, int site) const { return !cplx && site == 2 && M <= 128 && Nn <= 160; }
   GramPlan gram_plan(int M, int Nn, int njobs, long rws, int site = 0, const TuneChoice* tc = nullptr) const {
     GramPlan g;
-    g.lds = tc ? (tc->lds && gram_lds_ok(M, Nn, njobs)) : (gram_lds_ok(M, Nn, njobs) && std::min(M, Nn) >= 96);
-    const long target = tc ? tc->target : (g.lds ? 4096 : 2048);
-    const long floor_rows = tc ? tc->floor_rows : (g.lds ? 1024 : 256);
+    if (gram_block_ok(M, Nn, site)) {
+      g.lds = tc && tc->lds == 2 ? 2 : 0;  // measured: the one-wave kernel at ~4096 workgroups is as fast
+    } else {
+      g.lds = tc ? (tc->lds == 1 && gram_lds_ok(M, Nn, njobs)) : (gram_lds_ok(M, Nn, njobs) && std::min(M, Nn) >= 96);
+    }
+    const long target = tc ? tc->target : (g.lds ? (g.lds == 2 ? 2048 : 4096) : (site == 2 ? 4096 : 2048));
+    const long floor_rows = tc ? tc->floor_rows : (g.lds ? (g.lds == 2 ? 512 : 1024) : 256);
     long tiles, s, maxs;
-    if (g.lds) {
+    if (g.lds == 2) {
+      tiles = njobs;
+    } else if (g.lds) {
       tiles = (long)((M + 127) / 128) * ((Nn + 127) / 128);
     } else {
       const int tn = (site == 2 && !cplx) ? 80 : 64;  // per-block Grams use 64 x 80 tiles
@@ -550,6 +558,14 @@ struct Prob {
           c.target = tgt;
           cands.push_back(c);
         }
+        if (gram_block_ok(M, Nn, site))
+          for (int tgt : {1024, 2048, 4096}) {
+            TuneChoice c;
+            c.lds = 2;
+            c.target = tgt;
+            c.floor_rows = 512;
+            cands.push_back(c);
+          }
         if (gram_lds_ok(M, Nn, njobs))
           for (int tgt : {2048, 4096, 8192})
             for (int fl : {512, 1024}) {
@@ -1609,7 +1625,7 @@ int32_t ppcg_tune_report(const ppcg_handle* h, char* buf, int32_t cap) {
     snprintf(line, sizeof line, "%s site=%d %s%s%s%s %s<=%d N<=%d rows<=%ld -> %s target=%d floor=%d %.3f ms [", 
              k.kind ? "update" : "gram", k.site, k.f32 ? "f32" : "f64", k.cplx ? " complex" : "",
              k.multi ? " batched-jobs" : "", k.upper ? " upper" : "", k.kind ? "K" : "M", k.mb, k.nb, k.rb,
-             c.lds ? "lds" : "wave", c.target, c.floor_rows, c.ms);
+             c.lds == 2 ? "block" : (c.lds ? "lds" : "wave"), c.target, c.floor_rows, c.ms);
     out += line;
     out += c.tried;
     out += "]\n";
