@@ -101,6 +101,8 @@ TRAFFIC_KERNELS = {
 
 
 def _symbol_matches(sym, prefix, site):
+    if sym.startswith("void "):
+        sym = sym[5:]
     if not sym.startswith(prefix):
         return False
     if site is None:
@@ -108,7 +110,7 @@ def _symbol_matches(sym, prefix, site):
     return sym.rstrip().endswith(f", {site}>(ppcg::GramArgs)") or sym.rstrip().endswith(f", {site}>(ppcg::UpdateArgs)")
 
 
-def write_traffic(fetch_db, write_db, launches):
+def write_traffic(fetch_db, write_db, launches, path=None):
     """profiles/traffic.json from two rocprofv3 --pmc databases (FETCH_SIZE,
     WRITE_SIZE) of `bench.py --steps 1 --warmup 1 --only mixed --calib-copy`:
     per logical kernel, the mean HBM bytes per dispatch over the last
@@ -147,7 +149,7 @@ def write_traffic(fetch_db, write_db, launches):
             out["kernels"][name] = {"fetch_bytes_per_launch": d["FETCH_SIZE"], "write_bytes_per_launch": d["WRITE_SIZE"],
                                     "hbm_bytes_per_launch": d["FETCH_SIZE"] + d["WRITE_SIZE"],
                                     "launches": launches[name]}
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    path = path or os.path.join(ROOT, "profiles", "traffic.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
     log(f"wrote {path}: {sorted(out['kernels'])}")

@@ -179,11 +179,16 @@ struct RecOp {
   int kind;
   unsigned nwg;
   std::vector<uint8_t> args;
+  const char* name = nullptr;  // profiling name and algorithmic work of the op
+  double fl = 0, by = 0;
 };
 
 struct Recorder {
   std::vector<std::vector<RecOp>> lists;  // one op list per problem
   int cur = -1;
+  // work model of the op about to be recorded (set by the profiler scope)
+  const char* pend_name = nullptr;
+  double pend_fl = 0, pend_by = 0;
   void begin(int nprob) {
     lists.assign(nprob, {});
     cur = -1;
@@ -194,6 +199,11 @@ struct Recorder {
     op.nwg = nwg;
     op.args.resize(sz);
     std::memcpy(op.args.data(), a, sz);
+    op.name = pend_name;
+    op.fl = pend_fl;
+    op.by = pend_by;
+    pend_name = nullptr;
+    pend_fl = pend_by = 0;
     lists[cur].push_back(std::move(op));
   }
 };

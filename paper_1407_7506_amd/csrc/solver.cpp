@@ -113,6 +113,13 @@ struct Prof {
   // events are only recorded around real launches (not while recording a batch)
   bool active() const { return on && g_rec == nullptr; }
   // fl / by: algorithmic flops and compulsory HBM bytes of the launch
+  // recording a batch: the next recorded op carries this work model
+  void note(const char* n, double fl, double by) {
+    if (!on || !g_rec) return;
+    g_rec->pend_name = (fl + by > 0) ? n : nullptr;
+    g_rec->pend_fl = fl;
+    g_rec->pend_by = by;
+  }
   void begin(const char* n, double fl = 0, double by = 0) {
     if (!active()) return;
     hipEvent_t e = get();
@@ -160,9 +167,11 @@ struct Scope {
   bool live;
   Scope(Prof& p_, const char* n, double fl = 0, double by = 0) : p(p_), live(p_.active()) {
     if (live) p.begin(n, fl, by);
+    else p.note(n, fl, by);
   }
   ~Scope() {
     if (live) p.end();
+    else p.note(nullptr, 0, 0);
   }
 };
 
@@ -1079,12 +1088,19 @@ struct Driver {
 
   static const char* op_name(int kind) {
     switch (kind) {
-      case OP_GRAM_D0: case OP_GRAM_F0: case OP_GRAM_Z0: case OP_GRAM_C0: return "gram";
-      case OP_GRAM_D1: case OP_GRAM_F1: case OP_GRAM_Z1: case OP_GRAM_C1: return "gram_proj";
-      case OP_GRAM_D2: case OP_GRAM_F2: case OP_GRAM_Z2: case OP_GRAM_C2: return "gram_block";
+      case OP_GRAM_D0: case OP_GRAM_F0: case OP_GRAM_Z0: case OP_GRAM_C0: case OP_GRAML_D0: case OP_GRAML_F0:
+        return "gram";
+      case OP_GRAM_D1: case OP_GRAM_F1: case OP_GRAM_Z1: case OP_GRAM_C1: case OP_GRAML_D1: case OP_GRAML_F1:
+        return "gram_proj";
+      case OP_GRAM_D2: case OP_GRAM_F2: case OP_GRAM_Z2: case OP_GRAM_C2: case OP_GRAMB_1: case OP_GRAMB_2:
+        return "gram_block";
       case OP_REDUCE_D: case OP_REDUCE_F: case OP_REDUCE_Z: case OP_REDUCE_C: return "reduce";
-      case OP_UPDATE_D0: case OP_UPDATE_F0: case OP_UPDATE_Z0: case OP_UPDATE_C0: return "update";
-      case OP_UPDATE_D1: case OP_UPDATE_F1: case OP_UPDATE_Z1: case OP_UPDATE_C1: return "update_proj";
+      case OP_UPDATE_D0: case OP_UPDATE_F0: case OP_UPDATE_Z0: case OP_UPDATE_C0: case OP_UPDATEL_D0:
+      case OP_UPDATEL_F0:
+        return "update";
+      case OP_UPDATE_D1: case OP_UPDATE_F1: case OP_UPDATE_Z1: case OP_UPDATE_C1: case OP_UPDATEL_D1:
+      case OP_UPDATEL_F1:
+        return "update_proj";
       case OP_STENCIL_D2: case OP_STENCIL_D4: case OP_STENCIL_Z2: case OP_STENCIL_Z4: return "stencil_f64";
       case OP_STENCIL_F2: case OP_STENCIL_F4: case OP_STENCIL_C2: case OP_STENCIL_C4: return "stencil_f32";
       case OP_PENCIL24: case OP_PENCIL48: case OP_PENCIL96:
@@ -1145,7 +1161,15 @@ struct Driver {
         }
         continue;
       }
-      Scope sc(H->prof, op_name(g.kind));
+      double fl = 0, by = 0;
+      const char* nm = nullptr;
+      for (int i : g.idx) {
+        const RecOp& op = L[i][g.pos];
+        fl += op.fl;
+        by += op.by;
+        if (op.name) nm = op.name;
+      }
+      Scope sc(H->prof, nm ? nm : op_name(g.kind), fl, by);
       if (g.kind == OP_CHOL) {
         std::vector<CholArgs> jobs;
         for (int i : g.idx) {

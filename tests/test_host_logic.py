@@ -1,0 +1,113 @@
+"""Host-side logic without a GPU: the seeded input generators (shapes, ranges,
+determinism, the batch recipe), and the measurement helpers of bench.py (the
+roofline classification and the rocprofv3 counter reduction)."""
+import json
+import os
+import sqlite3
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1407_7506_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_default_nbuf_rule():
+    for k, q in [(64, 8), (512, 16), (2048, 32), (12, 4), (6, 1), (251, 8)]:
+        nb = I.default_nbuf(k, q)
+        assert (k + nb) % q == 0
+        assert nb >= max(2, int(np.ceil(0.02 * k)))
+        assert nb < max(2, int(np.ceil(0.02 * k))) + q
+
+
+def test_gaussian_wells_range_and_determinism():
+    V1 = I.gaussian_wells(16, 0.5, 4, 101)
+    V2 = I.gaussian_wells(16, 0.5, 4, 101)
+    assert np.array_equal(V1, V2)
+    assert V1.shape == (16 ** 3,)
+    # sum of 4 wells of depth in (1, 3): never below -12, never positive
+    assert V1.max() <= 0 and V1.min() >= -12.0
+    assert not np.array_equal(V1, I.gaussian_wells(16, 0.5, 4, 102))
+
+
+def test_smoothed_field_maps_onto_interval():
+    V = I.smoothed_field(12, 0.5, 103)
+    assert V.min() == pytest.approx(-2.0) and V.max() == pytest.approx(0.0)
+
+
+def test_start_block_statistics():
+    X = I.start_block(20000, 4, 5)
+    assert X.shape == (20000, 4) and X.dtype == np.float64
+    assert abs(X.mean()) < 0.02 and abs(X.var() - 1.0) < 0.03
+    Z = I.start_block(20000, 4, 5, complex_=True)
+    assert Z.dtype == np.complex128
+    assert abs(Z.real.var() - 0.5) < 0.02 and abs(Z.imag.var() - 0.5) < 0.02
+
+
+def test_workload_shapes():
+    p = I.wells48()
+    assert (p.grid.N, p.grid.order, p.k, p.q, p.K) == (48, 4, 512, 16, 528)
+    b = I.bloch96()
+    assert (b.grid.N, b.k, b.q, b.K) == (96, 2048, 32, 2112) and b.grid.is_complex
+    assert b.grid.kpt[0] == pytest.approx(2 * np.pi * 0.25 / 48.0)
+    ps = I.batch64()
+    assert len(ps) == 64
+    assert all(24 <= p.grid.N <= 40 and 32 <= p.k <= 256 and p.q == 8 and p.K % 8 == 0 for p in ps)
+    assert len({(p.grid.N, p.k) for p in ps}) > 40   # uneven sizes
+
+
+def test_colmajor_roundtrip():
+    X = np.arange(12.0).reshape(4, 3)
+    B = I.to_colmajor(X)
+    assert B.flags["C_CONTIGUOUS"] and B.shape == (3, 4)
+    assert np.array_equal(I.from_colmajor(B), X)
+
+
+def test_roofline_picks_bound_by_intensity():
+    # (ms, launches, flops, bytes)
+    kt = {"gram_proj": (10.0, 10, 1e12, 1e9), "stencil_f64": (5.0, 10, 1e9, 3e10), "eig": (50.0, 2, 0, 0)}
+    r = bench.roofline(kt, "mixed")
+    assert r["kernel"] == "gram_proj" and r["bound"] == "mfma" and r["dtype"] == "f32"
+    assert r["achieved"] == pytest.approx(100.0)            # 1e12 flops in 10 ms
+    assert r["frac"] == pytest.approx(100.0 / 157.3, abs=1e-4)
+    kt = {"stencil_f64": (5.0, 10, 1e9, 3e10)}
+    r = bench.roofline(kt, "fp64")
+    assert r["bound"] == "hbm" and r["achieved"] == pytest.approx(6000.0) and r["peak"] == 8000.0
+
+
+def _fake_db(path, counter, rows):
+    c = sqlite3.connect(path)
+    c.execute("create table counters_collection (dispatch_id int, kernel_name text, grid_size int, value real, "
+              "counter_name text)")
+    c.executemany("insert into counters_collection values (?,?,?,?,?)", [r + (counter,) for r in rows])
+    c.commit()
+    c.close()
+
+
+def test_traffic_reduction(tmp_path):
+    # the 1 GiB calibration copy reads as 512 MiB (factor 2) and writes as 1 GiB (factor 1)
+    gib_kib = float(1 << 20)
+    fetch = [(1, "__amd_rocclr_copyBuffer", 1, gib_kib / 2), (2, "__amd_rocclr_copyBuffer", 1, 4.0)]
+    write = [(1, "__amd_rocclr_copyBuffer", 1, gib_kib), (2, "__amd_rocclr_copyBuffer", 1, 4.0)]
+    # a warmup dispatch (not counted) and two timed ones of the site-1 Gram
+    for i, (f, w) in enumerate([(999.0, 999.0), (100.0, 10.0), (300.0, 30.0)]):
+        fetch.append((10 + i, "void ppcg::gram_lds_kernel<float, 32, 1>(ppcg::GramArgs)", 256, f))
+        write.append((10 + i, "void ppcg::gram_lds_kernel<float, 32, 1>(ppcg::GramArgs)", 256, w))
+    fetch.append((20, "void ppcg::gram_kernel<double, 4, 4, false, 0>(ppcg::GramArgs)", 64, 7.0))
+    write.append((20, "void ppcg::gram_kernel<double, 4, 4, false, 0>(ppcg::GramArgs)", 64, 7.0))
+    fdb, wdb = str(tmp_path / "f.db"), str(tmp_path / "w.db")
+    _fake_db(fdb, "FETCH_SIZE", fetch)
+    _fake_db(wdb, "WRITE_SIZE", write)
+    out = str(tmp_path / "traffic.json")
+    bench.write_traffic(fdb, wdb, {"gram_proj": 2}, path=out)
+    d = json.load(open(out))
+    g = d["kernels"]["gram_proj"]
+    assert g["launches"] == 2
+    assert g["fetch_bytes_per_launch"] == pytest.approx(2 * 1024 * (100 + 300) / 2, rel=1e-6)
+    assert g["write_bytes_per_launch"] == pytest.approx(1024 * (10 + 30) / 2, rel=1e-6)
+    assert d["calibration"]["FETCH_SIZE"]["factor"] == pytest.approx(2.0)
+    assert d["source_sha"] == bench.kernel_source_sha()
