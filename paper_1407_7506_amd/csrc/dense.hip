@@ -495,6 +495,7 @@ bool launch_grouped_dense(int kind, const void* jobs, const unsigned* start, int
 // block Jacobi
 // ---------------------------------------------------------------------------
 constexpr int JB = 16;           // block width
+constexpr int BJ_INIT_WG = 64;   // workgroups of the init step
 constexpr int J2 = 2 * JB;       // pair size
 constexpr int JLD = J2 + 1;
 #ifndef PPCG_BJ_INNER
@@ -518,7 +519,7 @@ struct EigDev {
   double* lam;
   double* Q;       // np x J2 x J2 scalars
   double* Vt;      // m x m accumulated rotations
-  double* tiny;
+  double* tiny;    // BJ_INIT_WG partial sums of |M|^2
   int* flags;      // np
   int* rank;       // m
   int* counter;    // shared by all problems of a call
@@ -541,7 +542,7 @@ static EigDev carve(const EigJob& j, int* counter) {
   w.lam = j.lam;
   w.Q = (double*)p; p += es * np * J2 * J2;
   w.Vt = (double*)p; p += es * (size_t)j.m * j.m;
-  w.tiny = (double*)p; p += 256;
+  w.tiny = (double*)p; p += sizeof(double) * BJ_INIT_WG;
   w.flags = (int*)p; p += sizeof(int) * ((np + 63) / 64 * 64);
   w.rank = (int*)p;
   w.counter = counter;
@@ -554,7 +555,8 @@ size_t eig_workspace_bytes(int m, int cplx) {
   int nblk = (m + JB - 1) / JB;
   int np = (nblk + 1) / 2;
   const size_t es = cplx ? 16 : 8;
-  return es * (size_t)np * J2 * J2 + es * (size_t)m * m + 256 + sizeof(int) * ((np + 63) / 64 * 64) +
+  return es * (size_t)np * J2 * J2 + es * (size_t)m * m + sizeof(double) * BJ_INIT_WG +
+         sizeof(int) * ((np + 63) / 64 * 64) +
          sizeof(int) * (size_t)m + 256;
 }
 
@@ -569,21 +571,29 @@ PPCG_DEV void pair_of(const EigDev& a, int t, int round, int& nI, int& nJ, int& 
 }
 
 // step kernels; `round` is shared by all jobs of a launch
+// BJ_INIT_WG workgroups: Vt = I, and partial sums of |M|^2 (one per workgroup)
+// from which every pair step forms the skip threshold rel_tol |M|_F
 template <class S>
-PPCG_DEV void bj_init_body(const EigDev& a, unsigned wg) {  // Vt = I; tiny (counter zeroed by the host)
+PPCG_DEV void bj_init_body(const EigDev& a, unsigned wg) {
   long mm = (long)a.m * a.m;
   S* Vt = (S*)a.Vt;
   const S* M = (const S*)a.M;
-  for (long e = wg * 256L + threadIdx.x; e < mm; e += 256L * 64) Vt[e] = from_real<S>(((e % a.m) == (e / a.m)) ? 1.0 : 0.0);
-  if (wg == 0) {
-    double s = 0;
-    for (long e = threadIdx.x; e < mm; e += 256) s += abs2_(M[(e % a.m) + (e / a.m) * a.ld]);
-    __shared__ double red[4];
-    s = wave_sum(s);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) *a.tiny = a.rel_tol * sqrt((red[0] + red[1]) + (red[2] + red[3]));
+  double s = 0;
+  for (long e = wg * 256L + threadIdx.x; e < mm; e += 256L * BJ_INIT_WG) {
+    const int i = (int)(e % a.m), j = (int)(e / a.m);
+    Vt[e] = from_real<S>(i == j ? 1.0 : 0.0);
+    s += abs2_(M[i + (long)j * a.ld]);
   }
+  __shared__ double red[4];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) a.tiny[wg] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+PPCG_DEV double bj_tiny(const EigDev& a) {
+  double s = 0;
+  for (int w = 0; w < BJ_INIT_WG; ++w) s += a.tiny[w];
+  return a.rel_tol * sqrt(s);
 }
 
 // NT threads per pair problem (more waves hide the LDS latency of the rounds)
@@ -600,7 +610,7 @@ PPCG_DEV void bj_pair_body(const EigDev& a, int round, unsigned t) {
   pair_of(a, t, round, nI, nJ, i0, j0);
   const int n2 = nI + nJ;
   auto gidx = [&](int x) { return x < nI ? i0 + x : j0 + (x - nI); };
-  const double tiny = *a.tiny;
+  const double tiny = bj_tiny(a);
   if (tid == 0) any = 0;
   __syncthreads();
   for (int e = tid; e < n2 * n2; e += NT) {
@@ -793,7 +803,7 @@ int block_jacobi_eig_grouped(const std::vector<EigJob>& jobs, Stage& stage, EigG
   auto wgs = [&](int step, const EigDev& a) -> unsigned {
     long mm = (long)a.m * a.m;
     switch (step) {
-      case 0: return (unsigned)std::min<long>(64, std::max<long>(1, (mm + 255) / 256));
+      case 0: return (unsigned)BJ_INIT_WG;
       case 1: return (unsigned)a.np;
       case 2: return (unsigned)(a.np * a.np + a.np * ((a.m + 63) / 64));
       case 3: return 1u;

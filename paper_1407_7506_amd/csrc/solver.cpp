@@ -798,8 +798,7 @@ struct Prob {
     double* Xn = xc(Xt(), nl);
     update(Xa, ld, m, Wk.Rinv.p, Kp, m, Xn, nullptr, m, ld, mixed ? fc(Wk.X32.f(), nl) : nullptr, nullptr, rows, 1.0,
            0.0, true, false, "update_xr");
-    launch_copy(X(), Xt(), (long)nl * ld * nc(), st);  // locked prefix
-    swapX();
+    swapX();  // the locked prefix is valid in both buffers (copied once per Rayleigh-Ritz)
   }
 
   // residual of the active columns: AX = H X, G = X^H AX, W = AX - X G.
@@ -928,6 +927,8 @@ struct Prob {
   // part 3: active G = diag(Lambda_act) and the residual bookkeeping for rho
   void enq_rr3() {
     int m = K - nl;
+    // the locked prefix of X, unchanged until the next Rayleigh-Ritz, into the other buffer
+    launch_copy(X(), Xt(), (long)nl * ld * nc(), st);
     launch_set_diag(Wk.G.d(), Kp, m, Wk.lam.d() + nl, cplx, st);
     int nwa = std::max(0, k - nl);
     launch_copy(Wk.cn.d() + nl, Wk.scal.d(), std::max(nwa, 1), st);  // shift cn by nl through scal
