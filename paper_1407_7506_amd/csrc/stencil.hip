@@ -23,41 +23,67 @@ PPCG_DEV S phased(S xp, S xm, const double* ph) {
 
 // S: double, float, zdouble, zfloat.  The coupling from point r to
 // r + a h e_d carries exp(i kappa_d a h) (gauge form of the Bloch phase).
+// A workgroup owns 256 consecutive points of an (x, y) plane and marches
+// through SZ consecutive z planes: the z neighbours of a point are the
+// centres of the planes before and after it, kept in registers, so each
+// point issues one load for z and the x, y neighbours come from the plane
+// the workgroup (or its neighbour) is loading anyway.
+constexpr int SZ = 16;  // z planes per workgroup
+
+PPCG_DEV int wrap_idx(int c, int d, int N) {
+  int r = c + d;
+  return r >= N ? r - N : (r < 0 ? r + N : r);
+}
+
 template <class S, int ORDER>
 PPCG_DEV void stencil_body(const StencilArgs& a, unsigned wg, unsigned nwg) {
   typedef typename sc_traits<S>::real_t R;
-  const long n = (long)a.N * a.N * a.N;
-  const unsigned bpc = (unsigned)((n + 255) / 256);
+  const int N = a.N;
+  const long NN = (long)N * N;
+  const unsigned tpp = (unsigned)((NN + 255) / 256);       // tiles per plane
+  const unsigned kch = (unsigned)((N + SZ - 1) / SZ);      // z chunks
   unsigned L = xcd_remap(wg, nwg);
-  int col = L / bpc;
-  long p = (long)(L % bpc) * 256 + threadIdx.x;
-  if (col >= a.ncols || p >= n) return;
+  const int col = (int)(L / (tpp * kch));
+  const unsigned rest = L % (tpp * kch);
+  const int kc = (int)(rest / tpp);
+  const long q = (long)(rest % tpp) * 256 + threadIdx.x;  // point inside the plane
+  if (col >= a.ncols || q >= NN) return;
   const S* x = (const S*)a.X + (long)col * a.ldx;
   S* y = (S*)a.Y + (long)col * a.ldy;
   const R* V = (const R*)a.V;
-  const int N = a.N;
-  const int NN = N * N;
-  int i = (int)(p % N);
-  int t = (int)(p / N);
-  int j = t % N;
-  int k = t / N;
-  const long b = p - i;                 // start of the x line
-  const long pl = p - (long)j * N;      // (i, 0, k)
-  const long pz = p - (long)k * NN;     // (i, j, 0)
-  auto wr = [N](int c, int d) { int r = c + d; return r >= N ? r - N : (r < 0 ? r + N : r); };
-  S xc = x[p];
-  S s1 = phased<S>(x[b + wr(i, 1)], x[b + wr(i, -1)], a.ph[0][0]) +
-         phased<S>(x[pl + (long)wr(j, 1) * N], x[pl + (long)wr(j, -1) * N], a.ph[1][0]) +
-         phased<S>(x[pz + (long)wr(k, 1) * NN], x[pz + (long)wr(k, -1) * NN], a.ph[2][0]);
-  S out = ((R)a.c0 + V[p]) * xc + (R)a.w1 * s1;
-  if (ORDER == 4) {
-    S s2 = phased<S>(x[b + wr(i, 2)], x[b + wr(i, -2)], a.ph[0][1]) +
-           phased<S>(x[pl + (long)wr(j, 2) * N], x[pl + (long)wr(j, -2) * N], a.ph[1][1]) +
-           phased<S>(x[pz + (long)wr(k, 2) * NN], x[pz + (long)wr(k, -2) * NN], a.ph[2][1]);
-    out += (R)a.w2 * s2;
+  const int i = (int)(q % N), j = (int)(q / N);
+  const long b = q - i;            // start of the x line in the plane
+  const long pl = q - (long)j * N;  // (i, 0) in the plane
+  const int k0 = kc * SZ;
+  const int k1 = k0 + SZ < N ? k0 + SZ : N;
+  auto at = [&](int k) { return x[q + (long)k * NN]; };
+  // z window: zm2 = k-2, zm1 = k-1, zc = k, zp1 = k+1, zp2 = k+2
+  S zm2 = ORDER == 4 ? at(wrap_idx(k0, -2, N)) : S{};
+  S zm1 = at(wrap_idx(k0, -1, N));
+  S zc = at(k0);
+  S zp1 = at(wrap_idx(k0, 1, N));
+  for (int k = k0; k < k1; ++k) {
+    S zp2 = ORDER == 4 ? at(wrap_idx(k, 2, N)) : S{};
+    const long pk = (long)k * NN;
+    const S* xp = x + pk;
+    const long p = q + pk;
+    S s1 = phased<S>(xp[b + wrap_idx(i, 1, N)], xp[b + wrap_idx(i, -1, N)], a.ph[0][0]) +
+           phased<S>(xp[pl + (long)wrap_idx(j, 1, N) * N], xp[pl + (long)wrap_idx(j, -1, N) * N], a.ph[1][0]) +
+           phased<S>(zp1, zm1, a.ph[2][0]);
+    S out = ((R)a.c0 + V[p]) * zc + (R)a.w1 * s1;
+    if (ORDER == 4) {
+      S s2 = phased<S>(xp[b + wrap_idx(i, 2, N)], xp[b + wrap_idx(i, -2, N)], a.ph[0][1]) +
+             phased<S>(xp[pl + (long)wrap_idx(j, 2, N) * N], xp[pl + (long)wrap_idx(j, -2, N) * N], a.ph[1][1]) +
+             phased<S>(zp2, zm2, a.ph[2][1]);
+      out += (R)a.w2 * s2;
+    }
+    if (a.shift) out -= (R)a.shift[col] * zc;
+    y[p] = out;
+    zm2 = zm1;
+    zm1 = zc;
+    zc = zp1;
+    zp1 = ORDER == 4 ? zp2 : at(wrap_idx(k, 2, N));
   }
-  if (a.shift) out -= (R)a.shift[col] * xc;
-  y[p] = out;
 }
 template <class S, int ORDER>
 __global__ __launch_bounds__(256) void stencil_kernel(StencilArgs a) {
@@ -91,8 +117,8 @@ static int stencil_kind(const StencilArgs& a) {
   }
 
 void launch_stencil(const StencilArgs& a, hipStream_t st) {
-  long n = (long)a.N * a.N * a.N;
-  unsigned blocks = (unsigned)(((n + 255) / 256) * a.ncols);
+  const long NN = (long)a.N * a.N;
+  unsigned blocks = (unsigned)(((NN + 255) / 256) * ((a.N + SZ - 1) / SZ) * (long)a.ncols);
   int kind = stencil_kind(a);
   if (g_rec) {
     g_rec->add(kind, &a, sizeof(a), blocks);
