@@ -268,45 +268,58 @@ PPCG_DEV void update_epilogue(const UpdateArgs& a, int job, int j0, long r0,
   constexpr int NC = CPLX ? 2 : 1;
   const int l = threadIdx.x & 63, lc = l & 15;
   const T alpha = (T)a.alpha, beta = (T)a.beta;
+  const bool norms = !CPLX && a.cpart != nullptr;
 #pragma unroll
   for (int x = 0; x < TJ; ++x)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      int j = j0 + 16 * x + acc_row<T>(l, v);
-      if (j >= a.N) continue;
-      T* cp;
-      bool scaled;
-      if (j < a.N0) {
-        cp = (T*)a.C0 + ((long)job * a.job_c_off + (long)j * a.ldc) * NC;
-        scaled = a.dsc != nullptr;
-      } else {
-        cp = (T*)a.C1 + ((long)job * a.job_c_off + (long)(j - a.N0) * a.ldc) * NC;
-        scaled = false;
-      }
-      float* c32 = a.C32 ? (float*)a.C32 + ((long)job * a.job_c_off + (long)j * a.ldc) * NC : nullptr;
+      const int j = j0 + 16 * x + acc_row<T>(l, v);
+      const bool jv = j < a.N;
+      double sq = 0;  // sum of squares of the values this lane stores in column j
+      if (jv) {
+        T* cp;
+        bool scaled;
+        if (j < a.N0) {
+          cp = (T*)a.C0 + ((long)job * a.job_c_off + (long)j * a.ldc) * NC;
+          scaled = a.dsc != nullptr;
+        } else {
+          cp = (T*)a.C1 + ((long)job * a.job_c_off + (long)(j - a.N0) * a.ldc) * NC;
+          scaled = false;
+        }
+        float* c32 = a.C32 ? (float*)a.C32 + ((long)job * a.job_c_off + (long)j * a.ldc) * NC : nullptr;
 #pragma unroll
-      for (int y = 0; y < TR; ++y) {
-        long r = (r0 + 16 * y + lc) * NC;
-        T v0 = alpha * acc[0][x][y][v];
-        T v1 = CPLX ? alpha * acc[NC - 1][x][y][v] : (T)0;
-        if (a.beta != 0) {
-          T c0 = cp[r], c1 = CPLX ? cp[r + 1] : (T)0;
-          if (scaled) {
-            T d = (T)a.dsc[r / NC];
-            c0 *= d;
-            c1 *= d;
+        for (int y = 0; y < TR; ++y) {
+          long r = (r0 + 16 * y + lc) * NC;
+          T v0 = alpha * acc[0][x][y][v];
+          T v1 = CPLX ? alpha * acc[NC - 1][x][y][v] : (T)0;
+          if (a.beta != 0) {
+            T c0 = cp[r], c1 = CPLX ? cp[r + 1] : (T)0;
+            if (scaled) {
+              T d = (T)a.dsc[r / NC];
+              c0 *= d;
+              c1 *= d;
+            }
+            v0 += beta * c0;
+            v1 += beta * c1;
           }
-          v0 += beta * c0;
-          v1 += beta * c1;
+          if (!a.c0_keep) {
+            cp[r] = v0;
+            if (CPLX) cp[r + 1] = v1;
+          }
+          if (c32) {
+            c32[r] = (float)v0;
+            if (CPLX) c32[r + 1] = (float)v1;
+          }
+          if (norms) {
+            const double w = c32 ? (double)(float)v0 : (double)v0;
+            sq += w * w;
+          }
         }
-        if (!a.c0_keep) {
-          cp[r] = v0;
-          if (CPLX) cp[r + 1] = v1;
-        }
-        if (c32) {
-          c32[r] = (float)v0;
-          if (CPLX) c32[r + 1] = (float)v1;
-        }
+      }
+      if (norms) {  // the 16 lanes of a lane group hold the same column: reduce over them
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) sq += __shfl_xor(sq, o, 64);
+        if (jv && lc == 0 && j < a.ncn) a.cpart[r0 / (16 * TR) + (long)j * a.ldp] = sq;
       }
     }
 }

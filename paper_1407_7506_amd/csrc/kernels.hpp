@@ -82,6 +82,10 @@ struct UpdateArgs {
   int site;        // call site (selects a distinct kernel symbol for profiling)
   int cplx;        // complex A, B, C (C32 then complex float)
   int lds;         // 1: LDS-staged 128 x 128 workgroup tiles (real, one job, rows % 128 == 0)
+  double* cpart;   // optional (real): per 64-row tile t and column j < ncn, the sum of squares of the
+                   // stored values at cpart[t + j * ldp] (column norms without re-reading C)
+  int ncn;
+  long ldp;
 };
 
 // stencil: Y = H X on an N^3 periodic grid (7- or 13-point), columns [0, ncols)
@@ -139,7 +143,7 @@ struct BlockUpdArgs {
 };
 
 // small per-problem kernels
-struct ColnormArgs { const void* X; int f32; long ld, rows; int ncols; double* out; };
+struct ColnormArgs { const void* X; int f32; long ld, rows; int ncols; double* out; int sum; };  // sum: plain column sums
 struct RitzArgs { const double* AX; const double* X; const double* lam; double* W; float* W32; long ld, rows; int ncols; };
 struct TransposeArgs { const double* src; int lds; double* dst; int ldd; int m, n; int cplx; };  // cplx: conjugate
 struct FillArgs { double* p; long count; double v; };
@@ -241,6 +245,8 @@ void launch_stencil(const StencilArgs& a, hipStream_t st);
 void launch_scale_rows(const double* d, const void* X, void* Y, long ld, long rows, int ncols, int f32, hipStream_t st);
 // out[c] = sum_r |X[r, c]|^2 (X f64 or f32), deterministic
 void launch_colnorm2(const void* X, int f32, long ld, long rows, int ncols, double* out, hipStream_t st);
+// out[j] = sum_r P[r + j ld], r < rows (double; fixed reduction order)
+void launch_colsum(const double* P, long ld, long rows, int ncols, double* out, hipStream_t st);
 // W[r, j] = AX[r, j] - X[r, j] * lam[j] (W and/or its float copy W32)
 void launch_ritz_resid(const double* AX, const double* X, const double* lam, double* W, float* W32, long ld,
                        long rows, int ncols, hipStream_t st);

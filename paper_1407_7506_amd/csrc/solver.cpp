@@ -182,7 +182,7 @@ struct Work {
   DBuf AXm;                           // float64 H X kept in mixed mode
   DBuf Vd, V32, td;
   DBuf G, GWP, L, Li, Rinv, SAS, SS, V1, Mr, Yv, Cc, lam;
-  DBuf part, bgram, bC, bflags, cn, scal, iflag, eigw, dminp, pwork;
+  DBuf part, bgram, bC, bflags, cn, scal, iflag, eigw, dminp, pwork, cpart;
   int* hpin = nullptr;                // pinned host scratch: doubles [0, 2Kp), ints from 4Kp + 8
   double* hpind = nullptr;
   size_t hpin_bytes = 0;
@@ -606,9 +606,10 @@ struct Prob {
   }
 
   // C = beta (D C) + alpha A B
+  // cpart (real only): column sums of squares of the stored values, per 64-row tile, for columns < ncn
   void update(const void* A, long lda, int Kk, const void* B, long ldb, int Nn, void* C0, void* C1, int N0, long ldc,
               float* C32, const double* dsc, long rws, double alpha, double beta, bool b_upper, bool f32,
-              const char* name = "update", bool c0_keep = false) {
+              const char* name = "update", bool c0_keep = false, double* cpart = nullptr, int ncn = 0) {
     if (Nn <= 0 || rws <= 0) return;
     UpdateArgs u{};
     u.A = A;
@@ -630,6 +631,11 @@ struct Prob {
     u.c0_keep = c0_keep;
     u.site = site_of(name);
     u.cplx = cplx;
+    if (cpart && !cplx && ncn > 0) {
+      u.cpart = cpart;
+      u.ncn = ncn;
+      u.ldp = rws / 64;
+    }
     const bool lds_ok = !cplx && rws % 128 == 0 && Nn >= 64;
     u.lds = lds_ok && Nn >= 96;
     if (tuning() && lds_ok) {
@@ -708,6 +714,7 @@ struct Prob {
     Wk.bgram.ensure((size_t)s * (nS + q) * (2 * nS - q) * xs());
     Wk.bC.ensure((size_t)s * 3 * q * q * xs());
     Wk.bflags.ensure((size_t)s * 4 + 256);
+    Wk.cpart.ensure((size_t)(rows / 64) * Kp * 8);
     if (3 * q > 48) Wk.pwork.ensure((size_t)s * pencil_work_elems() * xs());
     Wk.eigw.ensure(eig_workspace_bytes(K, cplx));
     // split partials: the largest Gram of the run
@@ -812,13 +819,18 @@ struct Prob {
     ColSet A = cols1(Xa, m, false), B = cols1(R, m, false);
     gram(A, B, m, m, rows, ld, nullptr, 0, Wk.G.p, Kp, true, false, 1, 0, 0, "gram_xax");
     float* W32a = mixed ? fc(Wk.W32.f(), nl) : nullptr;
-    update(Xa, ld, m, Wk.G.p, Kp, m, R, nullptr, m, ld, W32a, nullptr, rows, -1.0, 1.0, false, false, "update_resid",
-           mixed);
     int nwa = std::max(0, k - nl);
+    // real: column norms of the wanted active residual columns from the update's epilogue partials
+    double* cpart = cplx ? nullptr : Wk.cpart.d();
+    update(Xa, ld, m, Wk.G.p, Kp, m, R, nullptr, m, ld, W32a, nullptr, rows, -1.0, 1.0, false, false, "update_resid",
+           mixed, cpart, nwa);
     Scope s(prof, "colnorm");
-    // a complex column is read as a real column of twice the length
-    if (mixed) launch_colnorm2(W32a, 1, ld * nc(), rows * nc(), nwa, Wk.cn.d(), st);
-    else launch_colnorm2(R, 0, ld * nc(), rows * nc(), nwa, Wk.cn.d(), st);
+    if (!cplx) {
+      launch_colsum(Wk.cpart.d(), rows / 64, rows / 64, nwa, Wk.cn.d(), st);
+    } else {  // a complex column is read as a real column of twice the length
+      if (mixed) launch_colnorm2(W32a, 1, ld * nc(), rows * nc(), nwa, Wk.cn.d(), st);
+      else launch_colnorm2(R, 0, ld * nc(), rows * nc(), nwa, Wk.cn.d(), st);
+    }
     launch_frob2_sub(Wk.G.d(), Kp, nwa, Wk.scal.d(), cplx, st);
   }
 

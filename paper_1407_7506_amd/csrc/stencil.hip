@@ -158,7 +158,7 @@ PPCG_DEV void colnorm2_body(const ColnormArgs& a, unsigned wg, unsigned) {
   double s = 0;
   for (long r = threadIdx.x; r < a.rows; r += 256) {
     double v = (double)x[r];
-    s += v * v;
+    s += a.sum ? v : v * v;
   }
   __shared__ double red[4];
   s = wave_sum(s);
@@ -175,8 +175,18 @@ __global__ __launch_bounds__(256) void colnorm2_grouped(const ColnormArgs* jobs,
   int j = find_job(start, nj, blockIdx.x);
   colnorm2_body<T>(jobs[j], blockIdx.x - start[j], start[j + 1] - start[j]);
 }
+void launch_colsum(const double* P, long ld, long rows, int ncols, double* out, hipStream_t st) {
+  ColnormArgs a{P, 0, ld, rows, ncols, out, 1};
+  unsigned blocks = ncols > 0 ? (unsigned)ncols : 0;
+  if (g_rec) {
+    g_rec->add(OP_COLNORM_D, &a, sizeof(a), blocks);
+    return;
+  }
+  if (blocks == 0) return;
+  hipLaunchKernelGGL(colnorm2_kernel<double>, dim3(blocks), dim3(256), 0, st, a);
+}
 void launch_colnorm2(const void* X, int f32, long ld, long rows, int ncols, double* out, hipStream_t st) {
-  ColnormArgs a{X, f32, ld, rows, ncols, out};
+  ColnormArgs a{X, f32, ld, rows, ncols, out, 0};
   unsigned blocks = ncols > 0 ? (unsigned)ncols : 0;
   if (g_rec) {
     g_rec->add(f32 ? OP_COLNORM_F : OP_COLNORM_D, &a, sizeof(a), blocks);
