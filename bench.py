@@ -305,7 +305,7 @@ def main():
                          "tune_classes": len(tune.splitlines())}
         log(f"{prec}: {dt / args.steps:.3f} s/solve, iters {infos[-1]['iters']}, rr {infos[-1]['n_rr']}, "
             f"resid {infos[-1]['resid_final']:.3e}")
-        top = sorted(kt.items(), key=lambda x: -x[1][0])[:8]
+        top = sorted(kt.items(), key=lambda x: -x[1][0])[:24]
         for name, (ms, cnt, fl, by) in top:
             log(f"   {name:14s} {ms / args.steps:9.1f} ms/solve {cnt // args.steps:6d} launches "
                 f"{ms / max(cnt, 1) * 1e3:9.1f} us/launch")

@@ -40,8 +40,8 @@ PPCG_DEV void block_pencil_body(const PencilArgs& a, unsigned wg, unsigned) {
   static_assert(IN_LDS || 4L * NB * LD <= pencil_work_elems(), "pencil scratch too small");
   __shared__ S shm[IN_LDS ? 4 * NB * LD : 1];
   __shared__ double Dv[NB], cs[NB + 2];
-  __shared__ S uu[NB / 2 + 1];
-  __shared__ int keep[NB], acc[NB], pq[NB + 2], cnt, nacc, sing;
+  __shared__ JRot<S> jr[NB / 2 + 1];
+  __shared__ int keep[NB], acc[NB], pq[NB + 2], nacc, sing;
   const int tid = threadIdx.x;
   const int blk = (int)wg;
   S* b0 = IN_LDS ? shm : (S*)a.work + (long)blk * pencil_work_elems();
@@ -206,7 +206,7 @@ PPCG_DEV void block_pencil_body(const PencilArgs& a, unsigned wg, unsigned) {
 #pragma unroll
       for (int w = 0; w < NT / 64; ++w) fro += cs[w];
       __syncthreads();
-      lds_jacobi<NT, S>(b3, b0, r, LD, a.jacobi_rel * sqrt(fro), 40, cs, uu, pq, &cnt);
+      lds_jacobi<NT, S>(b3, b0, r, LD, a.jacobi_rel * sqrt(fro), 40, jr, cs);
     }
     // 8. ascending order (ties by index): rank -> keep[] reused as sel
     for (int x = tid; x < r; x += NT) {

@@ -600,9 +600,9 @@ PPCG_DEV double bj_tiny(const EigDev& a) {
 template <class S, int NT>
 PPCG_DEV void bj_pair_body(const EigDev& a, int round, unsigned t) {
   __shared__ S Sm[J2 * JLD], Qs[J2 * JLD];
-  __shared__ double cs[J2 + 2];
-  __shared__ S uu[J2 / 2 + 1];
-  __shared__ int pq[J2 + 2], cnt, any;
+  __shared__ double red[NT / 64];
+  __shared__ JRot<S> jr[J2 / 2 + 1];
+  __shared__ int any;
   const S* M = (const S*)a.M;
   const int tid = threadIdx.x;
   if (round >= a.nbe - 1) return;
@@ -624,7 +624,7 @@ PPCG_DEV void bj_pair_body(const EigDev& a, int round, unsigned t) {
     if (tid == 0) a.flags[t] = 0;
     return;
   }
-  lds_jacobi<NT, S>(Sm, Qs, n2, JLD, tiny, BJ_INNER, cs, uu, pq, &cnt);
+  lds_jacobi<NT, S>(Sm, Qs, n2, JLD, tiny, BJ_INNER, jr, red);
   S* Qg = (S*)a.Q + (long)t * J2 * J2;
   for (int e = tid; e < n2 * n2; e += NT) Qg[(e % n2) + (e / n2) * J2] = Qs[(e % n2) + (e / n2) * JLD];
   if (tid == 0) {

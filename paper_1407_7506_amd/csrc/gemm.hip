@@ -227,6 +227,7 @@ PPCG_DEV void reduce_body(const ReduceArgs& r, unsigned wg, unsigned) {
   if (r.upper_only && i > j) return;
   const T* p = (const T*)r.part + ((long)job * r.splits * r.split_stride + i + (long)j * r.ldp) * NC;
   double s0 = 0, s1 = 0;
+#pragma unroll 8
   for (int t = 0; t < r.splits; ++t) {
     s0 += (double)p[(long)t * r.split_stride * NC];
     if (CPLX) s1 += (double)p[(long)t * r.split_stride * NC + 1];

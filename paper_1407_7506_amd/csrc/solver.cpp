@@ -576,7 +576,7 @@ struct Prob {
             cands.push_back(c);
           }
         if (gram_lds_ok(M, Nn, njobs))
-          for (int tgt : {2048, 4096, 8192})
+          for (int tgt : {512, 1024, 2048, 4096, 8192})
             for (int fl : {512, 1024}) {
               TuneChoice c;
               c.lds = 1;
