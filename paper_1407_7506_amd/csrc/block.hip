@@ -58,20 +58,41 @@ PPCG_DEV void block_pencil_body(const PencilArgs& a, unsigned wg, unsigned) {
   for (int pass = 0; pass < 2; ++pass) {
     const bool allowP = (nS == 3 * q) && pass == 0;
     // 1. load A (b0) and B (b1)
-    for (int e = tid; e < nS * nS; e += NT) {
-      int i = e % nS, j = e / nS;
-      b1[i + j * LD] = gram[i + j * ldgr];
-      if (j >= q) {
-        // X rows of the W / P columns: (H X_j)^H W_j and (H X_j)^H P_j when available
-        b0[i + j * LD] = (a.ax_rows && i < q) ? gram[(nS + i) + j * ldgr] : gram[i + (nS + j - q) * ldgr];
-      } else if (i < q) {
-        b0[i + j * LD] = Gm[(c0 + i) + (long)(c0 + j) * a.ldg];
+    if (a.tiles16) {
+      // 16 x 16 tiles of the upper block triangle; the lower blocks mirror them
+      for (int e = tid; e < nS * nS; e += NT) {
+        const int i = e % nS, j = e / nS;
+        const int I = i >> 4, J = j >> 4;
+        const bool up = I <= J;
+        const int lo = up ? I : J, hi = up ? J : I;
+        const int o = up ? (i & 15) + 16 * (j & 15) : (j & 15) + 16 * (i & 15);
+        const int ts = lo == 0 ? hi : (lo == 1 ? 2 + hi : 5);
+        const int th = lo == 0 ? 8 + hi : (lo == 1 ? 5 + hi : 8);
+        const S vs = gram[ts * 256 + o];
+        b1[i + j * LD] = up ? vs : conj_(vs);
+        if (hi == 0) {
+          b0[i + j * LD] = Gm[(c0 + i) + (long)(c0 + j) * a.ldg];
+        } else {
+          const S vh = gram[th * 256 + o];
+          b0[i + j * LD] = up ? vh : conj_(vh);
+        }
       }
-    }
-    __syncthreads();
-    for (int e = tid; e < nS * q; e += NT) {
-      int j = e % q, i = q + e / q;  // fill the X columns below the X block
-      if (i < nS) b0[i + j * LD] = conj_(b0[j + i * LD]);
+    } else {
+      for (int e = tid; e < nS * nS; e += NT) {
+        int i = e % nS, j = e / nS;
+        b1[i + j * LD] = gram[i + j * ldgr];
+        if (j >= q) {
+          // X rows of the W / P columns: (H X_j)^H W_j and (H X_j)^H P_j when available
+          b0[i + j * LD] = (a.ax_rows && i < q) ? gram[(nS + i) + j * ldgr] : gram[i + (nS + j - q) * ldgr];
+        } else if (i < q) {
+          b0[i + j * LD] = Gm[(c0 + i) + (long)(c0 + j) * a.ldg];
+        }
+      }
+      __syncthreads();
+      for (int e = tid; e < nS * q; e += NT) {
+        int j = e % q, i = q + e / q;  // fill the X columns below the X block
+        if (i < nS) b0[i + j * LD] = conj_(b0[j + i * LD]);
+      }
     }
     __syncthreads();
     // Hermitian parts

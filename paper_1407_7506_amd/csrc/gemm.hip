@@ -410,6 +410,92 @@ __global__ __launch_bounds__(64) void update_grouped(const UpdateArgs* jobs, con
 }
 
 // ---------------------------------------------------------------------------
+// Per-block pencil Grams for 16-column blocks (one wave per block and split):
+// every slab of the block is read once per row (lane group g reads 4
+// consecutive rows of column lc, as in gram_body) and only the 11 tiles of
+// the overlap and H matrices that the pencil uses are accumulated, in
+// float64.
+// ---------------------------------------------------------------------------
+template <bool F32, bool HASP, bool AXR>
+PPCG_DEV void block_gram_body(const BlockGramArgs& a, unsigned wg, unsigned nwg) {
+  typedef typename AccT<double>::type acc_t;
+  const int l = threadIdx.x, lc = l & 15, g = l >> 4;
+  const unsigned L = xcd_remap(wg, nwg);
+  const int blk = (int)(L % (unsigned)a.nblocks);
+  const int split = (int)(L / (unsigned)a.nblocks);
+  const long rbeg = (long)split * a.chunk;
+  const long rend = rbeg + a.chunk < a.rows ? rbeg + a.chunk : a.rows;
+  const long col = ((long)blk * 16 + lc) * a.ld;
+  const int es = F32 ? 4 : 8;
+  const char* px = (const char*)(a.X + col);
+  const char* pw = (const char*)a.W + col * es;
+  const char* pp = HASP ? (const char*)a.P + col * es : nullptr;
+  const char* paw = (const char*)a.AW + col * es;
+  const char* pap = HASP ? (const char*)a.AP + col * es : nullptr;
+  const char* pax = AXR ? (const char*)(a.AX + col) : nullptr;
+  acc_t acc[BG_TILES];
+#pragma unroll
+  for (int t = 0; t < BG_TILES; ++t) acc[t] = acc_t{0, 0, 0, 0};
+  for (long r = rbeg; r < rend; r += 16) {
+    const long rr = r + 4 * g;
+    double x[4], w[4], p[4], aw[4], ap[4], ax[4];
+    Load4<double, false>::go(px + rr * 8, false, x, nullptr);
+    Load4<double, false>::go(pw + rr * es, F32, w, nullptr);
+    Load4<double, false>::go(paw + rr * es, F32, aw, nullptr);
+    if (HASP) {
+      Load4<double, false>::go(pp + rr * es, F32, p, nullptr);
+      Load4<double, false>::go(pap + rr * es, F32, ap, nullptr);
+    }
+    if (AXR) Load4<double, false>::go(pax + rr * 8, false, ax, nullptr);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      acc[0] = mfma(x[e], x[e], acc[0]);
+      acc[1] = mfma(x[e], w[e], acc[1]);
+      acc[3] = mfma(w[e], w[e], acc[3]);
+      acc[6] = mfma(w[e], aw[e], acc[6]);
+      acc[9] = AXR ? mfma(ax[e], w[e], acc[9]) : mfma(x[e], aw[e], acc[9]);
+      if (HASP) {
+        acc[2] = mfma(x[e], p[e], acc[2]);
+        acc[4] = mfma(w[e], p[e], acc[4]);
+        acc[5] = mfma(p[e], p[e], acc[5]);
+        acc[7] = mfma(w[e], ap[e], acc[7]);
+        acc[8] = mfma(p[e], ap[e], acc[8]);
+        acc[10] = AXR ? mfma(ax[e], p[e], acc[10]) : mfma(x[e], ap[e], acc[10]);
+      }
+    }
+  }
+  double* out = a.out + ((long)blk * a.splits + split) * (BG_TILES * 256);
+#pragma unroll
+  for (int t = 0; t < BG_TILES; ++t) {
+    if (!HASP && (t == 2 || t == 4 || t == 5 || t == 7 || t == 8 || t == 10)) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) out[t * 256 + acc_row<double>(l, v) + 16 * lc] = acc[t][v];
+  }
+}
+template <bool F32, bool HASP, bool AXR>
+__global__ __launch_bounds__(64) void block_gram_kernel(BlockGramArgs a) {
+  block_gram_body<F32, HASP, AXR>(a, blockIdx.x, gridDim.x);
+}
+
+void launch_block_gram(const BlockGramArgs& a, hipStream_t st) {
+  if (g_rec) throw std::invalid_argument("block gram: not available in grouped launches");
+  if (a.rows % 16 || a.chunk % 16 || a.nblocks <= 0 || a.splits <= 0 || !a.X || !a.W || !a.AW || !a.out ||
+      (a.hasP && (!a.P || !a.AP)))
+    throw std::invalid_argument("block gram: bad arguments");
+  const unsigned grid = (unsigned)a.nblocks * (unsigned)a.splits;
+  const bool axr = a.AX != nullptr;
+#define PPCG_BG(F, H, X) hipLaunchKernelGGL((block_gram_kernel<F, H, X>), dim3(grid), dim3(64), 0, st, a)
+  if (a.f32) {
+    if (a.hasP) { if (axr) PPCG_BG(true, true, true); else PPCG_BG(true, true, false); }
+    else { if (axr) PPCG_BG(true, false, true); else PPCG_BG(true, false, false); }
+  } else {
+    if (a.hasP) { if (axr) PPCG_BG(false, true, true); else PPCG_BG(false, true, false); }
+    else { if (axr) PPCG_BG(false, false, true); else PPCG_BG(false, false, false); }
+  }
+#undef PPCG_BG
+}
+
+// ---------------------------------------------------------------------------
 // LDS-staged variants for large real shapes.  A workgroup of four waves
 // (2 x 2) owns a 128 x 128 output tile.  Each chunk of KC reduction indices
 // (rows of the tall operands for gram, columns of A for update) of both

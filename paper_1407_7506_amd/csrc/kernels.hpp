@@ -49,6 +49,31 @@ struct GramArgs {
                       // 2: per-block single pass (real, float64 accumulation, M <= 128, N <= 160)
 };
 
+// Per-block Grams of the 3q x 3q pencils for q = 16, real: only the tiles the
+// pencil reads.  Block j owns columns [16 j, 16 j + 16) of every slab.  Per
+// block and split, 11 tiles of 16 x 16 (column-major) in this order:
+//   overlap  0 X^T X, 1 X^T W, 2 X^T P, 3 W^T W, 4 W^T P, 5 P^T P
+//   H        6 W^T AW, 7 W^T AP, 8 P^T AP,
+//            9 X^T H W and 10 X^T H P (from AX^T W and AX^T P when AX is given,
+//              else from X^T AW and X^T AP)
+// Without P the tiles that involve P are not formed.
+constexpr int BG_TILES = 11;
+struct BlockGramArgs {
+  const double* X;   // float64 slabs, ld
+  const void* W;     // W, P, AW, AP: float32 when f32, else float64
+  const void* P;
+  const void* AW;
+  const void* AP;
+  const double* AX;  // optional float64 H X (mixed precision)
+  long ld;
+  long rows;         // multiple of 16
+  int nblocks, hasP, f32;
+  int splits;
+  long chunk;        // rows per split (multiple of 16)
+  double* out;       // partials: out + (block * splits + split) * BG_TILES * 256
+};
+void launch_block_gram(const BlockGramArgs& a, hipStream_t st);
+
 struct ReduceArgs {
   const void* part;
   int M, N, ldp, splits;
@@ -107,7 +132,7 @@ struct StencilArgs {
 
 // block pencils (steps 12-13): one workgroup per sub-block
 struct PencilArgs {
-  const double* gram;   // per block: Gram rows x (2 nS - q), ld = rows, stride gstride
+  const double* gram;   // per block: Gram rows x (2 nS - q), ld = rows (or BG_TILES tiles), stride gstride
   long gstride;
   const double* G;      // X^H A X of the active columns (m x m, ldg); the X block is G[jq.., jq..]
   int ldg;
@@ -121,6 +146,7 @@ struct PencilArgs {
   double jacobi_rel;    // rotations below jacobi_rel |M|_F are skipped
   int nblocks;
   int cplx;             // complex Hermitian pencils (gram, G and C complex)
+  int tiles16;          // 1: gram holds the BG_TILES tiles of the 16-column block Gram kernel
   void* work;           // nS > 48 only: per block 4 * 96 * 97 scalars of device scratch for the
                         // pencil matrices (too large for LDS), stride pencil_work_elems()
 };

@@ -204,7 +204,7 @@ struct Work {
 // Autotuner table: the fastest kernel variant and row-split schedule found
 // for each shape class (powers-of-two buckets of the operand sizes).
 struct TuneKey {
-  int kind;     // 0 Gram, 1 update
+  int kind;     // 0 Gram, 1 update, 2 16-column block Grams
   int site;     // Gram call site (0 plain, 1 projection, 2 per-block); -1 for updates
   int f32, cplx, multi, upper;
   int mb, nb;   // buckets of M x N (Gram) or K x N (update)
@@ -414,7 +414,8 @@ struct Prob {
       HIPCHECK(hipEventElapsedTime(&ms, H->tev[0], H->tev[1]));
       cands[i].ms = ms;
       char b[96];
-      snprintf(b, sizeof b, "%s%s/%d/%d:%.3f", i ? " " : "", cands[i].lds == 2 ? "block" : (cands[i].lds ? "lds" : "wave"), cands[i].target,
+      snprintf(b, sizeof b, "%s%s/%d/%d:%.3f", i ? " " : "",
+               cands[i].lds == 3 ? "tiles16" : (cands[i].lds == 2 ? "block" : (cands[i].lds ? "lds" : "wave")), cands[i].target,
                cands[i].floor_rows, ms);
       tried += b;
       if (ms < cands[best].ms) best = (int)i;
@@ -605,6 +606,84 @@ struct Prob {
     launch_reduce(r, f32acc, st);
   }
 
+  // Per-block pencil Grams of 16-column real blocks (steps 12-13 input) with
+  // the tile kernel: the slabs of each block are read once and only the
+  // tiles the pencil uses are formed.  Returns false where it does not apply
+  // (complex, other block widths, grouped launches).
+  long bg_splits(long target, int s) const {
+    long sp = std::max(1L, std::min((target + s - 1) / s, std::max(1L, rows / 256)));
+    long chunk = round_up((rows + sp - 1) / sp, 16);
+    return (rows + chunk - 1) / chunk;
+  }
+  bool block_gram(const void* Wa, const void* Pa, const void* AWa, const void* APa, bool hasP, int s) {
+    if (cplx || q != 16 || g_rec || rows % 16 || s <= 0) return false;
+    BlockGramArgs b{};
+    b.X = xc(X(), nl);
+    b.W = Wa;
+    b.P = hasP ? Pa : nullptr;
+    b.AW = AWa;
+    b.AP = hasP ? APa : nullptr;
+    b.AX = mixed ? xc(Wk.AXm.d(), nl) : nullptr;
+    b.ld = ld;
+    b.rows = rows;
+    b.nblocks = s;
+    b.hasP = hasP;
+    b.f32 = mixed;
+    b.out = Wk.part.d();
+    const long one = (long)s * BG_TILES * 256 * 8;
+    ReduceArgs r{};
+    r.part = Wk.part.p;
+    r.M = BG_TILES * 256;
+    r.N = 1;
+    r.ldp = r.M;
+    r.split_stride = r.M;
+    r.njobs = s;
+    r.dst = Wk.bgram.p;
+    r.ldd = r.M;
+    r.dst_job_stride = r.M;
+    r.alpha = 1.0;
+    r.beta = 0.0;
+    auto set_plan = [&](long target) {
+      long sp = std::min(bg_splits(target, s), std::max(1L, (long)(Wk.part.bytes / one)));
+      b.chunk = round_up((rows + sp - 1) / sp, 16);
+      b.splits = (int)((rows + b.chunk - 1) / b.chunk);
+      r.splits = b.splits;
+    };
+    long target = 4096;
+    if (tuning()) {
+      TuneKey key{2, 2, mixed ? 1 : 0, 0, 0, hasP ? 1 : 0, bucket(s), 16, bucket(rows)};
+      auto it = H->tune.find(key);
+      if (it == H->tune.end()) {
+        std::vector<TuneChoice> cands;
+        for (int tgt : {1024, 2048, 4096, 8192}) {
+          TuneChoice c;
+          c.lds = 3;
+          c.target = tgt;
+          cands.push_back(c);
+        }
+        TuneChoice best = time_candidates(cands, [&](const TuneChoice& c) {
+          set_plan(c.target);
+          launch_block_gram(b, st);
+          launch_reduce(r, false, st);
+        });
+        it = H->tune.emplace(key, best).first;
+      }
+      target = it->second.target;
+    }
+    set_plan(target);
+    {
+      const double es = mixed ? 4.0 : 8.0;
+      const double tiles = hasP ? BG_TILES : 5;
+      const double fl = tiles * 2.0 * 256.0 * (double)rows * s;
+      const double by = (double)rows * 16.0 * s * (8.0 + (hasP ? 4 : 2) * es + (mixed ? 8.0 : 0.0));
+      Scope sc(prof, "gram_block", fl, by);
+      launch_block_gram(b, st);
+    }
+    Scope sr(prof, "reduce");
+    launch_reduce(r, false, st);
+    return true;
+  }
+
   // C = beta (D C) + alpha A B
   // cpart (real only): column sums of squares of the stored values, per 64-row tile, for columns < ncn
   void update(const void* A, long lda, int Kk, const void* B, long ldb, int Nn, void* C0, void* C1, int N0, long ldc,
@@ -745,6 +824,8 @@ struct Prob {
     acc(K, K, 1, rows, xs());
     acc(nS + q, 2 * nS - q, s, rows, xs(), 2);
     acc(K, K, 1, Kp, xs());
+    if (!cplx && q == 16)  // 16-column block Grams, finest candidate
+      need = std::max(need, (size_t)bg_splits(8192, s) * s * BG_TILES * 256 * 8);
     Wk.part.ensure(need);
     Wk.pinned((size_t)(4 * Kp + 64) * 8);
     // zero everything that carries padding rows
@@ -1011,11 +1092,14 @@ struct Prob {
       }
       B.nseg = bi;
       int Nb = 2 * nS - q;
-      gram(A, B, Ma, Nb, rows, ld, nullptr, 0, Wk.bgram.p, Ma, false, false, s, (long)q * ld, (long)Ma * Nb,
-           "gram_block");
+      const bool tiles = block_gram(Wa, Pa, AWa, APa, hasP, s);
+      if (!tiles)
+        gram(A, B, Ma, Nb, rows, ld, nullptr, 0, Wk.bgram.p, Ma, false, false, s, (long)q * ld, (long)Ma * Nb,
+             "gram_block");
       PencilArgs pa{};
       pa.gram = Wk.bgram.d();
-      pa.gstride = (long)Ma * Nb;
+      pa.gstride = tiles ? (long)BG_TILES * 256 : (long)Ma * Nb;
+      pa.tiles16 = tiles;
       pa.ax_rows = mixed;
       pa.G = Wk.G.d();
       pa.ldg = Kp;
@@ -1660,9 +1744,9 @@ int32_t ppcg_tune_report(const ppcg_handle* h, char* buf, int32_t cap) {
     const TuneChoice& c = kv.second;
     char line[256];
     snprintf(line, sizeof line, "%s site=%d %s%s%s%s %s<=%d N<=%d rows<=%ld -> %s target=%d floor=%d %.3f ms [", 
-             k.kind ? "update" : "gram", k.site, k.f32 ? "f32" : "f64", k.cplx ? " complex" : "",
-             k.multi ? " batched-jobs" : "", k.upper ? " upper" : "", k.kind ? "K" : "M", k.mb, k.nb, k.rb,
-             c.lds == 2 ? "block" : (c.lds ? "lds" : "wave"), c.target, c.floor_rows, c.ms);
+             k.kind == 2 ? "block-gram" : (k.kind ? "update" : "gram"), k.site, k.f32 ? "f32" : "f64", k.cplx ? " complex" : "",
+             k.multi ? " batched-jobs" : "", k.upper ? (k.kind == 2 ? " with-P" : " upper") : "", k.kind ? "K" : "M", k.mb, k.nb, k.rb,
+             c.lds == 3 ? "tiles16" : (c.lds == 2 ? "block" : (c.lds ? "lds" : "wave")), c.target, c.floor_rows, c.ms);
     out += line;
     out += c.tried;
     out += "]\n";

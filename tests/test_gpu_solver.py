@@ -94,6 +94,7 @@ SMALL = [
     dict(N=10, k=36, q=20, order=2),           # 2q = 40 and 3q = 60: LDS and device-scratch pencils
     dict(N=12, k=60, q=32, order=4),           # q = 32: 96 x 96 pencils in device scratch
     dict(N=16, k=120, q=8, order=4),           # K = 128: LDS-staged 128 x 128 Gram / update kernels
+    dict(N=16, k=48, q=16, order=4),           # q = 16, default nbuf: 16-column block Gram tiles
 ]
 
 
@@ -138,7 +139,7 @@ def test_wells16_fp64_golden(h64):
     assert np.abs(lam - lo).max() / np.abs(lo).max() <= 1e-9
 
 
-@pytest.mark.parametrize("case", SMALL[:4] + SMALL[-1:], ids=lambda c: "-".join(f"{k}{v}" for k, v in c.items()))
+@pytest.mark.parametrize("case", SMALL[:4] + SMALL[-2:], ids=lambda c: "-".join(f"{k}{v}" for k, v in c.items()))
 def test_mixed_matches_oracle(hmix, case):
     p = I.small_problem(tol=1e-8, **case)
     say("mixed vs oracle", p.name)
