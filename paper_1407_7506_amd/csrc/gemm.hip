@@ -908,7 +908,7 @@ constexpr int GTM = 4, GTN = 4, UTJ = 4, UTR = 4;   // real tiles
 constexpr int BTN = 5;  // real per-block Grams: 64 x 80 tiles, i.e. one tile per block for q <= 16
 constexpr int ZTM = 2, ZTN = 2, ZTJ = 2, ZTR = 2;   // complex tiles
 
-constexpr int GKC_D = 16, GKC_F = 32, UKC_D = 32, UKC_F = 32;  // LDS chunk depths (measured best)
+constexpr int GKC_D = 16, GKC_F = 32, UKC_D = 32, UKC_F = 16;  // LDS chunk depths (measured best)
 
 void gram_tiles(GramArgs& a) {
   if (a.lds == 2) {
