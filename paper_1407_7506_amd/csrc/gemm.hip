@@ -565,6 +565,14 @@ PPCG_DEV void gram_lds_body(const GramArgs& a, unsigned wg, unsigned nwg) {
     pb[q] = (const char*)seg_col(a.B, vb[q] ? cb : 0, a.ld, joff, fb[q], 8);
     sb[q] = a.dsc != nullptr && cb < a.nsc;
   }
+  // 16 x 16 sub-tiles of this wave's quadrant that carry results: inside
+  // M x N and, for a diagonal tile of an upper-only Gram, on or above the
+  // diagonal (the rest is never read; skipping it leaves every used entry
+  // bitwise the same)
+  const int nxv = max(0, min(4, (a.M - (i0 + wi * 64) + 15) / 16));
+  const int nyv = max(0, min(4, (a.N - (j0 + wj * 64) + 15) / 16));
+  const bool dg = a.upper_only && ti == tj;
+  const bool full = nxv == 4 && nyv == 4 && !dg;
   T ra[NQ][4], rb[NQ][4];
   auto gload = [&](long r) {
     const long rr = r + 4 * part;
@@ -617,12 +625,23 @@ PPCG_DEV void gram_lds_body(const GramArgs& a, unsigned wg, unsigned nwg) {
         get4(&As[buf][(wi * 64 + 16 * t + lc) * S + kk + 4 * g], av[t]);
         get4(&Bs[buf][(wj * 64 + 16 * t + lc) * S + kk + 4 * g], bv[t]);
       }
+      if (full) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
+        for (int e = 0; e < 4; ++e)
 #pragma unroll
-        for (int x = 0; x < 4; ++x)
+          for (int x = 0; x < 4; ++x)
 #pragma unroll
-          for (int y = 0; y < 4; ++y) acc[x][y] = mfma(av[x][e], bv[y][e], acc[x][y]);
+            for (int y = 0; y < 4; ++y) acc[x][y] = mfma(av[x][e], bv[y][e], acc[x][y]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y)
+              if (x < nxv && y < nyv && !(dg && (wi > wj || (wi == wj && x > y))))
+                acc[x][y] = mfma(av[x][e], bv[y][e], acc[x][y]);
+      }
     }
     if (NBUF == 1) __syncthreads();
     if (c + 1 < nch) sput(NBUF == 2 ? buf ^ 1 : 0);
@@ -717,33 +736,59 @@ PPCG_DEV void update_lds_body(const UpdateArgs& a, unsigned wg, unsigned nwg) {
   for (int x = 0; x < 4; ++x)
 #pragma unroll
     for (int y = 0; y < 4; ++y) acc[0][x][y] = acc_t{0, 0, 0, 0};
+  // output columns of this wave's quadrant inside N, in 16-column sub-tiles
+  const int nxv = max(0, min(4, (a.N - (j0 + wj * 64) + 15) / 16));
   if (nch > 0) {
     gload(0);
     sput(0);
   }
   __syncthreads();
-  for (int c = 0; c < nch; ++c) {
-    const int buf = NBUF == 2 ? (c & 1) : 0;
-    if (c + 1 < nch) gload((c + 1) * KC);
+  // the chunk loop; MODE 0 tests for a whole quadrant inside the loop, MODE 1
+  // (whole) and 2 (partial) take that choice once per wave, outside it (both
+  // run the same barriers).  Measured: float64 is faster with the test inside,
+  // float32 with it outside.
+  auto chunks = [&](auto mode) {
+    constexpr int MODE = decltype(mode)::value;
+    for (int c = 0; c < nch; ++c) {
+      const int buf = NBUF == 2 ? (c & 1) : 0;
+      if (c + 1 < nch) gload((c + 1) * KC);
 #pragma unroll
-    for (int kk = 0; kk < KC; kk += 16) {
-      T bv[4][4], av[4][4];
+      for (int kk = 0; kk < KC; kk += 16) {
+        T bv[4][4], av[4][4];
 #pragma unroll
-      for (int x = 0; x < 4; ++x) get4(&Bs[buf][(wj * 64 + 16 * x + lc) * SB + kk + 4 * g], bv[x]);
+        for (int x = 0; x < 4; ++x) get4(&Bs[buf][(wj * 64 + 16 * x + lc) * SB + kk + 4 * g], bv[x]);
 #pragma unroll
-      for (int y = 0; y < 4; ++y)
+        for (int y = 0; y < 4; ++y)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) av[y][e] = As[buf][(kk + 4 * g + e) * SA + wr * 64 + 16 * y + lc];
+          for (int e = 0; e < 4; ++e) av[y][e] = As[buf][(kk + 4 * g + e) * SA + wr * 64 + 16 * y + lc];
+        if (MODE == 1 || (MODE == 0 && nxv == 4)) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
+          for (int e = 0; e < 4; ++e)
 #pragma unroll
-        for (int x = 0; x < 4; ++x)
+            for (int x = 0; x < 4; ++x)
 #pragma unroll
-          for (int y = 0; y < 4; ++y) acc[0][x][y] = mfma(bv[x][e], av[y][e], acc[0][x][y]);
+              for (int y = 0; y < 4; ++y) acc[0][x][y] = mfma(bv[x][e], av[y][e], acc[0][x][y]);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+              if (x < nxv) {
+#pragma unroll
+                for (int y = 0; y < 4; ++y) acc[0][x][y] = mfma(bv[x][e], av[y][e], acc[0][x][y]);
+              }
+        }
+      }
+      if (NBUF == 1) __syncthreads();
+      if (c + 1 < nch) sput(NBUF == 2 ? buf ^ 1 : 0);
+      __syncthreads();
     }
-    if (NBUF == 1) __syncthreads();
-    if (c + 1 < nch) sput(NBUF == 2 ? buf ^ 1 : 0);
-    __syncthreads();
+  };
+  if constexpr (sizeof(T) == 8) {
+    chunks(std::integral_constant<int, 0>{});
+  } else {
+    if (nxv == 4) chunks(std::integral_constant<int, 1>{});
+    else chunks(std::integral_constant<int, 2>{});
   }
   update_epilogue<T, 4, 4, false>(a, job, j0 + wj * 64, r0 + wr * 64, acc);
 }
