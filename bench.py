@@ -94,7 +94,7 @@ def traffic_for(name):
 
 # logical kernel name -> (symbol prefix, call-site template argument or None)
 TRAFFIC_KERNELS = {
-    "gram_proj": ("ppcg::gram", "1"), "update_proj": ("ppcg::update", "1"), "gram_block": ("ppcg::gram", "2"),
+    "gram_proj": ("ppcg::gram", "1"), "update_proj": ("ppcg::update", "1"), "gram_block": ("ppcg::block_gram_kernel", None),
     "stencil_f64": ("ppcg::stencil_kernel<double", None), "stencil_f32": ("ppcg::stencil_kernel<float", None),
     "block_update": ("ppcg::block_update_kernel", None), "block_pencil": ("ppcg::block_pencil_kernel", None),
 }
