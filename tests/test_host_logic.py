@@ -111,3 +111,19 @@ def test_traffic_reduction(tmp_path):
     assert g["write_bytes_per_launch"] == pytest.approx(1024 * (10 + 30) / 2, rel=1e-6)
     assert d["calibration"]["FETCH_SIZE"]["factor"] == pytest.approx(2.0)
     assert d["source_sha"] == bench.kernel_source_sha()
+
+
+def test_traffic_kernel_symbols():
+    """Each logical kernel of the traffic table matches its device symbols and no other."""
+    m = bench._symbol_matches
+    gb = bench.TRAFFIC_KERNELS["gram_block"]
+    assert m("void ppcg::block_gram_kernel<true, true, true>(ppcg::BlockGramArgs)", *gb)
+    assert m("void ppcg::block_gram_kernel<false, false, false>(ppcg::BlockGramArgs)", *gb)
+    assert not m("void ppcg::gram_kernel<double, 4, 5, false, 2>(ppcg::GramArgs)", *gb)
+    gp = bench.TRAFFIC_KERNELS["gram_proj"]
+    assert m("void ppcg::gram_lds_kernel<float, 32, 1>(ppcg::GramArgs)", *gp)
+    assert m("void ppcg::gram_kernel<float, 4, 4, false, 1>(ppcg::GramArgs)", *gp)
+    assert not m("void ppcg::gram_lds_kernel<double, 16, 0>(ppcg::GramArgs)", *gp)
+    up = bench.TRAFFIC_KERNELS["update_proj"]
+    assert m("void ppcg::update_lds_kernel<float, 16, 1>(ppcg::UpdateArgs)", *up)
+    assert not m("void ppcg::update_lds_kernel<double, 32, 0>(ppcg::UpdateArgs)", *up)
