@@ -349,6 +349,12 @@ PPCG_DEV void set_diag_body(const SetDiagArgs& a, unsigned wg, unsigned) {
   a.G[o] = (i == j) ? a.lam[i] : 0.0;
   if (a.cplx) a.G[o + 1] = 0.0;
 }
+PPCG_DEV void offdiag_body(const OffdiagArgs& a, unsigned wg, unsigned) {
+  long e = wg * 256L + threadIdx.x;
+  if (e >= (long)a.m * a.m) return;
+  int i = e % a.m, j = e / a.m;
+  a.F[i + (long)j * a.ldf] = i == j ? 0.0f : (float)a.G[i + (long)j * a.ldg];
+}
 PPCG_DEV void symm_body(const SymmArgs& a, unsigned wg, unsigned) {
   long e = wg * 256L + threadIdx.x;
   if (e >= (long)a.m * a.m) return;
@@ -415,6 +421,7 @@ PPCG_SIMPLE(transpose, TransposeArgs)
 PPCG_SIMPLE(fill, FillArgs)
 PPCG_SIMPLE(set_diag, SetDiagArgs)
 PPCG_SIMPLE(symm, SymmArgs)
+PPCG_SIMPLE(offdiag, OffdiagArgs)
 PPCG_SIMPLE(frob2, Frob2Args)
 PPCG_SIMPLE(orth, OrthArgs)
 PPCG_SIMPLE(zero_int, ZeroIntArgs)
@@ -434,6 +441,11 @@ static void simple_launch(int kind, void (*k)(A), const A& a, unsigned blocks, h
 void launch_transpose(const double* src, int lds, double* dst, int ldd, int m, int n, int cplx, hipStream_t st) {
   TransposeArgs a{src, lds, dst, ldd, m, n, cplx};
   simple_launch(OP_TRANSPOSE, transpose_kernel, a, (unsigned)(((m + 31) / 32) * ((n + 31) / 32)), st);
+}
+void launch_offdiag32(const double* G, int ldg, int m, float* F, int ldf, hipStream_t st) {
+  OffdiagArgs a{G, ldg, m, F, ldf};
+  long t = (long)m * m;
+  simple_launch(OP_OFFDIAG, offdiag_kernel, a, (unsigned)((t + 255) / 256), st);
 }
 void launch_fill(double* p, long count, double v, hipStream_t st) {
   FillArgs a{p, count, v};
@@ -482,6 +494,7 @@ bool launch_grouped_dense(int kind, const void* jobs, const unsigned* start, int
     case OP_FILL: PPCG_G(fill, FillArgs); return true;
     case OP_SETDIAG: PPCG_G(set_diag, SetDiagArgs); return true;
     case OP_SYMM: PPCG_G(symm, SymmArgs); return true;
+    case OP_OFFDIAG: PPCG_G(offdiag, OffdiagArgs); return true;
     case OP_FROB2: PPCG_G(frob2, Frob2Args); return true;
     case OP_ORTH: PPCG_G(orth, OrthArgs); return true;
     case OP_ZEROINT: PPCG_G(zero_int, ZeroIntArgs); return true;

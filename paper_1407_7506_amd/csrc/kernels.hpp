@@ -111,6 +111,13 @@ struct UpdateArgs {
                    // stored values at cpart[t + j * ldp] (column norms without re-reading C)
   int ncn;
   long ldp;
+  // optional (real, float32 kernels): float64 input c64 (ld ldc) read in place of
+  // C0, and the float64 term - xd[r, j] gd[j * gds] added; the result is formed
+  // in float64 and stored through C32 (c0_keep)
+  const double* c64;
+  const double* xd;
+  const double* gd;
+  long gds;
 };
 
 // stencil: Y = H X on an N^3 periodic grid (7- or 13-point), columns [0, ncols)
@@ -175,6 +182,8 @@ struct TransposeArgs { const double* src; int lds; double* dst; int ldd; int m, 
 struct FillArgs { double* p; long count; double v; };
 struct SetDiagArgs { double* G; int ld, m; const double* lam; int cplx; };
 struct SymmArgs { double* G; int ld, m; int cplx; };
+// F (float, ldf) <- G with a zero diagonal (m x m, real)
+struct OffdiagArgs { const double* G; int ldg, m; float* F; int ldf; };
 struct Frob2Args { const double* G; int ld, nw; double* out; int cplx; };
 struct OrthArgs { const double* G; int ld, k; double* out; int cplx; };
 struct ZeroIntArgs { int* p; int n; };
@@ -199,7 +208,7 @@ enum OpKind : int {
   OP_PENCIL24, OP_PENCIL48, OP_PENCIL96, OP_PENCILZ24, OP_PENCILZ48, OP_PENCILZ96,
   OP_BUPD_D4, OP_BUPD_D8, OP_BUPD_D16, OP_BUPD_D32, OP_BUPD_F4, OP_BUPD_F8, OP_BUPD_F16, OP_BUPD_F32,
   OP_BUPD_Z4, OP_BUPD_Z8, OP_BUPD_Z16, OP_BUPD_Z32, OP_BUPD_C4, OP_BUPD_C8, OP_BUPD_C16, OP_BUPD_C32,
-  OP_TRANSPOSE, OP_FILL, OP_SETDIAG, OP_SYMM, OP_FROB2, OP_ORTH, OP_ZEROINT, OP_COPY, OP_PREP,
+  OP_TRANSPOSE, OP_FILL, OP_SETDIAG, OP_SYMM, OP_FROB2, OP_ORTH, OP_ZEROINT, OP_COPY, OP_PREP, OP_OFFDIAG,
   OP_CHOL,   // composite: expanded by the grouped executor
   OP_D2H,    // host copy
   OP_COUNT
@@ -286,6 +295,7 @@ void launch_block_update(const BlockUpdArgs& a, hipStream_t st);
 void chol_inverse_grouped(const std::vector<CholArgs>& jobs, Stage& stage, hipStream_t st);
 // dst (n x m) = src^T (src^H when cplx)
 void launch_transpose(const double* src, int lds, double* dst, int ldd, int m, int n, int cplx, hipStream_t st);
+void launch_offdiag32(const double* G, int ldg, int m, float* F, int ldf, hipStream_t st);
 void launch_fill(double* p, long count, double v, hipStream_t st);
 void launch_set_diag(double* G, int ld, int m, const double* lam, int cplx, hipStream_t st);
 void launch_symmetrize(double* G, int ld, int m, int cplx, hipStream_t st);

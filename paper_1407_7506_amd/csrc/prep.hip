@@ -60,6 +60,7 @@ size_t op_args_size(int kind) {
     case OP_FILL: return sizeof(FillArgs);
     case OP_SETDIAG: return sizeof(SetDiagArgs);
     case OP_SYMM: return sizeof(SymmArgs);
+    case OP_OFFDIAG: return sizeof(OffdiagArgs);
     case OP_FROB2: return sizeof(Frob2Args);
     case OP_ORTH: return sizeof(OrthArgs);
     case OP_ZEROINT: return sizeof(ZeroIntArgs);

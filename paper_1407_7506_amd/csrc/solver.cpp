@@ -182,7 +182,7 @@ struct Work {
   DBuf AXm;                           // float64 H X kept in mixed mode
   DBuf Vd, V32, td;
   DBuf G, GWP, L, Li, Rinv, SAS, SS, V1, Mr, Yv, Cc, lam;
-  DBuf part, bgram, bC, bflags, cn, scal, iflag, eigw, dminp, pwork, cpart;
+  DBuf part, bgram, bC, bflags, cn, scal, iflag, eigw, dminp, pwork, cpart, G32;
   int* hpin = nullptr;                // pinned host scratch: doubles [0, 2Kp), ints from 4Kp + 8
   double* hpind = nullptr;
   size_t hpin_bytes = 0;
@@ -688,9 +688,14 @@ struct Prob {
   // cpart (real only): column sums of squares of the stored values, per 64-row tile, for columns < ncn
   void update(const void* A, long lda, int Kk, const void* B, long ldb, int Nn, void* C0, void* C1, int N0, long ldc,
               float* C32, const double* dsc, long rws, double alpha, double beta, bool b_upper, bool f32,
-              const char* name = "update", bool c0_keep = false, double* cpart = nullptr, int ncn = 0) {
+              const char* name = "update", bool c0_keep = false, double* cpart = nullptr, int ncn = 0,
+              const double* c64 = nullptr, const double* xd = nullptr, const double* gd = nullptr, long gds = 0) {
     if (Nn <= 0 || rws <= 0) return;
     UpdateArgs u{};
+    u.c64 = c64;
+    u.xd = xd;
+    u.gd = gd;
+    u.gds = gds;
     u.A = A;
     u.lda = lda;
     u.B = B;
@@ -748,6 +753,7 @@ struct Prob {
     double nn = (double)std::min(rws, n), es = (f32 ? 4.0 : 8.0) * nc();
     double fl = (b_upper ? (double)Nn * (Nn + 1) * nn : 2.0 * Kk * Nn * nn) * (cplx ? 4 : 1);
     double by = ((double)Kk + Nn * (beta != 0 ? 2.0 : 1.0)) * nn * es + (C32 ? 4.0 * nc() * Nn * nn : 0.0);
+    if (c64) by += (8.0 - es + (xd ? 8.0 : 0.0)) * Nn * nn;  // float64 input (and X) instead of C0
     Scope s(prof, name, fl, by);
     launch_update(u, f32, st);
   }
@@ -794,6 +800,7 @@ struct Prob {
     Wk.bC.ensure((size_t)s * 3 * q * q * xs());
     Wk.bflags.ensure((size_t)s * 4 + 256);
     Wk.cpart.ensure((size_t)(rows / 64) * Kp * 8);
+    if (mixed) Wk.G32.ensure((size_t)Kp * Kp * 4);
     if (3 * q > 48) Wk.pwork.ensure((size_t)s * pencil_work_elems() * xs());
     Wk.eigw.ensure(eig_workspace_bytes(K, cplx));
     // split partials: the largest Gram of the run
@@ -891,7 +898,8 @@ struct Prob {
 
   // residual of the active columns: AX = H X, G = X^H AX, W = AX - X G.
   // plain: H X and then W overwrite the W block; mixed: H X stays in AXm
-  // (float64) and only the float copy W32 of the residual is written.
+  // (float64) and only the float copy W32 of the residual is written (real:
+  // the off-diagonal part of X G on float32 MFMA).
   // Column norms of the wanted active columns go to cn, G's to scal.
   void enq_residual(int m) {
     double* Xa = xc(X(), nl);
@@ -903,8 +911,17 @@ struct Prob {
     int nwa = std::max(0, k - nl);
     // real: column norms of the wanted active residual columns from the update's epilogue partials
     double* cpart = cplx ? nullptr : Wk.cpart.d();
-    update(Xa, ld, m, Wk.G.p, Kp, m, R, nullptr, m, ld, W32a, nullptr, rows, -1.0, 1.0, false, false, "update_resid",
-           mixed, cpart, nwa);
+    if (mixed && !cplx) {
+      // W = (AX - X diag(G)) - X (G - diag(G)): the first part per entry in
+      // float64, the coupling of the columns (off-diagonal G, of the size of
+      // the residual near convergence) as a float32 product of the X shadow
+      launch_offdiag32(Wk.G.d(), Kp, m, Wk.G32.f(), Kp, st);
+      update(fc(Wk.X32.f(), nl), ld, m, Wk.G32.p, Kp, m, R, nullptr, m, ld, W32a, nullptr, rows, -1.0, 1.0, false,
+             true, "update_resid", true, cpart, nwa, R, Xa, Wk.G.d(), (long)Kp + 1);
+    } else {
+      update(Xa, ld, m, Wk.G.p, Kp, m, R, nullptr, m, ld, W32a, nullptr, rows, -1.0, 1.0, false, false,
+             "update_resid", mixed, cpart, nwa);
+    }
     Scope s(prof, "colnorm");
     if (!cplx) {
       launch_colsum(Wk.cpart.d(), rows / 64, rows / 64, nwa, Wk.cn.d(), st);
