@@ -347,15 +347,21 @@ void launch_block_pencil(const PencilArgs& a, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// TW: storage of W/P (double, float, zdouble, zfloat); SX: X and arithmetic
+// TW: storage of W/P (double, float, zdouble, zfloat); SX: X and arithmetic.
+// One thread per row and RPT rows per thread (256 apart): every lane reads
+// the block's 3q x q coefficients from LDS as broadcasts, so with q = 16
+// those reads, not HBM, bound a one-row-per-thread kernel; two rows per
+// thread halve them per row (real blocks up to 16 columns).
+template <class SX, int QM> constexpr int bupd_rpt() { return (sc_traits<SX>::cplx || QM > 16) ? 1 : 2; }
 template <class TW, class SX, int QM>
 PPCG_DEV void block_update_body(const BlockUpdArgs& a, unsigned wg, unsigned nwg) {
+  constexpr int RPT = bupd_rpt<SX, QM>();
   __shared__ SX Cs[3 * QM * QM];
   const int q = a.q;
-  const unsigned rtiles = (unsigned)(a.rows / 256);
+  const unsigned rtiles = (unsigned)((a.rows + 256 * RPT - 1) / (256 * RPT));
   unsigned L = xcd_remap(wg, nwg);
   int blk = L / rtiles;
-  long r = (long)(L % rtiles) * 256 + threadIdx.x;
+  const long r0 = (long)(L % rtiles) * 256 * RPT + threadIdx.x;
   const SX* C = (const SX*)a.C + (long)blk * a.cstride;
   const int ldc = 3 * q;
   for (int e = threadIdx.x; e < 3 * q * q; e += 256) {
@@ -368,31 +374,48 @@ PPCG_DEV void block_update_body(const BlockUpdArgs& a, unsigned wg, unsigned nwg
   TW* W = (TW*)a.W + cb;
   TW* P = (TW*)a.P + cb;
   const SX zero = from_real<SX>(0.0);
-  SX x[QM], w[QM], p[QM];
+  SX x[RPT][QM], w[RPT][QM], p[RPT][QM];
+  bool ok[RPT];
 #pragma unroll
-  for (int i = 0; i < QM; ++i) {
-    if (i < q) {
-      x[i] = X[r + i * a.ld];
-      w[i] = cvt<SX, TW>(W[r + i * a.ld]);
-      p[i] = a.hasP ? cvt<SX, TW>(P[r + i * a.ld]) : zero;
-    } else {
-      x[i] = w[i] = p[i] = zero;
+  for (int u = 0; u < RPT; ++u) {
+    const long r = r0 + 256L * u;
+    ok[u] = r < a.rows;
+#pragma unroll
+    for (int i = 0; i < QM; ++i) {
+      if (i < q && ok[u]) {
+        x[u][i] = X[r + i * a.ld];
+        w[u][i] = cvt<SX, TW>(W[r + i * a.ld]);
+        p[u][i] = a.hasP ? cvt<SX, TW>(P[r + i * a.ld]) : zero;
+      } else {
+        x[u][i] = w[u][i] = p[u][i] = zero;
+      }
     }
   }
   for (int t = 0; t < q; ++t) {
     const SX* ct = Cs + t * 3 * QM;
-    SX pn = zero, xn = zero;
+    SX pn[RPT], xn[RPT];
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) pn[u] = xn[u] = zero;
 #pragma unroll
     for (int i = 0; i < QM; ++i) {
       if (i < q) {
-        pn += w[i] * ct[q + i];
-        if (a.hasP) pn += p[i] * ct[2 * q + i];
-        xn += x[i] * ct[i];
+        const SX cw = ct[q + i], cp = ct[2 * q + i], cx = ct[i];
+#pragma unroll
+        for (int u = 0; u < RPT; ++u) {
+          pn[u] += w[u][i] * cw;
+          if (a.hasP) pn[u] += p[u][i] * cp;
+          xn[u] += x[u][i] * cx;
+        }
       }
     }
-    xn += pn;
-    P[r + t * a.ld] = cvt<TW, SX>(pn);
-    X[r + t * a.ld] = xn;
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      if (!ok[u]) continue;
+      const long r = r0 + 256L * u;
+      xn[u] += pn[u];
+      P[r + t * a.ld] = cvt<TW, SX>(pn[u]);
+      X[r + t * a.ld] = xn[u];
+    }
   }
 }
 
@@ -433,7 +456,9 @@ static int bupd_kind(const BlockUpdArgs& a) {
   }
 
 void launch_block_update(const BlockUpdArgs& a, hipStream_t st) {
-  unsigned blocks = (unsigned)((a.rows / 256) * (a.nblocks > 0 ? a.nblocks : 0));
+  // rows per workgroup: 256 times the rows per thread of the selected kernel
+  const long rpw = (a.cplx || a.q > 16) ? 256 : 512;
+  unsigned blocks = (unsigned)(((a.rows + rpw - 1) / rpw) * (a.nblocks > 0 ? a.nblocks : 0));
   int kind = bupd_kind(a);
   if (g_rec) {
     g_rec->add(kind, &a, sizeof(a), blocks);
