@@ -10,7 +10,7 @@ Both precisions are timed: the mixed FP32-bulk path (the value reported) and
 the plain FP64 path (reported beside it).  Inputs are resident in HBM before
 the timed region starts.
 
-Prints ONE JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+Prints ONE JSON line.  --gpus N with N > 1 exits: the solver runs on one GPU.
 """
 from __future__ import annotations
 
@@ -256,7 +256,7 @@ def main():
         launches = {kv.split("=")[0]: int(kv.split("=")[1]) for kv in args.traffic_launches.split(",") if "=" in kv}
         return write_traffic(args.traffic_from[0], args.traffic_from[1], launches)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU; --gpus must be 1", file=sys.stderr)
+        print("bench.py: the solver runs on one GPU; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch64":
         return bench_batch(args)

@@ -5,8 +5,7 @@ practical aspects of section 5: block updates (5.1), the relative subspace
 residual (5.2), buffer vectors (5.3), projections of W and P (5.4),
 Cholesky-QR (5.5), periodic Rayleigh-Ritz (5.6) and soft locking (5.7).
 
-Readings of places where the paper is silent or ambiguous (each is listed in
-DESIGN.md as well):
+Readings of places where the paper is silent or ambiguous:
   * the start block is orthonormalised by Cholesky-QR (the paper assumes an
     orthonormal X0);
   * in the per-block problem the q_j smallest pairs are kept (the algorithm
