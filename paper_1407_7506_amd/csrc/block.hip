@@ -177,13 +177,16 @@ PPCG_DEV void block_pencil_body(const PencilArgs& a, unsigned wg, unsigned) {
       b3[x + y * LD] = b0[acc[x] + acc[y] * LD];
     }
     __syncthreads();
-    // 5. Linv (b1) by forward substitution, one thread per column
+    // 5. Linv (b1) by forward substitution, one thread per column, in column
+    //    order: entry x of column y receives the terms L_xt Linv_ty in
+    //    increasing t, as in the dot-product form, but the updates of one
+    //    step t are independent of each other
     for (int y = tid; y < r; y += NT) {
-      for (int x = 0; x < r; ++x) b1[x + y * LD] = zero;
-      for (int x = y; x < r; ++x) {
-        S s = from_real<S>(x == y ? 1.0 : 0.0);
-        for (int t = y; t < x; ++t) s -= b2[x + t * LD] * b1[t + y * LD];
-        b1[x + y * LD] = (1.0 / real_(b2[x + x * LD])) * s;
+      for (int x = 0; x < r; ++x) b1[x + y * LD] = from_real<S>(x == y ? 1.0 : 0.0);
+      for (int t = y; t < r; ++t) {
+        const S lt = (1.0 / real_(b2[t + t * LD])) * b1[t + y * LD];
+        b1[t + y * LD] = lt;
+        for (int x = t + 1; x < r; ++x) b1[x + y * LD] -= b2[x + t * LD] * lt;
       }
     }
     __syncthreads();
@@ -267,21 +270,28 @@ PPCG_DEV void block_pencil_body(const PencilArgs& a, unsigned wg, unsigned) {
         b3[u + v * LD] = s;
       }
       __syncthreads();
-      if (tid == 0) {
-        double gmax = 0;
-        for (int u = 0; u < q; ++u) gmax = fmax(gmax, real_(b3[u + u * LD]));
-        int bad = 0;
-        // sequential Cholesky of the q x q Gram, relative pivot test
-        for (int c = 0; c < q && !bad; ++c) {
-          double piv = real_(b3[c + c * LD]);
-          if (!(piv >= a.pivot_tol * gmax)) { bad = 1; break; }
-          double l = sqrt(piv);
-          for (int i = c + 1; i < q; ++i) b3[i + c * LD] = (1.0 / l) * b3[i + c * LD];
-          for (int j = c + 1; j < q; ++j)
-            for (int i = j; i < q; ++i) b3[i + j * LD] -= b3[i + c * LD] * conj_(b3[j + c * LD]);
+      // right-looking Cholesky of the q x q Gram over the workgroup, relative
+      // pivot test (every thread reads the same pivots, so the exit is uniform)
+      double gmax = 0;
+      for (int u = 0; u < q; ++u) gmax = fmax(gmax, real_(b3[u + u * LD]));
+      int bad = 0;
+      for (int c = 0; c < q; ++c) {
+        const double piv = real_(b3[c + c * LD]);
+        if (!(piv >= a.pivot_tol * gmax)) {
+          bad = 1;
+          break;
         }
-        sing = bad;
+        const double l = sqrt(piv);
+        for (int i = c + 1 + tid; i < q; i += NT) b3[i + c * LD] = (1.0 / l) * b3[i + c * LD];
+        __syncthreads();
+        const int nr = q - c - 1;
+        for (int e = tid; e < nr * nr; e += NT) {
+          const int i = c + 1 + e % nr, j = c + 1 + e / nr;
+          if (i >= j) b3[i + j * LD] -= b3[i + c * LD] * conj_(b3[j + c * LD]);
+        }
+        __syncthreads();
       }
+      if (tid == 0) sing = bad;
       __syncthreads();
       if (sing) {
         flag |= 2;
