@@ -353,7 +353,9 @@ PPCG_DEV void offdiag_body(const OffdiagArgs& a, unsigned wg, unsigned) {
   long e = wg * 256L + threadIdx.x;
   if (e >= (long)a.m * a.m) return;
   int i = e % a.m, j = e / a.m;
-  a.F[i + (long)j * a.ldf] = i == j ? 0.0f : (float)a.G[i + (long)j * a.ldg];
+  const int nc = a.cplx ? 2 : 1;
+  const long f = (i + (long)j * a.ldf) * nc, g = (i + (long)j * a.ldg) * nc;
+  for (int c = 0; c < nc; ++c) a.F[f + c] = i == j ? 0.0f : (float)a.G[g + c];
 }
 PPCG_DEV void symm_body(const SymmArgs& a, unsigned wg, unsigned) {
   long e = wg * 256L + threadIdx.x;
@@ -442,8 +444,8 @@ void launch_transpose(const double* src, int lds, double* dst, int ldd, int m, i
   TransposeArgs a{src, lds, dst, ldd, m, n, cplx};
   simple_launch(OP_TRANSPOSE, transpose_kernel, a, (unsigned)(((m + 31) / 32) * ((n + 31) / 32)), st);
 }
-void launch_offdiag32(const double* G, int ldg, int m, float* F, int ldf, hipStream_t st) {
-  OffdiagArgs a{G, ldg, m, F, ldf};
+void launch_offdiag32(const double* G, int ldg, int m, float* F, int ldf, int cplx, hipStream_t st) {
+  OffdiagArgs a{G, ldg, m, F, ldf, cplx};
   long t = (long)m * m;
   simple_launch(OP_OFFDIAG, offdiag_kernel, a, (unsigned)((t + 255) / 256), st);
 }

@@ -293,11 +293,17 @@ PPCG_DEV void update_epilogue(const UpdateArgs& a, int job, int j0, long r0,
           long r = (r0 + 16 * y + lc) * NC;
           T v0 = alpha * acc[0][x][y][v];
           T v1 = CPLX ? alpha * acc[NC - 1][x][y][v] : (T)0;
-          if (!CPLX && a.c64) {  // float64 input and diagonal term, combined in float64
-            const long o = (long)job * a.job_c_off + (long)j * a.ldc + r;
-            double w = a.beta * a.c64[o] + (double)v0;
-            if (a.xd) w -= a.xd[o] * a.gd[(long)j * a.gds];
-            v0 = (T)w;
+          if (a.c64) {  // float64 input and diagonal term, combined in float64
+            const long o = ((long)job * a.job_c_off + (long)j * a.ldc) * NC + r;
+            const double g = a.xd ? a.gd[(long)j * a.gds * NC] : 0.0;  // real diagonal of a Hermitian G
+            double w0 = a.beta * a.c64[o] + (double)v0;
+            if (a.xd) w0 -= a.xd[o] * g;
+            v0 = (T)w0;
+            if (CPLX) {
+              double w1 = a.beta * a.c64[o + 1] + (double)v1;
+              if (a.xd) w1 -= a.xd[o + 1] * g;
+              v1 = (T)w1;
+            }
           } else if (a.beta != 0) {
             T c0 = cp[r], c1 = CPLX ? cp[r + 1] : (T)0;
             if (scaled) {
@@ -1104,8 +1110,8 @@ void launch_reduce(const ReduceArgs& r, bool f32, hipStream_t st) {
 
 void launch_update(const UpdateArgs& a0, bool f32, hipStream_t st) {
   UpdateArgs a = a0;
-  if (a.c64 && (!a.c0_keep || a.cplx || !f32 || (a.xd && !a.gd)))
-    throw std::invalid_argument("update: float64 input needs a real float32 update that keeps C0");
+  if (a.c64 && (!a.c0_keep || !f32 || (a.xd && !a.gd)))
+    throw std::invalid_argument("update: float64 input needs a float32 update that keeps C0");
   if (a.lds)  // the LDS-staged kernel's preconditions; otherwise the one-wave kernel
     a.lds = !a.cplx && a.rows % LB == 0 && a.lda % 4 == 0 && aligned16(a.A) && a.job_a_off == 0 &&
             a.job_b_off == 0 && a.job_c_off == 0;

@@ -111,9 +111,9 @@ struct UpdateArgs {
                    // stored values at cpart[t + j * ldp] (column norms without re-reading C)
   int ncn;
   long ldp;
-  // optional (real, float32 kernels): float64 input c64 (ld ldc) read in place of
-  // C0, and the float64 term - xd[r, j] gd[j * gds] added; the result is formed
-  // in float64 and stored through C32 (c0_keep)
+  // optional (float32 kernels): float64 input c64 (ld ldc, complex interleaved
+  // when cplx) read in place of C0, and the float64 term - xd[r, j] Re gd[j * gds]
+  // added; the result is formed in float64 and stored through C32 (c0_keep)
   const double* c64;
   const double* xd;
   const double* gd;
@@ -182,8 +182,8 @@ struct TransposeArgs { const double* src; int lds; double* dst; int ldd; int m, 
 struct FillArgs { double* p; long count; double v; };
 struct SetDiagArgs { double* G; int ld, m; const double* lam; int cplx; };
 struct SymmArgs { double* G; int ld, m; int cplx; };
-// F (float, ldf) <- G with a zero diagonal (m x m, real)
-struct OffdiagArgs { const double* G; int ldg, m; float* F; int ldf; };
+// F (float, ldf) <- G with a zero diagonal (m x m; complex interleaved when cplx)
+struct OffdiagArgs { const double* G; int ldg, m; float* F; int ldf; int cplx; };
 struct Frob2Args { const double* G; int ld, nw; double* out; int cplx; };
 struct OrthArgs { const double* G; int ld, k; double* out; int cplx; };
 struct ZeroIntArgs { int* p; int n; };
@@ -295,7 +295,7 @@ void launch_block_update(const BlockUpdArgs& a, hipStream_t st);
 void chol_inverse_grouped(const std::vector<CholArgs>& jobs, Stage& stage, hipStream_t st);
 // dst (n x m) = src^T (src^H when cplx)
 void launch_transpose(const double* src, int lds, double* dst, int ldd, int m, int n, int cplx, hipStream_t st);
-void launch_offdiag32(const double* G, int ldg, int m, float* F, int ldf, hipStream_t st);
+void launch_offdiag32(const double* G, int ldg, int m, float* F, int ldf, int cplx, hipStream_t st);
 void launch_fill(double* p, long count, double v, hipStream_t st);
 void launch_set_diag(double* G, int ld, int m, const double* lam, int cplx, hipStream_t st);
 void launch_symmetrize(double* G, int ld, int m, int cplx, hipStream_t st);

@@ -806,7 +806,7 @@ struct Prob {
     Wk.bC.ensure((size_t)s * 3 * q * q * xs());
     Wk.bflags.ensure((size_t)s * 4 + 256);
     Wk.cpart.ensure((size_t)(rows / 64) * Kp * 8);
-    if (mixed) Wk.G32.ensure((size_t)Kp * Kp * 4);
+    if (mixed) Wk.G32.ensure((size_t)Kp * Kp * x32s());
     if (3 * q > 48) Wk.pwork.ensure((size_t)s * pencil_work_elems() * xs());
     Wk.eigw.ensure(eig_workspace_bytes(K, cplx));
     // split partials: the largest Gram of the run
@@ -904,8 +904,8 @@ struct Prob {
 
   // residual of the active columns: AX = H X, G = X^H AX, W = AX - X G.
   // plain: H X and then W overwrite the W block; mixed: H X stays in AXm
-  // (float64) and only the float copy W32 of the residual is written (real:
-  // the off-diagonal part of X G on float32 MFMA).
+  // (float64) and only the float copy W32 of the residual is written (the
+  // off-diagonal part of X G on float32 MFMA).
   // Column norms of the wanted active columns go to cn, G's to scal.
   void enq_residual(int m) {
     double* Xa = xc(X(), nl);
@@ -917,11 +917,11 @@ struct Prob {
     int nwa = std::max(0, k - nl);
     // real: column norms of the wanted active residual columns from the update's epilogue partials
     double* cpart = cplx ? nullptr : Wk.cpart.d();
-    if (mixed && !cplx) {
+    if (mixed) {
       // W = (AX - X diag(G)) - X (G - diag(G)): the first part per entry in
       // float64, the coupling of the columns (off-diagonal G, of the size of
       // the residual near convergence) as a float32 product of the X shadow
-      launch_offdiag32(Wk.G.d(), Kp, m, Wk.G32.f(), Kp, st);
+      launch_offdiag32(Wk.G.d(), Kp, m, Wk.G32.f(), Kp, cplx, st);
       update(fc(Wk.X32.f(), nl), ld, m, Wk.G32.p, Kp, m, R, nullptr, m, ld, W32a, nullptr, rows, -1.0, 1.0, false,
              true, "update_resid", true, cpart, nwa, R, Xa, Wk.G.d(), (long)Kp + 1);
     } else {
