@@ -63,9 +63,12 @@ typedef enum { PPCG_PRECOND_NONE = 0, PPCG_PRECOND_JACOBI = 1 } ppcg_precond;
 typedef struct {
   int32_t precision;  /* ppcg_precision.  PPCG_MIXED keeps W, P, HW, HP and the
                          projections X^H W, X^H P in float32 (MFMA, float32
-                         accumulation); X, the Cholesky-QR, every Gram of the
+                         accumulation), and forms the column coupling
+                         X (G - diag G) of the residual from a float32 shadow
+                         of X; X, H X, the Cholesky-QR, every Gram of the
                          sub-block pencils, the pencils themselves, the
-                         Rayleigh-Ritz and the residual H X - X G stay float64 */
+                         Rayleigh-Ritz, H X - X diag(G) and the final residual
+                         check stay float64 */
   int32_t nbuf;       /* buffer vectors (section 5.3); -1 = sbsize*ceil((k +
                          max(2, ceil(0.02 k)))/sbsize) - k, so k + nbuf is a
                          multiple of sbsize */
