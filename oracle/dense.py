@@ -19,14 +19,17 @@ Readings where the paper is silent:
     whose pivot falls below PIVOT_TOL (a direction that is numerically in the
     span of the columns already accepted).
   * Theorem 1 indicator in block form: if C_X of the kept eigenvectors is
-    numerically singular (Cholesky pivot of C_X^H C_X below PIVOT_TOL times
-    its largest diagonal entry) and P was used, the block is solved again
-    without P (the backtrack of Theorem 2).
+    numerically singular (a Cholesky pivot of C_X^H C_X below PIVOT_TOL; the
+    columns of C are B-orthonormal and X is orthonormal and orthogonal to W
+    and P, so C_X^H C_X <= I and its scale is 1) and P was used, the block is
+    solved again without P (the backtrack of Theorem 2).
 
 Pins: tests/test_oracle_dense.py (scipy.linalg.eigh(A, B) on random pencils,
 the closed-form 2 x 2 problem in the proof of Theorem 2, C^H B C = I, CholQR invariants).
 """
 from __future__ import annotations
+
+from typing import NamedTuple
 
 import numpy as np
 import scipy.linalg as sla
@@ -37,6 +40,14 @@ PIVOT_TOL = 1e-12     # Cholesky pivot (of a unit-diagonal matrix) floor
 
 class RankError(RuntimeError):
     """Cholesky-QR or Rayleigh-Ritz met a numerically rank-deficient block."""
+
+
+class PencilResult(NamedTuple):
+    C: np.ndarray          # (rows of A, nx) coefficients, zero rows for dropped columns
+    theta: np.ndarray      # the nx lowest Ritz values, ascending
+    used_p: bool           # some P column took part in the returned solution
+    backtracked: bool      # Theorem 1 test failed; solved again without P
+    dropped: int           # W/P columns of the solved pencil left out as zero or dependent
 
 
 def sym(M: np.ndarray) -> np.ndarray:
@@ -75,11 +86,15 @@ def _greedy_cholesky(B: np.ndarray, order: list, tol: float):
     return acc, L[:nacc, :nacc]
 
 
-def block_pencil(A: np.ndarray, B: np.ndarray, nx: int, has_p: bool, _allow_backtrack=True):
+def block_pencil(A: np.ndarray, B: np.ndarray, nx: int, has_p: bool, _allow_backtrack=True,
+                 singular_tol: float = PIVOT_TOL):
     """Lowest nx eigenpairs of the projected pencil (A, B) of one sub-block
     S = [X_j, W_j, P_j] (columns 0..nx-1 are X_j, then nx W_j columns, then
-    nx P_j columns when has_p).  Returns (C, theta, used_p) where C has shape
-    (rows of A, nx), C^H B C = I on the kept rows and dropped rows are zero."""
+    nx P_j columns when has_p).  Returns a PencilResult: C has shape
+    (rows of A, nx), C^H B C = I on the kept rows and dropped rows are zero;
+    backtracked is True when the Theorem 1 test found C_X singular (a
+    Cholesky pivot of C_X^H C_X below singular_tol) and the block was solved
+    again without P (Theorem 2)."""
     nb = A.shape[0]
     A = sym(A)
     B = sym(B)
@@ -108,13 +123,17 @@ def block_pencil(A: np.ndarray, B: np.ndarray, nx: int, has_p: bool, _allow_back
     C[acc, :] = Dv[acc, None] * Cacc
     used_p = has_p and any(c >= 2 * nx for c in acc)
     if used_p and _allow_backtrack:
+        # C^H B C = I with X orthonormal and orthogonal to W, P gives
+        # C_X^H C_X <= I: its pivots are compared with 1, not with its own
+        # largest entry (a C_X that vanishes to rounding is singular too)
         Cx = C[:nx, :]
         G = sym(Cx.conj().T @ Cx)
-        gmax = np.real(np.diag(G)).max()
-        _, Lx = _greedy_cholesky(G, list(range(nx)), PIVOT_TOL * gmax)
+        _, Lx = _greedy_cholesky(G, list(range(nx)), singular_tol)
         if Lx.shape[0] < nx:
-            return block_pencil(A, B, nx, False, _allow_backtrack=False)
-    return C, theta[:nx], used_p
+            r = block_pencil(A, B, nx, False, _allow_backtrack=False)
+            return PencilResult(r.C, r.theta, False, True, r.dropped)
+    nfull = (3 if has_p else 2) * nx
+    return PencilResult(C, theta[:nx], used_p, False, nfull - len(acc))
 
 
 def rayleigh_ritz(S: np.ndarray, AS: np.ndarray):

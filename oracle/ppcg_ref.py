@@ -33,6 +33,7 @@ import math
 
 import numpy as np
 
+from . import dense
 from .dense import RankError, block_pencil, cholqr, rayleigh_ritz, sym
 
 
@@ -50,18 +51,25 @@ class Info:
     rho: float = math.inf
     fresh_resid: float = math.inf
     history: list = dataclasses.field(default_factory=list)
-    n_backtrack: int = 0
+    n_backtrack: int = 0      # sub-block solves redone without P (Theorem 1 test, Theorem 2)
+    n_p_dropped: int = 0      # sub-blocks whose P columns were all dropped as dependent
+    n_dropped: int = 0        # W/P columns left out of sub-block pencils (zero or dependent)
+    n_unlock: int = 0         # Rayleigh-Ritz steps at which the locked set shrank (P reset)
 
 
 def _fro2(M):
     return float(np.vdot(M, M).real) if M.size else 0.0
 
 
-def ppcg(apply_a, tdiag, X0, k, sbsize, tol, rr_period, max_iter=20000, record=False):
+def ppcg(apply_a, tdiag, X0, k, sbsize, tol, rr_period, max_iter=20000, record=False,
+         singular_tol=dense.PIVOT_TOL):
     """Lowest k eigenpairs of the Hermitian operator ``apply_a`` (n x m -> n x m).
 
     tdiag : (n,) diagonal of the preconditioner T (Jacobi: 1/diag(H)), must be > 0.
     X0    : (n, K) start block, K = k + nbuf columns (buffer vectors included).
+    singular_tol : relative pivot floor of the Theorem 1 test on C_X (a block
+            whose C_X^H C_X has a smaller Cholesky pivot is solved again
+            without P).
     Returns (lam[:k] ascending, X[:, :k], Info).  Raises RankError on a
     Cholesky breakdown and NoConvergence after max_iter iterations.
     """
@@ -99,6 +107,8 @@ def ppcg(apply_a, tdiag, X0, k, sbsize, tol, rr_period, max_iter=20000, record=F
             nl_new += 1
         nl_new = (nl_new // q) * q
         if P is not None:
+            if nl_new < nl:
+                info.n_unlock += 1
             P = P[:, nl_new - nl:] if nl_new >= nl else None
         return Xn, lam, AXn, Wall, wn, fresh, nl_new, P
 
@@ -160,9 +170,13 @@ def ppcg(apply_a, tdiag, X0, k, sbsize, tol, rr_period, max_iter=20000, record=F
             Aj = sym(S.conj().T @ AS)
             Bj = sym(S.conj().T @ S)
             nx = c1 - c0
-            C, _, used_p = block_pencil(Aj, Bj, nx, P is not None)
-            if P is not None and not used_p:
+            res = block_pencil(Aj, Bj, nx, P is not None, singular_tol=singular_tol)
+            C = res.C
+            info.n_dropped += res.dropped
+            if res.backtracked:
                 info.n_backtrack += 1
+            elif P is not None and not res.used_p:
+                info.n_p_dropped += 1
             Cx, Cw = C[:nx], C[nx:2 * nx]
             Pj = W[:, c0:c1] @ Cw
             if P is not None:

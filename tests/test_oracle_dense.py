@@ -23,7 +23,7 @@ def test_block_pencil_matches_scipy(nb, cplx):
     rng = np.random.default_rng(nb + cplx)
     A, B = rand_pencil(nb, cplx, rng)
     nx = nb // 3
-    C, th, used_p = dense.block_pencil(A, B, nx, True, _allow_backtrack=False)
+    C, th, used_p, _, _ = dense.block_pencil(A, B, nx, True, _allow_backtrack=False)
     ref = sla.eigh(A, B, eigvals_only=True)
     np.testing.assert_allclose(th, ref[:nx], rtol=1e-11, atol=1e-11)
     np.testing.assert_allclose(C.conj().T @ B @ C, np.eye(nx), atol=1e-11)
@@ -36,7 +36,7 @@ def test_two_by_two_closed_form():
     a, b, c, d = 0.7, 0.3, 2.5, 0.04
     A = np.array([[a, b], [b, c]])
     B = np.diag([1.0, d])
-    C, th, _ = dense.block_pencil(A, B, 1, False)
+    C, th, _, _, _ = dense.block_pencil(A, B, 1, False)
     disc = (a * d + c) ** 2 - 4 * d * (a * c - b * b)
     root = ((a * d + c) - np.sqrt(disc)) / (2 * d)
     assert abs(th[0] - root) < 1e-13
@@ -55,7 +55,7 @@ def test_block_pencil_drops_dependent_and_zero_columns():
     H = dense.sym(rng.standard_normal((n, n)))
     S = np.concatenate([X, W, P], axis=1)
     A, B = S.T @ H @ S, S.T @ S
-    C, th, used_p = dense.block_pencil(A, B, q, True)
+    C, th, used_p, back, dropped = dense.block_pencil(A, B, q, True)
     assert np.all(C[q + 1] == 0) and np.all(C[2 * q:] == 0)
     assert not used_p
     np.testing.assert_allclose(C.T @ B @ C, np.eye(q), atol=1e-10)
@@ -90,3 +90,81 @@ def test_rayleigh_ritz(cplx):
     np.testing.assert_allclose(lam, ref, rtol=1e-11, atol=1e-11)
     np.testing.assert_allclose(X.conj().T @ X, np.eye(K), atol=1e-11)
     np.testing.assert_allclose(X.conj().T @ H @ X, np.diag(lam), atol=1e-10)
+
+
+# --- Theorem 1 indicator and the Theorem 2 backtrack (section 3) -----------------------------
+
+def _pencil_from_operator(cplx, p_low, rng, q=2, n=40):
+    """S = [X, W, P] from the eigenbasis Q of a Hermitian H = Q diag(lam) Q^H.
+    X, W are orthonormal combinations of eigenvectors 10..13 (so x^H H w != 0);
+    P spans eigenvectors 0..q-1 with a non-orthonormal basis, and their
+    eigenvalues are ``p_low`` (below everything X and W reach when all are
+    low, or only one of them below when p_low has a large second entry)."""
+    Z = rng.standard_normal((n, n)) + (1j * rng.standard_normal((n, n)) if cplx else 0)
+    Q, _ = np.linalg.qr(Z)
+    lam = np.linspace(1.0, 5.0, n)
+    lam[:q] = p_low
+    H = (Q * lam) @ Q.conj().T
+    Y = rng.standard_normal((4, 4)) + (1j * rng.standard_normal((4, 4)) if cplx else 0)
+    Y, _ = np.linalg.qr(Y)
+    X = Q[:, 10:14] @ Y[:, :q]
+    W = Q[:, 10:14] @ Y[:, q:2 * q] * np.array([0.3, 2.0])[None, :q]
+    Rp = rng.standard_normal((q, q)) + 3 * np.eye(q)
+    P = Q[:, :q] @ Rp
+    S = np.concatenate([X, W, P], axis=1)
+    return dense.sym(S.conj().T @ H @ S), dense.sym(S.conj().T @ S), S, H
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("p_low", [(-10.0, -9.0), (-10.0, 10.0)], ids=["CX-zero", "CX-rank1"])
+def test_theorem1_singular_cx_backtracks(cplx, p_low):
+    """C_X of the q lowest pairs of the full pencil is singular (P spans the
+    lowest directions and is orthogonal to X): the block is solved again
+    without P and the result is exactly the 2q x 2q solution, whose C_X is
+    nonsingular (Theorem 2, x^H H w != 0)."""
+    rng = np.random.default_rng(31 + cplx)
+    q = 2
+    A, B, S, H = _pencil_from_operator(cplx, np.array(p_low), rng, q)
+    # premise: with P the q lowest Ritz vectors have a singular X part
+    full = dense.block_pencil(A, B, q, True, _allow_backtrack=False)
+    assert full.used_p
+    assert np.linalg.svd(full.C[:q], compute_uv=False).min() < 1e-10
+    r = dense.block_pencil(A, B, q, True)
+    assert r.backtracked and not r.used_p
+    nop = dense.block_pencil(A, B, q, False)
+    np.testing.assert_array_equal(r.C, nop.C)
+    np.testing.assert_array_equal(r.theta, nop.theta)
+    assert np.all(r.C[2 * q:] == 0)
+    # the no-P solution against the library: the 2q lowest of (S2^H H S2, S2^H S2)
+    S2 = S[:, :2 * q]
+    ref = sla.eigh(S2.conj().T @ H @ S2, S2.conj().T @ S2, eigvals_only=True)[:q]
+    np.testing.assert_allclose(r.theta, ref, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(r.C.conj().T @ B @ r.C, np.eye(q), atol=1e-11)
+    assert np.linalg.svd(r.C[:q], compute_uv=False).min() > 1e-3   # Theorem 2: alpha != 0
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_theorem1_threshold_is_absolute_pivot(cplx):
+    """A weak X-P coupling makes C_X small but nonsingular: kept with P at the
+    default floor, solved without P once singular_tol exceeds the smallest
+    Cholesky pivot of C_X^H C_X (whose scale is 1: C^H B C = I)."""
+    rng = np.random.default_rng(41 + cplx)
+    q = 2
+    A, B, S, H = _pencil_from_operator(cplx, np.array([-10.0, -9.0]), rng, q)
+    eps = 1e-2
+    A = A.copy()
+    A[0, 2 * q] += eps
+    A[2 * q, 0] += eps
+    A[1, 2 * q + 1] += eps
+    A[2 * q + 1, 1] += eps
+    r = dense.block_pencil(A, B, q, True)
+    assert r.used_p and not r.backtracked
+    Cx = r.C[:q]
+    ev = np.linalg.eigvalsh(dense.sym(Cx.conj().T @ Cx))
+    assert 1e-12 < ev.min() and ev.max() < 1e-2
+    # the Cholesky pivots of a q x q Gram lie between its extreme eigenvalues
+    r2 = dense.block_pencil(A, B, q, True, singular_tol=ev.max() * 2)
+    assert r2.backtracked and not r2.used_p
+    np.testing.assert_array_equal(r2.C, dense.block_pencil(A, B, q, False).C)
+    r3 = dense.block_pencil(A, B, q, True, singular_tol=ev.min() / 2)
+    assert r3.used_p and not r3.backtracked

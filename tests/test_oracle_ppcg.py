@@ -141,3 +141,44 @@ def test_wells16_matches_golden_brute_force():
     assert np.abs(lam - ref[:p.k]).max() / np.abs(ref).max() < 1e-9
     R = A(X) - X * lam[None, :]
     assert np.linalg.norm(R) / np.linalg.norm(lam) <= p.tol
+
+
+def test_theorem2_backtrack_in_ppcg():
+    """A Theorem 1 floor of 0.9 on the pivots of C_X^H C_X (whose scale is 1)
+    makes the early, large steps re-solve their blocks without P (Theorem 2).
+    The solve still reaches the dense eigenvalues."""
+    p = I.small_problem(N=8, k=12, q=4, order=2, tol=1e-9)
+    (lam, X, info), A = run(p, singular_tol=0.9)
+    assert info.n_backtrack > 0
+    check_solution(p, lam, X, info, A, 1e-9)
+
+
+def test_locked_set_shrinks_and_p_resets():
+    """V = 0 on 8^3 with k = 16 inside the 12-fold shell 7..18: a column
+    locked at one Rayleigh-Ritz is mixed with its degenerate partners at the
+    next one and the locked prefix shrinks (P is then reset).  The values
+    are the closed-form Laplacian spectrum."""
+    p = I.small_problem(N=8, k=16, q=4, nwells=0, seed=1, rr_period=5, tol=1e-8)
+    (lam, X, info), A = run(p)
+    assert info.n_unlock >= 1
+    ex = laplacian_spectrum(8, 0.5, 2)
+    np.testing.assert_allclose(lam, ex[:16], atol=1e-10)
+    np.testing.assert_allclose(X.T @ X, np.eye(16), atol=1e-12)
+
+
+def test_exact_eigenvector_in_start_block():
+    """A start block holding an exact eigenvector (the constant vector at
+    V = 0) has a zero residual column: its search direction is dropped from
+    the block pencil (Theorem 2 excludes r_j = 0) and the column stays put."""
+    p = I.small_problem(N=8, k=7, q=2, nwells=0, tol=1e-9)
+    X0 = p.start()
+    X0[:, 0] = 1.0
+    g = p.grid
+    A = lambda Y: stencil.apply_h(Y, p.V, g.N, g.h, g.order)
+    Q, _ = dense.cholqr(X0)
+    R = A(Q) - Q @ (Q.T @ A(Q))
+    assert np.linalg.norm(R[:, 0]) <= 1e-13 * np.linalg.norm(R)    # premise: w_0 = 0
+    (lam, X, info), _ = run(p, X0=X0)
+    assert info.n_dropped > 0
+    ex = laplacian_spectrum(8, 0.5, 2)
+    np.testing.assert_allclose(lam, ex[:7], atol=1e-11)
