@@ -43,6 +43,50 @@ def kernel_source_sha():
 F32_KERNELS = ("gram_proj", "update_proj", "stencil_f32")
 
 
+STAGES = ("gemm", "ax", "rr", "cholqr", "small_eig", "other")
+
+
+def is_f32(name, precision):
+    return precision == "mixed" and name in F32_KERNELS
+
+
+def hbm_rates(kt, precision):
+    """Achieved HBM rate (algorithmic bytes / device time) of every kernel
+    kind whose compulsory bytes at 8 TB/s take longer than its flops at the
+    dtype's dense peak (HBM-bound by its own intensity), with the counter
+    rate where the committed traffic summary covers it."""
+    out = {}
+    for name, (ms, cnt, fl, by) in kt.items():
+        if cnt == 0 or by <= 0 or ms <= 0:
+            continue
+        pf = PEAK["f32"] if is_f32(name, precision) else PEAK["f64"]
+        if fl / (pf * 1e12) > by / (PEAK["hbm"] * 1e9):
+            continue
+        d = {"algorithmic_GBps": round(by / (ms * 1e-3) / 1e9, 1), "frac": round(by / (ms * 1e-3) / 1e9 / PEAK["hbm"], 4),
+             "avg_launch_us": round(ms / cnt * 1e3, 2)}
+        t = traffic_for(name, precision)
+        if t is not None:
+            d["counter_GBps"] = round(t * cnt / (ms * 1e-3) / 1e9, 1)
+            d["traffic_over_algorithmic"] = round(t * cnt / by, 3)
+        out[name] = d
+    return out
+
+
+def solve_roofline(info):
+    """Whole-solve roofline fraction: sum over the modelled launches of
+    max(bytes / 8 TB/s, flops / MFMA peak), divided by the solve's wall time
+    (kernels without a model -- eigensolves, pencils, Cholesky -- count 0)."""
+    if not info.get("roofline_ms"):
+        return None
+    meas = info["time_s"] * 1e3
+    return {"roofline_ms": round(info["roofline_ms"], 2), "measured_ms": round(meas, 2),
+            "frac": round(info["roofline_ms"] / meas, 4)}
+
+
+def stage_ms(info):
+    return {k: round(v, 2) for k, v in zip(STAGES, info["stage_ms"])}
+
+
 def roofline(kt, precision):
     """Dominant kernel (largest device time among kernels with an algorithmic
     model), placed on the roofline by its own arithmetic intensity: MFMA-bound
@@ -57,7 +101,7 @@ def roofline(kt, precision):
     if best is None:
         return None
     name, ms, cnt, fl, by = best
-    f32 = precision == "mixed" and name in F32_KERNELS
+    f32 = is_f32(name, precision)
     pflops = PEAK["f32"] if f32 else PEAK["f64"]
     t_flop = fl / (pflops * 1e12)
     t_byte = by / (PEAK["hbm"] * 1e9)
@@ -72,21 +116,26 @@ def roofline(kt, precision):
     out.update({"kernel": name, "dtype": "f32" if f32 else "f64", "launches": cnt,
                 "avg_launch_us": round(ms / cnt * 1e3, 2),
                 "algorithmic_flops_per_launch": fl / cnt, "algorithmic_bytes_per_launch": by / cnt,
-                "traffic": traffic_for(name)})
+                "traffic": traffic_for(name, precision)})
     return out
 
 
-def traffic_for(name):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+def traffic_path(precision):
+    return os.path.join(ROOT, "profiles", f"traffic_wells48_{precision}.json")
+
+
+def traffic_for(name, precision):
+    """HBM bytes per launch of the kernel in a solve of the given precision,
+    from the committed rocprofv3 counter summary of that precision, if it was
+    taken on the current kernel sources; else None."""
+    path = traffic_path(precision)
     if not os.path.exists(path):
         return None
     try:
         d = json.load(open(path))
     except Exception:
         return None
-    if d.get("source_sha") != kernel_source_sha():
+    if d.get("source_sha") != kernel_source_sha() or d.get("precision") != precision:
         return None
     k = d.get("kernels", {}).get(name)
     return None if k is None else k.get("hbm_bytes_per_launch")
@@ -110,9 +159,10 @@ def _symbol_matches(sym, prefix, site):
     return sym.rstrip().endswith(f", {site}>(ppcg::GramArgs)") or sym.rstrip().endswith(f", {site}>(ppcg::UpdateArgs)")
 
 
-def write_traffic(fetch_db, write_db, launches, path=None):
-    """profiles/traffic.json from two rocprofv3 --pmc databases (FETCH_SIZE,
-    WRITE_SIZE) of `bench.py --steps 1 --warmup 1 --only mixed --calib-copy`:
+def write_traffic(fetch_db, write_db, launches, precision, path=None):
+    """profiles/traffic_wells48_<precision>.json from two rocprofv3 --pmc
+    databases (FETCH_SIZE, WRITE_SIZE) of `bench.py --steps 1 --warmup 1
+    --only <precision> --calib-copy --no-cpu-baseline`:
     per logical kernel, the mean HBM bytes per dispatch over the last
     `launches[name]` dispatches (the timed solve), each counter scaled by the
     bytes it reports for the 1 GiB device copy of the calibration step."""
@@ -124,7 +174,7 @@ def write_traffic(fetch_db, write_db, launches, path=None):
                          "where counter_name = ? order by dispatch_id", (counter,)).fetchall()
         return rows
 
-    out = {"source_sha": kernel_source_sha(), "kernels": {}, "calibration": {}}
+    out = {"source_sha": kernel_source_sha(), "precision": precision, "kernels": {}, "calibration": {}}
     per = {}
     for db, counter in ((fetch_db, "FETCH_SIZE"), (write_db, "WRITE_SIZE")):
         rows = load(db, counter)
@@ -149,7 +199,7 @@ def write_traffic(fetch_db, write_db, launches, path=None):
             out["kernels"][name] = {"fetch_bytes_per_launch": d["FETCH_SIZE"], "write_bytes_per_launch": d["WRITE_SIZE"],
                                     "hbm_bytes_per_launch": d["FETCH_SIZE"] + d["WRITE_SIZE"],
                                     "launches": launches[name]}
-    path = path or os.path.join(ROOT, "profiles", "traffic.json")
+    path = path or traffic_path(precision)
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
     log(f"wrote {path}: {sorted(out['kernels'])}")
@@ -233,6 +283,76 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_bloch(args):
+    """The 96^3 complex Hermitian workload (Bloch vector (2 pi 0.25 / L, 0, 0),
+    smoothed random potential in [-2, 0], 13-point stencil, k = 2048,
+    sbsize 32, nbuf 64): one complete solve per precision (complex64 bulk
+    with complex128 master, and plain complex128), fixed kernel plans (no
+    autotuner warmup solve: a solve takes minutes).  Progress goes to stderr
+    every 10 iterations.  The oracle cannot run at this size on the host (one
+    n x K complex128 block is 30 GB and it keeps about ten), so no
+    cpu_baseline is reported."""
+    import numpy as np
+    import torch
+    from paper_1407_7506_amd import binding as B
+    from paper_1407_7506_amd import inputs as I
+
+    p = I.bloch96()
+    g = p.grid
+    V = torch.tensor(p.V, device="cuda")
+    torch.cuda.synchronize()
+    results = {}
+    precs = ["mixed", "fp64"] if args.only == "both" else [args.only]
+    for prec in precs:
+        def prog(r, prec=prec):
+            if r["iter"] % 10 == 0 or r["kind"] == "final_rr_failed":
+                log(f"  {prec} iter {r['iter']:4d} rho {r['rho']:.3e} locked {r['n_locked']:5d} "
+                    f"t {r['time_s']:8.1f} s")
+        h = B.Handle(prec, profile=True, max_iter=args.max_iter, log=prog)
+        X0 = torch.tensor(p.start(), device="cuda")   # (n, K) complex128, 30 GB
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lam, X, info = h.solve(V, g.N, p.k, p.q, p.tol, p.rr_period, X0, h=g.h, order=g.order, kpt=g.kpt,
+                               check=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        del X0, X
+        torch.cuda.empty_cache()
+        kt = h.kernel_times()
+        results[prec] = {"s": dt, "info": info, "lam": lam.cpu().numpy(), "kt": kt}
+        log(f"{prec}: {dt:.1f} s, status {info['status']}, iters {info['iters']}, rr {info['n_rr']}, "
+            f"resid {info['resid_final']:.3e}")
+        for name, (ms, cnt, fl, by) in sorted(kt.items(), key=lambda x: -x[1][0])[:16]:
+            log(f"   {name:14s} {ms:10.1f} ms {cnt:6d} launches {ms / max(cnt, 1):9.2f} ms/launch")
+        h.close()
+    main_prec = "mixed" if "mixed" in results else "fp64"
+    r = results[main_prec]
+    out = {
+        "metric": METRIC, "value": round(r["s"], 3), "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": round(r["s"] * 1e3, 1), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c64+c128 (mixed)" if main_prec == "mixed" else "c128", "data": "synthetic",
+        "config": {"workload": "bloch96_k2048: 13-point 96^3 periodic FD Hamiltonian with Bloch vector "
+                               "(2 pi 0.25/L, 0, 0), smoothed N(0,1) potential in [-2, 0], k=2048, sbsize=32, "
+                               "nbuf=64, rr_period=5, tol=1e-6, Jacobi, N(0,1) start",
+                   "n": g.n, "k": p.k, "sbsize": p.q, "K": p.K, "precision": main_prec, "max_iter": args.max_iter},
+        "status": r["info"]["status"], "iters": r["info"]["iters"], "n_rr": r["info"]["n_rr"],
+        "resid_final": r["info"]["resid_final"], "orth_err": r["info"]["orth_err"],
+        "n_locked": r["info"]["n_locked"],
+        "roofline": roofline(r["kt"], main_prec), "solve_roofline": solve_roofline(r["info"]),
+        "stage_ms": stage_ms(r["info"]), "hbm": hbm_rates(r["kt"], main_prec),
+        "cpu_baseline": None,
+    }
+    if "fp64" in results and "mixed" in results:
+        lf, lm = results["fp64"]["lam"], results["mixed"]["lam"]
+        out["fp64_s"] = round(results["fp64"]["s"], 3)
+        out["fp64_status"] = results["fp64"]["info"]["status"]
+        out["fp64_iters"] = results["fp64"]["info"]["iters"]
+        out["fp64_stage_ms"] = stage_ms(results["fp64"]["info"])
+        out["speedup_mixed_vs_fp64"] = round(results["fp64"]["s"] / results["mixed"]["s"], 3)
+        out["mixed_vs_fp64_max_err"] = float(np.abs(lm - lf).max() / np.abs(lf).max())
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -243,23 +363,29 @@ def main():
     ap.add_argument("--only", choices=["both", "fp64", "mixed"], default="both")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain device copy of 1 GiB (counter calibration under rocprofv3)")
-    ap.add_argument("--workload", choices=["wells48", "batch64"], default="wells48")
+    ap.add_argument("--workload", choices=["wells48", "batch64", "bloch96"], default="wells48")
     ap.add_argument("--no-autotune", action="store_true",
                     help="fixed kernel plans instead of the autotuner's (tuning happens in the warmup solve)")
     ap.add_argument("--nprob", type=int, default=64, help="problems of the batch64 workload")
+    ap.add_argument("--max-iter", type=int, default=20000, help="iteration cap (bloch96)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
-                    help="write profiles/traffic.json from two rocprofv3 --pmc databases and exit (no GPU use)")
+                    help="write profiles/traffic_wells48_<precision>.json from two rocprofv3 --pmc databases "
+                         "and exit (no GPU use)")
+    ap.add_argument("--traffic-precision", choices=["fp64", "mixed"], default="mixed",
+                    help="precision of the solve the counter databases were taken on")
     ap.add_argument("--traffic-launches", default="",
                     help="name=count,... launches per timed solve (from the bench run under the profiler)")
     args = ap.parse_args()
     if args.traffic_from:
         launches = {kv.split("=")[0]: int(kv.split("=")[1]) for kv in args.traffic_launches.split(",") if "=" in kv}
-        return write_traffic(args.traffic_from[0], args.traffic_from[1], launches)
+        return write_traffic(args.traffic_from[0], args.traffic_from[1], launches, args.traffic_precision)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: the solver runs on one GPU; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch64":
         return bench_batch(args)
+    if args.workload == "bloch96":
+        return bench_bloch(args)
 
     import numpy as np
     import torch
@@ -304,7 +430,7 @@ def main():
         results[prec] = {"s": dt / args.steps, "info": infos[-1], "lam": lam.cpu().numpy(), "kt": kt,
                          "tune_classes": len(tune.splitlines())}
         log(f"{prec}: {dt / args.steps:.3f} s/solve, iters {infos[-1]['iters']}, rr {infos[-1]['n_rr']}, "
-            f"resid {infos[-1]['resid_final']:.3e}")
+            f"resid {infos[-1]['resid_final']:.3e}, stages {stage_ms(infos[-1])}")
         top = sorted(kt.items(), key=lambda x: -x[1][0])[:24]
         for name, (ms, cnt, fl, by) in top:
             log(f"   {name:14s} {ms / args.steps:9.1f} ms/solve {cnt // args.steps:6d} launches "
@@ -337,6 +463,9 @@ def main():
         "resid_final": r["info"]["resid_final"],
         "orth_err": r["info"]["orth_err"],
         "roofline": roofline(kt, main_prec),
+        "solve_roofline": solve_roofline(r["info"]),
+        "stage_ms": stage_ms(r["info"]),
+        "hbm": hbm_rates(kt, main_prec),
         "kernel_share": {k: round(v[0] / tot_ms, 4) for k, v in sorted(kt.items(), key=lambda x: -x[1][0])[:8]},
         "launches_per_solve": {k: v[1] // args.steps for k, v in kt.items() if k in TRAFFIC_KERNELS},
         "autotune": {"enabled": not args.no_autotune, "shape_classes": r["tune_classes"],
@@ -344,11 +473,15 @@ def main():
     }
     if "fp64" in results and "mixed" in results:
         lf, lm = results["fp64"]["lam"], results["mixed"]["lam"]
-        out["fp64_s"] = round(results["fp64"]["s"], 4)
-        out["fp64_iters"] = results["fp64"]["info"]["iters"]
-        out["speedup_mixed_vs_fp64"] = round(results["fp64"]["s"] / results["mixed"]["s"], 3)
+        rf = results["fp64"]
+        out["fp64_s"] = round(rf["s"], 4)
+        out["fp64_iters"] = rf["info"]["iters"]
+        out["speedup_mixed_vs_fp64"] = round(rf["s"] / results["mixed"]["s"], 3)
         out["mixed_vs_fp64_max_err"] = float(np.abs(lm - lf).max() / np.abs(lf).max())
-        out["roofline_fp64"] = roofline(results["fp64"]["kt"], "fp64")
+        out["roofline_fp64"] = roofline(rf["kt"], "fp64")
+        out["solve_roofline_fp64"] = solve_roofline(rf["info"])
+        out["stage_ms_fp64"] = stage_ms(rf["info"])
+        out["hbm_fp64"] = hbm_rates(rf["kt"], "fp64")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(p, r["info"]["iters"], args.cpu_iters)

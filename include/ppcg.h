@@ -60,6 +60,20 @@ typedef enum {
 typedef enum { PPCG_FP64 = 0, PPCG_MIXED = 1 } ppcg_precision;
 typedef enum { PPCG_PRECOND_NONE = 0, PPCG_PRECOND_JACOBI = 1 } ppcg_precond;
 
+/* One record per PPCG iteration, passed to options.log_cb at the loop head
+ * (convergence test of section 5.2) on the host thread of the call. */
+typedef struct {
+  int32_t iter;         /* iterations completed so far (0 = after the start block) */
+  int32_t n_locked;     /* locked columns (soft locking, section 5.7) */
+  int32_t n_active;     /* active columns K - n_locked */
+  int32_t kind;         /* what the last iteration ended with: 0 start, 1 Cholesky-QR
+                           (steps 18-20), 2 Rayleigh-Ritz (steps 21-31), 3 final
+                           Rayleigh-Ritz that failed the fresh residual check */
+  double rho;           /* relative subspace residual of the k wanted columns */
+  double time_s;        /* wall time since the call started */
+} ppcg_iter_log;
+typedef void (*ppcg_log_fn)(const ppcg_iter_log* rec, void* user);
+
 typedef struct {
   int32_t precision;  /* ppcg_precision.  PPCG_MIXED keeps W, P, HW, HP and the
                          projections X^H W, X^H P in float32 (MFMA, float32
@@ -76,6 +90,20 @@ typedef struct {
   int32_t profile;    /* nonzero: time every kernel launch with HIP events on
                          the handle's stream (see ppcg_kernel_times) */
   int32_t flags;      /* bit set of ppcg_flags */
+  double singular_tol;/* Theorem 1 test of a sub-block step taken with P: C_X counts
+                         as singular when a Cholesky pivot of C_X^H C_X is below this
+                         floor (C^H B C = I and X orthonormal give C_X^H C_X <= I), and
+                         the block is solved again without P (Theorem 2).  <= 0: 1e-12 */
+  uint64_t seed;      /* X0 == NULL in ppcg_solve: the start block is drawn on the
+                         device, N(0,1) entries (complex: real and imaginary parts
+                         N(0,1/2)) from the Philox-4x32-10 counter generator keyed
+                         by this seed, counter (row, column) */
+  const char* tune_table; /* PPCG_AUTOTUNE: text file of autotuner decisions, read by
+                         ppcg_create when it exists (an unreadable or malformed file
+                         is PPCG_EINVAL) and rewritten after a solve that timed a
+                         new shape class; NULL = decisions live in the handle only */
+  ppcg_log_fn log_cb; /* per-iteration record (ppcg_iter_log); NULL = none */
+  void* log_user;     /* passed back to log_cb */
 } ppcg_options;
 
 typedef enum {
@@ -108,8 +136,29 @@ typedef struct {
                            from a fresh float64 H X */
   double orth_err;      /* |X^H X - I|_F of the returned X */
   double time_s;        /* wall time of the call */
-  double stage_ms[6];   /* GEMM, stencil (AX), RR, CholQR, small eig, other --
-                           filled when options.profile is set */
+  double stage_ms[6];   /* device time (HIP events, options.profile set; zeros
+                           otherwise) in the categories of the paper's time
+                           breakdown (section 6, Tables 4-5):
+                           [0] GEMM: projection Grams and updates (steps 9-10),
+                               per-block Grams (step 13 input), block update
+                               (steps 14-15), residual X^H H X and H X - X G;
+                           [1] AX: stencil products;
+                           [2] RR: Rayleigh-Ritz Grams, Cholesky, eigensolve,
+                               rotation and Ritz residuals (steps 21-31, final);
+                           [3] CholQR: X^H X, Cholesky + inverse, X R^{-1}
+                               (steps 18-19), and the start block's;
+                           [4] small eig: the sub-block pencils (step 13);
+                           [5] other: reductions of split partials outside the
+                               above, column norms, copies */
+  int32_t n_dropped;    /* W/P columns left out of sub-block pencils as zero or
+                           dependent (summed over iterations and blocks) */
+  int32_t n_unlock;     /* Rayleigh-Ritz steps at which the locked prefix shrank
+                           (P is then reset: P(J_act) is undefined) */
+  double roofline_ms;   /* options.profile set: sum over the modelled launches of
+                           max(bytes / 8 TB/s, flops / dense MFMA peak of the
+                           launch's dtype: 78.6 TFLOP/s float64, 157.3 float32),
+                           i.e. the time of this solve with every modelled kernel
+                           at the MI355X roofline */
 } ppcg_info;
 
 typedef struct ppcg_handle ppcg_handle;
@@ -126,8 +175,9 @@ ppcg_status ppcg_create(ppcg_handle** out, const ppcg_options* opt, void* stream
  *   tol       relative subspace residual |HX - X(X^H H X)|_F / |X^H H X|_F
  *             over the k wanted columns (section 5.2); > 0
  *   rr_period Rayleigh-Ritz every rr_period iterations (section 5.6); >= 1
- *   X0        device, n x K start block (ld n), need not be orthonormal;
- *             NULL is an error (complex when op->kpt != 0)
+ *   X0        device, n x K start block (ld n), need not be orthonormal
+ *             (complex when op->kpt != 0); NULL draws a seeded N(0,1) block on
+ *             the device (options.seed)
  *   X_out     device, n x k (ld n): eigenvectors, orthonormal (complex when
  *             op->kpt != 0)
  *   lambda_out device, k: eigenvalues ascending
@@ -150,12 +200,15 @@ ppcg_status ppcg_solve(ppcg_handle* h, const ppcg_operator* op, int32_t k, int32
  *   w         device, n; NULL means w = 0 (eigenvalue terms only)
  *   dL_dV     device, n (output)
  *   max_iter  CG iteration cap (<= 0: 10000); iters (may be NULL) receives
- *             the iterations used.
- * PPCG_ENOSTATE without a successful solve; PPCG_EINVAL when that solve had a
- * complex operator (real operators only).  Requires a gap between
- * lambda_k and lambda_{k+1} (the density is not differentiable otherwise). */
+ *             the iterations used, resid (may be NULL) the largest relative
+ *             residual |r_i| / |b_i| over the columns at exit.
+ * PPCG_ENOCONV when the cap is reached with a column above tol (dL_dV then
+ * holds the gradient of the last CG iterate); PPCG_ENOSTATE without a
+ * successful solve; PPCG_EINVAL when that solve had a complex operator (real
+ * operators only).  Requires a gap between lambda_k and lambda_{k+1} (the
+ * density is not differentiable otherwise). */
 ppcg_status ppcg_grad(ppcg_handle* h, const double* g_lambda, const double* w, double* dL_dV, double tol,
-                      int32_t max_iter, int32_t* iters);
+                      int32_t max_iter, int32_t* iters, double* resid);
 
 /* rho[r] = sum_{i<k} x_i(r)^2 for the pairs of the last successful solve
  * (device, n).  PPCG_ENOSTATE without a successful solve, PPCG_EINVAL after a
@@ -176,7 +229,9 @@ int32_t ppcg_columns(const ppcg_handle* h, int32_t k, int32_t sbsize);
  * follows exactly the arithmetic of ppcg_solve, so results equal those of
  * nprob separate ppcg_solve calls.
  *   ops, k, X0, X_out, lambda_out: host arrays of nprob entries (the
- *                 pointers they hold are device pointers)
+ *                 pointers they hold are device pointers); X0 may be NULL,
+ *                 or hold NULL entries: problem b then draws its start block
+ *                 on the device with seed options.seed + b
  *   infos, statuses: host arrays of nprob entries, may be NULL
  * A batch holds either only real or only complex operators; a problem whose
  * kind differs from the first valid one gets PPCG_EINVAL.
@@ -189,8 +244,32 @@ ppcg_status ppcg_solve_batched(ppcg_handle* h, int32_t nprob, const ppcg_operato
                                int32_t* statuses);
 
 /* Y = H X for ncols columns (device, ld n): the operator product alone.
- * X and Y are complex (interleaved) when op->kpt != 0. */
+ * X and Y are complex (interleaved) when op->kpt != 0.  PPCG_EINVAL for
+ * nx < 4, h <= 0 or an order other than 2 and 4. */
 ppcg_status ppcg_apply_h(ppcg_handle* h, const ppcg_operator* op, int32_t ncols, const double* X, double* Y);
+
+/* The sub-block projected problems of one PPCG iteration alone (step 13 of
+ * Algorithm 3; section 5.1; Theorems 1-2), for tests of that step: for each
+ * of nblocks pencils (A_j, B_j) of order nS = 3q (has_p) or 2q, columns
+ * ordered [X_j, W_j, P_j], returns the q lowest eigenvectors C_j of
+ * herm(A_j) c = theta herm(B_j) c with C_j^H B_j C_j = I, exactly as
+ * ppcg_solve computes them: diagonal scaling, zero W/P columns dropped,
+ * greedy Cholesky in the order X, W, P, cyclic Jacobi, and when P took part
+ * the Theorem 1 test on C_X (options.singular_tol) with the re-solve without
+ * P of Theorem 2.
+ *   A, B     device, nblocks matrices of nS x nS (column-major, ld nS,
+ *            stride nS*nS; complex interleaved when cplx)
+ *   tol      the solve tolerance the Jacobi skip threshold is tied to
+ *            (rotations below max(2.2e-16, min(1e-10, 1e-4 tol)) |M|_F are
+ *            skipped, as in ppcg_solve)
+ *   C        device out, nblocks x (3q x q), ld 3q, stride 3q*q; rows of
+ *            dropped columns (and the P rows without P) are zero
+ *   flags    device out, nblocks ints: bit 0 P used, bit 1 backtracked
+ *            (Theorem 1 test failed), bit 2 rank below q (C then holds
+ *            [I; 0; 0]), bits 8.. number of W/P columns left out
+ * 1 <= q <= 32; PPCG_EINVAL otherwise. */
+ppcg_status ppcg_block_pencils(ppcg_handle* h, int32_t nblocks, int32_t q, int32_t has_p, int32_t cplx,
+                               const double* A, const double* B, double tol, double* C, int32_t* flags);
 
 /* Per-kernel accumulated device time (ms) and launch counts since the last
  * reset, for kernels launched while options.profile was set.  names,

@@ -136,6 +136,7 @@ def ppcg(apply_a, tdiag, X0, k, sbsize, tol, rr_period, max_iter=20000, record=F
             continue
         if it > max_iter:
             info.iters = it - 1
+            info.n_locked = nl
             X2, lam, _ = rayleigh_ritz(X, apply_a(X))
             raise NoConvergence("max_iter reached", lam[:k], X2[:, :k], info)
 

@@ -15,7 +15,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from ctypes import POINTER, byref, c_char_p, c_double, c_int32, c_int64, c_void_p
+from ctypes import CFUNCTYPE, POINTER, byref, c_char_p, c_double, c_int32, c_int64, c_uint64, c_void_p
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libppcg.so")
@@ -34,9 +34,19 @@ class PPCGError(RuntimeError):
         self.info = info
 
 
+class IterLog(ctypes.Structure):
+    _fields_ = [("iter", c_int32), ("n_locked", c_int32), ("n_active", c_int32), ("kind", c_int32),
+                ("rho", c_double), ("time_s", c_double)]
+
+
+LOG_FN = CFUNCTYPE(None, POINTER(IterLog), c_void_p)
+ITER_KIND = {0: "start", 1: "cholqr", 2: "rr", 3: "final_rr_failed"}
+
+
 class Options(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("nbuf", c_int32), ("max_iter", c_int32), ("profile", c_int32),
-                ("flags", c_int32)]
+                ("flags", c_int32), ("singular_tol", c_double), ("seed", c_uint64), ("tune_table", c_char_p),
+                ("log_cb", LOG_FN), ("log_user", c_void_p)]
 
 
 class Operator(ctypes.Structure):
@@ -47,7 +57,8 @@ class Operator(ctypes.Structure):
 class Info(ctypes.Structure):
     _fields_ = [("iters", c_int32), ("n_rr", c_int32), ("n_locked", c_int32), ("n_backtrack", c_int32),
                 ("resid_final", c_double), ("orth_err", c_double), ("time_s", c_double),
-                ("stage_ms", c_double * 6)]
+                ("stage_ms", c_double * 6), ("n_dropped", c_int32), ("n_unlock", c_int32),
+                ("roofline_ms", c_double)]
 
     def as_dict(self):
         return {f: (list(getattr(self, f)) if f == "stage_ms" else getattr(self, f)) for f, _ in self._fields_}
@@ -73,7 +84,8 @@ def lib():
                                      c_int32, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p),
                                      POINTER(Info), POINTER(c_int32)]
     L.ppcg_solve_batched.restype = c_int32
-    L.ppcg_grad.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int32, POINTER(c_int32)]
+    L.ppcg_grad.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int32, POINTER(c_int32),
+                            POINTER(c_double)]
     L.ppcg_grad.restype = c_int32
     L.ppcg_density.argtypes = [c_void_p, c_void_p]
     L.ppcg_density.restype = c_int32
@@ -81,6 +93,9 @@ def lib():
     L.ppcg_columns.restype = c_int32
     L.ppcg_apply_h.argtypes = [c_void_p, POINTER(Operator), c_int32, c_void_p, c_void_p]
     L.ppcg_apply_h.restype = c_int32
+    L.ppcg_block_pencils.argtypes = [c_void_p, c_int32, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_double,
+                                     c_void_p, c_void_p]
+    L.ppcg_block_pencils.restype = c_int32
     L.ppcg_kernel_times.argtypes = [c_void_p, POINTER(c_char_p), POINTER(c_double), POINTER(c_int64), c_int32]
     L.ppcg_kernel_times.restype = c_int32
     L.ppcg_kernel_stats.argtypes = [c_void_p, POINTER(c_char_p), POINTER(c_double), POINTER(c_int64),
@@ -115,11 +130,22 @@ class Handle:
     """One libppcg handle bound to the current device and torch stream."""
 
     def __init__(self, precision: str = "fp64", nbuf: int = -1, max_iter: int = 0, profile: bool = False,
-                 stream=None, graphs: bool = True, autotune: bool = False):
+                 stream=None, graphs: bool = True, autotune: bool = False, singular_tol: float = 0.0,
+                 seed: int = 0, tune_table: str | None = None, log=None):
+        """log: optional callable receiving one dict per PPCG iteration (iter,
+        n_locked, n_active, kind, rho, time_s)."""
         import torch
         self._L = lib()
         flags = (0 if graphs else PPCG_NO_GRAPHS) | (PPCG_AUTOTUNE if autotune else 0)
-        opt = Options(PPCG_MIXED if precision == "mixed" else PPCG_FP64, nbuf, max_iter, 1 if profile else 0, flags)
+        self._log_fn = LOG_FN(0)
+        if log is not None:
+            def _cb(rec, _user):
+                r = rec.contents
+                log({"iter": r.iter, "n_locked": r.n_locked, "n_active": r.n_active,
+                     "kind": ITER_KIND.get(r.kind, r.kind), "rho": r.rho, "time_s": r.time_s})
+            self._log_fn = LOG_FN(_cb)
+        opt = Options(PPCG_MIXED if precision == "mixed" else PPCG_FP64, nbuf, max_iter, 1 if profile else 0, flags,
+                      float(singular_tol), int(seed), tune_table.encode() if tune_table else None, self._log_fn, None)
         st = stream if stream is not None else torch.cuda.current_stream()
         self.stream = st
         h = c_void_p()
@@ -173,22 +199,28 @@ class Handle:
 
     def solve(self, V, N, k, sbsize, tol, rr_period, X0, h=0.5, order=2, check=True, kpt=(0.0, 0.0, 0.0)):
         """Lowest k eigenpairs.  X0: (n, K) start block (torch CUDA float64, or
-        complex128 for a nonzero Bloch vector kpt).
+        complex128 for a nonzero Bloch vector kpt), or None for a start block
+        drawn on the device from the handle's seed.
         Returns (lam (k,), X (n, k), info dict)."""
         import torch
         n = N ** 3
-        _check_tensor(X0, "X0", cplx=_is_complex_kpt(kpt))
+        cplx = _is_complex_kpt(kpt)
         K = self.columns(k, sbsize)
-        if X0.dim() != 2 or X0.shape[0] != n or X0.shape[1] != K:
-            raise ValueError(f"X0 must have shape (n, K) = ({n}, {K})")
-        X0cm = X0.t().contiguous()
-        Xout = torch.empty((k, n), dtype=X0.dtype, device=X0.device)
-        lam = torch.empty(k, dtype=torch.float64, device=X0.device)
+        if X0 is not None:
+            _check_tensor(X0, "X0", cplx=cplx)
+            if X0.dim() != 2 or X0.shape[0] != n or X0.shape[1] != K:
+                raise ValueError(f"X0 must have shape (n, K) = ({n}, {K})")
+            X0cm = X0.t().contiguous()
+        else:
+            X0cm = None
+        dt = torch.complex128 if cplx else torch.float64
+        Xout = torch.empty((k, n), dtype=dt, device=V.device)
+        lam = torch.empty(k, dtype=torch.float64, device=V.device)
         op = self.operator(V, N, h, order, kpt)
         info = Info()
         code = self._L.ppcg_solve(self._h, byref(op), int(k), int(sbsize), float(tol), int(rr_period),
-                                  c_void_p(X0cm.data_ptr()), c_void_p(Xout.data_ptr()), c_void_p(lam.data_ptr()),
-                                  byref(info))
+                                  c_void_p(X0cm.data_ptr()) if X0cm is not None else None,
+                                  c_void_p(Xout.data_ptr()), c_void_p(lam.data_ptr()), byref(info))
         self._last_n = n if code == 0 else None
         if code != 0 and check:
             raise PPCGError(code, self.error(), info.as_dict())
@@ -199,7 +231,8 @@ class Handle:
     def solve_batched(self, problems, sbsize, tol, rr_period, check=True):
         """Solve many independent problems in lockstep.  problems: list of
         dicts with V (CUDA float64, N^3), N, k, X0 ((n, K) CUDA float64, or
-        complex128 with kpt), and optional h, order, kpt.  All problems are
+        complex128 with kpt; None or absent: drawn on the device from the
+        handle's seed + problem index), and optional h, order, kpt.  All problems are
         real or all complex.  Returns a list of (lam, X (n, k), info, status)."""
         import torch
         nb = len(problems)
@@ -216,20 +249,24 @@ class Handle:
             N, k = int(p["N"]), int(p["k"])
             n = N ** 3
             K = self.columns(k, sbsize)
-            X0 = p["X0"]
+            X0 = p.get("X0")
             kpt = p.get("kpt", (0.0, 0.0, 0.0))
-            _check_tensor(X0, "X0", cplx=_is_complex_kpt(kpt))
-            if X0.dim() != 2 or X0.shape[0] != n or X0.shape[1] != K:
-                raise ValueError(f"problem {b}: X0 must have shape ({n}, {K})")
-            X0cm = X0.t().contiguous()
-            Xo = torch.empty((k, n), dtype=X0.dtype, device=X0.device)
-            lo = torch.empty(k, dtype=torch.float64, device=X0.device)
+            cplx = _is_complex_kpt(kpt)
+            if X0 is not None:
+                _check_tensor(X0, "X0", cplx=cplx)
+                if X0.dim() != 2 or X0.shape[0] != n or X0.shape[1] != K:
+                    raise ValueError(f"problem {b}: X0 must have shape ({n}, {K})")
+                X0cm = X0.t().contiguous()
+                keep.append(X0cm)
+            dt = torch.complex128 if cplx else torch.float64
+            Xo = torch.empty((k, n), dtype=dt, device=p["V"].device)
+            lo = torch.empty(k, dtype=torch.float64, device=p["V"].device)
             ops[b] = self.operator(p["V"], N, p.get("h", 0.5), p.get("order", 2), kpt)
             ks[b] = k
-            x0p[b] = X0cm.data_ptr()
+            x0p[b] = X0cm.data_ptr() if X0 is not None else None
             xop[b] = Xo.data_ptr()
             lop[b] = lo.data_ptr()
-            keep += [X0cm, p["V"]]
+            keep.append(p["V"])
             outs.append((lo, Xo))
         code = self._L.ppcg_solve_batched(self._h, nb, ops, ks, int(sbsize), float(tol), int(rr_period), x0p, xop,
                                           lop, infos, sts)
@@ -250,12 +287,38 @@ class Handle:
             raise PPCGError(5, "no successful solve on this handle")
         out = torch.empty(n, dtype=torch.float64, device=g_lambda.device)
         it = c_int32(0)
+        res = c_double(0.0)
         code = self._L.ppcg_grad(self._h, c_void_p(g_lambda.contiguous().data_ptr()),
                                  c_void_p(w.contiguous().data_ptr()) if w is not None else None,
-                                 c_void_p(out.data_ptr()), float(tol), int(max_iter), byref(it))
+                                 c_void_p(out.data_ptr()), float(tol), int(max_iter), byref(it), byref(res))
+        self.grad_iters, self.grad_resid = it.value, res.value
+        if code != 0:
+            raise PPCGError(code, self.error(), {"iters": it.value, "resid": res.value})
+        return out, it.value
+
+    def block_pencils(self, A, B, q, has_p, tol=1e-9):
+        """The sub-block projected problems alone: A, B (nblocks, nS, nS)
+        CUDA float64 / complex128 tensors (row-major view of column-major
+        matrices: element [j, c, r] is row r, column c of block j), nS = 3q
+        with P or 2q.  Returns (C (nblocks, q, 3q): C[j, t, i] is row i of
+        eigenvector t, flags (nblocks,) int32)."""
+        import torch
+        cplx = A.dtype == torch.complex128
+        _check_tensor(A, "A", cplx=cplx)
+        _check_tensor(B, "B", cplx=cplx)
+        nb, nS = A.shape[0], A.shape[1]
+        if A.shape != (nb, nS, nS) or B.shape != A.shape or nS != (3 if has_p else 2) * q:
+            raise ValueError("A, B must be (nblocks, nS, nS) with nS = 3q (has_p) or 2q")
+        A = A.contiguous()
+        B = B.contiguous()
+        C = torch.zeros((nb, q, 3 * q), dtype=A.dtype, device=A.device)
+        flags = torch.zeros(nb, dtype=torch.int32, device=A.device)
+        code = self._L.ppcg_block_pencils(self._h, int(nb), int(q), 1 if has_p else 0, 1 if cplx else 0,
+                                          c_void_p(A.data_ptr()), c_void_p(B.data_ptr()), float(tol),
+                                          c_void_p(C.data_ptr()), c_void_p(flags.data_ptr()))
         if code != 0:
             raise PPCGError(code, self.error())
-        return out, it.value
+        return C, flags
 
     def density(self):
         """rho = sum_i x_i^2 of the last solve (torch CUDA float64, (n,))."""

@@ -270,14 +270,15 @@ PPCG_DEV void block_pencil_body(const PencilArgs& a, unsigned wg, unsigned) {
         b3[u + v * LD] = s;
       }
       __syncthreads();
-      // right-looking Cholesky of the q x q Gram over the workgroup, relative
-      // pivot test (every thread reads the same pivots, so the exit is uniform)
-      double gmax = 0;
-      for (int u = 0; u < q; ++u) gmax = fmax(gmax, real_(b3[u + u * LD]));
+      // right-looking Cholesky of the q x q Gram over the workgroup (every
+      // thread reads the same pivots, so the exit is uniform).  The columns
+      // of C are B-orthonormal and X is orthonormal and orthogonal to W and
+      // P, so C_X^H C_X <= I: pivots are compared with 1, and a C_X that
+      // vanishes to rounding counts as singular.
       int bad = 0;
       for (int c = 0; c < q; ++c) {
         const double piv = real_(b3[c + c * LD]);
-        if (!(piv >= a.pivot_tol * gmax)) {
+        if (!(piv >= a.sing_tol)) {
           bad = 1;
           break;
         }
@@ -299,6 +300,7 @@ PPCG_DEV void block_pencil_body(const PencilArgs& a, unsigned wg, unsigned) {
       }
     }
     if (usedP) flag |= 1;
+    flag |= ((allowP ? 3 * q : 2 * q) - r) << 8;  // W/P columns left out
     // 11. write C (nS x q, ld 3q): zero rows for dropped columns
     S* C = (S*)a.C + (long)blk * a.cstride;
     const int ldc = 3 * q;

@@ -20,7 +20,7 @@
 
 namespace ppcg {
 
-Recorder* g_rec = nullptr;
+thread_local Recorder* g_rec = nullptr;
 
 // ---------------------------------------------------------------------------
 // staging of job arrays

@@ -148,8 +148,10 @@ struct PencilArgs {
                         //    X-W / X-P blocks of the projected A are taken from them
   double* C;            // out: per block nS x q (ld 3q), stride cstride
   long cstride;
-  int* flags;           // out: per block bit0 = P used, bit1 = backtracked, bit2 = rank failure
+  int* flags;           // out: per block bit0 = P used, bit1 = backtracked, bit2 = rank failure,
+                        //      bits 8.. = W/P columns of the solved pencil left out (zero or dependent)
   double drop_tol, pivot_tol;
+  double sing_tol;      // Theorem 1 test: C_X singular when a Cholesky pivot of C_X^H C_X is below it
   double jacobi_rel;    // rotations below jacobi_rel |M|_F are skipped
   int nblocks;
   int cplx;             // complex Hermitian pencils (gram, G and C complex)
@@ -246,7 +248,7 @@ struct Recorder {
     lists[cur].push_back(std::move(op));
   }
 };
-extern Recorder* g_rec;  // non-null while the batched driver records
+extern thread_local Recorder* g_rec;  // non-null while the batched driver of this thread records
 
 // Pinned host staging + device mirror for job arrays.  Bump allocation; the
 // owner calls reset() only after synchronising the stream, so a region is
@@ -352,5 +354,8 @@ void launch_grad_rows(const double* X, const double* Z, const double* g, long ld
 void launch_prep_diag(const double* V, long n, double c0, double* td, float* V32, double* dmin_part, int nparts,
                       int* nan_flag, hipStream_t st);
 void launch_zero_int(int* p, int n, hipStream_t st);
+// N(0,1) start block (Philox-4x32-10 counter (row, column), Box-Muller); launched directly, also
+// while a batch records (it is the first step of the start-up phase)
+void launch_randn(double* X, long ld, long n, int ncols, uint64_t seed, bool cplx, hipStream_t st);
 
 }  // namespace ppcg

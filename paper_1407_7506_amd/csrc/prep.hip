@@ -40,6 +40,54 @@ void launch_prep_diag(const double* V, long n, double c0, double* td, float* V32
   hipLaunchKernelGGL(prep_kernel, dim3(nparts), dim3(256), 0, st, a);
 }
 
+// Start block X0 ~ N(0,1) drawn on the device (ppcg_solve with X0 = NULL).
+// Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
+// easy as 1, 2, 3", SC 2011): counter (row, column, 0, 0), key (seed low,
+// seed high) -> four 32-bit words -> two 53-bit uniforms in (0, 1) -> two
+// normals by the Box-Muller transform.  Real blocks take the first normal;
+// complex blocks take both, scaled by sqrt(1/2) (real and imaginary parts
+// N(0, 1/2)).
+PPCG_DEV void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0], p1 = (uint64_t)0xCD9E8D57u * c[2];
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+__global__ __launch_bounds__(256) void randn_kernel(double* X, long ld, long n, int ncols, uint64_t seed, int cplx) {
+  const long r = blockIdx.x * 256L + threadIdx.x;
+  const int col = blockIdx.y;
+  if (r >= n || col >= ncols) return;
+  uint32_t c[4] = {(uint32_t)r, (uint32_t)col, (uint32_t)(r >> 32), 0u};
+  philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+  const double two53 = 1.0 / 9007199254740992.0;
+  const double u1 = ((double)(c[0] >> 5) * 67108864.0 + (double)(c[1] >> 6) + 0.5) * two53;
+  const double u2 = ((double)(c[2] >> 5) * 67108864.0 + (double)(c[3] >> 6) + 0.5) * two53;
+  const double rad = sqrt(-2.0 * log(u1));
+  double sn, cs;
+  sincospi(2.0 * u2, &sn, &cs);
+  if (cplx) {
+    const double s = 0.70710678118654752440;
+    X[2 * (r + col * ld)] = s * rad * cs;
+    X[2 * (r + col * ld) + 1] = s * rad * sn;
+  } else {
+    X[r + col * ld] = rad * cs;
+  }
+}
+
+void launch_randn(double* X, long ld, long n, int ncols, uint64_t seed, bool cplx, hipStream_t st) {
+  if (n <= 0 || ncols <= 0) return;
+  hipLaunchKernelGGL(randn_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)ncols), dim3(256), 0, st, X, ld, n,
+                     ncols, seed, cplx ? 1 : 0);
+}
+
 bool launch_grouped_prep(int kind, const void* jobs, const unsigned* start, int nj, unsigned total, hipStream_t st) {
   if (kind != OP_PREP) return false;
   hipLaunchKernelGGL(prep_grouped, dim3(total), dim3(256), 0, st, (const PrepArgs*)jobs, start, nj);

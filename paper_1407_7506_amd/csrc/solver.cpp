@@ -75,19 +75,46 @@ struct DBuf {
 
 // ---------------------------------------------------------------------------
 // per-kernel event timing (options.profile)
+
+// MI355X peaks of the per-launch roofline time: HBM and dense MFMA by dtype
+constexpr double PEAK_HBM = 8.0e12, PEAK_F64 = 78.6e12, PEAK_F32 = 157.3e12;
+
+// time categories of the paper's breakdown (section 6, Tables 4-5)
+enum { CAT_GEMM = 0, CAT_AX = 1, CAT_RR = 2, CAT_CHOLQR = 3, CAT_SMALL = 4, CAT_OTHER = 5, NCAT = 6 };
+
 struct Prof {
   bool on = false;
   hipStream_t st = nullptr;
+  int ctx = -1;  // category of launches whose name does not fix one (Cholesky, reductions)
   std::vector<hipEvent_t> pool;
-  struct Rec { int kind; hipEvent_t a, b; };
+  struct Rec { int kind, cat; hipEvent_t a, b; };
   std::vector<Rec> pending;
   std::vector<std::string> names;
   std::map<std::string, int> ids;
   std::vector<double> ms;
   std::vector<long> counts;
   std::vector<double> flops, bytes;
-  struct Open { int kind; hipEvent_t ev; double fl, by; };
+  double cat_ms[NCAT] = {};
+  double roof_ms = 0;  // sum over launches of max(bytes / HBM peak, flops / MFMA peak)
+  struct Open { int kind, cat; hipEvent_t ev; double fl, by; };
   std::vector<Open> open;
+  static int cat_of_name(const char* n) {
+    static const std::map<std::string, int> m = {
+        {"stencil_f64", CAT_AX},     {"stencil_f32", CAT_AX},     {"block_pencil", CAT_SMALL},
+        {"gram_proj", CAT_GEMM},     {"update_proj", CAT_GEMM},   {"gram_block", CAT_GEMM},
+        {"block_update", CAT_GEMM},  {"gram_xax", CAT_GEMM},      {"update_resid", CAT_GEMM},
+        {"gram_rr", CAT_RR},         {"update_small", CAT_RR},    {"gram_small", CAT_RR},
+        {"eig", CAT_RR},             {"update_rot", CAT_RR},      {"ritz_resid", CAT_RR},
+        {"gram_xx", CAT_CHOLQR},     {"update_xr", CAT_CHOLQR}};
+    auto it = m.find(n);
+    return it == m.end() ? -1 : it->second;
+  }
+  // the category a launch named n is charged to
+  int cat_of(const char* n) const {
+    int c = cat_of_name(n);
+    if (c >= 0) return c;
+    return ctx >= 0 ? ctx : CAT_OTHER;
+  }
   hipEvent_t get() {
     if (!pool.empty()) {
       hipEvent_t e = pool.back();
@@ -120,11 +147,13 @@ struct Prof {
     g_rec->pend_fl = fl;
     g_rec->pend_by = by;
   }
-  void begin(const char* n, double fl = 0, double by = 0) {
+  // peak: dense MFMA rate of the launch's dtype (flops / s)
+  void begin(const char* n, double fl = 0, double by = 0, double peak = PEAK_F64, int cat = -1) {
     if (!active()) return;
     hipEvent_t e = get();
     HIPCHECK(hipEventRecord(e, st));
-    open.push_back({id(n), e, fl, by});
+    open.push_back({id(n), cat >= 0 ? cat : cat_of(n), e, fl, by});
+    roof_ms += 1e3 * std::max(by / PEAK_HBM, fl / peak);
   }
   void end() {
     if (!active() || open.empty()) return;
@@ -132,7 +161,7 @@ struct Prof {
     open.pop_back();
     hipEvent_t b = get();
     HIPCHECK(hipEventRecord(b, st));
-    pending.push_back({o.kind, o.ev, b});
+    pending.push_back({o.kind, o.cat, o.ev, b});
     flops[o.kind] += o.fl;
     bytes[o.kind] += o.by;
     if (pending.size() > 4096) collect();
@@ -145,6 +174,7 @@ struct Prof {
       HIPCHECK(hipEventElapsedTime(&t, r.a, r.b));
       ms[r.kind] += t;
       counts[r.kind] += 1;
+      cat_ms[r.cat] += t;
       pool.push_back(r.a);
       pool.push_back(r.b);
     }
@@ -156,6 +186,8 @@ struct Prof {
     std::fill(counts.begin(), counts.end(), 0L);
     std::fill(flops.begin(), flops.end(), 0.0);
     std::fill(bytes.begin(), bytes.end(), 0.0);
+    std::fill(cat_ms, cat_ms + NCAT, 0.0);
+    roof_ms = 0;
   }
   ~Prof() {
     for (auto e : pool) hipEventDestroy(e);
@@ -165,14 +197,23 @@ struct Prof {
 struct Scope {
   Prof& p;
   bool live;
-  Scope(Prof& p_, const char* n, double fl = 0, double by = 0) : p(p_), live(p_.active()) {
-    if (live) p.begin(n, fl, by);
+  Scope(Prof& p_, const char* n, double fl = 0, double by = 0, double peak = PEAK_F64, int cat = -1)
+      : p(p_), live(p_.active()) {
+    if (live) p.begin(n, fl, by, peak, cat);
     else p.note(n, fl, by);
   }
   ~Scope() {
     if (live) p.end();
     else p.note(nullptr, 0, 0);
   }
+};
+
+// charges launches without a category of their own (Cholesky, reductions) to cat
+struct CatCtx {
+  Prof& p;
+  int old;
+  CatCtx(Prof& p_, int cat) : p(p_), old(p_.ctx) { p.ctx = cat; }
+  ~CatCtx() { p.ctx = old; }
 };
 
 // per-problem workspace
@@ -234,9 +275,12 @@ struct ppcg_handle {
   int* hcounter = nullptr;
   EigGraphCache eig_graph;            // captured block-Jacobi sweep
   std::map<TuneKey, TuneChoice> tune; // autotuner decisions (PPCG_AUTOTUNE)
+  std::string tune_path;              // options.tune_table (empty: none)
+  size_t tune_saved = 0;              // entries the file holds
   DBuf tune_scratch;                  // output copy for timing non-idempotent updates
   hipEvent_t tev[2] = {nullptr, nullptr};
   DBuf gZ, gR, gP, gAP, gY, gw, gsc;  // backward-pass work
+  DBuf pen_gram, pen_G, pen_work;     // ppcg_block_pencils inputs in the solver's pencil layout
   // state of the last successful single solve (for ppcg_grad / ppcg_density)
   bool has_state = false;
   bool s_cplx = false;
@@ -295,7 +339,8 @@ struct Prob {
   bool cplx = false;          // complex Hermitian (Bloch phase) operator
   double ph[3][2][2] = {};    // exp(i kappa_d a h), a = 1, 2
   const double* V = nullptr;
-  const double* X0 = nullptr;
+  const double* X0 = nullptr;  // NULL: seeded N(0,1) start block drawn on the device
+  uint64_t seed = 0;
   double* Xout = nullptr;
   double* lamout = nullptr;
   // state
@@ -305,6 +350,7 @@ struct Prob {
   int it = 1;
   bool noconv = false;
   double fresh = INFINITY;
+  int last_kind = 0;  // what the last iteration ended with (ppcg_iter_log.kind)
   std::vector<double> lock_wn, lock_lam;
   ppcg_info info{};
   ppcg_status status = PPCG_OK;
@@ -345,7 +391,7 @@ struct Prob {
   void setup(const ppcg_operator* op, int k_, int q_, double tol_, int rrp, const double* X0_, double* Xout_,
              double* lamout_) {
     t0 = std::chrono::steady_clock::now();
-    if (!op || !op->V || !X0_ || !Xout_ || !lamout_) throw PpcgError{PPCG_EINVAL, "null pointer argument"};
+    if (!op || !op->V || !Xout_ || !lamout_) throw PpcgError{PPCG_EINVAL, "null pointer argument"};
     if (op->order != 2 && op->order != 4) throw PpcgError{PPCG_EINVAL, "order must be 2 or 4"};
     cplx = bloch_phases(op, ph);
     if (op->precond != PPCG_PRECOND_JACOBI) throw PpcgError{PPCG_EINVAL, "only the Jacobi preconditioner"};
@@ -435,7 +481,7 @@ struct Prob {
   void stencil(const void* Xs, void* Ys, int ncols, bool f32) {
     double es = (f32 ? 4 : 8) * nc();
     Scope s(prof, f32 ? "stencil_f32" : "stencil_f64", (order == 4 ? 16.0 : 10.0) * (cplx ? 3 : 1) * n * ncols,
-            2.0 * es * n * ncols + es / nc() * n);
+            2.0 * es * n * ncols + es / nc() * n, f32 ? PEAK_F32 : PEAK_F64);
     StencilArgs a{};
     a.X = Xs;
     a.Y = Ys;
@@ -605,10 +651,10 @@ struct Prob {
       double nn = (double)std::min(rws, n), es_in = (f32acc ? 4.0 : 8.0) * nc();
       double fl = (upper ? (double)M * (M + 1) * nn : 2.0 * M * Nn * nn) * (cplx ? 4 : 1);
       double by = (double)njobs * (upper ? M : (M + Nn)) * nn * es_in;
-      Scope s(prof, name, fl * njobs, by);
+      Scope s(prof, name, fl * njobs, by, f32acc ? PEAK_F32 : PEAK_F64);
       launch_gram(g, f32acc, st);
     }
-    Scope s(prof, "reduce");
+    Scope s(prof, "reduce", 0, 0, PEAK_F64, prof.cat_of(name));
     launch_reduce(r, f32acc, st);
   }
 
@@ -685,7 +731,7 @@ struct Prob {
       Scope sc(prof, "gram_block", fl, by);
       launch_block_gram(b, st);
     }
-    Scope sr(prof, "reduce");
+    Scope sr(prof, "reduce", 0, 0, PEAK_F64, CAT_GEMM);
     launch_reduce(r, false, st);
     return true;
   }
@@ -760,7 +806,7 @@ struct Prob {
     double fl = (b_upper ? (double)Nn * (Nn + 1) * nn : 2.0 * Kk * Nn * nn) * (cplx ? 4 : 1);
     double by = ((double)Kk + Nn * (beta != 0 ? 2.0 : 1.0)) * nn * es + (C32 ? 4.0 * nc() * Nn * nn : 0.0);
     if (c64) by += (8.0 - es + (xd ? 8.0 : 0.0)) * Nn * nn;  // float64 input (and X) instead of C0
-    Scope s(prof, name, fl, by);
+    Scope s(prof, name, fl, by, f32 ? PEAK_F32 : PEAK_F64);
     launch_update(u, f32, st);
   }
 
@@ -876,8 +922,11 @@ struct Prob {
 
   // phase: orthonormal start block and first residual (steps 1-4)
   void enq_init() {
-    HIPCHECK(hipMemcpy2DAsync(X(), (size_t)ld * xs(), X0, (size_t)n * xs(), (size_t)n * xs(), K,
-                              hipMemcpyDeviceToDevice, st));
+    if (X0)
+      HIPCHECK(hipMemcpy2DAsync(X(), (size_t)ld * xs(), X0, (size_t)n * xs(), (size_t)n * xs(), K,
+                                hipMemcpyDeviceToDevice, st));
+    else
+      launch_randn(X(), ld, n, K, seed, cplx, st);
     nl = 0;
     hasP = false;
     it = 1;
@@ -888,6 +937,7 @@ struct Prob {
 
   // X (active columns) <- X R^{-1}; result lands in Xt then X/Xt swap
   void enq_cholqr(int m) {
+    CatCtx cc(prof, CAT_CHOLQR);
     double* Xa = xc(X(), nl);
     {
       ColSet A = cols1(Xa, m, false);
@@ -945,6 +995,19 @@ struct Prob {
     launch_d2h(Wk.hpin + 4 * Kp + 8, Wk.iflag.p, 4, st);
   }
 
+  // per-iteration record for options.log_cb
+  void log(double rho) const {
+    if (!H->opt.log_cb) return;
+    ppcg_iter_log rec{};
+    rec.iter = it - 1;
+    rec.n_locked = nl;
+    rec.n_active = K - nl;
+    rec.kind = last_kind;
+    rec.rho = rho;
+    rec.time_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    H->opt.log_cb(&rec, H->opt.log_user);
+  }
+
   // rho of the loop head from the last residual (cn, scal) and the locked parts
   double post_rho() {
     int nwa = std::max(0, k - nl);
@@ -964,6 +1027,7 @@ struct Prob {
   // Rayleigh-Ritz over all K columns (S = [X_lock, X_act]), part 1: the
   // reduced matrix Mr = L^{-1} S^H H S L^{-H} with S^H S = L L^H.
   void enq_rr1() {
+    CatCtx cc(prof, CAT_RR);
     double* S = X();
     double* AS = mixed ? Wk.AXm.d() : Wk.AW.d();
     stencil(S, AS, K, false);
@@ -987,6 +1051,7 @@ struct Prob {
 
   // part 2: C = L^{-H} Y, X <- S C, fresh W = H X - X Lambda (all columns)
   void enq_rr2() {
+    CatCtx cc(prof, CAT_RR);
     double* S = X();
     update(Wk.Rinv.p, Kp, K, Wk.Yv.p, Kp, K, Wk.Cc.p, nullptr, K, Kp, nullptr, nullptr, Kp, 1.0, 0.0, false, false,
            "update_small");
@@ -1028,7 +1093,10 @@ struct Prob {
     int nlnew = 0;
     while (nlnew < k && std::sqrt(wn2[nlnew]) <= thr) ++nlnew;
     nlnew = nlnew / q * q;
-    if (hasP && nlnew < nl) hasP = false;  // P(J_act) undefined when the locked set shrinks
+    if (hasP && nlnew < nl) {  // P(J_act) undefined when the locked set shrinks
+      hasP = false;
+      info.n_unlock++;
+    }
     nl = nlnew;
     lock_wn.assign(nl, 0.0);
     lock_lam.assign(nl, 0.0);
@@ -1042,6 +1110,7 @@ struct Prob {
 
   // part 3: active G = diag(Lambda_act) and the residual bookkeeping for rho
   void enq_rr3() {
+    CatCtx cc(prof, CAT_RR);
     int m = K - nl;
     // the locked prefix of X, unchanged until the next Rayleigh-Ritz, into the other buffer
     launch_copy(X(), Xt(), (long)nl * ld * nc(), st);
@@ -1133,6 +1202,7 @@ struct Prob {
       pa.flags = Wk.bflags.i();
       pa.drop_tol = 1e-14;
       pa.pivot_tol = 1e-12;
+      pa.sing_tol = H->opt.singular_tol;
       pa.jacobi_rel = pencil_rel_tol();
       pa.nblocks = s;
       pa.cplx = cplx;
@@ -1155,8 +1225,9 @@ struct Prob {
       bu.cstride = 3L * q * q;
       bu.nblocks = s;
       bu.cplx = cplx;
+      // reads X, W (and P), writes X and P: X at its float64 size in both modes
       Scope sc(prof, "block_update", 6.0 * (cplx ? 4 : 1) * (double)n * q * q * s * (hasP ? 1.0 : 2.0 / 3.0),
-               (double)n * q * s * (hasP ? 5.0 : 4.0) * (double)esz());
+               (double)n * q * s * (2.0 * xs() + (hasP ? 3.0 : 2.0) * esz()), mixed ? PEAK_F32 : PEAK_F64);
       launch_block_update(bu, st);
     }
     launch_d2h(Wk.hpin, Wk.bflags.p, (size_t)s * 4, st);
@@ -1166,6 +1237,7 @@ struct Prob {
     for (int j = 0; j < s; ++j) {
       if (Wk.hpin[j] & 4) throw PpcgError{PPCG_ERANK, "sub-block pencil has rank below sbsize"};
       if (Wk.hpin[j] & 2) info.n_backtrack++;
+      info.n_dropped += Wk.hpin[j] >> 8;
     }
     hasP = true;
   }
@@ -1377,6 +1449,7 @@ struct Driver {
       std::vector<Prob*> fin, body, done, again;
       post(act, [&](Prob& p) {
         double r = p.post_rho();
+        p.log(r);
         if (r <= p.tol) fin.push_back(&p);
         else if (p.it > p.max_iter) {
           p.noconv = true;
@@ -1392,7 +1465,10 @@ struct Driver {
             p->status = PPCG_ENOCONV;
             p->err = "max_iter reached";
             done.push_back(p);
-          } else again.push_back(p);
+          } else {
+            p->last_kind = 3;
+            again.push_back(p);
+          }
         }
         phase(again, [](Prob& p) { p.enq_rr3(); });
       }
@@ -1401,7 +1477,10 @@ struct Driver {
         sync(H);
         post(body, [](Prob& p) { p.post_body1(); });
         std::vector<Prob*> cq, rr;
-        for (Prob* p : body) (p->it % p->rr_period != 0 ? cq : rr).push_back(p);
+        for (Prob* p : body) {
+          p->last_kind = p->it % p->rr_period != 0 ? 1 : 2;
+          (p->it % p->rr_period != 0 ? cq : rr).push_back(p);
+        }
         phase(cq, [](Prob& p) { p.enq_cq(); });
         if (!rr.empty()) {
           rayleigh_ritz(rr);
@@ -1435,6 +1514,7 @@ struct Grad {
   Prof& prof;
   int k = 0;
   long n = 0, rows = 0, ld = 0;
+  double resid = 0;  // largest |r_i| / |b_i| over the columns at exit
   Grad(ppcg_handle* h) : H(h), st(h->st), prof(h->prof) {}
 
   // Y <- (I - X X^H) Y over the k saved eigenvectors
@@ -1541,11 +1621,64 @@ struct Grad {
       launch_cg_p(P, Y, beta, ld, rows, k, st);
     }
     launch_grad_rows(Wk.X.d(), Z, g, ld, n, k, out, st);
+    HIPCHECK(hipMemcpyAsync(Wk.hpind, rr, (size_t)k * 8, hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipMemcpyAsync(Wk.hpind + k, bb, (size_t)k * 8, hipMemcpyDeviceToHost, st));
     sync(H);
+    resid = 0;
+    for (int j = 0; j < k; ++j) {
+      const double b2 = Wk.hpind[k + j];
+      if (b2 > 0) resid = std::max(resid, std::sqrt(Wk.hpind[j] / b2));
+    }
     prof.collect();
     return it;
   }
 };
+
+// Autotuner table file: one decision per line,
+//   kind site f32 cplx multi upper mb nb rb lds target floor_rows ms
+// ('#' starts a comment line).
+void load_tune_table(ppcg_handle* H) {
+  FILE* f = fopen(H->tune_path.c_str(), "r");
+  if (!f) return;  // no table yet: the first tuned solve writes it
+  char line[512];
+  int ln = 0;
+  while (fgets(line, sizeof line, f)) {
+    ++ln;
+    if (line[0] == '#' || line[0] == '\n') continue;
+    TuneKey k{};
+    TuneChoice c;
+    long rb = 0;
+    int n = sscanf(line, "%d %d %d %d %d %d %d %d %ld %d %d %d %lf", &k.kind, &k.site, &k.f32, &k.cplx, &k.multi,
+                   &k.upper, &k.mb, &k.nb, &rb, &c.lds, &c.target, &c.floor_rows, &c.ms);
+    k.rb = rb;
+    if (n != 13 || k.kind < 0 || k.kind > 2 || c.lds < 0 || c.lds > 3 || c.target <= 0 || c.floor_rows <= 0) {
+      fclose(f);
+      throw PpcgError{PPCG_EINVAL, "tune table " + H->tune_path + ": malformed line " + std::to_string(ln)};
+    }
+    c.tried = "(from table)";
+    H->tune[k] = c;
+  }
+  fclose(f);
+  H->tune_saved = H->tune.size();
+}
+
+void save_tune_table(ppcg_handle* H) {
+  if (H->tune_path.empty() || H->tune.size() == H->tune_saved) return;
+  std::string tmp = H->tune_path + ".tmp";
+  FILE* f = fopen(tmp.c_str(), "w");
+  if (!f) throw PpcgError{PPCG_EINVAL, "cannot write tune table " + tmp};
+  fprintf(f, "# libppcg autotuner decisions: kind site f32 cplx multi upper mb nb rb lds target floor_rows ms\n");
+  for (const auto& kv : H->tune) {
+    const TuneKey& k = kv.first;
+    const TuneChoice& c = kv.second;
+    fprintf(f, "%d %d %d %d %d %d %d %d %ld %d %d %d %.6f\n", k.kind, k.site, k.f32, k.cplx, k.multi, k.upper, k.mb,
+            k.nb, k.rb, c.lds, c.target, c.floor_rows, c.ms);
+  }
+  bool ok = fclose(f) == 0;
+  if (!ok || rename(tmp.c_str(), H->tune_path.c_str()) != 0)
+    throw PpcgError{PPCG_EINVAL, "cannot write tune table " + H->tune_path};
+  H->tune_saved = H->tune.size();
+}
 
 ppcg_status guard(ppcg_handle* h, const std::function<ppcg_status()>& f) {
   try {
@@ -1585,8 +1718,19 @@ ppcg_status ppcg_create(ppcg_handle** out, const ppcg_options* opt, void* stream
     delete h;
     return PPCG_EINVAL;
   }
+  if (!(h->opt.singular_tol > 0)) h->opt.singular_tol = 1e-12;
+  if (h->opt.tune_table) h->tune_path = h->opt.tune_table;
+  h->opt.tune_table = nullptr;  // the handle keeps its own copy of the path
   h->prof.on = h->opt.profile != 0;
   h->prof.st = h->st;
+  if (!h->tune_path.empty()) {
+    try {
+      load_tune_table(h);
+    } catch (const PpcgError& e) {
+      delete h;
+      return e.code;
+    }
+  }
   *out = h;
   return PPCG_OK;
 }
@@ -1597,14 +1741,26 @@ ppcg_status ppcg_solve(ppcg_handle* h, const ppcg_operator* op, int32_t k, int32
   return guard(h, [&]() {
     h->has_state = false;
     Prob p(h, h->work(0));
+    h->prof.collect();
+    double cat0[NCAT], roof0 = h->prof.roof_ms;
+    std::copy(h->prof.cat_ms, h->prof.cat_ms + NCAT, cat0);
+    auto stages = [&]() {
+      if (!h->prof.on) return;
+      h->prof.collect();
+      for (int c = 0; c < NCAT; ++c) p.info.stage_ms[c] = h->prof.cat_ms[c] - cat0[c];
+      p.info.roofline_ms = h->prof.roof_ms - roof0;
+    };
     try {
       p.setup(op, k, sbsize, tol, rr_period, X0, X_out, lambda_out);
+      p.seed = h->opt.seed;
       Driver d(h, false);
       d.run({&p});
+      stages();
     } catch (...) {
       if (info) *info = p.info;
       throw;
     }
+    save_tune_table(h);
     if (info) *info = p.info;
     if (p.status != PPCG_OK) {
       h->err = p.err;
@@ -1630,7 +1786,7 @@ ppcg_status ppcg_solve_batched(ppcg_handle* h, int32_t nprob, const ppcg_operato
                                int32_t sbsize, double tol, int32_t rr_period, const double* const* X0,
                                double* const* X_out, double* const* lambda_out, ppcg_info* infos,
                                int32_t* statuses) {
-  if (!h || nprob < 0 || (nprob > 0 && (!ops || !k || !X0 || !X_out || !lambda_out))) return PPCG_EINVAL;
+  if (!h || nprob < 0 || (nprob > 0 && (!ops || !k || !X_out || !lambda_out))) return PPCG_EINVAL;
   return guard(h, [&]() {
     h->has_state = false;
     std::vector<std::unique_ptr<Prob>> ps;
@@ -1639,7 +1795,8 @@ ppcg_status ppcg_solve_batched(ppcg_handle* h, int32_t nprob, const ppcg_operato
     for (int b = 0; b < nprob; ++b) {
       ps.emplace_back(new Prob(h, h->work(b)));
       try {
-        ps[b]->setup(&ops[b], k[b], sbsize, tol, rr_period, X0[b], X_out[b], lambda_out[b]);
+        ps[b]->setup(&ops[b], k[b], sbsize, tol, rr_period, X0 ? X0[b] : nullptr, X_out[b], lambda_out[b]);
+        ps[b]->seed = h->opt.seed + (uint64_t)b;
         if (!run.empty() && ps[b]->cplx != run[0]->cplx)
           throw PpcgError{PPCG_EINVAL, "a batch cannot mix real and complex (Bloch) operators"};
         run.push_back(ps[b].get());
@@ -1663,12 +1820,17 @@ ppcg_status ppcg_solve_batched(ppcg_handle* h, int32_t nprob, const ppcg_operato
 }
 
 ppcg_status ppcg_grad(ppcg_handle* h, const double* g_lambda, const double* w, double* dL_dV, double tol,
-                      int32_t max_iter, int32_t* iters) {
+                      int32_t max_iter, int32_t* iters, double* resid) {
   if (!h) return PPCG_EINVAL;
   return guard(h, [&]() {
     Grad g(h);
     int it = g.run(g_lambda, w, dL_dV, tol, max_iter > 0 ? max_iter : 10000);
     if (iters) *iters = it;
+    if (resid) *resid = g.resid;
+    if (g.resid > tol) {
+      h->err = "Sternheimer block CG stopped at max_iter with relative residual " + std::to_string(g.resid);
+      return PPCG_ENOCONV;
+    }
     return PPCG_OK;
   });
 }
@@ -1699,6 +1861,7 @@ ppcg_status ppcg_apply_h(ppcg_handle* h, const ppcg_operator* op, int32_t ncols,
   if (!h || !op || !op->V || !X || !Y || ncols < 0) return PPCG_EINVAL;
   return guard(h, [&]() {
     if (op->order != 2 && op->order != 4) throw PpcgError{PPCG_EINVAL, "order must be 2 or 4"};
+    if (op->nx < 4 || !(op->h > 0)) throw PpcgError{PPCG_EINVAL, "bad grid: need nx >= 4 and h > 0"};
     double ih2 = 1.0 / (op->h * op->h);
     long n = (long)op->nx * op->nx * op->nx;
     StencilArgs a{};
@@ -1717,6 +1880,59 @@ ppcg_status ppcg_apply_h(ppcg_handle* h, const ppcg_operator* op, int32_t ncols,
     {
       Scope sc(h->prof, "stencil_f64");
       launch_stencil(a, h->st);
+    }
+    HIPCHECK(hipGetLastError());
+    sync(h);
+    return PPCG_OK;
+  });
+}
+
+ppcg_status ppcg_block_pencils(ppcg_handle* h, int32_t nblocks, int32_t q, int32_t has_p, int32_t cplx,
+                               const double* A, const double* B, double tol, double* C, int32_t* flags) {
+  if (!h || nblocks < 0 || q < 1 || q > 32 || !(tol > 0) || (nblocks > 0 && (!A || !B || !C || !flags)))
+    return PPCG_EINVAL;
+  return guard(h, [&]() {
+    if (nblocks == 0) return PPCG_OK;
+    const int nS = has_p ? 3 * q : 2 * q, Nb = 2 * nS - q;
+    const size_t es = cplx ? 16 : 8;
+    // the solver's layout: per block an nS x Nb Gram (ld nS) holding S^H S in
+    // columns [0, nS) and S^H [H W, H P] in [nS, Nb); the X block S^H H S
+    // comes from G at rows and columns [j q, j q + q) -- here each q x q X
+    // block sits at offset j q (q + 1) with leading dimension q, which is
+    // that addressing with ldg = q
+    h->pen_gram.ensure((size_t)nblocks * nS * Nb * es);
+    h->pen_G.ensure((size_t)nblocks * q * (q + 1) * es);
+    if (nS > 48) h->pen_work.ensure((size_t)nblocks * pencil_work_elems() * es);
+    const size_t mat = (size_t)nS * nS * es;
+    for (int j = 0; j < nblocks; ++j) {
+      char* gj = (char*)h->pen_gram.p + (size_t)j * nS * Nb * es;
+      const char* Aj = (const char*)A + j * mat;
+      HIPCHECK(hipMemcpyAsync(gj, (const char*)B + j * mat, mat, hipMemcpyDeviceToDevice, h->st));
+      HIPCHECK(hipMemcpyAsync(gj + mat, Aj + (size_t)q * nS * es, (size_t)(nS - q) * nS * es,
+                              hipMemcpyDeviceToDevice, h->st));
+      HIPCHECK(hipMemcpy2DAsync((char*)h->pen_G.p + (size_t)j * q * (q + 1) * es, (size_t)q * es, Aj,
+                                (size_t)nS * es, (size_t)q * es, q, hipMemcpyDeviceToDevice, h->st));
+    }
+    PencilArgs pa{};
+    pa.gram = h->pen_gram.d();
+    pa.gstride = (long)nS * Nb;
+    pa.G = h->pen_G.d();
+    pa.ldg = q;
+    pa.q = q;
+    pa.nS = nS;
+    pa.C = C;
+    pa.cstride = 3L * q * q;
+    pa.flags = flags;
+    pa.drop_tol = 1e-14;
+    pa.pivot_tol = 1e-12;
+    pa.sing_tol = h->opt.singular_tol;
+    pa.jacobi_rel = std::max(2.2e-16, std::min(1e-10, 1e-4 * tol));
+    pa.nblocks = nblocks;
+    pa.cplx = cplx ? 1 : 0;
+    pa.work = nS > 48 ? h->pen_work.p : nullptr;
+    {
+      Scope sc(h->prof, "block_pencil");
+      launch_block_pencil(pa, h->st);
     }
     HIPCHECK(hipGetLastError());
     sync(h);

@@ -103,14 +103,14 @@ def test_traffic_reduction(tmp_path):
     _fake_db(fdb, "FETCH_SIZE", fetch)
     _fake_db(wdb, "WRITE_SIZE", write)
     out = str(tmp_path / "traffic.json")
-    bench.write_traffic(fdb, wdb, {"gram_proj": 2}, path=out)
+    bench.write_traffic(fdb, wdb, {"gram_proj": 2}, "mixed", path=out)
     d = json.load(open(out))
     g = d["kernels"]["gram_proj"]
     assert g["launches"] == 2
     assert g["fetch_bytes_per_launch"] == pytest.approx(2 * 1024 * (100 + 300) / 2, rel=1e-6)
     assert g["write_bytes_per_launch"] == pytest.approx(1024 * (10 + 30) / 2, rel=1e-6)
     assert d["calibration"]["FETCH_SIZE"]["factor"] == pytest.approx(2.0)
-    assert d["source_sha"] == bench.kernel_source_sha()
+    assert d["source_sha"] == bench.kernel_source_sha() and d["precision"] == "mixed"
 
 
 def test_traffic_kernel_symbols():
@@ -127,3 +127,25 @@ def test_traffic_kernel_symbols():
     up = bench.TRAFFIC_KERNELS["update_proj"]
     assert m("void ppcg::update_lds_kernel<float, 16, 1>(ppcg::UpdateArgs)", *up)
     assert not m("void ppcg::update_lds_kernel<double, 32, 0>(ppcg::UpdateArgs)", *up)
+
+
+def test_traffic_is_keyed_by_precision(tmp_path, monkeypatch):
+    """A counter summary taken on one precision never answers for the other."""
+    monkeypatch.setattr(bench, "traffic_path", lambda prec: str(tmp_path / f"t_{prec}.json"))
+    d = {"source_sha": bench.kernel_source_sha(), "precision": "mixed",
+         "kernels": {"update_proj": {"hbm_bytes_per_launch": 7.0e8}}}
+    json.dump(d, open(tmp_path / "t_mixed.json", "w"))
+    assert bench.traffic_for("update_proj", "mixed") == 7.0e8
+    assert bench.traffic_for("update_proj", "fp64") is None
+    json.dump(dict(d, precision="mixed"), open(tmp_path / "t_fp64.json", "w"))
+    assert bench.traffic_for("update_proj", "fp64") is None
+
+
+def test_hbm_rates_and_solve_roofline():
+    kt = {"stencil_f64": (10.0, 10, 1e9, 4e10), "gram_proj": (10.0, 10, 1e12, 1e9)}
+    r = bench.hbm_rates(kt, "mixed")
+    assert list(r) == ["stencil_f64"]                      # the Gram is MFMA-bound by intensity
+    assert r["stencil_f64"]["algorithmic_GBps"] == pytest.approx(4000.0)
+    sr = bench.solve_roofline({"roofline_ms": 50.0, "time_s": 0.2})
+    assert sr["frac"] == pytest.approx(0.25)
+    assert bench.stage_ms({"stage_ms": [1, 2, 3, 4, 5, 6]})["cholqr"] == 4
