@@ -353,6 +353,68 @@ def bench_bloch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_scf(args):
+    """The SCF-style sequence on the 48^3 workload's operator family (section
+    6 of the paper): 15 potentials V_s = V + 0.5 * 0.7^s * dV; the first is
+    solved to tol 1e-6, each of the 14 others gets two PPCG iterations without
+    Cholesky-QR, warm-started from the previous step's 528 Ritz vectors.
+    Timed: the 14 warm steps (inputs in HBM).  Reported beside them: the cold
+    first solve, and a full solve of the last potential for the eigenvalue
+    error of the last step."""
+    import numpy as np
+    import torch
+    from paper_1407_7506_amd import binding as B
+    from paper_1407_7506_amd import inputs as I
+
+    p = I.wells48()
+    g = p.grid
+    Vs = [torch.tensor(V, device="cuda") for V in I.scf_potentials(p, steps=14, amp=0.5, decay=0.7)]
+    X0 = torch.tensor(p.start(), device="cuda")
+    out = {}
+    for prec in (["mixed", "fp64"] if args.only == "both" else [args.only]):
+        first = B.Handle(prec, return_buffers=True, autotune=not args.no_autotune, profile=True)
+        step = B.Handle(prec, max_iter=2, orth="none", return_buffers=True, autotune=not args.no_autotune,
+                        profile=True)
+        t0 = time.perf_counter()
+        lam, X, info0 = first.solve(Vs[0], g.N, p.k, p.q, p.tol, p.rr_period, X0, h=g.h, order=g.order)
+        torch.cuda.synchronize()
+        t_first = time.perf_counter() - t0
+        # warmup of the step handle (autotuner), on the first potential
+        step.solve(Vs[0], g.N, p.k, p.q, p.tol, p.rr_period, X, h=g.h, order=g.order, check=False)
+        torch.cuda.synchronize()
+        step.reset_kernel_times()
+        t0 = time.perf_counter()
+        infos = []
+        for V in Vs[1:]:
+            lam, X, info = step.solve(V, g.N, p.k, p.q, p.tol, p.rr_period, X, h=g.h, order=g.order, check=False)
+            infos.append(info)
+        torch.cuda.synchronize()
+        t_steps = time.perf_counter() - t0
+        ref, _, rinfo = first.solve(Vs[-1], g.N, p.k, p.q, p.tol, p.rr_period, X0, h=g.h, order=g.order)
+        lk, rk = lam[:p.k].cpu().numpy(), ref[:p.k].cpu().numpy()
+        err = float(np.abs(lk - rk).max() / np.abs(rk).max())
+        stages = np.sum([i["stage_ms"] for i in infos], axis=0)
+        log(f"{prec}: first solve {t_first:.3f} s ({info0['iters']} iters); 14 warm steps {t_steps:.3f} s "
+            f"({t_steps / 14 * 1e3:.1f} ms/step); last-step eigenvalue error {err:.2e}")
+        out[prec] = {"steps_s": round(t_steps, 4), "ms_per_step": round(t_steps / 14 * 1e3, 2),
+                     "first_solve_s": round(t_first, 3), "first_iters": info0["iters"],
+                     "last_step_err_vs_full_solve": err, "last_step_rho_status": infos[-1]["status"],
+                     "cholqr_in_steps": int(sum(i["n_cholqr"] for i in infos)),
+                     "stage_ms_steps": {k: round(v, 2) for k, v in zip(STAGES, stages)}}
+        first.close()
+        step.close()
+    main_prec = "mixed" if "mixed" in out else "fp64"
+    r = out[main_prec]
+    line = {"metric": METRIC, "value": r["steps_s"], "unit": "s", "n_gpus": 1, "steps": 14, "warmup": 1,
+            "ms_per_step": r["ms_per_step"], "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32+f64 (mixed)" if main_prec == "mixed" else "f64", "data": "synthetic",
+            "config": {"workload": "scf48: 15 potentials V_s = V_wells48 + 0.5*0.7^s*dV (dV smoothed field seed 106); "
+                                   "first solved to tol 1e-6, then 14 warm-started steps of 2 PPCG iterations "
+                                   "without Cholesky-QR (k=512, sbsize=16, K=528)", "precision": main_prec},
+            "results": out, "cpu_baseline": None}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -363,7 +425,7 @@ def main():
     ap.add_argument("--only", choices=["both", "fp64", "mixed"], default="both")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain device copy of 1 GiB (counter calibration under rocprofv3)")
-    ap.add_argument("--workload", choices=["wells48", "batch64", "bloch96"], default="wells48")
+    ap.add_argument("--workload", choices=["wells48", "batch64", "bloch96", "scf48"], default="wells48")
     ap.add_argument("--no-autotune", action="store_true",
                     help="fixed kernel plans instead of the autotuner's (tuning happens in the warmup solve)")
     ap.add_argument("--nprob", type=int, default=64, help="problems of the batch64 workload")
@@ -386,6 +448,8 @@ def main():
         return bench_batch(args)
     if args.workload == "bloch96":
         return bench_bloch(args)
+    if args.workload == "scf48":
+        return bench_scf(args)
 
     import numpy as np
     import torch

@@ -58,6 +58,25 @@ typedef enum {
 } ppcg_status;
 
 typedef enum { PPCG_FP64 = 0, PPCG_MIXED = 1 } ppcg_precision;
+/* Orthonormalisation of the updated block in iterations without a
+ * Rayleigh-Ritz step (steps 17-19 of Algorithm 3; section 5.5), decided from
+ * e = |Xbar^H Xbar - I|_F over the active columns. */
+typedef enum {
+  PPCG_ORTH_CHOLQR = 0, /* Cholesky-QR every such iteration */
+  PPCG_ORTH_SKIP = 1,   /* omit steps 18-19 while e <= orth_skip, else Cholesky-QR */
+  PPCG_ORTH_TAYLOR = 2, /* omit while e <= orth_skip; X <- X (I - Y/2 + 3Y^2/8 - 5Y^3/16),
+                           Y = Xbar^H Xbar - I (four Taylor terms of the polar factor)
+                           while e <= orth_taylor; else Cholesky-QR */
+  PPCG_ORTH_NONE = 3    /* always omit steps 18-19 (the SCF use of section 6) */
+} ppcg_orth;
+/* Stopping test (section 5.2). */
+typedef enum {
+  PPCG_STOP_RESIDUAL = 0, /* relative subspace residual <= tol, then the final
+                             Rayleigh-Ritz must pass a fresh residual check */
+  PPCG_STOP_TRACE = 1     /* |trace(X^H H X) - previous| <= tol |trace(X^H H X)| between
+                             consecutive iterations (all K columns), then the final
+                             Rayleigh-Ritz (its residual is reported, not required) */
+} ppcg_stop;
 typedef enum { PPCG_PRECOND_NONE = 0, PPCG_PRECOND_JACOBI = 1 } ppcg_precond;
 
 /* One record per PPCG iteration, passed to options.log_cb at the loop head
@@ -71,6 +90,11 @@ typedef struct {
                            Rayleigh-Ritz that failed the fresh residual check */
   double rho;           /* relative subspace residual of the k wanted columns */
   double time_s;        /* wall time since the call started */
+  double orth_err;      /* |Xbar^H Xbar - I|_F of the active block before the last
+                           iteration's orthonormalisation (section 5.5); -1 when
+                           not measured (Rayleigh-Ritz iterations, PPCG_ORTH_NONE) */
+  double trace;         /* trace(X^H H X) over all K columns (locked ones from the
+                           last Rayleigh-Ritz): the quantity PPCG minimises */
 } ppcg_iter_log;
 typedef void (*ppcg_log_fn)(const ppcg_iter_log* rec, void* user);
 
@@ -104,6 +128,14 @@ typedef struct {
                          new shape class; NULL = decisions live in the handle only */
   ppcg_log_fn log_cb; /* per-iteration record (ppcg_iter_log); NULL = none */
   void* log_user;     /* passed back to log_cb */
+  int32_t orth;       /* ppcg_orth (default PPCG_ORTH_CHOLQR) */
+  int32_t stop;       /* ppcg_stop (default PPCG_STOP_RESIDUAL) */
+  int32_t rr_max;     /* dynamic Rayleigh-Ritz period (section 5.6): the first
+                         Rayleigh-Ritz after rr_max iterations, each following
+                         interval one iteration shorter, down to rr_period;
+                         <= rr_period: fixed period rr_period */
+  double orth_skip;   /* PPCG_ORTH_SKIP / _TAYLOR threshold on e; <= 0: 0.1 */
+  double orth_taylor; /* PPCG_ORTH_TAYLOR threshold on e (< 1); <= 0: 0.3 */
 } ppcg_options;
 
 typedef enum {
@@ -114,7 +146,13 @@ typedef enum {
                          splits of each new shape class once on the handle and
                          keep the fastest (see ppcg_tune_report); results stay
                          within rounding of the untuned choice, and after the
-                         first solve of a shape class repeat exactly */
+                         first solve of a shape class repeat exactly */,
+  PPCG_RETURN_BUFFERS = 4 /* X_out receives all K = k + nbuf columns (n x K) and
+                         lambda_out all K Ritz values of the final
+                         Rayleigh-Ritz, buffer vectors included: the start
+                         block of a warm-started next solve (a sequence of
+                         slowly changing operators, as in the SCF use of
+                         section 6) */
 } ppcg_flags;
 
 typedef struct {
@@ -154,6 +192,9 @@ typedef struct {
                            dependent (summed over iterations and blocks) */
   int32_t n_unlock;     /* Rayleigh-Ritz steps at which the locked prefix shrank
                            (P is then reset: P(J_act) is undefined) */
+  int32_t n_cholqr;     /* iterations without Rayleigh-Ritz that ran Cholesky-QR, */
+  int32_t n_taylor;     /* ... the Taylor polar step, */
+  int32_t n_orth_skip;  /* ... and neither (steps 18-19 omitted) */
   double roofline_ms;   /* options.profile set: sum over the modelled launches of
                            max(bytes / 8 TB/s, flops / dense MFMA peak of the
                            launch's dtype: 78.6 TFLOP/s float64, 157.3 float32),
@@ -179,8 +220,8 @@ ppcg_status ppcg_create(ppcg_handle** out, const ppcg_options* opt, void* stream
  *             (complex when op->kpt != 0); NULL draws a seeded N(0,1) block on
  *             the device (options.seed)
  *   X_out     device, n x k (ld n): eigenvectors, orthonormal (complex when
- *             op->kpt != 0)
- *   lambda_out device, k: eigenvalues ascending
+ *             op->kpt != 0); n x K with PPCG_RETURN_BUFFERS
+ *   lambda_out device, k: eigenvalues ascending (K with PPCG_RETURN_BUFFERS)
  *   info      may be NULL
  * On PPCG_ENOCONV the outputs hold the last Rayleigh-Ritz pairs. */
 ppcg_status ppcg_solve(ppcg_handle* h, const ppcg_operator* op, int32_t k, int32_t sbsize, double tol,

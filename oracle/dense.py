@@ -2,6 +2,7 @@
 
   sym            Hermitian part (M + M^H)/2 of a computed Gram
   cholqr         Cholesky-QR: X^H X = R^H R, X <- X R^{-1} (section 5.5)
+  polar_taylor   X (X^H X)^{-1/2} by four Taylor terms (section 5.5)
   block_pencil   the 3q x 3q (2q x 2q without P) projected problem of the block
                  update (section 5.1, with the projected problem of section 2);
                  C^H B C = I, the q lowest
@@ -134,6 +135,18 @@ def block_pencil(A: np.ndarray, B: np.ndarray, nx: int, has_p: bool, _allow_back
             return PencilResult(r.C, r.theta, False, True, r.dropped)
     nfull = (3 if has_p else 2) * nx
     return PencilResult(C, theta[:nx], used_p, False, nfull - len(acc))
+
+
+def polar_taylor(X: np.ndarray, G: np.ndarray) -> np.ndarray:
+    """Nearly orthonormal X -> X (X^H X)^{-1/2}, the orthonormal factor of its
+    polar decomposition, with (I + Y)^{-1/2} replaced by the first four terms
+    of the Taylor series of (1 + y)^{-1/2}: I - Y/2 + 3 Y^2/8 - 5 Y^3/16,
+    Y = G - I, G = sym(X^H X) (section 5.5).  The truncation error in the
+    spectral norm is at most (35/128) |Y|^4 / (1 - |Y|) for |Y| < 1."""
+    Y = sym(G) - np.eye(G.shape[0])
+    Y2 = Y @ Y
+    T = np.eye(G.shape[0]) - 0.5 * Y + 0.375 * Y2 - 0.3125 * (Y2 @ Y)
+    return X @ T
 
 
 def rayleigh_ritz(S: np.ndarray, AS: np.ndarray):

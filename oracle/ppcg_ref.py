@@ -55,21 +55,54 @@ class Info:
     n_p_dropped: int = 0      # sub-blocks whose P columns were all dropped as dependent
     n_dropped: int = 0        # W/P columns left out of sub-block pencils (zero or dependent)
     n_unlock: int = 0         # Rayleigh-Ritz steps at which the locked set shrank (P reset)
+    n_cholqr: int = 0         # non-RR iterations orthonormalised by Cholesky-QR
+    n_taylor: int = 0         # ... by the Taylor polar step
+    n_orth_skip: int = 0      # ... left as they were (steps 18-19 omitted)
+    rr_iters: list = dataclasses.field(default_factory=list)   # iterations that ended with a Rayleigh-Ritz
+    trace: float = math.nan   # trace of X^H A X over all K columns at the last loop head
 
 
 def _fro2(M):
     return float(np.vdot(M, M).real) if M.size else 0.0
 
 
+ORTH = ("cholqr", "skip", "taylor", "none")
+
+
+def rr_schedule(rr_period, rr_max):
+    """Iterations that end with a Rayleigh-Ritz step.  Fixed (rr_max <= rr_period):
+    every rr_period-th iteration.  Dynamic (section 5.6: few Rayleigh-Ritz
+    steps early, more once pairs converge and can be locked): the first after
+    rr_max iterations, each following interval one shorter, down to rr_period."""
+    it, gap = 0, max(rr_max, rr_period)
+    while True:
+        it += gap
+        yield it
+        gap = max(rr_period, gap - 1)
+
+
 def ppcg(apply_a, tdiag, X0, k, sbsize, tol, rr_period, max_iter=20000, record=False,
-         singular_tol=dense.PIVOT_TOL):
+         singular_tol=dense.PIVOT_TOL, orth="cholqr", orth_skip=0.1, orth_taylor=0.3, rr_max=0,
+         stop="residual"):
     """Lowest k eigenpairs of the Hermitian operator ``apply_a`` (n x m -> n x m).
 
     tdiag : (n,) diagonal of the preconditioner T (Jacobi: 1/diag(H)), must be > 0.
     X0    : (n, K) start block, K = k + nbuf columns (buffer vectors included).
-    singular_tol : relative pivot floor of the Theorem 1 test on C_X (a block
-            whose C_X^H C_X has a smaller Cholesky pivot is solved again
-            without P).
+    singular_tol : floor of the Theorem 1 test on C_X (a block whose
+            C_X^H C_X has a smaller Cholesky pivot is solved again without P).
+    orth  : orthonormalisation of the updated block in iterations without a
+            Rayleigh-Ritz step (steps 17-19; section 5.5), decided from
+            e = |Xbar^H Xbar - I|_F over the active columns:
+            "cholqr" always Cholesky-QR; "skip" omit steps 18-19 while
+            e <= orth_skip, else Cholesky-QR; "taylor" omit while e <= orth_skip,
+            the four-term Taylor polar step while e <= orth_taylor, else
+            Cholesky-QR; "none" always omit them (the SCF use of section 6).
+    rr_max : dynamic Rayleigh-Ritz period (see rr_schedule); 0 = fixed.
+    stop  : "residual" -- relative subspace residual <= tol and the fresh
+            residual check after the final Rayleigh-Ritz (section 5.2);
+            "trace" -- relative change of trace(X^H A X) (all K columns)
+            between consecutive loop heads below tol, then the final
+            Rayleigh-Ritz without the fresh check (section 5.2).
     Returns (lam[:k] ascending, X[:, :k], Info).  Raises RankError on a
     Cholesky breakdown and NoConvergence after max_iter iterations.
     """
@@ -80,6 +113,11 @@ def ppcg(apply_a, tdiag, X0, k, sbsize, tol, rr_period, max_iter=20000, record=F
     tdiag = np.asarray(tdiag, dtype=np.float64)
     if np.any(~(tdiag > 0)):
         raise ValueError("preconditioner is not positive definite")
+    if orth not in ORTH or stop not in ("residual", "trace"):
+        raise ValueError("invalid orth or stop")
+    sched = rr_schedule(rr_period, rr_max)
+    next_rr = next(sched)
+    trace_prev = None
     info = Info()
 
     # steps 1-4: orthonormal start, residual W = AX - X (X^H A X)
@@ -119,16 +157,24 @@ def ppcg(apply_a, tdiag, X0, k, sbsize, tol, rr_period, max_iter=20000, record=F
         den = float(np.sum(lock_lam ** 2)) + _fro2(G[:nwa, :nwa])
         rho = math.sqrt(num / den) if den > 0 else math.inf
         info.rho = rho
+        trace = float(np.sum(lock_lam)) + float(np.real(np.trace(G)))
+        info.trace = trace
         if record:
             info.history.append(rho)
-        if rho <= tol:
+        if stop == "trace":
+            done = trace_prev is not None and abs(trace - trace_prev) <= tol * abs(trace)
+            trace_prev = trace
+        else:
+            done = rho <= tol
+        if done:
             # final Rayleigh-Ritz (steps 22-24) and a fresh residual check
             X, lam, AXn, Wall, wn, fresh, nl, P = rr_and_lock(X, nl, P)
             info.n_rr += 1
             info.fresh_resid = fresh
-            if fresh <= tol:
+            if fresh <= tol or stop == "trace":
                 info.iters = it - 1
                 info.n_locked = nl
+                info.X_all, info.lam_all = X, lam
                 return lam[:k].copy(), X[:, :k].copy(), info
             lock_wn, lock_lam = wn[:nl], lam[:nl]
             W, G = Wall[:, nl:], np.diag(lam[nl:]).astype(X.dtype)
@@ -138,6 +184,7 @@ def ppcg(apply_a, tdiag, X0, k, sbsize, tol, rr_period, max_iter=20000, record=F
             info.iters = it - 1
             info.n_locked = nl
             X2, lam, _ = rayleigh_ritz(X, apply_a(X))
+            info.X_all, info.lam_all = X2, lam
             raise NoConvergence("max_iter reached", lam[:k], X2[:, :k], info)
 
         XL = X[:, :nl]
@@ -185,9 +232,19 @@ def ppcg(apply_a, tdiag, X0, k, sbsize, tol, rr_period, max_iter=20000, record=F
             Pn[:, c0:c1] = Pj
             Xbar[:, c0:c1] = Xa[:, c0:c1] @ Cx + Pj
         P = Pn
-        if it % rr_period != 0:
-            # steps 18-20: Cholesky-QR, new residual
-            Xa, _ = cholqr(Xbar)
+        if it != next_rr:
+            # steps 17-20: orthonormalise (or not, section 5.5), new residual
+            G1 = sym(Xbar.conj().T @ Xbar)
+            e = float(np.linalg.norm(G1 - np.eye(G1.shape[0])))
+            if orth == "none" or (orth in ("skip", "taylor") and e <= orth_skip):
+                Xa = Xbar
+                info.n_orth_skip += 1
+            elif orth == "taylor" and e <= orth_taylor:
+                Xa = dense.polar_taylor(Xbar, G1)
+                info.n_taylor += 1
+            else:
+                Xa, _ = cholqr(Xbar)
+                info.n_cholqr += 1
             X = np.concatenate([XL, Xa], axis=1)
             AXa = apply_a(Xa)
             G = sym(Xa.conj().T @ AXa)
@@ -197,6 +254,8 @@ def ppcg(apply_a, tdiag, X0, k, sbsize, tol, rr_period, max_iter=20000, record=F
             X = np.concatenate([XL, Xbar], axis=1)
             X, lam, AXn, Wall, wn, fresh, nl, P = rr_and_lock(X, nl, P)
             info.n_rr += 1
+            info.rr_iters.append(it)
+            next_rr = next(sched)
             lock_wn, lock_lam = wn[:nl], lam[:nl]
             W, G = Wall[:, nl:], np.diag(lam[nl:]).astype(X.dtype)
             AXa = AXn[:, nl:]

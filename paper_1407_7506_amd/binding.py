@@ -21,9 +21,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libppcg.so")
 
 PPCG_FP64, PPCG_MIXED = 0, 1
-PPCG_NO_GRAPHS, PPCG_AUTOTUNE = 1, 2
+PPCG_NO_GRAPHS, PPCG_AUTOTUNE, PPCG_RETURN_BUFFERS = 1, 2, 4
 STATUS = {0: "PPCG_OK", 1: "PPCG_EINVAL", 2: "PPCG_ENOTHPD", 3: "PPCG_ERANK", 4: "PPCG_ENOCONV",
           5: "PPCG_ENOSTATE", 6: "PPCG_EHIP", 7: "PPCG_ENOMEM"}
+STATUS_CODE = {v: k for k, v in STATUS.items()}
 
 
 class PPCGError(RuntimeError):
@@ -36,7 +37,7 @@ class PPCGError(RuntimeError):
 
 class IterLog(ctypes.Structure):
     _fields_ = [("iter", c_int32), ("n_locked", c_int32), ("n_active", c_int32), ("kind", c_int32),
-                ("rho", c_double), ("time_s", c_double)]
+                ("rho", c_double), ("time_s", c_double), ("orth_err", c_double), ("trace", c_double)]
 
 
 LOG_FN = CFUNCTYPE(None, POINTER(IterLog), c_void_p)
@@ -46,7 +47,12 @@ ITER_KIND = {0: "start", 1: "cholqr", 2: "rr", 3: "final_rr_failed"}
 class Options(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("nbuf", c_int32), ("max_iter", c_int32), ("profile", c_int32),
                 ("flags", c_int32), ("singular_tol", c_double), ("seed", c_uint64), ("tune_table", c_char_p),
-                ("log_cb", LOG_FN), ("log_user", c_void_p)]
+                ("log_cb", LOG_FN), ("log_user", c_void_p), ("orth", c_int32), ("stop", c_int32),
+                ("rr_max", c_int32), ("orth_skip", c_double), ("orth_taylor", c_double)]
+
+
+ORTH = {"cholqr": 0, "skip": 1, "taylor": 2, "none": 3}
+STOP = {"residual": 0, "trace": 1}
 
 
 class Operator(ctypes.Structure):
@@ -58,6 +64,7 @@ class Info(ctypes.Structure):
     _fields_ = [("iters", c_int32), ("n_rr", c_int32), ("n_locked", c_int32), ("n_backtrack", c_int32),
                 ("resid_final", c_double), ("orth_err", c_double), ("time_s", c_double),
                 ("stage_ms", c_double * 6), ("n_dropped", c_int32), ("n_unlock", c_int32),
+                ("n_cholqr", c_int32), ("n_taylor", c_int32), ("n_orth_skip", c_int32),
                 ("roofline_ms", c_double)]
 
     def as_dict(self):
@@ -131,21 +138,29 @@ class Handle:
 
     def __init__(self, precision: str = "fp64", nbuf: int = -1, max_iter: int = 0, profile: bool = False,
                  stream=None, graphs: bool = True, autotune: bool = False, singular_tol: float = 0.0,
-                 seed: int = 0, tune_table: str | None = None, log=None):
+                 seed: int = 0, tune_table: str | None = None, log=None, orth: str = "cholqr",
+                 orth_skip: float = 0.0, orth_taylor: float = 0.0, rr_max: int = 0, stop: str = "residual",
+                 return_buffers: bool = False):
         """log: optional callable receiving one dict per PPCG iteration (iter,
-        n_locked, n_active, kind, rho, time_s)."""
+        n_locked, n_active, kind, rho, time_s, orth_err, trace).  orth:
+        "cholqr", "skip", "taylor" or "none"; stop: "residual" or "trace".
+        return_buffers: solve returns all K columns and Ritz values."""
         import torch
         self._L = lib()
-        flags = (0 if graphs else PPCG_NO_GRAPHS) | (PPCG_AUTOTUNE if autotune else 0)
+        flags = (0 if graphs else PPCG_NO_GRAPHS) | (PPCG_AUTOTUNE if autotune else 0) | \
+            (PPCG_RETURN_BUFFERS if return_buffers else 0)
+        self.return_buffers = return_buffers
         self._log_fn = LOG_FN(0)
         if log is not None:
             def _cb(rec, _user):
                 r = rec.contents
                 log({"iter": r.iter, "n_locked": r.n_locked, "n_active": r.n_active,
-                     "kind": ITER_KIND.get(r.kind, r.kind), "rho": r.rho, "time_s": r.time_s})
+                     "kind": ITER_KIND.get(r.kind, r.kind), "rho": r.rho, "time_s": r.time_s,
+                     "orth_err": r.orth_err, "trace": r.trace})
             self._log_fn = LOG_FN(_cb)
         opt = Options(PPCG_MIXED if precision == "mixed" else PPCG_FP64, nbuf, max_iter, 1 if profile else 0, flags,
-                      float(singular_tol), int(seed), tune_table.encode() if tune_table else None, self._log_fn, None)
+                      float(singular_tol), int(seed), tune_table.encode() if tune_table else None, self._log_fn, None,
+                      ORTH[orth], STOP[stop], int(rr_max), float(orth_skip), float(orth_taylor))
         st = stream if stream is not None else torch.cuda.current_stream()
         self.stream = st
         h = c_void_p()
@@ -214,8 +229,9 @@ class Handle:
         else:
             X0cm = None
         dt = torch.complex128 if cplx else torch.float64
-        Xout = torch.empty((k, n), dtype=dt, device=V.device)
-        lam = torch.empty(k, dtype=torch.float64, device=V.device)
+        kout = K if self.return_buffers else k
+        Xout = torch.empty((kout, n), dtype=dt, device=V.device)
+        lam = torch.empty(kout, dtype=torch.float64, device=V.device)
         op = self.operator(V, N, h, order, kpt)
         info = Info()
         code = self._L.ppcg_solve(self._h, byref(op), int(k), int(sbsize), float(tol), int(rr_period),
@@ -259,8 +275,9 @@ class Handle:
                 X0cm = X0.t().contiguous()
                 keep.append(X0cm)
             dt = torch.complex128 if cplx else torch.float64
-            Xo = torch.empty((k, n), dtype=dt, device=p["V"].device)
-            lo = torch.empty(k, dtype=torch.float64, device=p["V"].device)
+            kout = K if self.return_buffers else k
+            Xo = torch.empty((kout, n), dtype=dt, device=p["V"].device)
+            lo = torch.empty(kout, dtype=torch.float64, device=p["V"].device)
             ops[b] = self.operator(p["V"], N, p.get("h", 0.5), p.get("order", 2), kpt)
             ks[b] = k
             x0p[b] = X0cm.data_ptr() if X0 is not None else None
@@ -313,9 +330,8 @@ class Handle:
         B = B.contiguous()
         C = torch.zeros((nb, q, 3 * q), dtype=A.dtype, device=A.device)
         flags = torch.zeros(nb, dtype=torch.int32, device=A.device)
-        code = self._L.ppcg_block_pencils(self._h, int(nb), int(q), 1 if has_p else 0, 1 if cplx else 0,
-                                          c_void_p(A.data_ptr()), c_void_p(B.data_ptr()), float(tol),
-                                          c_void_p(C.data_ptr()), c_void_p(flags.data_ptr()))
+        code = self._L.ppcg_block_pencils(self._h, int(nb), int(q), 1 if has_p else 0, 1 if cplx else 0, c_void_p(A.data_ptr()),
+                  c_void_p(B.data_ptr()), float(tol), c_void_p(C.data_ptr()), c_void_p(flags.data_ptr()))
         if code != 0:
             raise PPCGError(code, self.error())
         return C, flags

@@ -345,6 +345,40 @@ static int pencil_kind(const PencilArgs& a) {
     default: break;                                                                                            \
   }
 
+// Lays out given pencils (A_j, B_j), nS x nS each (ld nS, stride nS^2), in
+// the pencil kernel's input form: per block an nS x (2 nS - q) Gram holding
+// B_j in columns [0, nS) and the columns [q, nS) of A_j after them, and the
+// q x q X block of A_j at offset j q (q + 1) with leading dimension q (the
+// kernel's G[j q + i, j q + c] addressing with ldg = q).  S: double or zdouble.
+template <class S>
+__global__ __launch_bounds__(256) void pencil_pack_kernel(const S* A, const S* B, int nblocks, int q, int nS, S* gram,
+                                                         S* G) {
+  const long e = blockIdx.x * 256L + threadIdx.x;
+  const long per = (long)nS * nS;
+  if (e >= per * nblocks) return;
+  const int j = (int)(e / per);
+  const int r = (int)(e % per);
+  const int i = r % nS, c = r / nS;
+  const long Nb = 2L * nS - q;
+  S* gj = gram + (long)j * nS * Nb;
+  gj[r] = B[e];
+  const S a = A[e];
+  if (c >= q) gj[per + i + (long)(c - q) * nS] = a;
+  if (i < q && c < q) G[(long)j * q * (q + 1) + i + (long)c * q] = a;
+}
+
+void launch_pencil_pack(const double* A, const double* B, int nblocks, int q, int nS, int cplx, double* gram,
+                        double* G, hipStream_t st) {
+  const long tot = (long)nS * nS * nblocks;
+  if (tot <= 0) return;
+  const unsigned grid = (unsigned)((tot + 255) / 256);
+  if (cplx)
+    hipLaunchKernelGGL(pencil_pack_kernel<zdouble>, dim3(grid), dim3(256), 0, st, (const zdouble*)A,
+                       (const zdouble*)B, nblocks, q, nS, (zdouble*)gram, (zdouble*)G);
+  else
+    hipLaunchKernelGGL(pencil_pack_kernel<double>, dim3(grid), dim3(256), 0, st, A, B, nblocks, q, nS, gram, G);
+}
+
 void launch_block_pencil(const PencilArgs& a, hipStream_t st) {
   unsigned blocks = a.nblocks > 0 ? (unsigned)a.nblocks : 0;
   if (a.nS > 96 || (a.nS > 48 && !a.work))

@@ -393,16 +393,56 @@ PPCG_DEV void orth_body(const OrthArgs& a, unsigned, unsigned) {
   const int nc = a.cplx ? 2 : 1;
   for (long e = threadIdx.x; e < (long)a.k * a.k; e += 256) {
     long i = e % a.k, j = e / a.k;
+    if (a.upper && i > j) continue;
     long o = (i + j * a.ld) * nc;
     double v = a.G[o] - (i == j ? 1.0 : 0.0);
-    s += v * v;
-    if (a.cplx) s += a.G[o + 1] * a.G[o + 1];
+    double t = v * v;
+    if (a.cplx) t += a.G[o + 1] * a.G[o + 1];
+    s += (a.upper && i < j) ? 2.0 * t : t;  // a Hermitian G: the lower triangle mirrors the upper
   }
   __shared__ double red[4];
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) *a.out = (red[0] + red[1]) + (red[2] + red[3]);
+}
+PPCG_DEV void polar_body(const PolarArgs& a, unsigned wg, unsigned) {
+  long e = wg * 256L + threadIdx.x;
+  if (e >= (long)a.m * a.m) return;
+  const int i = e % a.m, j = e / a.m;
+  const int nc = a.cplx ? 2 : 1;
+  const bool up = i <= j;
+  const long src = (up ? i + (long)j * a.ld : j + (long)i * a.ld) * nc;  // Hermitian: lower = conj(upper)
+  const long o = (i + (long)j * a.ld) * nc;
+  const double yr = a.G[src] - (i == j ? 1.0 : 0.0);
+  a.Y[o] = yr;
+  a.M[o] = (i == j ? 0.375 : 0.0) - 0.3125 * yr;
+  if (a.cplx) {
+    const double yi = i == j ? 0.0 : (up ? a.G[src + 1] : -a.G[src + 1]);
+    a.Y[o + 1] = yi;
+    a.M[o + 1] = -0.3125 * yi;
+  }
+}
+PPCG_DEV void add_diag_body(const AddDiagArgs& a, unsigned wg, unsigned) {
+  int i = wg * 256 + threadIdx.x;
+  if (i < a.m) a.G[(i + (long)i * a.ld) * (a.cplx ? 2 : 1)] += a.v;
+}
+PPCG_DEV void trace_body(const TraceArgs& a, unsigned, unsigned) {
+  double s = 0;
+  for (int i = threadIdx.x; i < a.m; i += 256) s += a.G[(i + (long)i * a.ld) * (a.cplx ? 2 : 1)];
+  __shared__ double red[4];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) *a.out = (red[0] + red[1]) + (red[2] + red[3]);
+}
+PPCG_DEV void to_f32_body(const ToF32Args& a, unsigned wg, unsigned) {
+  const int nc = a.cplx ? 2 : 1;
+  const long per = a.rows * nc;
+  const long e = wg * 256L + threadIdx.x;
+  if (e >= per * a.ncols) return;
+  const long c = e / per, r = e % per;
+  a.Y[r + c * a.ld * nc] = (float)a.X[r + c * a.ld * nc];
 }
 PPCG_DEV void zero_int_body(const ZeroIntArgs& a, unsigned wg, unsigned) {
   int e = wg * 256 + threadIdx.x;
@@ -428,6 +468,10 @@ PPCG_SIMPLE(frob2, Frob2Args)
 PPCG_SIMPLE(orth, OrthArgs)
 PPCG_SIMPLE(zero_int, ZeroIntArgs)
 PPCG_SIMPLE(copy, CopyArgs)
+PPCG_SIMPLE(polar, PolarArgs)
+PPCG_SIMPLE(add_diag, AddDiagArgs)
+PPCG_SIMPLE(trace, TraceArgs)
+PPCG_SIMPLE(to_f32, ToF32Args)
 #undef PPCG_SIMPLE
 
 template <class A>
@@ -467,9 +511,27 @@ void launch_frob2_sub(const double* G, int ld, int nw, double* out, int cplx, hi
   Frob2Args a{G, ld, nw, out, cplx};
   simple_launch(OP_FROB2, frob2_kernel, a, (unsigned)(nw > 0 ? nw : 0), st);
 }
-void launch_orth_err2(const double* G, int ld, int k, double* out, int cplx, hipStream_t st) {
-  OrthArgs a{G, ld, k, out, cplx};
+void launch_orth_err2(const double* G, int ld, int k, double* out, int cplx, hipStream_t st, bool upper) {
+  OrthArgs a{G, ld, k, out, cplx, upper ? 1 : 0};
   simple_launch(OP_ORTH, orth_kernel, a, 1u, st);
+}
+void launch_polar_prep(const double* G, int ld, int m, double* Y, double* M, int cplx, hipStream_t st) {
+  PolarArgs a{G, ld, m, Y, M, cplx};
+  long t = (long)m * m;
+  simple_launch(OP_POLAR, polar_kernel, a, (unsigned)((t + 255) / 256), st);
+}
+void launch_add_diag(double* G, int ld, int m, double v, int cplx, hipStream_t st) {
+  AddDiagArgs a{G, ld, m, v, cplx};
+  simple_launch(OP_ADDDIAG, add_diag_kernel, a, (unsigned)((m + 255) / 256), st);
+}
+void launch_trace(const double* G, int ld, int m, double* out, int cplx, hipStream_t st) {
+  TraceArgs a{G, ld, m, out, cplx};
+  simple_launch(OP_TRACE, trace_kernel, a, 1u, st);
+}
+void launch_to_f32(const double* X, float* Y, long ld, long rows, int ncols, int cplx, hipStream_t st) {
+  ToF32Args a{X, Y, ld, rows, ncols, cplx};
+  long t = rows * (cplx ? 2 : 1) * ncols;
+  simple_launch(OP_TOF32, to_f32_kernel, a, (unsigned)(t > 0 ? (t + 255) / 256 : 0), st);
 }
 void launch_zero_int(int* p, int n, hipStream_t st) {
   ZeroIntArgs a{p, n};
@@ -501,6 +563,10 @@ bool launch_grouped_dense(int kind, const void* jobs, const unsigned* start, int
     case OP_ORTH: PPCG_G(orth, OrthArgs); return true;
     case OP_ZEROINT: PPCG_G(zero_int, ZeroIntArgs); return true;
     case OP_COPY: PPCG_G(copy, CopyArgs); return true;
+    case OP_POLAR: PPCG_G(polar, PolarArgs); return true;
+    case OP_ADDDIAG: PPCG_G(add_diag, AddDiagArgs); return true;
+    case OP_TRACE: PPCG_G(trace, TraceArgs); return true;
+    case OP_TOF32: PPCG_G(to_f32, ToF32Args); return true;
   }
 #undef PPCG_G
   return false;

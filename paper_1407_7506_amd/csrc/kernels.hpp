@@ -161,6 +161,9 @@ struct PencilArgs {
 };
 // scalars of device scratch one block pencil with nS > 48 uses
 constexpr long pencil_work_elems() { return 4L * 96 * 97; }
+// given pencils (A_j, B_j) -> the block pencil kernel's gram / G input layout (one launch)
+void launch_pencil_pack(const double* A, const double* B, int nblocks, int q, int nS, int cplx, double* gram,
+                        double* G, hipStream_t st);
 
 // block update (steps 14-15): P_j <- W_j C_W + P_j C_P ; X_j <- X_j C_X + P_j
 struct BlockUpdArgs {
@@ -187,7 +190,17 @@ struct SymmArgs { double* G; int ld, m; int cplx; };
 // F (float, ldf) <- G with a zero diagonal (m x m; complex interleaved when cplx)
 struct OffdiagArgs { const double* G; int ldg, m; float* F; int ldf; int cplx; };
 struct Frob2Args { const double* G; int ld, nw; double* out; int cplx; };
-struct OrthArgs { const double* G; int ld, k; double* out; int cplx; };
+// |G - I|_F^2 of a k x k Gram; upper: only the upper triangle of G is valid
+struct OrthArgs { const double* G; int ld, k; double* out; int cplx; int upper; };
+// Taylor polar step (section 5.5): from the upper triangle of G = X^H X,
+// Y = G - I (Hermitian) and M = (3/8) I - (5/16) Y, m x m at leading dimension ld
+struct PolarArgs { const double* G; int ld, m; double* Y; double* M; int cplx; };
+// G += v I on the m x m leading block
+struct AddDiagArgs { double* G; int ld, m; double v; int cplx; };
+// out[0] = sum_i Re G_ii over the m x m leading block (one workgroup)
+struct TraceArgs { const double* G; int ld, m; double* out; int cplx; };
+// float shadow of a float64 block: Y = (float) X over rows x ncols (ld in elements)
+struct ToF32Args { const double* X; float* Y; long ld, rows; int ncols; int cplx; };
 struct ZeroIntArgs { int* p; int n; };
 struct CopyArgs { const double* src; double* dst; long count; };
 struct PrepArgs { const double* V; long n; double c0; double* td; float* V32; double* dmin_part; int nparts; int* nan_flag; };
@@ -211,6 +224,7 @@ enum OpKind : int {
   OP_BUPD_D4, OP_BUPD_D8, OP_BUPD_D16, OP_BUPD_D32, OP_BUPD_F4, OP_BUPD_F8, OP_BUPD_F16, OP_BUPD_F32,
   OP_BUPD_Z4, OP_BUPD_Z8, OP_BUPD_Z16, OP_BUPD_Z32, OP_BUPD_C4, OP_BUPD_C8, OP_BUPD_C16, OP_BUPD_C32,
   OP_TRANSPOSE, OP_FILL, OP_SETDIAG, OP_SYMM, OP_FROB2, OP_ORTH, OP_ZEROINT, OP_COPY, OP_PREP, OP_OFFDIAG,
+  OP_POLAR, OP_ADDDIAG, OP_TRACE, OP_TOF32,
   OP_CHOL,   // composite: expanded by the grouped executor
   OP_D2H,    // host copy
   OP_COUNT
@@ -304,7 +318,11 @@ void launch_symmetrize(double* G, int ld, int m, int cplx, hipStream_t st);
 // out[j] = sum_{i<nw} G[i, j]^2, j < nw
 void launch_frob2_sub(const double* G, int ld, int nw, double* out, int cplx, hipStream_t st);
 // out = |G[:k, :k] - I|_F^2
-void launch_orth_err2(const double* G, int ld, int k, double* out, int cplx, hipStream_t st);
+void launch_orth_err2(const double* G, int ld, int k, double* out, int cplx, hipStream_t st, bool upper = false);
+void launch_polar_prep(const double* G, int ld, int m, double* Y, double* M, int cplx, hipStream_t st);
+void launch_add_diag(double* G, int ld, int m, double v, int cplx, hipStream_t st);
+void launch_trace(const double* G, int ld, int m, double* out, int cplx, hipStream_t st);
+void launch_to_f32(const double* X, float* Y, long ld, long rows, int ncols, int cplx, hipStream_t st);
 void launch_copy(const double* src, double* dst, long count, hipStream_t st);
 void launch_d2h(void* dst, const void* src, size_t bytes, hipStream_t st);
 

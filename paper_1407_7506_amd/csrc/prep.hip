@@ -111,6 +111,10 @@ size_t op_args_size(int kind) {
     case OP_OFFDIAG: return sizeof(OffdiagArgs);
     case OP_FROB2: return sizeof(Frob2Args);
     case OP_ORTH: return sizeof(OrthArgs);
+    case OP_POLAR: return sizeof(PolarArgs);
+    case OP_ADDDIAG: return sizeof(AddDiagArgs);
+    case OP_TRACE: return sizeof(TraceArgs);
+    case OP_TOF32: return sizeof(ToF32Args);
     case OP_ZEROINT: return sizeof(ZeroIntArgs);
     case OP_COPY: return sizeof(CopyArgs);
     case OP_PREP: return sizeof(PrepArgs);

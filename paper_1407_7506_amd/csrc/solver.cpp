@@ -351,6 +351,14 @@ struct Prob {
   bool noconv = false;
   double fresh = INFINITY;
   int last_kind = 0;  // what the last iteration ended with (ppcg_iter_log.kind)
+  // orthonormalisation policy (section 5.5) and stopping test (section 5.2)
+  int orth = PPCG_ORTH_CHOLQR, stop = PPCG_STOP_RESIDUAL;
+  double orth_skip = 0.1, orth_taylor = 0.3;
+  double orth_e = -1;          // |Xbar^H Xbar - I|_F measured in the last iteration (-1: not measured)
+  int orth_mode = 2;           // this iteration: 0 omit steps 18-19, 1 Taylor polar, 2 Cholesky-QR
+  double trace_prev = NAN, trace_cur = NAN;
+  // Rayleigh-Ritz schedule (section 5.6): next iteration with a Rayleigh-Ritz step, current interval
+  int next_rr = 0, rr_gap = 0;
   std::vector<double> lock_wn, lock_lam;
   ppcg_info info{};
   ppcg_status status = PPCG_OK;
@@ -423,6 +431,14 @@ struct Prob {
     tol = tol_;
     rr_period = rrp;
     mixed = H->opt.precision == PPCG_MIXED;
+    orth = H->opt.orth;
+    stop = H->opt.stop;
+    if (orth < PPCG_ORTH_CHOLQR || orth > PPCG_ORTH_NONE || stop < PPCG_STOP_RESIDUAL || stop > PPCG_STOP_TRACE)
+      throw PpcgError{PPCG_EINVAL, "bad options.orth or options.stop"};
+    orth_skip = H->opt.orth_skip > 0 ? H->opt.orth_skip : 0.1;
+    orth_taylor = H->opt.orth_taylor > 0 ? H->opt.orth_taylor : 0.3;
+    rr_gap = std::max(H->opt.rr_max, rrp);
+    next_rr = rr_gap;
     max_iter = H->opt.max_iter > 0 ? H->opt.max_iter : 20000;
     if (k <= 0 || q < 1 || q > 32 || !(tol > 0) || rr_period < 1)
       throw PpcgError{PPCG_EINVAL, "need k > 0, 1 <= sbsize <= 32, tol > 0, rr_period >= 1"};
@@ -935,14 +951,22 @@ struct Prob {
     enq_rho_d2h();
   }
 
-  // X (active columns) <- X R^{-1}; result lands in Xt then X/Xt swap
-  void enq_cholqr(int m) {
+  // G = Xbar^H Xbar of the active columns (upper triangle)
+  void enq_gram_xx(int m) {
     CatCtx cc(prof, CAT_CHOLQR);
     double* Xa = xc(X(), nl);
-    {
-      ColSet A = cols1(Xa, m, false);
-      gram(A, A, m, m, rows, ld, nullptr, 0, Wk.G.p, Kp, true, false, 1, 0, 0, "gram_xx");
-    }
+    ColSet A = cols1(Xa, m, false);
+    gram(A, A, m, m, rows, ld, nullptr, 0, Wk.G.p, Kp, true, false, 1, 0, 0, "gram_xx");
+  }
+  // |G - I|_F^2 of that Gram into scal[Kp + 1] and the pinned slot 2 Kp + 1
+  void enq_orth_err() {
+    launch_orth_err2(Wk.G.d(), Kp, K - nl, Wk.scal.d() + Kp + 1, cplx, st, true);
+    launch_d2h(Wk.hpind + 2 * Kp + 1, Wk.scal.d() + Kp + 1, 8, st);
+  }
+  // X (active columns) <- X R^{-1} with G = R^H R; result lands in Xt then X/Xt swap
+  void enq_chol_apply(int m) {
+    CatCtx cc(prof, CAT_CHOLQR);
+    double* Xa = xc(X(), nl);
     launch_zero_int(Wk.iflag.i(), 4, st);
     chol(Wk.G.d(), m);
     launch_transpose(Wk.Li.d(), Kp, Wk.Rinv.d(), Kp, m, m, cplx, st);  // R^{-1} = L^{-H}
@@ -950,6 +974,32 @@ struct Prob {
     update(Xa, ld, m, Wk.Rinv.p, Kp, m, Xn, nullptr, m, ld, mixed ? fc(Wk.X32.f(), nl) : nullptr, nullptr, rows, 1.0,
            0.0, true, false, "update_xr");
     swapX();  // the locked prefix is valid in both buffers (copied once per Rayleigh-Ritz)
+  }
+  void enq_cholqr(int m) {
+    enq_gram_xx(m);
+    enq_chol_apply(m);
+  }
+  // X (active) <- X (I - Y/2 + 3Y^2/8 - 5Y^3/16), Y = G - I: the orthonormal
+  // polar factor by four Taylor terms (section 5.5), evaluated as
+  // I + Y (-I/2 + Y (3I/8 - 5Y/16)) with small products on the K x K buffers
+  void enq_taylor(int m) {
+    CatCtx cc(prof, CAT_CHOLQR);
+    double* Xa = xc(X(), nl);
+    launch_polar_prep(Wk.G.d(), Kp, m, Wk.Yv.d(), Wk.Mr.d(), cplx, st);
+    update(Wk.Yv.p, Kp, m, Wk.Mr.p, Kp, m, Wk.V1.p, nullptr, m, Kp, nullptr, nullptr, Kp, 1.0, 0.0, false, false,
+           "update_polar");
+    launch_add_diag(Wk.V1.d(), Kp, m, -0.5, cplx, st);
+    update(Wk.Yv.p, Kp, m, Wk.V1.p, Kp, m, Wk.Cc.p, nullptr, m, Kp, nullptr, nullptr, Kp, 1.0, 0.0, false, false,
+           "update_polar");
+    launch_add_diag(Wk.Cc.d(), Kp, m, 1.0, cplx, st);
+    double* Xn = xc(Xt(), nl);
+    update(Xa, ld, m, Wk.Cc.p, Kp, m, Xn, nullptr, m, ld, mixed ? fc(Wk.X32.f(), nl) : nullptr, nullptr, rows, 1.0,
+           0.0, false, false, "update_xr");
+    swapX();
+  }
+  // steps 18-19 omitted: X stays Xbar; the float shadow follows it
+  void enq_orth_skip(int m) {
+    if (mixed) launch_to_f32(xc(X(), nl), fc(Wk.X32.f(), nl), ld, rows, m, cplx, st);
   }
 
   // residual of the active columns: AX = H X, G = X^H AX, W = AX - X G.
@@ -989,6 +1039,8 @@ struct Prob {
   }
 
   void enq_rho_d2h() {
+    launch_trace(Wk.G.d(), Kp, K - nl, Wk.scal.d() + Kp, cplx, st);
+    launch_d2h(Wk.hpind + 2 * Kp, Wk.scal.d() + Kp, 8, st);
     int nwa = std::max(0, k - nl);
     launch_d2h(Wk.hpind, Wk.cn.p, (size_t)std::max(nwa, 1) * 8, st);
     launch_d2h(Wk.hpind + Kp, Wk.scal.p, (size_t)std::max(nwa, 1) * 8, st);
@@ -1005,6 +1057,8 @@ struct Prob {
     rec.kind = last_kind;
     rec.rho = rho;
     rec.time_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    rec.orth_err = orth_e;
+    rec.trace = trace_cur;
     H->opt.log_cb(&rec, H->opt.log_user);
   }
 
@@ -1017,11 +1071,26 @@ struct Prob {
       num += Wk.hpind[i];
       den += Wk.hpind[Kp + i];
     }
+    double tr = Wk.hpind[2 * Kp];  // trace of the active block of X^H H X
     for (size_t i = 0; i < lock_wn.size(); ++i) {
       num += lock_wn[i] * lock_wn[i];
       den += lock_lam[i] * lock_lam[i];
+      tr += lock_lam[i];
     }
+    trace_prev = trace_cur;
+    trace_cur = tr;
     return den > 0 ? std::sqrt(num / den) : INFINITY;
+  }
+  // the loop head's stopping test (section 5.2) on this iteration's rho and trace
+  bool converged(double rho) const {
+    if (stop == PPCG_STOP_TRACE)
+      return std::isfinite(trace_prev) && std::fabs(trace_cur - trace_prev) <= tol * std::fabs(trace_cur);
+    return rho <= tol;
+  }
+  bool rr_iteration() const { return it == next_rr; }
+  void advance_rr() {
+    rr_gap = std::max(rr_period, rr_gap - 1);
+    next_rr += rr_gap;
   }
 
   // Rayleigh-Ritz over all K columns (S = [X_lock, X_act]), part 1: the
@@ -1242,19 +1311,57 @@ struct Prob {
     hasP = true;
   }
 
-  // phase: steps 18-20
+  // phase: steps 17-20 when the orthonormalisation needs no host decision
+  // (Cholesky-QR every iteration, or never)
   void enq_cq() {
     int m = K - nl;
-    enq_cholqr(m);
+    if (orth == PPCG_ORTH_NONE) {
+      orth_e = -1;
+      orth_mode = 0;
+      info.n_orth_skip++;
+      enq_orth_skip(m);
+    } else {
+      enq_gram_xx(m);
+      enq_orth_err();
+      enq_chol_apply(m);
+      orth_mode = 2;
+      info.n_cholqr++;
+    }
     enq_residual(m);
     enq_rho_d2h();
+  }
+  // adaptive orthonormalisation (section 5.5), part 1: measure e = |Xbar^H Xbar - I|_F
+  void enq_cq_a() {
+    enq_gram_xx(K - nl);
+    enq_orth_err();
+  }
+  void post_cq_a() {
+    orth_e = std::sqrt(Wk.hpind[2 * Kp + 1]);
+    if (orth_e <= orth_skip) orth_mode = 0;
+    else if (orth == PPCG_ORTH_TAYLOR && orth_e <= orth_taylor) orth_mode = 1;
+    else orth_mode = 2;
+    (orth_mode == 0 ? info.n_orth_skip : orth_mode == 1 ? info.n_taylor : info.n_cholqr)++;
+  }
+  // part 2: the chosen step, then the residual (step 20)
+  void enq_cq_b() {
+    int m = K - nl;
+    if (orth_mode == 0) enq_orth_skip(m);
+    else if (orth_mode == 1) enq_taylor(m);
+    else enq_chol_apply(m);
+    enq_residual(m);
+    enq_rho_d2h();
+  }
+  // the measured e of a Cholesky-QR iteration is read at the next loop head
+  void post_cq() {
+    if (orth != PPCG_ORTH_NONE) orth_e = std::sqrt(Wk.hpind[2 * Kp + 1]);
   }
 
   // phase: outputs and the orthogonality check of the returned block
   void enq_finish() {
-    HIPCHECK(hipMemcpy2DAsync(Xout, (size_t)n * xs(), X(), (size_t)ld * xs(), (size_t)n * xs(), k,
+    const int kout = (H->opt.flags & PPCG_RETURN_BUFFERS) ? K : k;
+    HIPCHECK(hipMemcpy2DAsync(Xout, (size_t)n * xs(), X(), (size_t)ld * xs(), (size_t)n * xs(), kout,
                               hipMemcpyDeviceToDevice, st));
-    HIPCHECK(hipMemcpyAsync(lamout, Wk.lam.p, (size_t)k * 8, hipMemcpyDeviceToDevice, st));
+    HIPCHECK(hipMemcpyAsync(lamout, Wk.lam.p, (size_t)kout * 8, hipMemcpyDeviceToDevice, st));
     ColSet A = cols1(X(), k, false);
     gram(A, A, k, k, rows, ld, nullptr, 0, Wk.G.p, Kp, false, false, 1, 0, 0, "gram_check");
     launch_orth_err2(Wk.G.d(), Kp, k, Wk.scal.d(), cplx, st);
@@ -1449,8 +1556,9 @@ struct Driver {
       std::vector<Prob*> fin, body, done, again;
       post(act, [&](Prob& p) {
         double r = p.post_rho();
+        if (p.last_kind == 1) p.post_cq();
         p.log(r);
-        if (r <= p.tol) fin.push_back(&p);
+        if (p.converged(r)) fin.push_back(&p);
         else if (p.it > p.max_iter) {
           p.noconv = true;
           fin.push_back(&p);
@@ -1460,7 +1568,7 @@ struct Driver {
       if (!fin.empty()) {
         rayleigh_ritz(fin);
         for (Prob* p : fin) {
-          if (p->fresh <= p->tol) done.push_back(p);
+          if (p->fresh <= p->tol || (p->stop == PPCG_STOP_TRACE && !p->noconv)) done.push_back(p);
           else if (p->noconv) {
             p->status = PPCG_ENOCONV;
             p->err = "max_iter reached";
@@ -1476,15 +1584,28 @@ struct Driver {
         phase(body, [](Prob& p) { p.enq_body1(); });
         sync(H);
         post(body, [](Prob& p) { p.post_body1(); });
-        std::vector<Prob*> cq, rr;
+        std::vector<Prob*> cq, cqa, rr;
         for (Prob* p : body) {
-          p->last_kind = p->it % p->rr_period != 0 ? 1 : 2;
-          (p->it % p->rr_period != 0 ? cq : rr).push_back(p);
+          const bool r_it = p->rr_iteration();
+          p->last_kind = r_it ? 2 : 1;
+          if (r_it) rr.push_back(p);
+          else if (p->orth == PPCG_ORTH_SKIP || p->orth == PPCG_ORTH_TAYLOR) cqa.push_back(p);
+          else cq.push_back(p);
         }
         phase(cq, [](Prob& p) { p.enq_cq(); });
+        if (!cqa.empty()) {  // the orthonormalisation step depends on the measured e
+          phase(cqa, [](Prob& p) { p.enq_cq_a(); });
+          sync(H);
+          post(cqa, [](Prob& p) { p.post_cq_a(); });
+          phase(cqa, [](Prob& p) { p.enq_cq_b(); });
+        }
         if (!rr.empty()) {
           rayleigh_ritz(rr);
-          phase(rr, [](Prob& p) { p.enq_rr3(); });
+          phase(rr, [](Prob& p) {
+            p.enq_rr3();
+            p.orth_e = -1;
+            p.advance_rr();
+          });
         }
         for (Prob* p : body) {
           p->info.iters = p->it;
@@ -1577,6 +1698,10 @@ struct Grad {
     }
     HIPCHECK(hipMemsetAsync(H->gw.p, 0, H->gw.bytes, st));
     HIPCHECK(hipMemcpyAsync(H->gw.p, w, n * 8, hipMemcpyDeviceToDevice, st));
+    // the stencil writes only the n grid rows of A P and the projection keeps
+    // the padding rows as they are: they must start (and stay) zero, or the
+    // CG residual norms over the padded rows pick up stale memory
+    HIPCHECK(hipMemsetAsync(H->gAP.p, 0, H->gAP.bytes, st));
     double *Z = H->gZ.d(), *R = H->gR.d(), *P = H->gP.d(), *AP = H->gAP.d(), *Y = H->gY.d();
     // b = Q (w x_i)
     launch_scale_rows(H->gw.d(), Wk.X.p, R, ld, rows, k, 0, st);
@@ -1678,6 +1803,49 @@ void save_tune_table(ppcg_handle* H) {
   if (!ok || rename(tmp.c_str(), H->tune_path.c_str()) != 0)
     throw PpcgError{PPCG_EINVAL, "cannot write tune table " + H->tune_path};
   H->tune_saved = H->tune.size();
+}
+
+// Input of the block pencil kernel for given pencils: the Gram layout a
+// solve builds (per block nS x (2 nS - q): B, then columns [q, nS) of A), the
+// q x q X blocks of A, and for nS > 48 the per-block work matrices.
+struct PencilLayout {
+  size_t gram_bytes = 0, g_bytes = 0, work_bytes = 0;
+};
+PencilLayout pencil_layout(int nblocks, int q, bool has_p, bool cplx) {
+  const size_t es = cplx ? 16 : 8;
+  const int nS = has_p ? 3 * q : 2 * q, Nb = 2 * nS - q;
+  PencilLayout L;
+  L.gram_bytes = (size_t)nblocks * nS * Nb * es;
+  L.g_bytes = (size_t)nblocks * q * (q + 1) * es;
+  L.work_bytes = nS > 48 ? (size_t)nblocks * pencil_work_elems() * es : 0;
+  return L;
+}
+
+// packs the pencils and launches the block pencil kernel on the handle's
+// stream (no synchronisation)
+void enqueue_pencils(ppcg_handle* h, int nblocks, int q, bool has_p, bool cplx, const double* A, const double* B,
+                     double tol, double* C, int32_t* flags, double* gram, double* G, void* work) {
+  const int nS = has_p ? 3 * q : 2 * q, Nb = 2 * nS - q;
+  launch_pencil_pack(A, B, nblocks, q, nS, cplx ? 1 : 0, gram, G, h->st);
+  PencilArgs pa{};
+  pa.gram = gram;
+  pa.gstride = (long)nS * Nb;
+  pa.G = G;
+  pa.ldg = q;
+  pa.q = q;
+  pa.nS = nS;
+  pa.C = C;
+  pa.cstride = 3L * q * q;
+  pa.flags = flags;
+  pa.drop_tol = 1e-14;
+  pa.pivot_tol = 1e-12;
+  pa.sing_tol = h->opt.singular_tol;
+  pa.jacobi_rel = std::max(2.2e-16, std::min(1e-10, 1e-4 * tol));
+  pa.nblocks = nblocks;
+  pa.cplx = cplx ? 1 : 0;
+  pa.work = work;
+  Scope sc(h->prof, "block_pencil");
+  launch_block_pencil(pa, h->st);
 }
 
 ppcg_status guard(ppcg_handle* h, const std::function<ppcg_status()>& f) {
@@ -1893,48 +2061,12 @@ ppcg_status ppcg_block_pencils(ppcg_handle* h, int32_t nblocks, int32_t q, int32
     return PPCG_EINVAL;
   return guard(h, [&]() {
     if (nblocks == 0) return PPCG_OK;
-    const int nS = has_p ? 3 * q : 2 * q, Nb = 2 * nS - q;
-    const size_t es = cplx ? 16 : 8;
-    // the solver's layout: per block an nS x Nb Gram (ld nS) holding S^H S in
-    // columns [0, nS) and S^H [H W, H P] in [nS, Nb); the X block S^H H S
-    // comes from G at rows and columns [j q, j q + q) -- here each q x q X
-    // block sits at offset j q (q + 1) with leading dimension q, which is
-    // that addressing with ldg = q
-    h->pen_gram.ensure((size_t)nblocks * nS * Nb * es);
-    h->pen_G.ensure((size_t)nblocks * q * (q + 1) * es);
-    if (nS > 48) h->pen_work.ensure((size_t)nblocks * pencil_work_elems() * es);
-    const size_t mat = (size_t)nS * nS * es;
-    for (int j = 0; j < nblocks; ++j) {
-      char* gj = (char*)h->pen_gram.p + (size_t)j * nS * Nb * es;
-      const char* Aj = (const char*)A + j * mat;
-      HIPCHECK(hipMemcpyAsync(gj, (const char*)B + j * mat, mat, hipMemcpyDeviceToDevice, h->st));
-      HIPCHECK(hipMemcpyAsync(gj + mat, Aj + (size_t)q * nS * es, (size_t)(nS - q) * nS * es,
-                              hipMemcpyDeviceToDevice, h->st));
-      HIPCHECK(hipMemcpy2DAsync((char*)h->pen_G.p + (size_t)j * q * (q + 1) * es, (size_t)q * es, Aj,
-                                (size_t)nS * es, (size_t)q * es, q, hipMemcpyDeviceToDevice, h->st));
-    }
-    PencilArgs pa{};
-    pa.gram = h->pen_gram.d();
-    pa.gstride = (long)nS * Nb;
-    pa.G = h->pen_G.d();
-    pa.ldg = q;
-    pa.q = q;
-    pa.nS = nS;
-    pa.C = C;
-    pa.cstride = 3L * q * q;
-    pa.flags = flags;
-    pa.drop_tol = 1e-14;
-    pa.pivot_tol = 1e-12;
-    pa.sing_tol = h->opt.singular_tol;
-    pa.jacobi_rel = std::max(2.2e-16, std::min(1e-10, 1e-4 * tol));
-    pa.nblocks = nblocks;
-    pa.cplx = cplx ? 1 : 0;
-    pa.work = nS > 48 ? h->pen_work.p : nullptr;
-    {
-      Scope sc(h->prof, "block_pencil");
-      launch_block_pencil(pa, h->st);
-    }
-    HIPCHECK(hipGetLastError());
+    const PencilLayout L = pencil_layout(nblocks, q, has_p != 0, cplx != 0);
+    h->pen_gram.ensure(L.gram_bytes);
+    h->pen_G.ensure(L.g_bytes);
+    if (L.work_bytes) h->pen_work.ensure(L.work_bytes);
+    enqueue_pencils(h, nblocks, q, has_p != 0, cplx != 0, A, B, tol, C, flags, h->pen_gram.d(), h->pen_G.d(),
+                    L.work_bytes ? h->pen_work.p : nullptr);
     sync(h);
     return PPCG_OK;
   });

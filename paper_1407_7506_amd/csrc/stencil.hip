@@ -89,6 +89,90 @@ template <class S, int ORDER>
 __global__ __launch_bounds__(256) void stencil_kernel(StencilArgs a) {
   stencil_body<S, ORDER>(a, blockIdx.x, gridDim.x);
 }
+
+// LDS-staged variant (single launches).  For each z plane the workgroup loads
+// a window of the flattened (x, y) plane -- its 256 points and R N points on
+// either side (R = ORDER / 2, plane-periodic) -- once, coalesced, into LDS;
+// the x and y neighbours of a point are then LDS reads and the z neighbours
+// stay in registers.  Two window buffers: plane k + 1 is loaded while plane k
+// is computed, one barrier per plane.  A point costs about (256 + 2 R N) / 256
+// coalesced loads for the window plus one for its z neighbour and one for V,
+// instead of one load per neighbour.
+template <int ORDER>
+constexpr int stencil_rad() { return ORDER / 2; }
+inline int stencil_window(int N, int order) { return 256 + 2 * (order / 2) * N; }
+
+template <class S, int ORDER>
+__global__ __launch_bounds__(256) void stencil_lds_kernel(StencilArgs a) {
+  typedef typename sc_traits<S>::real_t R;
+  extern __shared__ __align__(16) char smem[];
+  S* win0 = (S*)smem;
+  constexpr int RAD = stencil_rad<ORDER>();
+  const int N = a.N;
+  const int NN = N * N;
+  const int W = 256 + 2 * RAD * N;
+  S* win1 = win0 + W;
+  const unsigned tpp = (unsigned)((NN + 255) / 256);
+  const unsigned kch = (unsigned)((N + SZ - 1) / SZ);
+  const unsigned L = xcd_remap(blockIdx.x, gridDim.x);
+  const int col = (int)(L / (tpp * kch));
+  const unsigned rest = L % (tpp * kch);
+  const int kc = (int)(rest / tpp);
+  const int q0 = (int)(rest % tpp) * 256;
+  if (col >= a.ncols) return;  // uniform over the workgroup
+  const int tid = threadIdx.x;
+  const int q = q0 + tid;
+  const bool act = q < NN;
+  const int wbase = q0 - RAD * N;  // plane index of window element 0 (taken modulo NN)
+  const S* x = (const S*)a.X + (long)col * a.ldx;
+  S* y = (S*)a.Y + (long)col * a.ldy;
+  const R* V = (const R*)a.V;
+  const int i = act ? q % N : 0;
+  const int c = tid + RAD * N;  // this point in the window
+  // window offsets of the x neighbours (wrapped inside the point's x line)
+  const int xp1 = c + wrap_idx(i, 1, N) - i, xm1 = c + wrap_idx(i, -1, N) - i;
+  const int xp2 = c + wrap_idx(i, 2, N) - i, xm2 = c + wrap_idx(i, -2, N) - i;
+  const int k0 = kc * SZ;
+  const int k1 = k0 + SZ < N ? k0 + SZ : N;
+  auto stage = [&](int k, S* buf) {
+    const S* xp = x + (long)k * NN;
+    for (int e = tid; e < W; e += 256) {
+      int s = (wbase + e) % NN;
+      s = s < 0 ? s + NN : s;
+      buf[e] = xp[s];
+    }
+  };
+  auto at = [&](int k) { return act ? x[q + (long)k * NN] : S{}; };
+  S zm2 = ORDER == 4 ? at(wrap_idx(k0, -2, N)) : S{};
+  S zm1 = at(wrap_idx(k0, -1, N));
+  S zc = at(k0);
+  S zp1 = at(wrap_idx(k0, 1, N));
+  stage(k0, win0);
+  __syncthreads();
+  for (int k = k0; k < k1; ++k) {
+    S* cur = ((k - k0) & 1) ? win1 : win0;
+    if (k + 1 < k1) stage(k + 1, ((k - k0) & 1) ? win0 : win1);
+    S zp2 = ORDER == 4 ? at(wrap_idx(k, 2, N)) : S{};
+    if (act) {
+      const long p = q + (long)k * NN;
+      S s1 = phased<S>(cur[xp1], cur[xm1], a.ph[0][0]) + phased<S>(cur[c + N], cur[c - N], a.ph[1][0]) +
+             phased<S>(zp1, zm1, a.ph[2][0]);
+      S out = ((R)a.c0 + V[p]) * zc + (R)a.w1 * s1;
+      if (ORDER == 4) {
+        S s2 = phased<S>(cur[xp2], cur[xm2], a.ph[0][1]) + phased<S>(cur[c + 2 * N], cur[c - 2 * N], a.ph[1][1]) +
+               phased<S>(zp2, zm2, a.ph[2][1]);
+        out += (R)a.w2 * s2;
+      }
+      if (a.shift) out -= (R)a.shift[col] * zc;
+      y[p] = out;
+    }
+    __syncthreads();
+    zm2 = zm1;
+    zm1 = zc;
+    zc = zp1;
+    zp1 = ORDER == 4 ? zp2 : at(wrap_idx(k, 2, N));
+  }
+}
 template <class S, int ORDER>
 __global__ __launch_bounds__(256) void stencil_grouped(const StencilArgs* jobs, const unsigned* start, int nj) {
   int j = find_job(start, nj, blockIdx.x);
@@ -116,15 +200,35 @@ static int stencil_kind(const StencilArgs& a) {
     default: break;                                                                                                  \
   }
 
+#ifndef PPCG_STENCIL_LDS
+#define PPCG_STENCIL_LDS 1
+#endif
+
 void launch_stencil(const StencilArgs& a, hipStream_t st) {
   const long NN = (long)a.N * a.N;
   unsigned blocks = (unsigned)(((NN + 255) / 256) * ((a.N + SZ - 1) / SZ) * (long)a.ncols);
   int kind = stencil_kind(a);
-  if (g_rec) {
+  if (g_rec) {  // grouped launches keep the register kernel (one LDS size for every job)
     g_rec->add(kind, &a, sizeof(a), blocks);
     return;
   }
   if (blocks == 0) return;
+  const size_t es = (a.f32 ? 4 : 8) * (a.cplx ? 2 : 1);
+  const size_t lds = 2 * (size_t)stencil_window(a.N, a.order) * es;
+  if (PPCG_STENCIL_LDS && lds <= 64 * 1024 && NN < (1L << 30)) {
+    switch (kind) {
+      case OP_STENCIL_D2: hipLaunchKernelGGL((stencil_lds_kernel<double, 2>), dim3(blocks), dim3(256), lds, st, a); break;
+      case OP_STENCIL_D4: hipLaunchKernelGGL((stencil_lds_kernel<double, 4>), dim3(blocks), dim3(256), lds, st, a); break;
+      case OP_STENCIL_F2: hipLaunchKernelGGL((stencil_lds_kernel<float, 2>), dim3(blocks), dim3(256), lds, st, a); break;
+      case OP_STENCIL_F4: hipLaunchKernelGGL((stencil_lds_kernel<float, 4>), dim3(blocks), dim3(256), lds, st, a); break;
+      case OP_STENCIL_Z2: hipLaunchKernelGGL((stencil_lds_kernel<zdouble, 2>), dim3(blocks), dim3(256), lds, st, a); break;
+      case OP_STENCIL_Z4: hipLaunchKernelGGL((stencil_lds_kernel<zdouble, 4>), dim3(blocks), dim3(256), lds, st, a); break;
+      case OP_STENCIL_C2: hipLaunchKernelGGL((stencil_lds_kernel<zfloat, 2>), dim3(blocks), dim3(256), lds, st, a); break;
+      case OP_STENCIL_C4: hipLaunchKernelGGL((stencil_lds_kernel<zfloat, 4>), dim3(blocks), dim3(256), lds, st, a); break;
+      default: break;
+    }
+    return;
+  }
   PPCG_STENCIL_SWITCH(stencil_kernel, blocks, a)
 }
 

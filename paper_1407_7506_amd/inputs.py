@@ -230,3 +230,15 @@ def small_problem(N: int = 10, k: int = 12, q: int = 4, order: int = 2, nwells: 
     V = gaussian_wells(N, 0.5, nwells, seed) if nwells > 0 else np.zeros(N ** 3)
     nb = default_nbuf(k, q) if nbuf is None else nbuf
     return Problem(f"small{N}_k{k}_q{q}_o{order}", g, V, k, q, nb, rr_period, tol, seed + 1000)
+
+
+def scf_potentials(base: Problem, steps: int = 14, amp: float = 0.5, decay: float = 0.7,
+                   seed: int = 106) -> list:
+    """A slowly converging sequence of potentials standing in for the
+    self-consistent-field iterations of the paper's section 6 (no density
+    functional here): V_s = V + amp * decay^s * dV for s = 0..steps, with dV
+    a smoothed N(0,1) field (width 2h) mapped onto [-1, 1] from its own seed.
+    V_0 is the first SCF potential; V_s -> V."""
+    g = base.grid
+    dV = smoothed_field(g.N, g.h, seed, -1.0, 1.0)
+    return [base.V + amp * decay ** s * dV for s in range(steps + 1)]

@@ -168,3 +168,29 @@ def test_theorem1_threshold_is_absolute_pivot(cplx):
     np.testing.assert_array_equal(r2.C, dense.block_pencil(A, B, q, False).C)
     r3 = dense.block_pencil(A, B, q, True, singular_tol=ev.min() / 2)
     assert r3.used_p and not r3.backtracked
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("size", [0.02, 0.1, 0.3])
+def test_polar_taylor_against_exact_polar_factor(cplx, size):
+    """Four Taylor terms of (I + Y)^{-1/2} against the polar factor computed
+    from the eigendecomposition of X^H X, within the series' remainder bound
+    (35/128) |Y|^4 / (1 - |Y|) (spectral norms; section 5.5)."""
+    rng = np.random.default_rng(int(size * 100) + cplx)
+    n, m = 300, 24
+    Q, _ = np.linalg.qr(rng.standard_normal((n, m)) + (1j * rng.standard_normal((n, m)) if cplx else 0))
+    E = rng.standard_normal((m, m)) + (1j * rng.standard_normal((m, m)) if cplx else 0)
+    E = dense.sym(E)
+    E *= size / np.linalg.norm(E, 2) / 2.5
+    X = Q @ (np.eye(m) + E)                  # X^H X = (I + E)^2: |Y| about 2 |E|
+    G = dense.sym(X.conj().T @ X)
+    ev, U = np.linalg.eigh(G)
+    exact = X @ (U * ev ** -0.5) @ U.conj().T
+    y = np.linalg.norm(G - np.eye(m), 2)
+    bound = 35 / 128 * y ** 4 / (1 - y)
+    Xt = dense.polar_taylor(X, G)
+    # X (T - (I+Y)^{-1/2}) has spectral norm <= |X|_2 * remainder
+    err = np.linalg.norm(Xt - exact, 2)
+    assert err <= bound * np.linalg.norm(X, 2) * 1.0001 + 1e-14
+    assert err >= 1e-3 * bound          # the truncation is what is measured, not rounding
+    np.testing.assert_allclose(exact.conj().T @ exact, np.eye(m), atol=1e-12)

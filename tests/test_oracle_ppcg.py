@@ -182,3 +182,96 @@ def test_exact_eigenvector_in_start_block():
     assert info.n_dropped > 0
     ex = laplacian_spectrum(8, 0.5, 2)
     np.testing.assert_allclose(lam, ex[:7], atol=1e-11)
+
+
+@pytest.mark.parametrize("orth,kw", [("skip", {}), ("taylor", {"orth_skip": 1e-300}), ("taylor", {}), ("none", {})],
+                         ids=["skip", "taylor-always", "taylor", "none"])
+def test_orthonormalisation_policies(orth, kw):
+    """Section 5.5: omitting steps 18-19 while |Xbar^H Xbar - I|_F is small,
+    the four-term Taylor polar step, or never orthonormalising between
+    Rayleigh-Ritz steps -- every policy still reaches the dense eigenvalues."""
+    p = I.small_problem(N=8, k=12, q=4, order=2, tol=1e-9)
+    (lam, X, info), A = run(p, orth=orth, **kw)
+    check_solution(p, lam, X, info, A, 1e-9)
+    if orth == "none":
+        assert info.n_cholqr == 0 and info.n_taylor == 0 and info.n_orth_skip > 0
+    elif orth == "skip":
+        assert info.n_orth_skip > 0 and info.n_taylor == 0
+    elif kw:
+        assert info.n_taylor > 0 and info.n_orth_skip == 0
+    else:
+        assert info.n_orth_skip > 0
+
+
+def test_rr_schedule():
+    import itertools
+    assert list(itertools.islice(ppcg_ref.rr_schedule(5, 0), 4)) == [5, 10, 15, 20]
+    assert list(itertools.islice(ppcg_ref.rr_schedule(5, 9), 7)) == [9, 17, 24, 30, 35, 40, 45]
+    assert list(itertools.islice(ppcg_ref.rr_schedule(3, 3), 3)) == [3, 6, 9]
+
+
+def test_dynamic_rr_period():
+    """Section 5.6: few Rayleigh-Ritz steps early, then every rr_period."""
+    p = I.small_problem(N=8, k=12, q=4, order=2, tol=1e-9)
+    (lam, X, info), A = run(p, rr_max=10)
+    check_solution(p, lam, X, info, A, 1e-9)
+    sched = ppcg_ref.rr_schedule(5, 10)
+    assert info.rr_iters == [next(sched) for _ in info.rr_iters]
+    assert info.rr_iters[:3] == [10, 19, 27]
+
+
+def test_trace_stopping_criterion():
+    """Section 5.2: stop once the relative change of trace(X^H A X) between
+    iterations is below tol; the returned pairs come from the final
+    Rayleigh-Ritz.  At tol 1e-13 the eigenvalues are the dense ones."""
+    p = I.small_problem(N=8, k=12, q=4, order=2, tol=1e-9)
+    (lam, X, info), A = run(p, stop="trace", tol=1e-13)
+    lb = brute.lowest_values(p.V, 8, 0.5, 2, p.k)
+    assert np.abs(lam - lb).max() / np.abs(lb).max() < 1e-10
+    np.testing.assert_allclose(X.T @ X, np.eye(p.k), atol=1e-12)
+
+
+def _sequence(p, Vs, iters=2):
+    """The oracle over a sequence of potentials: the first solved to tol, each
+    later one iters PPCG iterations without Cholesky-QR from the previous K
+    Ritz vectors."""
+    g = p.grid
+    out = []
+    X0 = p.start()
+    for s, V in enumerate(Vs):
+        A = lambda X, V=V: stencil.apply_h(X, V, g.N, g.h, g.order)
+        T = 1.0 / stencil.diag_h(V, g.h, g.order)
+        kw = {} if s == 0 else dict(max_iter=iters, orth="none")
+        try:
+            lam, X, info = ppcg_ref.ppcg(A, T, X0, p.k, p.q, p.tol, p.rr_period, **kw)
+            st = "ok"
+        except ppcg_ref.NoConvergence as e:
+            lam, info, st = e.lam, e.info, "noconv"
+        X0 = info.X_all
+        out.append((lam, st, info))
+    return out
+
+
+def test_sequence_fixed_point():
+    """A converged subspace is a fixed point of the warm-started steps: with
+    an unchanging potential every step stops at its first loop head and
+    returns the dense eigenvalues."""
+    p = I.small_problem(N=10, k=20, q=4, order=4, tol=1e-9)
+    Vs = I.scf_potentials(p, steps=3, amp=0.0)
+    lb = brute.lowest_values(p.V, 10, 0.5, 4, p.k)
+    for lam, st, info in _sequence(p, Vs):
+        assert st == "ok" and np.abs(lam - lb).max() / np.abs(lb).max() < 1e-10
+
+
+def test_sequence_tracks_changing_potential():
+    """Two iterations per step on a converging sequence of potentials: every
+    step's Ritz values lie above the exact eigenvalues of its potential
+    (Cauchy interlacing) and within 1e-2 of them."""
+    p = I.small_problem(N=10, k=20, q=4, order=4, tol=1e-9)
+    Vs = I.scf_potentials(p, steps=6, amp=0.5, decay=0.7)
+    for s, (lam, st, info) in enumerate(_sequence(p, Vs)):
+        lb = brute.lowest_values(Vs[s], 10, 0.5, 4, p.k)
+        scale = np.abs(lb).max()
+        assert np.all(lam >= lb - 1e-12 * scale)
+        assert np.abs(lam - lb).max() / scale < 1e-2
+        assert (st == "ok") == (s == 0)
