@@ -312,6 +312,21 @@ ppcg_status ppcg_apply_h(ppcg_handle* h, const ppcg_operator* op, int32_t ncols,
 ppcg_status ppcg_block_pencils(ppcg_handle* h, int32_t nblocks, int32_t q, int32_t has_p, int32_t cplx,
                                const double* A, const double* B, double tol, double* C, int32_t* flags);
 
+/* ppcg_block_pencils for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments, results bit-identical to ppcg_block_pencils,
+ * but the packed pencils and the work matrices live in a static device
+ * array of 32 MiB that each GPU the library runs on holds until the process
+ * ends (no hipMalloc, hipFree or other allocating call).  The work is only
+ * enqueued on the handle's stream: C and flags are valid once that stream's
+ * work has completed.  Every call on one GPU shares that array and its
+ * contents: calls that overlap on one GPU (other streams or handles) race.
+ * PPCG_EINVAL when the nblocks pencils need more than 32 MiB (per block:
+ * nS (2 nS - q) + q (q + 1) scalars, plus 4 * 96 * 97 for nS > 48, scalars of
+ * 8 bytes, 16 when complex, each area rounded up to 256 bytes). */
+ppcg_status ppcg_block_pencils_noalloc(ppcg_handle* h, int32_t nblocks, int32_t q, int32_t has_p, int32_t cplx,
+                                       const double* A, const double* B, double tol, double* C, int32_t* flags);
+
 /* Per-kernel accumulated device time (ms) and launch counts since the last
  * reset, for kernels launched while options.profile was set.  names,
  * ms and counts are host arrays of capacity `cap`; returns the number of

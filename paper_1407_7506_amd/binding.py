@@ -103,6 +103,8 @@ def lib():
     L.ppcg_block_pencils.argtypes = [c_void_p, c_int32, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_double,
                                      c_void_p, c_void_p]
     L.ppcg_block_pencils.restype = c_int32
+    L.ppcg_block_pencils_noalloc.argtypes = L.ppcg_block_pencils.argtypes
+    L.ppcg_block_pencils_noalloc.restype = c_int32
     L.ppcg_kernel_times.argtypes = [c_void_p, POINTER(c_char_p), POINTER(c_double), POINTER(c_int64), c_int32]
     L.ppcg_kernel_times.restype = c_int32
     L.ppcg_kernel_stats.argtypes = [c_void_p, POINTER(c_char_p), POINTER(c_double), POINTER(c_int64),
@@ -313,12 +315,14 @@ class Handle:
             raise PPCGError(code, self.error(), {"iters": it.value, "resid": res.value})
         return out, it.value
 
-    def block_pencils(self, A, B, q, has_p, tol=1e-9):
+    def block_pencils(self, A, B, q, has_p, tol=1e-9, noalloc=False):
         """The sub-block projected problems alone: A, B (nblocks, nS, nS)
         CUDA float64 / complex128 tensors (row-major view of column-major
         matrices: element [j, c, r] is row r, column c of block j), nS = 3q
         with P or 2q.  Returns (C (nblocks, q, 3q): C[j, t, i] is row i of
-        eigenvector t, flags (nblocks,) int32)."""
+        eigenvector t, flags (nblocks,) int32).  noalloc=True calls
+        ppcg_block_pencils_noalloc (library scratch in a static device array;
+        the call only enqueues, so the handle's stream is synchronised here)."""
         import torch
         cplx = A.dtype == torch.complex128
         _check_tensor(A, "A", cplx=cplx)
@@ -330,10 +334,13 @@ class Handle:
         B = B.contiguous()
         C = torch.zeros((nb, q, 3 * q), dtype=A.dtype, device=A.device)
         flags = torch.zeros(nb, dtype=torch.int32, device=A.device)
-        code = self._L.ppcg_block_pencils(self._h, int(nb), int(q), 1 if has_p else 0, 1 if cplx else 0, c_void_p(A.data_ptr()),
+        fn = self._L.ppcg_block_pencils_noalloc if noalloc else self._L.ppcg_block_pencils
+        code = fn(self._h, int(nb), int(q), 1 if has_p else 0, 1 if cplx else 0, c_void_p(A.data_ptr()),
                   c_void_p(B.data_ptr()), float(tol), c_void_p(C.data_ptr()), c_void_p(flags.data_ptr()))
         if code != 0:
             raise PPCGError(code, self.error())
+        if noalloc:
+            self.stream.synchronize()
         return C, flags
 
     def density(self):

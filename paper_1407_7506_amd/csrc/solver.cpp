@@ -27,7 +27,39 @@
 #include "kernels.hpp"
 #include "ppcg.h"
 
+#include <mutex>
+
 using namespace ppcg;
+
+// Scratch of ppcg_block_pencils_noalloc, for callers that cannot allocate
+// device memory: a static array that every GPU the library runs on holds
+// until the process ends (each GPU its own copy, at its own address).  Host
+// code must use the address hipGetSymbolAddress returns for the current
+// device, never the array's name (a host-side stand-in).  Calls that overlap
+// on one GPU share it and race.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)32 << 20;
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on `device` (which must be current), resolved
+// once per device
+hipError_t resolve_scratch(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
+}  // namespace
 
 namespace {
 
@@ -281,6 +313,7 @@ struct ppcg_handle {
   hipEvent_t tev[2] = {nullptr, nullptr};
   DBuf gZ, gR, gP, gAP, gY, gw, gsc;  // backward-pass work
   DBuf pen_gram, pen_G, pen_work;     // ppcg_block_pencils inputs in the solver's pencil layout
+  void* noalloc_scratch = nullptr;    // this device's copy of `scratch` (ppcg_block_pencils_noalloc)
   // state of the last successful single solve (for ppcg_grad / ppcg_density)
   bool has_state = false;
   bool s_cplx = false;
@@ -1810,14 +1843,19 @@ void save_tune_table(ppcg_handle* H) {
 // q x q X blocks of A, and for nS > 48 the per-block work matrices.
 struct PencilLayout {
   size_t gram_bytes = 0, g_bytes = 0, work_bytes = 0;
+  size_t g_off = 0, work_off = 0;  // offsets inside one scratch area (256-byte aligned)
+  size_t total() const { return work_off + work_bytes; }
 };
 PencilLayout pencil_layout(int nblocks, int q, bool has_p, bool cplx) {
   const size_t es = cplx ? 16 : 8;
   const int nS = has_p ? 3 * q : 2 * q, Nb = 2 * nS - q;
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
   PencilLayout L;
   L.gram_bytes = (size_t)nblocks * nS * Nb * es;
   L.g_bytes = (size_t)nblocks * q * (q + 1) * es;
   L.work_bytes = nS > 48 ? (size_t)nblocks * pencil_work_elems() * es : 0;
+  L.g_off = al(L.gram_bytes);
+  L.work_off = L.g_off + al(L.g_bytes);
   return L;
 }
 
@@ -1875,6 +1913,10 @@ ppcg_status ppcg_create(ppcg_handle** out, const ppcg_options* opt, void* stream
     return PPCG_EHIP;
   }
   h->st = (hipStream_t)stream;
+  if (resolve_scratch(h->device, &h->noalloc_scratch) != hipSuccess) {
+    delete h;
+    return PPCG_EHIP;
+  }
   if (opt) h->opt = *opt;
   else {
     h->opt.precision = PPCG_FP64;
@@ -2068,6 +2110,26 @@ ppcg_status ppcg_block_pencils(ppcg_handle* h, int32_t nblocks, int32_t q, int32
     enqueue_pencils(h, nblocks, q, has_p != 0, cplx != 0, A, B, tol, C, flags, h->pen_gram.d(), h->pen_G.d(),
                     L.work_bytes ? h->pen_work.p : nullptr);
     sync(h);
+    return PPCG_OK;
+  });
+}
+
+ppcg_status ppcg_block_pencils_noalloc(ppcg_handle* h, int32_t nblocks, int32_t q, int32_t has_p, int32_t cplx,
+                                       const double* A, const double* B, double tol, double* C, int32_t* flags) {
+  if (!h || nblocks < 0 || q < 1 || q > 32 || !(tol > 0) || (nblocks > 0 && (!A || !B || !C || !flags)))
+    return PPCG_EINVAL;
+  return guard(h, [&]() {
+    if (nblocks == 0) return PPCG_OK;
+    const PencilLayout L = pencil_layout(nblocks, q, has_p != 0, cplx != 0);
+    if (L.total() > NOALLOC_SCRATCH_BYTES)
+      throw PpcgError{PPCG_EINVAL, "ppcg_block_pencils_noalloc: " + std::to_string(nblocks) +
+                                       " pencils need " + std::to_string(L.total()) + " bytes of scratch, more than " +
+                                       std::to_string(NOALLOC_SCRATCH_BYTES)};
+    char* base = (char*)h->noalloc_scratch;  // this device's copy of the static array (set by ppcg_create)
+    if (!base) throw PpcgError{PPCG_EHIP, "no-allocation scratch of this device not resolved"};
+    enqueue_pencils(h, nblocks, q, has_p != 0, cplx != 0, A, B, tol, C, flags, (double*)base,
+                    (double*)(base + L.g_off), L.work_bytes ? (void*)(base + L.work_off) : nullptr);
+    HIPCHECK(hipGetLastError());
     return PPCG_OK;
   });
 }
