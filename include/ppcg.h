@@ -230,10 +230,10 @@ ppcg_status ppcg_solve(ppcg_handle* h, const ppcg_operator* op, int32_t k, int32
 /* Backward pass (derivative of the eigen-decomposition).  For the pairs saved
  * by the last successful ppcg_solve on this handle (X n x k, Lambda), and the
  * loss L = sum_i g_lambda[i] lambda_i + sum_r w[r] rho[r] with the density
- * rho = sum_{i<k} x_i^2 (x_i Euclidean-normalised), writes
- *   dL_dV[r] = sum_i g_lambda[i] x_i(r)^2 - 2 sum_i z_i(r) x_i(r),
+ * rho = sum_{i<k} |x_i|^2 (x_i Euclidean-normalised), writes
+ *   dL_dV[r] = sum_i g_lambda[i] |x_i(r)|^2 - 2 Re sum_i conj(z_i(r)) x_i(r),
  * where z_i (orthogonal to X) solves the projected Sternheimer system
- *   Q (H - lambda_i) Q z_i = Q (w .* x_i),  Q = I - X X^T,
+ *   Q (H - lambda_i) Q z_i = Q (w .* x_i),  Q = I - X X^H,
  * by block preconditioned CG (Jacobi 1/(diag(H) - lambda_i) when positive)
  * to relative residual `tol` per column (first-order perturbation of the
  * occupied invariant subspace; d lambda_i / dV = x_i^2 is Hellmann-Feynman).
@@ -243,17 +243,17 @@ ppcg_status ppcg_solve(ppcg_handle* h, const ppcg_operator* op, int32_t k, int32
  *   max_iter  CG iteration cap (<= 0: 10000); iters (may be NULL) receives
  *             the iterations used, resid (may be NULL) the largest relative
  *             residual |r_i| / |b_i| over the columns at exit.
+ * Real and complex Hermitian (Bloch) operators; V, w, g_lambda and dL_dV are
+ * real in both cases.
  * PPCG_ENOCONV when the cap is reached with a column above tol (dL_dV then
  * holds the gradient of the last CG iterate); PPCG_ENOSTATE without a
- * successful solve; PPCG_EINVAL when that solve had a complex operator (real
- * operators only).  Requires a gap between lambda_k and lambda_{k+1} (the
+ * successful solve.  Requires a gap between lambda_k and lambda_{k+1} (the
  * density is not differentiable otherwise). */
 ppcg_status ppcg_grad(ppcg_handle* h, const double* g_lambda, const double* w, double* dL_dV, double tol,
                       int32_t max_iter, int32_t* iters, double* resid);
 
-/* rho[r] = sum_{i<k} x_i(r)^2 for the pairs of the last successful solve
- * (device, n).  PPCG_ENOSTATE without a successful solve, PPCG_EINVAL after a
- * complex one. */
+/* rho[r] = sum_{i<k} |x_i(r)|^2 for the pairs of the last successful solve
+ * (device, n, real).  PPCG_ENOSTATE without a successful solve. */
 ppcg_status ppcg_density(ppcg_handle* h, double* rho);
 
 /* Columns K = k + nbuf of the start block ppcg_solve expects for this handle's

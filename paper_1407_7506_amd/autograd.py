@@ -1,7 +1,8 @@
 """torch.autograd.Function over libppcg: (lambda, rho) = EigDensity.apply(V, cfg).
 
 forward : the k lowest eigenpairs of H(V) = -1/2 Lap_h + diag(V) by ppcg_solve,
-          and the density rho = sum_i x_i^2 by ppcg_density.
+          and the density rho = sum_i |x_i|^2 by ppcg_density (real or complex
+          Hermitian operators: cfg.kpt).
 backward: dL/dV from the incoming gradients (g_lambda, g_rho) by ppcg_grad
           (Hellmann-Feynman for the eigenvalues, projected Sternheimer
           systems for the density).  Every step runs in libppcg.
@@ -25,6 +26,7 @@ class EigConfig:
     rr_period: int = 5
     h: float = 0.5
     order: int = 2
+    kpt: tuple = (0.0, 0.0, 0.0)   # Bloch vector (nonzero: complex Hermitian operator)
     precision: str = "fp64"
     sternheimer_tol: float = 1e-10
     handle: binding.Handle | None = None
@@ -35,7 +37,7 @@ class EigDensity(torch.autograd.Function):
     def forward(ctx, V, cfg: EigConfig):
         h = cfg.handle or binding.Handle(cfg.precision)
         lam, X, info = h.solve(V.detach().contiguous(), cfg.N, cfg.k, cfg.sbsize, cfg.tol, cfg.rr_period,
-                               cfg.X0, h=cfg.h, order=cfg.order)
+                               cfg.X0, h=cfg.h, order=cfg.order, kpt=cfg.kpt)
         rho = h.density()
         ctx.handle = h
         ctx.cfg = cfg

@@ -18,6 +18,7 @@
 // rank indicator of Theorem 1 (C_X singular) answered by re-solving the
 // block without P (Theorem 2).  S is double or zdouble (Hermitian).
 #include <stdexcept>
+#include <type_traits>
 
 #include "common.hpp"
 #include "jacobi.hpp"
@@ -394,58 +395,101 @@ void launch_block_pencil(const PencilArgs& a, hipStream_t st) {
 
 // ---------------------------------------------------------------------------
 // TW: storage of W/P (double, float, zdouble, zfloat); SX: X and arithmetic.
-// One thread per row and RPT rows per thread (256 apart): every lane reads
-// the block's 3q x q coefficients from LDS as broadcasts, so with q = 16
-// those reads, not HBM, bound a one-row-per-thread kernel; two rows per
-// thread halve them per row (real blocks up to 16 columns).
+// Real blocks up to 16 columns: two consecutive rows per thread, read and
+// written as 8- or 16-byte pairs (half the memory instructions of one row
+// per thread, which matters most for the float32 W and P of the mixed path);
+// complex or wider blocks: one row per thread.  The 3q x q coefficients are
+// the same for every lane.
 template <class SX, int QM> constexpr int bupd_rpt() { return (sc_traits<SX>::cplx || QM > 16) ? 1 : 2; }
+#ifndef PPCG_BUPD_SCALAR_C
+#define PPCG_BUPD_SCALAR_C 1
+#endif
+// a value at a workgroup-uniform address of memory the kernel does not write,
+// read through the constant address space (a scalar load into SGPRs)
+template <class S>
+PPCG_DEV S uniform_load(const S* p) {
+  typedef typename sc_traits<S>::real_t R;
+  typedef const __attribute__((address_space(4))) R* CR;
+  CR r = (CR)(const R*)p;
+  if constexpr (sc_traits<S>::cplx) return S{r[0], r[1]};
+  else return r[0];
+}
+
 template <class TW, class SX, int QM>
 PPCG_DEV void block_update_body(const BlockUpdArgs& a, unsigned wg, unsigned nwg) {
   constexpr int RPT = bupd_rpt<SX, QM>();
-  __shared__ SX Cs[3 * QM * QM];
   const int q = a.q;
   const unsigned rtiles = (unsigned)((a.rows + 256 * RPT - 1) / (256 * RPT));
   unsigned L = xcd_remap(wg, nwg);
   int blk = L / rtiles;
-  const long r0 = (long)(L % rtiles) * 256 * RPT + threadIdx.x;
-  const SX* C = (const SX*)a.C + (long)blk * a.cstride;
+  const long r0 = (long)(L % rtiles) * 256 * RPT + (long)threadIdx.x * RPT;  // rows r0 .. r0 + RPT - 1
+  const SX* __restrict__ C = (const SX*)a.C + (long)blk * a.cstride;
   const int ldc = 3 * q;
+#if PPCG_BUPD_SCALAR_C
+  // the coefficients are the same for every lane: read through the constant
+  // address space at workgroup-uniform addresses, i.e. by scalar loads into
+  // SGPRs that the FMAs take as operands (C is not written by this kernel)
+  const SX* Cs = C;
+  constexpr int CLD = 0;  // column t of C at Cs + t * ldc
+#else
+  __shared__ SX Cs[3 * QM * QM];
+  constexpr int CLD = 3 * QM;
   for (int e = threadIdx.x; e < 3 * q * q; e += 256) {
     int i = e % ldc, t = e / ldc;
     Cs[i + t * 3 * QM] = C[i + t * ldc];
   }
   __syncthreads();
+#endif
   const long cb = (long)blk * q * a.ld;
   SX* X = (SX*)a.X + cb;
   TW* W = (TW*)a.W + cb;
   TW* P = (TW*)a.P + cb;
   const SX zero = from_real<SX>(0.0);
   SX x[RPT][QM], w[RPT][QM], p[RPT][QM];
-  bool ok[RPT];
+  // rows is a multiple of 256 and r0 a multiple of RPT: a thread's rows are all in range or all out
+  const bool ok = r0 < a.rows;
 #pragma unroll
-  for (int u = 0; u < RPT; ++u) {
-    const long r = r0 + 256L * u;
-    ok[u] = r < a.rows;
-#pragma unroll
-    for (int i = 0; i < QM; ++i) {
-      if (i < q && ok[u]) {
-        x[u][i] = X[r + i * a.ld];
-        w[u][i] = cvt<SX, TW>(W[r + i * a.ld]);
-        p[u][i] = a.hasP ? cvt<SX, TW>(P[r + i * a.ld]) : zero;
+  for (int i = 0; i < QM; ++i) {
+    if (i < q && ok) {
+      const long o = r0 + i * a.ld;
+      if constexpr (RPT == 2) {  // real: pairs of consecutive rows (ld and r0 even: aligned)
+        typedef typename std::conditional<sizeof(TW) == 8, double2, float2>::type tw2;
+        const double2 xv = *(const double2*)(X + o);
+        const tw2 wv = *(const tw2*)(W + o);
+        x[0][i] = xv.x;
+        x[1][i] = xv.y;
+        w[0][i] = (SX)wv.x;
+        w[1][i] = (SX)wv.y;
+        if (a.hasP) {
+          const tw2 pv = *(const tw2*)(P + o);
+          p[0][i] = (SX)pv.x;
+          p[1][i] = (SX)pv.y;
+        } else {
+          p[0][i] = p[1][i] = zero;
+        }
       } else {
-        x[u][i] = w[u][i] = p[u][i] = zero;
+        x[0][i] = X[o];
+        w[0][i] = cvt<SX, TW>(W[o]);
+        p[0][i] = a.hasP ? cvt<SX, TW>(P[o]) : zero;
       }
+    } else {
+#pragma unroll
+      for (int u = 0; u < RPT; ++u) x[u][i] = w[u][i] = p[u][i] = zero;
     }
   }
   for (int t = 0; t < q; ++t) {
-    const SX* ct = Cs + t * 3 * QM;
+    const SX* ct = Cs + t * (CLD ? CLD : ldc);
     SX pn[RPT], xn[RPT];
 #pragma unroll
     for (int u = 0; u < RPT; ++u) pn[u] = xn[u] = zero;
 #pragma unroll
     for (int i = 0; i < QM; ++i) {
       if (i < q) {
+#if PPCG_BUPD_SCALAR_C
+        const SX cw = uniform_load(ct + q + i), cp = uniform_load(ct + 2 * q + i), cx = uniform_load(ct + i);
+#else
         const SX cw = ct[q + i], cp = ct[2 * q + i], cx = ct[i];
+#endif
 #pragma unroll
         for (int u = 0; u < RPT; ++u) {
           pn[u] += w[u][i] * cw;
@@ -454,13 +498,21 @@ PPCG_DEV void block_update_body(const BlockUpdArgs& a, unsigned wg, unsigned nwg
         }
       }
     }
+    if (ok) {
+      const long o = r0 + t * a.ld;
 #pragma unroll
-    for (int u = 0; u < RPT; ++u) {
-      if (!ok[u]) continue;
-      const long r = r0 + 256L * u;
-      xn[u] += pn[u];
-      P[r + t * a.ld] = cvt<TW, SX>(pn[u]);
-      X[r + t * a.ld] = xn[u];
+      for (int u = 0; u < RPT; ++u) xn[u] += pn[u];
+      if constexpr (RPT == 2) {
+        typedef typename std::conditional<sizeof(TW) == 8, double2, float2>::type tw2;
+        tw2 pv;
+        pv.x = (decltype(pv.x))pn[0];
+        pv.y = (decltype(pv.y))pn[1];
+        *(tw2*)(P + o) = pv;
+        *(double2*)(X + o) = make_double2(xn[0], xn[1]);
+      } else {
+        P[o] = cvt<TW, SX>(pn[0]);
+        X[o] = xn[0];
+      }
     }
   }
 }

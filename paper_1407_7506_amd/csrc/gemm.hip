@@ -7,6 +7,7 @@
 // W = AX - X (X^H A X) (section 2) and the Rayleigh-Ritz Grams and rotation
 // (section 5.6).  Real operands use one MFMA per 16x16x4 tile; complex
 // operands four (real and imaginary parts in separate accumulators).
+#include <stdexcept>
 #include <type_traits>
 
 #include "common.hpp"
@@ -225,12 +226,21 @@ PPCG_DEV void reduce_body(const ReduceArgs& r, unsigned wg, unsigned) {
   long ij = e % per;
   int i = ij % r.M, j = ij / r.M;
   if (r.upper_only && i > j) return;
-  const T* p = (const T*)r.part + ((long)job * r.splits * r.split_stride + i + (long)j * r.ldp) * NC;
   double s0 = 0, s1 = 0;
+  if (CPLX && r.im_off > 0) {  // real partials: real parts, imaginary parts im_off further
+    const T* p = (const T*)r.part + ((long)job * r.splits * r.split_stride + i + (long)j * r.ldp);
 #pragma unroll 8
-  for (int t = 0; t < r.splits; ++t) {
-    s0 += (double)p[(long)t * r.split_stride * NC];
-    if (CPLX) s1 += (double)p[(long)t * r.split_stride * NC + 1];
+    for (int t = 0; t < r.splits; ++t) {
+      s0 += (double)p[(long)t * r.split_stride];
+      s1 += (double)p[(long)t * r.split_stride + r.im_off];
+    }
+  } else {
+    const T* p = (const T*)r.part + ((long)job * r.splits * r.split_stride + i + (long)j * r.ldp) * NC;
+#pragma unroll 8
+    for (int t = 0; t < r.splits; ++t) {
+      s0 += (double)p[(long)t * r.split_stride * NC];
+      if (CPLX) s1 += (double)p[(long)t * r.split_stride * NC + 1];
+    }
   }
   T* dbase = (T*)r.dst + (long)job * r.dst_job_stride * NC;
   T* d = dbase + (i + (long)j * r.ldd) * NC;
@@ -576,6 +586,7 @@ PPCG_DEV void gram_lds_body(const GramArgs& a, unsigned wg, unsigned nwg) {
     pb[q] = (const char*)seg_col(a.B, vb[q] ? cb : 0, a.ld, joff, fb[q], 8);
     sb[q] = a.dsc != nullptr && cb < a.nsc;
   }
+  const int dsh = a.il ? 1 : 0;  // interleaved complex rows: two real rows per grid point
   // 16 x 16 sub-tiles of this wave's quadrant that carry results: inside
   // M x N and, for a diagonal tile of an upper-only Gram, on or above the
   // diagonal (the rest is never read; skipping it leaves every used entry
@@ -599,7 +610,14 @@ PPCG_DEV void gram_lds_body(const GramArgs& a, unsigned wg, unsigned nwg) {
         Load4<T, false>::go(pb[q] + rr * (fb[q] ? 4 : 8), fb[q], rb[q], nullptr);
         if (sb[q]) {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) rb[q][e] *= (T)a.dsc[rr + e];
+          for (int e = 0; e < 4; ++e) rb[q][e] *= (T)a.dsc[(rr + e) >> dsh];
+        }
+        if (a.rotB) {  // (re, im) -> (im, -re): rr is a multiple of 4, so pairs do not straddle quads
+          const T r0 = rb[q][0], r2 = rb[q][2];
+          rb[q][0] = rb[q][1];
+          rb[q][1] = -r0;
+          rb[q][2] = rb[q][3];
+          rb[q][3] = -r2;
         }
       } else {
 #pragma unroll
@@ -1067,6 +1085,7 @@ void launch_gram(const GramArgs& a0, bool f32acc, hipStream_t st) {
     a.lds = ok ? 2 : 0;
   } else if (a.lds) {  // the LDS-staged kernel's preconditions; otherwise the one-wave kernel
     bool ok = !a.cplx && a.njobs == 1 && a.chunk % 32 == 0 && a.ld % 4 == 0;
+    if (a.il && !ok) throw std::invalid_argument("interleaved complex Gram: LDS kernel preconditions not met");
     for (int s = 0; s < a.A.nseg; ++s) ok = ok && aligned16(a.A.p[s]);
     for (int s = 0; s < a.B.nseg; ++s) ok = ok && aligned16(a.B.p[s]);
     a.lds = ok;

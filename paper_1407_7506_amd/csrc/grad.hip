@@ -29,22 +29,27 @@ void launch_coldot(const double* A, const double* B, long ld, long rows, int nco
   if (ncols > 0) hipLaunchKernelGGL(coldot_kernel, dim3(ncols), dim3(256), 0, st, A, B, ld, rows, out);
 }
 
-// Y[r, j] = R[r, j] / (c0 + V[r] - lam[j])  (or R when unprec); zero on padding rows
+// Y[r, j] = R[r, j] / (c0 + V[r] - lam[j])  (or R when unprec); zero on padding rows.
+// nc = 2: complex columns (interleaved), both parts divided by the real diagonal.
 __global__ __launch_bounds__(256) void cg_precond_kernel(const double* R, double* Y, const double* V, double c0,
-                                                         const double* lam, long ld, long n, long rows, int unprec) {
-  long r = blockIdx.x * 256L + threadIdx.x;
+                                                         const double* lam, long ld, long n, long rows, int unprec,
+                                                         int nc) {
+  long e = blockIdx.x * 256L + threadIdx.x;  // element of the (interleaved) column
   int j = blockIdx.y;
-  if (r >= rows) return;
-  double v = R[r + j * ld];
+  if (e >= rows * nc) return;
+  const long r = nc == 2 ? e >> 1 : e;
+  const long o = e + j * ld * nc;
+  double v = R[o];
   if (r >= n) v = 0.0;
   else if (!unprec) v /= (c0 + V[r] - lam[j]);
-  Y[r + j * ld] = v;
+  Y[o] = v;
 }
 void launch_cg_precond(const double* R, double* Y, const double* V, double c0, const double* lam, long ld, long n,
-                       long rows, int ncols, int unprec, hipStream_t st) {
+                       long rows, int ncols, int unprec, hipStream_t st, int cplx) {
+  const int nc = cplx ? 2 : 1;
   if (ncols > 0)
-    hipLaunchKernelGGL(cg_precond_kernel, dim3((rows + 255) / 256, ncols), dim3(256), 0, st, R, Y, V, c0, lam, ld, n,
-                       rows, unprec);
+    hipLaunchKernelGGL(cg_precond_kernel, dim3((rows * nc + 255) / 256, ncols), dim3(256), 0, st, R, Y, V, c0, lam,
+                       ld, n, rows, unprec, nc);
 }
 
 // alpha_j = rz_j / pAp_j (0 when pAp_j <= 0 or the column has converged)
@@ -107,23 +112,45 @@ void launch_cg_check(const double* rr, const double* bb, double tol, int* done, 
   hipLaunchKernelGGL(cg_check_kernel, dim3((k + 255) / 256), dim3(256), 0, st, rr, bb, tol, done, left, k);
 }
 
-// out[r] = sum_j (g_j X[r,j]^2 - 2 Z[r,j] X[r,j]) for r < n  (Z may be null; g null = all ones)
+// out[r] = sum_j (g_j |X[r,j]|^2 - 2 Re(conj(Z[r,j]) X[r,j])) for r < n  (Z may be null; g null = all
+// ones); nc = 2: complex columns (interleaved, leading dimension ld complex elements)
 __global__ __launch_bounds__(256) void grad_rows_kernel(const double* X, const double* Z, const double* g, long ld,
-                                                        long n, int k, double* out) {
+                                                        long n, int k, double* out, int nc) {
   long r = blockIdx.x * 256L + threadIdx.x;
   if (r >= n) return;
   double s = 0;
   for (int j = 0; j < k; ++j) {
-    double x = X[r + j * ld];
-    double t = (g ? g[j] : 1.0) * x;
-    if (Z) t -= 2.0 * Z[r + j * ld];
-    s += t * x;
+    for (int c = 0; c < nc; ++c) {
+      const long o = (r + j * ld) * nc + c;
+      double x = X[o];
+      double t = (g ? g[j] : 1.0) * x;
+      if (Z) t -= 2.0 * Z[o];
+      s += t * x;
+    }
   }
   out[r] = s;
 }
 void launch_grad_rows(const double* X, const double* Z, const double* g, long ld, long n, int k, double* out,
-                      hipStream_t st) {
-  hipLaunchKernelGGL(grad_rows_kernel, dim3((n + 255) / 256), dim3(256), 0, st, X, Z, g, ld, n, k, out);
+                      hipStream_t st, int cplx) {
+  hipLaunchKernelGGL(grad_rows_kernel, dim3((n + 255) / 256), dim3(256), 0, st, X, Z, g, ld, n, k, out,
+                     cplx ? 2 : 1);
+}
+
+// Y[r, j] = w[r] X[r, j] over rows (complex columns: both parts), the right-hand sides w x_i
+__global__ __launch_bounds__(256) void scale_rows_c_kernel(const double* w, const double* X, double* Y, long ld,
+                                                           long rows, int nc) {
+  long e = blockIdx.x * 256L + threadIdx.x;
+  int j = blockIdx.y;
+  if (e >= rows * nc) return;
+  const long o = e + j * ld * nc;
+  Y[o] = w[nc == 2 ? e >> 1 : e] * X[o];
+}
+void launch_scale_rows_c(const double* w, const double* X, double* Y, long ld, long rows, int ncols, int cplx,
+                         hipStream_t st) {
+  const int nc = cplx ? 2 : 1;
+  if (ncols > 0)
+    hipLaunchKernelGGL(scale_rows_c_kernel, dim3((rows * nc + 255) / 256, ncols), dim3(256), 0, st, w, X, Y, ld,
+                       rows, nc);
 }
 
 }  // namespace ppcg

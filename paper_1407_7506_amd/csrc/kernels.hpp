@@ -47,6 +47,11 @@ struct GramArgs {
   int cplx;           // complex operands (f32 segments then mean complex float)
   int lds;            // 1: LDS-staged 128 x 128 workgroup tiles (real, one job, chunk % 32 == 0);
                       // 2: per-block single pass (real, float64 accumulation, M <= 128, N <= 160)
+  int il;             // LDS kernel on complex columns read as real columns of interleaved (re, im)
+                      // rows (ld, rows and chunk in real rows): the row scale dsc is indexed by
+                      // row / 2, and with rotB every B pair (re, im) is taken as (im, -re), so the
+                      // real Gram is Re(A^H B) without and Im(A^H B) with it
+  int rotB;
 };
 
 // Per-block Grams of the 3q x 3q pencils for q = 16, real: only the tiles the
@@ -85,6 +90,8 @@ struct ReduceArgs {
   double alpha, beta;
   int upper_only;
   int cplx;          // complex entries; the mirrored entry of upper_only is conjugated
+  long im_off;       // > 0: complex result from real partials, the imaginary parts at part + im_off
+                     // elements (the two real Grams of an interleaved complex Gram)
 };
 
 struct UpdateArgs {
@@ -359,7 +366,7 @@ int block_jacobi_eig_grouped(const std::vector<EigJob>& jobs, Stage& stage, EigG
 // backward pass (grad.hip)
 void launch_coldot(const double* A, const double* B, long ld, long rows, int ncols, double* out, hipStream_t st);
 void launch_cg_precond(const double* R, double* Y, const double* V, double c0, const double* lam, long ld, long n,
-                       long rows, int ncols, int unprec, hipStream_t st);
+                       long rows, int ncols, int unprec, hipStream_t st, int cplx = 0);
 void launch_cg_alpha(const double* rz, const double* pAp, const int* done, double* alpha, int k, hipStream_t st);
 void launch_cg_beta(double* rz, const double* rznew, const int* done, double* beta, int k, hipStream_t st);
 void launch_cg_xr(double* Z, double* R, const double* P, const double* AP, const double* alpha, long ld, long rows,
@@ -367,7 +374,10 @@ void launch_cg_xr(double* Z, double* R, const double* P, const double* AP, const
 void launch_cg_p(double* P, const double* Y, const double* beta, long ld, long rows, int k, hipStream_t st);
 void launch_cg_check(const double* rr, const double* bb, double tol, int* done, int* left, int k, hipStream_t st);
 void launch_grad_rows(const double* X, const double* Z, const double* g, long ld, long n, int k, double* out,
-                      hipStream_t st);
+                      hipStream_t st, int cplx = 0);
+// Y = diag(w) X over rows x ncols (complex columns: both parts), leading dimension ld elements
+void launch_scale_rows_c(const double* w, const double* X, double* Y, long ld, long rows, int ncols, int cplx,
+                         hipStream_t st);
 
 void launch_prep_diag(const double* V, long n, double c0, double* td, float* V32, double* dmin_part, int nparts,
                       int* nan_flag, hipStream_t st);

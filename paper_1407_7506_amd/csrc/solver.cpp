@@ -320,6 +320,7 @@ struct ppcg_handle {
   int s_N = 0, s_order = 0, s_k = 0;
   long s_n = 0, s_rows = 0, s_ld = 0;
   double s_c0 = 0, s_w1 = 0, s_w2 = 0, s_dmin = 0;
+  double s_ph[3][2][2] = {};          // Bloch phases of that solve's operator
   ~ppcg_handle() {
     if (hcounter) hipHostFree(hcounter);
     for (hipEvent_t e : tev)
@@ -572,7 +573,8 @@ struct Prob {
     int splits;
     long chunk;
   };
-  bool gram_lds_ok(int M, int Nn, int njobs) const { return !cplx && njobs == 1 && std::min(M, Nn) >= 64; }
+  // LDS-staged Grams: real ones, and complex ones as two real Grams over interleaved rows
+  bool gram_lds_ok(int M, int Nn, int njobs) const { return njobs == 1 && std::min(M, Nn) >= 64 && !(cplx && g_rec); }
   // per-block Grams: the single-pass kernel (lds = 2) for real blocks
   bool gram_block_ok(int M, int Nn, int site) const { return !cplx && site == 2 && M <= 128 && Nn <= 160; }
   GramPlan gram_plan(int M, int Nn, int njobs, long rws, int site = 0, const TuneChoice* tc = nullptr) const {
@@ -655,6 +657,31 @@ struct Prob {
       g.lds = pl.lds;
       r.splits = pl.splits;
     };
+    // A complex Gram on the LDS-staged kernel: the columns read as real
+    // columns of 2 rows per grid point, Re(A^H B) from the plain real Gram
+    // and Im(A^H B) = Re(A^H (-i B)) from the one with every B pair (re, im)
+    // taken as (im, -re); both upper-only when the result is Hermitian (the
+    // real part is symmetric, the imaginary part antisymmetric), their split
+    // partials one after the other, joined by the reduction.
+    auto launch_g = [&]() {
+      if (!(cplx && g.lds == 1)) {
+        r.im_off = 0;
+        launch_gram(g, f32acc, st);
+        return;
+      }
+      GramArgs gi = g;
+      gi.cplx = 0;
+      gi.il = 1;
+      gi.ld = 2 * ldab;
+      gi.rows = 2 * rws;
+      gi.chunk = 2 * g.chunk;
+      gi.rotB = 0;
+      launch_gram(gi, f32acc, st);
+      gi.rotB = 1;
+      gi.out = (char*)Wk.part.p + (size_t)g.splits * M * Nn * (f32acc ? 4 : 8);
+      launch_gram(gi, f32acc, st);
+      r.im_off = (long)g.splits * M * Nn;
+    };
     // the Gram and its reduction are idempotent (the reduction overwrites
     // dst), so candidates run in place
     const TuneChoice* tc = nullptr;
@@ -688,7 +715,7 @@ struct Prob {
             }
         TuneChoice best = time_candidates(cands, [&](const TuneChoice& c) {
           set_plan(capped(gram_plan(M, Nn, njobs, rws, site, &c)));
-          launch_gram(g, f32acc, st);
+          launch_g();
           launch_reduce(r, f32acc, st);
         });
         it = H->tune.emplace(key, best).first;
@@ -701,7 +728,7 @@ struct Prob {
       double fl = (upper ? (double)M * (M + 1) * nn : 2.0 * M * Nn * nn) * (cplx ? 4 : 1);
       double by = (double)njobs * (upper ? M : (M + Nn)) * nn * es_in;
       Scope s(prof, name, fl * njobs, by, f32acc ? PEAK_F32 : PEAK_F64);
-      launch_gram(g, f32acc, st);
+      launch_g();
     }
     Scope s(prof, "reduce", 0, 0, PEAK_F64, prof.cat_of(name));
     launch_reduce(r, f32acc, st);
@@ -1630,7 +1657,13 @@ struct Driver {
           phase(cqa, [](Prob& p) { p.enq_cq_a(); });
           sync(H);
           post(cqa, [](Prob& p) { p.post_cq_a(); });
-          phase(cqa, [](Prob& p) { p.enq_cq_b(); });
+          // one phase per decision: grouped launches need the same steps in every problem
+          for (int mode = 0; mode < 3; ++mode) {
+            std::vector<Prob*> grp;
+            for (Prob* p : cqa)
+              if (p->orth_mode == mode) grp.push_back(p);
+            phase(grp, [](Prob& p) { p.enq_cq_b(); });
+          }
         }
         if (!rr.empty()) {
           rayleigh_ritz(rr);
@@ -1668,6 +1701,8 @@ struct Grad {
   Prof& prof;
   int k = 0;
   long n = 0, rows = 0, ld = 0;
+  bool cplx = false;  // complex Hermitian (Bloch) operator: interleaved complex columns
+  int nc = 1;         // doubles per element
   double resid = 0;  // largest |r_i| / |b_i| over the columns at exit
   Grad(ppcg_handle* h) : H(h), st(h->st), prof(h->prof) {}
 
@@ -1677,6 +1712,7 @@ struct Grad {
     s.n = n;
     s.rows = rows;
     s.ld = ld;
+    s.cplx = cplx;
     ColSet A = Prob::cols1(H->work(0).X.p, k, false), B = Prob::cols1(Y, k, false);
     s.gram(A, B, k, k, rows, ld, nullptr, 0, H->gsc.p, (int)round_up(k, 64), false, false, 1, 0, 0, "gram_grad");
     s.update(H->work(0).X.p, ld, k, H->gsc.p, round_up(k, 64), k, Y, nullptr, k, ld, nullptr, nullptr, rows, -1.0,
@@ -1696,30 +1732,36 @@ struct Grad {
     a.V = H->work(0).Vd.p;
     a.f32 = 0;
     a.shift = H->work(0).lam.d();
-    Scope sc(prof, "stencil_f64", (H->s_order == 4 ? 17.0 : 11.0) * n * k, 16.0 * n * k);
+    a.cplx = cplx;
+    std::memcpy(a.ph, H->s_ph, sizeof(a.ph));
+    Scope sc(prof, "stencil_f64", (H->s_order == 4 ? 17.0 : 11.0) * (cplx ? 3 : 1) * n * k, 16.0 * nc * n * k);
     launch_stencil(a, st);
   }
 
   int run(const double* g, const double* w, double* out, double tol, int max_iter) {
     if (!H->has_state) throw PpcgError{PPCG_ENOSTATE, "ppcg_grad needs a successful ppcg_solve on this handle"};
-    if (H->s_cplx) throw PpcgError{PPCG_EINVAL, "ppcg_grad supports real (kappa = 0) operators only"};
     if (!g || !out || !(tol > 0)) throw PpcgError{PPCG_EINVAL, "null pointer or tol <= 0"};
     Work& Wk = H->work(0);
     k = H->s_k;
     n = H->s_n;
     rows = H->s_rows;
     ld = H->s_ld;
+    cplx = H->s_cplx;
+    nc = cplx ? 2 : 1;
     if (!w) {
-      launch_grad_rows(Wk.X.d(), nullptr, g, ld, n, k, out, st);
+      launch_grad_rows(Wk.X.d(), nullptr, g, ld, n, k, out, st, cplx);
       sync(H);
       return 0;
     }
-    const size_t blk = (size_t)ld * k * 8;
+    // complex columns are addressed as real columns of twice the length by
+    // the element-wise CG kernels (the CG scalars Re(a^H b) are real dots)
+    const long ldr = ld * nc, rowsr = rows * nc;
+    const size_t blk = (size_t)ld * k * 8 * nc;
     for (DBuf* b : {&H->gZ, &H->gR, &H->gP, &H->gAP, &H->gY}) b->ensure(blk);
     H->gw.ensure((size_t)rows * 8);
     int kp = (int)round_up(k, 64);
-    H->gsc.ensure((size_t)kp * kp * 8 + (size_t)16 * kp * 8);
-    double* sc = H->gsc.d() + (size_t)kp * kp;  // per-column scalars
+    H->gsc.ensure((size_t)kp * kp * 8 * nc + (size_t)16 * kp * 8);
+    double* sc = H->gsc.d() + (size_t)kp * kp * nc;  // per-column scalars
     double *rz = sc, *rznew = sc + kp, *pAp = sc + 2 * kp, *alpha = sc + 3 * kp, *beta = sc + 4 * kp,
            *bb = sc + 5 * kp, *rr = sc + 6 * kp;
     int* done = (int*)(sc + 7 * kp);
@@ -1727,7 +1769,8 @@ struct Grad {
     // the partial buffer holds the split partials of the k x k projection Gram
     {
       Prob tmp(H, Wk);
-      Wk.part.ensure((size_t)tmp.gram_plan(k, k, 1, rows).splits * k * k * 8);
+      tmp.cplx = cplx;
+      Wk.part.ensure((size_t)tmp.gram_plan(k, k, 1, rows).splits * k * k * 8 * nc);
     }
     HIPCHECK(hipMemsetAsync(H->gw.p, 0, H->gw.bytes, st));
     HIPCHECK(hipMemcpyAsync(H->gw.p, w, n * 8, hipMemcpyDeviceToDevice, st));
@@ -1737,10 +1780,10 @@ struct Grad {
     HIPCHECK(hipMemsetAsync(H->gAP.p, 0, H->gAP.bytes, st));
     double *Z = H->gZ.d(), *R = H->gR.d(), *P = H->gP.d(), *AP = H->gAP.d(), *Y = H->gY.d();
     // b = Q (w x_i)
-    launch_scale_rows(H->gw.d(), Wk.X.p, R, ld, rows, k, 0, st);
+    launch_scale_rows_c(H->gw.d(), Wk.X.d(), R, ld, rows, k, cplx, st);
     project(R);
-    launch_coldot(R, R, ld, rows, k, bb, st);
-    launch_fill(Z, (long)ld * k, 0.0, st);
+    launch_coldot(R, R, ldr, rowsr, k, bb, st);
+    launch_fill(Z, (long)ld * k * nc, 0.0, st);
     launch_zero_int(done, k, st);
     // Jacobi preconditioner 1/(diag(H) - lambda_i) when it is positive definite
     HIPCHECK(hipMemcpyAsync(Wk.hpind, Wk.lam.p, (size_t)k * 8, hipMemcpyDeviceToHost, st));
@@ -1749,20 +1792,20 @@ struct Grad {
     for (int j = 0; j < k; ++j) lmax = std::max(lmax, Wk.hpind[j]);
     int unprec = !(H->s_dmin - lmax > 0);
     auto precond = [&]() {
-      launch_cg_precond(R, Y, Wk.Vd.d(), H->s_c0, Wk.lam.d(), ld, n, rows, k, unprec, st);
+      launch_cg_precond(R, Y, Wk.Vd.d(), H->s_c0, Wk.lam.d(), ld, n, rows, k, unprec, st, cplx);
       project(Y);
     };
     precond();
     HIPCHECK(hipMemcpyAsync(P, Y, blk, hipMemcpyDeviceToDevice, st));
-    launch_coldot(R, Y, ld, rows, k, rz, st);
+    launch_coldot(R, Y, ldr, rowsr, k, rz, st);
     int it = 0;
     for (; it < max_iter; ++it) {
       stencil_shift(P, AP);
       project(AP);
-      launch_coldot(P, AP, ld, rows, k, pAp, st);
+      launch_coldot(P, AP, ldr, rowsr, k, pAp, st);
       launch_cg_alpha(rz, pAp, done, alpha, k, st);
-      launch_cg_xr(Z, R, P, AP, alpha, ld, rows, k, st);
-      launch_coldot(R, R, ld, rows, k, rr, st);
+      launch_cg_xr(Z, R, P, AP, alpha, ldr, rowsr, k, st);
+      launch_coldot(R, R, ldr, rowsr, k, rr, st);
       launch_zero_int(left, 1, st);
       launch_cg_check(rr, bb, tol, done, left, k, st);
       if (it % 4 == 3 || it == max_iter - 1) {
@@ -1774,11 +1817,11 @@ struct Grad {
         }
       }
       precond();
-      launch_coldot(R, Y, ld, rows, k, rznew, st);
+      launch_coldot(R, Y, ldr, rowsr, k, rznew, st);
       launch_cg_beta(rz, rznew, done, beta, k, st);
-      launch_cg_p(P, Y, beta, ld, rows, k, st);
+      launch_cg_p(P, Y, beta, ldr, rowsr, k, st);
     }
-    launch_grad_rows(Wk.X.d(), Z, g, ld, n, k, out, st);
+    launch_grad_rows(Wk.X.d(), Z, g, ld, n, k, out, st, cplx);
     HIPCHECK(hipMemcpyAsync(Wk.hpind, rr, (size_t)k * 8, hipMemcpyDeviceToHost, st));
     HIPCHECK(hipMemcpyAsync(Wk.hpind + k, bb, (size_t)k * 8, hipMemcpyDeviceToHost, st));
     sync(H);
@@ -1988,6 +2031,7 @@ ppcg_status ppcg_solve(ppcg_handle* h, const ppcg_operator* op, int32_t k, int32
     h->s_w1 = p.w1;
     h->s_w2 = p.w2;
     h->s_dmin = p.dmin;
+    std::memcpy(h->s_ph, p.ph, sizeof(p.ph));
     return PPCG_OK;
   });
 }
@@ -2049,8 +2093,7 @@ ppcg_status ppcg_density(ppcg_handle* h, double* rho) {
   if (!h || !rho) return PPCG_EINVAL;
   return guard(h, [&]() {
     if (!h->has_state) throw PpcgError{PPCG_ENOSTATE, "ppcg_density needs a successful ppcg_solve on this handle"};
-    if (h->s_cplx) throw PpcgError{PPCG_EINVAL, "ppcg_density supports real (kappa = 0) operators only"};
-    launch_grad_rows(h->work(0).X.d(), nullptr, nullptr, h->s_ld, h->s_n, h->s_k, rho, h->st);
+    launch_grad_rows(h->work(0).X.d(), nullptr, nullptr, h->s_ld, h->s_n, h->s_k, rho, h->st, h->s_cplx);
     HIPCHECK(hipGetLastError());
     sync(h);
     return PPCG_OK;

@@ -105,6 +105,7 @@ SMALL = [
     dict(N=8, k=6, q=1, order=2, kpt=(0.6, 0.0, 0.0)),
     dict(N=10, k=15, q=5, order=2, kpt=(0.5, 0.5, 0.0), rr_period=1),
     dict(N=12, k=60, q=32, order=4, kpt=bloch_kpt(12)),   # q = 32: complex 96 x 96 pencils in device scratch
+    dict(N=16, k=120, q=8, order=4, kpt=bloch_kpt(16)),   # K = 128: complex Grams on the LDS kernel (interleaved)
 ]
 
 
@@ -135,7 +136,7 @@ def test_complex_fp64_matches_oracle_and_brute(h64, case):
         assert subspace_dist(X, Xo) < 1e-6
 
 
-@pytest.mark.parametrize("case", SMALL[:4], ids=_ids)
+@pytest.mark.parametrize("case", SMALL[:4] + SMALL[-1:], ids=_ids)
 def test_complex_mixed_matches_oracle(hmix, case):
     p = I.small_problem(tol=1e-8, **case)
     if p.nbuf != I.default_nbuf(p.k, p.q):
@@ -180,13 +181,16 @@ def test_complex_deterministic(h64):
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
-def test_grad_refuses_complex_state(h64):
-    p = I.small_problem(N=8, k=12, q=4, order=2, kpt=(0.9, 0.0, 0.0), tol=1e-8)
-    gpu_solve(h64, p)
-    with pytest.raises(B.PPCGError):
-        h64.grad(dev(np.ones(p.k)))
-    with pytest.raises(B.PPCGError):
-        h64.density()
+def test_density_and_hellmann_feynman_complex(h64):
+    """Density sum_i |x_i|^2 and the eigenvalue part of dL/dV (w = 0) of a
+    Bloch solve: both equal sum_i g_i |x_i|^2 of the returned vectors."""
+    p = I.small_problem(N=8, k=12, q=4, order=2, kpt=(0.9, 0.0, 0.0), tol=1e-10)
+    lam, X, info = gpu_solve(h64, p)
+    rho = h64.density().cpu().numpy()
+    np.testing.assert_allclose(rho, np.sum(np.abs(X) ** 2, axis=1), atol=1e-12)
+    g = np.arange(1.0, p.k + 1)
+    hf, its = h64.grad(dev(g))
+    np.testing.assert_allclose(hf.cpu().numpy(), (np.abs(X) ** 2) @ g, atol=1e-12)
 
 
 def test_batch_complex_matches_single(h64):
@@ -246,4 +250,25 @@ def test_bloch96_full_size_properties():
             "resid", np.linalg.norm(hx - lam[i] * x))
         assert abs(nx2 - 1.0) <= 1e-10      # rounding of K = 2112-term rotations, as orth_err
         assert abs(rq - lam[i]) <= 1e-10 * scale
+    h.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_complex_autotuned_lds_grams(prec):
+    """Autotuned handle on a complex K = 128 problem: the tuner times the
+    interleaved LDS Gram (two real Grams, Re and Im, over (re, im) rows)
+    against the one-wave complex kernel; whatever it keeps, the solve agrees
+    with the oracle, and repeated solves repeat bit for bit."""
+    p = I.small_problem(N=16, k=120, q=8, order=4, kpt=bloch_kpt(16), tol=1e-9 if prec == "fp64" else 1e-8)
+    h = B.Handle(prec, max_iter=MAX_IT, autotune=True)
+    a = gpu_solve(h, p)
+    b = gpu_solve(h, p)
+    rep = h.tune_report()
+    say(rep)
+    assert "complex" in rep and "lds/" in rep
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    lo, Xo, io = oracle_solve(p, p.tol)
+    err = np.abs(a[0] - lo).max() / np.abs(lo).max()
+    say(prec, "autotuned complex err", err, "iters", a[2]["iters"], io.iters)
+    assert err <= p.tol
     h.close()

@@ -102,3 +102,75 @@ def test_fd_directions_wells32():
         worst = max(worst, rel)
         say(f"dir {i}: fd {fd:.10f} analytic {an:.10f} rel {rel:.2e}")
     assert worst <= 1e-4
+
+
+@pytest.mark.parametrize("kpt", [(0.7, 0.0, 0.0), (0.2, 0.4, 0.1)])
+def test_grad_complex_matches_dense_formula(kpt):
+    """Complex Hermitian (Bloch) operator: the block Sternheimer CG on
+    interleaved complex columns against the dense double sum
+    2 Re(conj(x_i(r)) x_j(r) conj(x_j(s)) x_i(s)) / (lambda_i - lambda_j)."""
+    N, k, q = 8, 6, 2
+    V = I.gaussian_wells(N, 0.5, 2, 11)
+    H = stencil.assemble_h(V, N, 0.5, 2, kpt)
+    lam_all, X_all = np.linalg.eigh(H)
+    assert lam_all[k] - lam_all[k - 1] > 1e-3
+    rng = np.random.default_rng(3)
+    g = rng.standard_normal(k)
+    w = rng.standard_normal(N ** 3)
+    h = B.Handle("fp64", max_iter=MAX_IT)
+    K = h.columns(k, q)
+    lam, X, info = h.solve(dev(V), N, k, q, 1e-12, 5, dev(I.start_block(N ** 3, K, 5, complex_=True)), kpt=kpt)
+    dV, its = h.grad(dev(g), dev(w), tol=1e-13)
+    ref = ograd.dense_grad(lam_all, X_all, k, g, w)
+    err = np.abs(dV.cpu().numpy() - ref).max() / np.abs(ref).max()
+    say("complex dense grad err", err, "cg iters", its)
+    assert err <= 1e-8
+    assert abs(dV.sum().item() - g.sum()) <= 1e-9 * max(1.0, abs(g.sum()))
+
+
+def test_grad_complex_matches_oracle_sternheimer():
+    p = I.small_problem(N=12, k=20, q=4, order=4, kpt=(0.5, 0.0, 0.0), tol=1e-11)
+    g = p.grid
+    h = B.Handle("fp64", max_iter=MAX_IT)
+    lam, X, info = h.solve(dev(p.V), g.N, p.k, p.q, 1e-11, p.rr_period, dev(p.start()), order=g.order, kpt=g.kpt)
+    w = I.loss_weights(g.n, 306)
+    gl = np.ones(p.k)
+    dV, its = h.grad(dev(gl), dev(w), tol=1e-11)
+    Xn, ln = X.cpu().numpy(), lam.cpu().numpy()
+    A = lambda Y: stencil.apply_h(Y, p.V, g.N, g.h, g.order, g.kpt)
+    ref, oit, rel = ograd.sternheimer_grad(A, stencil.diag_h(p.V, g.h, g.order), Xn, ln, gl, w, tol=1e-11)
+    err = np.abs(dV.cpu().numpy() - ref).max() / np.abs(ref).max()
+    say("complex grad vs oracle", err, "cg iters gpu/oracle", its, oit)
+    assert err <= 1e-7
+
+
+def test_fd_directions_complex():
+    """Central finite differences (step 1e-5) of L = sum lambda + w . rho
+    through EigDensity on a Bloch operator, 8 seeded directions."""
+    p = I.small_problem(N=10, k=12, q=4, order=4, kpt=(0.6, 0.0, 0.0), tol=1e-12)
+    g = p.grid
+    w = dev(I.loss_weights(g.n, 307))
+    X0 = dev(p.start())
+    V = dev(p.V).requires_grad_(True)
+    cfg = EigConfig(N=g.N, k=p.k, sbsize=p.q, X0=X0, tol=1e-12, rr_period=p.rr_period, order=g.order, kpt=g.kpt,
+                    sternheimer_tol=1e-12)
+    lam, rho = EigDensity.apply(V, cfg)
+    L = lam.sum() + (w * rho).sum()
+    L.backward()
+    dV = V.grad.detach()
+    h = B.Handle("fp64", max_iter=MAX_IT)
+    eps = 1e-5
+
+    def loss(Vv):
+        lm, Xm, _ = h.solve(Vv, g.N, p.k, p.q, 1e-12, p.rr_period, X0, order=g.order, kpt=g.kpt)
+        return lm.sum().item() + (w * h.density()).sum().item()
+
+    worst = 0.0
+    for i, d in enumerate(I.unit_directions(g.n, 8, 408)):
+        dd = dev(d)
+        fd = (loss(V.detach() + eps * dd) - loss(V.detach() - eps * dd)) / (2 * eps)
+        an = torch.dot(dV, dd).item()
+        rel = abs(fd - an) / max(abs(fd), 1e-3)
+        worst = max(worst, rel)
+        say(f"complex dir {i}: fd {fd:.10f} analytic {an:.10f} rel {rel:.2e}")
+    assert worst <= 1e-4
