@@ -22,3 +22,11 @@ def lowest(V, N, h, order, k, kpt=(0.0, 0.0, 0.0)):
 def lowest_values(V, N, h, order, k, kpt=(0.0, 0.0, 0.0)):
     """The k smallest eigenvalues of H (values only, numpy.linalg.eigvalsh)."""
     return np.linalg.eigvalsh(assemble_h(V, N, h, order, kpt))[:k]
+
+
+def lowest_values_gen(V, N, h, order, k, b, kpt=(0.0, 0.0, 0.0)):
+    """The k smallest eigenvalues of H x = lambda diag(b) x (scipy.linalg.eigh
+    of the pencil, values only)."""
+    import scipy.linalg as sla
+    H = assemble_h(V, N, h, order, kpt)
+    return sla.eigh(H, np.diag(np.asarray(b, dtype=np.float64)), eigvals_only=True)[:k]

@@ -55,9 +55,10 @@ def sym(M: np.ndarray) -> np.ndarray:
     return 0.5 * (M + M.conj().T)
 
 
-def cholqr(X: np.ndarray):
-    """Return (X R^{-1}, R) with R upper triangular, R^H R = sym(X^H X)."""
-    G = sym(X.conj().T @ X)
+def cholqr(X: np.ndarray, BX: np.ndarray | None = None):
+    """Return (X R^{-1}, R) with R upper triangular, R^H R = sym(X^H X), or
+    sym(X^H B X) when BX = B X is given (B-orthonormal result)."""
+    G = sym(X.conj().T @ (X if BX is None else BX))
     try:
         R = sla.cholesky(G, lower=False)
     except np.linalg.LinAlgError as e:
@@ -149,11 +150,12 @@ def polar_taylor(X: np.ndarray, G: np.ndarray) -> np.ndarray:
     return X @ T
 
 
-def rayleigh_ritz(S: np.ndarray, AS: np.ndarray):
-    """Ritz pairs of span(S): sym(S^H A S) C = sym(S^H S) C Omega, C^H S^H S C = I,
-    all columns, ascending.  Returns (S C, Omega, C)."""
+def rayleigh_ritz(S: np.ndarray, AS: np.ndarray, BS: np.ndarray | None = None):
+    """Ritz pairs of span(S): sym(S^H A S) C = sym(S^H B S) C Omega,
+    C^H S^H B S C = I (B = I when BS is None), all columns, ascending.
+    Returns (S C, Omega, C)."""
     SAS = sym(S.conj().T @ AS)
-    SS = sym(S.conj().T @ S)
+    SS = sym(S.conj().T @ (S if BS is None else BS))
     try:
         L = sla.cholesky(SS, lower=True)
     except np.linalg.LinAlgError as e:

@@ -83,7 +83,7 @@ def rr_schedule(rr_period, rr_max):
 
 def ppcg(apply_a, tdiag, X0, k, sbsize, tol, rr_period, max_iter=20000, record=False,
          singular_tol=dense.PIVOT_TOL, orth="cholqr", orth_skip=0.1, orth_taylor=0.3, rr_max=0,
-         stop="residual"):
+         stop="residual", bdiag=None):
     """Lowest k eigenpairs of the Hermitian operator ``apply_a`` (n x m -> n x m).
 
     tdiag : (n,) diagonal of the preconditioner T (Jacobi: 1/diag(H)), must be > 0.
@@ -103,6 +103,12 @@ def ppcg(apply_a, tdiag, X0, k, sbsize, tol, rr_period, max_iter=20000, record=F
             "trace" -- relative change of trace(X^H A X) (all K columns)
             between consecutive loop heads below tol, then the final
             Rayleigh-Ritz without the fresh check (section 5.2).
+    bdiag : (n,) positive diagonal of B for the generalized problem
+            A x = lambda B x (section 1: the method carries over without
+            factoring B): every inner product of the method becomes a B inner
+            product -- X^H B X = I, residual A X - B X (X^H A X), projector
+            I - X (B X)^H, sub-block and Rayleigh-Ritz Grams S^H B S.
+            None: B = I.
     Returns (lam[:k] ascending, X[:, :k], Info).  Raises RankError on a
     Cholesky breakdown and NoConvergence after max_iter iterations.
     """
@@ -115,17 +121,23 @@ def ppcg(apply_a, tdiag, X0, k, sbsize, tol, rr_period, max_iter=20000, record=F
         raise ValueError("preconditioner is not positive definite")
     if orth not in ORTH or stop not in ("residual", "trace"):
         raise ValueError("invalid orth or stop")
+    if bdiag is not None:
+        bdiag = np.asarray(bdiag, dtype=np.float64)
+        if np.any(~(bdiag > 0)):
+            raise ValueError("B is not positive definite")
+    Bm = (lambda Y: Y) if bdiag is None else (lambda Y: bdiag[:, None] * Y)
     sched = rr_schedule(rr_period, rr_max)
     next_rr = next(sched)
     trace_prev = None
     info = Info()
 
     # steps 1-4: orthonormal start, residual W = AX - X (X^H A X)
-    X, _ = cholqr(np.array(X0, dtype=np.result_type(X0.dtype, np.float64)))
+    X0 = np.array(X0, dtype=np.result_type(X0.dtype, np.float64))
+    X, _ = cholqr(X0, Bm(X0))
     nl = 0
     AXa = apply_a(X)
     G = sym(X.conj().T @ AXa)
-    W = AXa - X @ G
+    W = AXa - Bm(X) @ G
     P = None
     lock_wn = np.zeros(0)
     lock_lam = np.zeros(0)
@@ -134,9 +146,9 @@ def ppcg(apply_a, tdiag, X0, k, sbsize, tol, rr_period, max_iter=20000, record=F
     def rr_and_lock(X, nl, P):
         """Rayleigh-Ritz over [X, X_lock] then locking (RR branch)."""
         AS = apply_a(X)
-        Xn, lam, _ = rayleigh_ritz(X, AS)
+        Xn, lam, _ = rayleigh_ritz(X, AS, Bm(X))
         AXn = apply_a(Xn)
-        Wall = AXn - Xn * lam[None, :]
+        Wall = AXn - Bm(Xn) * lam[None, :]
         wn = np.sqrt(np.real(np.sum(Wall[:, :k].conj() * Wall[:, :k], axis=0)))
         fresh = math.sqrt(_fro2(Wall[:, :k])) / max(np.linalg.norm(lam[:k]), np.finfo(float).tiny)
         thr = 0.5 * tol * np.linalg.norm(lam[:k]) / math.sqrt(k)
@@ -183,7 +195,7 @@ def ppcg(apply_a, tdiag, X0, k, sbsize, tol, rr_period, max_iter=20000, record=F
         if it > max_iter:
             info.iters = it - 1
             info.n_locked = nl
-            X2, lam, _ = rayleigh_ritz(X, apply_a(X))
+            X2, lam, _ = rayleigh_ritz(X, apply_a(X), Bm(X))
             info.X_all, info.lam_all = X2, lam
             raise NoConvergence("max_iter reached", lam[:k], X2[:, :k], info)
 
@@ -192,14 +204,16 @@ def ppcg(apply_a, tdiag, X0, k, sbsize, tol, rr_period, max_iter=20000, record=F
         # step 8: precondition
         W = tdiag[:, None] * W
         # step 9: W <- (I - X X^H) W, then (I - X_lock X_lock^H) W
-        W = W - Xa @ (Xa.conj().T @ W)
+        # (generalized problem: the B-orthogonal projector I - X (B X)^H)
+        BXa, BXL = Bm(Xa), Bm(XL)
+        W = W - Xa @ (BXa.conj().T @ W)
         if nl:
-            W = W - XL @ (XL.conj().T @ W)
+            W = W - XL @ (BXL.conj().T @ W)
         # step 10: same for P
         if P is not None:
-            P = P - Xa @ (Xa.conj().T @ P)
+            P = P - Xa @ (BXa.conj().T @ P)
             if nl:
-                P = P - XL @ (XL.conj().T @ P)
+                P = P - XL @ (BXL.conj().T @ P)
         AW = apply_a(W)
         AP = apply_a(P) if P is not None else None
         # steps 11-16: independent projected problems per sub-block
@@ -216,7 +230,7 @@ def ppcg(apply_a, tdiag, X0, k, sbsize, tol, rr_period, max_iter=20000, record=F
             S = np.concatenate(blocks, axis=1)
             AS = np.concatenate(ablocks, axis=1)
             Aj = sym(S.conj().T @ AS)
-            Bj = sym(S.conj().T @ S)
+            Bj = sym(S.conj().T @ Bm(S))
             nx = c1 - c0
             res = block_pencil(Aj, Bj, nx, P is not None, singular_tol=singular_tol)
             C = res.C
@@ -234,7 +248,7 @@ def ppcg(apply_a, tdiag, X0, k, sbsize, tol, rr_period, max_iter=20000, record=F
         P = Pn
         if it != next_rr:
             # steps 17-20: orthonormalise (or not, section 5.5), new residual
-            G1 = sym(Xbar.conj().T @ Xbar)
+            G1 = sym(Xbar.conj().T @ Bm(Xbar))
             e = float(np.linalg.norm(G1 - np.eye(G1.shape[0])))
             if orth == "none" or (orth in ("skip", "taylor") and e <= orth_skip):
                 Xa = Xbar
@@ -243,12 +257,12 @@ def ppcg(apply_a, tdiag, X0, k, sbsize, tol, rr_period, max_iter=20000, record=F
                 Xa = dense.polar_taylor(Xbar, G1)
                 info.n_taylor += 1
             else:
-                Xa, _ = cholqr(Xbar)
+                Xa, _ = cholqr(Xbar, Bm(Xbar))
                 info.n_cholqr += 1
             X = np.concatenate([XL, Xa], axis=1)
             AXa = apply_a(Xa)
             G = sym(Xa.conj().T @ AXa)
-            W = AXa - Xa @ G
+            W = AXa - Bm(Xa) @ G
         else:
             # steps 21-31: Rayleigh-Ritz over [X, X_lock], then locking
             X = np.concatenate([XL, Xbar], axis=1)

@@ -242,3 +242,10 @@ def scf_potentials(base: Problem, steps: int = 14, amp: float = 0.5, decay: floa
     g = base.grid
     dV = smoothed_field(g.N, g.h, seed, -1.0, 1.0)
     return [base.V + amp * decay ** s * dV for s in range(steps + 1)]
+
+
+def mass_weights(N: int, h: float, seed: int, lo: float = 0.8, hi: float = 1.25) -> np.ndarray:
+    """Positive diagonal B of a generalized problem H x = lambda B x (a
+    position-dependent weight, e.g. a lumped overlap or metric): a smoothed
+    N(0,1) field (width 2h) mapped onto [lo, hi] from its own seed."""
+    return smoothed_field(N, h, seed, lo, hi)

@@ -275,3 +275,31 @@ def test_sequence_tracks_changing_potential():
         assert np.all(lam >= lb - 1e-12 * scale)
         assert np.abs(lam - lb).max() / scale < 1e-2
         assert (st == "ok") == (s == 0)
+
+
+@pytest.mark.parametrize("kpt", [(0.0, 0.0, 0.0), (0.7, 0.0, 0.0)], ids=["real", "bloch"])
+def test_generalized_problem_matches_pencil_eigh(kpt):
+    """Section 1: H x = lambda B x with B HPD (here diagonal), solved without
+    factoring B -- B inner products throughout.  Against scipy's eigh of the
+    pencil; X^H B X = I and |H X - B X Lambda| small."""
+    p = I.small_problem(N=8, k=12, q=4, order=4, tol=1e-9, kpt=kpt)
+    g = p.grid
+    b = I.mass_weights(g.N, g.h, 17)
+    (lam, X, info), A = run(p, bdiag=b)
+    ref = brute.lowest_values_gen(p.V, g.N, g.h, g.order, p.k, b, g.kpt)
+    scale = np.abs(ref).max()
+    assert np.abs(lam - ref).max() / scale < 1e-10
+    assert np.all(lam >= ref - 1e-12 * scale)
+    np.testing.assert_allclose(X.conj().T @ (b[:, None] * X), np.eye(p.k), atol=1e-12)
+    R = A(X) - (b[:, None] * X) * lam[None, :]
+    assert np.linalg.norm(R) / np.linalg.norm(lam) <= 1e-9 * 1.0001
+
+
+def test_generalized_with_identity_is_the_standard_solve():
+    """B = I: the generalized solve is the standard one (up to the rounding
+    of forming X^H X as a product of two arrays)."""
+    p = I.small_problem(N=8, k=12, q=4, order=2, tol=1e-9)
+    (l1, X1, i1), _ = run(p)
+    (l2, X2, i2), _ = run(p, bdiag=np.ones(p.grid.n))
+    assert np.abs(l1 - l2).max() / np.abs(l1).max() < 1e-13
+    assert abs(i1.iters - i2.iters) <= 10
