@@ -163,6 +163,13 @@ typedef struct {
                            operator, otherwise complex Hermitian blocks */
   const double* V;      /* device, n potential values */
   int32_t precond;      /* ppcg_precond; only PPCG_PRECOND_JACOBI */
+  const double* B;      /* device, n positive values, or NULL: the generalized
+                           problem H x = lambda B x with B = diag(B) (section 1:
+                           solved without factoring B, every inner product of
+                           the method a B inner product, X^H B X = I on return).
+                           Single FP64 solves only (PPCG_EINVAL with PPCG_MIXED,
+                           in ppcg_solve_batched, and in ppcg_grad after such a
+                           solve); B <= 0 anywhere is PPCG_ENOTHPD */
 } ppcg_operator;
 
 typedef struct {

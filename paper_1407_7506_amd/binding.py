@@ -57,7 +57,7 @@ STOP = {"residual": 0, "trace": 1}
 
 class Operator(ctypes.Structure):
     _fields_ = [("nx", c_int32), ("h", c_double), ("order", c_int32), ("kpt", c_double * 3),
-                ("V", c_void_p), ("precond", c_int32)]
+                ("V", c_void_p), ("precond", c_int32), ("B", c_void_p)]
 
 
 class Info(ctypes.Structure):
@@ -188,9 +188,12 @@ class Handle:
         return self._L.ppcg_last_error(self._h).decode()
 
     @staticmethod
-    def operator(V, N, h=0.5, order=2, kpt=(0.0, 0.0, 0.0)):
+    def operator(V, N, h=0.5, order=2, kpt=(0.0, 0.0, 0.0), B=None):
         _check_tensor(V, "V", N ** 3)
-        return Operator(int(N), float(h), int(order), (c_double * 3)(*kpt), c_void_p(V.data_ptr()), 1)
+        if B is not None:
+            _check_tensor(B, "B", N ** 3)
+        return Operator(int(N), float(h), int(order), (c_double * 3)(*kpt), c_void_p(V.data_ptr()), 1,
+                        c_void_p(B.data_ptr()) if B is not None else None)
 
     def columns(self, k, sbsize):
         """K = k + nbuf columns the start block must have."""
@@ -214,10 +217,11 @@ class Handle:
             raise PPCGError(code, self.error())
         return Y
 
-    def solve(self, V, N, k, sbsize, tol, rr_period, X0, h=0.5, order=2, check=True, kpt=(0.0, 0.0, 0.0)):
+    def solve(self, V, N, k, sbsize, tol, rr_period, X0, h=0.5, order=2, check=True, kpt=(0.0, 0.0, 0.0), B=None):
         """Lowest k eigenpairs.  X0: (n, K) start block (torch CUDA float64, or
         complex128 for a nonzero Bloch vector kpt), or None for a start block
-        drawn on the device from the handle's seed.
+        drawn on the device from the handle's seed.  B: optional diagonal of the
+        generalized problem H x = lambda B x (CUDA float64, n).
         Returns (lam (k,), X (n, k), info dict)."""
         import torch
         n = N ** 3
@@ -234,7 +238,7 @@ class Handle:
         kout = K if self.return_buffers else k
         Xout = torch.empty((kout, n), dtype=dt, device=V.device)
         lam = torch.empty(kout, dtype=torch.float64, device=V.device)
-        op = self.operator(V, N, h, order, kpt)
+        op = self.operator(V, N, h, order, kpt, B)
         info = Info()
         code = self._L.ppcg_solve(self._h, byref(op), int(k), int(sbsize), float(tol), int(rr_period),
                                   c_void_p(X0cm.data_ptr()) if X0cm is not None else None,

@@ -112,7 +112,7 @@ PPCG_DEV void gram_body(const GramArgs& a, unsigned wg, unsigned nwg) {
   const void* pa[TM];
   bool fa[TM], va[TM];
   const void* pb[TN];
-  bool fb[TN], vb[TN], sb[TN];
+  bool fb[TN], vb[TN], sb[TN], sb2[TN];
 #pragma unroll
   for (int t = 0; t < TM; ++t) {
     int c = i0 + 16 * t + lc;
@@ -125,6 +125,7 @@ PPCG_DEV void gram_body(const GramArgs& a, unsigned wg, unsigned nwg) {
     vb[t] = c < a.N;
     pb[t] = seg_col(a.B, vb[t] ? c : 0, a.ld, joff, fb[t], esz64);
     sb[t] = a.dsc != nullptr && c < a.nsc;
+    sb2[t] = a.dsc2 != nullptr && c >= a.nsc;
   }
   acc_t acc[NC][TM][TN];
 #pragma unroll
@@ -147,11 +148,16 @@ PPCG_DEV void gram_body(const GramArgs& a, unsigned wg, unsigned nwg) {
         for (int e = 0; e < Q; ++e) ar[t][e] = ai[t][e] = 0;
       }
     }
-    T dv[Q];
+    T dv[Q], dv2[Q];
     if (a.dsc) {
       const double* dp = a.dsc + rr;
 #pragma unroll
       for (int e = 0; e < Q; ++e) dv[e] = (T)dp[e];
+    }
+    if (a.dsc2) {
+      const double* dp = a.dsc2 + rr;
+#pragma unroll
+      for (int e = 0; e < Q; ++e) dv2[e] = (T)dp[e];
     }
 #pragma unroll
     for (int t = 0; t < TN; ++t) {
@@ -163,6 +169,13 @@ PPCG_DEV void gram_body(const GramArgs& a, unsigned wg, unsigned nwg) {
           for (int e = 0; e < Q; ++e) {
             br[t][e] *= dv[e];
             if (CPLX) bi[t][e] *= dv[e];
+          }
+        }
+        if (sb2[t]) {
+#pragma unroll
+          for (int e = 0; e < Q; ++e) {
+            br[t][e] *= dv2[e];
+            if (CPLX) bi[t][e] *= dv2[e];
           }
         }
       } else {
@@ -575,7 +588,7 @@ PPCG_DEV void gram_lds_body(const GramArgs& a, unsigned wg, unsigned nwg) {
   const int part = tid % PQ;
   const char* pa[NQ];
   const char* pb[NQ];
-  bool fa[NQ], fb[NQ], va[NQ], vb[NQ], sb[NQ];
+  bool fa[NQ], fb[NQ], va[NQ], vb[NQ], sb[NQ], sb2[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     const int col = tid / PQ + q * CS;
@@ -585,6 +598,7 @@ PPCG_DEV void gram_lds_body(const GramArgs& a, unsigned wg, unsigned nwg) {
     pa[q] = (const char*)seg_col(a.A, va[q] ? ca : 0, a.ld, joff, fa[q], 8);
     pb[q] = (const char*)seg_col(a.B, vb[q] ? cb : 0, a.ld, joff, fb[q], 8);
     sb[q] = a.dsc != nullptr && cb < a.nsc;
+    sb2[q] = a.dsc2 != nullptr && cb >= a.nsc;
   }
   const int dsh = a.il ? 1 : 0;  // interleaved complex rows: two real rows per grid point
   // 16 x 16 sub-tiles of this wave's quadrant that carry results: inside
@@ -611,6 +625,10 @@ PPCG_DEV void gram_lds_body(const GramArgs& a, unsigned wg, unsigned nwg) {
         if (sb[q]) {
 #pragma unroll
           for (int e = 0; e < 4; ++e) rb[q][e] *= (T)a.dsc[(rr + e) >> dsh];
+        }
+        if (sb2[q]) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) rb[q][e] *= (T)a.dsc2[(rr + e) >> dsh];
         }
         if (a.rotB) {  // (re, im) -> (im, -re): rr is a multiple of 4, so pairs do not straddle quads
           const T r0 = rb[q][0], r2 = rb[q][2];
@@ -1079,7 +1097,7 @@ void launch_gram(const GramArgs& a0, bool f32acc, hipStream_t st) {
       a0 = a.A.end[sA];
     }
     bool ok = !a.cplx && !f32acc && a.M <= 128 && a.N <= 160 && a.N + extra <= BG_MAXU && a.chunk % 16 == 0 &&
-              a.ld % 4 == 0;
+              a.ld % 4 == 0 && !a.dsc && !a.dsc2;  // this kernel applies no row scales
     for (int s = 0; s < a.A.nseg; ++s) ok = ok && aligned16(a.A.p[s]);
     for (int s = 0; s < a.B.nseg; ++s) ok = ok && aligned16(a.B.p[s]);
     a.lds = ok ? 2 : 0;

@@ -31,6 +31,7 @@ struct GramArgs {
   ColSet A, B;
   const double* dsc;  // optional row scale of B columns [0, nsc)
   int nsc;
+  const double* dsc2; // optional row scale of B columns [nsc, N) (generalized problem: B P next to B T W)
   int M, N;
   long ld;            // leading dimension of every segment
   long rows;          // rows summed (multiple of 16)
@@ -189,7 +190,10 @@ struct BlockUpdArgs {
 
 // small per-problem kernels
 struct ColnormArgs { const void* X; int f32; long ld, rows; int ncols; double* out; int sum; };  // sum: plain column sums
-struct RitzArgs { const double* AX; const double* X; const double* lam; double* W; float* W32; long ld, rows; int ncols; };
+// W = AX - (B) X diag(lam); b: optional diagonal B of a generalized problem, indexed by row >> bshift
+// (complex columns read as real columns of twice the length: bshift = 1)
+struct RitzArgs { const double* AX; const double* X; const double* lam; double* W; float* W32; long ld, rows; int ncols;
+                  const double* b; int bshift; };
 struct TransposeArgs { const double* src; int lds; double* dst; int ldd; int m, n; int cplx; };  // cplx: conjugate
 struct FillArgs { double* p; long count; double v; };
 struct SetDiagArgs { double* G; int ld, m; const double* lam; int cplx; };
@@ -307,7 +311,7 @@ void launch_colnorm2(const void* X, int f32, long ld, long rows, int ncols, doub
 void launch_colsum(const double* P, long ld, long rows, int ncols, double* out, hipStream_t st);
 // W[r, j] = AX[r, j] - X[r, j] * lam[j] (W and/or its float copy W32)
 void launch_ritz_resid(const double* AX, const double* X, const double* lam, double* W, float* W32, long ld,
-                       long rows, int ncols, hipStream_t st);
+                       long rows, int ncols, hipStream_t st, const double* b = nullptr, int bshift = 0);
 
 void launch_block_pencil(const PencilArgs& a, hipStream_t st);
 void launch_block_update(const BlockUpdArgs& a, hipStream_t st);

@@ -254,6 +254,7 @@ struct Work {
   DBuf X32, W32, P32, AW32, AP32;     // float32 blocks (mixed mode)
   DBuf AXm;                           // float64 H X kept in mixed mode
   DBuf Vd, V32, td;
+  DBuf Bd, btd;                       // generalized problem: diag(B) and B T (padding rows zero)
   DBuf G, GWP, L, Li, Rinv, SAS, SS, V1, Mr, Yv, Cc, lam;
   DBuf part, bgram, bC, bflags, cn, scal, iflag, eigw, dminp, pwork, cpart, G32;
   int* hpin = nullptr;                // pinned host scratch: doubles [0, 2Kp), ints from 4Kp + 8
@@ -321,6 +322,7 @@ struct ppcg_handle {
   long s_n = 0, s_rows = 0, s_ld = 0;
   double s_c0 = 0, s_w1 = 0, s_w2 = 0, s_dmin = 0;
   double s_ph[3][2][2] = {};          // Bloch phases of that solve's operator
+  bool s_gen = false;                 // that solve was a generalized problem (H x = lambda B x)
   ~ppcg_handle() {
     if (hcounter) hipHostFree(hcounter);
     for (hipEvent_t e : tev)
@@ -373,6 +375,8 @@ struct Prob {
   bool cplx = false;          // complex Hermitian (Bloch phase) operator
   double ph[3][2][2] = {};    // exp(i kappa_d a h), a = 1, 2
   const double* V = nullptr;
+  const double* Bsrc = nullptr;  // generalized problem: diag(B) (caller's), else NULL
+  bool gen = false;
   const double* X0 = nullptr;  // NULL: seeded N(0,1) start block drawn on the device
   uint64_t seed = 0;
   double* Xout = nullptr;
@@ -408,6 +412,8 @@ struct Prob {
   double pencil_rel_tol() const { return std::max(2.2e-16, std::min(1e-10, 1e-4 * tol)); }
 
   double* X() { return Wk.X.d(); }
+  // diag(B) of a generalized problem (row scale of every B inner product), else NULL
+  const double* bdiag() const { return gen ? Wk.Bd.d() : nullptr; }
   double* Xt() { return Wk.Xt.d(); }
   void swapX() {
     std::swap(Wk.X.p, Wk.Xt.p);
@@ -486,6 +492,9 @@ struct Prob {
     if ((long)K * 4 > n) throw PpcgError{PPCG_EINVAL, "k + nbuf must not exceed n/4"};
     Kp = (int)round_up(K, 64);
     V = op->V;
+    Bsrc = op->B;
+    gen = Bsrc != nullptr;
+    if (gen && mixed) throw PpcgError{PPCG_EINVAL, "the generalized problem (operator B) runs in FP64 only"};
     X0 = X0_;
     Xout = Xout_;
     lamout = lamout_;
@@ -606,7 +615,7 @@ struct Prob {
   // dst (M x N, ldd) = A^H (D B) over `rws` rows; njobs strided jobs
   void gram(const ColSet& A, const ColSet& B, int M, int Nn, long rws, long ldab, const double* dsc, int nsc,
             void* dst, int ldd, bool upper, bool f32acc, int njobs = 1, long job_col_off = 0,
-            long dst_job_stride = 0, const char* name = "gram") {
+            long dst_job_stride = 0, const char* name = "gram", const double* dsc2 = nullptr) {
     if (M <= 0 || Nn <= 0) return;
     const int site = site_of(name);
     size_t es = (f32acc ? 4 : 8) * nc();
@@ -625,6 +634,7 @@ struct Prob {
     g.B = B;
     g.dsc = dsc;
     g.nsc = nsc;
+    g.dsc2 = dsc2;
     g.M = M;
     g.N = Nn;
     g.ld = ldab;
@@ -744,7 +754,7 @@ struct Prob {
     return (rows + chunk - 1) / chunk;
   }
   bool block_gram(const void* Wa, const void* Pa, const void* AWa, const void* APa, bool hasP, int s) {
-    if (cplx || q != 16 || g_rec || rows % 16 || s <= 0) return false;
+    if (cplx || gen || q != 16 || g_rec || rows % 16 || s <= 0) return false;
     BlockGramArgs b{};
     b.X = xc(X(), nl);
     b.W = Wa;
@@ -914,6 +924,10 @@ struct Prob {
     }
     Wk.Vd.ensure((size_t)rows * 8);
     Wk.td.ensure((size_t)rows * 8);
+    if (gen) {
+      Wk.Bd.ensure((size_t)rows * 8);
+      Wk.btd.ensure((size_t)rows * 8);
+    }
     size_t kk = (size_t)Kp * Kp * xs();
     for (DBuf* b : {&Wk.G, &Wk.L, &Wk.Li, &Wk.Rinv, &Wk.SAS, &Wk.SS, &Wk.V1, &Wk.Mr, &Wk.Yv, &Wk.Cc}) b->ensure(kk);
     Wk.GWP.ensure((size_t)Kp * 2 * K * xs());
@@ -962,7 +976,7 @@ struct Prob {
     if (!cplx && q == 16)  // 16-column block Grams, finest candidate
       need = std::max(need, (size_t)bg_splits(8192, s) * s * BG_TILES * 256 * 8);
     Wk.part.ensure(need);
-    Wk.pinned((size_t)(4 * Kp + 64) * 8);
+    Wk.pinned((size_t)std::max(4 * Kp + 64, 1024) * 8);
     // zero everything that carries padding rows
     std::vector<DBuf*> blocks = {&Wk.X, &Wk.Xt};
     if (mixed) {
@@ -976,6 +990,11 @@ struct Prob {
       HIPCHECK(hipMemsetAsync(b->p, 0, b->bytes, st));
     if (mixed) HIPCHECK(hipMemsetAsync(Wk.V32.p, 0, Wk.V32.bytes, st));
     HIPCHECK(hipMemcpyAsync(Wk.Vd.p, V, n * 8, hipMemcpyDeviceToDevice, st));
+    if (gen) {
+      HIPCHECK(hipMemsetAsync(Wk.Bd.p, 0, Wk.Bd.bytes, st));
+      HIPCHECK(hipMemsetAsync(Wk.btd.p, 0, Wk.btd.bytes, st));
+      HIPCHECK(hipMemcpyAsync(Wk.Bd.p, Bsrc, n * 8, hipMemcpyDeviceToDevice, st));
+    }
   }
 
   // phase: Jacobi preconditioner and checks of V
@@ -986,6 +1005,12 @@ struct Prob {
                      st);
     launch_d2h(Wk.hpind, Wk.dminp.p, nparts * 8, st);
     launch_d2h(Wk.hpin + 2 * nparts, Wk.iflag.p, 4, st);
+    if (gen) {  // min and NaN scan of B (its reciprocal lands in btd, overwritten below)
+      launch_prep_diag(Wk.Bd.d(), n, 0.0, Wk.btd.d(), nullptr, Wk.dminp.d() + nparts, nparts, Wk.iflag.i() + 1, st);
+      launch_d2h(Wk.hpind + 512, Wk.dminp.d() + nparts, nparts * 8, st);
+      launch_d2h(Wk.hpin + 2 * nparts + 1, Wk.iflag.i() + 1, 4, st);
+      launch_scale_rows(Wk.Bd.d(), Wk.td.d(), Wk.btd.d(), rows, rows, 1, 0, st);  // B T
+    }
   }
   void post_prep() {
     const int nparts = 256;
@@ -994,6 +1019,12 @@ struct Prob {
     if (Wk.hpin[2 * nparts]) throw PpcgError{PPCG_EINVAL, "V contains NaN"};
     if (!(mn > 0)) throw PpcgError{PPCG_ENOTHPD, "diag(H) has a non-positive entry: Jacobi preconditioner not HPD"};
     dmin = mn;
+    if (gen) {
+      double bm = 1e308;
+      for (int i = 0; i < nparts; ++i) bm = std::min(bm, Wk.hpind[512 + i]);
+      if (Wk.hpin[2 * nparts + 1]) throw PpcgError{PPCG_EINVAL, "B contains NaN"};
+      if (!(bm > 0)) throw PpcgError{PPCG_ENOTHPD, "B has a non-positive entry: not positive definite"};
+    }
   }
 
   // phase: orthonormal start block and first residual (steps 1-4)
@@ -1016,7 +1047,7 @@ struct Prob {
     CatCtx cc(prof, CAT_CHOLQR);
     double* Xa = xc(X(), nl);
     ColSet A = cols1(Xa, m, false);
-    gram(A, A, m, m, rows, ld, nullptr, 0, Wk.G.p, Kp, true, false, 1, 0, 0, "gram_xx");
+    gram(A, A, m, m, rows, ld, bdiag(), bdiag() ? m : 0, Wk.G.p, Kp, true, false, 1, 0, 0, "gram_xx");  // X^H B X
   }
   // |G - I|_F^2 of that Gram into scal[Kp + 1] and the pinned slot 2 Kp + 1
   void enq_orth_err() {
@@ -1085,7 +1116,14 @@ struct Prob {
       update(fc(Wk.X32.f(), nl), ld, m, Wk.G32.p, Kp, m, R, nullptr, m, ld, W32a, nullptr, rows, -1.0, 1.0, false,
              true, "update_resid", true, cpart, nwa, R, Xa, Wk.G.d(), (long)Kp + 1);
     } else {
-      update(Xa, ld, m, Wk.G.p, Kp, m, R, nullptr, m, ld, W32a, nullptr, rows, -1.0, 1.0, false, false,
+      // generalized problem: W = H X - (B X) G, with B X formed in the (free) H W buffer
+      const double* XG = Xa;
+      if (gen) {
+        double* BXa = xc(Wk.AW.d(), nl);
+        launch_scale_rows_c(Wk.Bd.d(), Xa, BXa, ld, rows, m, cplx, st);
+        XG = BXa;
+      }
+      update(XG, ld, m, Wk.G.p, Kp, m, R, nullptr, m, ld, W32a, nullptr, rows, -1.0, 1.0, false, false,
              "update_resid", mixed, cpart, nwa);
     }
     Scope s(prof, "colnorm");
@@ -1162,7 +1200,7 @@ struct Prob {
     stencil(S, AS, K, false);
     ColSet A = cols1(S, K, false);
     gram(A, cols1(AS, K, false), K, K, rows, ld, nullptr, 0, Wk.SAS.p, Kp, true, false, 1, 0, 0, "gram_rr");
-    gram(A, A, K, K, rows, ld, nullptr, 0, Wk.SS.p, Kp, true, false, 1, 0, 0, "gram_rr");
+    gram(A, A, K, K, rows, ld, bdiag(), bdiag() ? K : 0, Wk.SS.p, Kp, true, false, 1, 0, 0, "gram_rr");  // S^H B S
     launch_zero_int(Wk.iflag.i(), 4, st);
     chol(Wk.SS.d(), K);
     launch_transpose(Wk.Li.d(), Kp, Wk.Rinv.d(), Kp, K, K, cplx, st);  // Rinv = Linv^H
@@ -1196,8 +1234,8 @@ struct Prob {
       if (mixed) {
         launch_ritz_resid(R, X(), Wk.lam.d(), nullptr, Wk.W32.f(), ldr, rowsr, K, st);
         launch_colnorm2(Wk.W32.p, 1, ldr, rowsr, K, Wk.cn.d(), st);
-      } else {
-        launch_ritz_resid(R, X(), Wk.lam.d(), R, nullptr, ldr, rowsr, K, st);
+      } else {  // generalized problem: H X - B X Lambda
+        launch_ritz_resid(R, X(), Wk.lam.d(), R, nullptr, ldr, rowsr, K, st, bdiag(), cplx ? 1 : 0);
         launch_colnorm2(R, 0, ldr, rowsr, K, Wk.cn.d(), st);
       }
     }
@@ -1275,7 +1313,9 @@ struct Prob {
         B.nseg = 2;
       }
       int ncol = hasP ? 2 * m : m;
-      gram(A, B, K, ncol, rows, ld, Wk.td.d(), m, Wk.GWP.p, Kp, false, mixed, 1, 0, 0, "gram_proj");
+      // X^H (T W) and X^H P; generalized problem: X^H B (T W) and X^H B P (B-orthogonal projector)
+      gram(A, B, K, ncol, rows, ld, gen ? Wk.btd.d() : Wk.td.d(), m, Wk.GWP.p, Kp, false, mixed, 1, 0, 0,
+           "gram_proj", gen ? Wk.Bd.d() : nullptr);
       const void* Xs = mixed ? (const void*)Wk.X32.p : (const void*)X();
       update(Xs, ld, K, Wk.GWP.p, Kp, ncol, Wa, Pa, m, ld, nullptr, Wk.td.d(), rows, -1.0, 1.0, false, mixed,
              "update_proj");
@@ -1314,9 +1354,9 @@ struct Prob {
       B.nseg = bi;
       int Nb = 2 * nS - q;
       const bool tiles = block_gram(Wa, Pa, AWa, APa, hasP, s);
-      if (!tiles)
-        gram(A, B, Ma, Nb, rows, ld, nullptr, 0, Wk.bgram.p, Ma, false, false, s, (long)q * ld, (long)Ma * Nb,
-             "gram_block");
+      if (!tiles)  // generalized problem: the overlap columns [0, nS) carry B
+        gram(A, B, Ma, Nb, rows, ld, bdiag(), gen ? nS : 0, Wk.bgram.p, Ma, false, false, s, (long)q * ld,
+             (long)Ma * Nb, "gram_block");
       PencilArgs pa{};
       pa.gram = Wk.bgram.d();
       pa.gstride = tiles ? (long)BG_TILES * 256 : (long)Ma * Nb;
@@ -1423,7 +1463,7 @@ struct Prob {
                               hipMemcpyDeviceToDevice, st));
     HIPCHECK(hipMemcpyAsync(lamout, Wk.lam.p, (size_t)kout * 8, hipMemcpyDeviceToDevice, st));
     ColSet A = cols1(X(), k, false);
-    gram(A, A, k, k, rows, ld, nullptr, 0, Wk.G.p, Kp, false, false, 1, 0, 0, "gram_check");
+    gram(A, A, k, k, rows, ld, bdiag(), bdiag() ? k : 0, Wk.G.p, Kp, false, false, 1, 0, 0, "gram_check");
     launch_orth_err2(Wk.G.d(), Kp, k, Wk.scal.d(), cplx, st);
     launch_d2h(Wk.hpind, Wk.scal.p, 8, st);
   }
@@ -1740,6 +1780,7 @@ struct Grad {
 
   int run(const double* g, const double* w, double* out, double tol, int max_iter) {
     if (!H->has_state) throw PpcgError{PPCG_ENOSTATE, "ppcg_grad needs a successful ppcg_solve on this handle"};
+    if (H->s_gen) throw PpcgError{PPCG_EINVAL, "ppcg_grad: not for a generalized problem (operator B)"};
     if (!g || !out || !(tol > 0)) throw PpcgError{PPCG_EINVAL, "null pointer or tol <= 0"};
     Work& Wk = H->work(0);
     k = H->s_k;
@@ -2032,6 +2073,7 @@ ppcg_status ppcg_solve(ppcg_handle* h, const ppcg_operator* op, int32_t k, int32
     h->s_w2 = p.w2;
     h->s_dmin = p.dmin;
     std::memcpy(h->s_ph, p.ph, sizeof(p.ph));
+    h->s_gen = p.gen;
     return PPCG_OK;
   });
 }
@@ -2053,6 +2095,7 @@ ppcg_status ppcg_solve_batched(ppcg_handle* h, int32_t nprob, const ppcg_operato
         ps[b]->seed = h->opt.seed + (uint64_t)b;
         if (!run.empty() && ps[b]->cplx != run[0]->cplx)
           throw PpcgError{PPCG_EINVAL, "a batch cannot mix real and complex (Bloch) operators"};
+        if (ps[b]->gen) throw PpcgError{PPCG_EINVAL, "the generalized problem (operator B) is not batched"};
         run.push_back(ps[b].get());
       } catch (const PpcgError& e) {
         ps[b]->status = e.code;

@@ -307,7 +307,9 @@ PPCG_DEV void ritz_body(const RitzArgs& a, unsigned wg, unsigned) {
   long c = wg / bpc;
   long r = (long)(wg % bpc) * 256 + threadIdx.x;
   if (r >= a.rows) return;
-  double v = a.AX[r + c * a.ld] - a.X[r + c * a.ld] * a.lam[c];
+  double xb = a.X[r + c * a.ld];
+  if (a.b) xb *= a.b[r >> a.bshift];
+  double v = a.AX[r + c * a.ld] - xb * a.lam[c];
   if (a.W) a.W[r + c * a.ld] = v;
   if (a.W32) a.W32[r + c * a.ld] = (float)v;
 }
@@ -317,8 +319,8 @@ __global__ __launch_bounds__(256) void ritz_grouped(const RitzArgs* jobs, const 
   ritz_body(jobs[j], blockIdx.x - start[j], start[j + 1] - start[j]);
 }
 void launch_ritz_resid(const double* AX, const double* X, const double* lam, double* W, float* W32, long ld,
-                       long rows, int ncols, hipStream_t st) {
-  RitzArgs a{AX, X, lam, W, W32, ld, rows, ncols};
+                       long rows, int ncols, hipStream_t st, const double* b, int bshift) {
+  RitzArgs a{AX, X, lam, W, W32, ld, rows, ncols, b, bshift};
   unsigned blocks = ncols > 0 ? (unsigned)(((rows + 255) / 256) * ncols) : 0;
   if (g_rec) {
     g_rec->add(OP_RITZ, &a, sizeof(a), blocks);
