@@ -308,8 +308,11 @@ def bench_bloch(args):
             if r["iter"] % 10 == 0 or r["kind"] == "final_rr_failed":
                 log(f"  {prec} iter {r['iter']:4d} rho {r['rho']:.3e} locked {r['n_locked']:5d} "
                     f"t {r['time_s']:8.1f} s")
-        h = B.Handle(prec, profile=True, max_iter=args.max_iter, log=prog)
-        X0 = torch.tensor(p.start(), device="cuda")   # (n, K) complex128, 30 GB
+        h = B.Handle(prec, profile=True, max_iter=args.max_iter, log=prog, seed=203,
+                     orth="skip" if args.orth_skip else "cholqr")
+        # (n, K) complex128 start block, 30 GB: from the host generator, or drawn
+        # on the device (Philox, seed 203) with --device-x0
+        X0 = None if args.device_x0 else torch.tensor(p.start(), device="cuda")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         lam, X, info = h.solve(V, g.N, p.k, p.q, p.tol, p.rr_period, X0, h=g.h, order=g.order, kpt=g.kpt,
@@ -334,7 +337,9 @@ def bench_bloch(args):
         "config": {"workload": "bloch96_k2048: 13-point 96^3 periodic FD Hamiltonian with Bloch vector "
                                "(2 pi 0.25/L, 0, 0), smoothed N(0,1) potential in [-2, 0], k=2048, sbsize=32, "
                                "nbuf=64, rr_period=5, tol=1e-6, Jacobi, N(0,1) start",
-                   "n": g.n, "k": p.k, "sbsize": p.q, "K": p.K, "precision": main_prec, "max_iter": args.max_iter},
+                   "n": g.n, "k": p.k, "sbsize": p.q, "K": p.K, "precision": main_prec, "max_iter": args.max_iter,
+                   "start_block": "device Philox seed 203" if args.device_x0 else "host N(0,1) seed 203",
+                   "orth": "skip" if args.orth_skip else "cholqr"},
         "status": r["info"]["status"], "iters": r["info"]["iters"], "n_rr": r["info"]["n_rr"],
         "resid_final": r["info"]["resid_final"], "orth_err": r["info"]["orth_err"],
         "n_locked": r["info"]["n_locked"],
@@ -430,6 +435,9 @@ def main():
                     help="fixed kernel plans instead of the autotuner's (tuning happens in the warmup solve)")
     ap.add_argument("--nprob", type=int, default=64, help="problems of the batch64 workload")
     ap.add_argument("--max-iter", type=int, default=20000, help="iteration cap (bloch96)")
+    ap.add_argument("--device-x0", action="store_true", help="bloch96: start block drawn on the device")
+    ap.add_argument("--orth-skip", action="store_true",
+                    help="bloch96: omit Cholesky-QR while |X^H X - I|_F <= 0.1 (section 5.5)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
                     help="write profiles/traffic_wells48_<precision>.json from two rocprofv3 --pmc databases "
                          "and exit (no GPU use)")
