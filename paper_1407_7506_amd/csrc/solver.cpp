@@ -389,6 +389,9 @@ struct Prob {
   bool noconv = false;
   double fresh = INFINITY;
   int last_kind = 0;  // what the last iteration ended with (ppcg_iter_log.kind)
+  int pend_flags = 0; // sub-block pencil flags of the last iteration still to be read (block count)
+  // pinned slot of those flags (ints), clear of the slots the residual and Rayleigh-Ritz read-backs use
+  int* flag_slot() { return Wk.hpin + 4 * Kp + 32; }
   // orthonormalisation policy (section 5.5) and stopping test (section 5.2)
   int orth = PPCG_ORTH_CHOLQR, stop = PPCG_STOP_RESIDUAL;
   double orth_skip = 0.1, orth_taylor = 0.3;
@@ -976,7 +979,7 @@ struct Prob {
     if (!cplx && q == 16)  // 16-column block Grams, finest candidate
       need = std::max(need, (size_t)bg_splits(8192, s) * s * BG_TILES * 256 * 8);
     Wk.part.ensure(need);
-    Wk.pinned((size_t)std::max(4 * Kp + 64, 1024) * 8);
+    Wk.pinned((size_t)std::max(4 * Kp + 64 + (K / q + 1) / 2, 1024) * 8);
     // zero everything that carries padding rows
     std::vector<DBuf*> blocks = {&Wk.X, &Wk.Xt};
     if (mixed) {
@@ -1399,16 +1402,21 @@ struct Prob {
                (double)n * q * s * (2.0 * xs() + (hasP ? 3.0 : 2.0) * esz()), mixed ? PEAK_F32 : PEAK_F64);
       launch_block_update(bu, st);
     }
-    launch_d2h(Wk.hpin, Wk.bflags.p, (size_t)s * 4, st);
-  }
-  void post_body1() {
-    const int s = (K - nl) / q;
-    for (int j = 0; j < s; ++j) {
-      if (Wk.hpin[j] & 4) throw PpcgError{PPCG_ERANK, "sub-block pencil has rank below sbsize"};
-      if (Wk.hpin[j] & 2) info.n_backtrack++;
-      info.n_dropped += Wk.hpin[j] >> 8;
-    }
+    // the flags are read at the next synchronisation (no wait here): a rank
+    // failure leaves its block unchanged (C = [I; 0; 0]) and ends the solve there
+    launch_d2h(flag_slot(), Wk.bflags.p, (size_t)s * 4, st);
+    pend_flags = s;
     hasP = true;
+  }
+  void post_body_flags() {
+    const int* f = flag_slot();
+    const int s = pend_flags;
+    pend_flags = 0;
+    for (int j = 0; j < s; ++j) {
+      if (f[j] & 4) throw PpcgError{PPCG_ERANK, "sub-block pencil has rank below sbsize"};
+      if (f[j] & 2) info.n_backtrack++;
+      info.n_dropped += f[j] >> 8;
+    }
   }
 
   // phase: steps 17-20 when the orthonormalisation needs no host decision
@@ -1655,6 +1663,7 @@ struct Driver {
     while (!act.empty()) {
       std::vector<Prob*> fin, body, done, again;
       post(act, [&](Prob& p) {
+        p.post_body_flags();
         double r = p.post_rho();
         if (p.last_kind == 1) p.post_cq();
         p.log(r);
@@ -1682,8 +1691,6 @@ struct Driver {
       }
       if (!body.empty()) {
         phase(body, [](Prob& p) { p.enq_body1(); });
-        sync(H);
-        post(body, [](Prob& p) { p.post_body1(); });
         std::vector<Prob*> cq, cqa, rr;
         for (Prob* p : body) {
           const bool r_it = p->rr_iteration();
