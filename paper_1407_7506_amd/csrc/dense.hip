@@ -117,7 +117,12 @@ PPCG_DEV void tile_put4(S* T, const S (&c)[4]) {
 }
 
 // factor the diagonal tile p of G (already updated by every earlier step):
-// Li_pp = L_pp^{-1}; a non-positive pivot sets *flag = p + 1
+// Li_pp = L_pp^{-1}; a non-positive pivot sets *flag = p + 1.  The inverse is
+// formed inside the factorization loop by forward substitution in column
+// (axpy) order: once column c of L is scaled, row c of the inverse takes its
+// 1 / L_cc and every row below subtracts L_xc times it.  Each entry of the
+// inverse receives the same operations in the same order as row-by-row
+// substitution, with no barriers beyond the factorization's own.
 template <class S>
 PPCG_DEV void chol_diag_body(const DenseStep& a, int p) {
   __shared__ S Sm[CB * CLD], I[CB * CLD];
@@ -133,6 +138,7 @@ PPCG_DEV void chol_diag_body(const DenseStep& a, int p) {
     S v = zero;
     if (i < nb && j < nb) v = (i >= j) ? G[(n0 + i) + (long)(n0 + j) * a.ld] : conj_(G[(n0 + j) + (long)(n0 + i) * a.ld]);
     Sm[i + j * CLD] = v;
+    I[i + j * CLD] = from_real<S>(i == j && i < nb ? 1.0 : 0.0);
   }
   if (tid == 0) bad = 0;
   __syncthreads();
@@ -141,27 +147,22 @@ PPCG_DEV void chol_diag_body(const DenseStep& a, int p) {
     double lcc = (piv > 0) ? sqrt(piv) : 1.0;
     if (!(piv > 0) && tid == 0) bad = 1;
     __syncthreads();
-    for (int i = c + 1 + tid; i < nb; i += 256) Sm[i + c * CLD] = (1.0 / lcc) * Sm[i + c * CLD];
+    const double rl = 1.0 / lcc;
+    for (int i = c + 1 + tid; i < nb; i += 256) Sm[i + c * CLD] = rl * Sm[i + c * CLD];
     if (tid == 0) Sm[c + c * CLD] = from_real<S>(lcc);
+    if (tid <= c) I[c + tid * CLD] = rl * I[c + tid * CLD];  // row c of the inverse is final
     __syncthreads();
     int nr = nb - c - 1;
     for (int e = tid; e < nr * nr; e += 256) {
       int i = c + 1 + e % nr, j = c + 1 + e / nr;
       if (i >= j) Sm[i + j * CLD] -= Sm[i + c * CLD] * conj_(Sm[j + c * CLD]);
     }
+    for (int e = tid; e < nr * (c + 1); e += 256) {  // rows x > c, columns y <= c
+      int x = c + 1 + e % nr, y = e / nr;
+      I[x + y * CLD] -= Sm[x + c * CLD] * I[c + y * CLD];
+    }
     __syncthreads();
   }
-  // inverse of the lower-triangular tile, one thread per column
-  if (tid < nb) {
-    int y = tid;
-    for (int x = 0; x < nb; ++x) I[x + y * CLD] = zero;
-    for (int x = y; x < nb; ++x) {
-      S sum = from_real<S>(x == y ? 1.0 : 0.0);
-      for (int t = y; t < x; ++t) sum -= Sm[x + t * CLD] * I[t + y * CLD];
-      I[x + y * CLD] = (1.0 / real_(Sm[x + x * CLD])) * sum;
-    }
-  }
-  __syncthreads();
   for (int e = tid; e < nb * nb; e += 256) {
     int i = e % nb, j = e / nb;
     Li[(n0 + i) + (long)(n0 + j) * a.ld] = (i >= j) ? I[i + j * CLD] : zero;
@@ -708,10 +709,32 @@ PPCG_DEV void bj_pair_body(const EigDev& a, int round, unsigned t) {
   lds_jacobi<NT, S>(Sm, Qs, n2, JLD, tiny, BJ_INNER, jr, red);
   S* Qg = (S*)a.Q + (long)t * J2 * J2;
   for (int e = tid; e < n2 * n2; e += NT) Qg[(e % n2) + (e / n2) * J2] = Qs[(e % n2) + (e / n2) * JLD];
-  if (tid == 0) {
-    a.flags[t] = 1;
-    atomicAdd(a.counter, 1);
+  if (tid == 0) a.flags[t] = 1;
+}
+
+// Stop test after a sweep: counts the workgroups that see an off-diagonal
+// entry of M above the skip threshold.  Every off-diagonal entry of M lies in
+// the pair problem of some round, and while nothing rotates M stays as it is,
+// so the next sweep would rotate anything exactly when this count is nonzero:
+// the loop ends without running a last sweep that only confirms convergence.
+constexpr int BJ_CHECK_PER_WG = 256 * 16;
+template <class S>
+PPCG_DEV void bj_check_body(const EigDev& a, unsigned wg) {
+  __shared__ int any;
+  const S* M = (const S*)a.M;
+  const double tiny = bj_tiny(a);
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
+  const long mm = (long)a.m * a.m;
+  const long e1 = min(mm, (long)(wg + 1) * BJ_CHECK_PER_WG);
+  bool hit = false;
+  for (long e = (long)wg * BJ_CHECK_PER_WG + threadIdx.x; e < e1; e += 256) {
+    const int i = (int)(e % a.m), j = (int)(e / a.m);
+    if (i != j && sqrt(abs2_(M[i + (long)j * a.ld])) > tiny) hit = true;
   }
+  if (hit) any = 1;
+  __syncthreads();
+  if (threadIdx.x == 0 && any) atomicAdd(a.counter, 1);
 }
 
 // One round's two-sided update in a single launch.  Items [0, np^2): the
@@ -805,17 +828,27 @@ PPCG_DEV void bj_update_body(const EigDev& a, int round, unsigned wg) {
 }
 
 // ranks of the (real) diagonal (ascending, ties by index) -> lam; then Vt
-// columns gathered into V
+// columns gathered into V.  One thread per diagonal entry, ceil(m / 256)
+// workgroups; the diagonal is read through LDS in chunks of 1024.
 template <class S>
-PPCG_DEV void bj_rank_body(const EigDev& a) {
+PPCG_DEV void bj_rank_body(const EigDev& a, unsigned wg) {
+  __shared__ double dg[1024];
   const S* M = (const S*)a.M;
-  for (int x = threadIdx.x; x < a.m; x += 256) {
-    double lx = real_(M[x + (long)x * a.ld]);
-    int rk = 0;
-    for (int y = 0; y < a.m; ++y) {
-      double ly = real_(M[y + (long)y * a.ld]);
-      rk += (ly < lx) || (ly == lx && y < x);
-    }
+  const int x = (int)wg * 256 + (int)threadIdx.x;
+  const double lx = x < a.m ? real_(M[x + (long)x * a.ld]) : 0.0;
+  int rk = 0;
+  for (int y0 = 0; y0 < a.m; y0 += 1024) {
+    const int ny = min(1024, a.m - y0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < ny; e += 256) dg[e] = real_(M[(y0 + e) + (long)(y0 + e) * a.ld]);
+    __syncthreads();
+    if (x < a.m)
+      for (int e = 0; e < ny; ++e) {
+        const double ly = dg[e];
+        rk += (ly < lx) || (ly == lx && y0 + e < x);
+      }
+  }
+  if (x < a.m) {
     a.rank[x] = rk;
     a.lam[rk] = lx;
   }
@@ -828,7 +861,8 @@ PPCG_DEV void bj_gather_body(const EigDev& a, unsigned wg) {
   ((S*)a.V)[i + (long)a.rank[j] * a.ldv] = ((const S*)a.Vt)[i + (long)j * a.m];
 }
 
-// STEP: 0 init, 1 pair eigensolves, 2 two-sided update of M and Vt, 3 rank, 4 gather
+// STEP: 0 init, 1 pair eigensolves, 2 two-sided update of M and Vt, 3 rank, 4 gather,
+// 5 stop test
 #ifndef PPCG_BJ_PAIR_NT
 #define PPCG_BJ_PAIR_NT 1024
 #endif
@@ -842,8 +876,9 @@ __global__ __launch_bounds__(bj_threads<STEP>()) void bj_grouped(const EigDev* j
   if (STEP == 0) bj_init_body<S>(a, wg);
   if (STEP == 1) bj_pair_body<S, BJ_PAIR_NT>(a, round, wg);
   if (STEP == 2) bj_update_body<S>(a, round, wg);
-  if (STEP == 3) bj_rank_body<S>(a);
+  if (STEP == 3) bj_rank_body<S>(a, wg);
   if (STEP == 4) bj_gather_body<S>(a, wg);
+  if (STEP == 5) bj_check_body<S>(a, wg);
 }
 
 void EigGraphCache::clear() {
@@ -887,11 +922,12 @@ int block_jacobi_eig_grouped(const std::vector<EigJob>& jobs, Stage& stage, EigG
       case 0: return (unsigned)BJ_INIT_WG;
       case 1: return (unsigned)a.np;
       case 2: return (unsigned)(a.np * a.np + a.np * ((a.m + 63) / 64));
-      case 3: return 1u;
-      default: return (unsigned)((mm + 255) / 256);
+      case 3: return (unsigned)((a.m + 255) / 256);
+      case 4: return (unsigned)((mm + 255) / 256);
+      default: return (unsigned)((mm + BJ_CHECK_PER_WG - 1) / BJ_CHECK_PER_WG);
     }
   };
-  constexpr int NSTEP = 5;
+  constexpr int NSTEP = 6;
   const unsigned* sd[NSTEP];
   unsigned tot[NSTEP];
   std::vector<unsigned> starts;
@@ -944,7 +980,8 @@ int block_jacobi_eig_grouped(const std::vector<EigJob>& jobs, Stage& stage, EigG
         case 1: launch(bj_grouped<zdouble, 1>, step, round); break;
         case 2: launch(bj_grouped<zdouble, 2>, step, round); break;
         case 3: launch(bj_grouped<zdouble, 3>, step, round); break;
-        default: launch(bj_grouped<zdouble, 4>, step, round); break;
+        case 4: launch(bj_grouped<zdouble, 4>, step, round); break;
+        default: launch(bj_grouped<zdouble, 5>, step, round); break;
       }
     } else {
       switch (step) {
@@ -952,18 +989,21 @@ int block_jacobi_eig_grouped(const std::vector<EigJob>& jobs, Stage& stage, EigG
         case 1: launch(bj_grouped<double, 1>, step, round); break;
         case 2: launch(bj_grouped<double, 2>, step, round); break;
         case 3: launch(bj_grouped<double, 3>, step, round); break;
-        default: launch(bj_grouped<double, 4>, step, round); break;
+        case 4: launch(bj_grouped<double, 4>, step, round); break;
+        default: launch(bj_grouped<double, 5>, step, round); break;
       }
     }
   };
-  // one sweep: zero the rotation counter, every round's two launches, read the count back
+  // one sweep: every round's two launches, then the stop test into the zeroed
+  // counter, read back
   auto sweep_ops = [&]() {
-    ZeroIntArgs z{dev_counter, 1};
-    hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(256), 0, st, z);
     for (int round = 0; round < maxr; ++round) {
       run(1, round);
       run(2, round);
     }
+    ZeroIntArgs z{dev_counter, 1};
+    hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(256), 0, st, z);
+    run(5, 0);
     hipMemcpyAsync(host_counter, dev_counter, sizeof(int), hipMemcpyDeviceToHost, st);
   };
   if (graphs && !reuse) {

@@ -361,7 +361,7 @@ struct EigGraphCache {
 };
 // All problems in lockstep (one workgroup set per problem and launch);
 // dev_counter / host_counter: one int of device / pinned host memory for the
-// rotation count of a sweep.  Synchronises the stream once per sweep.
+// stop test after each sweep.  Synchronises the stream once per sweep.
 // Returns the sweeps used.
 int block_jacobi_eig_grouped(const std::vector<EigJob>& jobs, Stage& stage, EigGraphCache* graphs, int* dev_counter,
                              int* host_counter,

@@ -90,28 +90,31 @@ __global__ __launch_bounds__(256) void stencil_kernel(StencilArgs a) {
   stencil_body<S, ORDER>(a, blockIdx.x, gridDim.x);
 }
 
-// LDS-staged variant (single launches).  For each z plane the workgroup loads
-// a window of the flattened (x, y) plane -- its 256 points and R N points on
-// either side (R = ORDER / 2, plane-periodic) -- once, coalesced, into LDS;
-// the x and y neighbours of a point are then LDS reads and the z neighbours
-// stay in registers.  Two window buffers: plane k + 1 is loaded while plane k
-// is computed, one barrier per plane.  A point costs about (256 + 2 R N) / 256
-// coalesced loads for the window plus one for its z neighbour and one for V,
-// instead of one load per neighbour.
+// LDS-staged, software-pipelined variant (single launches).  For each z
+// plane the workgroup stages a window of the flattened (x, y) plane -- its
+// 256 points and R N points on either side (R = ORDER / 2, plane-periodic) --
+// in LDS; the x and y neighbours of a point are then LDS reads and the z
+// neighbours stay in registers.  The loads for plane k + 1 (its window, V and
+// the z value entering the register window) are issued before plane k is
+// computed and written to the second LDS buffer after it, so every wave keeps
+// a plane's worth of loads in flight while it computes: one barrier per
+// plane.  The window offsets (wrapped in the plane) are computed once.  A
+// point costs (256 + 2 R N) / 256 coalesced loads for the window plus one for
+// its z neighbour and one for V, instead of one load per neighbour.
 template <int ORDER>
 constexpr int stencil_rad() { return ORDER / 2; }
 inline int stencil_window(int N, int order) { return 256 + 2 * (order / 2) * N; }
 
-template <class S, int ORDER>
+template <class S, int ORDER, int WPT>
 __global__ __launch_bounds__(256) void stencil_lds_kernel(StencilArgs a) {
   typedef typename sc_traits<S>::real_t R;
   extern __shared__ __align__(16) char smem[];
-  S* win0 = (S*)smem;
   constexpr int RAD = stencil_rad<ORDER>();
   const int N = a.N;
   const int NN = N * N;
-  const int W = 256 + 2 * RAD * N;
-  S* win1 = win0 + W;
+  const int W = 256 + 2 * RAD * N;  // WPT * 256 >= W (checked by the launcher)
+  S* const win0 = (S*)smem;
+  S* const win1 = win0 + W;
   const unsigned tpp = (unsigned)((NN + 255) / 256);
   const unsigned kch = (unsigned)((N + SZ - 1) / SZ);
   const unsigned L = xcd_remap(blockIdx.x, gridDim.x);
@@ -123,7 +126,6 @@ __global__ __launch_bounds__(256) void stencil_lds_kernel(StencilArgs a) {
   const int tid = threadIdx.x;
   const int q = q0 + tid;
   const bool act = q < NN;
-  const int wbase = q0 - RAD * N;  // plane index of window element 0 (taken modulo NN)
   const S* x = (const S*)a.X + (long)col * a.ldx;
   S* y = (S*)a.Y + (long)col * a.ldy;
   const R* V = (const R*)a.V;
@@ -132,45 +134,78 @@ __global__ __launch_bounds__(256) void stencil_lds_kernel(StencilArgs a) {
   // window offsets of the x neighbours (wrapped inside the point's x line)
   const int xp1 = c + wrap_idx(i, 1, N) - i, xm1 = c + wrap_idx(i, -1, N) - i;
   const int xp2 = c + wrap_idx(i, 2, N) - i, xm2 = c + wrap_idx(i, -2, N) - i;
+  // plane offsets of this thread's window elements tid + 256 u
+  int woff[WPT];
+  bool wv[WPT];
+#pragma unroll
+  for (int u = 0; u < WPT; ++u) {
+    const int e = tid + 256 * u;
+    wv[u] = e < W;
+    int s2 = (q0 - RAD * N + e) % NN;
+    woff[u] = s2 < 0 ? s2 + NN : s2;
+  }
   const int k0 = kc * SZ;
   const int k1 = k0 + SZ < N ? k0 + SZ : N;
-  auto stage = [&](int k, S* buf) {
+  S wr[WPT];
+  auto wload = [&](int k) {
     const S* xp = x + (long)k * NN;
-    for (int e = tid; e < W; e += 256) {
-      int s = (wbase + e) % NN;
-      s = s < 0 ? s + NN : s;
-      buf[e] = xp[s];
-    }
+#pragma unroll
+    for (int u = 0; u < WPT; ++u) wr[u] = wv[u] ? xp[woff[u]] : S{};
+  };
+  auto wstore = [&](S* buf) {
+#pragma unroll
+    for (int u = 0; u < WPT; ++u)
+      if (wv[u]) buf[tid + 256 * u] = wr[u];
   };
   auto at = [&](int k) { return act ? x[q + (long)k * NN] : S{}; };
+  auto vat = [&](int k) { return act ? V[q + (long)k * NN] : R{}; };
+  // z register window: planes k - RAD .. k + RAD
   S zm2 = ORDER == 4 ? at(wrap_idx(k0, -2, N)) : S{};
   S zm1 = at(wrap_idx(k0, -1, N));
   S zc = at(k0);
   S zp1 = at(wrap_idx(k0, 1, N));
-  stage(k0, win0);
+  S zp2 = ORDER == 4 ? at(wrap_idx(k0, 2, N)) : S{};
+  R vc = vat(k0);
+  wload(k0);
+  wstore(win0);
   __syncthreads();
   for (int k = k0; k < k1; ++k) {
-    S* cur = ((k - k0) & 1) ? win1 : win0;
-    if (k + 1 < k1) stage(k + 1, ((k - k0) & 1) ? win0 : win1);
-    S zp2 = ORDER == 4 ? at(wrap_idx(k, 2, N)) : S{};
+    const bool odd = ((k - k0) & 1) != 0;
+    const S* cur = odd ? win1 : win0;
+    const bool more = k + 1 < k1;
+    S znew = S{};
+    R vn = R{};
+    if (more) {
+      wload(k + 1);
+      vn = vat(k + 1);
+      znew = at(wrap_idx(k + 1, RAD, N));
+    }
     if (act) {
-      const long p = q + (long)k * NN;
       S s1 = phased<S>(cur[xp1], cur[xm1], a.ph[0][0]) + phased<S>(cur[c + N], cur[c - N], a.ph[1][0]) +
              phased<S>(zp1, zm1, a.ph[2][0]);
-      S out = ((R)a.c0 + V[p]) * zc + (R)a.w1 * s1;
+      S out = ((R)a.c0 + vc) * zc + (R)a.w1 * s1;
       if (ORDER == 4) {
         S s2 = phased<S>(cur[xp2], cur[xm2], a.ph[0][1]) + phased<S>(cur[c + 2 * N], cur[c - 2 * N], a.ph[1][1]) +
                phased<S>(zp2, zm2, a.ph[2][1]);
         out += (R)a.w2 * s2;
       }
       if (a.shift) out -= (R)a.shift[col] * zc;
-      y[p] = out;
+      y[q + (long)k * NN] = out;
     }
+    if (more) wstore(odd ? win0 : win1);
     __syncthreads();
-    zm2 = zm1;
-    zm1 = zc;
-    zc = zp1;
-    zp1 = ORDER == 4 ? zp2 : at(wrap_idx(k, 2, N));
+    if (ORDER == 4) {
+      zm2 = zm1;
+      zm1 = zc;
+      zc = zp1;
+      zp1 = zp2;
+      zp2 = znew;
+    } else {
+      zm1 = zc;
+      zc = zp1;
+      zp1 = znew;
+    }
+    vc = vn;
   }
 }
 template <class S, int ORDER>
@@ -203,6 +238,9 @@ static int stencil_kind(const StencilArgs& a) {
 #ifndef PPCG_STENCIL_LDS
 #define PPCG_STENCIL_LDS 1
 #endif
+#ifndef PPCG_STENCIL_LDS_MIN_ES
+#define PPCG_STENCIL_LDS_MIN_ES 4
+#endif
 
 void launch_stencil(const StencilArgs& a, hipStream_t st) {
   const long NN = (long)a.N * a.N;
@@ -214,20 +252,29 @@ void launch_stencil(const StencilArgs& a, hipStream_t st) {
   }
   if (blocks == 0) return;
   const size_t es = (a.f32 ? 4 : 8) * (a.cplx ? 2 : 1);
-  const size_t lds = 2 * (size_t)stencil_window(a.N, a.order) * es;
-  // the LDS window pays for 8- and 16-byte elements; float32 real blocks keep
-  // the register kernel (measured at 48^3, 13-point: 186 vs 220 us float64,
-  // 121 vs 80 us float32)
-  if (PPCG_STENCIL_LDS && es >= 8 && lds <= 64 * 1024 && NN < (1L << 30)) {
+  const int W = stencil_window(a.N, a.order);
+  const size_t lds = 2 * (size_t)W * es;
+  const int wpt = (W + 255) / 256;
+  if (PPCG_STENCIL_LDS && es >= PPCG_STENCIL_LDS_MIN_ES && lds <= 64 * 1024 && wpt <= 4 && NN < (1L << 30)) {
+#define PPCG_STENCIL_LDS_CASE(S, ORDER)                                                                            \
+  switch (wpt) {                                                                                                   \
+    case 1: hipLaunchKernelGGL((stencil_lds_kernel<S, ORDER, 1>), dim3(blocks), dim3(256), lds, st, a); break;     \
+    case 2: hipLaunchKernelGGL((stencil_lds_kernel<S, ORDER, 2>), dim3(blocks), dim3(256), lds, st, a); break;     \
+    case 3: hipLaunchKernelGGL((stencil_lds_kernel<S, ORDER, 3>), dim3(blocks), dim3(256), lds, st, a); break;     \
+    default: hipLaunchKernelGGL((stencil_lds_kernel<S, ORDER, 4>), dim3(blocks), dim3(256), lds, st, a); break;    \
+  }
     switch (kind) {
-      case OP_STENCIL_D2: hipLaunchKernelGGL((stencil_lds_kernel<double, 2>), dim3(blocks), dim3(256), lds, st, a); break;
-      case OP_STENCIL_D4: hipLaunchKernelGGL((stencil_lds_kernel<double, 4>), dim3(blocks), dim3(256), lds, st, a); break;
-      case OP_STENCIL_Z2: hipLaunchKernelGGL((stencil_lds_kernel<zdouble, 2>), dim3(blocks), dim3(256), lds, st, a); break;
-      case OP_STENCIL_Z4: hipLaunchKernelGGL((stencil_lds_kernel<zdouble, 4>), dim3(blocks), dim3(256), lds, st, a); break;
-      case OP_STENCIL_C2: hipLaunchKernelGGL((stencil_lds_kernel<zfloat, 2>), dim3(blocks), dim3(256), lds, st, a); break;
-      case OP_STENCIL_C4: hipLaunchKernelGGL((stencil_lds_kernel<zfloat, 4>), dim3(blocks), dim3(256), lds, st, a); break;
+      case OP_STENCIL_D2: PPCG_STENCIL_LDS_CASE(double, 2) break;
+      case OP_STENCIL_D4: PPCG_STENCIL_LDS_CASE(double, 4) break;
+      case OP_STENCIL_F2: PPCG_STENCIL_LDS_CASE(float, 2) break;
+      case OP_STENCIL_F4: PPCG_STENCIL_LDS_CASE(float, 4) break;
+      case OP_STENCIL_Z2: PPCG_STENCIL_LDS_CASE(zdouble, 2) break;
+      case OP_STENCIL_Z4: PPCG_STENCIL_LDS_CASE(zdouble, 4) break;
+      case OP_STENCIL_C2: PPCG_STENCIL_LDS_CASE(zfloat, 2) break;
+      case OP_STENCIL_C4: PPCG_STENCIL_LDS_CASE(zfloat, 4) break;
       default: break;
     }
+#undef PPCG_STENCIL_LDS_CASE
     return;
   }
   PPCG_STENCIL_SWITCH(stencil_kernel, blocks, a)
