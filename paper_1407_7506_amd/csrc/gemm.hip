@@ -470,17 +470,56 @@ PPCG_DEV void block_gram_body(const BlockGramArgs& a, unsigned wg, unsigned nwg)
   acc_t acc[BG_TILES];
 #pragma unroll
   for (int t = 0; t < BG_TILES; ++t) acc[t] = acc_t{0, 0, 0, 0};
-  for (long r = rbeg; r < rend; r += 16) {
+  // software pipeline: the raw 16-byte pieces of the next 16 rows are loaded
+  // while the MFMAs of the current rows run, and decoded (float32 widened)
+  // only after them; element accesses go through scalars before
+  // reinterpretation
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  constexpr int NW = F32 ? 1 : 2;  // pieces per quad of W, P, AW, AP
+  u32x4 rx[2], rw[NW], rp[NW], raw_[NW], rap[NW], rax[2];
+  auto fetch = [&](long r) {
     const long rr = r + 4 * g;
-    double x[4], w[4], p[4], aw[4], ap[4], ax[4];
-    Load4<double, false>::go(px + rr * 8, false, x, nullptr);
-    Load4<double, false>::go(pw + rr * es, F32, w, nullptr);
-    Load4<double, false>::go(paw + rr * es, F32, aw, nullptr);
+    const char* q;
+    q = px + rr * 8; rx[0] = *(const u32x4*)q; rx[1] = *(const u32x4*)(q + 16);
+    q = pw + rr * es; rw[0] = *(const u32x4*)q; if constexpr (NW == 2) rw[1] = *(const u32x4*)(q + 16);
+    q = paw + rr * es; raw_[0] = *(const u32x4*)q; if constexpr (NW == 2) raw_[1] = *(const u32x4*)(q + 16);
     if (HASP) {
-      Load4<double, false>::go(pp + rr * es, F32, p, nullptr);
-      Load4<double, false>::go(pap + rr * es, F32, ap, nullptr);
+      q = pp + rr * es; rp[0] = *(const u32x4*)q; if constexpr (NW == 2) rp[1] = *(const u32x4*)(q + 16);
+      q = pap + rr * es; rap[0] = *(const u32x4*)q; if constexpr (NW == 2) rap[1] = *(const u32x4*)(q + 16);
     }
-    if (AXR) Load4<double, false>::go(pax + rr * 8, false, ax, nullptr);
+    if (AXR) { q = pax + rr * 8; rax[0] = *(const u32x4*)q; rax[1] = *(const u32x4*)(q + 16); }
+  };
+  auto dec64 = [](const u32x4* x, double* v) {
+    const unsigned w0 = x[0].x, w1 = x[0].y, w2 = x[0].z, w3 = x[0].w;
+    const unsigned w4 = x[1].x, w5 = x[1].y, w6 = x[1].z, w7 = x[1].w;
+    v[0] = __hiloint2double((int)w1, (int)w0);
+    v[1] = __hiloint2double((int)w3, (int)w2);
+    v[2] = __hiloint2double((int)w5, (int)w4);
+    v[3] = __hiloint2double((int)w7, (int)w6);
+  };
+  auto decw = [&](const u32x4* x, double* v) {
+    if constexpr (F32) {
+      const unsigned w0 = x[0].x, w1 = x[0].y, w2 = x[0].z, w3 = x[0].w;
+      v[0] = (double)__uint_as_float(w0);
+      v[1] = (double)__uint_as_float(w1);
+      v[2] = (double)__uint_as_float(w2);
+      v[3] = (double)__uint_as_float(w3);
+    } else {
+      dec64(x, v);
+    }
+  };
+  if (rbeg < rend) fetch(rbeg);
+  for (long r = rbeg; r < rend; r += 16) {
+    double x[4], w[4], p[4], aw[4], ap[4], ax[4];
+    dec64(rx, x);
+    decw(rw, w);
+    decw(raw_, aw);
+    if (HASP) {
+      decw(rp, p);
+      decw(rap, ap);
+    }
+    if (AXR) dec64(rax, ax);
+    if (r + 16 < rend) fetch(r + 16);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       acc[0] = mfma(x[e], x[e], acc[0]);
@@ -497,6 +536,9 @@ PPCG_DEV void block_gram_body(const BlockGramArgs& a, unsigned wg, unsigned nwg)
         acc[10] = AXR ? mfma(ax[e], p[e], acc[10]) : mfma(x[e], ap[e], acc[10]);
       }
     }
+    // the next rows are decoded only after every MFMA of these rows (the
+    // loads issued above stay in flight meanwhile)
+    __builtin_amdgcn_sched_barrier(0);
   }
   double* out = a.out + ((long)blk * a.splits + split) * (BG_TILES * 256);
 #pragma unroll
@@ -609,7 +651,14 @@ PPCG_DEV void gram_lds_body(const GramArgs& a, unsigned wg, unsigned nwg) {
   const int nyv = max(0, min(4, (a.N - (j0 + wj * 64) + 15) / 16));
   const bool dg = a.upper_only && ti == tj;
   const bool full = nxv == 4 && nyv == 4 && !dg;
+  // Row scales and the complex rotation of the B operand: applied as the
+  // chunk is loaded for float64 (measured faster there), and for float32
+  // after the current chunk's MFMAs, as the chunk is stored to LDS, so that
+  // its loads stay in flight meanwhile (the scales of this thread's four rows
+  // are loaded once per chunk, not once per quad).
+  constexpr bool DEFER = sizeof(T) == 4;
   T ra[NQ][4], rb[NQ][4];
+  double dv[4], dv2[4];
   auto gload = [&](long r) {
     const long rr = r + 4 * part;
 #pragma unroll
@@ -622,24 +671,36 @@ PPCG_DEV void gram_lds_body(const GramArgs& a, unsigned wg, unsigned nwg) {
       }
       if (vb[q]) {
         Load4<T, false>::go(pb[q] + rr * (fb[q] ? 4 : 8), fb[q], rb[q], nullptr);
-        if (sb[q]) {
+        if constexpr (!DEFER) {
+          if (sb[q]) {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) rb[q][e] *= (T)a.dsc[(rr + e) >> dsh];
-        }
-        if (sb2[q]) {
+            for (int e = 0; e < 4; ++e) rb[q][e] *= (T)a.dsc[(rr + e) >> dsh];
+          }
+          if (sb2[q]) {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) rb[q][e] *= (T)a.dsc2[(rr + e) >> dsh];
-        }
-        if (a.rotB) {  // (re, im) -> (im, -re): rr is a multiple of 4, so pairs do not straddle quads
-          const T r0 = rb[q][0], r2 = rb[q][2];
-          rb[q][0] = rb[q][1];
-          rb[q][1] = -r0;
-          rb[q][2] = rb[q][3];
-          rb[q][3] = -r2;
+            for (int e = 0; e < 4; ++e) rb[q][e] *= (T)a.dsc2[(rr + e) >> dsh];
+          }
+          if (a.rotB) {  // (re, im) -> (im, -re): rows come in quads, so pairs do not straddle them
+            const T r0 = rb[q][0], r2 = rb[q][2];
+            rb[q][0] = rb[q][1];
+            rb[q][1] = -r0;
+            rb[q][2] = rb[q][3];
+            rb[q][3] = -r2;
+          }
         }
       } else {
 #pragma unroll
         for (int e = 0; e < 4; ++e) rb[q][e] = 0;
+      }
+    }
+    if constexpr (DEFER) {
+      if (a.dsc) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) dv[e] = a.dsc[(rr + e) >> dsh];
+      }
+      if (a.dsc2) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) dv2[e] = a.dsc2[(rr + e) >> dsh];
       }
     }
   };
@@ -647,10 +708,30 @@ PPCG_DEV void gram_lds_body(const GramArgs& a, unsigned wg, unsigned nwg) {
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int col = tid / PQ + q * CS;
+      if constexpr (DEFER) {
+        if (vb[q]) {
+          if (sb[q]) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) rb[q][e] *= (T)dv[e];
+          }
+          if (sb2[q]) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) rb[q][e] *= (T)dv2[e];
+          }
+          if (a.rotB) {
+            const T r0 = rb[q][0], r2 = rb[q][2];
+            rb[q][0] = rb[q][1];
+            rb[q][1] = -r0;
+            rb[q][2] = rb[q][3];
+            rb[q][3] = -r2;
+          }
+        }
+      }
       put4(&As[buf][col * S + 4 * part], ra[q]);
       put4(&Bs[buf][col * S + 4 * part], rb[q]);
     }
   };
+
   acc_t acc[4][4];
 #pragma unroll
   for (int x = 0; x < 4; ++x)
@@ -720,7 +801,7 @@ __global__ __launch_bounds__(256) void gram_lds_grouped(const GramArgs* jobs, co
 // update, C (rows x N) = beta (D C) + alpha A B for one 128 x 128 tile; real.
 // NBUF = 2: double-buffered LDS panels (one barrier per chunk); NBUF = 1: one
 // LDS buffer refilled between two barriers (half the LDS, deeper chunks).
-template <class T, int KC, int NBUF = 2>
+template <class T, int KC, int NBUF = 2, bool LEAN = false>
 PPCG_DEV void update_lds_body(const UpdateArgs& a, unsigned wg, unsigned nwg) {
   constexpr int SB = LdsPad<T, KC>::S;                 // B panel [col][k]
   constexpr int SA = LB + (sizeof(T) == 8 ? 2 : 4);    // A panel [k][row]
@@ -801,6 +882,25 @@ PPCG_DEV void update_lds_body(const UpdateArgs& a, unsigned wg, unsigned nwg) {
       if (c + 1 < nch) gload((c + 1) * KC);
 #pragma unroll
       for (int kk = 0; kk < KC; kk += 16) {
+        if constexpr (LEAN) {
+          // operands read one reduction step at a time (same MFMA order as
+          // below): fewer live registers, so two workgroups share a CU
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            T bx[4], ay[4];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) bx[x] = Bs[buf][(wj * 64 + 16 * x + lc) * SB + kk + 4 * g + e];
+#pragma unroll
+            for (int y = 0; y < 4; ++y) ay[y] = As[buf][(kk + 4 * g + e) * SA + wr * 64 + 16 * y + lc];
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+              if (MODE == 1 || (MODE == 0 && nxv == 4) || x < nxv) {
+#pragma unroll
+                for (int y = 0; y < 4; ++y) acc[0][x][y] = mfma(bx[x], ay[y], acc[0][x][y]);
+              }
+          }
+          continue;
+        }
         T bv[4][4], av[4][4];
 #pragma unroll
         for (int x = 0; x < 4; ++x) get4(&Bs[buf][(wj * 64 + 16 * x + lc) * SB + kk + 4 * g], bv[x]);
@@ -843,6 +943,19 @@ PPCG_DEV void update_lds_body(const UpdateArgs& a, unsigned wg, unsigned nwg) {
 template <class T, int KC, int SITE>
 __global__ __launch_bounds__(256) void update_lds_kernel(UpdateArgs a) {
   update_lds_body<T, KC>(a, blockIdx.x, gridDim.x);
+}
+// float64 update with 16-deep chunks (70 KB of LDS) and operands read per
+// reduction step, held to 256 registers: two workgroups per CU, so one
+// workgroup's barrier and load waits are covered by the other's MFMAs
+template <class T, int KC, int SITE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void update_lds_kernel_lean(UpdateArgs a) {
+  update_lds_body<T, KC, 2, true>(a, blockIdx.x, gridDim.x);
+}
+template <class T, int KC, int SITE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void update_lds_grouped_lean(
+    const UpdateArgs* jobs, const unsigned* start, int nj) {
+  int j = find_job(start, nj, blockIdx.x);
+  update_lds_body<T, KC, 2, true>(jobs[j], blockIdx.x - start[j], start[j + 1] - start[j]);
 }
 template <class T, int KC, int SITE>
 __global__ __launch_bounds__(256) void update_lds_grouped(const UpdateArgs* jobs, const unsigned* start, int nj) {
@@ -1063,9 +1176,19 @@ static int update_kind(const UpdateArgs& a, bool f32) {
   case OP_GRAMB_1: hipLaunchKernelGGL((KERNEL<1, 5>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;          \
   case OP_GRAMB_2: hipLaunchKernelGGL((KERNEL<2, 10>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;
 
+#ifndef PPCG_UPD64_LEAN
+#define PPCG_UPD64_LEAN 0
+#endif
+#if PPCG_UPD64_LEAN
+#define PPCG_UPDATEL_D(KERNEL, SITE, GRID, ...) \
+  hipLaunchKernelGGL((KERNEL##_lean<double, 16, SITE>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__)
+#else
+#define PPCG_UPDATEL_D(KERNEL, SITE, GRID, ...) \
+  hipLaunchKernelGGL((KERNEL<double, UKC_D, SITE>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__)
+#endif
 #define PPCG_UPDATEL_CASES(KERNEL, GRID, ...)                                                                    \
-  case OP_UPDATEL_D0: hipLaunchKernelGGL((KERNEL<double, UKC_D, 0>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break; \
-  case OP_UPDATEL_D1: hipLaunchKernelGGL((KERNEL<double, UKC_D, 1>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break; \
+  case OP_UPDATEL_D0: PPCG_UPDATEL_D(KERNEL, 0, GRID, __VA_ARGS__); break;                                         \
+  case OP_UPDATEL_D1: PPCG_UPDATEL_D(KERNEL, 1, GRID, __VA_ARGS__); break;                                         \
   case OP_UPDATEL_F0: hipLaunchKernelGGL((KERNEL<float, UKC_F, 0>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;  \
   case OP_UPDATEL_F1: hipLaunchKernelGGL((KERNEL<float, UKC_F, 1>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;
 
