@@ -18,11 +18,6 @@ PPCG_DEV int rr_player(int pos, int round, int rr) {
   return pos == 0 ? 0 : ((pos - 1 + round) % (rr - 1)) + 1;
 }
 
-// u = M_pq / |M_pq|: a unit complex number, or the sign (+1 / -1) for real data
-template <class S> PPCG_DEV S unit_phase(S a, double mag) {
-  if constexpr (sc_traits<S>::cplx) return S{a.x / mag, a.y / mag};
-  else return a >= 0 ? (S)1.0 : (S)-1.0;
-}
 template <class S> PPCG_DEV double mag_(S a) {
   if constexpr (sc_traits<S>::cplx) return sqrt(abs2_(a));
   else return fabs(a);
@@ -40,7 +35,24 @@ PPCG_DEV int rr_at(int pos, int round, int rr) {
   return x + 1;
 }
 
-// Rotation parameters of one pair: J as above, identity when off
+// 1/sqrt(x) for finite x > 0: the hardware estimate refined by two Newton
+// steps (each squares the relative error), i.e. to within a few ulp
+PPCG_DEV double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const double e = fma(-x * y, y, 1.0);  // 1 - x y^2
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
+// Rotation parameters of one pair: J as above, identity when off.  With
+// d = a_qq - a_pp, r = sqrt(d^2 + 4 |a_pq|^2) and w = |d| + r, the tangent is
+// t = sign(d) 2 |a_pq| / w, so c = w / sqrt(w^2 + 4 |a_pq|^2) and
+// s = sign(d) 2 |a_pq| / sqrt(w^2 + 4 |a_pq|^2), where w^2 + 4 |a_pq|^2 = 2 r w:
+// two refined reciprocal square roots instead of a chain of three divisions
+// and two square roots (same rotation, to a few ulp).
 template <class S> struct JRot {
   double c, s;
   S u;
@@ -53,13 +65,24 @@ PPCG_DEV JRot<S> jacobi_rot(S apq, double app, double aqq, double tiny) {
   o.s = 0.0;
   o.u = from_real<S>(1.0);
   o.on = 0;
-  const double mag = mag_(apq);
+  double mag, imag = 0.0;
+  if constexpr (sc_traits<S>::cplx) {  // |a_pq| exactly as the sweep stop tests take it
+    const double m2 = abs2_(apq);
+    mag = sqrt(m2);
+    imag = m2 > 0 ? rsqrt_nr(m2) : 0.0;
+  } else {
+    mag = fabs(apq);
+  }
   if (mag > tiny) {
-    const double th = (aqq - app) / (2.0 * mag);
-    const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
-    o.c = 1.0 / sqrt(1.0 + t * t);
-    o.s = t * o.c;
-    o.u = unit_phase(apq, mag);
+    const double d = aqq - app;
+    const double q = fma(d, d, 4.0 * mag * mag);
+    const double r = q * rsqrt_nr(q);
+    const double w = fabs(d) + r;
+    const double inv = rsqrt_nr(2.0 * r * w);
+    o.c = w * inv;
+    o.s = (d >= 0 ? 2.0 : -2.0) * mag * inv;
+    if constexpr (sc_traits<S>::cplx) o.u = S{apq.x * imag, apq.y * imag};
+    else o.u = apq >= 0 ? (S)1.0 : (S)-1.0;
     o.on = 1;
   }
   return o;
