@@ -599,14 +599,15 @@ struct EigDev {
   double* V;
   int ldv;
   double* lam;
-  double* Q;       // np x J2 x J2 scalars
+  double* Q;       // 2 x np x J2 x J2 scalars: the rotations of rounds of even / odd parity
+  double* M2;      // m x m (ld m): the second buffer of M for fused rounds
   double* Vt;      // m x m accumulated rotations
   double* tiny;    // BJ_INIT_WG partial sums of |M|^2
-  int* flags;      // np
+  int* flags;      // 2 x fst: which pairs rotated, per parity
   int* rank;       // m
   int* counter;    // shared by all problems of a call
   double rel_tol;
-  int nbe, np;
+  int nbe, np, fst;
 };
 
 static EigDev carve(const EigJob& j, int* counter) {
@@ -622,10 +623,12 @@ static EigDev carve(const EigJob& j, int* counter) {
   w.V = j.V;
   w.ldv = j.ldv;
   w.lam = j.lam;
-  w.Q = (double*)p; p += es * np * J2 * J2;
+  w.fst = (np + 63) / 64 * 64;
+  w.Q = (double*)p; p += es * 2 * np * J2 * J2;
+  w.M2 = (double*)p; p += es * (size_t)j.m * j.m;
   w.Vt = (double*)p; p += es * (size_t)j.m * j.m;
   w.tiny = (double*)p; p += sizeof(double) * BJ_INIT_WG;
-  w.flags = (int*)p; p += sizeof(int) * ((np + 63) / 64 * 64);
+  w.flags = (int*)p; p += sizeof(int) * 2 * w.fst;
   w.rank = (int*)p;
   w.counter = counter;
   w.rel_tol = j.rel_tol;
@@ -637,9 +640,8 @@ size_t eig_workspace_bytes(int m, int cplx) {
   int nblk = (m + JB - 1) / JB;
   int np = (nblk + 1) / 2;
   const size_t es = cplx ? 16 : 8;
-  return es * (size_t)np * J2 * J2 + es * (size_t)m * m + sizeof(double) * BJ_INIT_WG +
-         sizeof(int) * ((np + 63) / 64 * 64) +
-         sizeof(int) * (size_t)m + 256;
+  return es * 2 * (size_t)np * J2 * J2 + 2 * es * (size_t)m * m + sizeof(double) * BJ_INIT_WG +
+         sizeof(int) * 2 * ((np + 63) / 64 * 64) + sizeof(int) * (size_t)m + 256;
 }
 
 PPCG_DEV void pair_of(const EigDev& a, int t, int round, int& nI, int& nJ, int& i0, int& j0) {
@@ -678,38 +680,162 @@ PPCG_DEV double bj_tiny(const EigDev& a) {
   return a.rel_tol * sqrt(s);
 }
 
-// NT threads per pair problem (more waves hide the LDS latency of the rounds)
+// the pair of `round` that holds block B, and B's offset inside that pair
+PPCG_DEV void locate(const EigDev& a, int B, int round, int& t, int& off) {
+  const int n1 = a.nbe - 1;
+  int pos = 0;
+  if (B != 0) pos = ((B - 1 - round) % n1 + n1) % n1 + 1;
+  t = pos < a.np ? pos : a.nbe - 1 - pos;
+  int nI, nJ, i0, j0;
+  pair_of(a, t, round, nI, nJ, i0, j0);
+  off = (B * JB == i0) ? 0 : nI;
+}
+
+// M of the rounds: M_0 is the caller's matrix; with fused rounds, M_r (r >= 1)
+// alternates between the second buffer (r odd) and the caller's matrix (r
+// even), and the last round of a sweep writes the caller's matrix
+template <class S>
+PPCG_DEV S* bj_buf(const EigDev& a, int r, int& ld) {
+  const bool second = r > 0 && (r & 1);
+  ld = second ? a.m : a.ld;
+  return (S*)(second ? a.M2 : a.M);
+}
+
+// Q_a^H M_ab Q_b for pairs ta (rows) and tb (columns) of `round`, read from
+// src (ld lds), Q and the flags of parity par; Q = I for a pair that did not
+// rotate.  Leaves the na x nb result in sh (ld JLD) and returns true, or
+// returns false when neither pair rotated (the tile is src unchanged).  The
+// same arithmetic serves the stored update and the fused pair step, so both
+// see identical values.
+template <class S>
+PPCG_DEV bool bj_tile(const EigDev& a, int round, const S* src, long lds, int par, int ta, int tb, S* sh, int& na,
+                      int& nb) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int* fl = a.flags + par * a.fst;
+  const bool ra = fl[ta] != 0, rb = fl[tb] != 0;
+  int nIa, nJa, i0a, j0a, nIb, nJb, i0b, j0b;
+  pair_of(a, ta, round, nIa, nJa, i0a, j0a);
+  pair_of(a, tb, round, nIb, nJb, i0b, j0b);
+  na = nIa + nJa;
+  nb = nIb + nJb;
+  if (!ra && !rb) return false;
+  auto ga = [&](int x) { return x < nIa ? i0a + x : j0a + (x - nIa); };
+  auto gb = [&](int y) { return y < nIb ? i0b + y : j0b + (y - nIb); };
+  const S zero = from_real<S>(0.0);
+  S* Ms = sh;
+  S* Ts = sh + J2 * JLD;
+  S* QA = sh + 2 * J2 * JLD;
+  S* QB = sh + 3 * J2 * JLD;
+  const S* Qp = (const S*)a.Q + (long)par * a.np * J2 * J2;
+  const S* qa = Qp + (long)ta * J2 * J2;
+  const S* qb = Qp + (long)tb * J2 * J2;
+  for (int e = tid; e < na * nb; e += nt) {
+    int x = e % na, y = e / na;
+    Ms[x + y * JLD] = src[ga(x) + (long)gb(y) * lds];
+  }
+  if (ra)
+    for (int e = tid; e < na * na; e += nt) QA[(e % na) + (e / na) * JLD] = qa[(e % na) + (e / na) * J2];
+  if (rb)
+    for (int e = tid; e < nb * nb; e += nt) QB[(e % nb) + (e / nb) * JLD] = qb[(e % nb) + (e / nb) * J2];
+  __syncthreads();
+  for (int e = tid; e < na * nb; e += nt) {  // T = M_ab Q_b
+    int x = e % na, y = e / na;
+    S t = zero;
+    if (rb) {
+      for (int u = 0; u < nb; ++u) t += Ms[x + u * JLD] * QB[u + y * JLD];
+    } else {
+      t = Ms[x + y * JLD];
+    }
+    Ts[x + y * JLD] = t;
+  }
+  __syncthreads();
+  for (int e = tid; e < na * nb; e += nt) {  // Q_a^H T
+    int x = e % na, y = e / na;
+    S t = zero;
+    if (ra) {
+      for (int u = 0; u < na; ++u) t += conj_(QA[u + x * JLD]) * Ts[u + y * JLD];
+    } else {
+      t = Ts[x + y * JLD];
+    }
+    Ms[x + y * JLD] = t;
+  }
+  __syncthreads();
+  return true;
+}
+
+// Pair eigensolve t of `round` (NT threads; more waves hide the LDS latency of
+// the Jacobi rounds).  The pair problem is read from M_round; with fused
+// rounds and round >= 1 it is formed here from M_{round-1} and the previous
+// round's rotations, tile by tile (sh: scratch for bj_tile).  Writes Q and the
+// flag of parity `par`.
 template <class S, int NT>
-PPCG_DEV void bj_pair_body(const EigDev& a, int round, unsigned t) {
+PPCG_DEV void bj_pair_body(const EigDev& a, int round, unsigned t, bool fused, int par, S* sh) {
   __shared__ S Sm[J2 * JLD], Qs[J2 * JLD];
   __shared__ double red[NT / 64];
   __shared__ JRot<S> jr[J2 / 2 + 1];
   __shared__ int any;
-  const S* M = (const S*)a.M;
   const int tid = threadIdx.x;
   if (round >= a.nbe - 1) return;
   int nI, nJ, i0, j0;
   pair_of(a, t, round, nI, nJ, i0, j0);
   const int n2 = nI + nJ;
-  auto gidx = [&](int x) { return x < nI ? i0 + x : j0 + (x - nI); };
   const double tiny = bj_tiny(a);
   if (tid == 0) any = 0;
-  __syncthreads();
-  for (int e = tid; e < n2 * n2; e += NT) {
-    int x = e % n2, y = e / n2;
-    S v = M[gidx(x) + (long)gidx(y) * a.ld];
-    Sm[x + y * JLD] = v;
-    if (x != y && sqrt(abs2_(v)) > tiny) any = 1;
+  if (fused && round > 0) {
+    int lds;
+    const S* src = bj_buf<S>(a, round - 1, lds);
+    // blocks of this pair: (global block, size, offset in this pair)
+    const int nbk = nJ > 0 ? 2 : 1;
+    const int bk[2] = {i0 / JB, j0 / JB}, bs[2] = {nI, nJ}, bo[2] = {0, nI};
+    int pt[2], po[2];
+    for (int u = 0; u < nbk; ++u) locate(a, bk[u], round - 1, pt[u], po[u]);
+    for (int u = 0; u < nbk; ++u)
+      for (int v = 0; v < nbk; ++v) {
+        int na, nb;
+        __syncthreads();
+        const bool rot = bj_tile<S>(a, round - 1, src, lds, par ^ 1, pt[u], pt[v], sh, na, nb);
+        int nIu, nJu, i0u, j0u, nIv, nJv, i0v, j0v;
+        pair_of(a, pt[u], round - 1, nIu, nJu, i0u, j0u);
+        pair_of(a, pt[v], round - 1, nIv, nJv, i0v, j0v);
+        for (int e = tid; e < bs[u] * bs[v]; e += NT) {
+          const int x = e % bs[u], y = e / bs[u];
+          S val;
+          if (rot) {
+            val = sh[(po[u] + x) + (po[v] + y) * JLD];
+          } else {
+            const int xx = po[u] + x, yy = po[v] + y;
+            const int gx = xx < nIu ? i0u + xx : j0u + (xx - nIu);
+            const int gy = yy < nIv ? i0v + yy : j0v + (yy - nIv);
+            val = src[gx + (long)gy * lds];
+          }
+          const int xs = bo[u] + x, ys = bo[v] + y;
+          Sm[xs + ys * JLD] = val;
+          if (xs != ys && sqrt(abs2_(val)) > tiny) any = 1;
+        }
+      }
+    __syncthreads();
+  } else {
+    int lds;
+    const S* M = bj_buf<S>(a, fused ? round : 0, lds);
+    auto gidx = [&](int x) { return x < nI ? i0 + x : j0 + (x - nI); };
+    __syncthreads();
+    for (int e = tid; e < n2 * n2; e += NT) {
+      int x = e % n2, y = e / n2;
+      S v = M[gidx(x) + (long)gidx(y) * lds];
+      Sm[x + y * JLD] = v;
+      if (x != y && sqrt(abs2_(v)) > tiny) any = 1;
+    }
+    __syncthreads();
   }
-  __syncthreads();
+  int* fl = a.flags + par * a.fst;
   if (!any) {
-    if (tid == 0) a.flags[t] = 0;
+    if (tid == 0) fl[t] = 0;
     return;
   }
   lds_jacobi<NT, S>(Sm, Qs, n2, JLD, tiny, BJ_INNER, jr, red);
-  S* Qg = (S*)a.Q + (long)t * J2 * J2;
+  S* Qg = (S*)a.Q + ((long)par * a.np + t) * J2 * J2;
   for (int e = tid; e < n2 * n2; e += NT) Qg[(e % n2) + (e / n2) * J2] = Qs[(e % n2) + (e / n2) * JLD];
-  if (tid == 0) a.flags[t] = 1;
+  if (tid == 0) fl[t] = 1;
 }
 
 // Stop test after a sweep: counts the workgroups that see an off-diagonal
@@ -737,89 +863,65 @@ PPCG_DEV void bj_check_body(const EigDev& a, unsigned wg) {
   if (threadIdx.x == 0 && any) atomicAdd(a.counter, 1);
 }
 
-// One round's two-sided update in a single launch.  Items [0, np^2): the
-// tile (rows of pair a) x (columns of pair b) of M becomes Q_a^H M_ab Q_b
-// (Q = I for a pair that did not rotate); tiles are disjoint, so no item
-// depends on another.  Items [np^2, np^2 + np * ceil(m/64)): 64 rows of the
-// accumulated rotations, Vt[rows, cols of pair b] <- Vt[rows, cols] Q_b.
+// One round's two-sided update.  Items [0, np^2): the tile (rows of pair a) x
+// (columns of pair b) of M_round becomes Q_a^H M_ab Q_b in M_{round+1} (Q = I
+// for a pair that did not rotate; a tile neither pair rotated is copied when
+// the two buffers differ); tiles are disjoint, so no item depends on another.
+// Items [np^2, np^2 + np * ceil(m/64)): 64 rows of the accumulated rotations,
+// Vt[rows, cols of pair b] <- Vt[rows, cols] Q_b, in place.  Unfused rounds
+// update the caller's matrix in place (src = dst, parity 0).
 template <class S>
-PPCG_DEV void bj_update_body(const EigDev& a, int round, unsigned wg) {
-  __shared__ S sh[4 * J2 * JLD];
+PPCG_DEV void bj_update_body(const EigDev& a, int round, unsigned wg, bool fused, int par, S* sh) {
   if (round >= a.nbe - 1) return;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, nt = blockDim.x;
   const int np = a.np;
   const unsigned nmt = (unsigned)np * np;
   const S zero = from_real<S>(0.0);
+  int lds = a.ld, ldd = a.ld;
+  const S* src = (const S*)a.M;
+  S* dst = (S*)a.M;
+  if (fused) {
+    src = bj_buf<S>(a, round, lds);
+    dst = round + 1 == a.nbe - 1 ? (S*)a.M : bj_buf<S>(a, round + 1, ldd);
+    if (round + 1 == a.nbe - 1) ldd = a.ld;
+  }
   if (wg < nmt) {
     const int ta = (int)(wg % np), tb = (int)(wg / np);
-    const bool ra = a.flags[ta] != 0, rb = a.flags[tb] != 0;
-    if (!ra && !rb) return;
+    int na, nb;
+    const bool rot = bj_tile<S>(a, round, src, lds, par, ta, tb, sh, na, nb);
+    if (!rot && src == dst) return;
     int nIa, nJa, i0a, j0a, nIb, nJb, i0b, j0b;
     pair_of(a, ta, round, nIa, nJa, i0a, j0a);
     pair_of(a, tb, round, nIb, nJb, i0b, j0b);
-    const int na = nIa + nJa, nb = nIb + nJb;
-    if (na == 0 || nb == 0) return;
     auto ga = [&](int x) { return x < nIa ? i0a + x : j0a + (x - nIa); };
     auto gb = [&](int y) { return y < nIb ? i0b + y : j0b + (y - nIb); };
-    S* Ms = sh;
-    S* Ts = sh + J2 * JLD;
-    S* QA = sh + 2 * J2 * JLD;
-    S* QB = sh + 3 * J2 * JLD;
-    S* M = (S*)a.M;
-    const S* qa = (const S*)a.Q + (long)ta * J2 * J2;
-    const S* qb = (const S*)a.Q + (long)tb * J2 * J2;
-    for (int e = tid; e < na * nb; e += 256) {
+    for (int e = tid; e < na * nb; e += nt) {
       int x = e % na, y = e / na;
-      Ms[x + y * JLD] = M[ga(x) + (long)gb(y) * a.ld];
-    }
-    if (ra)
-      for (int e = tid; e < na * na; e += 256) QA[(e % na) + (e / na) * JLD] = qa[(e % na) + (e / na) * J2];
-    if (rb)
-      for (int e = tid; e < nb * nb; e += 256) QB[(e % nb) + (e / nb) * JLD] = qb[(e % nb) + (e / nb) * J2];
-    __syncthreads();
-    for (int e = tid; e < na * nb; e += 256) {  // T = M_ab Q_b
-      int x = e % na, y = e / na;
-      S t = zero;
-      if (rb) {
-        for (int u = 0; u < nb; ++u) t += Ms[x + u * JLD] * QB[u + y * JLD];
-      } else {
-        t = Ms[x + y * JLD];
-      }
-      Ts[x + y * JLD] = t;
-    }
-    __syncthreads();
-    for (int e = tid; e < na * nb; e += 256) {  // Q_a^H T
-      int x = e % na, y = e / na;
-      S t = zero;
-      if (ra) {
-        for (int u = 0; u < na; ++u) t += conj_(QA[u + x * JLD]) * Ts[u + y * JLD];
-      } else {
-        t = Ts[x + y * JLD];
-      }
-      M[ga(x) + (long)gb(y) * a.ld] = t;
+      dst[ga(x) + (long)gb(y) * ldd] = rot ? sh[x + y * JLD] : src[ga(x) + (long)gb(y) * lds];
     }
     return;
   }
+  const int* fl = a.flags + par * a.fst;
   const unsigned it = wg - nmt;
   const int tb = (int)(it % np), chunk = (int)(it / np);
-  if (!a.flags[tb]) return;
+  if (!fl[tb]) return;
   int nI, nJ, i0, j0;
   pair_of(a, tb, round, nI, nJ, i0, j0);
   const int n2 = nI + nJ;
   auto gidx = [&](int x) { return x < nI ? i0 + x : j0 + (x - nI); };
   S* Qs = sh;
   S* R = sh + J2 * JLD;  // 64 rows x n2, ld JLD
-  const S* Qg = (const S*)a.Q + (long)tb * J2 * J2;
-  for (int e = tid; e < n2 * n2; e += 256) Qs[(e % n2) + (e / n2) * JLD] = Qg[(e % n2) + (e / n2) * J2];
+  const S* Qg = (const S*)a.Q + ((long)par * np + tb) * J2 * J2;
+  for (int e = tid; e < n2 * n2; e += nt) Qs[(e % n2) + (e / n2) * JLD] = Qg[(e % n2) + (e / n2) * J2];
   const int c0 = chunk * 64;
   const int nc = min(64, a.m - c0);
   S* Vt = (S*)a.Vt;
-  for (int e = tid; e < nc * n2; e += 256) {
+  for (int e = tid; e < nc * n2; e += nt) {
     int r = e % nc, x = e / nc;
     R[x + r * JLD] = Vt[(c0 + r) + (long)gidx(x) * a.m];
   }
   __syncthreads();
-  for (int e = tid; e < nc * n2; e += 256) {
+  for (int e = tid; e < nc * n2; e += nt) {
     int r = e % nc, x = e / nc;
     S t = zero;
     for (int u = 0; u < n2; ++u) t += R[u + r * JLD] * Qs[u + x * JLD];
@@ -861,24 +963,40 @@ PPCG_DEV void bj_gather_body(const EigDev& a, unsigned wg) {
   ((S*)a.V)[i + (long)a.rank[j] * a.ldv] = ((const S*)a.Vt)[i + (long)j * a.m];
 }
 
-// STEP: 0 init, 1 pair eigensolves, 2 two-sided update of M and Vt, 3 rank, 4 gather,
-// 5 stop test
+// STEP: 0 init, 1 pair eigensolves, 2 two-sided update of M and Vt, 3 rank,
+// 4 gather, 5 stop test; fused rounds: 6 pair eigensolves of round 0, 7 pair
+// eigensolves of `round` beside the update of round - 1, 8 the update of the
+// last round
 #ifndef PPCG_BJ_PAIR_NT
 #define PPCG_BJ_PAIR_NT 1024
 #endif
+#ifndef PPCG_BJ_FUSED
+#define PPCG_BJ_FUSED 0
+#endif
 constexpr int BJ_PAIR_NT = PPCG_BJ_PAIR_NT;
-template <int STEP> constexpr int bj_threads() { return STEP == 1 ? BJ_PAIR_NT : 256; }
+template <int STEP> constexpr int bj_threads() { return (STEP == 1 || STEP >= 6) ? BJ_PAIR_NT : 256; }
+template <class S>
+PPCG_DEV S* bj_scratch() {
+  __shared__ S sh[4 * J2 * JLD];
+  return sh;
+}
 template <class S, int STEP>
 __global__ __launch_bounds__(bj_threads<STEP>()) void bj_grouped(const EigDev* jobs, const unsigned* start, int nj, int round) {
   int j = find_job(start, nj, blockIdx.x);
   unsigned wg = blockIdx.x - start[j];
   const EigDev& a = jobs[j];
-  if (STEP == 0) bj_init_body<S>(a, wg);
-  if (STEP == 1) bj_pair_body<S, BJ_PAIR_NT>(a, round, wg);
-  if (STEP == 2) bj_update_body<S>(a, round, wg);
-  if (STEP == 3) bj_rank_body<S>(a, wg);
-  if (STEP == 4) bj_gather_body<S>(a, wg);
-  if (STEP == 5) bj_check_body<S>(a, wg);
+  if constexpr (STEP == 0) bj_init_body<S>(a, wg);
+  if constexpr (STEP == 1) bj_pair_body<S, BJ_PAIR_NT>(a, round, wg, false, 0, nullptr);
+  if constexpr (STEP == 2) bj_update_body<S>(a, round, wg, false, 0, bj_scratch<S>());
+  if constexpr (STEP == 3) bj_rank_body<S>(a, wg);
+  if constexpr (STEP == 4) bj_gather_body<S>(a, wg);
+  if constexpr (STEP == 5) bj_check_body<S>(a, wg);
+  if constexpr (STEP == 6) bj_pair_body<S, BJ_PAIR_NT>(a, 0, wg, true, 0, bj_scratch<S>());
+  if constexpr (STEP == 7) {
+    if (wg < (unsigned)a.np) bj_pair_body<S, BJ_PAIR_NT>(a, round, wg, true, round & 1, bj_scratch<S>());
+    else bj_update_body<S>(a, round - 1, wg - a.np, true, (round - 1) & 1, bj_scratch<S>());
+  }
+  if constexpr (STEP == 8) bj_update_body<S>(a, round, wg, true, round & 1, bj_scratch<S>());
 }
 
 void EigGraphCache::clear() {
@@ -924,10 +1042,13 @@ int block_jacobi_eig_grouped(const std::vector<EigJob>& jobs, Stage& stage, EigG
       case 2: return (unsigned)(a.np * a.np + a.np * ((a.m + 63) / 64));
       case 3: return (unsigned)((a.m + 255) / 256);
       case 4: return (unsigned)((mm + 255) / 256);
-      default: return (unsigned)((mm + BJ_CHECK_PER_WG - 1) / BJ_CHECK_PER_WG);
+      case 5: return (unsigned)((mm + BJ_CHECK_PER_WG - 1) / BJ_CHECK_PER_WG);
+      case 6: return (unsigned)a.np;
+      case 7: return (unsigned)(a.np + a.np * a.np + a.np * ((a.m + 63) / 64));
+      default: return (unsigned)(a.np * a.np + a.np * ((a.m + 63) / 64));
     }
   };
-  constexpr int NSTEP = 6;
+  constexpr int NSTEP = 9;
   const unsigned* sd[NSTEP];
   unsigned tot[NSTEP];
   std::vector<unsigned> starts;
@@ -970,7 +1091,8 @@ int block_jacobi_eig_grouped(const std::vector<EigJob>& jobs, Stage& stage, EigG
   const EigDev* dj = (const EigDev*)dev;
   for (int step = 0; step < NSTEP; ++step) sd[step] = (const unsigned*)(dev + jb) + step * (nj + 1);
   auto launch = [&](auto kernel, int step, int round) {
-    hipLaunchKernelGGL(kernel, dim3(tot[step]), dim3(step == 1 ? BJ_PAIR_NT : 256), 0, st, dj, sd[step], nj, round);
+    const int nt = (step == 1 || step >= 6) ? BJ_PAIR_NT : 256;
+    hipLaunchKernelGGL(kernel, dim3(tot[step]), dim3(nt), 0, st, dj, sd[step], nj, round);
   };
   auto run = [&](int step, int round) {
     if (!tot[step]) return;
@@ -981,7 +1103,10 @@ int block_jacobi_eig_grouped(const std::vector<EigJob>& jobs, Stage& stage, EigG
         case 2: launch(bj_grouped<zdouble, 2>, step, round); break;
         case 3: launch(bj_grouped<zdouble, 3>, step, round); break;
         case 4: launch(bj_grouped<zdouble, 4>, step, round); break;
-        default: launch(bj_grouped<zdouble, 5>, step, round); break;
+        case 5: launch(bj_grouped<zdouble, 5>, step, round); break;
+        case 6: launch(bj_grouped<zdouble, 6>, step, round); break;
+        case 7: launch(bj_grouped<zdouble, 7>, step, round); break;
+        default: launch(bj_grouped<zdouble, 8>, step, round); break;
       }
     } else {
       switch (step) {
@@ -990,16 +1115,25 @@ int block_jacobi_eig_grouped(const std::vector<EigJob>& jobs, Stage& stage, EigG
         case 2: launch(bj_grouped<double, 2>, step, round); break;
         case 3: launch(bj_grouped<double, 3>, step, round); break;
         case 4: launch(bj_grouped<double, 4>, step, round); break;
-        default: launch(bj_grouped<double, 5>, step, round); break;
+        case 5: launch(bj_grouped<double, 5>, step, round); break;
+        case 6: launch(bj_grouped<double, 6>, step, round); break;
+        case 7: launch(bj_grouped<double, 7>, step, round); break;
+        default: launch(bj_grouped<double, 8>, step, round); break;
       }
     }
   };
   // one sweep: every round's two launches, then the stop test into the zeroed
   // counter, read back
   auto sweep_ops = [&]() {
-    for (int round = 0; round < maxr; ++round) {
-      run(1, round);
-      run(2, round);
+    if (PPCG_BJ_FUSED) {  // one launch per round: its pair eigensolves beside the previous round's update
+      run(6, 0);
+      for (int round = 1; round < maxr; ++round) run(7, round);
+      run(8, maxr - 1);
+    } else {
+      for (int round = 0; round < maxr; ++round) {
+        run(1, round);
+        run(2, round);
+      }
     }
     ZeroIntArgs z{dev_counter, 1};
     hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(256), 0, st, z);

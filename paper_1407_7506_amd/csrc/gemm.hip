@@ -1177,7 +1177,7 @@ static int update_kind(const UpdateArgs& a, bool f32) {
   case OP_GRAMB_2: hipLaunchKernelGGL((KERNEL<2, 10>), dim3(GRID), dim3(256), 0, st, __VA_ARGS__); break;
 
 #ifndef PPCG_UPD64_LEAN
-#define PPCG_UPD64_LEAN 0
+#define PPCG_UPD64_LEAN 1
 #endif
 #if PPCG_UPD64_LEAN
 #define PPCG_UPDATEL_D(KERNEL, SITE, GRID, ...) \

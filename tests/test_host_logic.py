@@ -149,3 +149,115 @@ def test_hbm_rates_and_solve_roofline():
     sr = bench.solve_roofline({"roofline_ms": 50.0, "time_s": 0.2})
     assert sr["frac"] == pytest.approx(0.25)
     assert bench.stage_ms({"stage_ms": [1, 2, 3, 4, 5, 6]})["cholqr"] == 4
+
+
+# --- the block-Jacobi round schedule of the Rayleigh-Ritz eigensolver --------
+# 16-wide blocks, circle (round-robin) pairing; the device code fuses the pair
+# eigensolves of round r with the two-sided update of round r - 1, keeping M_r
+# in alternating buffers and forming each pair problem from M_{r-1} and the
+# previous round's rotations.  These tests replay that schedule in numpy (the
+# pair eigensolves by numpy's eigh) and check it against rounds run one after
+# the other, and the inverse of the pairing it relies on.
+JB = 16
+
+
+def _rr_player(pos, rnd, n):
+    return 0 if pos == 0 else ((pos - 1 + rnd) % (n - 1)) + 1
+
+
+def _pair(m, nbe, t, rnd):
+    nblk = (m + JB - 1) // JB
+    i, j = sorted((_rr_player(t, rnd, nbe), _rr_player(nbe - 1 - t, rnd, nbe)))
+    idx = list(range(i * JB, min(m, i * JB + JB))) if i < nblk else []
+    return idx + (list(range(j * JB, min(m, j * JB + JB))) if j < nblk else [])
+
+
+def _locate(nbe, b, rnd):
+    n1, npairs = nbe - 1, nbe // 2
+    pos = 0 if b == 0 else ((b - 1 - rnd) % n1 + n1) % n1 + 1
+    return pos if pos < npairs else nbe - 1 - pos
+
+
+def _tile(M, Q, rot, a, b, pa, pb):
+    T = M[np.ix_(pa, pb)]
+    T = T @ Q[b] if rot[b] else T
+    return Q[a].T @ T if rot[a] else T
+
+
+def _sweep_sequential(M, m, nbe):
+    M, Vt = M.copy(), np.eye(m)
+    for rnd in range(nbe - 1):
+        P = [_pair(m, nbe, t, rnd) for t in range(nbe // 2)]
+        Q = {t: np.linalg.eigh(M[np.ix_(p, p)])[1] for t, p in enumerate(P) if p}
+        rot = {t: bool(p) for t, p in enumerate(P)}
+        new = M.copy()
+        for a, pa in enumerate(P):
+            for b, pb in enumerate(P):
+                if pa and pb:
+                    new[np.ix_(pa, pb)] = _tile(M, Q, rot, a, b, pa, pb)
+        M = new
+        for b, pb in enumerate(P):
+            if rot[b]:
+                Vt[:, pb] = Vt[:, pb] @ Q[b]
+    return M, Vt
+
+
+def _sweep_fused(M, m, nbe):
+    home, second, Vt, R = M.copy(), np.full_like(M, np.nan), np.eye(m), nbe - 1
+    buf = (lambda r: second if r % 2 else home)
+    Qs, rots = [{}, {}], [{}, {}]
+    for r in range(R + 1):
+        if r < R:  # pair eigensolves of round r, from M_{r-1} and the rotations of r - 1
+            par = r & 1
+            for t in range(nbe // 2):
+                idx = _pair(m, nbe, t, r)
+                rots[par][t] = bool(idx)
+                if not idx:
+                    continue
+                if r == 0:
+                    S = home[np.ix_(idx, idx)]
+                else:
+                    prev = [_pair(m, nbe, u, r - 1) for u in range(nbe // 2)]
+                    S = np.empty((len(idx), len(idx)))
+                    for x, gx in enumerate(idx):
+                        for y, gy in enumerate(idx):
+                            a, b = _locate(nbe, gx // JB, r - 1), _locate(nbe, gy // JB, r - 1)
+                            T = _tile(buf(r - 1), Qs[par ^ 1], rots[par ^ 1], a, b, prev[a], prev[b])
+                            S[x, y] = T[prev[a].index(gx), prev[b].index(gy)]
+                Qs[par][t] = np.linalg.eigh(S)[1]
+        if r >= 1:  # update of round r - 1 into M_r (the caller's matrix after the last round)
+            rp, par = r - 1, (r - 1) & 1
+            P = [_pair(m, nbe, t, rp) for t in range(nbe // 2)]
+            src, dst = buf(rp), (home if rp + 1 == R else buf(rp + 1))
+            out = {(a, b): _tile(src, Qs[par], rots[par], a, b, pa, pb)
+                   for a, pa in enumerate(P) for b, pb in enumerate(P) if pa and pb}
+            for (a, b), v in out.items():
+                dst[np.ix_(P[a], P[b])] = v
+            for b, pb in enumerate(P):
+                if rots[par][b]:
+                    Vt[:, pb] = Vt[:, pb] @ Qs[par][b]
+    return home, Vt
+
+
+def test_block_jacobi_pairing_inverse():
+    for m in list(range(1, 120)) + [528, 2112]:
+        nblk = (m + JB - 1) // JB
+        nbe = nblk + (nblk & 1)
+        for rnd in range(nbe - 1):
+            for t in range(nbe // 2):
+                for gx in _pair(m, nbe, t, rnd):
+                    assert _locate(nbe, gx // JB, rnd) == t
+
+
+@pytest.mark.parametrize("m", [17, 40, 48, 70])
+def test_fused_jacobi_rounds_equal_sequential_rounds(m):
+    rng = np.random.default_rng(m)
+    A = rng.standard_normal((m, m))
+    A = A + A.T
+    nblk = (m + JB - 1) // JB
+    nbe = nblk + (nblk & 1)
+    M1, V1 = _sweep_sequential(A, m, nbe)
+    M2, V2 = _sweep_fused(A, m, nbe)
+    assert np.array_equal(M1, M2) and np.array_equal(V1, V2)
+    # one sweep is a similarity transform by an orthogonal matrix
+    assert np.allclose(V1.T @ A @ V1, M1, atol=1e-10)
