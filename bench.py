@@ -323,6 +323,8 @@ def bench_bloch(args):
         torch.cuda.empty_cache()
         kt = h.kernel_times()
         results[prec] = {"s": dt, "info": info, "lam": lam.cpu().numpy(), "kt": kt}
+        if args.save_lam:
+            np.save(f"{args.save_lam}_{prec}.npy", results[prec]["lam"])
         log(f"{prec}: {dt:.1f} s, status {info['status']}, iters {info['iters']}, rr {info['n_rr']}, "
             f"resid {info['resid_final']:.3e}")
         for name, (ms, cnt, fl, by) in sorted(kt.items(), key=lambda x: -x[1][0])[:16]:
@@ -436,6 +438,8 @@ def main():
     ap.add_argument("--nprob", type=int, default=64, help="problems of the batch64 workload")
     ap.add_argument("--max-iter", type=int, default=20000, help="iteration cap (bloch96)")
     ap.add_argument("--device-x0", action="store_true", help="bloch96: start block drawn on the device")
+    ap.add_argument("--save-lam", default="",
+                    help="bloch96: write the eigenvalues of each precision's solve to <path>_<precision>.npy")
     ap.add_argument("--orth-skip", action="store_true",
                     help="bloch96: omit Cholesky-QR while |X^H X - I|_F <= 0.1 (section 5.5)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),

@@ -415,8 +415,77 @@ PPCG_DEV S uniform_load(const S* p) {
   else return r[0];
 }
 
+// Complex or wide blocks: one row per lane, the q output columns split into
+// groups of NO, one group per wave (or pair of waves) of the workgroup, and
+// the inputs streamed one column at a time, so only the 2 NO accumulators of a
+// group stay in registers.  Every group reads the whole row of X, W and P
+// (from the CU's cache after the first); a barrier separates those reads from
+// the in-place stores of X and P.  Each output receives the same operations
+// in the same order as in the row-per-thread form.
+template <class SX> constexpr int bupd_no() { return sc_traits<SX>::cplx ? 8 : 16; }
+template <class TW, class SX, int QM>
+PPCG_DEV void block_update_wide_body(const BlockUpdArgs& a, unsigned wg, unsigned nwg) {
+  constexpr int NO = QM < bupd_no<SX>() ? QM : bupd_no<SX>();
+  constexpr int G = QM / NO;    // output groups
+  constexpr int RW = 256 / G;   // rows per workgroup (a multiple of 64: groups are whole waves)
+  const int q = a.q;
+  const unsigned rtiles = (unsigned)((a.rows + RW - 1) / RW);
+  const unsigned L = xcd_remap(wg, nwg);
+  const int blk = L / rtiles;
+  const int grp = threadIdx.x / RW;
+  const long r = (long)(L % rtiles) * RW + threadIdx.x % RW;
+  const int t0 = grp * NO;
+  const bool ok = r < a.rows;
+  const SX* __restrict__ C = (const SX*)a.C + (long)blk * a.cstride;
+  const int ldc = 3 * q;
+  const long cb = (long)blk * q * a.ld;
+  SX* X = (SX*)a.X + cb;
+  TW* W = (TW*)a.W + cb;
+  TW* P = (TW*)a.P + cb;
+  const SX zero = from_real<SX>(0.0);
+  SX xn[NO], pn[NO];
+#pragma unroll
+  for (int u = 0; u < NO; ++u) xn[u] = pn[u] = zero;
+  if (ok && t0 < q) {
+    for (int i = 0; i < q; ++i) {
+      const long o = r + i * a.ld;
+      const SX x = X[o];
+      const SX w = cvt<SX, TW>(W[o]);
+      const SX p = a.hasP ? cvt<SX, TW>(P[o]) : zero;
+#pragma unroll
+      for (int u = 0; u < NO; ++u) {
+        const int t = t0 + u;
+        if (t < q) {
+          const SX* ct = C + t * ldc;
+          const SX cw = uniform_load(ct + q + i), cp = uniform_load(ct + 2 * q + i), cx = uniform_load(ct + i);
+          pn[u] += w * cw;
+          if (a.hasP) pn[u] += p * cp;
+          xn[u] += x * cx;
+        }
+      }
+    }
+  }
+  __syncthreads();  // every group has read the row before any group overwrites it
+  if (ok && t0 < q) {
+#pragma unroll
+    for (int u = 0; u < NO; ++u) {
+      const int t = t0 + u;
+      if (t < q) {
+        const long o = r + t * a.ld;
+        xn[u] += pn[u];
+        P[o] = cvt<TW, SX>(pn[u]);
+        X[o] = xn[u];
+      }
+    }
+  }
+}
+
 template <class TW, class SX, int QM>
 PPCG_DEV void block_update_body(const BlockUpdArgs& a, unsigned wg, unsigned nwg) {
+  if constexpr (sc_traits<SX>::cplx || QM > 16) {
+    block_update_wide_body<TW, SX, QM>(a, wg, nwg);
+    return;
+  }
   constexpr int RPT = bupd_rpt<SX, QM>();
   const int q = a.q;
   const unsigned rtiles = (unsigned)((a.rows + 256 * RPT - 1) / (256 * RPT));
@@ -554,8 +623,11 @@ static int bupd_kind(const BlockUpdArgs& a) {
   }
 
 void launch_block_update(const BlockUpdArgs& a, hipStream_t st) {
-  // rows per workgroup: 256 times the rows per thread of the selected kernel
-  const long rpw = (a.cplx || a.q > 16) ? 256 : 512;
+  // rows per workgroup of the selected kernel: the wide form's 256 / groups,
+  // else 256 times the rows per thread
+  const int qm = a.q <= 4 ? 4 : a.q <= 8 ? 8 : a.q <= 16 ? 16 : 32;
+  const int no = a.cplx ? 8 : 16;
+  const long rpw = (a.cplx || a.q > 16) ? 256 / (qm < no ? 1 : qm / no) : 512;
   unsigned blocks = (unsigned)(((a.rows + rpw - 1) / rpw) * (a.nblocks > 0 ? a.nblocks : 0));
   int kind = bupd_kind(a);
   if (g_rec) {
