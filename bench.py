@@ -174,7 +174,12 @@ def write_traffic(fetch_db, write_db, launches, precision, path=None):
                          "where counter_name = ? order by dispatch_id", (counter,)).fetchall()
         return rows
 
-    out = {"source_sha": kernel_source_sha(), "precision": precision, "kernels": {}, "calibration": {}}
+    out = {"source_sha": kernel_source_sha(), "precision": precision, "kernels": {}, "calibration": {},
+           "command": ("two rocprofv3 runs from the repository root, one per counter: rocprofv3 --pmc FETCH_SIZE "
+                       "(then WRITE_SIZE) -d <dir> -o run -- python3 bench.py --steps 1 --warmup 1 --only "
+                       f"{precision} --calib-copy --no-cpu-baseline; reduced by python3 bench.py --traffic-from "
+                       f"<FETCH_DB> <WRITE_DB> --traffic-precision {precision} --traffic-launches "
+                       "<launches_per_solve of the profiled run>")}
     per = {}
     for db, counter in ((fetch_db, "FETCH_SIZE"), (write_db, "WRITE_SIZE")):
         rows = load(db, counter)
