@@ -443,6 +443,15 @@ PPCG_DEV void block_update_wide_body(const BlockUpdArgs& a, unsigned wg, unsigne
   TW* W = (TW*)a.W + cb;
   TW* P = (TW*)a.P + cb;
   const SX zero = from_real<SX>(0.0);
+  // the block's coefficients in LDS, [input i][output t] for each of the
+  // X, W and P parts, read as broadcasts (one address for the whole wave)
+  __shared__ SX Cs[3 * QM * QM];
+  for (int e = threadIdx.x; e < 3 * q * q; e += 256) {
+    const int i = e % ldc, t = e / ldc;  // C is 3q x q, ld 3q
+    const int part = i / q, ii = i % q;
+    Cs[(part * QM + ii) * QM + t] = C[i + (long)t * ldc];
+  }
+  __syncthreads();
   SX xn[NO], pn[NO];
 #pragma unroll
   for (int u = 0; u < NO; ++u) xn[u] = pn[u] = zero;
@@ -452,15 +461,15 @@ PPCG_DEV void block_update_wide_body(const BlockUpdArgs& a, unsigned wg, unsigne
       const SX x = X[o];
       const SX w = cvt<SX, TW>(W[o]);
       const SX p = a.hasP ? cvt<SX, TW>(P[o]) : zero;
+      const SX* cx_ = Cs + i * QM + t0;
+      const SX* cw_ = Cs + (QM + i) * QM + t0;
+      const SX* cp_ = Cs + (2 * QM + i) * QM + t0;
 #pragma unroll
       for (int u = 0; u < NO; ++u) {
-        const int t = t0 + u;
-        if (t < q) {
-          const SX* ct = C + t * ldc;
-          const SX cw = uniform_load(ct + q + i), cp = uniform_load(ct + 2 * q + i), cx = uniform_load(ct + i);
-          pn[u] += w * cw;
-          if (a.hasP) pn[u] += p * cp;
-          xn[u] += x * cx;
+        if (t0 + u < q) {
+          pn[u] += w * cw_[u];
+          if (a.hasP) pn[u] += p * cp_[u];
+          xn[u] += x * cx_[u];
         }
       }
     }
