@@ -13,6 +13,7 @@
 #include <algorithm>
 
 #include <stdexcept>
+#include <type_traits>
 
 #include "common.hpp"
 #include "jacobi.hpp"
@@ -116,6 +117,31 @@ PPCG_DEV void tile_put4(S* T, const S (&c)[4]) {
   }
 }
 
+// Float64 32 x 32 tile product on the matrix cores: each of the four waves
+// forms one 16 x 16 quadrant of A op(B) (op = identity, or transpose when BH)
+// from LDS tiles (ld CLD) in 8 MFMA steps; acc value v of lane l is entry
+// (16 qx + 4 v + l/16, 16 qy + l%16).
+template <bool BH>
+PPCG_DEV d4v tile_mfma(const double* A, const double* B) {
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int qx = w & 1, qy = w >> 1, lc = l & 15, g = l >> 4;
+  d4v acc = {0, 0, 0, 0};
+#pragma unroll
+  for (int t0 = 0; t0 < CB; t0 += 4) {
+    const double av = A[(16 * qx + lc) + (t0 + g) * CLD];
+    const double bv = BH ? B[(16 * qy + lc) + (t0 + g) * CLD] : B[(t0 + g) + (16 * qy + lc) * CLD];
+    acc = mfma(av, bv, acc);
+  }
+  return acc;
+}
+template <class S>
+PPCG_DEV void acc_put(S* T, const d4v& acc) {
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int qx = w & 1, qy = w >> 1;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) T[(16 * qx + 4 * v + (l >> 4)) + (16 * qy + (l & 15)) * CLD] = acc[v];
+}
+
 // factor the diagonal tile p of G (already updated by every earlier step):
 // Li_pp = L_pp^{-1}; a non-positive pivot sets *flag = p + 1.  The inverse is
 // formed inside the factorization loop by forward substitution in column
@@ -174,6 +200,10 @@ PPCG_DEV void chol_diag_body(const DenseStep& a, int p) {
 template <class S>
 PPCG_DEV void chol_step_body(const DenseStep& a, int p, unsigned wg) {
   __shared__ S T0[CB * CLD], T1[CB * CLD], T2[CB * CLD];
+  constexpr bool MF = std::is_same<S, double>::value;  // float64: tile products on the matrix cores
+  __shared__ S T3[MF ? CB * CLD : 1], T4[MF ? CB * CLD : 1];
+  const int ml = threadIdx.x & 63, mw = threadIdx.x >> 6;
+  const int mx0 = 16 * (mw & 1) + 4 * 0 + (ml >> 4), my = 16 * (mw >> 1) + (ml & 15);  // acc value v: row mx0 + 4 v
   S* G = (S*)a.G;
   S* W = (S*)a.W;
   S* Li = (S*)a.Li;
@@ -193,18 +223,30 @@ PPCG_DEV void chol_step_body(const DenseStep& a, int p, unsigned wg) {
     tile_get(T1, G, ld, i * CB, n0, nbi, nbp);       // G_ip
     tile_get(T2, G, ld, j * CB, n0, nbj, nbp);       // G_jp
     __syncthreads();
-    S d[4];
-    tile_mul4<S, true>(c, T1, T0);                   // L_ip = G_ip Li_pp^H
-    tile_mul4<S, true>(d, T2, T0);                   // L_jp
-    __syncthreads();
-    tile_put4(T1, c);
-    tile_put4(T2, d);
-    __syncthreads();
-    tile_mul4<S, true>(c, T1, T2);                   // L_ip L_jp^H
+    if constexpr (MF) {
+      acc_put(T3, tile_mfma<true>(T1, T0));          // L_ip = G_ip Li_pp^T
+      acc_put(T4, tile_mfma<true>(T2, T0));          // L_jp
+      __syncthreads();
+      const d4v r = tile_mfma<true>(T3, T4);         // L_ip L_jp^T
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      int e = threadIdx.x + 256 * s, x = e % CB, y = e / CB;
-      if (x < nbi && y < nbj && (i != j || x >= y)) G[(i * CB + x) + (long)(j * CB + y) * ld] -= c[s];
+      for (int v = 0; v < 4; ++v) {
+        const int x = mx0 + 4 * v, y = my;
+        if (x < nbi && y < nbj && (i != j || x >= y)) G[(i * CB + x) + (long)(j * CB + y) * ld] -= r[v];
+      }
+    } else {
+      S d[4];
+      tile_mul4<S, true>(c, T1, T0);                 // L_ip = G_ip Li_pp^H
+      tile_mul4<S, true>(d, T2, T0);                 // L_jp
+      __syncthreads();
+      tile_put4(T1, c);
+      tile_put4(T2, d);
+      __syncthreads();
+      tile_mul4<S, true>(c, T1, T2);                 // L_ip L_jp^H
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        int e = threadIdx.x + 256 * s, x = e % CB, y = e / CB;
+        if (x < nbi && y < nbj && (i != j || x >= y)) G[(i * CB + x) + (long)(j * CB + y) * ld] -= c[s];
+      }
     }
     if (i == j && i == p + 1) {  // the next diagonal step, on the tile just updated
       __syncthreads();
@@ -218,11 +260,20 @@ PPCG_DEV void chol_step_body(const DenseStep& a, int p, unsigned wg) {
     tile_get(T0, Li, ld, n0, n0, nbp, nbp);
     tile_get(T1, W, ld, n0, cc * CB, nbp, nbc);
     __syncthreads();
-    tile_mul4<S, false>(c, T0, T1);
+    if constexpr (MF) {
+      const d4v r = tile_mfma<false>(T0, T1);
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      int e = threadIdx.x + 256 * s, x = e % CB, y = e / CB;
-      if (x < nbp && y < nbc) Li[(n0 + x) + (long)(cc * CB + y) * ld] = c[s];
+      for (int v = 0; v < 4; ++v) {
+        const int x = mx0 + 4 * v, y = my;
+        if (x < nbp && y < nbc) Li[(n0 + x) + (long)(cc * CB + y) * ld] = r[v];
+      }
+    } else {
+      tile_mul4<S, false>(c, T0, T1);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        int e = threadIdx.x + 256 * s, x = e % CB, y = e / CB;
+        if (x < nbp && y < nbc) Li[(n0 + x) + (long)(cc * CB + y) * ld] = c[s];
+      }
     }
     return;
   }
@@ -234,20 +285,35 @@ PPCG_DEV void chol_step_body(const DenseStep& a, int p, unsigned wg) {
     tile_get(T1, G, ld, i * CB, n0, nbi, nbp);       // G_ip
     if (cc < p) tile_get(T2, W, ld, n0, cc * CB, nbp, nbc);
     __syncthreads();
-    S d[4];
-    tile_mul4<S, true>(c, T1, T0);                   // L_ip
-    if (cc < p) tile_mul4<S, false>(d, T0, T2);      // Li_pp W_pc
-    __syncthreads();
-    tile_put4(T1, c);
-    if (cc < p) tile_put4(T2, d);
-    __syncthreads();
-    tile_mul4<S, false>(c, T1, cc < p ? T2 : T0);    // L_ip (Li_pp W_pc); W_pp = I
+    if constexpr (MF) {
+      acc_put(T3, tile_mfma<true>(T1, T0));          // L_ip
+      if (cc < p) acc_put(T4, tile_mfma<false>(T0, T2));  // Li_pp W_pc
+      __syncthreads();
+      const d4v r = tile_mfma<false>(T3, cc < p ? T4 : T0);  // L_ip (Li_pp W_pc); W_pp = I
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      int e = threadIdx.x + 256 * s, x = e % CB, y = e / CB;
-      if (x < nbi && y < nbc) {
-        S* w = W + (i * CB + x) + (long)(cc * CB + y) * ld;
-        *w = (cc < p) ? *w - c[s] : -c[s];
+      for (int v = 0; v < 4; ++v) {
+        const int x = mx0 + 4 * v, y = my;
+        if (x < nbi && y < nbc) {
+          S* w = W + (i * CB + x) + (long)(cc * CB + y) * ld;
+          *w = (cc < p) ? *w - r[v] : -r[v];
+        }
+      }
+    } else {
+      S d[4];
+      tile_mul4<S, true>(c, T1, T0);                 // L_ip
+      if (cc < p) tile_mul4<S, false>(d, T0, T2);    // Li_pp W_pc
+      __syncthreads();
+      tile_put4(T1, c);
+      if (cc < p) tile_put4(T2, d);
+      __syncthreads();
+      tile_mul4<S, false>(c, T1, cc < p ? T2 : T0);  // L_ip (Li_pp W_pc); W_pp = I
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        int e = threadIdx.x + 256 * s, x = e % CB, y = e / CB;
+        if (x < nbi && y < nbc) {
+          S* w = W + (i * CB + x) + (long)(cc * CB + y) * ld;
+          *w = (cc < p) ? *w - c[s] : -c[s];
+        }
       }
     }
   }
