@@ -296,6 +296,19 @@ ppcg_status ppcg_solve_batched(ppcg_handle* h, int32_t nprob, const ppcg_operato
  * nx < 4, h <= 0 or an order other than 2 and 4. */
 ppcg_status ppcg_apply_h(ppcg_handle* h, const ppcg_operator* op, int32_t ncols, const double* X, double* Y);
 
+/* The start block ppcg_solve draws on the device when X0 == NULL (the random
+ * initial X of Algorithm 3), alone, so that the generator can be checked:
+ * X[i + j n] for row i < n, column j < ncols is N(0,1) (cplx: real and
+ * imaginary parts N(0,1/2), interleaved), from Philox-4x32-10 with counter
+ * (i mod 2^32, j, i >> 32, 0) and key (seed mod 2^32, seed >> 32); the four
+ * output words give two 53-bit uniforms u1, u2 in (0,1) and the Box-Muller
+ * pair sqrt(-2 ln u1) (cos 2 pi u2, sin 2 pi u2).  Real blocks take the
+ * first, complex blocks both, times sqrt(1/2).
+ *   X   device out, n x ncols column-major (ld n), caller-owned
+ * 0 <= n <= 2^31, 0 <= ncols <= 65535 (either zero: nothing drawn);
+ * PPCG_EINVAL otherwise. */
+ppcg_status ppcg_start_block(ppcg_handle* h, int64_t n, int32_t ncols, int32_t cplx, uint64_t seed, double* X);
+
 /* The sub-block projected problems of one PPCG iteration alone (step 13 of
  * Algorithm 3; section 5.1; Theorems 1-2), for tests of that step: for each
  * of nblocks pencils (A_j, B_j) of order nS = 3q (has_p) or 2q, columns

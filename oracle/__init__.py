@@ -12,6 +12,7 @@ Modules
   ppcg_ref  the PPCG iteration (paper, Algorithm 3 with sections 5.1-5.7)
   brute     dense brute-force eigendecomposition for tiny grids
   grad      dL/dV by projected Sternheimer solves and by the dense formula
+  rng       the start block from Philox-4x32-10 and Box-Muller
 
 Every function is pinned by a ``-m "not gpu"`` test against something other
 than itself (closed forms, brute force, library routines, invariants); see

@@ -100,6 +100,8 @@ def lib():
     L.ppcg_columns.restype = c_int32
     L.ppcg_apply_h.argtypes = [c_void_p, POINTER(Operator), c_int32, c_void_p, c_void_p]
     L.ppcg_apply_h.restype = c_int32
+    L.ppcg_start_block.argtypes = [c_void_p, c_int64, c_int32, c_int32, c_uint64, c_void_p]
+    L.ppcg_start_block.restype = c_int32
     L.ppcg_block_pencils.argtypes = [c_void_p, c_int32, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_double,
                                      c_void_p, c_void_p]
     L.ppcg_block_pencils.restype = c_int32
@@ -216,6 +218,18 @@ class Handle:
         if code != 0:
             raise PPCGError(code, self.error())
         return Y
+
+    def start_block(self, n, ncols, seed, cplx=False):
+        """The start block a solve draws on the device when X0 is None, for a
+        given seed: a (ncols, n) column-major CUDA tensor, float64 N(0,1) or
+        complex128 with N(0,1/2) parts."""
+        import torch
+        X = torch.empty((int(ncols), int(n)), dtype=torch.complex128 if cplx else torch.float64, device="cuda")
+        code = self._L.ppcg_start_block(self._h, int(n), int(ncols), 1 if cplx else 0, int(seed),
+                                        c_void_p(X.data_ptr()) if X.numel() else None)
+        if code != 0:
+            raise PPCGError(code, self.error())
+        return X
 
     def solve(self, V, N, k, sbsize, tol, rr_period, X0, h=0.5, order=2, check=True, kpt=(0.0, 0.0, 0.0), B=None):
         """Lowest k eigenpairs.  X0: (n, K) start block (torch CUDA float64, or

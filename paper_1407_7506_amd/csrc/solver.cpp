@@ -2190,6 +2190,17 @@ ppcg_status ppcg_apply_h(ppcg_handle* h, const ppcg_operator* op, int32_t ncols,
   });
 }
 
+ppcg_status ppcg_start_block(ppcg_handle* h, int64_t n, int32_t ncols, int32_t cplx, uint64_t seed, double* X) {
+  if (!h || n < 0 || n > (int64_t(1) << 31) || ncols < 0 || ncols > 65535 || (n > 0 && ncols > 0 && !X))
+    return PPCG_EINVAL;
+  return guard(h, [&]() {
+    launch_randn(X, (long)n, (long)n, ncols, seed, cplx != 0, h->st);
+    HIPCHECK(hipGetLastError());
+    sync(h);
+    return PPCG_OK;
+  });
+}
+
 ppcg_status ppcg_block_pencils(ppcg_handle* h, int32_t nblocks, int32_t q, int32_t has_p, int32_t cplx,
                                const double* A, const double* B, double tol, double* C, int32_t* flags) {
   if (!h || nblocks < 0 || q < 1 || q > 32 || !(tol > 0) || (nblocks > 0 && (!A || !B || !C || !flags)))

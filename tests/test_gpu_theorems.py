@@ -6,7 +6,8 @@ of section 3) and of the solver's boundary behaviour, through the C ABI.
   (the re-solve without P of Theorem 2) and the singular_tol threshold.
 * ppcg_solve on problems where the backtrack fires, where the locked set
   shrinks, and whose start block holds an exact eigenvector.
-* the start block drawn on the device (X0 = NULL), the persisted autotuner
+* the start block drawn on the device (X0 = NULL) and ppcg_start_block
+  against the oracle's generator, the persisted autotuner
   table, the per-iteration log, the stage times, and ppcg_grad's
   PPCG_ENOCONV."""
 import math
@@ -18,7 +19,7 @@ import pytest
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-from oracle import brute, dense, ppcg_ref, stencil  # noqa: E402
+from oracle import brute, dense, ppcg_ref, rng, stencil  # noqa: E402
 from paper_1407_7506_amd import binding as B  # noqa: E402
 from paper_1407_7506_amd import inputs as I  # noqa: E402
 
@@ -239,6 +240,32 @@ def test_start_block_drawn_on_device(kpt):
         assert np.abs(lam - lb).max() / np.abs(lb).max() <= 1e-9
         assert info["resid_final"] <= 1e-9
     assert not np.array_equal(res[0][1], res[2][1])
+
+
+@pytest.mark.parametrize("cplx", [False, True], ids=["real", "complex"])
+def test_device_start_block_matches_oracle_generator(cplx):
+    """ppcg_start_block against the oracle's Philox-4x32-10 + Box-Muller
+    block, entry by entry: ragged row counts, a seed with a nonzero high
+    word, empty blocks.  The uniforms are exact integer maps on both sides;
+    log, sqrt and cos/sincospi differ by a few ulps, so |d - o| <= 3e-14 +
+    1e-14 |o| (entries are below 8.7 in magnitude).  Then a solve with
+    X0 = NULL equals, bit for bit, the solve given that block."""
+    h = B.Handle("fp64", max_iter=MAX_IT, seed=11)
+    for n, ncols, seed in ((1000, 7, 203), (777, 3, (1 << 40) + 5), (0, 3, 1), (5, 0, 1)):
+        Xd = h.start_block(n, ncols, seed, cplx).cpu().numpy().T
+        Xo = rng.start_block(n, ncols, seed, cplx)
+        assert Xd.shape == Xo.shape == (n, ncols)
+        err = np.abs(Xd - Xo)
+        say("start block", n, ncols, seed, "max |d - o|", err.max() if err.size else 0.0)
+        assert np.all(err <= 3e-14 + 1e-14 * np.abs(Xo))
+    kpt = (0.7, 0.0, 0.0) if cplx else (0.0, 0.0, 0.0)
+    p = I.small_problem(N=8, k=12, q=4, order=2, tol=1e-9, kpt=kpt)
+    K = h.columns(p.k, p.q)
+    X0 = h.start_block(p.grid.n, K, 11, cplx).cpu().numpy().T
+    a = gpu_solve(h, p, X0=None)
+    b = gpu_solve(h, p, X0=X0)
+    h.close()
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
 def test_tune_table_persists(tmp_path):
