@@ -427,6 +427,41 @@ def bench_scf(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_library_gemm(args):
+    """The projection's two products at the wells48 shape (n = 110592 rows,
+    K = 528 columns of X, 2m = 472 columns of [W P]: the timed solve's mean
+    active width) through the vendor BLAS: Gram X^T [W P] and update
+    [W P] - X G, float32 and float64, 20 timed repetitions each after 3 untimed
+    ones.  Not part of the solver: a reference rate for its own kernels."""
+    import torch
+    torch.backends.cuda.matmul.allow_tf32 = False
+    n, K, m2 = 110592, 528, 472
+    out = {"library_gemm": "torch.matmul / addmm (hipBLASLt or rocBLAS as torch dispatches), no TF32",
+           "shape": {"n": n, "K": K, "2m": m2}, "results": []}
+    for dt, tag, peak in ((torch.float32, "f32", 157.3), (torch.float64, "f64", 78.6)):
+        Xcm = torch.randn(K, n, device="cuda", dtype=dt)     # X, column-major n x K
+        Wcm = torch.randn(m2, n, device="cuda", dtype=dt)    # [W P], column-major n x 2m
+        G = torch.randn(K, m2, device="cuda", dtype=dt)
+        ops = (("gram", lambda: Xcm @ Wcm.t()),
+               ("update", lambda: torch.addmm(Wcm, G.t(), Xcm, alpha=-1.0)))
+        for name, f in ops:
+            for _ in range(3):
+                f()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(20):
+                f()
+            e1.record()
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) / 20 * 1e3
+            tf = 2.0 * n * K * m2 / us / 1e6
+            out["results"].append({"op": name, "dtype": tag, "us": round(us, 1), "TFLOP/s": round(tf, 2),
+                                   "peak": peak, "frac": round(tf / peak, 4)})
+        del Xcm, Wcm, G
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -447,6 +482,9 @@ def main():
                     help="bloch96: write the eigenvalues of each precision's solve to <path>_<precision>.npy")
     ap.add_argument("--orth-skip", action="store_true",
                     help="bloch96: omit Cholesky-QR while |X^H X - I|_F <= 0.1 (section 5.5)")
+    ap.add_argument("--library-gemm", action="store_true",
+                    help="time the vendor BLAS (torch.matmul, no TF32) on the wells48 projection shapes, "
+                         "print one JSON line and exit: a reference for the projection kernels' MFMA rate")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
                     help="write profiles/traffic_wells48_<precision>.json from two rocprofv3 --pmc databases "
                          "and exit (no GPU use)")
@@ -461,6 +499,8 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: the solver runs on one GPU; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
+    if args.library_gemm:
+        return bench_library_gemm(args)
     if args.workload == "batch64":
         return bench_batch(args)
     if args.workload == "bloch96":
