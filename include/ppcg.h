@@ -162,7 +162,10 @@ typedef struct {
   double kpt[3];        /* Bloch vector kappa (1/length); all zero = real
                            operator, otherwise complex Hermitian blocks */
   const double* V;      /* device, n potential values */
-  int32_t precond;      /* ppcg_precond; only PPCG_PRECOND_JACOBI */
+  int32_t precond;      /* ppcg_precond: PPCG_PRECOND_JACOBI, T = diag(H)^-1
+                           (PPCG_ENOTHPD when diag(H) <= 0 anywhere), or
+                           PPCG_PRECOND_NONE, T = I (step 8 of Algorithm 3
+                           leaves W as it is); other values PPCG_EINVAL */
   const double* B;      /* device, n positive values, or NULL: the generalized
                            problem H x = lambda B x with B = diag(B) (section 1:
                            solved without factoring B, every inner product of

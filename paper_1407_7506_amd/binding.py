@@ -124,6 +124,9 @@ def lib():
     return L
 
 
+_PRECONDS = {"none": 0, "jacobi": 1}  # ppcg_precond
+
+
 def _is_complex_kpt(kpt) -> bool:
     return any(float(c) != 0.0 for c in kpt)
 
@@ -190,11 +193,12 @@ class Handle:
         return self._L.ppcg_last_error(self._h).decode()
 
     @staticmethod
-    def operator(V, N, h=0.5, order=2, kpt=(0.0, 0.0, 0.0), B=None):
+    def operator(V, N, h=0.5, order=2, kpt=(0.0, 0.0, 0.0), B=None, precond="jacobi"):
         _check_tensor(V, "V", N ** 3)
         if B is not None:
             _check_tensor(B, "B", N ** 3)
-        return Operator(int(N), float(h), int(order), (c_double * 3)(*kpt), c_void_p(V.data_ptr()), 1,
+        code = _PRECONDS.get(precond, precond)  # a name, or a raw ppcg_precond value passed through
+        return Operator(int(N), float(h), int(order), (c_double * 3)(*kpt), c_void_p(V.data_ptr()), int(code),
                         c_void_p(B.data_ptr()) if B is not None else None)
 
     def columns(self, k, sbsize):
@@ -231,11 +235,13 @@ class Handle:
             raise PPCGError(code, self.error())
         return X
 
-    def solve(self, V, N, k, sbsize, tol, rr_period, X0, h=0.5, order=2, check=True, kpt=(0.0, 0.0, 0.0), B=None):
+    def solve(self, V, N, k, sbsize, tol, rr_period, X0, h=0.5, order=2, check=True, kpt=(0.0, 0.0, 0.0), B=None,
+              precond="jacobi"):
         """Lowest k eigenpairs.  X0: (n, K) start block (torch CUDA float64, or
         complex128 for a nonzero Bloch vector kpt), or None for a start block
         drawn on the device from the handle's seed.  B: optional diagonal of the
-        generalized problem H x = lambda B x (CUDA float64, n).
+        generalized problem H x = lambda B x (CUDA float64, n).  precond:
+        "jacobi" (T = diag(H)^-1) or "none" (T = I).
         Returns (lam (k,), X (n, k), info dict)."""
         import torch
         n = N ** 3
@@ -252,7 +258,7 @@ class Handle:
         kout = K if self.return_buffers else k
         Xout = torch.empty((kout, n), dtype=dt, device=V.device)
         lam = torch.empty(kout, dtype=torch.float64, device=V.device)
-        op = self.operator(V, N, h, order, kpt, B)
+        op = self.operator(V, N, h, order, kpt, B, precond)
         info = Info()
         code = self._L.ppcg_solve(self._h, byref(op), int(k), int(sbsize), float(tol), int(rr_period),
                                   c_void_p(X0cm.data_ptr()) if X0cm is not None else None,

@@ -377,6 +377,7 @@ struct Prob {
   const double* V = nullptr;
   const double* Bsrc = nullptr;  // generalized problem: diag(B) (caller's), else NULL
   bool gen = false;
+  bool jac = true;             // Jacobi preconditioner T = diag(H)^-1, else T = I
   const double* X0 = nullptr;  // NULL: seeded N(0,1) start block drawn on the device
   uint64_t seed = 0;
   double* Xout = nullptr;
@@ -445,7 +446,9 @@ struct Prob {
     if (!op || !op->V || !Xout_ || !lamout_) throw PpcgError{PPCG_EINVAL, "null pointer argument"};
     if (op->order != 2 && op->order != 4) throw PpcgError{PPCG_EINVAL, "order must be 2 or 4"};
     cplx = bloch_phases(op, ph);
-    if (op->precond != PPCG_PRECOND_JACOBI) throw PpcgError{PPCG_EINVAL, "only the Jacobi preconditioner"};
+    if (op->precond != PPCG_PRECOND_JACOBI && op->precond != PPCG_PRECOND_NONE)
+      throw PpcgError{PPCG_EINVAL, "precond must be PPCG_PRECOND_NONE or PPCG_PRECOND_JACOBI"};
+    jac = op->precond == PPCG_PRECOND_JACOBI;
     if (op->nx < 4 || !(op->h > 0)) throw PpcgError{PPCG_EINVAL, "bad grid"};
     N = op->nx;
     order = op->order;
@@ -1006,6 +1009,7 @@ struct Prob {
     launch_zero_int(Wk.iflag.i(), 4, st);
     launch_prep_diag(Wk.Vd.d(), n, c0, Wk.td.d(), mixed ? Wk.V32.f() : nullptr, Wk.dminp.d(), nparts, Wk.iflag.i(),
                      st);
+    if (!jac) launch_fill(Wk.td.d(), n, 1.0, st);  // T = I: the row scales of step 8 become ones
     launch_d2h(Wk.hpind, Wk.dminp.p, nparts * 8, st);
     launch_d2h(Wk.hpin + 2 * nparts, Wk.iflag.p, 4, st);
     if (gen) {  // min and NaN scan of B (its reciprocal lands in btd, overwritten below)
@@ -1020,7 +1024,8 @@ struct Prob {
     double mn = 1e308;
     for (int i = 0; i < nparts; ++i) mn = std::min(mn, Wk.hpind[i]);
     if (Wk.hpin[2 * nparts]) throw PpcgError{PPCG_EINVAL, "V contains NaN"};
-    if (!(mn > 0)) throw PpcgError{PPCG_ENOTHPD, "diag(H) has a non-positive entry: Jacobi preconditioner not HPD"};
+    if (jac && !(mn > 0))
+      throw PpcgError{PPCG_ENOTHPD, "diag(H) has a non-positive entry: Jacobi preconditioner not HPD"};
     dmin = mn;
     if (gen) {
       double bm = 1e308;

@@ -7,7 +7,8 @@ of section 3) and of the solver's boundary behaviour, through the C ABI.
 * ppcg_solve on problems where the backtrack fires, where the locked set
   shrinks, and whose start block holds an exact eigenvector.
 * the start block drawn on the device (X0 = NULL) and ppcg_start_block
-  against the oracle's generator, the persisted autotuner
+  against the oracle's generator, the solve without a preconditioner
+  (T = I), the persisted autotuner
   table, the per-iteration log, the stage times, and ppcg_grad's
   PPCG_ENOCONV."""
 import math
@@ -266,6 +267,46 @@ def test_device_start_block_matches_oracle_generator(cplx):
     b = gpu_solve(h, p, X0=X0)
     h.close()
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_unpreconditioned_solve_matches_oracle(prec):
+    """precond = PPCG_PRECOND_NONE (T = I in step 8 of Algorithm 3): the GPU
+    against the oracle run with T = 1 and against the dense eigenvalues.
+    With T = I a potential that makes diag(H) negative everywhere is solved
+    (the spectrum shifts with it), where the Jacobi preconditioner reports
+    PPCG_ENOTHPD; an unknown preconditioner value is PPCG_EINVAL."""
+    p = I.small_problem(N=8, k=12, q=4, order=2, tol=1e-9)
+    g = p.grid
+    tol_l = 1e-9 if prec == "fp64" else 1e-7
+    h = B.Handle(prec, max_iter=MAX_IT)
+
+    def solve(V, **kw):
+        lam, X, info = h.solve(dev(V), g.N, p.k, p.q, p.tol, p.rr_period, dev(p.start()), h=g.h, order=g.order, **kw)
+        return lam.cpu().numpy(), X.cpu().numpy(), info
+
+    lam, X, info = solve(p.V, precond="none")
+    A = lambda Y: stencil.apply_h(Y, p.V, g.N, g.h, g.order, g.kpt)
+    lo, Xo, io = ppcg_ref.ppcg(A, np.ones(g.n), p.start(), p.k, p.q, p.tol, p.rr_period)
+    lj, _, ij = solve(p.V)
+    lb = brute.lowest_values(p.V, 8, 0.5, 2, p.k)
+    scale = np.abs(lb).max()
+    say(prec, "T = I iters gpu", info["iters"], "oracle", io.iters, "| Jacobi iters gpu", ij["iters"])
+    assert np.abs(lo - lb).max() / scale <= 1e-9
+    assert np.abs(lam - lb).max() / scale <= tol_l
+    assert np.abs(lam - lo).max() / scale <= tol_l
+    assert info["resid_final"] <= p.tol
+    np.testing.assert_allclose(X.T @ X, np.eye(p.k), atol=1e-12)
+    Vneg = p.V - 14.0   # diag(H) = 12 + V < 0 at every point
+    ln, _, infon = solve(Vneg, precond="none")
+    assert np.abs(ln - (lb - 14.0)).max() / np.abs(lb - 14.0).max() <= tol_l
+    with pytest.raises(B.PPCGError) as e:
+        solve(Vneg, precond="jacobi")
+    assert e.value.status == "PPCG_ENOTHPD"
+    with pytest.raises(B.PPCGError) as e:
+        solve(p.V, precond=7)
+    assert e.value.status == "PPCG_EINVAL"
+    h.close()
 
 
 def test_tune_table_persists(tmp_path):

@@ -56,6 +56,24 @@ def test_ppcg_matches_brute_force(case):
     assert info.fresh_resid <= 1e-9
 
 
+@pytest.mark.parametrize("case", CASES[:3], ids=lambda c: "-".join(f"{k}{v}" for k, v in c.items()))
+def test_unpreconditioned_matches_brute_force(case):
+    """T = I (no preconditioner) is a valid HPD choice: the same dense
+    eigenpairs; with T = I the iterates do not depend on a constant shift of
+    the potential (W = AX - XG is unchanged by it), so a shift that makes
+    diag(H) negative everywhere moves the eigenvalues by exactly the shift."""
+    p = I.small_problem(tol=1e-9, **case)
+    g = p.grid
+    A = lambda X: stencil.apply_h(X, p.V, g.N, g.h, g.order, g.kpt)
+    lam, X, info = ppcg_ref.ppcg(A, np.ones(g.n), p.start(), p.k, p.q, p.tol, p.rr_period, record=True)
+    check_solution(p, lam, X, info, A, 1e-9)
+    c = -3.0 * stencil.diag_h(p.V, g.h, g.order).max()
+    As = lambda X: stencil.apply_h(X, p.V + c, g.N, g.h, g.order, g.kpt)
+    ls, _, _ = ppcg_ref.ppcg(As, np.ones(g.n), p.start(), p.k, p.q, p.tol, p.rr_period)
+    lb = brute.lowest_values(p.V, g.N, g.h, g.order, p.k, g.kpt)
+    assert np.abs(ls - (lb + c)).max() / np.abs(lb + c).max() < 1e-10
+
+
 def laplacian_spectrum(N, h, order):
     th = 2 * np.pi * np.arange(N) / N
     if order == 2:
