@@ -427,6 +427,31 @@ def bench_scf(args):
     print(json.dumps(line), flush=True)
 
 
+def eig_error_bound(h, V, g, lam, X):
+    """A-posteriori accuracy of a returned solve (after the timed region):
+    per-column residuals r_i = H x_i - lambda_i x_i from a fresh float64
+    stencil product, and the quadratic bound |lambda_i - exact| <=
+    |r_i|^2 / gap_i, gap_i the distance to the nearest other returned value,
+    over the columns whose gap exceeds 1e-3 max|lambda| (within a cluster the
+    bound says nothing); errors relative to max|lambda|."""
+    import numpy as np
+    import torch
+    Xcm = X.t().contiguous()
+    Y = h.apply_h(V, g.N, Xcm, h=g.h, order=g.order)
+    rn = torch.linalg.norm(Y - lam[:, None] * Xcm, dim=1).cpu().numpy()
+    del Y, Xcm
+    lv = lam.cpu().numpy()
+    scale = float(np.abs(lv).max())
+    d = np.abs(lv[:, None] - lv[None, :])
+    np.fill_diagonal(d, np.inf)
+    gap = d.min(axis=1)
+    sel = gap > 1e-3 * scale
+    quad = rn[sel] ** 2 / gap[sel]
+    return {"max_col_resid_rel": float(rn.max() / scale),
+            "quadratic_bound_rel": float(quad.max() / scale) if sel.any() else None,
+            "columns_with_gap": int(sel.sum()), "columns": int(lv.size)}
+
+
 def bench_library_gemm(args):
     """The projection's two products at the wells48 shape (n = 110592 rows,
     K = 528 columns of X, 2m = 472 columns of [W P]: the timed solve's mean
@@ -549,7 +574,8 @@ def main():
             for line in tune.splitlines():
                 log("   " + line)
         results[prec] = {"s": dt / args.steps, "info": infos[-1], "lam": lam.cpu().numpy(), "kt": kt,
-                         "tune_classes": len(tune.splitlines())}
+                         "tune_classes": len(tune.splitlines()),
+                         "eig_bound": eig_error_bound(h, V, g, lam, X)}
         log(f"{prec}: {dt / args.steps:.3f} s/solve, iters {infos[-1]['iters']}, rr {infos[-1]['n_rr']}, "
             f"resid {infos[-1]['resid_final']:.3e}, stages {stage_ms(infos[-1])}")
         top = sorted(kt.items(), key=lambda x: -x[1][0])[:24]
@@ -586,6 +612,7 @@ def main():
         "roofline": roofline(kt, main_prec),
         "solve_roofline": solve_roofline(r["info"]),
         "stage_ms": stage_ms(r["info"]),
+        "eig_bound": r["eig_bound"],
         "hbm": hbm_rates(kt, main_prec),
         "kernel_share": {k: round(v[0] / tot_ms, 4) for k, v in sorted(kt.items(), key=lambda x: -x[1][0])[:8]},
         "launches_per_solve": {k: v[1] // args.steps for k, v in kt.items() if k in TRAFFIC_KERNELS},
@@ -599,6 +626,7 @@ def main():
         out["fp64_iters"] = rf["info"]["iters"]
         out["speedup_mixed_vs_fp64"] = round(rf["s"] / results["mixed"]["s"], 3)
         out["mixed_vs_fp64_max_err"] = float(np.abs(lm - lf).max() / np.abs(lf).max())
+        out["eig_bound_fp64"] = rf["eig_bound"]
         out["roofline_fp64"] = roofline(rf["kt"], "fp64")
         out["solve_roofline_fp64"] = solve_roofline(rf["info"])
         out["stage_ms_fp64"] = stage_ms(rf["info"])
