@@ -208,6 +208,140 @@ __global__ __launch_bounds__(256) void stencil_lds_kernel(StencilArgs a) {
     vc = vn;
   }
 }
+// Vector variant for real columns (float or double) when N, the column
+// strides and the pointers allow 16-byte access: a lane owns VEC = 16 /
+// sizeof(S) consecutive points of one x line (N is a multiple of VEC), so the
+// plane window, the z values entering the register window, V and the output
+// move as 16-byte loads and stores, and a workgroup covers 256 VEC points of
+// the plane.  The y neighbours are 16-byte LDS reads at +-N, +-2N; the x
+// neighbours are the lane's own centre values plus one (13-point: two) LDS
+// values at each end of its run, wrapped inside the x line.  Same pipeline as
+// above: the loads of plane k + 1 are issued before plane k is computed, one
+// barrier per plane; the last plane of a chunk is peeled so that the loop body
+// has no conditional load.  Every global load is in bounds: window offsets are
+// taken modulo the plane and idle lanes read their column's first run.
+template <class S, int ORDER, int WPT>
+__global__ __launch_bounds__(256) void stencil_vec_kernel(StencilArgs a) {
+  constexpr int VEC = 16 / (int)sizeof(S);
+  typedef S VT __attribute__((ext_vector_type(VEC)));
+  extern __shared__ __align__(16) char smem[];
+  constexpr int RAD = stencil_rad<ORDER>();
+  constexpr int P = 256 * VEC;  // points of a plane per workgroup
+  const int N = a.N;
+  const int NN = N * N;
+  const int W = P + 2 * RAD * N;  // window elements (a multiple of VEC)
+  const int WV = W / VEC;         // window vectors, <= 256 WPT (checked by the launcher)
+  S* const win0 = (S*)smem;
+  S* const win1 = win0 + W;
+  const unsigned tpp = (unsigned)((NN + P - 1) / P);
+  const unsigned kch = (unsigned)((N + SZ - 1) / SZ);
+  const unsigned L = xcd_remap(blockIdx.x, gridDim.x);
+  const int col = (int)(L / (tpp * kch));
+  const unsigned rest = L % (tpp * kch);
+  const int kc = (int)(rest / tpp);
+  const int q0 = (int)(rest % tpp) * P;
+  if (col >= a.ncols) return;  // uniform over the workgroup
+  const int tid = threadIdx.x;
+  const int q = q0 + VEC * tid;  // first point of this lane's run
+  const bool act = q < NN;       // NN is a multiple of VEC: a run is wholly inside or outside
+  const int qa = act ? q : 0;
+  const S* x = (const S*)a.X + (long)col * a.ldx;
+  S* y = (S*)a.Y + (long)col * a.ldy;
+  const S* V = (const S*)a.V;
+  const int i0 = qa % N;           // x index of the run's first point; the run ends at i0 + VEC - 1 < N
+  const int c = RAD * N + VEC * tid;  // window position of the run's first point
+  const int xl1 = c + wrap_idx(i0, -1, N) - i0, xl2 = c + wrap_idx(i0, -2, N) - i0;
+  const int xr1 = c + wrap_idx(i0 + VEC - 1, 1, N) - i0, xr2 = c + wrap_idx(i0 + VEC - 1, 2, N) - i0;
+  int woff[WPT];
+  bool wv[WPT];
+#pragma unroll
+  for (int u = 0; u < WPT; ++u) {
+    const int e = tid + 256 * u;
+    wv[u] = e < WV;
+    const int s2 = (q0 - RAD * N + VEC * e) % NN;
+    woff[u] = s2 < 0 ? s2 + NN : s2;  // a multiple of VEC, at most NN - VEC
+  }
+  const int k0 = kc * SZ;
+  const int k1 = k0 + SZ < N ? k0 + SZ : N;
+  VT wr[WPT];
+  auto wload = [&](int k) {
+    const S* xp = x + (long)k * NN;
+#pragma unroll
+    for (int u = 0; u < WPT; ++u) wr[u] = *(const VT*)(xp + woff[u]);
+  };
+  auto wstore = [&](S* buf) {
+#pragma unroll
+    for (int u = 0; u < WPT; ++u)
+      if (wv[u]) *(VT*)(buf + VEC * (tid + 256 * u)) = wr[u];
+  };
+  auto at = [&](int k) { return *(const VT*)(x + qa + (long)k * NN); };
+  auto vat = [&](int k) { return *(const VT*)(V + qa + (long)k * NN); };
+  VT zm2 = ORDER == 4 ? at(wrap_idx(k0, -2, N)) : VT{};
+  VT zm1 = at(wrap_idx(k0, -1, N));
+  VT zc = at(k0);
+  VT zp1 = at(wrap_idx(k0, 1, N));
+  VT zp2 = ORDER == 4 ? at(wrap_idx(k0, 2, N)) : VT{};
+  VT vc = vat(k0);
+  wload(k0);
+  wstore(win0);
+  __syncthreads();
+  auto compute = [&](int k, const S* cur) {
+    if (!act) return;
+    const VT yp1 = *(const VT*)(cur + c + N), ym1 = *(const VT*)(cur + c - N);
+    VT yp2 = VT{}, ym2 = VT{};
+    if (ORDER == 4) {
+      yp2 = *(const VT*)(cur + c + 2 * N);
+      ym2 = *(const VT*)(cur + c - 2 * N);
+    }
+    S e[VEC + 4];  // x line values at i0 - 2 .. i0 + VEC + 1
+    e[0] = ORDER == 4 ? cur[xl2] : S{};
+    e[1] = cur[xl1];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) e[2 + v] = zc[v];
+    e[VEC + 2] = cur[xr1];
+    e[VEC + 3] = ORDER == 4 ? cur[xr2] : S{};
+    VT out;
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      const S s1 = (e[v + 3] + e[v + 1]) + (yp1[v] + ym1[v]) + (zp1[v] + zm1[v]);
+      S o = ((S)a.c0 + vc[v]) * zc[v] + (S)a.w1 * s1;
+      if (ORDER == 4) {
+        const S s2 = (e[v + 4] + e[v]) + (yp2[v] + ym2[v]) + (zp2[v] + zm2[v]);
+        o += (S)a.w2 * s2;
+      }
+      if (a.shift) o -= (S)a.shift[col] * zc[v];
+      out[v] = o;
+    }
+    *(VT*)(y + q + (long)k * NN) = out;
+  };
+  auto advance = [&](VT znew, VT vn) {
+    if (ORDER == 4) {
+      zm2 = zm1;
+      zm1 = zc;
+      zc = zp1;
+      zp1 = zp2;
+      zp2 = znew;
+    } else {
+      zm1 = zc;
+      zc = zp1;
+      zp1 = znew;
+    }
+    vc = vn;
+  };
+  int k = k0;
+  for (; k + 1 < k1; ++k) {
+    const bool odd = ((k - k0) & 1) != 0;
+    wload(k + 1);
+    const VT vn = vat(k + 1);
+    const VT znew = at(wrap_idx(k + 1, RAD, N));
+    compute(k, odd ? win1 : win0);
+    wstore(odd ? win0 : win1);
+    __syncthreads();
+    advance(znew, vn);
+  }
+  compute(k, ((k - k0) & 1) != 0 ? win1 : win0);
+}
+
 template <class S, int ORDER>
 __global__ __launch_bounds__(256) void stencil_grouped(const StencilArgs* jobs, const unsigned* start, int nj) {
   int j = find_job(start, nj, blockIdx.x);
@@ -238,6 +372,9 @@ static int stencil_kind(const StencilArgs& a) {
 #ifndef PPCG_STENCIL_LDS
 #define PPCG_STENCIL_LDS 1
 #endif
+#ifndef PPCG_STENCIL_VEC
+#define PPCG_STENCIL_VEC 1
+#endif
 #ifndef PPCG_STENCIL_LDS_MIN_ES
 #define PPCG_STENCIL_LDS_MIN_ES 4
 #endif
@@ -252,6 +389,34 @@ void launch_stencil(const StencilArgs& a, hipStream_t st) {
   }
   if (blocks == 0) return;
   const size_t es = (a.f32 ? 4 : 8) * (a.cplx ? 2 : 1);
+  if (PPCG_STENCIL_VEC && !a.cplx && NN < (1L << 30)) {
+    const int vec = 16 / (int)es;
+    const int rad = a.order / 2;
+    const long P = 256L * vec;
+    const long Wv = P + 2L * rad * a.N;
+    const long wpt = (Wv / vec + 255) / 256;
+    const size_t lds = 2 * (size_t)Wv * es;
+    const bool al = ((uintptr_t)a.X % 16 == 0) && ((uintptr_t)a.Y % 16 == 0) && ((uintptr_t)a.V % 16 == 0);
+    if (al && a.N % vec == 0 && a.ldx % vec == 0 && a.ldy % vec == 0 && wpt <= 4 && lds <= 64 * 1024) {
+      const unsigned vblocks = (unsigned)(((NN + P - 1) / P) * ((a.N + SZ - 1) / SZ) * (long)a.ncols);
+#define PPCG_STENCIL_VEC_CASE(S, ORDER)                                                                            \
+  switch (wpt) {                                                                                                   \
+    case 1: hipLaunchKernelGGL((stencil_vec_kernel<S, ORDER, 1>), dim3(vblocks), dim3(256), lds, st, a); break;    \
+    case 2: hipLaunchKernelGGL((stencil_vec_kernel<S, ORDER, 2>), dim3(vblocks), dim3(256), lds, st, a); break;    \
+    case 3: hipLaunchKernelGGL((stencil_vec_kernel<S, ORDER, 3>), dim3(vblocks), dim3(256), lds, st, a); break;    \
+    default: hipLaunchKernelGGL((stencil_vec_kernel<S, ORDER, 4>), dim3(vblocks), dim3(256), lds, st, a); break;   \
+  }
+      switch (kind) {
+        case OP_STENCIL_D2: PPCG_STENCIL_VEC_CASE(double, 2) break;
+        case OP_STENCIL_D4: PPCG_STENCIL_VEC_CASE(double, 4) break;
+        case OP_STENCIL_F2: PPCG_STENCIL_VEC_CASE(float, 2) break;
+        case OP_STENCIL_F4: PPCG_STENCIL_VEC_CASE(float, 4) break;
+        default: break;
+      }
+#undef PPCG_STENCIL_VEC_CASE
+      return;
+    }
+  }
   const int W = stencil_window(a.N, a.order);
   const size_t lds = 2 * (size_t)W * es;
   const int wpt = (W + 255) / 256;

@@ -72,7 +72,7 @@ def fresh_resid(p, lam, X):
     return np.linalg.norm(R) / np.linalg.norm(lam)
 
 
-@pytest.mark.parametrize("N,order", [(10, 2), (17, 4), (32, 4), (13, 2)])
+@pytest.mark.parametrize("N,order", [(10, 2), (17, 4), (32, 4), (13, 2), (4, 4), (8, 4), (12, 2), (48, 4)])
 def test_apply_h_matches_oracle(h64, N, order):
     say("apply_h", N, order)
     V = I.gaussian_wells(N, 0.5, 3, N)
